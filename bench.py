@@ -1,0 +1,139 @@
+"""Throughput of the LP granular-flow step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
+
+A step is one lp_step over the whole 64 x 64 x 128 = 524,288-particle
+granular column (h = 0.5/64 m, jitter 0.05 h, hydrostatic density, resting
+on the wall z = 0, dt = 2e-5 s): Morton cell build, mirrors, neighbour
+search and stencil selection with ghosts, least-squares fit of u, v, w,
+mu(I) closure, fit of P and eta, right-hand side and explicit update.
+The state is resident in HBM before the timed region; K consecutive steps
+are timed between device synchronisations.
+
+Printed (one JSON line): particle-updates/s, the dominant kernel's
+achieved rate against the FP64 vector roof (phase events on the library's
+stream), and the FP64 CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-updates/s per RHS eval (FP64 vs refined FP32) + adjoint steps/s"
+
+# Peaks of one MI355X (published): FP64 vector 78.6 TFLOP/s, HBM 8 TB/s.
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic work of the pass-1 kernel per particle (fit of u, v, w on a
+# 60-row, 9-column stencil plus closure), from the survey's count for a
+# Householder least-squares solve: 0.5k row build + 9.2k QR + 3 x 2.1k
+# (Q^T b and back substitution) + 0.2k closure.
+PASS1_FLOP_PER_PARTICLE = 16.2e3
+# What the kernel actually executes per particle with 60 stencil rows:
+# 60 x (45 Gram + 27 moment FMAs = 144 flop + 12 row flop) + ~1.4k for the
+# Cholesky factor, 3 solves, 3 rows of G^-1 and the closure.
+PASS1_FLOP_EXECUTED = 60 * 156 + 1.4e3
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, steps: int):
+    """The FP64 oracle as it stands on the host cores: full steps of the
+    same column (cell-list neighbours, OpenMP over particles)."""
+    import oracle
+    st = wl.state
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, _, _ = oracle.step(st, wl.offsets, wl.params, wl.dt, brute=False)
+    dt = time.perf_counter() - t0
+    return {"value": wl.n * steps / dt, "unit": "particle-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d full oracle step(s) of the %d-particle column "
+                      "(%.1f s)" % (steps, wl.n, dt)}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the LP step is measured on a "
+              "single MI355X (--gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import lpgen
+    import paper_2206_14061_amd as lp
+
+    torch.cuda.set_device(0)
+    wl = lpgen.column_bench()
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        ctx.lp_step(st, wl.dt)
+    ctx.sync_status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.lp_step(st, wl.dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.sync_status()
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = wl.n * args.steps / elapsed
+
+    # phase durations from HIP events on the library's stream
+    ctx.profile(True)
+    ctx.profile_read()
+    for _ in range(args.steps):
+        ctx.lp_step(st, wl.dt)
+    torch.cuda.synchronize()
+    ph = ctx.profile_read()
+    ctx.profile(False)
+    ctx.sync_status()
+    nst = max(ph.pop("steps"), 1)
+    phases = {k: v / nst for k, v in ph.items()}
+    stats = ctx.stats()
+    dominant = max(("stencil", "pass1", "pass2"), key=lambda k: phases[k])
+    t_pass1 = phases["pass1"] * 1e-3
+    achieved = PASS1_FLOP_PER_PARTICLE * wl.n / t_pass1 / 1e12
+    executed = PASS1_FLOP_EXECUTED * wl.n / t_pass1 / 1e12
+    roof = {"kernel": "k_pass1 (fit of u, v, w + mu(I) closure)",
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": None, "avg_launch_ms": phases["pass1"],
+            "executed_tflops": executed,
+            "executed_frac": executed / PEAK_FP64_TFLOPS,
+            "dominant_phase": dominant}
+    out = {"metric": METRIC, "value": value, "unit": "particle-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": wl.name, "particles": wl.n, "dt": wl.dt,
+                      "precision": args.precision, "m_max": 60,
+                      "R_over_h": 2.5, "parallelism": "none"},
+           "phases_ms": phases, "stats": stats, "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

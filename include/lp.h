@@ -1,0 +1,231 @@
+/*
+ * lp.h — C ABI of the MI355X (gfx950) library for one explicit time step
+ * of the Lagrangian-particle (LP) method for granular flow with mu(I)
+ * rheology (Zepeda & Samulyak, arXiv:2206.14061).
+ *
+ * The step (Sec. 3.1 of the paper, steps 5-10) is:
+ *   mirrors for the solid wall (step 9) -> neighbour search (step 5) ->
+ *   stencils with octant coverage and ghost completion (steps 5-6) ->
+ *   second-order least-squares derivatives (step 7) -> mu(I) closure
+ *   (Sec. 2.2, 2.2.1) -> second fit of P and eta -> momentum and volume
+ *   right-hand side (Sec. 2.1) -> explicit update (steps 8 and 10).
+ * The paper's octree (step 4) is replaced by a Morton-sorted uniform cell
+ * list (lp_build_cells).
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked
+ *    "host".  All floating point is IEEE float64.  Particle ids are int32
+ *    (at most 2^28 - 1 real + mirror particles).
+ *  - Work is enqueued asynchronously on the stream given to lp_create.
+ *    Only calls that return host values (lp_build_cells, lp_neighbors'
+ *    counts, lp_sync_status) synchronise that stream.
+ *  - Every call returns an lp_status; nothing throws across the ABI.
+ *    lp_last_error() gives a text description of the last failure.
+ *    Failures detected on the device (capacity overflow, non-finite
+ *    results) are latched in a device error word and reported by
+ *    lp_sync_status().
+ *  - After lp_reserve() no call allocates device memory.
+ *  - Particles of system s occupy the index range [offsets[s],
+ *    offsets[s+1]) and never interact with other systems.
+ *  - A context is not thread safe; calls that overlap on one context race.
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LP_OK = 0,
+    LP_E_ARG = 1,       /* invalid argument (null, size, parameter range)   */
+    LP_E_CAPACITY = 2,  /* workspace or output capacity exceeded            */
+    LP_E_NUMERIC = 3,   /* non-finite state produced                        */
+    LP_E_HIP = 4,       /* HIP runtime error                                */
+    LP_E_STATE = 5      /* call order violated or entry point unavailable   */
+} lp_status;
+
+enum { LP_FP64 = 0, LP_FP32_REFINED = 1 };
+enum { LP_W_UNIT = 0, LP_W_GAUSS = 1 };
+
+/* debug_flags: route every particle through the exact slow paths */
+enum { LP_DEBUG_SORTED_STENCIL = 1, LP_DEBUG_QR_FIT = 2 };
+
+/* Physical constants of one system (Sec. 2.2, 2.2.1 and Sec. 4).
+ * rho_s: grain material density (the paper's phi_s); d: grain diameter;
+ * mu_s, mu_2, I0: friction law mu(I) = mu_s + (mu_2 - mu_s)/(I0/I + 1);
+ * phi_c, phi_min: critical and minimum solid fraction (eq.
+ * inertialdensity, a = phi_c - phi_min); phi_max: start of the
+ * quasi-static branch; alpha, beta: quasi-static pressure
+ * P = rho_s (alpha + beta phi) (eq. CST2); g: body force; h: particle
+ * spacing (fit scaling, ghost offset); R: neighbour radius; wall_z: solid
+ * wall plane z = wall_z (mirror boundary).  Requires
+ * phi_min < phi_max < phi_c, beta > 0, R > 0, h > 0. */
+typedef struct {
+    double rho_s, d, mu_s, mu_2, I0, phi_c, phi_min, phi_max, alpha, beta;
+    double g[3];
+    double h, R, wall_z;
+} lp_params;
+
+/* Numerical configuration of a context.
+ * m_max: stencil cap (1..64; default 60).  precision: LP_FP64 or
+ * LP_FP32_REFINED.  cond_max: a stencil whose estimated condition number
+ * exceeds it is refitted by FP64 Householder QR.  weight: LP_W_UNIT or
+ * LP_W_GAUSS (w = exp(-4 r^2 / R^2)).  ghost_margin: an octant is covered
+ * when a neighbour lies beyond ghost_margin * h on every axis (0.5).
+ * fallback_tol: stencils with min|r_jj|/max|r_jj| below it (or fewer than 9
+ * rows) use a linear fit (1e-12).  debug_flags: LP_DEBUG_* bits. */
+typedef struct {
+    int32_t m_max;
+    int32_t precision;
+    double cond_max;
+    int32_t weight;
+    double ghost_margin;
+    double fallback_tol;
+    int32_t debug_flags;
+} lp_config;
+
+/* Structure-of-arrays particle state, device float64 arrays of length n
+ * (total particles of all systems): position x y z, velocity u v w and
+ * specific volume V = 1/phi. */
+typedef struct {
+    double *x, *y, *z, *u, *v, *w, *V;
+} lp_state;
+
+typedef struct lp_ctx lp_ctx;
+
+/* Fills *cfg with the defaults listed above. */
+void lp_config_default(lp_config* cfg);
+
+/* Creates a context bound to the current HIP device and to `stream` (a
+ * hipStream_t, may be null for the default stream).  cfg may be null for
+ * the defaults.  *out receives the context. */
+lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg);
+
+/* Releases the context and its workspace (null is ignored). */
+void lp_destroy(lp_ctx* ctx);
+
+/* Text of the last error on this context (never null). */
+const char* lp_last_error(const lp_ctx* ctx);
+
+/* Reserves workspace for up to n_max particles (mirrors included) and
+ * cells_max cells per call.  Allocates; every later call on this context
+ * allocates nothing.  May be called again to grow. */
+lp_status lp_reserve(lp_ctx* ctx, int64_t n_max, int64_t cells_max);
+
+/* Sets the systems: n_sys >= 1, offsets (host, n_sys + 1 entries,
+ * offsets[0] = 0, non-decreasing), params (host, n_sys records).  Copies
+ * both; validates parameter ranges (LP_E_ARG). */
+lp_status lp_set_systems(lp_ctx* ctx, int32_t n_sys, const int64_t* offsets,
+                         const lp_params* params);
+
+/* Morton-sorted cell list (replaces the octree of Sec. 3.1 step 4 and
+ * Sec. 3.2).  Per system: origin (min x, min y, min(min z, wall_z - R)),
+ * cell edge c = R (1 + 2^-20) >= R, cell coordinate floor((x - origin)/c),
+ * key = bit interleave of the cell coordinates (x -> bit 3k, y -> 3k+1,
+ * z -> 3k+2).  Particles are reordered in place by (system, key, old
+ * index); perm (device int32[n], optional) receives perm[new] = old.
+ * Then builds the mirror particles of Sec. 3.1 step 9 (one per particle
+ * with z - wall_z < R, at (x, y, 2 wall_z - z), velocity (u, v, -w), same
+ * V; mirror id n + k in ascending source order) and the cell tables of
+ * reals and mirrors.  Synchronises the stream once (grid sizes).
+ * LP_E_CAPACITY if the particles, mirrors or cells exceed the reservation
+ * or a cell coordinate needs more than 16 bits. */
+lp_status lp_build_cells(lp_ctx* ctx, lp_state* s, int32_t* perm);
+
+/* Neighbours, stencils and ghosts (Sec. 3.1 steps 5-6, free boundary of
+ * step 9) of every real particle of the state passed to the last
+ * lp_build_cells (unchanged since):
+ *  - candidates C_i = { j real or mirror of the same system, j != i :
+ *    (dx*dx + dy*dy) + dz*dz < R*R in float64 without fused operations };
+ *  - stencil: the nearest candidate (key (r^2, id)) of each octant
+ *    [dx>=0] + 2[dy>=0] + 4[dz>=0], then the nearest others, truncated to
+ *    m_max;
+ *  - ghost mask: bit o ([sx>0] + 2[sy>0] + 4[sz>0]) set when no candidate
+ *    lies beyond ghost_margin*h on every axis in octant s; each set bit
+ *    adds a ghost row at offset h*s.
+ * Stores them in the context for the fits.  Optional exports (null to
+ * skip): cand_off (int64[n+1]) and cand_idx (int32[cap]) = candidate CSR
+ * with ascending ids; needed (host) = total candidates (if cap is too
+ * small nothing is written to cand_idx and LP_E_CAPACITY is returned);
+ * sten_cnt (int32[n]) and sten_idx (int32[n*m_max], row-major, ascending
+ * ids, padded with -1); ghost_mask (uint8[n]); n_mirror (host).  Exports
+ * of cand_off/needed synchronise the stream. */
+lp_status lp_neighbors(lp_ctx* ctx, const lp_state* s, int64_t* cand_off,
+                       int32_t* cand_idx, int64_t cap, int64_t* needed,
+                       int32_t* sten_cnt, int32_t* sten_idx,
+                       uint8_t* ghost_mask, int64_t* n_mirror);
+
+/* Second-order least-squares derivatives (Sec. 3.1 step 7, 3D): for each
+ * real i and field q, minimises sum_rows w (a_r . c - (f_r - f_i))^2 with
+ * Taylor rows a = (xi_x, xi_y, xi_z, xi_x^2/2, xi_y^2/2, xi_z^2/2,
+ * xi_x xi_y, xi_x xi_z, xi_y xi_z), xi = (x_r - x_i)/h, over the stencil
+ * and ghost rows (xi = s).  f: k x n (row-major, reals).  Mirror value =
+ * mirror_sign[q] (host int32[k]) times the value at its source; ghost value
+ * = f_i, or 0 when ghost_zero[q] (host int32[k]) is non-zero.  coef:
+ * k x 9 x n (row-major): d/dx, d/dy, d/dz, d2/dx2, d2/dy2, d2/dz2,
+ * d2/dxdy, d2/dxdz, d2/dydz.  flags (uint8[n], optional): bit0 linear
+ * fallback (fewer than 9 rows or min|r_jj|/max|r_jj| < fallback_tol),
+ * bit3 the stencil was refitted by Householder QR.  1 <= k <= 8. */
+lp_status lp_fit_derivs(lp_ctx* ctx, const lp_state* s, const double* f,
+                        int32_t k, const int32_t* mirror_sign,
+                        const int32_t* ghost_zero, double* coef,
+                        uint8_t* flags);
+
+/* mu(I) closure and right-hand side from given velocity derivatives
+ * coef_u (3 x 9 x n, layout of lp_fit_derivs for u, v, w):
+ *   G_ab = d u_a/d x_b, D = (G + G^T)/2, gd = D - div/3 I,
+ *   |gd| = sqrt(gd:gd/2), phi = 1/V; P and eta from eq. EOS2 with
+ *   eta = mu(I) P/|gd| in the inertial branch (I = (phi_c - phi)/a), 0
+ *   otherwise; mirrors carry P(phi_src, |gd| = 0) and eta = 0, ghosts 0;
+ *   grad P and grad eta by the same fit (first derivatives);
+ *   acc_a = V (-d_a P + gd_ab d_b eta + eta (Lap u_a/2 + d_a div u/6))
+ *           / rho_s + g_a,   dVdt = V div u.
+ * Outputs (device, any may be null except acc and dVdt): dVdt (n),
+ * acc (3 x n), diag (5 x n: P, eta, I, mu, |gd|; I = mu = 0 off the
+ * inertial branch), grad (6 x n: grad P, grad eta), flags (n: bit0 linear
+ * fallback, bits1-2 branch 0 gas / 1 inertial / 2 quasi-static, bit3 QR
+ * refit). */
+lp_status lp_rheology_rhs(lp_ctx* ctx, const lp_state* s,
+                          const double* coef_u, double* dVdt, double* acc,
+                          double* diag, double* grad, uint8_t* flags);
+
+/* One explicit step (Sec. 3.1 steps 5-10): lp_build_cells (the state is
+ * reordered in place, perm optional as there), stencils, fit of u, v, w,
+ * closure, fit of P and eta, right-hand side, then
+ *   V' = V + dt dVdt,  u' = u + dt acc,  x' = x + dt (u + u')/2.
+ * dt > 0.  A non-finite result latches LP_E_NUMERIC (lp_sync_status). */
+lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
+
+/* Adjoint of lp_step (not available in this version: returns
+ * LP_E_STATE). */
+lp_status lp_step_adjoint(lp_ctx* ctx);
+
+/* Synchronises the context's stream and returns the first latched device
+ * error (LP_OK if none), then clears it.  *index (host, optional)
+ * receives the first offending particle or -1. */
+lp_status lp_sync_status(lp_ctx* ctx, int64_t* index);
+
+/* Diagnostics of the last lp_step / lp_rheology_rhs / lp_fit_derivs
+ * (host int64[8]): particles, mirrors, QR refits, sorted-path stencils,
+ * below-wall particles after the last update, 0, 0, 0.  Synchronises. */
+lp_status lp_stats(lp_ctx* ctx, int64_t* out8);
+
+/* Phase timing (instrumentation).  lp_profile(ctx, 1) makes lp_step
+ * record HIP events on the context's stream around its kernel groups:
+ * 0 cell build, 1 stencil selection (k_stencil), 2 exact sorted-stencil
+ * path, 3 pass-1 fit + closure (k_pass1), 4 pass-1 QR refits, 5 pass-2
+ * fit + RHS + update (k_pass2), 6 pass-2 QR refits; each lp_step then
+ * waits for its last event.  lp_profile_read (host double[8], int64 steps)
+ * returns the summed milliseconds per phase and the number of profiled
+ * steps, then resets them.  lp_profile(ctx, 0) stops recording. */
+lp_status lp_profile(lp_ctx* ctx, int32_t enable);
+lp_status lp_profile_read(lp_ctx* ctx, double* ms8, int64_t* steps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H */

@@ -1,0 +1,471 @@
+// C ABI entry points, context and workspace of the LP granular-step library.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "lp_internal.h"
+
+namespace lp {
+
+constexpr int SYS_CAP = 4096;
+
+lp_status hip_fail(lp_ctx* c, hipError_t e, const char* what)
+{
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return LP_E_HIP;
+}
+
+void prof_mark(lp_ctx* c, int ph, bool end)
+{
+    if (!c->prof) return;
+    hipEventRecord(c->ev[2 * ph + (end ? 1 : 0)], c->stream);
+}
+
+View make_view(lp_ctx* c, const double* const st[7])
+{
+    Work& w = c->w;
+    View v;
+    v.n = c->n;
+    v.n_sys = c->n_sys;
+    v.m_max = c->cfg.m_max;
+    v.off = w.off;
+    v.prm = w.prm;
+    v.grid = w.grid;
+    v.x = st[0]; v.y = st[1]; v.z = st[2];
+    v.u = st[3]; v.v = st[4]; v.w = st[5]; v.V = st[6];
+    v.mx = w.mst[0]; v.my = w.mst[1]; v.mz = w.mst[2];
+    v.mu = w.mst[3]; v.mv = w.mst[4]; v.mw = w.mst[5]; v.mV = w.mst[6];
+    v.msrc = w.msrc;
+    v.msx = w.msx; v.msy = w.msy; v.msz = w.msz; v.msid = w.msid;
+    v.n_mirror = w.n_mirror;
+    v.cs = w.cs; v.ce = w.ce; v.mcs = w.mcs; v.mce = w.mce;
+    v.sten = w.sten;
+    v.scnt = w.scnt;
+    v.gmask = w.gmask;
+    v.ghost_margin = c->cfg.ghost_margin;
+    v.fallback_tol = c->cfg.fallback_tol;
+    v.redo_ratio = 1.0 / c->cfg.cond_max;
+    v.weight = c->cfg.weight;
+    v.debug = c->cfg.debug_flags;
+    return v;
+}
+
+namespace {
+
+template <class T>
+hipError_t alloc(T*& p, int64_t count)
+{
+    if (p) {
+        hipFree(p);
+        p = nullptr;
+    }
+    const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    return hipMalloc((void**)&p, bytes);
+}
+
+void free_work(Work& w)
+{
+    auto f = [](auto*& p) {
+        if (p) hipFree(p);
+        p = nullptr;
+    };
+    f(w.off); f(w.prm); f(w.grid); f(w.bbox); f(w.mcount); f(w.summary);
+    f(w.err); f(w.cnt); f(w.keys0); f(w.keys1); f(w.vals0); f(w.vals1);
+    f(w.hist);
+    for (int a = 0; a < 7; ++a) { f(w.sst[a]); f(w.mst[a]); }
+    f(w.msrc); f(w.msx); f(w.msy); f(w.msz); f(w.msid); f(w.n_mirror);
+    f(w.scan); f(w.bsum); f(w.cs); f(w.ce); f(w.mcs); f(w.mce);
+    f(w.sten); f(w.scnt); f(w.gmask); f(w.hard); f(w.hard_n); f(w.hard_r2);
+    f(w.hard_id); f(w.redo); f(w.redo_n); f(w.qr_scratch); f(w.P); f(w.eta);
+    f(w.hand); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
+    if (w.h_summary) hipHostFree(w.h_summary);
+    w.h_summary = nullptr;
+    w.n_max = w.cells_max = 0;
+}
+
+lp_status check_ready(lp_ctx* c, const lp_state* s)
+{
+    if (!c) return LP_E_ARG;
+    if (c->w.n_max == 0) {
+        c->err = "lp_reserve has not been called";
+        return LP_E_STATE;
+    }
+    if (c->n_sys == 0) {
+        c->err = "lp_set_systems has not been called";
+        return LP_E_STATE;
+    }
+    if (c->n > c->w.n_max) {
+        c->err = "systems hold " + std::to_string(c->n) + " particles, reserved " +
+                 std::to_string(c->w.n_max);
+        return LP_E_CAPACITY;
+    }
+    if (s) {
+        const double* p[7] = {s->x, s->y, s->z, s->u, s->v, s->w, s->V};
+        for (int a = 0; a < 7; ++a)
+            if (!p[a] && c->n > 0) {
+                c->err = "null state array";
+                return LP_E_ARG;
+            }
+    }
+    return LP_OK;
+}
+
+void state_arrays(const lp_state* s, double* st[7])
+{
+    st[0] = s->x; st[1] = s->y; st[2] = s->z;
+    st[3] = s->u; st[4] = s->v; st[5] = s->w; st[6] = s->V;
+}
+
+}  // namespace
+}  // namespace lp
+
+using namespace lp;
+
+extern "C" {
+
+void lp_config_default(lp_config* cfg)
+{
+    if (!cfg) return;
+    cfg->m_max = 60;
+    cfg->precision = LP_FP64;
+    cfg->cond_max = 100.0;
+    cfg->weight = LP_W_UNIT;
+    cfg->ghost_margin = 0.5;
+    cfg->fallback_tol = 1e-12;
+    cfg->debug_flags = 0;
+}
+
+lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
+{
+    if (!out) return LP_E_ARG;
+    *out = nullptr;
+    lp_config c0;
+    lp_config_default(&c0);
+    if (cfg) c0 = *cfg;
+    if (c0.m_max < 1 || c0.m_max > MMAX_LIMIT || !(c0.cond_max > 1.0) ||
+        !(c0.ghost_margin >= 0.0) || !(c0.fallback_tol >= 0.0) ||
+        (c0.weight != LP_W_UNIT && c0.weight != LP_W_GAUSS) ||
+        (c0.precision != LP_FP64 && c0.precision != LP_FP32_REFINED))
+        return LP_E_ARG;
+    lp_ctx* c = new (std::nothrow) lp_ctx();
+    if (!c) return LP_E_ARG;
+    c->stream = (hipStream_t)stream;
+    c->cfg = c0;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return LP_E_HIP;
+    }
+    *out = c;
+    return LP_OK;
+}
+
+void lp_destroy(lp_ctx* c)
+{
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    for (int q = 0; q < 16; ++q)
+        if (c->ev[q]) hipEventDestroy(c->ev[q]);
+    free_work(c->w);
+    delete c;
+}
+
+const char* lp_last_error(const lp_ctx* c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
+{
+    if (!c || n_max < 1 || cells_max < 1 || n_max >= (1ll << 27)) {
+        if (c) c->err = "lp_reserve: n_max in [1, 2^27), cells_max >= 1";
+        return LP_E_ARG;
+    }
+    hipStreamSynchronize(c->stream);
+    Work& w = c->w;
+    free_work(w);
+    const int64_t nb = (n_max + SORT_TILE - 1) / SORT_TILE;
+    const int mm = c->cfg.m_max;
+    hipError_t e = hipSuccess;
+    auto A = [&](auto*& p, int64_t cnt) {
+        if (e == hipSuccess) e = alloc(p, cnt);
+    };
+    A(w.off, SYS_CAP + 1); A(w.prm, SYS_CAP); A(w.grid, SYS_CAP);
+    A(w.bbox, 6 * SYS_CAP); A(w.mcount, 1); A(w.summary, 1); A(w.err, 1);
+    A(w.cnt, 1);
+    A(w.keys0, n_max); A(w.keys1, n_max); A(w.vals0, n_max); A(w.vals1, n_max);
+    A(w.hist, 256 * nb);
+    for (int a = 0; a < 7; ++a) { A(w.sst[a], n_max); A(w.mst[a], n_max); }
+    A(w.msrc, n_max); A(w.msx, n_max); A(w.msy, n_max); A(w.msz, n_max);
+    A(w.msid, n_max); A(w.n_mirror, 1); A(w.scan, 1); A(w.bsum, nb + 1);
+    A(w.cs, cells_max); A(w.ce, cells_max); A(w.mcs, cells_max); A(w.mce, cells_max);
+    A(w.sten, (int64_t)mm * n_max); A(w.scnt, n_max); A(w.gmask, n_max);
+    A(w.hard, n_max); A(w.hard_n, 1);
+    A(w.hard_r2, (int64_t)HARD_SLOTS * HARD_CAP);
+    A(w.hard_id, (int64_t)HARD_SLOTS * HARD_CAP);
+    A(w.redo, n_max); A(w.redo_n, 1);
+    A(w.qr_scratch, (int64_t)QR_SLOTS * MAXROWS * 17);
+    A(w.P, n_max); A(w.eta, n_max); A(w.hand, (int64_t)HAND * n_max);
+    A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
+    A(w.coff, n_max + 1);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&w.h_summary, sizeof(Summary));
+    if (e == hipSuccess) e = hipMemset(w.err, 0, sizeof(ErrWord));
+    if (e == hipSuccess) e = hipMemset(w.cnt, 0, sizeof(Counters));
+    if (e == hipSuccess) {
+        ErrWord ew{0, 0, ~0ull};
+        e = hipMemcpy(w.err, &ew, sizeof(ew), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        free_work(w);
+        return hip_fail(c, e, "lp_reserve");
+    }
+    w.n_max = n_max;
+    w.cells_max = cells_max;
+    w.m_max = mm;
+    w.hist_cap = 256 * nb;
+    c->cells_ok = c->stencils_ok = false;
+    if (c->n_sys > 0) {
+        // re-upload the systems into the new buffers
+        std::vector<int64_t> off = c->h_off;
+        std::vector<lp_params> prm = c->h_prm;
+        return lp_set_systems(c, c->n_sys, off.data(), prm.data());
+    }
+    return LP_OK;
+}
+
+lp_status lp_set_systems(lp_ctx* c, int32_t n_sys, const int64_t* offsets,
+                         const lp_params* params)
+{
+    if (!c) return LP_E_ARG;
+    if (n_sys < 1 || n_sys > SYS_CAP || !offsets || !params) {
+        c->err = "lp_set_systems: 1 <= n_sys <= 4096 with host offsets and params";
+        return LP_E_ARG;
+    }
+    if (offsets[0] != 0) {
+        c->err = "offsets[0] must be 0";
+        return LP_E_ARG;
+    }
+    for (int s = 0; s < n_sys; ++s) {
+        if (offsets[s + 1] < offsets[s]) {
+            c->err = "offsets must be non-decreasing";
+            return LP_E_ARG;
+        }
+        const lp_params& p = params[s];
+        const bool ok = p.phi_min < p.phi_max && p.phi_max < p.phi_c &&
+                        p.phi_min > 0.0 && p.beta > 0.0 && p.R > 0.0 &&
+                        p.h > 0.0 && p.rho_s > 0.0 && p.d > 0.0 && p.I0 > 0.0 &&
+                        std::isfinite(p.wall_z) && std::isfinite(p.alpha) &&
+                        std::isfinite(p.g[0]) && std::isfinite(p.g[1]) &&
+                        std::isfinite(p.g[2]) && std::isfinite(p.mu_s) &&
+                        std::isfinite(p.mu_2);
+        if (!ok) {
+            c->err = "invalid parameters of system " + std::to_string(s);
+            return LP_E_ARG;
+        }
+    }
+    if (offsets[n_sys] >= (1ll << 27)) {
+        c->err = "at most 2^27 - 1 particles";
+        return LP_E_ARG;
+    }
+    c->h_off.assign(offsets, offsets + n_sys + 1);
+    c->h_prm.assign(params, params + n_sys);
+    c->n_sys = n_sys;
+    c->n = offsets[n_sys];
+    c->cells_ok = c->stencils_ok = false;
+    if (c->w.n_max == 0) return LP_OK;   // uploaded by lp_reserve
+    hipError_t e = hipMemcpyAsync(c->w.off, c->h_off.data(),
+                                  sizeof(int64_t) * (n_sys + 1),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->w.prm, c->h_prm.data(), sizeof(lp_params) * n_sys,
+                           hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lp_set_systems upload");
+    return LP_OK;
+}
+
+lp_status lp_build_cells(lp_ctx* c, lp_state* s, int32_t* perm)
+{
+    if (!s) return LP_E_ARG;
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    double* st[7];
+    state_arrays(s, st);
+    r = cells_build(c, st, perm, true, st);
+    if (r == LP_OK) c->built_x = s->x;
+    return r;
+}
+
+lp_status lp_neighbors(lp_ctx* c, const lp_state* s, int64_t* cand_off,
+                       int32_t* cand_idx, int64_t cap, int64_t* needed,
+                       int32_t* sten_cnt, int32_t* sten_idx,
+                       uint8_t* ghost_mask, int64_t* n_mirror)
+{
+    if (!s) return LP_E_ARG;
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    if (!c->cells_ok || c->built_x != s->x) {
+        c->err = "lp_build_cells must be called on this state first";
+        return LP_E_STATE;
+    }
+    double* st[7];
+    state_arrays(s, st);
+    r = stencils_build(c, st);
+    if (r != LP_OK) return r;
+    if (n_mirror) *n_mirror = c->n_mirror;
+    return stencils_export(c, st, cand_off, cand_idx, cap, needed, sten_cnt,
+                           sten_idx, ghost_mask);
+}
+
+lp_status lp_fit_derivs(lp_ctx* c, const lp_state* s, const double* f,
+                        int32_t k, const int32_t* mirror_sign,
+                        const int32_t* ghost_zero, double* coef,
+                        uint8_t* flags)
+{
+    if (!s || !f || !coef || !mirror_sign || !ghost_zero || k < 1 || k > 8) {
+        if (c) c->err = "lp_fit_derivs: 1 <= k <= 8 and non-null arrays";
+        return LP_E_ARG;
+    }
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    if (!c->stencils_ok || c->built_x != s->x) {
+        c->err = "lp_neighbors must be called on this state first";
+        return LP_E_STATE;
+    }
+    double* st[7];
+    state_arrays(s, st);
+    return fit_generic(c, st, f, k, mirror_sign, ghost_zero, coef, flags);
+}
+
+lp_status lp_rheology_rhs(lp_ctx* c, const lp_state* s, const double* coef_u,
+                          double* dVdt, double* acc, double* diag, double* grad,
+                          uint8_t* flags)
+{
+    if (!s || !coef_u || !dVdt || !acc) {
+        if (c) c->err = "lp_rheology_rhs: coef_u, dVdt and acc are required";
+        return LP_E_ARG;
+    }
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    if (!c->stencils_ok || c->built_x != s->x) {
+        c->err = "lp_neighbors must be called on this state first";
+        return LP_E_STATE;
+    }
+    double* st[7];
+    state_arrays(s, st);
+    return rhs_from_coef(c, st, coef_u, dVdt, acc, diag, grad, flags);
+}
+
+lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
+{
+    if (!s || !(dt > 0.0) || !std::isfinite(dt)) {
+        if (c) c->err = "lp_step: dt must be positive and finite";
+        return LP_E_ARG;
+    }
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    double* in[7];
+    state_arrays(s, in);
+    prof_mark(c, 0, false);
+    r = cells_build(c, in, perm, false, in);
+    prof_mark(c, 0, true);
+    if (r != LP_OK) return r;
+    const double* sorted[7];
+    double* const* sst = c->w.sst;
+    for (int a = 0; a < 7; ++a) sorted[a] = sst[a];
+    r = stencils_build(c, sorted);
+    if (r == LP_OK) r = step_rhs(c, sorted);
+    if (r == LP_OK) r = step_update(c, sorted, dt, in);
+    // the cell tables describe the positions before the update
+    c->cells_ok = c->stencils_ok = false;
+    c->built_x = nullptr;
+    if (r == LP_OK && c->prof) {
+        hipError_t e = hipEventSynchronize(c->ev[13]);
+        if (e != hipSuccess) return hip_fail(c, e, "profile sync");
+        for (int ph = 0; ph < 7; ++ph) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev[2 * ph], c->ev[2 * ph + 1]) == hipSuccess)
+                c->prof_ms[ph] += ms;
+        }
+        ++c->prof_steps;
+    }
+    return r;
+}
+
+lp_status lp_profile(lp_ctx* c, int32_t enable)
+{
+    if (!c) return LP_E_ARG;
+    if (enable && !c->ev[0])
+        for (int q = 0; q < 16; ++q) {
+            hipError_t e = hipEventCreate(&c->ev[q]);
+            if (e != hipSuccess) return hip_fail(c, e, "lp_profile");
+        }
+    c->prof = enable != 0;
+    return LP_OK;
+}
+
+lp_status lp_profile_read(lp_ctx* c, double* ms8, int64_t* steps)
+{
+    if (!c || !ms8) return LP_E_ARG;
+    for (int q = 0; q < 8; ++q) {
+        ms8[q] = c->prof_ms[q];
+        c->prof_ms[q] = 0.0;
+    }
+    if (steps) *steps = c->prof_steps;
+    c->prof_steps = 0;
+    return LP_OK;
+}
+
+lp_status lp_step_adjoint(lp_ctx* c)
+{
+    if (c) c->err = "lp_step_adjoint is not available in this version";
+    return LP_E_STATE;
+}
+
+lp_status lp_sync_status(lp_ctx* c, int64_t* index)
+{
+    if (!c) return LP_E_ARG;
+    if (index) *index = -1;
+    if (!c->w.err) return LP_OK;
+    ErrWord ew;
+    hipError_t e = hipMemcpyAsync(&ew, c->w.err, sizeof(ew), hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lp_sync_status");
+    if (ew.code == 0) return LP_OK;
+    ErrWord clear{0, 0, ~0ull};
+    e = hipMemcpyAsync(c->w.err, &clear, sizeof(clear), hipMemcpyHostToDevice,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (index) *index = (int64_t)ew.index;
+    if (ew.code & ERR_CAPACITY) {
+        c->err = "device capacity exceeded (too many candidates for the sorted "
+                 "stencil path) at particle " + std::to_string(ew.index);
+        return LP_E_CAPACITY;
+    }
+    c->err = "non-finite state at particle " + std::to_string(ew.index);
+    return LP_E_NUMERIC;
+}
+
+lp_status lp_stats(lp_ctx* c, int64_t* out8)
+{
+    if (!c || !out8) return LP_E_ARG;
+    for (int q = 0; q < 8; ++q) out8[q] = 0;
+    out8[0] = c->n;
+    out8[1] = c->n_mirror;
+    if (!c->w.cnt) return LP_OK;
+    Counters k;
+    hipError_t e = hipMemcpyAsync(&k, c->w.cnt, sizeof(k), hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lp_stats");
+    out8[2] = (int64_t)k.qr_refits;
+    out8[3] = (int64_t)k.hard_stencils;
+    out8[4] = (int64_t)k.below_wall;
+    Counters z{};
+    e = hipMemcpyAsync(c->w.cnt, &z, sizeof(z), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "lp_stats reset");
+}
+
+}  // extern "C"

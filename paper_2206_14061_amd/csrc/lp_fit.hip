@@ -1,0 +1,995 @@
+// Least-squares derivatives (Sec. 3.1 step 7), mu(I) closure (Sec. 2.2,
+// 2.2.1), right-hand side (Sec. 2.1) and explicit update (Sec. 3.1 steps
+// 8 and 10).
+//
+// Fit: one thread per particle accumulates the 9x9 Gram matrix
+// G = sum_r w a_r a_r^T and the moments sum_r w a_r b_r of its Taylor rows
+// (stencil rows plus ghost rows), factors G = U^T U (Cholesky) and solves.
+// The rows are scaled by 1/h, so G is well conditioned on every regular
+// stencil (the pivot ratio min U_jj / max U_jj is checked); this needs no
+// cross-lane reductions and keeps every accumulator in registers.  A
+// stencil whose pivot ratio falls below the refit threshold is refitted
+// by float64 Householder QR (one thread, matrix in global scratch), which
+// also applies the rank test min|r_jj|/max|r_jj| < fallback_tol.
+//
+// The second fit (P, eta) needs only first derivatives: pass 1 stores
+// rows 0-2 of G^{-1}, so pass 2 costs two moment accumulations and a 3x9
+// product per particle.
+#include "lp_internal.h"
+
+namespace lp {
+
+namespace {
+
+inline unsigned int blocks_for(int64_t n, int per = BLOCK)
+{
+    return (unsigned int)((n + per - 1) / per);
+}
+
+// upper-triangle index of (i, j), i <= j, in a packed 9x9
+__host__ __device__ constexpr int uix(int i, int j)
+{
+    return i * 9 - (i * (i - 1)) / 2 + (j - i);
+}
+
+__device__ __forceinline__ void taylor_row(double ex, double ey, double ez,
+                                           double a[9])
+{
+    a[0] = ex;
+    a[1] = ey;
+    a[2] = ez;
+    a[3] = 0.5 * ex * ex;
+    a[4] = 0.5 * ey * ey;
+    a[5] = 0.5 * ez * ez;
+    a[6] = ex * ey;
+    a[7] = ex * ez;
+    a[8] = ey * ez;
+}
+
+__device__ __forceinline__ void ghost_offset(int o, double& sx, double& sy,
+                                             double& sz)
+{
+    sx = (o & 1) ? 1.0 : -1.0;
+    sy = (o & 2) ? 1.0 : -1.0;
+    sz = (o & 4) ? 1.0 : -1.0;
+}
+
+// Coordinates of point j (real or mirror).
+__device__ __forceinline__ void point_xyz(const View& v, int32_t j, double& x,
+                                          double& y, double& z)
+{
+    if (j < v.n) {
+        x = v.x[j];
+        y = v.y[j];
+        z = v.z[j];
+    } else {
+        const int32_t q = j - (int32_t)v.n;
+        x = v.mx[q];
+        y = v.my[q];
+        z = v.mz[q];
+    }
+}
+
+// Row k of particle i's fit (k < m: stencil entry; else ghost number
+// k - m in octant order).  Returns the weight; point id in *jout (-1 for
+// a ghost).
+__device__ __forceinline__ double fit_row(const View& v, const GridInfo& g,
+                                          int64_t i, double xi, double yi,
+                                          double zi, int k, int m, uint8_t gm,
+                                          double a[9], int32_t* jout)
+{
+    if (k < m) {
+        const int32_t j = v.sten[(int64_t)k * v.n + i];
+        double xj, yj, zj;
+        point_xyz(v, j, xj, yj, zj);
+        const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+        taylor_row(dx * g.inv_h, dy * g.inv_h, dz * g.inv_h, a);
+        *jout = j;
+        if (v.weight == LP_W_GAUSS)
+            return exp(-4.0 * (dx * dx + dy * dy + dz * dz) / g.R2);
+        return 1.0;
+    }
+    int r = k - m, o = 0;
+    for (; o < 8; ++o)
+        if ((gm >> o) & 1) {
+            if (r == 0) break;
+            --r;
+        }
+    double sx, sy, sz;
+    ghost_offset(o, sx, sy, sz);
+    taylor_row(sx, sy, sz, a);
+    *jout = -1;
+    if (v.weight == LP_W_GAUSS) return exp(-12.0 * g.h * g.h / g.R2);
+    return 1.0;
+}
+
+// G = U^T U in place (packed upper); returns min U_jj / max U_jj, or -1
+// when a pivot is not positive.
+template <int N>
+__device__ __forceinline__ double cholesky(double (&G)[45])
+{
+    double dmin = INFINITY, dmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double s = G[uix(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= G[uix(k, j)] * G[uix(k, j)];
+        if (!(s > 0.0)) return -1.0;
+        const double d = sqrt(s);
+        const double inv = 1.0 / d;
+        G[uix(j, j)] = d;
+        dmin = fmin(dmin, d);
+        dmax = fmax(dmax, d);
+#pragma unroll
+        for (int l = j + 1; l < N; ++l) {
+            double t = G[uix(j, l)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= G[uix(k, j)] * G[uix(k, l)];
+            G[uix(j, l)] = t * inv;
+        }
+    }
+    return dmin / dmax;
+}
+
+// Solves U^T U c = b in place (b -> c).
+template <int N>
+__device__ __forceinline__ void chol_solve(const double (&U)[45], double (&b)[9])
+{
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double t = b[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) t -= U[uix(k, j)] * b[k];
+        b[j] = t / U[uix(j, j)];
+    }
+#pragma unroll
+    for (int j = N - 1; j >= 0; --j) {
+        double t = b[j];
+#pragma unroll
+        for (int k = j + 1; k < N; ++k) t -= U[uix(j, k)] * b[k];
+        b[j] = t / U[uix(j, j)];
+    }
+}
+
+// ---- closure (Sec. 2.2 and 2.2.1) --------------------------------------
+
+struct Closure {
+    double gd[6];       // xx yy zz xy xz yz of the shear-rate tensor
+    double div, gn, P, eta, I, mu;
+    int branch;         // 0 gas, 1 inertial, 2 quasi-static
+};
+
+// c[f*9 + q]: derivative q of velocity component f.
+__device__ __forceinline__ Closure closure(const lp_params& p, double V,
+                                           const double* c)
+{
+    Closure r;
+    const double gxx = c[0], gyy = c[9 + 1], gzz = c[18 + 2];
+    r.div = gxx + gyy + gzz;
+    const double third = r.div / 3.0;
+    r.gd[0] = gxx - third;
+    r.gd[1] = gyy - third;
+    r.gd[2] = gzz - third;
+    r.gd[3] = 0.5 * (c[1] + c[9 + 0]);      // (du/dy + dv/dx)/2
+    r.gd[4] = 0.5 * (c[2] + c[18 + 0]);     // (du/dz + dw/dx)/2
+    r.gd[5] = 0.5 * (c[9 + 2] + c[18 + 1]); // (dv/dz + dw/dy)/2
+    const double ss = r.gd[0] * r.gd[0] + r.gd[1] * r.gd[1] + r.gd[2] * r.gd[2] +
+                      2.0 * (r.gd[3] * r.gd[3] + r.gd[4] * r.gd[4] + r.gd[5] * r.gd[5]);
+    r.gn = sqrt(0.5 * ss);
+    const double phi = 1.0 / V;
+    r.P = r.eta = r.I = r.mu = 0.0;
+    if (phi <= p.phi_min) {
+        r.branch = 0;
+    } else if (phi <= p.phi_max) {
+        r.branch = 1;
+        const double a = p.phi_c - p.phi_min;
+        const double w = p.phi_c - phi;
+        const double k = 2.0 * a * p.d / w;
+        r.P = p.rho_s * (k * r.gn) * (k * r.gn);
+        r.I = w / a;
+        r.mu = p.mu_s + (p.mu_2 - p.mu_s) / (p.I0 / r.I + 1.0);
+        r.eta = p.rho_s * r.mu * k * k * r.gn;
+    } else {
+        r.branch = 2;
+        r.P = p.rho_s * (p.alpha + p.beta * phi);
+    }
+    return r;
+}
+
+__device__ __forceinline__ double mirror_pressure(const lp_params& p, double V)
+{
+    const double phi = 1.0 / V;
+    return phi > p.phi_max ? p.rho_s * (p.alpha + p.beta * phi) : 0.0;
+}
+
+// Lap u_a / 2 + d_a div u / 6 from the velocity coefficients.
+__device__ __forceinline__ void visc_terms(const double* c, double vis[3])
+{
+    const double lap0 = c[3] + c[4] + c[5];
+    const double lap1 = c[9 + 3] + c[9 + 4] + c[9 + 5];
+    const double lap2 = c[18 + 3] + c[18 + 4] + c[18 + 5];
+    const double gd0 = c[3] + c[9 + 6] + c[18 + 7];
+    const double gd1 = c[6] + c[9 + 4] + c[18 + 8];
+    const double gd2 = c[7] + c[9 + 8] + c[18 + 5];
+    vis[0] = 0.5 * lap0 + gd0 / 6.0;
+    vis[1] = 0.5 * lap1 + gd1 / 6.0;
+    vis[2] = 0.5 * lap2 + gd2 / 6.0;
+}
+
+// Handoff layout: [0,27) rows 0-2 of G^-1 (row-major 3x9), [27,33) gd,
+// 33 div, [34,37) viscous terms.
+__device__ __forceinline__ void store_hand(double* hand, int64_t n, int64_t i,
+                                           const double* ginv3, const Closure& r,
+                                           const double vis[3])
+{
+    if (ginv3)
+        for (int q = 0; q < 27; ++q) hand[(int64_t)q * n + i] = ginv3[q];
+    for (int q = 0; q < 6; ++q) hand[(int64_t)(27 + q) * n + i] = r.gd[q];
+    hand[(int64_t)33 * n + i] = r.div;
+    for (int q = 0; q < 3; ++q) hand[(int64_t)(34 + q) * n + i] = vis[q];
+}
+
+// rows 0-2 of G^{-1} from the factor (3 solves with unit vectors)
+template <int N>
+__device__ __forceinline__ void ginv_rows(const double (&U)[45], double out[27])
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double e[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) e[q] = (q == r) ? 1.0 : 0.0;
+        chol_solve<N>(U, e);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) out[r * 9 + q] = (q < N) ? e[q] : 0.0;
+    }
+}
+
+// ---- Householder QR for refits -----------------------------------------
+
+// min || A c - B || for A (mt x nc, leading dim 9) and nf right-hand sides
+// (leading dim 8) in scratch; C (nc x nf) receives the solution.  Returns
+// min|r_jj| / max|r_jj|.
+__device__ double qr_solve(double* A, double* B, int mt, int nc, int nf,
+                           double* C)
+{
+    double rd[9];
+    double rmin = INFINITY, rmax = 0.0;
+    for (int j = 0; j < nc; ++j) {
+        double s = 0.0;
+        for (int r = j; r < mt; ++r) s += A[r * 9 + j] * A[r * 9 + j];
+        const double nrm = sqrt(s);
+        const double ajj = A[j * 9 + j];
+        if (nrm == 0.0) {
+            rd[j] = 0.0;
+            rmin = 0.0;
+            continue;
+        }
+        const double alpha = ajj >= 0.0 ? -nrm : nrm;
+        A[j * 9 + j] = ajj - alpha;             // Householder vector in column j
+        const double beta = 1.0 / (nrm * (nrm + fabs(ajj)));  // 2 / v^T v
+        for (int l = j + 1; l < nc; ++l) {
+            double dot = 0.0;
+            for (int r = j; r < mt; ++r) dot += A[r * 9 + j] * A[r * 9 + l];
+            const double f = beta * dot;
+            for (int r = j; r < mt; ++r) A[r * 9 + l] -= f * A[r * 9 + j];
+        }
+        for (int l = 0; l < nf; ++l) {
+            double dot = 0.0;
+            for (int r = j; r < mt; ++r) dot += A[r * 9 + j] * B[r * 8 + l];
+            const double f = beta * dot;
+            for (int r = j; r < mt; ++r) B[r * 8 + l] -= f * A[r * 9 + j];
+        }
+        rd[j] = alpha;
+        rmin = fmin(rmin, fabs(alpha));
+        rmax = fmax(rmax, fabs(alpha));
+    }
+    for (int l = 0; l < nf; ++l)
+        for (int j = nc - 1; j >= 0; --j) {
+            double t = B[j * 8 + l];
+            for (int q = j + 1; q < nc; ++q) t -= A[j * 9 + q] * C[q * 8 + l];
+            C[j * 8 + l] = rd[j] != 0.0 ? t / rd[j] : 0.0;
+        }
+    return rmax > 0.0 ? rmin / rmax : 0.0;
+}
+
+// Field values at a point and at the ghosts.
+struct GenericFields {
+    const double* f;   // k x n
+    int k;
+    int32_t msign[8];
+    int32_t gzero[8];
+};
+
+template <class Get>
+__device__ uint8_t qr_fit_point(const View& v, const GridInfo& g, int64_t i,
+                                int nf, Get&& get, double* scratch,
+                                double* coef /* nf x 9, ld 9 */)
+{
+    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const int m = min(max(v.scnt[i], 0), v.m_max);
+    const uint8_t gm = v.gmask[i];
+    const int mt = m + __popc(gm);
+    double* A = scratch;
+    double* B = scratch + MAXROWS * 9;
+    double fi[8];
+    get(-2, fi);   // own values
+    auto build = [&]() {
+        for (int k = 0; k < mt; ++k) {
+            double a[9];
+            int32_t j;
+            const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
+            const double sw = sqrt(w);
+            double fj[8];
+            get(j, fj);
+            for (int q = 0; q < 9; ++q) A[k * 9 + q] = sw * a[q];
+            for (int f = 0; f < nf; ++f) B[k * 8 + f] = sw * (fj[f] - fi[f]);
+        }
+    };
+    double C[9 * 8];
+    uint8_t flags = FLAG_QR;
+    double ratio = 0.0;
+    if (mt >= 9) {
+        build();
+        ratio = qr_solve(A, B, mt, 9, nf, C);
+    }
+    if (mt < 9 || ratio < v.fallback_tol) {
+        flags |= FLAG_LINEAR;
+        for (int q = 0; q < 72; ++q) C[q] = 0.0;
+        if (mt >= 3) {
+            build();
+            qr_solve(A, B, mt, 3, nf, C);
+        }
+    }
+    for (int f = 0; f < nf; ++f)
+        for (int q = 0; q < 9; ++q)
+            coef[f * 9 + q] = C[q * 8 + f] * (q < 3 ? g.inv_h : g.inv_h * g.inv_h);
+    return flags;
+}
+
+// ---- lp_fit_derivs -------------------------------------------------------
+
+template <int NF>
+__global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
+                                                       double* coef, uint8_t* flags,
+                                                       int32_t* redo,
+                                                       unsigned int* redo_n,
+                                                       int force_qr)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= v.n) return;
+    const int64_t n = v.n;
+    const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
+    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const int m = min(max(v.scnt[i], 0), v.m_max);
+    const uint8_t gm = v.gmask[i];
+    const int mt = m + __popc(gm);
+    double fi[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) fi[f] = F.f[(int64_t)f * n + i];
+    double G[45], B[NF][9];
+#pragma unroll
+    for (int q = 0; q < 45; ++q) G[q] = 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) B[f][q] = 0.0;
+    for (int k = 0; k < mt; ++k) {
+        double a[9];
+        int32_t j;
+        const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
+        double b[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            double fj;
+            if (j < 0) fj = F.gzero[f] ? 0.0 : fi[f];
+            else if (j < n) fj = F.f[(int64_t)f * n + j];
+            else fj = (double)F.msign[f] * F.f[(int64_t)f * n + v.msrc[j - n]];
+            b[f] = w * (fj - fi[f]);
+        }
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const double wa = w * a[p];
+#pragma unroll
+            for (int q = p; q < 9; ++q) G[uix(p, q)] += wa * a[q];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) B[f][p] += a[p] * b[f];
+        }
+    }
+    uint8_t fl = 0;
+    double c[NF][9];
+    if (mt < 9) {
+        fl = FLAG_LINEAR;
+        const double ratio = cholesky<3>(G);
+        if (ratio < v.redo_ratio || force_qr) goto refit;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) c[f][q] = q < 3 ? B[f][q] : 0.0;
+            chol_solve<3>(G, c[f]);
+        }
+    } else {
+        const double ratio = cholesky<9>(G);
+        if (ratio < v.redo_ratio || force_qr) goto refit;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) c[f][q] = B[f][q];
+            chol_solve<9>(G, c[f]);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            coef[((int64_t)f * 9 + q) * n + i] =
+                c[f][q] * (q < 3 ? g.inv_h : g.inv_h * g.inv_h);
+    if (flags) flags[i] = fl;
+    return;
+refit:
+    redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
+    if (flags) flags[i] = FLAG_QR;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fit_generic_qr(
+    View v, GenericFields F, double* coef, uint8_t* flags, const int32_t* redo,
+    const unsigned int* redo_n, double* scratch, Counters* cnt)
+{
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const unsigned int total = *redo_n;
+    if (slot == 0) atomicAdd(&cnt->qr_refits, (unsigned long long)total);
+    double* scr = scratch + slot * (MAXROWS * 17);
+    const int64_t n = v.n;
+    for (int64_t t = slot; t < (int64_t)total; t += nth) {
+        const int64_t i = redo[t];
+        const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
+        auto get = [&](int32_t j, double* out) {
+            for (int f = 0; f < F.k; ++f) {
+                const double own = F.f[(int64_t)f * n + i];
+                if (j == -2) out[f] = own;
+                else if (j < 0) out[f] = F.gzero[f] ? 0.0 : own;
+                else if (j < n) out[f] = F.f[(int64_t)f * n + j];
+                else out[f] = (double)F.msign[f] * F.f[(int64_t)f * n + v.msrc[j - n]];
+            }
+        };
+        double c[8 * 9];
+        const uint8_t fl = qr_fit_point(v, g, i, F.k, get, scr, c);
+        for (int f = 0; f < F.k; ++f)
+            for (int q = 0; q < 9; ++q) coef[((int64_t)f * 9 + q) * n + i] = c[f * 9 + q];
+        if (flags) flags[i] = fl;
+    }
+}
+
+// ---- lp_step pass 1: fit u, v, w + closure --------------------------------
+
+struct StepOut {
+    double* P;
+    double* eta;
+    double* hand;
+    uint8_t* flags;
+    double* diag;       // optional 5 x n
+    double* coef_u;     // optional 27 x n
+};
+
+__device__ __forceinline__ void finish_pass1(const View& v, const lp_params& p,
+                                             int64_t i, const double* c,
+                                             const double* ginv3, uint8_t fl,
+                                             const StepOut& o)
+{
+    const int64_t n = v.n;
+    const Closure r = closure(p, v.V[i], c);
+    double vis[3];
+    visc_terms(c, vis);
+    o.P[i] = r.P;
+    o.eta[i] = r.eta;
+    store_hand(o.hand, n, i, ginv3, r, vis);
+    o.flags[i] = (uint8_t)(fl | (r.branch << 1));
+    if (o.diag) {
+        o.diag[i] = r.P;
+        o.diag[n + i] = r.eta;
+        o.diag[2 * n + i] = r.I;
+        o.diag[3 * n + i] = r.mu;
+        o.diag[4 * n + i] = r.gn;
+    }
+    if (o.coef_u)
+        for (int q = 0; q < 27; ++q) o.coef_u[(int64_t)q * n + i] = c[q];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pass1(View v, StepOut o,
+                                                 int32_t* redo,
+                                                 unsigned int* redo_n,
+                                                 int force_qr)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= v.n) return;
+    const int64_t n = v.n;
+    const int s = sys_of(v.off, v.n_sys, i);
+    const GridInfo& g = v.grid[s];
+    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
+    const int m = min(max(v.scnt[i], 0), v.m_max);
+    const uint8_t gm = v.gmask[i];
+    const int mt = m + __popc(gm);
+    double G[45], B[3][9];
+#pragma unroll
+    for (int q = 0; q < 45; ++q) G[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) B[0][q] = B[1][q] = B[2][q] = 0.0;
+    for (int k = 0; k < mt; ++k) {
+        double a[9];
+        int32_t j;
+        const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0;   // ghosts carry u_i (b = 0)
+        if (j >= 0 && j < n) {
+            b0 = w * (v.u[j] - ui);
+            b1 = w * (v.v[j] - vi);
+            b2 = w * (v.w[j] - wi);
+        } else if (j >= n) {
+            const int32_t q = j - (int32_t)n;
+            b0 = w * (v.mu[q] - ui);
+            b1 = w * (v.mv[q] - vi);
+            b2 = w * (v.mw[q] - wi);
+        }
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const double wa = w * a[p];
+#pragma unroll
+            for (int q = p; q < 9; ++q) G[uix(p, q)] += wa * a[q];
+            B[0][p] += a[p] * b0;
+            B[1][p] += a[p] * b1;
+            B[2][p] += a[p] * b2;
+        }
+    }
+    double c[27], ginv3[27];
+    uint8_t fl = 0;
+    if (mt < 9) {
+        fl = FLAG_LINEAR;
+        const double ratio = cholesky<3>(G);
+        if (ratio < v.redo_ratio || force_qr) goto refit;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            double t[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) t[q] = q < 3 ? B[f][q] : 0.0;
+            chol_solve<3>(G, t);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) c[f * 9 + q] = t[q];
+        }
+        ginv_rows<3>(G, ginv3);
+    } else {
+        const double ratio = cholesky<9>(G);
+        if (ratio < v.redo_ratio || force_qr) goto refit;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            double t[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) t[q] = B[f][q];
+            chol_solve<9>(G, t);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) c[f * 9 + q] = t[q];
+        }
+        ginv_rows<9>(G, ginv3);
+    }
+#pragma unroll
+    for (int q = 0; q < 27; ++q) c[q] *= ((q % 9) < 3 ? g.inv_h : g.inv_h * g.inv_h);
+    finish_pass1(v, v.prm[s], i, c, ginv3, fl, o);
+    return;
+refit:
+    redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
+    o.flags[i] = FLAG_QR;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pass1_qr(View v, StepOut o,
+                                                    const int32_t* redo,
+                                                    const unsigned int* redo_n,
+                                                    double* scratch, Counters* cnt)
+{
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const unsigned int total = *redo_n;
+    if (slot == 0) atomicAdd(&cnt->qr_refits, (unsigned long long)total);
+    double* scr = scratch + slot * (MAXROWS * 17);
+    const int64_t n = v.n;
+    for (int64_t t = slot; t < (int64_t)total; t += nth) {
+        const int64_t i = redo[t];
+        const int s = sys_of(v.off, v.n_sys, i);
+        const GridInfo& g = v.grid[s];
+        auto get = [&](int32_t j, double* out) {
+            if (j == -2 || j == -1) {
+                out[0] = v.u[i]; out[1] = v.v[i]; out[2] = v.w[i];
+            } else if (j < n) {
+                out[0] = v.u[j]; out[1] = v.v[j]; out[2] = v.w[j];
+            } else {
+                const int32_t q = j - (int32_t)n;
+                out[0] = v.mu[q]; out[1] = v.mv[q]; out[2] = v.mw[q];
+            }
+        };
+        double c[27];
+        const uint8_t fl = qr_fit_point(v, g, i, 3, get, scr, c);
+        finish_pass1(v, v.prm[s], i, c, nullptr, fl, o);
+    }
+}
+
+// lp_rheology_rhs: closure from given coefficients, Gram factor for pass 2
+__global__ __launch_bounds__(BLOCK) void k_closure_coef(View v, const double* coef_u,
+                                                        StepOut o, int32_t* redo,
+                                                        unsigned int* redo_n,
+                                                        int force_qr)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= v.n) return;
+    const int64_t n = v.n;
+    const int s = sys_of(v.off, v.n_sys, i);
+    const GridInfo& g = v.grid[s];
+    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const int m = min(max(v.scnt[i], 0), v.m_max);
+    const uint8_t gm = v.gmask[i];
+    const int mt = m + __popc(gm);
+    double c[27];
+    for (int q = 0; q < 27; ++q) c[q] = coef_u[(int64_t)q * n + i];
+    double G[45];
+#pragma unroll
+    for (int q = 0; q < 45; ++q) G[q] = 0.0;
+    for (int k = 0; k < mt; ++k) {
+        double a[9];
+        int32_t j;
+        const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const double wa = w * a[p];
+#pragma unroll
+            for (int q = p; q < 9; ++q) G[uix(p, q)] += wa * a[q];
+        }
+    }
+    double ginv3[27];
+    uint8_t fl = 0;
+    bool qr = force_qr != 0;
+    if (mt < 9) {
+        fl = FLAG_LINEAR;
+        const double ratio = cholesky<3>(G);
+        qr = qr || ratio < v.redo_ratio;
+        if (!qr) ginv_rows<3>(G, ginv3);
+    } else {
+        const double ratio = cholesky<9>(G);
+        qr = qr || ratio < v.redo_ratio;
+        if (!qr) ginv_rows<9>(G, ginv3);
+    }
+    if (qr) {
+        redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
+        fl = FLAG_QR;
+    }
+    finish_pass1(v, v.prm[s], i, c, qr ? nullptr : ginv3, fl, o);
+}
+
+// ---- pass 2: fit of P and eta, right-hand side, update --------------------
+
+struct RhsOut {
+    double* acc;        // 3 x n (optional in step mode)
+    double* dVdt;       // n (optional in step mode)
+    double* grad;       // 6 x n optional
+    double* out[7];     // new state (step mode) or nulls
+    double dt;
+    ErrWord* err;
+    Counters* cnt;
+};
+
+__device__ __forceinline__ void finish_rhs(const View& v, const lp_params& p,
+                                           int64_t i, const double* hand,
+                                           const double gP[3], const double gE[3],
+                                           const RhsOut& o)
+{
+    const int64_t n = v.n;
+    const double V = v.V[i];
+    const double eta = hand[0];   // own eta passed through hand[0]
+    const double* gd = hand + 1;  // xx yy zz xy xz yz
+    const double div = hand[7];
+    const double* vis = hand + 8;
+    double a[3];
+    const double t0 = gd[0] * gE[0] + gd[3] * gE[1] + gd[4] * gE[2];
+    const double t1 = gd[3] * gE[0] + gd[1] * gE[1] + gd[5] * gE[2];
+    const double t2 = gd[4] * gE[0] + gd[5] * gE[1] + gd[2] * gE[2];
+    a[0] = V * (-gP[0] + t0 + eta * vis[0]) / p.rho_s + p.g[0];
+    a[1] = V * (-gP[1] + t1 + eta * vis[1]) / p.rho_s + p.g[1];
+    a[2] = V * (-gP[2] + t2 + eta * vis[2]) / p.rho_s + p.g[2];
+    const double dV = V * div;
+    if (o.acc) {
+        o.acc[i] = a[0];
+        o.acc[n + i] = a[1];
+        o.acc[2 * n + i] = a[2];
+    }
+    if (o.dVdt) o.dVdt[i] = dV;
+    if (o.grad)
+        for (int q = 0; q < 3; ++q) {
+            o.grad[(int64_t)q * n + i] = gP[q];
+            o.grad[(int64_t)(3 + q) * n + i] = gE[q];
+        }
+    if (o.out[0]) {
+        const double dt = o.dt;
+        const double un = v.u[i] + dt * a[0];
+        const double vn = v.v[i] + dt * a[1];
+        const double wn = v.w[i] + dt * a[2];
+        const double xn = v.x[i] + dt * (0.5 * (v.u[i] + un));
+        const double yn = v.y[i] + dt * (0.5 * (v.v[i] + vn));
+        const double zn = v.z[i] + dt * (0.5 * (v.w[i] + wn));
+        const double Vn = V + dt * dV;
+        o.out[0][i] = xn;
+        o.out[1][i] = yn;
+        o.out[2][i] = zn;
+        o.out[3][i] = un;
+        o.out[4][i] = vn;
+        o.out[5][i] = wn;
+        o.out[6][i] = Vn;
+        const bool finite = isfinite(xn) && isfinite(yn) && isfinite(zn) &&
+                            isfinite(un) && isfinite(vn) && isfinite(wn) &&
+                            isfinite(Vn);
+        if (!finite) raise_error(o.err, ERR_NUMERIC, i);
+        if (zn < p.wall_z) atomicAdd(&o.cnt->below_wall, 1ull);
+    }
+}
+
+__device__ __forceinline__ void pass2_values(const View& v, const double* P,
+                                             const double* eta, int32_t j,
+                                             const lp_params& p, double& Pj,
+                                             double& Ej)
+{
+    if (j < 0) {
+        Pj = 0.0;
+        Ej = 0.0;
+    } else if (j < v.n) {
+        Pj = P[j];
+        Ej = eta[j];
+    } else {
+        Pj = mirror_pressure(p, v.mV[j - v.n]);
+        Ej = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
+                                                 const double* eta,
+                                                 const double* hand,
+                                                 const uint8_t* flags, RhsOut o)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= v.n) return;
+    if (flags[i] & FLAG_QR) return;
+    const int64_t n = v.n;
+    const int s = sys_of(v.off, v.n_sys, i);
+    const GridInfo& g = v.grid[s];
+    const lp_params& p = v.prm[s];
+    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const double Pi = P[i], Ei = eta[i];
+    const int m = min(max(v.scnt[i], 0), v.m_max);
+    const uint8_t gm = v.gmask[i];
+    const int mt = m + __popc(gm);
+    double yP[9], yE[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) yP[q] = yE[q] = 0.0;
+    for (int k = 0; k < mt; ++k) {
+        double a[9];
+        int32_t j;
+        const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
+        double Pj, Ej;
+        pass2_values(v, P, eta, j, p, Pj, Ej);
+        const double bP = w * (Pj - Pi), bE = w * (Ej - Ei);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            yP[q] += a[q] * bP;
+            yE[q] += a[q] * bE;
+        }
+    }
+    double gP[3], gE[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double sp = 0.0, se = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const double gi = hand[(int64_t)(r * 9 + q) * n + i];
+            sp += gi * yP[q];
+            se += gi * yE[q];
+        }
+        gP[r] = sp * g.inv_h;
+        gE[r] = se * g.inv_h;
+    }
+    double hv[11];
+    hv[0] = Ei;
+    for (int q = 0; q < 6; ++q) hv[1 + q] = hand[(int64_t)(27 + q) * n + i];
+    hv[7] = hand[(int64_t)33 * n + i];
+    for (int q = 0; q < 3; ++q) hv[8 + q] = hand[(int64_t)(34 + q) * n + i];
+    finish_rhs(v, p, i, hv, gP, gE, o);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pass2_qr(View v, const double* P,
+                                                    const double* eta,
+                                                    const double* hand,
+                                                    const int32_t* redo,
+                                                    const unsigned int* redo_n,
+                                                    double* scratch, RhsOut o)
+{
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const unsigned int total = *redo_n;
+    double* scr = scratch + slot * (MAXROWS * 17);
+    const int64_t n = v.n;
+    for (int64_t t = slot; t < (int64_t)total; t += nth) {
+        const int64_t i = redo[t];
+        const int s = sys_of(v.off, v.n_sys, i);
+        const GridInfo& g = v.grid[s];
+        const lp_params& p = v.prm[s];
+        auto get = [&](int32_t j, double* out) {
+            if (j == -2) {
+                out[0] = P[i];
+                out[1] = eta[i];
+            } else {
+                pass2_values(v, P, eta, j, p, out[0], out[1]);
+            }
+        };
+        double c[18];
+        qr_fit_point(v, g, i, 2, get, scr, c);
+        const double gP[3] = {c[0], c[1], c[2]};
+        const double gE[3] = {c[9], c[10], c[11]};
+        double hv[11];
+        hv[0] = eta[i];
+        for (int q = 0; q < 6; ++q) hv[1 + q] = hand[(int64_t)(27 + q) * n + i];
+        hv[7] = hand[(int64_t)33 * n + i];
+        for (int q = 0; q < 3; ++q) hv[8 + q] = hand[(int64_t)(34 + q) * n + i];
+        finish_rhs(v, p, i, hv, gP, gE, o);
+    }
+}
+
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
+
+__global__ void k_copy_u8(int64_t n, const uint8_t* a, uint8_t* b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+}  // namespace
+
+static lp_status need_stencils(lp_ctx* c)
+{
+    if (!c->stencils_ok) {
+        c->err = "lp_neighbors (or lp_step) must build the stencils first";
+        return LP_E_STATE;
+    }
+    return LP_OK;
+}
+
+lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
+                      int k, const int32_t* msign, const int32_t* gzero,
+                      double* coef, uint8_t* flags)
+{
+    lp_status r = need_stencils(c);
+    if (r != LP_OK) return r;
+    Work& w = c->w;
+    const int64_t n = c->n;
+    View v = make_view(c, st);
+    GenericFields F;
+    F.f = f;
+    F.k = k;
+    for (int q = 0; q < 8; ++q) {
+        F.msign[q] = q < k ? msign[q] : 0;
+        F.gzero[q] = q < k ? gzero[q] : 0;
+    }
+    uint8_t* fl = flags ? flags : w.flags;
+    const int fq = (c->cfg.debug_flags & LP_DEBUG_QR_FIT) ? 1 : 0;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+    if (n > 0) {
+        const dim3 gb(blocks_for(n)), bb(BLOCK);
+#define LP_FIT_CASE(K)                                                          \
+    case K:                                                                     \
+        hipLaunchKernelGGL(k_fit_generic<K>, gb, bb, 0, c->stream, v, F, coef, \
+                           fl, w.redo, w.redo_n, fq);                           \
+        break;
+        switch (k) {
+            LP_FIT_CASE(1) LP_FIT_CASE(2) LP_FIT_CASE(3) LP_FIT_CASE(4)
+            LP_FIT_CASE(5) LP_FIT_CASE(6) LP_FIT_CASE(7) LP_FIT_CASE(8)
+        default: break;
+        }
+#undef LP_FIT_CASE
+        hipLaunchKernelGGL(k_fit_generic_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+                           c->stream, v, F, coef, fl, w.redo, w.redo_n,
+                           w.qr_scratch, w.cnt);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "fit launch");
+    return LP_OK;
+}
+
+static RhsOut rhs_out(lp_ctx* c, double* acc, double* dVdt, double* grad)
+{
+    RhsOut o;
+    o.acc = acc;
+    o.dVdt = dVdt;
+    o.grad = grad;
+    for (int a = 0; a < 7; ++a) o.out[a] = nullptr;
+    o.dt = 0.0;
+    o.err = c->w.err;
+    o.cnt = c->w.cnt;
+    return o;
+}
+
+lp_status rhs_from_coef(lp_ctx* c, const double* const st[7],
+                        const double* coef_u, double* dVdt, double* acc,
+                        double* diag, double* grad, uint8_t* flags)
+{
+    lp_status r = need_stencils(c);
+    if (r != LP_OK) return r;
+    Work& w = c->w;
+    const int64_t n = c->n;
+    View v = make_view(c, st);
+    StepOut so{w.P, w.eta, w.hand, w.flags, diag, nullptr};
+    const int fq = (c->cfg.debug_flags & LP_DEBUG_QR_FIT) ? 1 : 0;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_closure_coef, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                           c->stream, v, coef_u, so, w.redo, w.redo_n, fq);
+        RhsOut o = rhs_out(c, acc, dVdt, grad);
+        hipLaunchKernelGGL(k_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
+                           v, (const double*)w.P, (const double*)w.eta,
+                           (const double*)w.hand, (const uint8_t*)w.flags, o);
+        hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+                           c->stream, v, (const double*)w.P, (const double*)w.eta,
+                           (const double*)w.hand, (const int32_t*)w.redo,
+                           (const unsigned int*)w.redo_n, w.qr_scratch, o);
+        if (flags)
+            hipLaunchKernelGGL(k_copy_u8, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, n, w.flags, flags);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "rhs launch");
+    return LP_OK;
+}
+
+lp_status step_rhs(lp_ctx* c, const double* const st[7])
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    View v = make_view(c, st);
+    StepOut so{w.P, w.eta, w.hand, w.flags, nullptr, nullptr};
+    const int fq = (c->cfg.debug_flags & LP_DEBUG_QR_FIT) ? 1 : 0;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+    if (n > 0) {
+        prof_mark(c, 3, false);
+        hipLaunchKernelGGL(k_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
+                           v, so, w.redo, w.redo_n, fq);
+        prof_mark(c, 3, true);
+        prof_mark(c, 4, false);
+        hipLaunchKernelGGL(k_pass1_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+                           c->stream, v, so, (const int32_t*)w.redo,
+                           (const unsigned int*)w.redo_n, w.qr_scratch, w.cnt);
+        prof_mark(c, 4, true);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "pass-1 launch");
+    return LP_OK;
+}
+
+lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
+                      double* const out[7])
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    View v = make_view(c, st);
+    RhsOut o = rhs_out(c, w.acc, w.dVdt, nullptr);
+    for (int a = 0; a < 7; ++a) o.out[a] = out[a];
+    o.dt = dt;
+    if (n > 0) {
+        prof_mark(c, 5, false);
+        hipLaunchKernelGGL(k_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
+                           v, (const double*)w.P, (const double*)w.eta,
+                           (const double*)w.hand, (const uint8_t*)w.flags, o);
+        prof_mark(c, 5, true);
+        prof_mark(c, 6, false);
+        hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+                           c->stream, v, (const double*)w.P, (const double*)w.eta,
+                           (const double*)w.hand, (const int32_t*)w.redo,
+                           (const unsigned int*)w.redo_n, w.qr_scratch, o);
+        prof_mark(c, 6, true);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "pass-2 launch");
+    return LP_OK;
+}
+
+}  // namespace lp

@@ -1,0 +1,256 @@
+// Internal declarations of the LP granular-step library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lp.h"
+
+namespace lp {
+
+constexpr int NCOEF = 9;          // unknowns of the 2nd-order 3D fit
+constexpr int MMAX_LIMIT = 64;    // largest supported stencil cap
+constexpr int MAXROWS = MMAX_LIMIT + 8;
+constexpr int HIST_BUCKETS = 64;  // r^2 histogram of the stencil selection
+constexpr int LIST_CAP = 8;       // threshold-bucket list held per thread
+constexpr int HARD_CAP = 256;     // candidates the sorted stencil path holds
+constexpr int HARD_SLOTS = 16384; // concurrent sorted-path threads
+constexpr int QR_SLOTS = 16384;   // concurrent QR-refit threads
+constexpr int HAND = 37;          // pass-1 -> pass-2 handoff doubles
+constexpr int BLOCK = 256;        // threads per block of per-particle kernels
+constexpr int SORT_ITEMS = 16;    // keys per thread in a radix tile
+constexpr int SORT_TILE = BLOCK * SORT_ITEMS;
+
+// flag bits per particle
+constexpr uint8_t FLAG_LINEAR = 1;
+constexpr uint8_t FLAG_QR = 8;
+
+// device error codes (bit set in the error word)
+constexpr int ERR_CAPACITY = 1;
+constexpr int ERR_NUMERIC = 2;
+
+// Per-system grid, built on the device from the bounding box.
+struct GridInfo {
+    double x0, y0, z0, inv_c;   // origin, 1 / cell edge
+    double R2, h, inv_h, R, wall;
+    int64_t cell_base;          // first cell of this system in the tables
+    int64_t pbeg, pend;         // particle range
+    int32_t nx, ny, nz, pad;
+};
+
+// Small block read back by the host after the grid is built.
+struct Summary {
+    int64_t total_cells;
+    int64_t n_mirror;
+    int32_t axis_bits;
+    int32_t bad;                // a cell coordinate needs more than 16 bits
+};
+
+// Device error word.
+struct ErrWord {
+    int32_t code;
+    int32_t pad;
+    unsigned long long index;   // smallest offending particle
+};
+
+// Diagnostic counters (device).
+struct Counters {
+    unsigned long long qr_refits;
+    unsigned long long hard_stencils;
+    unsigned long long below_wall;
+    unsigned long long pad[5];
+};
+
+// Everything a per-particle kernel needs to find neighbours and states.
+struct View {
+    int64_t n;                  // real particles
+    int32_t n_sys;
+    int32_t m_max;
+    const int64_t* off;         // system offsets (device)
+    const lp_params* prm;
+    const GridInfo* grid;
+    // real particles in cell order
+    const double *x, *y, *z, *u, *v, *w, *V;
+    // mirrors by id n + k
+    const double *mx, *my, *mz, *mu, *mv, *mw, *mV;
+    const int32_t* msrc;
+    // mirrors in cell order (coordinates and ids)
+    const double *msx, *msy, *msz;
+    const int32_t* msid;
+    const int64_t* n_mirror;    // device count
+    // cell tables
+    const int32_t *cs, *ce, *mcs, *mce;
+    // stencils
+    int32_t* sten;              // m_max x n (ELL, column k at k*n)
+    int32_t* scnt;              // n
+    uint8_t* gmask;             // n
+    double ghost_margin;
+    double fallback_tol;
+    double redo_ratio;          // Gram pivot ratio that triggers a QR refit
+    int32_t weight;
+    int32_t debug;
+};
+
+struct Work {
+    int64_t n_max = 0, cells_max = 0;
+    int32_t m_max = 0;
+    // systems
+    int64_t* off = nullptr;
+    lp_params* prm = nullptr;
+    GridInfo* grid = nullptr;
+    unsigned long long* bbox = nullptr;   // n_sys x 6 ordered encodings
+    unsigned long long* mcount = nullptr; // mirror count (bbox pass)
+    Summary* summary = nullptr;
+    Summary* h_summary = nullptr;         // pinned host copy
+    ErrWord* err = nullptr;
+    Counters* cnt = nullptr;
+    // sort
+    unsigned long long *keys0 = nullptr, *keys1 = nullptr;
+    int32_t *vals0 = nullptr, *vals1 = nullptr;
+    uint32_t* hist = nullptr;
+    int64_t hist_cap = 0;
+    // sorted real state (lp_step works on this copy)
+    double* sst[7] = {nullptr};
+    // mirrors by id, then in cell order
+    double* mst[7] = {nullptr};
+    int32_t* msrc = nullptr;
+    double *msx = nullptr, *msy = nullptr, *msz = nullptr;
+    int32_t* msid = nullptr;
+    int64_t* n_mirror = nullptr;
+    int32_t* scan = nullptr;              // mirror slot per particle
+    int32_t* bsum = nullptr;              // scan block sums
+    // cell tables
+    int32_t *cs = nullptr, *ce = nullptr, *mcs = nullptr, *mce = nullptr;
+    // stencils
+    int32_t* sten = nullptr;
+    int32_t* scnt = nullptr;
+    uint8_t* gmask = nullptr;
+    int32_t* hard = nullptr;
+    unsigned int* hard_n = nullptr;
+    double* hard_r2 = nullptr;            // HARD_SLOTS x HARD_CAP
+    int32_t* hard_id = nullptr;
+    // fits
+    int32_t* redo = nullptr;
+    unsigned int* redo_n = nullptr;
+    double* qr_scratch = nullptr;         // QR_SLOTS x MAXROWS x (9 + 8)
+    double *P = nullptr, *eta = nullptr;
+    double* hand = nullptr;               // HAND x n
+    double* acc = nullptr;                // 3 x n
+    double* dVdt = nullptr;
+    uint8_t* flags = nullptr;
+    // export helpers
+    int64_t* coff = nullptr;
+};
+
+}  // namespace lp
+
+struct lp_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    lp_config cfg{};
+    int32_t n_sys = 0;
+    int64_t n = 0;
+    std::vector<int64_t> h_off;
+    std::vector<lp_params> h_prm;
+    lp::Work w;
+    int axis_bits = 0;
+    int64_t total_cells = 0;
+    int64_t n_mirror = 0;
+    // phase timing (lp_profile)
+    bool prof = false;
+    hipEvent_t ev[16] = {nullptr};
+    double prof_ms[8] = {0};
+    int64_t prof_steps = 0;
+    // call-order state: the cell build and stencils refer to this state
+    const double* built_x = nullptr;
+    bool cells_ok = false;
+    bool stencils_ok = false;
+    std::string err;
+};
+
+namespace lp {
+
+// ---- device helpers -------------------------------------------------
+
+// Logical block index that gives each XCD a contiguous range of blocks.
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8); remapping keeps neighbouring particles (and their shared
+// neighbour data) in one XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t q = nb >> 3, r = nb & 7;
+    const int64_t x = b & 7, t = b >> 3;
+    return x * q + (x < r ? x : r) + t;
+}
+
+__device__ __forceinline__ int sys_of(const int64_t* off, int n_sys, int64_t i)
+{
+    int lo = 0, hi = n_sys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// bit k of the low 16 bits of x -> bit 3k
+__device__ __forceinline__ uint64_t spread3_64(uint64_t x)
+{
+    x &= 0xFFFFull;
+    x = (x | (x << 16)) & 0x0000FF0000FFull;
+    x = (x | (x << 8)) & 0x00F00F00F00Full;
+    x = (x | (x << 4)) & 0x0C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x249249249249ull;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t morton3(uint32_t cx, uint32_t cy, uint32_t cz)
+{
+    return spread3_64(cx) | (spread3_64(cy) << 1) | (spread3_64(cz) << 2);
+}
+
+// Exact float64 operations that the compiler must not contract.
+__device__ __forceinline__ double dsub(double a, double b) { return __dsub_rn(a, b); }
+__device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
+
+// r^2 exactly as the method defines it: (dx*dx + dy*dy) + dz*dz.
+__device__ __forceinline__ double dist2(double dx, double dy, double dz)
+{
+    return dadd(dadd(dmul(dx, dx), dmul(dy, dy)), dmul(dz, dz));
+}
+
+__device__ __forceinline__ void raise_error(ErrWord* e, int code, int64_t idx)
+{
+    atomicOr(&e->code, code);
+    atomicMin(&e->index, (unsigned long long)idx);
+}
+
+}  // namespace lp
+
+// ---- host-side launchers (defined in the .hip files) -----------------
+namespace lp {
+lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out,
+                      bool write_back, double* const out[7]);
+lp_status stencils_build(lp_ctx* c, const double* const st[7]);
+lp_status stencils_export(lp_ctx* c, const double* const st[7],
+                          int64_t* cand_off, int32_t* cand_idx, int64_t cap,
+                          int64_t* needed, int32_t* sten_cnt,
+                          int32_t* sten_idx, uint8_t* ghost_mask);
+lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
+                      int k, const int32_t* msign, const int32_t* gzero,
+                      double* coef, uint8_t* flags);
+lp_status rhs_from_coef(lp_ctx* c, const double* const st[7],
+                        const double* coef_u, double* dVdt, double* acc,
+                        double* diag, double* grad, uint8_t* flags);
+lp_status step_rhs(lp_ctx* c, const double* const st[7]);
+lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
+                      double* const out[7]);
+View make_view(lp_ctx* c, const double* const st[7]);
+// records the begin (end = false) or end event of phase `ph` when profiling
+void prof_mark(lp_ctx* c, int ph, bool end);
+lp_status hip_fail(lp_ctx* c, hipError_t e, const char* what);
+}  // namespace lp

@@ -1,0 +1,294 @@
+"""GPU parity: every entry point of the HIP library against the FP64 CPU
+oracle on identical seeded inputs.
+
+Integer results (permutation, candidate sets, stencil sets, ghost masks,
+fallback and branch flags) must match bit for bit.  Floating-point arrays
+must satisfy ||gpu - oracle||_inf <= 1e-10 ||oracle||_inf per array (FP64
+mode).  Inputs come from lpgen or from the oracle, never from the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2206_14061_amd as lp_mod
+    lp_mod._lib.load()
+    return lp_mod
+
+
+def _with_flow(wl):
+    """Smooth velocities and a density field visiting all three regimes."""
+    st = wl.state
+    st.u = 0.3 * np.sin(3.1 * st.y / wl.params[0].h * 0.0625 + 1.0) * np.cos(2.0 * st.z)
+    st.v = 0.2 * np.cos(2.3 * st.x) * np.sin(1.7 * st.z + 0.4)
+    st.w = 0.25 * np.sin(2.9 * st.x + 1.1 * st.y)
+    st.V = 1.0 / (0.47 + 0.15 * np.sin(4.0 * st.z / (wl.params[0].h * 16) + 2.0 * st.y))
+    return wl
+
+
+def _ragged(wl, drop=37):
+    """Drops `drop` seeded particles so the count is not a tile multiple."""
+    rng = np.random.default_rng(5)
+    keep = np.sort(rng.choice(wl.n, wl.n - drop, replace=False))
+    wl.state = wl.state.take(keep)
+    wl.offsets = np.array([0, wl.state.n])
+    return wl
+
+
+CASES = {
+    "column16": lambda: lpgen.column_small(),
+    "column16_flow_ragged": lambda: _ragged(_with_flow(lpgen.column_small())),
+    "sheared_20x20x12": lambda: lpgen.column_sheared(nx=20, ny=20, nz=12),
+    "ensemble_3": lambda: _with_flow(lpgen.ensemble(n_sys=3, n_lo=600, n_hi=3000)),
+}
+
+
+def _relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    sc = np.max(np.abs(b)) if b.size else 0.0
+    d = np.max(np.abs(a - b)) if b.size else 0.0
+    return d / sc if sc > 0 else d
+
+
+def _gpu_sorted(lp, wl, **cfg):
+    """GPU context with the workload's state Morton-sorted on the device."""
+    ctx = lp.make_context(wl, **cfg)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = ctx.lp_build_cells(st)
+    return ctx, st, perm
+
+
+def _oracle_sorted(wl):
+    perm, _ = oracle.sort_perm(wl.state, wl.offsets, wl.params)
+    st = wl.state.take(perm)
+    return perm, lpgen.State(*[np.ascontiguousarray(a) for a in st.arrays()])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_build_cells_permutation_bit_exact(lp, case):
+    wl = CASES[case]()
+    _log("case %s n=%d systems=%d" % (case, wl.n, wl.n_sys))
+    ctx, st, perm = _gpu_sorted(lp, wl)
+    ctx.sync_status()
+    operm, ost = _oracle_sorted(wl)
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    got = st.to_host()
+    for a, b in zip(got.arrays(), ost.arrays()):
+        assert np.array_equal(a, b)
+
+
+def _check_neighbours(lp, wl, **cfg):
+    ctx, st, perm = _gpu_sorted(lp, wl, **cfg)
+    _, ost = _oracle_sorted(wl)
+    o = oracle.Oracle(ost, wl.offsets, wl.params, brute=(wl.n <= 16384))
+    nb = o.neighbours()
+    g = ctx.lp_neighbors(st)
+    ctx.sync_status()
+    assert g["n_mirror"] == nb.n_mirror
+    assert np.array_equal(g["cand_off"].cpu().numpy(), nb.cand_off)
+    assert np.array_equal(g["cand_idx"].cpu().numpy(), nb.cand_idx)
+    assert np.array_equal(g["ghost_mask"].cpu().numpy(), nb.ghost_mask)
+    cnt = g["sten_cnt"].cpu().numpy()
+    assert np.array_equal(cnt, nb.sten_cnt)
+    gi = g["sten_idx"].cpu().numpy()
+    oi = np.where(np.arange(nb.sten_idx.shape[1])[None, :] < nb.sten_cnt[:, None],
+                  nb.sten_idx, np.iinfo(np.int32).max)
+    oi = np.sort(oi, axis=1)
+    oi[oi == np.iinfo(np.int32).max] = -1
+    assert np.array_equal(gi, oi)
+    return ctx
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_neighbours_stencils_ghosts_bit_exact(lp, case):
+    wl = CASES[case]()
+    _log("case %s n=%d" % (case, wl.n))
+    ctx = _check_neighbours(lp, wl)
+    _log("stats %s" % ctx.stats())
+
+
+@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12"])
+def test_sorted_stencil_path_bit_exact(lp, case):
+    """The exact sorted-candidate path (used for overflowing cut buckets)
+    gives the same stencils when forced for every particle."""
+    wl = CASES[case]()
+    _log("case %s n=%d (sorted stencil path)" % (case, wl.n))
+    _check_neighbours(lp, wl, debug_flags=lp.LP_DEBUG_SORTED_STENCIL)
+
+
+def _fields(st):
+    x, y, z = st.x, st.y, st.z
+    return np.stack([np.sin(3.0 * x + 1.0) * np.cos(2.0 * y) + z * z,
+                     np.exp(0.5 * x) * np.sin(2.5 * z) - 0.3 * y,
+                     np.cos(1.7 * x * y + z)])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("path", ["gram", "qr"])
+def test_fit_derivs_parity(lp, case, path):
+    wl = CASES[case]()
+    _log("case %s path %s n=%d" % (case, path, wl.n))
+    import torch
+    cfg = {} if path == "gram" else dict(debug_flags=lp.LP_DEBUG_QR_FIT)
+    ctx, st, _ = _gpu_sorted(lp, wl, **cfg)
+    _, ost = _oracle_sorted(wl)
+    ctx.lp_neighbors(st, candidates=False, stencils=False, ghosts=False)
+    F = _fields(ost)
+    ms, gz = [1, 1, -1], [0, 0, 1]
+    coef, flags = ctx.lp_fit_derivs(st, torch.tensor(F, device="cuda"), ms, gz)
+    ctx.sync_status()
+    o = oracle.Oracle(ost, wl.offsets, wl.params)
+    ocoef, oflags = o.fit(F, ms, gz)
+    gc = coef.cpu().numpy()
+    for f in range(3):
+        for q in range(9):
+            e = _relerr(gc[f, q], ocoef[f, q])
+            assert e <= TOL, (f, q, e)
+    assert np.array_equal(flags.cpu().numpy() & 1, oflags & 1)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_rheology_rhs_parity(lp, case):
+    """Closure, second fit and RHS from the oracle's velocity derivatives."""
+    wl = CASES[case]()
+    _log("case %s n=%d" % (case, wl.n))
+    import torch
+    ctx, st, _ = _gpu_sorted(lp, wl)
+    _, ost = _oracle_sorted(wl)
+    ctx.lp_neighbors(st, candidates=False, stencils=False, ghosts=False)
+    o = oracle.Oracle(ost, wl.offsets, wl.params)
+    r = o.evaluate()
+    g = ctx.lp_rheology_rhs(st, torch.tensor(r["coef_u"].reshape(27, -1), device="cuda"))
+    ctx.sync_status()
+    for name in ("dVdt", "acc", "diag", "grad"):
+        got = g[name].cpu().numpy()
+        want = r[name]
+        for q in range(want.shape[0] if want.ndim == 2 else 1):
+            a = got[q] if want.ndim == 2 else got
+            b = want[q] if want.ndim == 2 else want
+            e = _relerr(a, b)
+            assert e <= TOL, (name, q, e)
+    gf = g["flags"].cpu().numpy()
+    assert np.array_equal(gf & 7, r["flags"] & 7)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("path", ["gram", "qr"])
+def test_step_parity(lp, case, path):
+    """lp_step against the oracle step: permutation exact; increments of
+    position, velocity and volume within 1e-10 of the oracle's."""
+    wl = CASES[case]()
+    _log("case %s path %s n=%d" % (case, path, wl.n))
+    import torch
+    cfg = {} if path == "gram" else dict(debug_flags=lp.LP_DEBUG_QR_FIT)
+    ctx = lp.make_context(wl, **cfg)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    ctx.lp_step(st, wl.dt, perm)
+    ctx.sync_status()
+    ost, operm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt)
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = wl.state.take(operm)
+    got = st.to_host()
+    for k, (a, b, c) in enumerate(zip(got.arrays(), ost.arrays(), old.arrays())):
+        e = _relerr(a - c, b - c)
+        assert e <= TOL, (lp.DeviceState.NAMES[k], e)
+
+
+def test_isolated_particle_free_fall(lp):
+    """Edge case: a single gas-regime particle falls with a = g exactly."""
+    import torch
+    p = lpgen.default_params(0.05)
+    st0 = lpgen.State(np.array([0.1]), np.array([0.2]), np.array([4.0]),
+                      np.array([1.0]), np.array([-2.0]), np.array([0.5]),
+                      np.array([1.0 / 0.3]))
+    wl = lpgen.Workload("single", st0, np.array([0, 1]), [p], 1e-3, 1)
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(st0)
+    ctx.lp_step(st, 1e-3)
+    ctx.sync_status()
+    ost, _, _ = oracle.step(st0, wl.offsets, wl.params, 1e-3)
+    for a, b in zip(st.to_host().arrays(), ost.arrays()):
+        assert np.array_equal(a, b)
+
+
+def test_empty_system_and_neighbour_free_systems(lp):
+    """Edge cases: an empty system between two others, and systems far
+    apart in space that must not see each other."""
+    a = lpgen.column_small()
+    h = a.params[0].h
+    b = lpgen.lattice_column(5, 5, 4, h, seed=3, params=a.params[0])
+    st0 = lpgen.State.concat([a.state, b])   # b overlaps a in space
+    offs = np.array([0, a.n, a.n, a.n + b.n])
+    wl = lpgen.Workload("three", st0, offs, [a.params[0]] * 3, 1e-4, 1)
+    _log("three systems n=%d" % wl.n)
+    _check_neighbours(lp, wl)
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(st0)
+    ctx.lp_step(st, 1e-4)
+    ctx.sync_status()
+    ost, _, _ = oracle.step(st0, offs, wl.params, 1e-4)
+    old = st0.take(oracle.sort_perm(st0, offs, wl.params)[0])
+    for k, (x, y, c) in enumerate(zip(st.to_host().arrays(), ost.arrays(), old.arrays())):
+        assert _relerr(x - c, y - c) <= TOL, k
+
+
+def test_full_size_column_step_parity(lp):
+    """The 64 x 64 x 128 benchmark column (524,288 particles), one step in
+    the benchmark's launch configuration, every particle against the
+    oracle."""
+    import torch
+    wl = lpgen.column_bench()
+    _log("column_bench n=%d" % wl.n)
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    ctx.lp_step(st, wl.dt, perm)
+    ctx.sync_status()
+    _log("gpu stats %s" % ctx.stats())
+    ost, operm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt, brute=False)
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = wl.state.take(operm)
+    for k, (a, b, c) in enumerate(zip(st.to_host().arrays(), ost.arrays(), old.arrays())):
+        e = _relerr(a - c, b - c)
+        _log("  %s rel err %.3e" % (lp.DeviceState.NAMES[k], e))
+        assert e <= TOL
+
+
+def test_error_paths_report_cleanly(lp):
+    """Host-side validation: bad dt, calls out of order, capacity."""
+    wl = lpgen.column_small()
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    with pytest.raises(lp.LPError) as e:
+        ctx.lp_step(st, -1.0)
+    assert e.value.status == 1
+    with pytest.raises(lp.LPError) as e:
+        ctx.lp_neighbors(st)
+    assert e.value.status == 5
+    with pytest.raises(lp.LPError) as e:
+        ctx.lp_step_adjoint()
+    assert e.value.status == 5
+    small = lp.Context()
+    small.reserve(100)
+    with pytest.raises(lp.LPError) as e:
+        small.set_systems([0, wl.n], wl.params)
+        small.lp_step(st, 1e-4)
+    assert e.value.status == 2
