@@ -110,7 +110,22 @@ def main():
     nst = max(ph.pop("steps"), 1)
     phases = {k: v / nst for k, v in ph.items()}
     stats = ctx.stats()
-    dominant = max(("stencil", "pass1", "pass2"), key=lambda k: phases[k])
+    dominant = max(("select", "pass1", "pass2"), key=lambda k: phases[k])
+
+    # the same steps with the neighbour list rebuilt (and the column
+    # re-sorted) at every step
+    ctx0 = lp.make_context(wl, skin=0.0)
+    st0 = lp.DeviceState.from_host(wl.state)
+    for _ in range(args.warmup):
+        ctx0.lp_step(st0, wl.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k0 = max(2, args.steps // 2)
+    for _ in range(k0):
+        ctx0.lp_step(st0, wl.dt)
+    torch.cuda.synchronize()
+    ms_rebuild = 1e3 * (time.perf_counter() - t0) / k0
+    ctx0.sync_status()
     t_pass1 = phases["pass1"] * 1e-3
     achieved = PASS1_FLOP_PER_PARTICLE * wl.n / t_pass1 / 1e12
     executed = PASS1_FLOP_EXECUTED * wl.n / t_pass1 / 1e12
@@ -128,8 +143,10 @@ def main():
            "data": "synthetic",
            "config": {"workload": wl.name, "particles": wl.n, "dt": wl.dt,
                       "precision": args.precision, "m_max": 60,
-                      "R_over_h": 2.5, "parallelism": "none"},
-           "phases_ms": phases, "stats": stats, "roofline": roof}
+                      "R_over_h": 2.5, "skin": 0.1, "parallelism": "none"},
+           "phases_ms": phases, "stats": stats,
+           "ms_per_step_rebuild_every_step": ms_rebuild,
+           "roofline": roof}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -76,7 +76,12 @@ typedef struct {
  * LP_W_GAUSS (w = exp(-4 r^2 / R^2)).  ghost_margin: an octant is covered
  * when a neighbour lies beyond ghost_margin * h on every axis (0.5).
  * fallback_tol: stencils with min|r_jj|/max|r_jj| below it (or fewer than 9
- * rows) use a linear fit (1e-12).  debug_flags: LP_DEBUG_* bits. */
+ * rows) use a linear fit (1e-12).  debug_flags: LP_DEBUG_* bits.
+ * skin: neighbour-list margin in units of R (default 0.1): the list holds
+ * every pair within R (1 + skin) and is rebuilt (with a Morton re-sort)
+ * once a particle has moved skin R / 2 since the last build; 0 rebuilds
+ * at every step.  Results do not depend on it except through the particle
+ * order (ids), which changes only at rebuilds. */
 typedef struct {
     int32_t m_max;
     int32_t precision;
@@ -85,6 +90,7 @@ typedef struct {
     double ghost_margin;
     double fallback_tol;
     int32_t debug_flags;
+    double skin;
 } lp_config;
 
 /* Structure-of-arrays particle state, device float64 arrays of length n
@@ -121,23 +127,25 @@ lp_status lp_reserve(lp_ctx* ctx, int64_t n_max, int64_t cells_max);
 lp_status lp_set_systems(lp_ctx* ctx, int32_t n_sys, const int64_t* offsets,
                          const lp_params* params);
 
-/* Morton-sorted cell list (replaces the octree of Sec. 3.1 step 4 and
- * Sec. 3.2).  Per system: origin (min x, min y, min(min z, wall_z - R)),
- * cell edge c = R (1 + 2^-20) >= R, cell coordinate floor((x - origin)/c),
- * key = bit interleave of the cell coordinates (x -> bit 3k, y -> 3k+1,
- * z -> 3k+2).  Particles are reordered in place by (system, key, old
- * index); perm (device int32[n], optional) receives perm[new] = old.
- * Then builds the mirror particles of Sec. 3.1 step 9 (one per particle
- * with z - wall_z < R, at (x, y, 2 wall_z - z), velocity (u, v, -w), same
- * V; mirror id n + k in ascending source order) and the cell tables of
- * reals and mirrors.  Synchronises the stream once (grid sizes).
- * LP_E_CAPACITY if the particles, mirrors or cells exceed the reservation
- * or a cell coordinate needs more than 16 bits. */
+/* Morton-sorted cell list and neighbour list (replace the octree of Sec.
+ * 3.1 step 4 and Sec. 3.2).  Per system: origin (min x, min y,
+ * min(min z, wall_z - R)), cell edge c = R (1 + skin) (1 + 2^-20), cell
+ * coordinate floor((x - origin)/c), key = bit interleave of the cell
+ * coordinates (x -> bit 3k, y -> 3k+1, z -> 3k+2).  Particles are
+ * reordered in place by (system, key, old index); perm (device
+ * int32[n], optional) receives perm[new] = old.  Then records for every
+ * particle the reals within R (1 + skin) and the potential mirror sources
+ * (Sec. 3.1 step 9: a mirror of every particle with z - wall_z < R, at
+ * (x, y, 2 wall_z - z), velocity (u, v, -w), same V, id n + k in
+ * ascending source order).  Synchronises the stream once (grid sizes).
+ * LP_E_CAPACITY if the cells exceed the reservation or a cell coordinate
+ * needs more than 16 bits; more than 192 list entries for a particle
+ * latch LP_E_CAPACITY (lp_sync_status). */
 lp_status lp_build_cells(lp_ctx* ctx, lp_state* s, int32_t* perm);
 
 /* Neighbours, stencils and ghosts (Sec. 3.1 steps 5-6, free boundary of
  * step 9) of every real particle of the state passed to the last
- * lp_build_cells (unchanged since):
+ * lp_build_cells (positions changed since by less than skin R / 2):
  *  - candidates C_i = { j real or mirror of the same system, j != i :
  *    (dx*dx + dy*dy) + dz*dz < R*R in float64 without fused operations };
  *  - stencil: the nearest candidate (key (r^2, id)) of each octant
@@ -192,10 +200,15 @@ lp_status lp_rheology_rhs(lp_ctx* ctx, const lp_state* s,
                           const double* coef_u, double* dVdt, double* acc,
                           double* diag, double* grad, uint8_t* flags);
 
-/* One explicit step (Sec. 3.1 steps 5-10): lp_build_cells (the state is
- * reordered in place, perm optional as there), stencils, fit of u, v, w,
- * closure, fit of P and eta, right-hand side, then
+/* One explicit step (Sec. 3.1 steps 5-10): when the context has no
+ * neighbour list yet, or some particle has moved skin R / 2 since it was
+ * built (checked on the device; one synchronisation), the state is
+ * re-sorted as in lp_build_cells and the list rebuilt (perm as there);
+ * otherwise the order is kept (perm, if given, is the identity).  Then
+ * mirrors, stencils, fit of u, v, w, closure, fit of P and eta,
+ * right-hand side, and
  *   V' = V + dt dVdt,  u' = u + dt acc,  x' = x + dt (u + u')/2.
+ * The state must keep the order of the previous lp_step between calls.
  * dt > 0.  A non-finite result latches LP_E_NUMERIC (lp_sync_status). */
 lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
 
@@ -208,16 +221,18 @@ lp_status lp_step_adjoint(lp_ctx* ctx);
  * receives the first offending particle or -1. */
 lp_status lp_sync_status(lp_ctx* ctx, int64_t* index);
 
-/* Diagnostics of the last lp_step / lp_rheology_rhs / lp_fit_derivs
- * (host int64[8]): particles, mirrors, QR refits, sorted-path stencils,
- * below-wall particles after the last update, 0, 0, 0.  Synchronises. */
+/* Diagnostics accumulated since the last call (host int64[8]):
+ * particles, mirrors (last export), QR refits, sorted-path stencils,
+ * particles below the wall after updates, neighbour-list rebuilds by
+ * lp_step, 0, 0; then resets them.  Synchronises. */
 lp_status lp_stats(lp_ctx* ctx, int64_t* out8);
 
 /* Phase timing (instrumentation).  lp_profile(ctx, 1) makes lp_step
  * record HIP events on the context's stream around its kernel groups:
- * 0 cell build, 1 stencil selection (k_stencil), 2 exact sorted-stencil
- * path, 3 pass-1 fit + closure (k_pass1), 4 pass-1 QR refits, 5 pass-2
- * fit + RHS + update (k_pass2), 6 pass-2 QR refits; each lp_step then
+ * 0 displacement check and re-sort + list rebuild or state copy, 1 mirrors
+ * and stencil selection (k_select), 2 exact sorted-stencil path, 3 pass-1
+ * fit + closure (k_pass1), 4 pass-1 QR refits, 5 pass-2 fit + RHS +
+ * update (k_pass2), 6 pass-2 QR refits; each lp_step then
  * waits for its last event.  lp_profile_read (host double[8], int64 steps)
  * returns the summed milliseconds per phase and the number of profiled
  * steps, then resets them.  lp_profile(ctx, 0) stops recording. */

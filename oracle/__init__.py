@@ -56,7 +56,7 @@ def _load():
     lib = C.CDLL(path)
     P = C.c_void_p
     i64, i32 = C.c_int64, C.c_int32
-    lib.orc_sort.argtypes = [i64, i32, P, P, P, P, P, P, P]
+    lib.orc_sort.argtypes = [i64, i32, P, P, C.c_double, P, P, P, P, P]
     lib.orc_sort.restype = C.c_int
     lib.orc_nbr_build.argtypes = [i64, i32, P, P, P] + [P] * 7 + [C.c_int]
     lib.orc_nbr_build.restype = C.c_void_p
@@ -128,8 +128,13 @@ def closure_point(p: Params, V: float, G: np.ndarray):
     return (int(br), out[0], out[1], out[2], out[3], out[4], gd.reshape(3, 3))
 
 
-def sort_perm(state: State, offsets: np.ndarray, params: Sequence[Params]):
-    """Morton order inside each system: returns (perm new->old, keys)."""
+SKIN_DEFAULT = 0.1
+
+
+def sort_perm(state: State, offsets: np.ndarray, params: Sequence[Params],
+              skin: float = SKIN_DEFAULT):
+    """Morton order inside each system over cells of edge R (1 + skin)
+    (1 + 2^-20): returns (perm new->old, keys)."""
     lib = _load()
     n = state.n
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -137,8 +142,8 @@ def sort_perm(state: State, offsets: np.ndarray, params: Sequence[Params]):
     perm = np.empty(n, dtype=np.int32)
     keys = np.empty(n, dtype=np.uint64)
     x, y, z = _f64(state.x), _f64(state.y), _f64(state.z)
-    rc = lib.orc_sort(n, len(params), _ptr(off), _ptr(prm), _ptr(x), _ptr(y),
-                      _ptr(z), _ptr(perm), _ptr(keys))
+    rc = lib.orc_sort(n, len(params), _ptr(off), _ptr(prm), float(skin),
+                      _ptr(x), _ptr(y), _ptr(z), _ptr(perm), _ptr(keys))
     if rc != 0:
         raise ValueError("cell coordinate exceeds 21 bits")
     return perm, keys
@@ -255,10 +260,14 @@ def update(state: State, offsets, params: Sequence[Params], dt: float,
 
 
 def step(state: State, offsets, params: Sequence[Params], dt: float,
-         cfg: Optional[dict] = None, brute: Optional[bool] = None):
-    """One oracle step: Morton order, RHS, explicit update.  Returns
-    (new state in Morton order, perm new->old, RHS dict)."""
-    perm, _ = sort_perm(state, offsets, params)
+         cfg: Optional[dict] = None, brute: Optional[bool] = None,
+         skin: float = SKIN_DEFAULT, sort: bool = True):
+    """One oracle step: Morton order (unless ``sort`` is false), RHS,
+    explicit update.  Returns (new state, perm new->old, RHS dict)."""
+    if sort:
+        perm, _ = sort_perm(state, offsets, params, skin)
+    else:
+        perm = np.arange(state.n, dtype=np.int32)
     st = state.take(perm)
     st = State(*[np.ascontiguousarray(a) for a in st.arrays()])
     o = Oracle(st, offsets, params, cfg, brute)

@@ -83,14 +83,16 @@ static int cmp_keyidx(const void* a, const void* b)
     return p->idx < q->idx ? -1 : (p->idx > q->idx);
 }
 
-/* Cell edge c = R (1 + 2^-20), origin (min x, min y, min(min z, wall - R))
- * per system; cell coordinate floor((x - origin) / c) computed as
- * (x - origin) * (1/c); key = bit interleave (x -> 3k, y -> 3k+1,
- * z -> 3k+2).  Particles are ordered by (key, old index) inside each
- * system.  perm[new] = old.  Returns -1 if a cell coordinate needs more
- * than 21 bits. */
+/* Cell edge c = R (1 + skin) (1 + 2^-20), origin (min x, min y,
+ * min(min z, wall - R)) per system; cell coordinate floor((x - origin)/c)
+ * computed as (x - origin) * (1/c); key = bit interleave (x -> 3k,
+ * y -> 3k+1, z -> 3k+2).  Particles are ordered by (key, old index) inside
+ * each system.  perm[new] = old.  Returns -1 if a cell coordinate needs
+ * more than 21 bits.  (The order only affects which particle gets which
+ * id; skin is the neighbour-list margin of the GPU library, whose cells
+ * have this edge.) */
 int orc_sort(int64_t n, int32_t n_sys, const int64_t* off, const double* prm,
-             const double* x, const double* y, const double* z,
+             double skin, const double* x, const double* y, const double* z,
              int32_t* perm, uint64_t* keys)
 {
     KeyIdx* t = (KeyIdx*)malloc(sizeof(KeyIdx) * (size_t)(n > 0 ? n : 1));
@@ -107,7 +109,7 @@ int orc_sort(int64_t n, int32_t n_sys, const int64_t* off, const double* prm,
         }
         double zl = p[P_WALL] - p[P_R];
         if (zl < z0) z0 = zl;
-        double c = p[P_R] * (1.0 + 1.0 / 1048576.0);
+        double c = (p[P_R] * (1.0 + skin)) * (1.0 + 1.0 / 1048576.0);
         double ic = 1.0 / c;
         for (int64_t i = a; i < b; ++i) {
             double fx = (x[i] - x0) * ic, fy = (y[i] - y0) * ic,

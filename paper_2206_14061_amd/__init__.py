@@ -84,7 +84,7 @@ class Context:
     def __init__(self, m_max: int = 60, precision: int = LP_FP64,
                  cond_max: float = 100.0, weight: int = LP_W_UNIT,
                  ghost_margin: float = 0.5, fallback_tol: float = 1e-12,
-                 debug_flags: int = 0, stream=None):
+                 debug_flags: int = 0, skin: float = 0.1, stream=None):
         torch = _torch()
         self.lib = _lib.load()
         cfg = LPConfig()
@@ -92,6 +92,7 @@ class Context:
         cfg.m_max, cfg.precision, cfg.cond_max = m_max, precision, cond_max
         cfg.weight, cfg.ghost_margin = weight, ghost_margin
         cfg.fallback_tol, cfg.debug_flags = fallback_tol, debug_flags
+        cfg.skin = skin
         self.cfg = cfg
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -217,7 +218,7 @@ class Context:
         rc = self.lib.lp_sync_status(self.h, C.byref(idx))
         self._check(rc)
 
-    PHASES = ("cells", "stencil", "stencil_sorted", "pass1", "pass1_qr",
+    PHASES = ("rebuild_or_copy", "select", "select_sorted", "pass1", "pass1_qr",
               "pass2", "pass2_qr")
 
     def profile(self, enable: bool = True):
@@ -236,7 +237,7 @@ class Context:
         out = (C.c_int64 * 8)()
         self._check(self.lib.lp_stats(self.h, out))
         return dict(particles=out[0], mirrors=out[1], qr_refits=out[2],
-                    sorted_stencils=out[3], below_wall=out[4])
+                    sorted_stencils=out[3], below_wall=out[4], rebuilds=out[5])
 
 
 def make_context(workload, **cfg) -> Context:

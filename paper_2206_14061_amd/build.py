@@ -21,6 +21,9 @@ OUT = os.path.join(PKG, "liblp_gfx950.so")
 BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["lp_api.hip", "lp_cells.hip", "lp_stencil.hip", "lp_fit.hip"]
+# sources whose float64 decisions must round exactly like the plain
+# definitions (cell coordinates, candidate test, keys): no FMA contraction
+NO_CONTRACT = {"lp_cells.hip", "lp_stencil.hip"}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -31,7 +34,8 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-ffp-contract=off"] if src in NO_CONTRACT else []
+    cmd = [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))

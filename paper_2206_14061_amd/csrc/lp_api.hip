@@ -33,15 +33,12 @@ View make_view(lp_ctx* c, const double* const st[7])
     v.grid = w.grid;
     v.x = st[0]; v.y = st[1]; v.z = st[2];
     v.u = st[3]; v.v = st[4]; v.w = st[5]; v.V = st[6];
-    v.mx = w.mst[0]; v.my = w.mst[1]; v.mz = w.mst[2];
-    v.mu = w.mst[3]; v.mv = w.mst[4]; v.mw = w.mst[5]; v.mV = w.mst[6];
+    v.mirror_of = w.mirror_of;
     v.msrc = w.msrc;
-    v.msx = w.msx; v.msy = w.msy; v.msz = w.msz; v.msid = w.msid;
-    v.n_mirror = w.n_mirror;
-    v.cs = w.cs; v.ce = w.ce; v.mcs = w.mcs; v.mce = w.mce;
-    v.sten = w.sten;
-    v.scnt = w.scnt;
-    v.gmask = w.gmask;
+    v.vl = w.vl;
+    v.vcnt = w.vcnt;
+    v.rec = w.rec;
+    v.hsten = w.hsten;
     v.ghost_margin = c->cfg.ghost_margin;
     v.fallback_tol = c->cfg.fallback_tol;
     v.redo_ratio = 1.0 / c->cfg.cond_max;
@@ -69,15 +66,14 @@ void free_work(Work& w)
         if (p) hipFree(p);
         p = nullptr;
     };
-    f(w.off); f(w.prm); f(w.grid); f(w.bbox); f(w.mcount); f(w.summary);
-    f(w.err); f(w.cnt); f(w.keys0); f(w.keys1); f(w.vals0); f(w.vals1);
-    f(w.hist);
-    for (int a = 0; a < 7; ++a) { f(w.sst[a]); f(w.mst[a]); }
-    f(w.msrc); f(w.msx); f(w.msy); f(w.msz); f(w.msid); f(w.n_mirror);
-    f(w.scan); f(w.bsum); f(w.cs); f(w.ce); f(w.mcs); f(w.mce);
-    f(w.sten); f(w.scnt); f(w.gmask); f(w.hard); f(w.hard_n); f(w.hard_r2);
-    f(w.hard_id); f(w.redo); f(w.redo_n); f(w.qr_scratch); f(w.P); f(w.eta);
-    f(w.hand); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
+    f(w.off); f(w.prm); f(w.grid); f(w.bbox); f(w.summary); f(w.err); f(w.cnt);
+    f(w.keys0); f(w.keys1); f(w.vals0); f(w.vals1); f(w.hist);
+    for (int a = 0; a < 7; ++a) f(w.sst[a]);
+    for (int a = 0; a < 3; ++a) f(w.xref[a]);
+    f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
+    f(w.vl); f(w.vcnt); f(w.rec); f(w.hsten); f(w.hard); f(w.hard_n);
+    f(w.hard_r2); f(w.hard_id); f(w.redo); f(w.redo_n); f(w.qr_scratch);
+    f(w.P); f(w.eta); f(w.hand); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
     w.n_max = w.cells_max = 0;
@@ -133,6 +129,7 @@ void lp_config_default(lp_config* cfg)
     cfg->ghost_margin = 0.5;
     cfg->fallback_tol = 1e-12;
     cfg->debug_flags = 0;
+    cfg->skin = 0.1;
 }
 
 lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
@@ -145,7 +142,8 @@ lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
     if (c0.m_max < 1 || c0.m_max > MMAX_LIMIT || !(c0.cond_max > 1.0) ||
         !(c0.ghost_margin >= 0.0) || !(c0.fallback_tol >= 0.0) ||
         (c0.weight != LP_W_UNIT && c0.weight != LP_W_GAUSS) ||
-        (c0.precision != LP_FP64 && c0.precision != LP_FP32_REFINED))
+        (c0.precision != LP_FP64 && c0.precision != LP_FP32_REFINED) ||
+        !(c0.skin >= 0.0 && c0.skin <= 1.0))
         return LP_E_ARG;
     lp_ctx* c = new (std::nothrow) lp_ctx();
     if (!c) return LP_E_ARG;
@@ -191,15 +189,15 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
         if (e == hipSuccess) e = alloc(p, cnt);
     };
     A(w.off, SYS_CAP + 1); A(w.prm, SYS_CAP); A(w.grid, SYS_CAP);
-    A(w.bbox, 6 * SYS_CAP); A(w.mcount, 1); A(w.summary, 1); A(w.err, 1);
-    A(w.cnt, 1);
+    A(w.bbox, 6 * SYS_CAP); A(w.summary, 1); A(w.err, 1); A(w.cnt, 1);
     A(w.keys0, n_max); A(w.keys1, n_max); A(w.vals0, n_max); A(w.vals1, n_max);
     A(w.hist, 256 * nb);
-    for (int a = 0; a < 7; ++a) { A(w.sst[a], n_max); A(w.mst[a], n_max); }
-    A(w.msrc, n_max); A(w.msx, n_max); A(w.msy, n_max); A(w.msz, n_max);
-    A(w.msid, n_max); A(w.n_mirror, 1); A(w.scan, 1); A(w.bsum, nb + 1);
-    A(w.cs, cells_max); A(w.ce, cells_max); A(w.mcs, cells_max); A(w.mce, cells_max);
-    A(w.sten, (int64_t)mm * n_max); A(w.scnt, n_max); A(w.gmask, n_max);
+    for (int a = 0; a < 7; ++a) A(w.sst[a], n_max);
+    for (int a = 0; a < 3; ++a) A(w.xref[a], n_max);
+    A(w.mirror_of, n_max); A(w.msrc, n_max); A(w.bsum, nb + 1);
+    A(w.cs, cells_max); A(w.ce, cells_max);
+    A(w.vl, (int64_t)VCAP * n_max); A(w.vcnt, n_max);
+    A(w.rec, (int64_t)REC_FIELDS * n_max); A(w.hsten, (int64_t)mm * n_max);
     A(w.hard, n_max); A(w.hard_n, 1);
     A(w.hard_r2, (int64_t)HARD_SLOTS * HARD_CAP);
     A(w.hard_id, (int64_t)HARD_SLOTS * HARD_CAP);
@@ -211,6 +209,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     if (e == hipSuccess) e = hipHostMalloc((void**)&w.h_summary, sizeof(Summary));
     if (e == hipSuccess) e = hipMemset(w.err, 0, sizeof(ErrWord));
     if (e == hipSuccess) e = hipMemset(w.cnt, 0, sizeof(Counters));
+    if (e == hipSuccess) e = hipMemset(w.summary, 0, sizeof(Summary));
     if (e == hipSuccess) {
         ErrWord ew{0, 0, ~0ull};
         e = hipMemcpy(w.err, &ew, sizeof(ew), hipMemcpyHostToDevice);
@@ -223,7 +222,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     w.cells_max = cells_max;
     w.m_max = mm;
     w.hist_cap = 256 * nb;
-    c->cells_ok = c->stencils_ok = false;
+    c->cells_ok = c->stencils_ok = c->list_ok = false;
     if (c->n_sys > 0) {
         // re-upload the systems into the new buffers
         std::vector<int64_t> off = c->h_off;
@@ -271,7 +270,7 @@ lp_status lp_set_systems(lp_ctx* c, int32_t n_sys, const int64_t* offsets,
     c->h_prm.assign(params, params + n_sys);
     c->n_sys = n_sys;
     c->n = offsets[n_sys];
-    c->cells_ok = c->stencils_ok = false;
+    c->cells_ok = c->stencils_ok = c->list_ok = false;
     if (c->w.n_max == 0) return LP_OK;   // uploaded by lp_reserve
     hipError_t e = hipMemcpyAsync(c->w.off, c->h_off.data(),
                                   sizeof(int64_t) * (n_sys + 1),
@@ -291,7 +290,8 @@ lp_status lp_build_cells(lp_ctx* c, lp_state* s, int32_t* perm)
     if (r != LP_OK) return r;
     double* st[7];
     state_arrays(s, st);
-    r = cells_build(c, st, perm, true, st);
+    r = cells_build(c, st, perm);
+    if (r == LP_OK) r = state_write_back(c, st);
     if (r == LP_OK) c->built_x = s->x;
     return r;
 }
@@ -304,7 +304,7 @@ lp_status lp_neighbors(lp_ctx* c, const lp_state* s, int64_t* cand_off,
     if (!s) return LP_E_ARG;
     lp_status r = check_ready(c, s);
     if (r != LP_OK) return r;
-    if (!c->cells_ok || c->built_x != s->x) {
+    if (!c->cells_ok || !c->list_ok || c->built_x != s->x) {
         c->err = "lp_build_cells must be called on this state first";
         return LP_E_STATE;
     }
@@ -312,9 +312,8 @@ lp_status lp_neighbors(lp_ctx* c, const lp_state* s, int64_t* cand_off,
     state_arrays(s, st);
     r = stencils_build(c, st);
     if (r != LP_OK) return r;
-    if (n_mirror) *n_mirror = c->n_mirror;
     return stencils_export(c, st, cand_off, cand_idx, cap, needed, sten_cnt,
-                           sten_idx, ghost_mask);
+                           sten_idx, ghost_mask, n_mirror);
 }
 
 lp_status lp_fit_derivs(lp_ctx* c, const lp_state* s, const double* f,
@@ -367,17 +366,27 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
     double* in[7];
     state_arrays(s, in);
     prof_mark(c, 0, false);
-    r = cells_build(c, in, perm, false, in);
+    // the neighbour list stays valid until some particle has moved half
+    // the skin since the last build
+    bool rebuild = !c->list_ok || !(c->cfg.skin > 0.0);
+    if (!rebuild) {
+        double ratio = -1.0;
+        r = list_displacement(c, in, &ratio);
+        if (r != LP_OK) return r;
+        rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.49);
+    }
+    r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm);
     prof_mark(c, 0, true);
     if (r != LP_OK) return r;
+    if (rebuild) ++c->rebuilds;
     const double* sorted[7];
     double* const* sst = c->w.sst;
     for (int a = 0; a < 7; ++a) sorted[a] = sst[a];
     r = stencils_build(c, sorted);
     if (r == LP_OK) r = step_rhs(c, sorted);
     if (r == LP_OK) r = step_update(c, sorted, dt, in);
-    // the cell tables describe the positions before the update
-    c->cells_ok = c->stencils_ok = false;
+    // stencils of the API calls refer to lp_build_cells' state
+    c->stencils_ok = false;
     c->built_x = nullptr;
     if (r == LP_OK && c->prof) {
         hipError_t e = hipEventSynchronize(c->ev[13]);
@@ -462,6 +471,8 @@ lp_status lp_stats(lp_ctx* c, int64_t* out8)
     out8[2] = (int64_t)k.qr_refits;
     out8[3] = (int64_t)k.hard_stencils;
     out8[4] = (int64_t)k.below_wall;
+    out8[5] = c->rebuilds;
+    c->rebuilds = 0;
     Counters z{};
     e = hipMemcpyAsync(c->w.cnt, &z, sizeof(z), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

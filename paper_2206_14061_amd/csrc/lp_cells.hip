@@ -1,6 +1,8 @@
 // Morton-sorted cell list and mirror particles (the paper's octree of
 // Sec. 3.1 step 4 / Sec. 3.2 replaced by a uniform cell list sorted in
 // Z order; mirrors of Sec. 3.1 step 9).
+#include <cstring>
+
 #include "lp_internal.h"
 
 namespace lp {
@@ -19,12 +21,10 @@ __device__ __forceinline__ double ord_dec(unsigned long long e)
     return __longlong_as_double((long long)b);
 }
 
-__global__ void k_bbox_init(unsigned long long* bbox, int n_sys,
-                            unsigned long long* mcount)
+__global__ void k_bbox_init(unsigned long long* bbox, int n_sys)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 6 * n_sys) bbox[t] = (t % 6) < 3 ? ~0ull : 0ull;
-    if (t == 0) *mcount = 0;
 }
 
 constexpr int BBOX_CHUNK = 32;
@@ -38,19 +38,16 @@ __device__ void bbox_flush(unsigned long long* bbox, int s, const double* lo,
     }
 }
 
-// Per-system bounding box of the real particles and the number of
-// particles closer than R to their wall (the mirror count).
+// Per-system bounding box of the real particles.
 __global__ void k_bbox(int64_t n, int n_sys, const int64_t* off,
-                       const lp_params* prm, const double* x,
-                       const double* y, const double* z,
-                       unsigned long long* bbox, unsigned long long* mcount)
+                       const double* x, const double* y, const double* z,
+                       unsigned long long* bbox)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = t * BBOX_CHUNK;
     const int lane = threadIdx.x & 63;
     int cur = -1;
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    unsigned int mc = 0;
     if (b < n) {
         const int64_t e = (b + BBOX_CHUNK < n) ? b + BBOX_CHUNK : n;
         for (int64_t i = b; i < e; ++i) {
@@ -63,13 +60,11 @@ __global__ void k_bbox(int64_t n, int n_sys, const int64_t* off,
                 lo[1] = hi[1] = y[i];
                 lo[2] = hi[2] = z[i];
             }
-            double q[3] = {x[i], y[i], z[i]};
+            const double q[3] = {x[i], y[i], z[i]};
             for (int a = 0; a < 3; ++a) {
                 lo[a] = fmin(lo[a], q[a]);
                 hi[a] = fmax(hi[a], q[a]);
             }
-            const lp_params& p = prm[s];
-            if (dsub(z[i], p.wall_z) < p.R) ++mc;
         }
     }
     // wave-level combine when every lane holds the same system
@@ -85,15 +80,13 @@ __global__ void k_bbox(int64_t n, int n_sys, const int64_t* off,
     } else if (cur >= 0) {
         bbox_flush(bbox, cur, lo, hi);
     }
-    for (int off2 = 32; off2 > 0; off2 >>= 1) mc += __shfl_xor(mc, off2);
-    if (lane == 0 && mc) atomicAdd(mcount, (unsigned long long)mc);
 }
 
-// Grid of each system from its bounding box; totals for the host.
+// Grid of each system from its bounding box; totals for the host.  Cell
+// edge c = R (1 + skin) (1 + 2^-20) >= the list radius.
 __global__ void k_grid(int n_sys, const int64_t* off, const lp_params* prm,
-                       const unsigned long long* bbox,
-                       const unsigned long long* mcount, GridInfo* grid,
-                       Summary* sum)
+                       double skin, const unsigned long long* bbox,
+                       GridInfo* grid, Summary* sum)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int64_t base = 0;
@@ -108,7 +101,10 @@ __global__ void k_grid(int n_sys, const int64_t* off, const lp_params* prm,
         g.h = p.h;
         g.inv_h = 1.0 / p.h;
         g.wall = p.wall_z;
-        const double c = dmul(p.R, 1.0 + 1.0 / 1048576.0);
+        g.Rv = dmul(p.R, 1.0 + skin);
+        g.Rv2 = dmul(g.Rv, g.Rv);
+        g.inv_skin2 = skin > 0.0 ? 1.0 / ((skin * p.R) * (skin * p.R)) : 0.0;
+        const double c = dmul(g.Rv, 1.0 + 1.0 / 1048576.0);
         g.inv_c = 1.0 / c;
         if (g.pend > g.pbeg) {
             double lo[3], hi[3];
@@ -120,11 +116,9 @@ __global__ void k_grid(int n_sys, const int64_t* off, const lp_params* prm,
             g.y0 = lo[1];
             const double zl = dsub(p.wall_z, p.R);
             g.z0 = zl < lo[2] ? zl : lo[2];
-            const double zm = dsub(dmul(2.0, p.wall_z), lo[2]);
-            const double zt = zm > hi[2] ? zm : hi[2];
             const double ex = dmul(dsub(hi[0], g.x0), g.inv_c);
             const double ey = dmul(dsub(hi[1], g.y0), g.inv_c);
-            const double ez = dmul(dsub(zt, g.z0), g.inv_c);
+            const double ez = dmul(dsub(hi[2], g.z0), g.inv_c);
             if (!(ex < 65535.0 && ey < 65535.0 && ez < 65535.0)) {
                 bad = 1;
                 g.nx = g.ny = g.nz = 1;
@@ -148,7 +142,6 @@ __global__ void k_grid(int n_sys, const int64_t* off, const lp_params* prm,
         grid[s] = g;
     }
     sum->total_cells = base;
-    sum->n_mirror = (int64_t)*mcount;
     sum->axis_bits = bits;
     sum->bad = bad;
 }
@@ -167,12 +160,12 @@ __device__ __forceinline__ void cell_of(const GridInfo& g, double x, double y,
 // Sort keys (system, Morton code of the cell) and identity values.
 __global__ void k_keys(int64_t n, int n_sys, const int64_t* off,
                        const GridInfo* grid, const double* x, const double* y,
-                       const double* z, const int32_t* sys_src, int shift_sys,
+                       const double* z, int shift_sys,
                        unsigned long long* keys, int32_t* vals)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int s = sys_src ? sys_of(off, n_sys, sys_src[i]) : sys_of(off, n_sys, i);
+    const int s = sys_of(off, n_sys, i);
     const GridInfo& g = grid[s];
     int cx, cy, cz;
     cell_of(g, x[i], y[i], z[i], cx, cy, cz);
@@ -301,109 +294,12 @@ __global__ void k_fill_i32(int64_t n, int32_t* a, int32_t v)
     if (i < n) a[i] = v;
 }
 
-// ---- mirror compaction (exclusive scan of the wall flags) ------------
-
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum,
-                                                    uint32_t& total)
-{
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    uint32_t inc = v;
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(inc, d);
-        if (lane >= d) inc += o;
-    }
-    if (lane == 63) wsum[wave] = inc;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (int w = 0; w < BLOCK / 64; ++w) {
-        if (w < wave) pre += wsum[w];
-        tot += wsum[w];
-    }
-    __syncthreads();
-    total = tot;
-    return pre + inc - v;
-}
-
-__device__ __forceinline__ bool wall_flag(const int64_t* off, int n_sys,
-                                          const GridInfo* grid, const double* z,
-                                          int64_t i)
-{
-    const GridInfo& g = grid[sys_of(off, n_sys, i)];
-    return dsub(z[i], g.wall) < g.R;
-}
-
-__global__ void k_mirror_count(int64_t n, int n_sys, const int64_t* off,
-                               const GridInfo* grid, const double* z,
-                               int32_t* bsum)
-{
-    __shared__ uint32_t wsum[BLOCK / 64];
-    const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
-    uint32_t c = 0;
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        const int64_t i = b + r;
-        if (i < n && wall_flag(off, n_sys, grid, z, i)) ++c;
-    }
-    uint32_t tot;
-    block_excl_scan(c, wsum, tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = (int32_t)tot;
-}
-
-__global__ void k_mirror_write(int64_t n, int n_sys, const int64_t* off,
-                               const GridInfo* grid, const int32_t* bsum,
-                               const double* x, const double* y,
-                               const double* z, const double* u,
-                               const double* v, const double* w,
-                               const double* V, double* mx, double* my,
-                               double* mz, double* mu, double* mv, double* mw,
-                               double* mV, int32_t* msrc)
-{
-    __shared__ uint32_t wsum[BLOCK / 64];
-    const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
-    uint32_t c = 0;
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        const int64_t i = b + r;
-        if (i < n && wall_flag(off, n_sys, grid, z, i)) ++c;
-    }
-    uint32_t tot;
-    uint32_t k = block_excl_scan(c, wsum, tot) + (uint32_t)bsum[blockIdx.x];
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        const int64_t i = b + r;
-        if (i < n && wall_flag(off, n_sys, grid, z, i)) {
-            const GridInfo& g = grid[sys_of(off, n_sys, i)];
-            mx[k] = x[i];
-            my[k] = y[i];
-            mz[k] = dsub(dmul(2.0, g.wall), z[i]);
-            mu[k] = u[i];
-            mv[k] = v[i];
-            mw[k] = -w[i];
-            mV[k] = V[i];
-            msrc[k] = (int32_t)i;
-            ++k;
-        }
-    }
-}
-
-__global__ void k_mirror_order(int64_t nm, int64_t n, const int32_t* order,
-                               const double* mx, const double* my,
-                               const double* mz, double* sx, double* sy,
-                               double* sz, int32_t* sid)
-{
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nm) return;
-    const int32_t k = order[q];
-    sx[q] = mx[k];
-    sy[q] = my[k];
-    sz[q] = mz[k];
-    sid[q] = (int32_t)(n + k);
-}
-
 // Cell start/end from sorted keys; positions give the linear cell index.
 __global__ void k_cell_bounds(int64_t cnt, int n_sys, const int64_t* off,
                               const GridInfo* grid,
                               const unsigned long long* keys,
                               const double* x, const double* y,
-                              const double* z, const int32_t* sys_src,
-                              int32_t* cs, int32_t* ce)
+                              const double* z, int32_t* cs, int32_t* ce)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt) return;
@@ -411,7 +307,7 @@ __global__ void k_cell_bounds(int64_t cnt, int n_sys, const int64_t* off,
     const bool first = (i == 0) || keys[i - 1] != k;
     const bool last = (i == cnt - 1) || keys[i + 1] != k;
     if (!first && !last) return;
-    const int s = sys_src ? sys_of(off, n_sys, sys_src[i]) : sys_of(off, n_sys, i);
+    const int s = sys_of(off, n_sys, i);
     const GridInfo& g = grid[s];
     int cx, cy, cz;
     cell_of(g, x[i], y[i], z[i], cx, cy, cz);
@@ -420,14 +316,32 @@ __global__ void k_cell_bounds(int64_t cnt, int n_sys, const int64_t* off,
     if (last) ce[c] = (int32_t)(i + 1);
 }
 
-__global__ void k_gather_src(int64_t nm, const int32_t* order,
-                             const int32_t* msrc, int32_t* out)
+__global__ void k_iota(int64_t n, int32_t* p)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nm) out[q] = msrc[order[q]];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
 }
 
-__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+// Largest (displacement / (skin R))^2 since the list build.
+__global__ void k_disp(int64_t n, int n_sys, const int64_t* off,
+                       const GridInfo* grid, const double* x, const double* y,
+                       const double* z, const double* rx, const double* ry,
+                       const double* rz, Summary* sum)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (i < n) {
+        const GridInfo& g = grid[sys_of(off, n_sys, i)];
+        const double dx = x[i] - rx[i], dy = y[i] - ry[i], dz = z[i] - rz[i];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        r = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
+        if (!(r == r)) r = INFINITY;   // non-finite positions force a rebuild
+    }
+    for (int d = 32; d > 0; d >>= 1) r = fmax(r, __shfl_xor(r, d));
+    if ((threadIdx.x & 63) == 0) atomicMax(&sum->disp, ord_enc(r));
+}
+
+__global__ void k_disp_init(Summary* sum) { sum->disp = ord_enc(0.0); }
 
 inline unsigned int blocks_for(int64_t n, int per = BLOCK)
 {
@@ -464,8 +378,7 @@ void radix_sort(lp_ctx* c, int64_t cnt, int bits, unsigned long long*& kr,
 
 }  // namespace
 
-lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out,
-                      bool write_back, double* const out[7])
+lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out)
 {
     Work& w = c->w;
     const int64_t n = c->n;
@@ -473,15 +386,16 @@ lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out,
     hipStream_t s = c->stream;
     c->cells_ok = false;
     c->stencils_ok = false;
+    c->list_ok = false;
 
     hipLaunchKernelGGL(k_bbox_init, dim3(blocks_for(6 * ns)), dim3(BLOCK), 0,
-                       s, w.bbox, ns, w.mcount);
+                       s, w.bbox, ns);
     if (n > 0)
         hipLaunchKernelGGL(k_bbox, dim3(blocks_for((n + BBOX_CHUNK - 1) / BBOX_CHUNK)),
-                           dim3(BLOCK), 0, s, n, ns, w.off, w.prm, st[0], st[1],
-                           st[2], w.bbox, w.mcount);
+                           dim3(BLOCK), 0, s, n, ns, w.off, st[0], st[1], st[2],
+                           w.bbox);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, ns, w.off, w.prm,
-                       w.bbox, w.mcount, w.grid, w.summary);
+                       c->cfg.skin, w.bbox, w.grid, w.summary);
     hipError_t e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary),
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -498,19 +412,17 @@ lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out,
     }
     c->axis_bits = sm.axis_bits;
     c->total_cells = sm.total_cells;
-    c->n_mirror = sm.n_mirror;
     int sys_bits = 0;
     while ((1 << sys_bits) < ns) ++sys_bits;
     const int shift_sys = 3 * sm.axis_bits;
     const int bits = shift_sys + sys_bits;
 
-    // sort the real particles
     unsigned long long* kr = nullptr;
     int32_t* vr = nullptr;
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, ns,
-                           w.off, w.grid, st[0], st[1], st[2],
-                           (const int32_t*)nullptr, shift_sys, w.keys0, w.vals0);
+                           w.off, w.grid, st[0], st[1], st[2], shift_sys, w.keys0,
+                           w.vals0);
         radix_sort(c, n, bits, kr, vr);
         hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
                            vr, st[0], st[1], st[2], st[3], st[4], st[5], st[6],
@@ -519,58 +431,71 @@ lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out,
         if (perm_out)
             hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
                                n, vr, perm_out);
+        for (int a = 0; a < 3; ++a)
+            hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
+                               n, w.sst[a], w.xref[a]);
     }
     const int64_t tc = sm.total_cells;
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(tc)), dim3(BLOCK), 0, s, tc, w.cs, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(tc)), dim3(BLOCK), 0, s, tc, w.ce, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(tc)), dim3(BLOCK), 0, s, tc, w.mcs, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(tc)), dim3(BLOCK), 0, s, tc, w.mce, 0);
     if (n > 0)
         hipLaunchKernelGGL(k_cell_bounds, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
                            n, ns, w.off, w.grid, kr, w.sst[0], w.sst[1], w.sst[2],
-                           (const int32_t*)nullptr, w.cs, w.ce);
-
-    // mirrors, in ascending order of their (sorted) source
-    const int64_t nm = sm.n_mirror;
-    if (n > 0) {
-        const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
-        hipLaunchKernelGGL(k_mirror_count, dim3((unsigned)nb), dim3(BLOCK), 0, s,
-                           n, ns, w.off, w.grid, w.sst[2], w.bsum);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s,
-                           (uint32_t*)w.bsum, nb);
-        hipLaunchKernelGGL(k_mirror_write, dim3((unsigned)nb), dim3(BLOCK), 0, s,
-                           n, ns, w.off, w.grid, w.bsum, w.sst[0], w.sst[1],
-                           w.sst[2], w.sst[3], w.sst[4], w.sst[5], w.sst[6],
-                           w.mst[0], w.mst[1], w.mst[2], w.mst[3], w.mst[4],
-                           w.mst[5], w.mst[6], w.msrc);
-    }
-    if (nm > 0) {
-        hipLaunchKernelGGL(k_keys, dim3(blocks_for(nm)), dim3(BLOCK), 0, s, nm, ns,
-                           w.off, w.grid, w.mst[0], w.mst[1], w.mst[2],
-                           (const int32_t*)w.msrc, shift_sys, w.keys0, w.vals0);
-        unsigned long long* mk = nullptr;
-        int32_t* mv = nullptr;
-        radix_sort(c, nm, bits, mk, mv);
-        hipLaunchKernelGGL(k_mirror_order, dim3(blocks_for(nm)), dim3(BLOCK), 0, s,
-                           nm, n, mv, w.mst[0], w.mst[1], w.mst[2], w.msx, w.msy,
-                           w.msz, w.msid);
-        // the system of cell-ordered mirror q is that of its source
-        // msrc[order[q]]; the free value buffer holds those sources
-        int32_t* srcs = (w.vals1 == mv) ? w.vals0 : w.vals1;
-        hipLaunchKernelGGL(k_gather_src, dim3(blocks_for(nm)), dim3(BLOCK), 0, s,
-                           nm, mv, w.msrc, srcs);
-        hipLaunchKernelGGL(k_cell_bounds, dim3(blocks_for(nm)), dim3(BLOCK), 0, s,
-                           nm, ns, w.off, w.grid, mk, w.msx, w.msy, w.msz,
-                           (const int32_t*)srcs, w.mcs, w.mce);
-    }
-    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, w.n_mirror, nm);
-    if (write_back && n > 0)
-        for (int a = 0; a < 7; ++a)
-            hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
-                               n, w.sst[a], out[a]);
+                           w.cs, w.ce);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "cell build launch");
     c->cells_ok = true;
+    return list_build(c);
+}
+
+lp_status state_copy(lp_ctx* c, double* const st[7], int32_t* perm_out)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    if (n > 0) {
+        for (int a = 0; a < 7; ++a)
+            hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, n, st[a], w.sst[a]);
+        if (perm_out)
+            hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, n, perm_out);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "state copy");
+}
+
+lp_status state_write_back(lp_ctx* c, double* const out[7])
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    if (n > 0)
+        for (int a = 0; a < 7; ++a)
+            hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, n, w.sst[a], out[a]);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "state write-back");
+}
+
+lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    *ratio = -1.0;
+    if (!c->list_ok) return LP_OK;
+    hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
+    if (n > 0)
+        hipLaunchKernelGGL(k_disp, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
+                           c->n_sys, w.off, w.grid, st[0], st[1], st[2], w.xref[0],
+                           w.xref[1], w.xref[2], w.summary);
+    hipError_t e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary),
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "displacement check");
+    const unsigned long long enc = w.h_summary->disp;
+    const unsigned long long b = (enc >> 63) ? (enc & 0x7FFFFFFFFFFFFFFFull) : ~enc;
+    double r;
+    std::memcpy(&r, &b, sizeof(r));
+    *ratio = r;
     return LP_OK;
 }
 

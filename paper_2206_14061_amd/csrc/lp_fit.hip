@@ -15,7 +15,7 @@
 // The second fit (P, eta) needs only first derivatives: pass 1 stores
 // rows 0-2 of G^{-1}, so pass 2 costs two moment accumulations and a 3x9
 // product per particle.
-#include "lp_internal.h"
+#include "lp_visit.h"
 
 namespace lp {
 
@@ -54,53 +54,35 @@ __device__ __forceinline__ void ghost_offset(int o, double& sx, double& sy,
     sz = (o & 4) ? 1.0 : -1.0;
 }
 
-// Coordinates of point j (real or mirror).
-__device__ __forceinline__ void point_xyz(const View& v, int32_t j, double& x,
-                                          double& y, double& z)
+// Taylor row of a stencil point and its weight.
+__device__ __forceinline__ double point_row(const View& v, const GridInfo& g,
+                                            double dx, double dy, double dz,
+                                            double a[9])
 {
-    if (j < v.n) {
-        x = v.x[j];
-        y = v.y[j];
-        z = v.z[j];
-    } else {
-        const int32_t q = j - (int32_t)v.n;
-        x = v.mx[q];
-        y = v.my[q];
-        z = v.mz[q];
-    }
+    taylor_row(dx * g.inv_h, dy * g.inv_h, dz * g.inv_h, a);
+    if (v.weight == LP_W_GAUSS)
+        return exp(-4.0 * (dx * dx + dy * dy + dz * dz) / g.R2);
+    return 1.0;
 }
 
-// Row k of particle i's fit (k < m: stencil entry; else ghost number
-// k - m in octant order).  Returns the weight; point id in *jout (-1 for
-// a ghost).
-__device__ __forceinline__ double fit_row(const View& v, const GridInfo& g,
-                                          int64_t i, double xi, double yi,
-                                          double zi, int k, int m, uint8_t gm,
-                                          double a[9], int32_t* jout)
+// Taylor row of the ghost in octant o (offset h s) and its weight.
+__device__ __forceinline__ double ghost_row(const View& v, const GridInfo& g, int o,
+                                            double a[9])
 {
-    if (k < m) {
-        const int32_t j = v.sten[(int64_t)k * v.n + i];
-        double xj, yj, zj;
-        point_xyz(v, j, xj, yj, zj);
-        const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
-        taylor_row(dx * g.inv_h, dy * g.inv_h, dz * g.inv_h, a);
-        *jout = j;
-        if (v.weight == LP_W_GAUSS)
-            return exp(-4.0 * (dx * dx + dy * dy + dz * dz) / g.R2);
-        return 1.0;
-    }
-    int r = k - m, o = 0;
-    for (; o < 8; ++o)
-        if ((gm >> o) & 1) {
-            if (r == 0) break;
-            --r;
-        }
     double sx, sy, sz;
     ghost_offset(o, sx, sy, sz);
     taylor_row(sx, sy, sz, a);
-    *jout = -1;
     if (v.weight == LP_W_GAUSS) return exp(-12.0 * g.h * g.h / g.R2);
     return 1.0;
+}
+
+// Velocity carried by a stencil point (mirrors reverse w).
+__device__ __forceinline__ void point_velocity(const View& v, const Pt& p,
+                                               double& u, double& vv, double& w)
+{
+    u = v.u[p.src];
+    vv = v.v[p.src];
+    w = p.mirror ? -v.w[p.src] : v.w[p.src];
 }
 
 // G = U^T U in place (packed upper); returns min U_jj / max U_jj, or -1
@@ -222,10 +204,14 @@ __device__ __forceinline__ void store_hand(double* hand, int64_t n, int64_t i,
                                            const double* ginv3, const Closure& r,
                                            const double vis[3])
 {
-    if (ginv3)
+    if (ginv3) {
+#pragma unroll
         for (int q = 0; q < 27; ++q) hand[(int64_t)q * n + i] = ginv3[q];
+    }
+#pragma unroll
     for (int q = 0; q < 6; ++q) hand[(int64_t)(27 + q) * n + i] = r.gd[q];
     hand[(int64_t)33 * n + i] = r.div;
+#pragma unroll
     for (int q = 0; q < 3; ++q) hand[(int64_t)(34 + q) * n + i] = vis[q];
 }
 
@@ -292,46 +278,61 @@ __device__ double qr_solve(double* A, double* B, int mt, int nc, int nf,
     return rmax > 0.0 ? rmin / rmax : 0.0;
 }
 
-// Field values at a point and at the ghosts.
-struct GenericFields {
-    const double* f;   // k x n
-    int k;
-    int32_t msign[8];
-    int32_t gzero[8];
-};
-
-template <class Get>
-__device__ uint8_t qr_fit_point(const View& v, const GridInfo& g, int64_t i,
-                                int nf, Get&& get, double* scratch,
-                                double* coef /* nf x 9, ld 9 */)
+// Calls f(a, w, p) for every fit row of real particle i: the stencil rows
+// (p = the stencil point) then the ghost rows in octant order (p = null).
+// Returns the number of rows.
+template <class F>
+__device__ __forceinline__ int for_rows(const View& v, const GridInfo& g,
+                                        int64_t i, const Rec& r, F&& f)
 {
-    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
-    const int m = min(max(v.scnt[i], 0), v.m_max);
-    const uint8_t gm = v.gmask[i];
-    const int mt = m + __popc(gm);
+    int m = 0;
+    visit_stencil(v, g, i, r, [&](const Pt& p, double dx, double dy, double dz) {
+        double a[9];
+        const double w = point_row(v, g, dx, dy, dz, a);
+        f(a, w, &p);
+        ++m;
+    });
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+        if ((r.gm >> o) & 1) {
+            double a[9];
+            const double w = ghost_row(v, g, o, a);
+            f(a, w, (const Pt*)nullptr);
+            ++m;
+        }
+    return m;
+}
+
+// Householder least squares of particle i's rows (QR refit path).  vals(p,
+// out) gives the nf field values at a stencil point (p != null) or at the
+// ghosts (p == null); own: the values at the particle.  coef (nf x 9, ld
+// 9) receives derivative estimates.  Returns FLAG_QR plus FLAG_LINEAR
+// when the linear fallback was taken.
+template <class Vals>
+__device__ uint8_t qr_fit_point(const View& v, const GridInfo& g, int64_t i,
+                                const Rec& r, int nf, const double* own,
+                                Vals&& vals, double* scratch, double* coef)
+{
     double* A = scratch;
     double* B = scratch + MAXROWS * 9;
-    double fi[8];
-    get(-2, fi);   // own values
     auto build = [&]() {
-        for (int k = 0; k < mt; ++k) {
-            double a[9];
-            int32_t j;
-            const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
+        int k = 0;
+        return for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+            if (k >= MAXROWS) return;
             const double sw = sqrt(w);
             double fj[8];
-            get(j, fj);
+            vals(p, fj);
             for (int q = 0; q < 9; ++q) A[k * 9 + q] = sw * a[q];
-            for (int f = 0; f < nf; ++f) B[k * 8 + f] = sw * (fj[f] - fi[f]);
-        }
+            for (int f = 0; f < nf; ++f) B[k * 8 + f] = sw * (fj[f] - own[f]);
+            ++k;
+        });
     };
     double C[9 * 8];
     uint8_t flags = FLAG_QR;
     double ratio = 0.0;
-    if (mt >= 9) {
-        build();
-        ratio = qr_solve(A, B, mt, 9, nf, C);
-    }
+    int mt = build();
+    if (mt > MAXROWS) mt = MAXROWS;
+    if (mt >= 9) ratio = qr_solve(A, B, mt, 9, nf, C);
     if (mt < 9 || ratio < v.fallback_tol) {
         flags |= FLAG_LINEAR;
         for (int q = 0; q < 72; ++q) C[q] = 0.0;
@@ -346,7 +347,58 @@ __device__ uint8_t qr_fit_point(const View& v, const GridInfo& g, int64_t i,
     return flags;
 }
 
+// Solves the Gram system for nf right-hand sides; coefficients unscaled
+// (per unit h).  Returns false when the stencil needs a QR refit.
+template <int NF>
+__device__ __forceinline__ bool gram_solve(double (&G)[45], const double (&B)[NF][9],
+                                           int mt, double redo_ratio, bool force_qr,
+                                           double (&c)[NF][9], double (&ginv3)[27],
+                                           bool want_ginv, uint8_t& fl)
+{
+    if (mt < 9) {
+        fl = FLAG_LINEAR;
+        const double ratio = cholesky<3>(G);
+        if (ratio < redo_ratio || force_qr) return false;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) c[f][q] = q < 3 ? B[f][q] : 0.0;
+            chol_solve<3>(G, c[f]);
+        }
+        if (want_ginv) ginv_rows<3>(G, ginv3);
+    } else {
+        fl = 0;
+        const double ratio = cholesky<9>(G);
+        if (ratio < redo_ratio || force_qr) return false;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) c[f][q] = B[f][q];
+            chol_solve<9>(G, c[f]);
+        }
+        if (want_ginv) ginv_rows<9>(G, ginv3);
+    }
+    return true;
+}
+
+__device__ __forceinline__ void gram_add(double (&G)[45], const double* a, double w)
+{
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const double wa = w * a[p];
+#pragma unroll
+        for (int q = p; q < 9; ++q) G[uix(p, q)] += wa * a[q];
+    }
+}
+
 // ---- lp_fit_derivs -------------------------------------------------------
+
+struct GenericFields {
+    const double* f;   // k x n
+    int k;
+    int32_t msign[8];
+    int32_t gzero[8];
+};
 
 template <int NF>
 __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
@@ -359,10 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
     if (i >= v.n) return;
     const int64_t n = v.n;
     const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
-    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
-    const int m = min(max(v.scnt[i], 0), v.m_max);
-    const uint8_t gm = v.gmask[i];
-    const int mt = m + __popc(gm);
+    const Rec r = load_rec(v, i);
     double fi[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) fi[f] = F.f[(int64_t)f * n + i];
@@ -373,49 +422,25 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
     for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int q = 0; q < 9; ++q) B[f][q] = 0.0;
-    for (int k = 0; k < mt; ++k) {
-        double a[9];
-        int32_t j;
-        const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
-        double b[NF];
+    const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+        gram_add(G, a, w);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             double fj;
-            if (j < 0) fj = F.gzero[f] ? 0.0 : fi[f];
-            else if (j < n) fj = F.f[(int64_t)f * n + j];
-            else fj = (double)F.msign[f] * F.f[(int64_t)f * n + v.msrc[j - n]];
-            b[f] = w * (fj - fi[f]);
+            if (!p) fj = F.gzero[f] ? 0.0 : fi[f];
+            else if (p->mirror) fj = (double)F.msign[f] * F.f[(int64_t)f * n + p->src];
+            else fj = F.f[(int64_t)f * n + p->src];
+            const double b = w * (fj - fi[f]);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) B[f][q] += a[q] * b;
         }
-#pragma unroll
-        for (int p = 0; p < 9; ++p) {
-            const double wa = w * a[p];
-#pragma unroll
-            for (int q = p; q < 9; ++q) G[uix(p, q)] += wa * a[q];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) B[f][p] += a[p] * b[f];
-        }
-    }
-    uint8_t fl = 0;
-    double c[NF][9];
-    if (mt < 9) {
-        fl = FLAG_LINEAR;
-        const double ratio = cholesky<3>(G);
-        if (ratio < v.redo_ratio || force_qr) goto refit;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) c[f][q] = q < 3 ? B[f][q] : 0.0;
-            chol_solve<3>(G, c[f]);
-        }
-    } else {
-        const double ratio = cholesky<9>(G);
-        if (ratio < v.redo_ratio || force_qr) goto refit;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) c[f][q] = B[f][q];
-            chol_solve<9>(G, c[f]);
-        }
+    });
+    double c[NF][9], ginv3[27];
+    uint8_t fl;
+    if (!gram_solve<NF>(G, B, mt, v.redo_ratio, force_qr != 0, c, ginv3, false, fl)) {
+        redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
+        if (flags) flags[i] = FLAG_QR;
+        return;
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f)
@@ -424,10 +449,6 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
             coef[((int64_t)f * 9 + q) * n + i] =
                 c[f][q] * (q < 3 ? g.inv_h : g.inv_h * g.inv_h);
     if (flags) flags[i] = fl;
-    return;
-refit:
-    redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
-    if (flags) flags[i] = FLAG_QR;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_fit_generic_qr(
@@ -443,17 +464,18 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic_qr(
     for (int64_t t = slot; t < (int64_t)total; t += nth) {
         const int64_t i = redo[t];
         const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
-        auto get = [&](int32_t j, double* out) {
+        const Rec r = load_rec(v, i);
+        double own[8];
+        for (int f = 0; f < F.k; ++f) own[f] = F.f[(int64_t)f * n + i];
+        auto vals = [&](const Pt* p, double* out) {
             for (int f = 0; f < F.k; ++f) {
-                const double own = F.f[(int64_t)f * n + i];
-                if (j == -2) out[f] = own;
-                else if (j < 0) out[f] = F.gzero[f] ? 0.0 : own;
-                else if (j < n) out[f] = F.f[(int64_t)f * n + j];
-                else out[f] = (double)F.msign[f] * F.f[(int64_t)f * n + v.msrc[j - n]];
+                if (!p) out[f] = F.gzero[f] ? 0.0 : own[f];
+                else if (p->mirror) out[f] = (double)F.msign[f] * F.f[(int64_t)f * n + p->src];
+                else out[f] = F.f[(int64_t)f * n + p->src];
             }
         };
         double c[8 * 9];
-        const uint8_t fl = qr_fit_point(v, g, i, F.k, get, scr, c);
+        const uint8_t fl = qr_fit_point(v, g, i, r, F.k, own, vals, scr, c);
         for (int f = 0; f < F.k; ++f)
             for (int q = 0; q < 9; ++q) coef[((int64_t)f * 9 + q) * n + i] = c[f * 9 + q];
         if (flags) flags[i] = fl;
@@ -491,8 +513,10 @@ __device__ __forceinline__ void finish_pass1(const View& v, const lp_params& p,
         o.diag[3 * n + i] = r.mu;
         o.diag[4 * n + i] = r.gn;
     }
-    if (o.coef_u)
+    if (o.coef_u) {
+#pragma unroll
         for (int q = 0; q < 27; ++q) o.coef_u[(int64_t)q * n + i] = c[q];
+    }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pass1(View v, StepOut o,
@@ -502,81 +526,40 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(View v, StepOut o,
 {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     if (i >= v.n) return;
-    const int64_t n = v.n;
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
-    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const Rec r = load_rec(v, i);
     const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
-    const int m = min(max(v.scnt[i], 0), v.m_max);
-    const uint8_t gm = v.gmask[i];
-    const int mt = m + __popc(gm);
     double G[45], B[3][9];
 #pragma unroll
     for (int q = 0; q < 45; ++q) G[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) B[0][q] = B[1][q] = B[2][q] = 0.0;
-    for (int k = 0; k < mt; ++k) {
-        double a[9];
-        int32_t j;
-        const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0;   // ghosts carry u_i (b = 0)
-        if (j >= 0 && j < n) {
-            b0 = w * (v.u[j] - ui);
-            b1 = w * (v.v[j] - vi);
-            b2 = w * (v.w[j] - wi);
-        } else if (j >= n) {
-            const int32_t q = j - (int32_t)n;
-            b0 = w * (v.mu[q] - ui);
-            b1 = w * (v.mv[q] - vi);
-            b2 = w * (v.mw[q] - wi);
-        }
+    const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+        gram_add(G, a, w);
+        if (!p) return;   // ghosts carry u_i (b = 0)
+        double uj, vj, wj;
+        point_velocity(v, *p, uj, vj, wj);
+        const double b0 = w * (uj - ui), b1 = w * (vj - vi), b2 = w * (wj - wi);
 #pragma unroll
-        for (int p = 0; p < 9; ++p) {
-            const double wa = w * a[p];
-#pragma unroll
-            for (int q = p; q < 9; ++q) G[uix(p, q)] += wa * a[q];
-            B[0][p] += a[p] * b0;
-            B[1][p] += a[p] * b1;
-            B[2][p] += a[p] * b2;
+        for (int q = 0; q < 9; ++q) {
+            B[0][q] += a[q] * b0;
+            B[1][q] += a[q] * b1;
+            B[2][q] += a[q] * b2;
         }
+    });
+    double c3[3][9], ginv3[27];
+    uint8_t fl;
+    if (!gram_solve<3>(G, B, mt, v.redo_ratio, force_qr != 0, c3, ginv3, true, fl)) {
+        redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
+        o.flags[i] = FLAG_QR;
+        return;
     }
-    double c[27], ginv3[27];
-    uint8_t fl = 0;
-    if (mt < 9) {
-        fl = FLAG_LINEAR;
-        const double ratio = cholesky<3>(G);
-        if (ratio < v.redo_ratio || force_qr) goto refit;
+    double c[27];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            double t[9];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) t[q] = q < 3 ? B[f][q] : 0.0;
-            chol_solve<3>(G, t);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) c[f * 9 + q] = t[q];
-        }
-        ginv_rows<3>(G, ginv3);
-    } else {
-        const double ratio = cholesky<9>(G);
-        if (ratio < v.redo_ratio || force_qr) goto refit;
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            double t[9];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) t[q] = B[f][q];
-            chol_solve<9>(G, t);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) c[f * 9 + q] = t[q];
-        }
-        ginv_rows<9>(G, ginv3);
-    }
-#pragma unroll
-    for (int q = 0; q < 27; ++q) c[q] *= ((q % 9) < 3 ? g.inv_h : g.inv_h * g.inv_h);
+    for (int q = 0; q < 27; ++q)
+        c[q] = c3[q / 9][q % 9] * ((q % 9) < 3 ? g.inv_h : g.inv_h * g.inv_h);
     finish_pass1(v, v.prm[s], i, c, ginv3, fl, o);
-    return;
-refit:
-    redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
-    o.flags[i] = FLAG_QR;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pass1_qr(View v, StepOut o,
@@ -589,23 +572,21 @@ __global__ __launch_bounds__(BLOCK) void k_pass1_qr(View v, StepOut o,
     const unsigned int total = *redo_n;
     if (slot == 0) atomicAdd(&cnt->qr_refits, (unsigned long long)total);
     double* scr = scratch + slot * (MAXROWS * 17);
-    const int64_t n = v.n;
     for (int64_t t = slot; t < (int64_t)total; t += nth) {
         const int64_t i = redo[t];
         const int s = sys_of(v.off, v.n_sys, i);
         const GridInfo& g = v.grid[s];
-        auto get = [&](int32_t j, double* out) {
-            if (j == -2 || j == -1) {
-                out[0] = v.u[i]; out[1] = v.v[i]; out[2] = v.w[i];
-            } else if (j < n) {
-                out[0] = v.u[j]; out[1] = v.v[j]; out[2] = v.w[j];
+        const Rec r = load_rec(v, i);
+        const double own[3] = {v.u[i], v.v[i], v.w[i]};
+        auto vals = [&](const Pt* p, double* out) {
+            if (!p) {
+                out[0] = own[0]; out[1] = own[1]; out[2] = own[2];
             } else {
-                const int32_t q = j - (int32_t)n;
-                out[0] = v.mu[q]; out[1] = v.mv[q]; out[2] = v.mw[q];
+                point_velocity(v, *p, out[0], out[1], out[2]);
             }
         };
         double c[27];
-        const uint8_t fl = qr_fit_point(v, g, i, 3, get, scr, c);
+        const uint8_t fl = qr_fit_point(v, g, i, r, 3, own, vals, scr, c);
         finish_pass1(v, v.prm[s], i, c, nullptr, fl, o);
     }
 }
@@ -621,44 +602,26 @@ __global__ __launch_bounds__(BLOCK) void k_closure_coef(View v, const double* co
     const int64_t n = v.n;
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
-    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
-    const int m = min(max(v.scnt[i], 0), v.m_max);
-    const uint8_t gm = v.gmask[i];
-    const int mt = m + __popc(gm);
+    const Rec r = load_rec(v, i);
     double c[27];
+#pragma unroll
     for (int q = 0; q < 27; ++q) c[q] = coef_u[(int64_t)q * n + i];
     double G[45];
 #pragma unroll
     for (int q = 0; q < 45; ++q) G[q] = 0.0;
-    for (int k = 0; k < mt; ++k) {
-        double a[9];
-        int32_t j;
-        const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
-#pragma unroll
-        for (int p = 0; p < 9; ++p) {
-            const double wa = w * a[p];
-#pragma unroll
-            for (int q = p; q < 9; ++q) G[uix(p, q)] += wa * a[q];
-        }
-    }
-    double ginv3[27];
-    uint8_t fl = 0;
-    bool qr = force_qr != 0;
-    if (mt < 9) {
-        fl = FLAG_LINEAR;
-        const double ratio = cholesky<3>(G);
-        qr = qr || ratio < v.redo_ratio;
-        if (!qr) ginv_rows<3>(G, ginv3);
-    } else {
-        const double ratio = cholesky<9>(G);
-        qr = qr || ratio < v.redo_ratio;
-        if (!qr) ginv_rows<9>(G, ginv3);
-    }
-    if (qr) {
+    const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt*) {
+        gram_add(G, a, w);
+    });
+    const double B[1][9] = {{0, 0, 0, 0, 0, 0, 0, 0, 0}};
+    double c1[1][9], ginv3[27];
+    uint8_t fl;
+    const bool ok = gram_solve<1>(G, B, mt, v.redo_ratio, force_qr != 0, c1, ginv3,
+                                  true, fl);
+    if (!ok) {
         redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
         fl = FLAG_QR;
     }
-    finish_pass1(v, v.prm[s], i, c, qr ? nullptr : ginv3, fl, o);
+    finish_pass1(v, v.prm[s], i, c, ok ? ginv3 : nullptr, fl, o);
 }
 
 // ---- pass 2: fit of P and eta, right-hand side, update --------------------
@@ -667,6 +630,7 @@ struct RhsOut {
     double* acc;        // 3 x n (optional in step mode)
     double* dVdt;       // n (optional in step mode)
     double* grad;       // 6 x n optional
+    uint8_t* flags;     // updated with the fallback bit of QR refits
     double* out[7];     // new state (step mode) or nulls
     double dt;
     ErrWord* err;
@@ -727,21 +691,34 @@ __device__ __forceinline__ void finish_rhs(const View& v, const lp_params& p,
     }
 }
 
+// P and eta carried by a row: reals their own, mirrors the pressure of
+// their source's density at zero shear rate and no viscosity, ghosts 0.
 __device__ __forceinline__ void pass2_values(const View& v, const double* P,
-                                             const double* eta, int32_t j,
-                                             const lp_params& p, double& Pj,
+                                             const double* eta, const Pt* p,
+                                             const lp_params& prm, double& Pj,
                                              double& Ej)
 {
-    if (j < 0) {
+    if (!p) {
         Pj = 0.0;
         Ej = 0.0;
-    } else if (j < v.n) {
-        Pj = P[j];
-        Ej = eta[j];
+    } else if (!p->mirror) {
+        Pj = P[p->src];
+        Ej = eta[p->src];
     } else {
-        Pj = mirror_pressure(p, v.mV[j - v.n]);
+        Pj = mirror_pressure(prm, v.V[p->src]);
         Ej = 0.0;
     }
+}
+
+__device__ __forceinline__ void load_hand_tail(const double* hand, int64_t n,
+                                               int64_t i, double eta, double hv[11])
+{
+    hv[0] = eta;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) hv[1 + q] = hand[(int64_t)(27 + q) * n + i];
+    hv[7] = hand[(int64_t)33 * n + i];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) hv[8 + q] = hand[(int64_t)(34 + q) * n + i];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
@@ -755,47 +732,38 @@ __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
     const int64_t n = v.n;
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
-    const lp_params& p = v.prm[s];
-    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const lp_params& prm = v.prm[s];
+    const Rec r = load_rec(v, i);
     const double Pi = P[i], Ei = eta[i];
-    const int m = min(max(v.scnt[i], 0), v.m_max);
-    const uint8_t gm = v.gmask[i];
-    const int mt = m + __popc(gm);
     double yP[9], yE[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) yP[q] = yE[q] = 0.0;
-    for (int k = 0; k < mt; ++k) {
-        double a[9];
-        int32_t j;
-        const double w = fit_row(v, g, i, xi, yi, zi, k, m, gm, a, &j);
+    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
         double Pj, Ej;
-        pass2_values(v, P, eta, j, p, Pj, Ej);
+        pass2_values(v, P, eta, p, prm, Pj, Ej);
         const double bP = w * (Pj - Pi), bE = w * (Ej - Ei);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             yP[q] += a[q] * bP;
             yE[q] += a[q] * bE;
         }
-    }
+    });
     double gP[3], gE[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int rr = 0; rr < 3; ++rr) {
         double sp = 0.0, se = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            const double gi = hand[(int64_t)(r * 9 + q) * n + i];
+            const double gi = hand[(int64_t)(rr * 9 + q) * n + i];
             sp += gi * yP[q];
             se += gi * yE[q];
         }
-        gP[r] = sp * g.inv_h;
-        gE[r] = se * g.inv_h;
+        gP[rr] = sp * g.inv_h;
+        gE[rr] = se * g.inv_h;
     }
     double hv[11];
-    hv[0] = Ei;
-    for (int q = 0; q < 6; ++q) hv[1 + q] = hand[(int64_t)(27 + q) * n + i];
-    hv[7] = hand[(int64_t)33 * n + i];
-    for (int q = 0; q < 3; ++q) hv[8 + q] = hand[(int64_t)(34 + q) * n + i];
-    finish_rhs(v, p, i, hv, gP, gE, o);
+    load_hand_tail(hand, n, i, Ei, hv);
+    finish_rhs(v, prm, i, hv, gP, gE, o);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pass2_qr(View v, const double* P,
@@ -814,25 +782,21 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_qr(View v, const double* P,
         const int64_t i = redo[t];
         const int s = sys_of(v.off, v.n_sys, i);
         const GridInfo& g = v.grid[s];
-        const lp_params& p = v.prm[s];
-        auto get = [&](int32_t j, double* out) {
-            if (j == -2) {
-                out[0] = P[i];
-                out[1] = eta[i];
-            } else {
-                pass2_values(v, P, eta, j, p, out[0], out[1]);
-            }
+        const lp_params& prm = v.prm[s];
+        const Rec r = load_rec(v, i);
+        const double own[2] = {P[i], eta[i]};
+        auto vals = [&](const Pt* p, double* out) {
+            pass2_values(v, P, eta, p, prm, out[0], out[1]);
         };
         double c[18];
-        qr_fit_point(v, g, i, 2, get, scr, c);
+        const uint8_t fl = qr_fit_point(v, g, i, r, 2, own, vals, scr, c);
+        if (o.flags)
+            o.flags[i] = (uint8_t)((o.flags[i] & ~FLAG_LINEAR) | (fl & FLAG_LINEAR) | FLAG_QR);
         const double gP[3] = {c[0], c[1], c[2]};
         const double gE[3] = {c[9], c[10], c[11]};
         double hv[11];
-        hv[0] = eta[i];
-        for (int q = 0; q < 6; ++q) hv[1 + q] = hand[(int64_t)(27 + q) * n + i];
-        hv[7] = hand[(int64_t)33 * n + i];
-        for (int q = 0; q < 3; ++q) hv[8 + q] = hand[(int64_t)(34 + q) * n + i];
-        finish_rhs(v, p, i, hv, gP, gE, o);
+        load_hand_tail(hand, n, i, eta[i], hv);
+        finish_rhs(v, prm, i, hv, gP, gE, o);
     }
 }
 
@@ -902,6 +866,7 @@ static RhsOut rhs_out(lp_ctx* c, double* acc, double* dVdt, double* grad)
     o.acc = acc;
     o.dVdt = dVdt;
     o.grad = grad;
+    o.flags = c->w.flags;
     for (int a = 0; a < 7; ++a) o.out[a] = nullptr;
     o.dt = 0.0;
     o.err = c->w.err;

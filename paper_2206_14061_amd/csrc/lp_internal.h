@@ -15,7 +15,16 @@ constexpr int NCOEF = 9;          // unknowns of the 2nd-order 3D fit
 constexpr int MMAX_LIMIT = 64;    // largest supported stencil cap
 constexpr int MAXROWS = MMAX_LIMIT + 8;
 constexpr int HIST_BUCKETS = 64;  // r^2 histogram of the stencil selection
-constexpr int LIST_CAP = 8;       // threshold-bucket list held per thread
+constexpr int LIST_CAP = 8;       // cut sub-bucket entries held per thread
+constexpr int VCAP = 192;         // neighbour-list entries per particle
+constexpr int32_t MBIT = 0x40000000;  // list entry: mirror of the real id
+constexpr int32_t NOID = 0x7FFFFFFF;
+// per-particle stencil record (int32 fields, field f of particle i at
+// f*n + i): kept rows, ghost mask, mode, cut bucket, cut sub-bucket,
+// octant-first ids (8), kept ids of the cut sub-bucket (8)
+constexpr int REC_M = 0, REC_GM = 1, REC_MODE = 2, REC_B = 3, REC_S = 4,
+              REC_FIRST = 5, REC_CUT = 13, REC_FIELDS = 21;
+constexpr int MODE_ALL = 1, MODE_PARTIAL = 2, MODE_PARTIAL2 = 4, MODE_SORTED = 8;
 constexpr int HARD_CAP = 256;     // candidates the sorted stencil path holds
 constexpr int HARD_SLOTS = 16384; // concurrent sorted-path threads
 constexpr int QR_SLOTS = 16384;   // concurrent QR-refit threads
@@ -36,6 +45,8 @@ constexpr int ERR_NUMERIC = 2;
 struct GridInfo {
     double x0, y0, z0, inv_c;   // origin, 1 / cell edge
     double R2, h, inv_h, R, wall;
+    double Rv, Rv2;             // list radius R (1 + skin) and its square
+    double inv_skin2;           // 1 / (skin R)^2 (0 when skin = 0)
     int64_t cell_base;          // first cell of this system in the tables
     int64_t pbeg, pend;         // particle range
     int32_t nx, ny, nz, pad;
@@ -47,6 +58,7 @@ struct Summary {
     int64_t n_mirror;
     int32_t axis_bits;
     int32_t bad;                // a cell coordinate needs more than 16 bits
+    unsigned long long disp;    // ordered encoding of max (displacement/skin)^2
 };
 
 // Device error word.
@@ -72,21 +84,17 @@ struct View {
     const int64_t* off;         // system offsets (device)
     const lp_params* prm;
     const GridInfo* grid;
-    // real particles in cell order
+    // real particles in cell order (current positions)
     const double *x, *y, *z, *u, *v, *w, *V;
-    // mirrors by id n + k
-    const double *mx, *my, *mz, *mu, *mv, *mw, *mV;
+    // mirrors: mirror_of[j] = k (mirror id n + k) or -1; msrc[k] = j
+    const int32_t* mirror_of;
     const int32_t* msrc;
-    // mirrors in cell order (coordinates and ids)
-    const double *msx, *msy, *msz;
-    const int32_t* msid;
-    const int64_t* n_mirror;    // device count
-    // cell tables
-    const int32_t *cs, *ce, *mcs, *mce;
-    // stencils
-    int32_t* sten;              // m_max x n (ELL, column k at k*n)
-    int32_t* scnt;              // n
-    uint8_t* gmask;             // n
+    // neighbour list with skin (ELL, entry k of particle i at k*n + i)
+    const int32_t* vl;
+    const int32_t* vcnt;
+    // stencil records and explicit stencils of the sorted path
+    int32_t* rec;
+    int32_t* hsten;             // m_max x n
     double ghost_margin;
     double fallback_tol;
     double redo_ratio;          // Gram pivot ratio that triggers a QR refit
@@ -102,7 +110,6 @@ struct Work {
     lp_params* prm = nullptr;
     GridInfo* grid = nullptr;
     unsigned long long* bbox = nullptr;   // n_sys x 6 ordered encodings
-    unsigned long long* mcount = nullptr; // mirror count (bbox pass)
     Summary* summary = nullptr;
     Summary* h_summary = nullptr;         // pinned host copy
     ErrWord* err = nullptr;
@@ -112,22 +119,20 @@ struct Work {
     int32_t *vals0 = nullptr, *vals1 = nullptr;
     uint32_t* hist = nullptr;
     int64_t hist_cap = 0;
-    // sorted real state (lp_step works on this copy)
+    // working copy of the state (cell order)
     double* sst[7] = {nullptr};
-    // mirrors by id, then in cell order
-    double* mst[7] = {nullptr};
+    double* xref[3] = {nullptr};          // positions at the last list build
+    // mirrors
+    int32_t* mirror_of = nullptr;
     int32_t* msrc = nullptr;
-    double *msx = nullptr, *msy = nullptr, *msz = nullptr;
-    int32_t* msid = nullptr;
-    int64_t* n_mirror = nullptr;
-    int32_t* scan = nullptr;              // mirror slot per particle
     int32_t* bsum = nullptr;              // scan block sums
     // cell tables
-    int32_t *cs = nullptr, *ce = nullptr, *mcs = nullptr, *mce = nullptr;
-    // stencils
-    int32_t* sten = nullptr;
-    int32_t* scnt = nullptr;
-    uint8_t* gmask = nullptr;
+    int32_t *cs = nullptr, *ce = nullptr;
+    // neighbour list, records, sorted-path stencils
+    int32_t* vl = nullptr;
+    int32_t* vcnt = nullptr;
+    int32_t* rec = nullptr;
+    int32_t* hsten = nullptr;
     int32_t* hard = nullptr;
     unsigned int* hard_n = nullptr;
     double* hard_r2 = nullptr;            // HARD_SLOTS x HARD_CAP
@@ -159,6 +164,8 @@ struct lp_ctx {
     int axis_bits = 0;
     int64_t total_cells = 0;
     int64_t n_mirror = 0;
+    bool list_ok = false;       // neighbour list valid for the working state
+    int64_t rebuilds = 0;       // list rebuilds since the last lp_stats
     // phase timing (lp_profile)
     bool prof = false;
     hipEvent_t ev[16] = {nullptr};
@@ -212,15 +219,36 @@ __device__ __forceinline__ uint64_t morton3(uint32_t cx, uint32_t cy, uint32_t c
     return spread3_64(cx) | (spread3_64(cy) << 1) | (spread3_64(cz) << 2);
 }
 
-// Exact float64 operations that the compiler must not contract.
-__device__ __forceinline__ double dsub(double a, double b) { return __dsub_rn(a, b); }
-__device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
-__device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
+// Exact float64 operations: the integer decisions of the method (cell
+// coordinates, candidate test, ordering keys) must round exactly as the
+// plain float64 definition does, so these helpers forbid fused
+// multiply-add contraction.
+__device__ __forceinline__ double dsub(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a - b;
+}
+__device__ __forceinline__ double dmul(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ double dadd(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a + b;
+}
 
-// r^2 exactly as the method defines it: (dx*dx + dy*dy) + dz*dz.
+// r^2 exactly as the method defines it: (dx*dx + dy*dy) + dz*dz, each
+// product and sum rounded separately.
 __device__ __forceinline__ double dist2(double dx, double dy, double dz)
 {
-    return dadd(dadd(dmul(dx, dx), dmul(dy, dy)), dmul(dz, dz));
+#pragma clang fp contract(off)
+    const double xx = dx * dx;
+    const double yy = dy * dy;
+    const double zz = dz * dz;
+    const double s = xx + yy;
+    return s + zz;
 }
 
 __device__ __forceinline__ void raise_error(ErrWord* e, int code, int64_t idx)
@@ -233,13 +261,24 @@ __device__ __forceinline__ void raise_error(ErrWord* e, int code, int64_t idx)
 
 // ---- host-side launchers (defined in the .hip files) -----------------
 namespace lp {
-lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out,
-                      bool write_back, double* const out[7]);
+// Morton sort of the input into the working copy, cell tables, neighbour
+// list with skin and reference positions.
+lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out);
+// Copies the input into the working copy in the same order (no rebuild).
+lp_status state_copy(lp_ctx* c, double* const st[7], int32_t* perm_out);
+// Copies the working copy back into the caller's arrays.
+lp_status state_write_back(lp_ctx* c, double* const out[7]);
+// Largest displacement since the list build in units of the skin
+// (synchronises); returns a negative value when no list exists.
+lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio);
+// Mirror ids of the current state, stencil records.
 lp_status stencils_build(lp_ctx* c, const double* const st[7]);
 lp_status stencils_export(lp_ctx* c, const double* const st[7],
                           int64_t* cand_off, int32_t* cand_idx, int64_t cap,
                           int64_t* needed, int32_t* sten_cnt,
-                          int32_t* sten_idx, uint8_t* ghost_mask);
+                          int32_t* sten_idx, uint8_t* ghost_mask,
+                          int64_t* n_mirror);
+lp_status list_build(lp_ctx* c);
 lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
                       int k, const int32_t* msign, const int32_t* gzero,
                       double* coef, uint8_t* flags);

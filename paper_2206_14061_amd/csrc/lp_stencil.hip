@@ -1,21 +1,31 @@
-// Neighbour search, stencil selection and ghost masks (Sec. 3.1 steps 5-6
-// and the free-boundary ghosts of step 9).
+// Neighbour list, mirrors, stencil selection and ghost masks (Sec. 3.1
+// steps 5-6 and the solid-wall mirrors and free-boundary ghosts of step 9).
 //
-// One thread per real particle scans the 27 cells around its own (real and
-// mirror tables).  The exact stencil (nearest candidate of each octant,
-// then the nearest others by key (r^2, id), m_max in all) is found without
-// storing or sorting the candidate list:
-//   pass A: count candidates, keep the nearest per octant, OR the octant
-//           coverage bits, and histogram r^2 into 64 buckets of R^2/64
-//           (byte counters in LDS);
-//   the bucket holding the cut follows from the histogram;
-//   pass B: rescan; emit octant-firsts and every candidate below the cut
-//           bucket; candidates inside the cut bucket go to a per-thread
-//           LDS list that is resolved exactly by key at the end.
-// Bucketing is monotone in r^2, so the selected set equals the one a full
-// sort by (r^2, id) gives.  Particles whose cut bucket overflows the list
-// go to a slower path that collects and sorts all candidates.
-#include "lp_internal.h"
+// Neighbour list with skin: at a rebuild each particle records every real
+// particle within R (1 + skin) and every potential mirror source (a real
+// within R (1 + skin) of the wall whose reflection lies within R (1 + skin)).
+// Until some particle has moved more than skin R / 2, the list contains
+// every pair that can be closer than R, so every pass below applies the
+// exact candidate test r2 = (dx*dx + dy*dy) + dz*dz < R*R to the list and
+// obtains exactly the candidates a full search would.
+//
+// Stencil selection (nearest candidate of each octant, then the nearest
+// others by key (r^2, id), m_max in all), one thread per particle, without
+// storing or sorting the candidates:
+//   pass 1: count, octant coverage bits, nearest candidate per octant and
+//           a histogram of r^2 in 64 buckets of R^2/64 (byte counters in
+//           LDS); the bucket holding the cut follows from it;
+//   pass 2: when the cut falls inside that bucket, its members are split
+//           into 64 sub-buckets;
+//   pass 3: when the cut falls inside that sub-bucket, its few members are
+//           ranked exactly by key in a per-thread LDS list.
+// The result is a small record per particle (cut bucket and sub-bucket,
+// octant-first ids, kept ids of the cut sub-bucket); the fits re-apply it
+// while streaming the list.  Bucketing is monotone in r^2, so the kept set
+// equals the one a full sort by (r^2, id) gives.  Particles whose cut
+// sub-bucket holds more entries than the list, or with more than 255
+// candidates, take a slower path that sorts all candidates.
+#include "lp_visit.h"
 
 namespace lp {
 
@@ -26,78 +36,248 @@ inline unsigned int blocks_for(int64_t n, int per = BLOCK)
     return (unsigned int)((n + per - 1) / per);
 }
 
-struct Cand {
-    double r2;
-    int32_t id;
-    int32_t oct;       // [dx>=0] + 2[dy>=0] + 4[dz>=0]
-    int32_t cover;     // covered octant bit (0 if none)
-};
-
-__device__ __forceinline__ bool key_less(double ra, int32_t ia, double rb,
-                                         int32_t ib)
+__device__ __forceinline__ int cover_bit(double dx, double dy, double dz,
+                                         double margin)
 {
-    return ra < rb || (ra == rb && ia < ib);
+    const bool far = fabs(dx) > margin && fabs(dy) > margin && fabs(dz) > margin;
+    return far ? 1 << ((dx > 0.0 ? 1 : 0) + (dy > 0.0 ? 2 : 0) + (dz > 0.0 ? 4 : 0)) : 0;
 }
 
-// Visits every candidate of real i; f(Cand) is called in a fixed order.
-template <class F>
-__device__ __forceinline__ void for_candidates(const View& v, const GridInfo& g,
-                                               int64_t i, double margin, F&& f)
+__device__ __forceinline__ void cell_clamp(const GridInfo& g, double x, double y,
+                                           double z, int& cx, int& cy, int& cz)
 {
-    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
-    int ix = (int)dmul(dsub(xi, g.x0), g.inv_c);
-    int iy = (int)dmul(dsub(yi, g.y0), g.inv_c);
-    int iz = (int)dmul(dsub(zi, g.z0), g.inv_c);
-    ix = ix < 0 ? 0 : (ix >= g.nx ? g.nx - 1 : ix);
-    iy = iy < 0 ? 0 : (iy >= g.ny ? g.ny - 1 : iy);
-    iz = iz < 0 ? 0 : (iz >= g.nz ? g.nz - 1 : iz);
-    const double R2 = g.R2;
-    auto test = [&](double xj, double yj, double zj, int32_t id) {
-        const double dx = dsub(xj, xi), dy = dsub(yj, yi), dz = dsub(zj, zi);
-        const double r2 = dist2(dx, dy, dz);
-        if (r2 < R2 && id != (int32_t)i) {
-            Cand c;
-            c.r2 = r2;
-            c.id = id;
-            c.oct = (dx >= 0.0 ? 1 : 0) + (dy >= 0.0 ? 2 : 0) + (dz >= 0.0 ? 4 : 0);
-            const bool far = fabs(dx) > margin && fabs(dy) > margin && fabs(dz) > margin;
-            c.cover = far ? (1 << ((dx > 0.0 ? 1 : 0) + (dy > 0.0 ? 2 : 0) +
-                                   (dz > 0.0 ? 4 : 0)))
-                          : 0;
-            f(c);
+    const int ix = (int)dmul(dsub(x, g.x0), g.inv_c);
+    const int iy = (int)dmul(dsub(y, g.y0), g.inv_c);
+    const int iz = (int)dmul(dsub(z, g.z0), g.inv_c);
+    cx = ix < 0 ? 0 : (ix >= g.nx ? g.nx - 1 : ix);
+    cy = iy < 0 ? 0 : (iy >= g.ny ? g.ny - 1 : iy);
+    cz = iz < 0 ? 0 : (iz >= g.nz ? g.nz - 1 : iz);
+}
+
+// ---- neighbour-list build ---------------------------------------------
+
+__global__ __launch_bounds__(BLOCK) void k_list_build(
+    int64_t n, int n_sys, const int64_t* __restrict__ off,
+    const GridInfo* __restrict__ grid, const double* __restrict__ x,
+    const double* __restrict__ y, const double* __restrict__ z,
+    const int32_t* __restrict__ cs, const int32_t* __restrict__ ce,
+    int32_t* __restrict__ vl, int32_t* __restrict__ vcnt, ErrWord* err)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const GridInfo& g = grid[sys_of(off, n_sys, i)];
+    const double Rv2 = g.Rv2 * (1.0 + 1e-12);
+    const double xi = x[i], yi = y[i], zi = z[i];
+    int cnt = 0;
+    auto scan = [&](double qx, double qy, double qz, bool mirror) {
+        int cx, cy, cz;
+        cell_clamp(g, qx, qy, qz, cx, cy, cz);
+        for (int zz = cz - 1; zz <= cz + 1; ++zz) {
+            if (zz < 0 || zz >= g.nz) continue;
+            for (int yy = cy - 1; yy <= cy + 1; ++yy) {
+                if (yy < 0 || yy >= g.ny) continue;
+                const int64_t row = g.cell_base + (int64_t)g.nx * (yy + (int64_t)g.ny * zz);
+                const int x0 = cx > 0 ? cx - 1 : 0;
+                const int x1 = cx + 1 < g.nx ? cx + 1 : g.nx - 1;
+                for (int xx = x0; xx <= x1; ++xx) {
+                    const int64_t c = row + xx;
+                    for (int32_t j = cs[c]; j < ce[c]; ++j) {
+                        if (!mirror && j == (int32_t)i) continue;
+                        const double dx = x[j] - qx, dy = y[j] - qy, dz = z[j] - qz;
+                        if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
+                        if (mirror && !(z[j] - g.wall < g.Rv)) continue;
+                        if (cnt < VCAP)
+                            vl[(int64_t)cnt * n + i] = mirror ? (j | MBIT) : j;
+                        ++cnt;
+                    }
+                }
+            }
         }
     };
-    for (int z = iz - 1; z <= iz + 1; ++z) {
-        if (z < 0 || z >= g.nz) continue;
-        for (int y = iy - 1; y <= iy + 1; ++y) {
-            if (y < 0 || y >= g.ny) continue;
-            const int64_t row = g.cell_base + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-            const int x0 = ix > 0 ? ix - 1 : 0;
-            const int x1 = ix + 1 < g.nx ? ix + 1 : g.nx - 1;
-            // the cells of a row are contiguous in the tables; real
-            // particles of consecutive cells of a row are not (Z order),
-            // so each cell is visited separately
-            for (int x = x0; x <= x1; ++x) {
-                const int64_t c = row + x;
-                const int32_t a = v.cs[c], b = v.ce[c];
-                for (int32_t j = a; j < b; ++j) test(v.x[j], v.y[j], v.z[j], j);
-                const int32_t ma = v.mcs[c], mb = v.mce[c];
-                for (int32_t q = ma; q < mb; ++q)
-                    test(v.msx[q], v.msy[q], v.msz[q], v.msid[q]);
-            }
+    scan(xi, yi, zi, false);
+    // potential mirrors: reals near the wall whose reflection is near i,
+    // i.e. reals near the reflection of i (reflection is an isometry)
+    if (zi - g.wall < g.Rv) scan(xi, yi, dsub(dmul(2.0, g.wall), zi), true);
+    if (cnt > VCAP) {
+        raise_error(err, ERR_CAPACITY, i);
+        cnt = VCAP;
+    }
+    vcnt[i] = cnt;
+}
+
+// ---- mirrors of the current state --------------------------------------
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum,
+                                                    uint32_t& total)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(inc, d);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) {
+        if (w < wave) pre += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    total = tot;
+    return pre + inc - v;
+}
+
+__device__ __forceinline__ bool wall_flag(const int64_t* off, int n_sys,
+                                          const GridInfo* grid, const double* z,
+                                          int64_t i)
+{
+    const GridInfo& g = grid[sys_of(off, n_sys, i)];
+    return dsub(z[i], g.wall) < g.R;
+}
+
+__global__ void k_mirror_count(int64_t n, int n_sys, const int64_t* off,
+                               const GridInfo* grid, const double* z,
+                               int32_t* bsum)
+{
+    __shared__ uint32_t wsum[BLOCK / 64];
+    const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
+    uint32_t c = 0;
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = b + r;
+        if (i < n && wall_flag(off, n_sys, grid, z, i)) ++c;
+    }
+    uint32_t tot;
+    block_excl_scan(c, wsum, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (int32_t)tot;
+}
+
+// Exclusive scan in place of a uint32 array (single block of 1024); the
+// total goes to *total.
+__global__ void k_scan_total(uint32_t* a, int64_t cnt, int64_t* total)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (cnt + 1023) / 1024;
+    const int64_t b = t * chunk;
+    const int64_t e = (b + chunk < cnt) ? b + chunk : cnt;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += a[i];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        uint32_t v = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (t == 1023) *total = (int64_t)part[1023];
+}
+
+__global__ void k_mirror_write(int64_t n, int n_sys, const int64_t* off,
+                               const GridInfo* grid, const int32_t* bsum,
+                               const double* z, int32_t* mirror_of,
+                               int32_t* msrc)
+{
+    __shared__ uint32_t wsum[BLOCK / 64];
+    const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
+    uint32_t c = 0;
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = b + r;
+        if (i < n && wall_flag(off, n_sys, grid, z, i)) ++c;
+    }
+    uint32_t tot;
+    uint32_t k = block_excl_scan(c, wsum, tot) + (uint32_t)bsum[blockIdx.x];
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = b + r;
+        if (i >= n) break;
+        if (wall_flag(off, n_sys, grid, z, i)) {
+            mirror_of[i] = (int32_t)k;
+            msrc[k] = (int32_t)i;
+            ++k;
+        } else {
+            mirror_of[i] = -1;
         }
     }
 }
 
-__device__ __forceinline__ int bucket_of(double r2, double scale)
+// ---- stencil selection ---------------------------------------------------
+
+__device__ __forceinline__ int hist_get(const uint32_t (*hist)[BLOCK], int b, int t)
 {
-    const int b = (int)dmul(r2, scale);
-    return b > HIST_BUCKETS - 1 ? HIST_BUCKETS - 1 : b;
+    return (int)((hist[b >> 2][t] >> (8 * (b & 3))) & 255u);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_stencil(View v, int32_t* hard,
-                                                   unsigned int* hard_n,
-                                                   int force_sorted)
+__device__ __forceinline__ void hist_add(uint32_t (*hist)[BLOCK], int b, int t,
+                                         int d)
+{
+    hist[b >> 2][t] += (uint32_t)d << (8 * (b & 3));
+}
+
+// First bucket whose cumulative count reaches K; need = how many of its
+// members are kept, hc = its count.
+__device__ __forceinline__ int cut_bucket(const uint32_t (*hist)[BLOCK], int t,
+                                          int K, int& need, int& hc)
+{
+    int cum = 0;
+    for (int b = 0; b < HIST_BUCKETS; ++b) {
+        hc = hist_get(hist, b, t);
+        if (cum + hc >= K) {
+            need = K - cum;
+            return b;
+        }
+        cum += hc;
+    }
+    need = 0;
+    hc = 0;
+    return HIST_BUCKETS;
+}
+
+__device__ __forceinline__ void write_rec(const View& v, int64_t i, int m, int gm,
+                                          int mode, int b, int s,
+                                          const int32_t* first,
+                                          const int32_t* cut)
+{
+    const int64_t n = v.n;
+    int32_t* q = v.rec;
+    q[REC_M * n + i] = m;
+    q[REC_GM * n + i] = gm;
+    q[REC_MODE * n + i] = mode;
+    q[REC_B * n + i] = b;
+    q[REC_S * n + i] = s;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) q[(REC_FIRST + o) * n + i] = first[o];
+#pragma unroll
+    for (int o = 0; o < LIST_CAP; ++o) q[(REC_CUT + o) * n + i] = cut[o];
+}
+
+// Calls f(pt, dx, dy, dz, r2) for every candidate of particle i.
+template <class F>
+__device__ __forceinline__ void for_candidates(const View& v, const GridInfo& g,
+                                               int64_t i, F&& f)
+{
+    const int64_t n = v.n;
+    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const double R2 = g.R2;
+    const int cnt = v.vcnt[i];
+    for (int k = 0; k < cnt; ++k) {
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        if (!p.valid) continue;
+        const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
+        const double r2 = dist2(dx, dy, dz);
+        if (r2 < R2) f(p, dx, dy, dz, r2);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
+                                                  unsigned int* hard_n,
+                                                  int force_sorted)
 {
     __shared__ uint32_t hist[HIST_BUCKETS / 4][BLOCK];
     __shared__ double lr2[LIST_CAP][BLOCK];
@@ -105,143 +285,120 @@ __global__ __launch_bounds__(BLOCK) void k_stencil(View v, int32_t* hard,
     const int t = threadIdx.x;
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + t;
     if (i >= v.n) return;
-    const int s = sys_of(v.off, v.n_sys, i);
-    const GridInfo& g = v.grid[s];
+    const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
     const double margin = dmul(v.ghost_margin, g.h);
     const double scale = (double)HIST_BUCKETS / g.R2;
+#pragma unroll
     for (int q = 0; q < HIST_BUCKETS / 4; ++q) hist[q][t] = 0u;
 
-    // ---- pass A
+    // ---- pass 1
     int nc = 0, covered = 0;
-    double br2[8];
-    int32_t bid[8];
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        br2[o] = INFINITY;
-        bid[o] = 0x7FFFFFFF;
-    }
-    for_candidates(v, g, i, margin, [&](const Cand& c) {
+    double br0 = INFINITY, br1 = INFINITY, br2_ = INFINITY, br3 = INFINITY,
+           br4 = INFINITY, br5 = INFINITY, br6 = INFINITY, br7 = INFINITY;
+    int32_t bi0 = NOID, bi1 = NOID, bi2 = NOID, bi3 = NOID, bi4 = NOID, bi5 = NOID,
+            bi6 = NOID, bi7 = NOID;
+    for_candidates(v, g, i, [&](const Pt& p, double dx, double dy, double dz,
+                                double r2) {
         ++nc;
-        covered |= c.cover;
-        double cr = br2[0];
-        int32_t ci = bid[0];
-#pragma unroll
-        for (int o = 1; o < 8; ++o)
-            if (c.oct == o) {
-                cr = br2[o];
-                ci = bid[o];
-            }
-        if (key_less(c.r2, c.id, cr, ci)) {
-#pragma unroll
-            for (int o = 0; o < 8; ++o)
-                if (c.oct == o) {
-                    br2[o] = c.r2;
-                    bid[o] = c.id;
-                }
-        }
-        const int b = bucket_of(c.r2, scale);
-        hist[b >> 2][t] += 1u << (8 * (b & 3));
+        covered |= cover_bit(dx, dy, dz, margin);
+        const int oct = octant_of(dx, dy, dz);
+        const int32_t id = p.id;
+#define LP_UPD(o, BR, BI)                                                  \
+    if (oct == o && key_less(r2, id, BR, BI)) {                            \
+        BR = r2;                                                           \
+        BI = id;                                                           \
+    }
+        LP_UPD(0, br0, bi0) LP_UPD(1, br1, bi1) LP_UPD(2, br2_, bi2)
+        LP_UPD(3, br3, bi3) LP_UPD(4, br4, bi4) LP_UPD(5, br5, bi5)
+        LP_UPD(6, br6, bi6) LP_UPD(7, br7, bi7)
+#undef LP_UPD
+        hist_add(hist, bucket_of(r2, scale), t, 1);
     });
+    const int gm = ~covered & 0xFF;
     const int m_max = v.m_max;
-    v.gmask[i] = (uint8_t)(~covered & 0xFF);
-    const bool keep_all = nc <= m_max;
-    int bstar = HIST_BUCKETS, need = 0;
-    bool partial = false;
-    if (!keep_all) {
-        int n_oct = 0;
+    const int32_t first[8] = {bi0, bi1, bi2, bi3, bi4, bi5, bi6, bi7};
+    const double brs[8] = {br0, br1, br2_, br3, br4, br5, br6, br7};
+    int32_t cut[8];
 #pragma unroll
-        for (int o = 0; o < 8; ++o)
-            if (bid[o] != 0x7FFFFFFF) {
-                ++n_oct;
-                const int b = bucket_of(br2[o], scale);
-                hist[b >> 2][t] -= 1u << (8 * (b & 3));
-            }
-        const int K = m_max - n_oct;
-        if (K < 0 || nc > 255) {
-            // more octant-firsts than the cap, or byte counters could wrap
-            v.scnt[i] = -1;
-            const unsigned int slot = atomicAdd(hard_n, 1u);
-            hard[slot] = (int32_t)i;
-            return;
-        }
-        int cum = 0, hc = 0;
-        for (int b = 0; b < HIST_BUCKETS; ++b) {
-            hc = (int)((hist[b >> 2][t] >> (8 * (b & 3))) & 255u);
-            if (cum + hc >= K) {
-                bstar = b;
-                need = K - cum;
-                break;
-            }
-            cum += hc;
-        }
-        partial = need < hc;
-        if (force_sorted || (partial && hc > LIST_CAP)) {
-            v.scnt[i] = -1;
-            const unsigned int slot = atomicAdd(hard_n, 1u);
-            hard[slot] = (int32_t)i;
-            return;
-        }
-    } else if (force_sorted) {
-        v.scnt[i] = -1;
-        const unsigned int slot = atomicAdd(hard_n, 1u);
-        hard[slot] = (int32_t)i;
+    for (int o = 0; o < 8; ++o) cut[o] = -1;
+    if (force_sorted || nc > 255) {
+        write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, first, cut);
+        hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
         return;
     }
-
-    // ---- pass B
-    int k = 0, nl = 0;
-    const int64_t n = v.n;
-    int32_t* sten = v.sten;
-    for_candidates(v, g, i, margin, [&](const Cand& c) {
-        bool emit;
-        if (keep_all) {
-            emit = true;
-        } else {
-            int32_t first = bid[0];
+    if (nc <= m_max) {
+        write_rec(v, i, nc, gm, MODE_ALL, 0, 0, first, cut);
+        return;
+    }
+    int n_oct = 0;
 #pragma unroll
-            for (int o = 1; o < 8; ++o)
-                if (c.oct == o) first = bid[o];
-            const int b = bucket_of(c.r2, scale);
-            if (c.id == first || b < bstar) {
-                emit = true;
-            } else if (b == bstar) {
-                if (partial) {
-                    if (nl < LIST_CAP) {
-                        lr2[nl][t] = c.r2;
-                        lid[nl][t] = c.id;
-                        ++nl;
-                    }
-                    emit = false;
-                } else {
-                    emit = true;
-                }
-            } else {
-                emit = false;
+    for (int o = 0; o < 8; ++o)
+        if (first[o] != NOID) {
+            ++n_oct;
+            hist_add(hist, bucket_of(brs[o], scale), t, -1);
+        }
+    const int K = m_max - n_oct;
+    if (K < 0) {
+        write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, first, cut);
+        hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
+        return;
+    }
+    int need, hc;
+    const int bstar = cut_bucket(hist, t, K, need, hc);
+    int mode = 0, sstar = 0;
+    auto is_first = [&](int32_t id) {
+        bool f = false;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) f = f || (first[o] == id);
+        return f;
+    };
+    if (need < hc) {
+        // ---- pass 2: split the cut bucket
+        mode |= MODE_PARTIAL;
+#pragma unroll
+        for (int q = 0; q < HIST_BUCKETS / 4; ++q) hist[q][t] = 0u;
+        for_candidates(v, g, i, [&](const Pt& p, double, double, double, double r2) {
+            if (bucket_of(r2, scale) != bstar || is_first(p.id)) return;
+            hist_add(hist, sub_of(r2, scale, bstar), t, 1);
+        });
+        int need2, hc2;
+        sstar = cut_bucket(hist, t, need, need2, hc2);
+        if (need2 < hc2) {
+            // ---- pass 3: rank the members of the cut sub-bucket
+            mode |= MODE_PARTIAL2;
+            if (hc2 > LIST_CAP) {
+                write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, first, cut);
+                hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
+                return;
             }
-        }
-        if (emit && k < m_max) {
-            sten[(int64_t)k * n + i] = c.id;
-            ++k;
-        }
-    });
-    if (partial) {
-        // the `need` smallest keys of the cut bucket
-        for (int a = 0; a < nl; ++a) {
-            int rank = 0;
-            for (int b = 0; b < nl; ++b)
-                if (key_less(lr2[b][t], lid[b][t], lr2[a][t], lid[a][t])) ++rank;
-            if (rank < need && k < m_max) {
-                sten[(int64_t)k * n + i] = lid[a][t];
-                ++k;
+            int nl = 0;
+            for_candidates(v, g, i, [&](const Pt& p, double, double, double, double r2) {
+                if (bucket_of(r2, scale) != bstar || is_first(p.id)) return;
+                if (sub_of(r2, scale, bstar) != sstar || nl >= LIST_CAP) return;
+                lr2[nl][t] = r2;
+                lid[nl][t] = p.id;
+                ++nl;
+            });
+            int kc = 0;
+            for (int a = 0; a < nl; ++a) {
+                int rank = 0;
+                for (int b = 0; b < nl; ++b)
+                    if (key_less(lr2[b][t], lid[b][t], lr2[a][t], lid[a][t])) ++rank;
+                if (rank < need2) {
+#pragma unroll
+                    for (int o = 0; o < LIST_CAP; ++o)
+                        if (o == kc) cut[o] = lid[a][t];
+                    ++kc;
+                }
             }
         }
     }
-    v.scnt[i] = k;
+    write_rec(v, i, m_max, gm, mode, bstar, sstar, first, cut);
 }
 
 // Exact path: collect all candidates, sort by key, take octant-firsts then
 // the nearest others (the stencil rule written out directly).
-__global__ __launch_bounds__(BLOCK) void k_stencil_sorted(
+__global__ __launch_bounds__(BLOCK) void k_select_sorted(
     View v, const int32_t* hard, const unsigned int* hard_n, double* sr2,
     int32_t* sid, ErrWord* err, Counters* cnt)
 {
@@ -251,50 +408,47 @@ __global__ __launch_bounds__(BLOCK) void k_stencil_sorted(
     if (slot == 0) atomicAdd(&cnt->hard_stencils, (unsigned long long)total);
     double* r2s = sr2 + slot * HARD_CAP;
     int32_t* ids = sid + slot * HARD_CAP;
+    const int64_t n = v.n;
     for (int64_t tt = slot; tt < (int64_t)total; tt += nthreads) {
         const int64_t i = hard[tt];
-        const int s = sys_of(v.off, v.n_sys, i);
-        const GridInfo& g = v.grid[s];
-        const double margin = dmul(v.ghost_margin, g.h);
-        int nc = 0, covered = 0;
-        for_candidates(v, g, i, margin, [&](const Cand& c) {
-            covered |= c.cover;
+        const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
+        int nc = 0;
+        for_candidates(v, g, i, [&](const Pt& p, double dx, double dy, double dz,
+                                    double r2) {
             if (nc < HARD_CAP) {
-                // insertion by key (ascending)
-                int p = nc;
-                while (p > 0 && key_less(c.r2, c.id, r2s[p - 1], ids[p - 1] & 0x0FFFFFFF)) {
-                    r2s[p] = r2s[p - 1];
-                    ids[p] = ids[p - 1];
-                    --p;
+                int q = nc;
+                while (q > 0 && key_less(r2, p.id, r2s[q - 1], ids[q - 1] & 0x0FFFFFFF)) {
+                    r2s[q] = r2s[q - 1];
+                    ids[q] = ids[q - 1];
+                    --q;
                 }
-                r2s[p] = c.r2;
-                ids[p] = c.id | (c.oct << 28);
+                r2s[q] = r2;
+                ids[q] = p.id | (octant_of(dx, dy, dz) << 28);
             }
             ++nc;
         });
-        v.gmask[i] = (uint8_t)(~covered & 0xFF);
         if (nc > HARD_CAP) {
             raise_error(err, ERR_CAPACITY, i);
-            v.scnt[i] = 0;
+            v.rec[REC_M * n + i] = 0;
             continue;
         }
         int firstpos[8];
         for (int o = 0; o < 8; ++o) firstpos[o] = -1;
-        for (int p = 0; p < nc; ++p) {
-            const int o = (ids[p] >> 28) & 7;
-            if (firstpos[o] < 0) firstpos[o] = p;
+        for (int q = 0; q < nc; ++q) {
+            const int o = (ids[q] >> 28) & 7;
+            if (firstpos[o] < 0) firstpos[o] = q;
         }
         int k = 0;
         const int m_max = v.m_max;
         for (int o = 0; o < 8; ++o)
             if (firstpos[o] >= 0 && k < m_max)
-                v.sten[(int64_t)k++ * v.n + i] = ids[firstpos[o]] & 0x0FFFFFFF;
-        for (int p = 0; p < nc && k < m_max; ++p) {
+                v.hsten[(int64_t)k++ * n + i] = ids[firstpos[o]] & 0x0FFFFFFF;
+        for (int q = 0; q < nc && k < m_max; ++q) {
             bool f = false;
-            for (int o = 0; o < 8; ++o) f = f || (firstpos[o] == p);
-            if (!f) v.sten[(int64_t)k++ * v.n + i] = ids[p] & 0x0FFFFFFF;
+            for (int o = 0; o < 8; ++o) f = f || (firstpos[o] == q);
+            if (!f) v.hsten[(int64_t)k++ * n + i] = ids[q] & 0x0FFFFFFF;
         }
-        v.scnt[i] = k;
+        v.rec[REC_M * n + i] = k;
     }
 }
 
@@ -307,7 +461,7 @@ __global__ void k_count_candidates(View v, int64_t* counts /* n+1, at 1.. */)
     if (i >= v.n) return;
     const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
     int nc = 0;
-    for_candidates(v, g, i, 0.0, [&](const Cand&) { ++nc; });
+    for_candidates(v, g, i, [&](const Pt&, double, double, double, double) { ++nc; });
     counts[i + 1] = nc;
 }
 
@@ -324,9 +478,9 @@ __global__ void k_scan_i64(int64_t* a, int64_t n)
     part[t] = s;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
-        int64_t v = t >= d ? part[t - d] : 0;
+        int64_t vv = t >= d ? part[t - d] : 0;
         __syncthreads();
-        part[t] += v;
+        part[t] += vv;
         __syncthreads();
     }
     int64_t run = part[t] - s;
@@ -343,68 +497,93 @@ __global__ void k_write_candidates(View v, const int64_t* off, int32_t* idx)
     const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
     int32_t* out = idx + off[i];
     int nc = 0;
-    for_candidates(v, g, i, 0.0, [&](const Cand& c) {
-        int p = nc++;
-        while (p > 0 && out[p - 1] > c.id) {
-            out[p] = out[p - 1];
-            --p;
+    for_candidates(v, g, i, [&](const Pt& p, double, double, double, double) {
+        int q = nc++;
+        while (q > 0 && out[q - 1] > p.id) {
+            out[q] = out[q - 1];
+            --q;
         }
-        out[p] = c.id;
+        out[q] = p.id;
     });
 }
 
-__global__ void k_export_stencils(View v, int32_t* cnt_out, int32_t* idx_out)
+__global__ void k_export_stencils(View v, int32_t* cnt_out, int32_t* idx_out,
+                                  uint8_t* gm_out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= v.n) return;
+    const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
+    const Rec r = load_rec(v, i);
     const int mm = v.m_max;
-    const int m = min(max(v.scnt[i], 0), mm);
-    if (cnt_out) cnt_out[i] = v.scnt[i];
-    if (!idx_out) return;
-    int32_t* out = idx_out + i * mm;
-    for (int k = 0; k < m; ++k) {
-        const int32_t id = v.sten[(int64_t)k * v.n + i];
-        int p = k;
-        while (p > 0 && out[p - 1] > id) {
-            out[p] = out[p - 1];
-            --p;
+    if (gm_out) gm_out[i] = (uint8_t)r.gm;
+    int m = 0;
+    int32_t* out = idx_out ? idx_out + i * mm : nullptr;
+    visit_stencil(v, g, i, r, [&](const Pt& p, double, double, double) {
+        if (out && m < mm) {
+            int q = m;
+            while (q > 0 && out[q - 1] > p.id) {
+                out[q] = out[q - 1];
+                --q;
+            }
+            out[q] = p.id;
         }
-        out[p] = id;
-    }
-    for (int k = m; k < mm; ++k) out[k] = -1;
-}
-
-__global__ void k_copy_u8(int64_t n, const uint8_t* a, uint8_t* b)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
+        ++m;
+    });
+    if (out)
+        for (int k = m; k < mm; ++k) out[k] = -1;
+    if (cnt_out) cnt_out[i] = m;
 }
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 }  // namespace
 
+lp_status list_build(lp_ctx* c)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    c->list_ok = false;
+    if (n > 0)
+        hipLaunchKernelGGL(k_list_build, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                           c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
+                           w.sst[2], w.cs, w.ce, w.vl, w.vcnt, w.err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "list build launch");
+    c->list_ok = true;
+    return LP_OK;
+}
+
 lp_status stencils_build(lp_ctx* c, const double* const st[7])
 {
     Work& w = c->w;
     const int64_t n = c->n;
     c->stencils_ok = false;
-    if (!c->cells_ok) {
-        c->err = "lp_build_cells must precede the stencil build";
+    if (!c->list_ok) {
+        c->err = "the neighbour list has not been built";
         return LP_E_STATE;
     }
     View v = make_view(c, st);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.hard_n);
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, w.hard_n);
     if (n > 0) {
-        const int force = (c->cfg.debug_flags & LP_DEBUG_SORTED_STENCIL) ? 1 : 0;
+        // mirrors of the current state (ids n + k in ascending source order)
+        const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
         prof_mark(c, 1, false);
-        hipLaunchKernelGGL(k_stencil, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                           c->stream, v, w.hard, w.hard_n, force);
+        hipLaunchKernelGGL(k_mirror_count, dim3((unsigned)nb), dim3(BLOCK), 0, s, n,
+                           c->n_sys, w.off, w.grid, st[2], w.bsum);
+        hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1024), 0, s,
+                           (uint32_t*)w.bsum, nb, &w.summary->n_mirror);
+        hipLaunchKernelGGL(k_mirror_write, dim3((unsigned)nb), dim3(BLOCK), 0, s, n,
+                           c->n_sys, w.off, w.grid, w.bsum, st[2], w.mirror_of,
+                           w.msrc);
+        const int force = (c->cfg.debug_flags & LP_DEBUG_SORTED_STENCIL) ? 1 : 0;
+        hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v,
+                           w.hard, w.hard_n, force);
         prof_mark(c, 1, true);
         prof_mark(c, 2, false);
-        hipLaunchKernelGGL(k_stencil_sorted, dim3(HARD_SLOTS / BLOCK), dim3(BLOCK),
-                           0, c->stream, v, w.hard, w.hard_n, w.hard_r2, w.hard_id,
-                           w.err, w.cnt);
+        hipLaunchKernelGGL(k_select_sorted, dim3(HARD_SLOTS / BLOCK), dim3(BLOCK), 0,
+                           s, v, w.hard, w.hard_n, w.hard_r2, w.hard_id, w.err,
+                           w.cnt);
         prof_mark(c, 2, true);
     }
     hipError_t e = hipGetLastError();
@@ -416,12 +595,21 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7])
 lp_status stencils_export(lp_ctx* c, const double* const st[7],
                           int64_t* cand_off, int32_t* cand_idx, int64_t cap,
                           int64_t* needed, int32_t* sten_cnt,
-                          int32_t* sten_idx, uint8_t* ghost_mask)
+                          int32_t* sten_idx, uint8_t* ghost_mask,
+                          int64_t* n_mirror)
 {
     Work& w = c->w;
     const int64_t n = c->n;
     View v = make_view(c, st);
     hipStream_t s = c->stream;
+    if (n_mirror) {
+        hipError_t e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary),
+                                      hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(c, e, "mirror count");
+        *n_mirror = w.h_summary->n_mirror;
+        c->n_mirror = *n_mirror;
+    }
     if (cand_off || cand_idx || needed) {
         int64_t* off = cand_off ? cand_off : w.coff;
         hipLaunchKernelGGL(k_count_candidates, dim3(blocks_for(n + 1)), dim3(BLOCK),
@@ -444,12 +632,9 @@ lp_status stencils_export(lp_ctx* c, const double* const st[7],
                                    dim3(BLOCK), 0, s, v, off, cand_idx);
         }
     }
-    if ((sten_cnt || sten_idx) && n > 0)
+    if ((sten_cnt || sten_idx || ghost_mask) && n > 0)
         hipLaunchKernelGGL(k_export_stencils, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                           s, v, sten_cnt, sten_idx);
-    if (ghost_mask && n > 0)
-        hipLaunchKernelGGL(k_copy_u8, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
-                           w.gmask, ghost_mask);
+                           s, v, sten_cnt, sten_idx, ghost_mask);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "export launch");
     return LP_OK;

@@ -47,7 +47,7 @@ def test_struct_layouts_match_header():
     (16 doubles; natural alignment; 7 pointers)."""
     from paper_2206_14061_amd import _lib
     assert ctypes.sizeof(_lib.LPParams) == 16 * 8
-    assert ctypes.sizeof(_lib.LPConfig) == 48
+    assert ctypes.sizeof(_lib.LPConfig) == 56
     assert ctypes.sizeof(_lib.LPState) == 7 * 8
 
 

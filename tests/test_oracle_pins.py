@@ -46,7 +46,7 @@ def test_morton_keys_are_bit_interleaves():
     """Cell keys are the x/y/z bit interleave of the cell coordinates."""
     h = 0.1
     p = lpgen.default_params(h)
-    c = p.R * (1.0 + 2.0 ** -20)
+    c = (p.R * (1.0 + oracle.SKIN_DEFAULT)) * (1.0 + 2.0 ** -20)
     p.wall_z = 0.0 + p.R          # wall - R = 0 = lowest particle cell edge
     cells = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (3, 0, 0),
              (1, 1, 1), (5, 2, 7), (12, 9, 3), (2, 6, 1)]
@@ -146,6 +146,23 @@ def test_cell_list_equals_brute_force(kind):
     assert np.array_equal(a.cand_idx, b.cand_idx)
     assert np.array_equal(a.sten_idx, b.sten_idx)
     assert np.array_equal(a.ghost_mask, b.ghost_mask)
+
+
+def test_candidate_test_rounds_like_the_plain_definition():
+    """Pairs on the cut radius to the last bit: the oracle's candidate test
+    follows r2 = (dx*dx + dy*dy) + dz*dz with every operation rounded (no
+    fused multiply-add), checked against numpy float64 arithmetic."""
+    from rounding_cases import straddle_workload, unfused_r2
+    wl, want = straddle_workload()
+    o = oracle.Oracle(wl.state, wl.offsets, wl.params, brute=True)
+    nb = o.neighbours()
+    for s, inside in enumerate(want):
+        i = 2 * s
+        cand = nb.cand_idx[nb.cand_off[i]:nb.cand_off[i + 1]]
+        assert (i + 1 in cand) == inside
+        d = np.array([wl.state.x[i + 1] - wl.state.x[i], wl.state.y[i + 1] - wl.state.y[i],
+                      wl.state.z[i + 1] - wl.state.z[i]])
+        assert (unfused_r2(*d) < wl.params[s].R * wl.params[s].R) == inside
 
 
 def _keys(st, nb, i, ids):
