@@ -143,7 +143,7 @@ struct Closure {
 
 // c[f*9 + q]: derivative q of velocity component f.
 __device__ __forceinline__ Closure closure(const lp_params& p, double V,
-                                           const double* c)
+                                           const double (&c)[27])
 {
     Closure r;
     const double gxx = c[0], gyy = c[9 + 1], gzz = c[18 + 2];
@@ -185,7 +185,7 @@ __device__ __forceinline__ double mirror_pressure(const lp_params& p, double V)
 }
 
 // Lap u_a / 2 + d_a div u / 6 from the velocity coefficients.
-__device__ __forceinline__ void visc_terms(const double* c, double vis[3])
+__device__ __forceinline__ void visc_terms(const double (&c)[27], double (&vis)[3])
 {
     const double lap0 = c[3] + c[4] + c[5];
     const double lap1 = c[9 + 3] + c[9 + 4] + c[9 + 5];
@@ -201,10 +201,10 @@ __device__ __forceinline__ void visc_terms(const double* c, double vis[3])
 // Handoff layout: [0,27) rows 0-2 of G^-1 (row-major 3x9), [27,33) gd,
 // 33 div, [34,37) viscous terms.
 __device__ __forceinline__ void store_hand(double* hand, int64_t n, int64_t i,
-                                           const double* ginv3, const Closure& r,
-                                           const double vis[3])
+                                           const double (&ginv3)[27], bool has_ginv,
+                                           const Closure& r, const double (&vis)[3])
 {
-    if (ginv3) {
+    if (has_ginv) {
 #pragma unroll
         for (int q = 0; q < 27; ++q) hand[(int64_t)q * n + i] = ginv3[q];
     }
@@ -213,6 +213,23 @@ __device__ __forceinline__ void store_hand(double* hand, int64_t n, int64_t i,
     hand[(int64_t)33 * n + i] = r.div;
 #pragma unroll
     for (int q = 0; q < 3; ++q) hand[(int64_t)(34 + q) * n + i] = vis[q];
+}
+
+// rows 0-2 of G^{-1} from the factor, stored straight into the handoff
+// (one row live at a time)
+template <int N>
+__device__ __forceinline__ void store_ginv_rows(const double (&U)[45], double* hand,
+                                                int64_t n, int64_t i)
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double e[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) e[q] = (q == r) ? 1.0 : 0.0;
+        chol_solve<N>(U, e);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) hand[(int64_t)(r * 9 + q) * n + i] = (q < N) ? e[q] : 0.0;
+    }
 }
 
 // rows 0-2 of G^{-1} from the factor (3 solves with unit vectors)
@@ -286,7 +303,7 @@ __device__ __forceinline__ int for_rows(const View& v, const GridInfo& g,
                                         int64_t i, const Rec& r, F&& f)
 {
     int m = 0;
-    visit_stencil(v, g, i, r, [&](const Pt& p, double dx, double dy, double dz) {
+    visit_stencil(v, g, v.cr2, i, r, [&](const Pt& p, double dx, double dy, double dz) {
         double a[9];
         const double w = point_row(v, g, dx, dy, dz, a);
         f(a, w, &p);
@@ -381,14 +398,86 @@ __device__ __forceinline__ bool gram_solve(double (&G)[45], const double (&B)[NF
     return true;
 }
 
-__device__ __forceinline__ void gram_add(double (&G)[45], const double* a, double w)
+// The Gram matrix of the Taylor rows a = (x, y, z, x^2/2, y^2/2, z^2/2,
+// xy, xz, yz) has 31 distinct entries: the weighted sums of the monomials
+// of degree 2, 3 and 4 in (x, y, z).  They are accumulated row by row
+// (fewer registers and operations than the 45 products) and G is
+// assembled once per particle.
+//   0 xx 1 yy 2 zz 3 xy 4 xz 5 yz
+//   6 xxx 7 yyy 8 zzz 9 xxy 10 xxz 11 xyy 12 yyz 13 xzz 14 yzz 15 xyz
+//   16 xxxx 17 yyyy 18 zzzz 19 xxyy 20 xxzz 21 yyzz 22 xxxy 23 xxxz
+//   24 xyyy 25 yyyz 26 xzzz 27 yzzz 28 xxyz 29 xyyz 30 xyzz
+__device__ __forceinline__ void moments_add(double (&M)[31], const double* a,
+                                            double w)
 {
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-        const double wa = w * a[p];
-#pragma unroll
-        for (int q = p; q < 9; ++q) G[uix(p, q)] += wa * a[q];
-    }
+    const double x = a[0], y = a[1], z = a[2];
+    const double xx = x * x, yy = y * y, zz = z * z;
+    const double xy = a[6], xz = a[7], yz = a[8];
+    const double wxx = w * xx, wyy = w * yy, wzz = w * zz, wxy = w * xy;
+    M[0] += wxx;
+    M[1] += wyy;
+    M[2] += wzz;
+    M[3] += wxy;
+    M[4] += w * xz;
+    M[5] += w * yz;
+    M[6] += wxx * x;
+    M[7] += wyy * y;
+    M[8] += wzz * z;
+    M[9] += wxx * y;
+    M[10] += wxx * z;
+    M[11] += wyy * x;
+    M[12] += wyy * z;
+    M[13] += wzz * x;
+    M[14] += wzz * y;
+    M[15] += wxy * z;
+    M[16] += wxx * xx;
+    M[17] += wyy * yy;
+    M[18] += wzz * zz;
+    M[19] += wxx * yy;
+    M[20] += wxx * zz;
+    M[21] += wyy * zz;
+    M[22] += wxx * xy;
+    M[23] += wxx * xz;
+    M[24] += wyy * xy;
+    M[25] += wyy * yz;
+    M[26] += wzz * xz;
+    M[27] += wzz * yz;
+    M[28] += wxx * yz;
+    M[29] += wyy * xz;
+    M[30] += wzz * xy;
+}
+
+__device__ __forceinline__ void gram_from_moments(const double (&M)[31],
+                                                  double (&G)[45])
+{
+    // row 0: x
+    G[uix(0, 0)] = M[0];  G[uix(0, 1)] = M[3];  G[uix(0, 2)] = M[4];
+    G[uix(0, 3)] = 0.5 * M[6];  G[uix(0, 4)] = 0.5 * M[11];
+    G[uix(0, 5)] = 0.5 * M[13]; G[uix(0, 6)] = M[9];  G[uix(0, 7)] = M[10];
+    G[uix(0, 8)] = M[15];
+    // row 1: y
+    G[uix(1, 1)] = M[1];  G[uix(1, 2)] = M[5];  G[uix(1, 3)] = 0.5 * M[9];
+    G[uix(1, 4)] = 0.5 * M[7];  G[uix(1, 5)] = 0.5 * M[14];
+    G[uix(1, 6)] = M[11]; G[uix(1, 7)] = M[15]; G[uix(1, 8)] = M[12];
+    // row 2: z
+    G[uix(2, 2)] = M[2];  G[uix(2, 3)] = 0.5 * M[10]; G[uix(2, 4)] = 0.5 * M[12];
+    G[uix(2, 5)] = 0.5 * M[8];  G[uix(2, 6)] = M[15]; G[uix(2, 7)] = M[13];
+    G[uix(2, 8)] = M[14];
+    // row 3: x^2/2
+    G[uix(3, 3)] = 0.25 * M[16]; G[uix(3, 4)] = 0.25 * M[19];
+    G[uix(3, 5)] = 0.25 * M[20]; G[uix(3, 6)] = 0.5 * M[22];
+    G[uix(3, 7)] = 0.5 * M[23];  G[uix(3, 8)] = 0.5 * M[28];
+    // row 4: y^2/2
+    G[uix(4, 4)] = 0.25 * M[17]; G[uix(4, 5)] = 0.25 * M[21];
+    G[uix(4, 6)] = 0.5 * M[24];  G[uix(4, 7)] = 0.5 * M[29];
+    G[uix(4, 8)] = 0.5 * M[25];
+    // row 5: z^2/2
+    G[uix(5, 5)] = 0.25 * M[18]; G[uix(5, 6)] = 0.5 * M[30];
+    G[uix(5, 7)] = 0.5 * M[26];  G[uix(5, 8)] = 0.5 * M[27];
+    // rows 6-8: xy, xz, yz
+    G[uix(6, 6)] = M[19]; G[uix(6, 7)] = M[28]; G[uix(6, 8)] = M[29];
+    G[uix(7, 7)] = M[20]; G[uix(7, 8)] = M[30];
+    G[uix(8, 8)] = M[21];
 }
 
 // ---- lp_fit_derivs -------------------------------------------------------
@@ -415,15 +504,15 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
     double fi[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) fi[f] = F.f[(int64_t)f * n + i];
-    double G[45], B[NF][9];
+    double M[31], B[NF][9];
 #pragma unroll
-    for (int q = 0; q < 45; ++q) G[q] = 0.0;
+    for (int q = 0; q < 31; ++q) M[q] = 0.0;
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int q = 0; q < 9; ++q) B[f][q] = 0.0;
     const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
-        gram_add(G, a, w);
+        moments_add(M, a, w);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             double fj;
@@ -435,7 +524,8 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
             for (int q = 0; q < 9; ++q) B[f][q] += a[q] * b;
         }
     });
-    double c[NF][9], ginv3[27];
+    double G[45], c[NF][9], ginv3[27];
+    gram_from_moments(M, G);
     uint8_t fl;
     if (!gram_solve<NF>(G, B, mt, v.redo_ratio, force_qr != 0, c, ginv3, false, fl)) {
         redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
@@ -494,8 +584,9 @@ struct StepOut {
 };
 
 __device__ __forceinline__ void finish_pass1(const View& v, const lp_params& p,
-                                             int64_t i, const double* c,
-                                             const double* ginv3, uint8_t fl,
+                                             int64_t i, const double (&c)[27],
+                                             const double (&ginv3)[27],
+                                             bool has_ginv, uint8_t fl,
                                              const StepOut& o)
 {
     const int64_t n = v.n;
@@ -504,7 +595,7 @@ __device__ __forceinline__ void finish_pass1(const View& v, const lp_params& p,
     visc_terms(c, vis);
     o.P[i] = r.P;
     o.eta[i] = r.eta;
-    store_hand(o.hand, n, i, ginv3, r, vis);
+    store_hand(o.hand, n, i, ginv3, has_ginv, r, vis);
     o.flags[i] = (uint8_t)(fl | (r.branch << 1));
     if (o.diag) {
         o.diag[i] = r.P;
@@ -519,10 +610,10 @@ __device__ __forceinline__ void finish_pass1(const View& v, const lp_params& p,
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_pass1(View v, StepOut o,
-                                                 int32_t* redo,
-                                                 unsigned int* redo_n,
-                                                 int force_qr)
+__global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
+                                                    int32_t* redo,
+                                                    unsigned int* redo_n,
+                                                    int force_qr)
 {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     if (i >= v.n) return;
@@ -530,13 +621,13 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(View v, StepOut o,
     const GridInfo& g = v.grid[s];
     const Rec r = load_rec(v, i);
     const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
-    double G[45], B[3][9];
+    double M[31], B[3][9];
 #pragma unroll
-    for (int q = 0; q < 45; ++q) G[q] = 0.0;
+    for (int q = 0; q < 31; ++q) M[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) B[0][q] = B[1][q] = B[2][q] = 0.0;
     const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
-        gram_add(G, a, w);
+        moments_add(M, a, w);
         if (!p) return;   // ghosts carry u_i (b = 0)
         double uj, vj, wj;
         point_velocity(v, *p, uj, vj, wj);
@@ -548,9 +639,10 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(View v, StepOut o,
             B[2][q] += a[q] * b2;
         }
     });
-    double c3[3][9], ginv3[27];
+    double G[45], c3[3][9], none[27];
+    gram_from_moments(M, G);
     uint8_t fl;
-    if (!gram_solve<3>(G, B, mt, v.redo_ratio, force_qr != 0, c3, ginv3, true, fl)) {
+    if (!gram_solve<3>(G, B, mt, v.redo_ratio, force_qr != 0, c3, none, false, fl)) {
         redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
         o.flags[i] = FLAG_QR;
         return;
@@ -559,7 +651,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(View v, StepOut o,
 #pragma unroll
     for (int q = 0; q < 27; ++q)
         c[q] = c3[q / 9][q % 9] * ((q % 9) < 3 ? g.inv_h : g.inv_h * g.inv_h);
-    finish_pass1(v, v.prm[s], i, c, ginv3, fl, o);
+    finish_pass1(v, v.prm[s], i, c, none, false, fl, o);
+    if (mt < 9) store_ginv_rows<3>(G, o.hand, v.n, i);
+    else store_ginv_rows<9>(G, o.hand, v.n, i);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pass1_qr(View v, StepOut o,
@@ -585,9 +679,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass1_qr(View v, StepOut o,
                 point_velocity(v, *p, out[0], out[1], out[2]);
             }
         };
-        double c[27];
+        double c[27], none[27];
         const uint8_t fl = qr_fit_point(v, g, i, r, 3, own, vals, scr, c);
-        finish_pass1(v, v.prm[s], i, c, nullptr, fl, o);
+        finish_pass1(v, v.prm[s], i, c, none, false, fl, o);
     }
 }
 
@@ -606,12 +700,13 @@ __global__ __launch_bounds__(BLOCK) void k_closure_coef(View v, const double* co
     double c[27];
 #pragma unroll
     for (int q = 0; q < 27; ++q) c[q] = coef_u[(int64_t)q * n + i];
-    double G[45];
+    double M[31], G[45];
 #pragma unroll
-    for (int q = 0; q < 45; ++q) G[q] = 0.0;
+    for (int q = 0; q < 31; ++q) M[q] = 0.0;
     const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt*) {
-        gram_add(G, a, w);
+        moments_add(M, a, w);
     });
+    gram_from_moments(M, G);
     const double B[1][9] = {{0, 0, 0, 0, 0, 0, 0, 0, 0}};
     double c1[1][9], ginv3[27];
     uint8_t fl;
@@ -621,7 +716,7 @@ __global__ __launch_bounds__(BLOCK) void k_closure_coef(View v, const double* co
         redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
         fl = FLAG_QR;
     }
-    finish_pass1(v, v.prm[s], i, c, ok ? ginv3 : nullptr, fl, o);
+    finish_pass1(v, v.prm[s], i, c, ginv3, ok, fl, o);
 }
 
 // ---- pass 2: fit of P and eta, right-hand side, update --------------------

@@ -21,7 +21,7 @@ constexpr int32_t MBIT = 0x40000000;  // list entry: mirror of the real id
 constexpr int32_t NOID = 0x7FFFFFFF;
 // per-particle stencil record (int32 fields, field f of particle i at
 // f*n + i): kept rows, ghost mask, mode, cut bucket, cut sub-bucket,
-// octant-first ids (8), kept ids of the cut sub-bucket (8)
+// octant-first list indices (8), kept list indices of the cut sub-bucket
 constexpr int REC_M = 0, REC_GM = 1, REC_MODE = 2, REC_B = 3, REC_S = 4,
               REC_FIRST = 5, REC_CUT = 13, REC_FIELDS = 21;
 constexpr int MODE_ALL = 1, MODE_PARTIAL = 2, MODE_PARTIAL2 = 4, MODE_SORTED = 8;
@@ -92,6 +92,7 @@ struct View {
     // neighbour list with skin (ELL, entry k of particle i at k*n + i)
     const int32_t* vl;
     const int32_t* vcnt;
+    double* cr2;                // r^2 of every list entry (+inf: no candidate)
     // stencil records and explicit stencils of the sorted path
     int32_t* rec;
     int32_t* hsten;             // m_max x n
@@ -131,6 +132,7 @@ struct Work {
     // neighbour list, records, sorted-path stencils
     int32_t* vl = nullptr;
     int32_t* vcnt = nullptr;
+    double* cr2 = nullptr;                // VCAP x n
     int32_t* rec = nullptr;
     int32_t* hsten = nullptr;
     int32_t* hard = nullptr;

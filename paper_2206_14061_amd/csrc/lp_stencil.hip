@@ -241,8 +241,8 @@ __device__ __forceinline__ int cut_bucket(const uint32_t (*hist)[BLOCK], int t,
 
 __device__ __forceinline__ void write_rec(const View& v, int64_t i, int m, int gm,
                                           int mode, int b, int s,
-                                          const int32_t* first,
-                                          const int32_t* cut)
+                                          const int32_t (&first)[8],
+                                          const int32_t (&cut)[LIST_CAP])
 {
     const int64_t n = v.n;
     int32_t* q = v.rec;
@@ -275,52 +275,79 @@ __device__ __forceinline__ void for_candidates(const View& v, const GridInfo& g,
     }
 }
 
+// candidate id of list entry e (valid candidate assumed)
+__device__ __forceinline__ int32_t entry_id(const View& v, int32_t e)
+{
+    return (e & MBIT) ? (int32_t)v.n + v.mirror_of[e & ~MBIT] : e;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
                                                   unsigned int* hard_n,
                                                   int force_sorted)
 {
     __shared__ uint32_t hist[HIST_BUCKETS / 4][BLOCK];
     __shared__ double lr2[LIST_CAP][BLOCK];
-    __shared__ int32_t lid[LIST_CAP][BLOCK];
+    __shared__ int32_t lk[LIST_CAP][BLOCK];
     const int t = threadIdx.x;
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + t;
     if (i >= v.n) return;
+    const int64_t n = v.n;
     const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
     const double margin = dmul(v.ghost_margin, g.h);
     const double scale = (double)HIST_BUCKETS / g.R2;
+    const double R2 = g.R2;
+    double* __restrict__ cr2 = v.cr2;
 #pragma unroll
     for (int q = 0; q < HIST_BUCKETS / 4; ++q) hist[q][t] = 0u;
 
-    // ---- pass 1
+    // ---- pass 1: exact test of every list entry; its key is stored
+    // (entry k of all lanes at once: coalesced)
     int nc = 0, covered = 0;
     double br0 = INFINITY, br1 = INFINITY, br2_ = INFINITY, br3 = INFINITY,
            br4 = INFINITY, br5 = INFINITY, br6 = INFINITY, br7 = INFINITY;
     int32_t bi0 = NOID, bi1 = NOID, bi2 = NOID, bi3 = NOID, bi4 = NOID, bi5 = NOID,
             bi6 = NOID, bi7 = NOID;
-    for_candidates(v, g, i, [&](const Pt& p, double dx, double dy, double dz,
-                                double r2) {
-        ++nc;
-        covered |= cover_bit(dx, dy, dz, margin);
-        const int oct = octant_of(dx, dy, dz);
-        const int32_t id = p.id;
-#define LP_UPD(o, BR, BI)                                                  \
-    if (oct == o && key_less(r2, id, BR, BI)) {                            \
-        BR = r2;                                                           \
+    int32_t bk0 = -1, bk1 = -1, bk2 = -1, bk3 = -1, bk4 = -1, bk5 = -1, bk6 = -1,
+            bk7 = -1;
+    {
+        const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+        const int cnt = v.vcnt[i];
+        for (int k = 0; k < cnt; ++k) {
+            const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+            double r2 = INFINITY;
+            if (p.valid) {
+                const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
+                const double d2 = dist2(dx, dy, dz);
+                if (d2 < R2) {
+                    r2 = d2;
+                    ++nc;
+                    covered |= cover_bit(dx, dy, dz, margin);
+                    const int oct = octant_of(dx, dy, dz);
+                    const int32_t id = p.id;
+#define LP_UPD(o, BR, BI, BK)                                              \
+    if (oct == o && key_less(d2, id, BR, BI)) {                            \
+        BR = d2;                                                           \
         BI = id;                                                           \
+        BK = k;                                                            \
     }
-        LP_UPD(0, br0, bi0) LP_UPD(1, br1, bi1) LP_UPD(2, br2_, bi2)
-        LP_UPD(3, br3, bi3) LP_UPD(4, br4, bi4) LP_UPD(5, br5, bi5)
-        LP_UPD(6, br6, bi6) LP_UPD(7, br7, bi7)
+                    LP_UPD(0, br0, bi0, bk0) LP_UPD(1, br1, bi1, bk1)
+                    LP_UPD(2, br2_, bi2, bk2) LP_UPD(3, br3, bi3, bk3)
+                    LP_UPD(4, br4, bi4, bk4) LP_UPD(5, br5, bi5, bk5)
+                    LP_UPD(6, br6, bi6, bk6) LP_UPD(7, br7, bi7, bk7)
 #undef LP_UPD
-        hist_add(hist, bucket_of(r2, scale), t, 1);
-    });
+                    hist_add(hist, bucket_of(d2, scale), t, 1);
+                }
+            }
+            cr2[(int64_t)k * n + i] = r2;
+        }
+    }
     const int gm = ~covered & 0xFF;
     const int m_max = v.m_max;
-    const int32_t first[8] = {bi0, bi1, bi2, bi3, bi4, bi5, bi6, bi7};
+    const int32_t first[8] = {bk0, bk1, bk2, bk3, bk4, bk5, bk6, bk7};
     const double brs[8] = {br0, br1, br2_, br3, br4, br5, br6, br7};
-    int32_t cut[8];
+    int32_t cut[LIST_CAP];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) cut[o] = -1;
+    for (int o = 0; o < LIST_CAP; ++o) cut[o] = -1;
     if (force_sorted || nc > 255) {
         write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, first, cut);
         hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
@@ -333,7 +360,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     int n_oct = 0;
 #pragma unroll
     for (int o = 0; o < 8; ++o)
-        if (first[o] != NOID) {
+        if (first[o] >= 0) {
             ++n_oct;
             hist_add(hist, bucket_of(brs[o], scale), t, -1);
         }
@@ -346,25 +373,27 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     int need, hc;
     const int bstar = cut_bucket(hist, t, K, need, hc);
     int mode = 0, sstar = 0;
-    auto is_first = [&](int32_t id) {
+    const int cnt = v.vcnt[i];
+    auto is_first = [&](int k) {
         bool f = false;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) f = f || (first[o] == id);
+        for (int o = 0; o < 8; ++o) f = f || (first[o] == k);
         return f;
     };
     if (need < hc) {
-        // ---- pass 2: split the cut bucket
+        // ---- pass 2: split the cut bucket (stored keys, no gathers)
         mode |= MODE_PARTIAL;
 #pragma unroll
         for (int q = 0; q < HIST_BUCKETS / 4; ++q) hist[q][t] = 0u;
-        for_candidates(v, g, i, [&](const Pt& p, double, double, double, double r2) {
-            if (bucket_of(r2, scale) != bstar || is_first(p.id)) return;
+        for (int k = 0; k < cnt; ++k) {
+            const double r2 = cr2[(int64_t)k * n + i];
+            if (!(r2 < R2) || bucket_of(r2, scale) != bstar || is_first(k)) continue;
             hist_add(hist, sub_of(r2, scale, bstar), t, 1);
-        });
+        }
         int need2, hc2;
         sstar = cut_bucket(hist, t, need, need2, hc2);
         if (need2 < hc2) {
-            // ---- pass 3: rank the members of the cut sub-bucket
+            // ---- pass 3: rank the members of the cut sub-bucket by key
             mode |= MODE_PARTIAL2;
             if (hc2 > LIST_CAP) {
                 write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, first, cut);
@@ -372,22 +401,26 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
                 return;
             }
             int nl = 0;
-            for_candidates(v, g, i, [&](const Pt& p, double, double, double, double r2) {
-                if (bucket_of(r2, scale) != bstar || is_first(p.id)) return;
-                if (sub_of(r2, scale, bstar) != sstar || nl >= LIST_CAP) return;
+            for (int k = 0; k < cnt && nl < LIST_CAP; ++k) {
+                const double r2 = cr2[(int64_t)k * n + i];
+                if (!(r2 < R2) || bucket_of(r2, scale) != bstar || is_first(k)) continue;
+                if (sub_of(r2, scale, bstar) != sstar) continue;
                 lr2[nl][t] = r2;
-                lid[nl][t] = p.id;
+                lk[nl][t] = k;
                 ++nl;
-            });
+            }
             int kc = 0;
             for (int a = 0; a < nl; ++a) {
+                const int32_t ida = entry_id(v, v.vl[(int64_t)lk[a][t] * n + i]);
                 int rank = 0;
-                for (int b = 0; b < nl; ++b)
-                    if (key_less(lr2[b][t], lid[b][t], lr2[a][t], lid[a][t])) ++rank;
+                for (int b = 0; b < nl; ++b) {
+                    const int32_t idb = entry_id(v, v.vl[(int64_t)lk[b][t] * n + i]);
+                    if (key_less(lr2[b][t], idb, lr2[a][t], ida)) ++rank;
+                }
                 if (rank < need2) {
 #pragma unroll
                     for (int o = 0; o < LIST_CAP; ++o)
-                        if (o == kc) cut[o] = lid[a][t];
+                        if (o == kc) cut[o] = lk[a][t];
                     ++kc;
                 }
             }
@@ -518,7 +551,7 @@ __global__ void k_export_stencils(View v, int32_t* cnt_out, int32_t* idx_out,
     if (gm_out) gm_out[i] = (uint8_t)r.gm;
     int m = 0;
     int32_t* out = idx_out ? idx_out + i * mm : nullptr;
-    visit_stencil(v, g, i, r, [&](const Pt& p, double, double, double) {
+    visit_stencil(v, g, v.cr2, i, r, [&](const Pt& p, double, double, double) {
         if (out && m < mm) {
             int q = m;
             while (q > 0 && out[q - 1] > p.id) {

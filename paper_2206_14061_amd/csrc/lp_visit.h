@@ -93,11 +93,12 @@ __device__ __forceinline__ int sub_of(double r2, double scale, int b)
     return sb < 0 ? 0 : (sb > HIST_BUCKETS - 1 ? HIST_BUCKETS - 1 : sb);
 }
 
-// Stencil record of one particle, in registers.
+// Stencil record of one particle, in registers.  Octant-firsts and the
+// kept members of the cut sub-bucket are list indices (-1 when absent).
 struct Rec {
     int m, gm, mode, b, s;
     int32_t first[8];
-    int32_t cut[8];
+    int32_t cut[LIST_CAP];
 };
 
 __device__ __forceinline__ Rec load_rec(const View& v, int64_t i)
@@ -117,32 +118,34 @@ __device__ __forceinline__ Rec load_rec(const View& v, int64_t i)
     return r;
 }
 
-// Whether a candidate (r2 < R^2) belongs to the stencil.
-__device__ __forceinline__ bool keep_row(const Rec& r, double r2, int oct,
-                                         int32_t id, double scale)
+// Whether list entry k, a candidate with key r2, belongs to the stencil.
+__device__ __forceinline__ bool keep_entry(const Rec& r, int k, double r2,
+                                           double scale)
 {
     if (r.mode & MODE_ALL) return true;
-    int32_t f = r.first[0];
+    bool f = false;
 #pragma unroll
-    for (int o = 1; o < 8; ++o)
-        if (oct == o) f = r.first[o];
-    if (f == id) return true;
+    for (int o = 0; o < 8; ++o) f = f || (r.first[o] == k);
+    if (f) return true;
     const int b = bucket_of(r2, scale);
     if (b != r.b) return b < r.b;
     if (!(r.mode & MODE_PARTIAL)) return true;
     const int sb = sub_of(r2, scale, b);
     if (sb != r.s) return sb < r.s;
     if (!(r.mode & MODE_PARTIAL2)) return true;
-    bool k = false;
+    bool c = false;
 #pragma unroll
-    for (int o = 0; o < LIST_CAP; ++o) k = k || (r.cut[o] == id);
-    return k;
+    for (int o = 0; o < LIST_CAP; ++o) c = c || (r.cut[o] == k);
+    return c;
 }
 
 // Calls f(pt, dx, dy, dz) for every stencil row of real particle i (the
-// ghost rows are not visited: they follow from r.gm).
+// ghost rows are not visited: they follow from r.gm).  cr2 holds the
+// candidate key r^2 of every list entry (+inf for non-candidates), as
+// stored by the selection.
 template <class F>
 __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
+                                              const double* __restrict__ cr2,
                                               int64_t i, const Rec& r, F&& f)
 {
     const int64_t n = v.n;
@@ -158,12 +161,10 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
     const double scale = (double)HIST_BUCKETS / R2;
     const int cnt = v.vcnt[i];
     for (int k = 0; k < cnt; ++k) {
+        const double r2 = cr2[(int64_t)k * n + i];
+        if (!(r2 < R2) || !keep_entry(r, k, r2, scale)) continue;
         const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
-        if (!p.valid) continue;
-        const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
-        const double r2 = dist2(dx, dy, dz);
-        if (!(r2 < R2)) continue;
-        if (keep_row(r, r2, octant_of(dx, dy, dz), p.id, scale)) f(p, dx, dy, dz);
+        f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
     }
 }
 
