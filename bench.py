@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -51,7 +52,58 @@ def _parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three 1 GiB device-to-device copies, the "
+                         "reference for the HBM byte counters")
     return ap.parse_args()
+
+
+# Sources that make up the pass-1 kernel; its committed byte counts hold only
+# while they are unchanged.
+PASS1_SOURCES = ("paper_2206_14061_amd/csrc/lp_fit.hip",
+                 "paper_2206_14061_amd/csrc/lp_visit.h",
+                 "paper_2206_14061_amd/csrc/lp_internal.h",
+                 "paper_2206_14061_amd/build.py")
+PASS1_PROFILE = "profiles/k_pass1_column_64x64x128.md"
+
+
+def sources_digest(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pass1_traffic():
+    """HBM bytes per k_pass1 launch from the committed FETCH_SIZE and
+    WRITE_SIZE counts, each scaled by what the counter reads for a plain
+    copy of known size; None when the kernel's sources have changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, PASS1_PROFILE)
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"^traffic-record: (\{.*\})\s*$", open(path).read(), re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != sources_digest(PASS1_SOURCES):
+        return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"]
+                     + rec["write_kib"] * rec["write_scale"])
+
+
+def copy_calibration(torch):
+    """Three device-to-device copies of 1 GiB: far beyond the L2 and the
+    last-level cache, so each reads and writes exactly 2^30 bytes of HBM."""
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return 8 * n
 
 
 def cpu_baseline(wl, steps: int):
@@ -132,7 +184,7 @@ def main():
     roof = {"kernel": "k_pass1 (fit of u, v, w + mu(I) closure)",
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None, "avg_launch_ms": phases["pass1"],
+            "traffic": pass1_traffic(), "avg_launch_ms": phases["pass1"],
             "executed_tflops": executed,
             "executed_frac": executed / PEAK_FP64_TFLOPS,
             "dominant_phase": dominant}
@@ -149,6 +201,8 @@ def main():
            "roofline": roof}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    if args.copy_calibration:
+        out["copy_calibration_bytes"] = copy_calibration(torch)
     print(json.dumps(out), flush=True)
 
 

@@ -222,7 +222,7 @@ lp_status lp_step_adjoint(lp_ctx* ctx);
 lp_status lp_sync_status(lp_ctx* ctx, int64_t* index);
 
 /* Diagnostics accumulated since the last call (host int64[8]):
- * particles, mirrors (last export), QR refits, sorted-path stencils,
+ * particles, mirrors (last stencil build), QR refits, sorted-path stencils,
  * particles below the wall after updates, neighbour-list rebuilds by
  * lp_step, 0, 0; then resets them.  Synchronises. */
 lp_status lp_stats(lp_ctx* ctx, int64_t* out8);

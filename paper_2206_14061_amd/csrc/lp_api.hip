@@ -37,8 +37,9 @@ View make_view(lp_ctx* c, const double* const st[7])
     v.msrc = w.msrc;
     v.vl = w.vl;
     v.vcnt = w.vcnt;
-    v.cr2 = w.cr2;
+    v.code = w.code;
     v.rec = w.rec;
+    v.kmask = w.kmask;
     v.hsten = w.hsten;
     v.ghost_margin = c->cfg.ghost_margin;
     v.fallback_tol = c->cfg.fallback_tol;
@@ -72,7 +73,7 @@ void free_work(Work& w)
     for (int a = 0; a < 7; ++a) f(w.sst[a]);
     for (int a = 0; a < 3; ++a) f(w.xref[a]);
     f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
-    f(w.vl); f(w.vcnt); f(w.cr2); f(w.rec); f(w.hsten); f(w.hard); f(w.hard_n);
+    f(w.vl); f(w.vcnt); f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
     f(w.hard_r2); f(w.hard_id); f(w.redo); f(w.redo_n); f(w.qr_scratch);
     f(w.P); f(w.eta); f(w.hand); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
@@ -198,7 +199,8 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.mirror_of, n_max); A(w.msrc, n_max); A(w.bsum, nb + 1);
     A(w.cs, cells_max); A(w.ce, cells_max);
     A(w.vl, (int64_t)VCAP * n_max); A(w.vcnt, n_max);
-    A(w.cr2, (int64_t)VCAP * n_max);
+    A(w.code, (int64_t)VCAP * n_max);
+    A(w.kmask, (int64_t)MASK_WORDS * n_max);
     A(w.rec, (int64_t)REC_FIELDS * n_max); A(w.hsten, (int64_t)mm * n_max);
     A(w.hard, n_max); A(w.hard_n, 1);
     A(w.hard_r2, (int64_t)HARD_SLOTS * HARD_CAP);
@@ -463,12 +465,17 @@ lp_status lp_stats(lp_ctx* c, int64_t* out8)
     if (!c || !out8) return LP_E_ARG;
     for (int q = 0; q < 8; ++q) out8[q] = 0;
     out8[0] = c->n;
-    out8[1] = c->n_mirror;
     if (!c->w.cnt) return LP_OK;
     Counters k;
+    int64_t nm = 0;
     hipError_t e = hipMemcpyAsync(&k, c->w.cnt, sizeof(k), hipMemcpyDeviceToHost,
                                   c->stream);
+    // mirrors of the last stencil build
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&nm, &c->w.summary->n_mirror, sizeof(nm),
+                           hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    out8[1] = nm;
     if (e != hipSuccess) return hip_fail(c, e, "lp_stats");
     out8[2] = (int64_t)k.qr_refits;
     out8[3] = (int64_t)k.hard_stencils;

@@ -303,7 +303,7 @@ __device__ __forceinline__ int for_rows(const View& v, const GridInfo& g,
                                         int64_t i, const Rec& r, F&& f)
 {
     int m = 0;
-    visit_stencil(v, g, v.cr2, i, r, [&](const Pt& p, double dx, double dy, double dz) {
+    visit_stencil(v, g, i, r, [&](const Pt& p, double dx, double dy, double dz) {
         double a[9];
         const double w = point_row(v, g, dx, dy, dz, a);
         f(a, w, &p);

@@ -15,16 +15,17 @@ constexpr int NCOEF = 9;          // unknowns of the 2nd-order 3D fit
 constexpr int MMAX_LIMIT = 64;    // largest supported stencil cap
 constexpr int MAXROWS = MMAX_LIMIT + 8;
 constexpr int HIST_BUCKETS = 64;  // r^2 histogram of the stencil selection
-constexpr int LIST_CAP = 8;       // cut sub-bucket entries held per thread
+constexpr int LIST_CAP = 16;      // cut-bucket members ranked per thread
 constexpr int VCAP = 192;         // neighbour-list entries per particle
+constexpr int MASK_WORDS = VCAP / 64;  // keep bitmask words per particle
 constexpr int32_t MBIT = 0x40000000;  // list entry: mirror of the real id
 constexpr int32_t NOID = 0x7FFFFFFF;
 // per-particle stencil record (int32 fields, field f of particle i at
-// f*n + i): kept rows, ghost mask, mode, cut bucket, cut sub-bucket,
-// octant-first list indices (8), kept list indices of the cut sub-bucket
-constexpr int REC_M = 0, REC_GM = 1, REC_MODE = 2, REC_B = 3, REC_S = 4,
-              REC_FIRST = 5, REC_CUT = 13, REC_FIELDS = 21;
-constexpr int MODE_ALL = 1, MODE_PARTIAL = 2, MODE_PARTIAL2 = 4, MODE_SORTED = 8;
+// f*n + i): kept rows, ghost mask, mode; the kept list entries themselves
+// are a bitmask over the particle's neighbour list (word q at q*n + i)
+constexpr int REC_M = 0, REC_GM = 1, REC_MODE = 2, REC_FIELDS = 3;
+constexpr int MODE_ALL = 1, MODE_SORTED = 8;
+constexpr uint8_t NO_CAND = 0xFF; // key code of a list entry outside R
 constexpr int HARD_CAP = 256;     // candidates the sorted stencil path holds
 constexpr int HARD_SLOTS = 16384; // concurrent sorted-path threads
 constexpr int QR_SLOTS = 16384;   // concurrent QR-refit threads
@@ -92,9 +93,10 @@ struct View {
     // neighbour list with skin (ELL, entry k of particle i at k*n + i)
     const int32_t* vl;
     const int32_t* vcnt;
-    double* cr2;                // r^2 of every list entry (+inf: no candidate)
-    // stencil records and explicit stencils of the sorted path
+    uint8_t* code;              // r^2 bucket of every list entry (NO_CAND: none)
+    // stencil records, keep bitmasks and explicit stencils of the sorted path
     int32_t* rec;
+    uint64_t* kmask;            // MASK_WORDS x n
     int32_t* hsten;             // m_max x n
     double ghost_margin;
     double fallback_tol;
@@ -132,8 +134,9 @@ struct Work {
     // neighbour list, records, sorted-path stencils
     int32_t* vl = nullptr;
     int32_t* vcnt = nullptr;
-    double* cr2 = nullptr;                // VCAP x n
+    uint8_t* code = nullptr;              // VCAP x n
     int32_t* rec = nullptr;
+    uint64_t* kmask = nullptr;            // MASK_WORDS x n
     int32_t* hsten = nullptr;
     int32_t* hard = nullptr;
     unsigned int* hard_n = nullptr;

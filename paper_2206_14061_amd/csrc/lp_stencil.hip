@@ -12,19 +12,19 @@
 // Stencil selection (nearest candidate of each octant, then the nearest
 // others by key (r^2, id), m_max in all), one thread per particle, without
 // storing or sorting the candidates:
-//   pass 1: count, octant coverage bits, nearest candidate per octant and
-//           a histogram of r^2 in 64 buckets of R^2/64 (byte counters in
-//           LDS); the bucket holding the cut follows from it;
-//   pass 2: when the cut falls inside that bucket, its members are split
-//           into 64 sub-buckets;
-//   pass 3: when the cut falls inside that sub-bucket, its few members are
+//   pass 1: exact test of every list entry, count, octant coverage bits,
+//           nearest candidate per octant and a histogram of r^2 in 64
+//           buckets of R^2/64 (byte counters in LDS); each entry's bucket
+//           is stored as one byte; the bucket holding the cut follows from
+//           the histogram;
+//   pass 2: entries of lower buckets and the octant-firsts are kept; when
+//           the cut falls inside its bucket, that bucket's few members are
 //           ranked exactly by key in a per-thread LDS list.
-// The result is a small record per particle (cut bucket and sub-bucket,
-// octant-first ids, kept ids of the cut sub-bucket); the fits re-apply it
-// while streaming the list.  Bucketing is monotone in r^2, so the kept set
-// equals the one a full sort by (r^2, id) gives.  Particles whose cut
-// sub-bucket holds more entries than the list, or with more than 255
-// candidates, take a slower path that sorts all candidates.
+// The result is a keep bitmask over the list entries (plus row count and
+// ghost mask); the fits walk its set bits.  Bucketing is monotone in r^2,
+// so the kept set equals the one a full sort by (r^2, id) gives.
+// Particles whose cut bucket holds more members than the LDS list, or with
+// more than 255 candidates, take a slower path that sorts all candidates.
 #include "lp_visit.h"
 
 namespace lp {
@@ -240,21 +240,35 @@ __device__ __forceinline__ int cut_bucket(const uint32_t (*hist)[BLOCK], int t,
 }
 
 __device__ __forceinline__ void write_rec(const View& v, int64_t i, int m, int gm,
-                                          int mode, int b, int s,
-                                          const int32_t (&first)[8],
-                                          const int32_t (&cut)[LIST_CAP])
+                                          int mode, uint64_t m0, uint64_t m1,
+                                          uint64_t m2)
 {
     const int64_t n = v.n;
     int32_t* q = v.rec;
     q[REC_M * n + i] = m;
     q[REC_GM * n + i] = gm;
     q[REC_MODE * n + i] = mode;
-    q[REC_B * n + i] = b;
-    q[REC_S * n + i] = s;
-#pragma unroll
-    for (int o = 0; o < 8; ++o) q[(REC_FIRST + o) * n + i] = first[o];
-#pragma unroll
-    for (int o = 0; o < LIST_CAP; ++o) q[(REC_CUT + o) * n + i] = cut[o];
+    v.kmask[i] = m0;
+    v.kmask[n + i] = m1;
+    v.kmask[2 * n + i] = m2;
+}
+
+__device__ __forceinline__ void set_bit(uint64_t& m0, uint64_t& m1, uint64_t& m2,
+                                        int k)
+{
+    const uint64_t b = 1ull << (k & 63);
+    if (k < 64)
+        m0 |= b;
+    else if (k < 128)
+        m1 |= b;
+    else
+        m2 |= b;
+}
+
+__device__ __forceinline__ bool has_bit(uint64_t m0, uint64_t m1, uint64_t m2, int k)
+{
+    const uint64_t w = k < 64 ? m0 : (k < 128 ? m1 : m2);
+    return (w >> (k & 63)) & 1ull;
 }
 
 // Calls f(pt, dx, dy, dz, r2) for every candidate of particle i.
@@ -287,7 +301,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
 {
     __shared__ uint32_t hist[HIST_BUCKETS / 4][BLOCK];
     __shared__ double lr2[LIST_CAP][BLOCK];
-    __shared__ int32_t lk[LIST_CAP][BLOCK];
+    __shared__ uint8_t lk[LIST_CAP][BLOCK];
     const int t = threadIdx.x;
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + t;
     if (i >= v.n) return;
@@ -296,137 +310,118 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     const double margin = dmul(v.ghost_margin, g.h);
     const double scale = (double)HIST_BUCKETS / g.R2;
     const double R2 = g.R2;
-    double* __restrict__ cr2 = v.cr2;
+    uint8_t* __restrict__ code = v.code;
+    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const int cnt = v.vcnt[i];
 #pragma unroll
     for (int q = 0; q < HIST_BUCKETS / 4; ++q) hist[q][t] = 0u;
 
-    // ---- pass 1: exact test of every list entry; its key is stored
+    // ---- pass 1: exact test of every list entry; its bucket is stored
     // (entry k of all lanes at once: coalesced)
     int nc = 0, covered = 0;
+    uint64_t c0 = 0, c1 = 0, c2 = 0;   // candidate entries
     double br0 = INFINITY, br1 = INFINITY, br2_ = INFINITY, br3 = INFINITY,
            br4 = INFINITY, br5 = INFINITY, br6 = INFINITY, br7 = INFINITY;
     int32_t bi0 = NOID, bi1 = NOID, bi2 = NOID, bi3 = NOID, bi4 = NOID, bi5 = NOID,
             bi6 = NOID, bi7 = NOID;
     int32_t bk0 = -1, bk1 = -1, bk2 = -1, bk3 = -1, bk4 = -1, bk5 = -1, bk6 = -1,
             bk7 = -1;
-    {
-        const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
-        const int cnt = v.vcnt[i];
-        for (int k = 0; k < cnt; ++k) {
-            const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
-            double r2 = INFINITY;
-            if (p.valid) {
-                const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
-                const double d2 = dist2(dx, dy, dz);
-                if (d2 < R2) {
-                    r2 = d2;
-                    ++nc;
-                    covered |= cover_bit(dx, dy, dz, margin);
-                    const int oct = octant_of(dx, dy, dz);
-                    const int32_t id = p.id;
+    for (int k = 0; k < cnt; ++k) {
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        uint8_t kc = NO_CAND;
+        if (p.valid) {
+            const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
+            const double d2 = dist2(dx, dy, dz);
+            if (d2 < R2) {
+                ++nc;
+                set_bit(c0, c1, c2, k);
+                covered |= cover_bit(dx, dy, dz, margin);
+                const int oct = octant_of(dx, dy, dz);
+                const int32_t id = p.id;
 #define LP_UPD(o, BR, BI, BK)                                              \
     if (oct == o && key_less(d2, id, BR, BI)) {                            \
         BR = d2;                                                           \
         BI = id;                                                           \
         BK = k;                                                            \
     }
-                    LP_UPD(0, br0, bi0, bk0) LP_UPD(1, br1, bi1, bk1)
-                    LP_UPD(2, br2_, bi2, bk2) LP_UPD(3, br3, bi3, bk3)
-                    LP_UPD(4, br4, bi4, bk4) LP_UPD(5, br5, bi5, bk5)
-                    LP_UPD(6, br6, bi6, bk6) LP_UPD(7, br7, bi7, bk7)
+                LP_UPD(0, br0, bi0, bk0) LP_UPD(1, br1, bi1, bk1)
+                LP_UPD(2, br2_, bi2, bk2) LP_UPD(3, br3, bi3, bk3)
+                LP_UPD(4, br4, bi4, bk4) LP_UPD(5, br5, bi5, bk5)
+                LP_UPD(6, br6, bi6, bk6) LP_UPD(7, br7, bi7, bk7)
 #undef LP_UPD
-                    hist_add(hist, bucket_of(d2, scale), t, 1);
-                }
+                const int b = bucket_of(d2, scale);
+                hist_add(hist, b, t, 1);
+                kc = (uint8_t)b;
             }
-            cr2[(int64_t)k * n + i] = r2;
         }
+        code[(int64_t)k * n + i] = kc;
     }
     const int gm = ~covered & 0xFF;
     const int m_max = v.m_max;
-    const int32_t first[8] = {bk0, bk1, bk2, bk3, bk4, bk5, bk6, bk7};
-    const double brs[8] = {br0, br1, br2_, br3, br4, br5, br6, br7};
-    int32_t cut[LIST_CAP];
-#pragma unroll
-    for (int o = 0; o < LIST_CAP; ++o) cut[o] = -1;
     if (force_sorted || nc > 255) {
-        write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, first, cut);
+        write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, 0);
         hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
         return;
     }
     if (nc <= m_max) {
-        write_rec(v, i, nc, gm, MODE_ALL, 0, 0, first, cut);
+        write_rec(v, i, nc, gm, MODE_ALL, c0, c1, c2);
         return;
     }
+    const int32_t first[8] = {bk0, bk1, bk2, bk3, bk4, bk5, bk6, bk7};
+    const double brs[8] = {br0, br1, br2_, br3, br4, br5, br6, br7};
+    uint64_t f0 = 0, f1 = 0, f2 = 0;   // octant-first entries
     int n_oct = 0;
 #pragma unroll
     for (int o = 0; o < 8; ++o)
         if (first[o] >= 0) {
             ++n_oct;
+            set_bit(f0, f1, f2, first[o]);
             hist_add(hist, bucket_of(brs[o], scale), t, -1);
         }
     const int K = m_max - n_oct;
-    if (K < 0) {
-        write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, first, cut);
+    int need = 0, hc = 0;
+    const int bstar = K < 0 ? 0 : cut_bucket(hist, t, K, need, hc);
+    if (K < 0 || (need < hc && hc > LIST_CAP)) {
+        write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, 0);
         hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
         return;
     }
-    int need, hc;
-    const int bstar = cut_bucket(hist, t, K, need, hc);
-    int mode = 0, sstar = 0;
-    const int cnt = v.vcnt[i];
-    auto is_first = [&](int k) {
-        bool f = false;
-#pragma unroll
-        for (int o = 0; o < 8; ++o) f = f || (first[o] == k);
-        return f;
-    };
-    if (need < hc) {
-        // ---- pass 2: split the cut bucket (stored keys, no gathers)
-        mode |= MODE_PARTIAL;
-#pragma unroll
-        for (int q = 0; q < HIST_BUCKETS / 4; ++q) hist[q][t] = 0u;
-        for (int k = 0; k < cnt; ++k) {
-            const double r2 = cr2[(int64_t)k * n + i];
-            if (!(r2 < R2) || bucket_of(r2, scale) != bstar || is_first(k)) continue;
-            hist_add(hist, sub_of(r2, scale, bstar), t, 1);
-        }
-        int need2, hc2;
-        sstar = cut_bucket(hist, t, need, need2, hc2);
-        if (need2 < hc2) {
-            // ---- pass 3: rank the members of the cut sub-bucket by key
-            mode |= MODE_PARTIAL2;
-            if (hc2 > LIST_CAP) {
-                write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, first, cut);
-                hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
-                return;
-            }
-            int nl = 0;
-            for (int k = 0; k < cnt && nl < LIST_CAP; ++k) {
-                const double r2 = cr2[(int64_t)k * n + i];
-                if (!(r2 < R2) || bucket_of(r2, scale) != bstar || is_first(k)) continue;
-                if (sub_of(r2, scale, bstar) != sstar) continue;
-                lr2[nl][t] = r2;
-                lk[nl][t] = k;
-                ++nl;
-            }
-            int kc = 0;
-            for (int a = 0; a < nl; ++a) {
-                const int32_t ida = entry_id(v, v.vl[(int64_t)lk[a][t] * n + i]);
-                int rank = 0;
-                for (int b = 0; b < nl; ++b) {
-                    const int32_t idb = entry_id(v, v.vl[(int64_t)lk[b][t] * n + i]);
-                    if (key_less(lr2[b][t], idb, lr2[a][t], ida)) ++rank;
-                }
-                if (rank < need2) {
-#pragma unroll
-                    for (int o = 0; o < LIST_CAP; ++o)
-                        if (o == kc) cut[o] = lk[a][t];
-                    ++kc;
-                }
-            }
+
+    // ---- pass 2: keep the octant-firsts and every lower bucket; collect
+    // the members of the cut bucket when only some of them are kept
+    const bool whole = need == hc;
+    uint64_t m0 = f0, m1 = f1, m2 = f2;
+    int nl = 0;
+    for (int k = 0; k < cnt; ++k) {
+        const int kc = code[(int64_t)k * n + i];
+        if (kc < bstar || (kc == bstar && whole)) {
+            set_bit(m0, m1, m2, k);
+        } else if (kc == bstar && !has_bit(f0, f1, f2, k)) {
+            // member of the cut bucket: its exact key again
+            const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+            lr2[nl][t] = dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
+            lk[nl][t] = (uint8_t)k;
+            ++nl;
         }
     }
-    write_rec(v, i, m_max, gm, mode, bstar, sstar, first, cut);
+    // the `need` smallest keys (r^2, id) of the cut bucket
+    for (int a = 0; a < nl; ++a) {
+        const double ra = lr2[a][t];
+        int rank = 0;
+        int32_t ida = -1;
+        for (int b = 0; b < nl; ++b) {
+            const double rb = lr2[b][t];
+            if (rb < ra) {
+                ++rank;
+            } else if (rb == ra && b != a) {
+                if (ida < 0) ida = entry_id(v, v.vl[(int64_t)lk[a][t] * n + i]);
+                const int32_t idb = entry_id(v, v.vl[(int64_t)lk[b][t] * n + i]);
+                if (idb < ida) ++rank;
+            }
+        }
+        if (rank < need) set_bit(m0, m1, m2, lk[a][t]);
+    }
+    write_rec(v, i, m_max, gm, 0, m0, m1, m2);
 }
 
 // Exact path: collect all candidates, sort by key, take octant-firsts then
@@ -551,7 +546,7 @@ __global__ void k_export_stencils(View v, int32_t* cnt_out, int32_t* idx_out,
     if (gm_out) gm_out[i] = (uint8_t)r.gm;
     int m = 0;
     int32_t* out = idx_out ? idx_out + i * mm : nullptr;
-    visit_stencil(v, g, v.cr2, i, r, [&](const Pt& p, double, double, double) {
+    visit_stencil(v, g, i, r, [&](const Pt& p, double, double, double) {
         if (out && m < mm) {
             int q = m;
             while (q > 0 && out[q - 1] > p.id) {

@@ -86,19 +86,11 @@ __device__ __forceinline__ int bucket_of(double r2, double scale)
     return b > HIST_BUCKETS - 1 ? HIST_BUCKETS - 1 : b;
 }
 
-// sub-bucket of r^2 inside bucket b (monotone in r^2)
-__device__ __forceinline__ int sub_of(double r2, double scale, int b)
-{
-    const int sb = (int)dmul(dsub(dmul(r2, scale), (double)b), (double)HIST_BUCKETS);
-    return sb < 0 ? 0 : (sb > HIST_BUCKETS - 1 ? HIST_BUCKETS - 1 : sb);
-}
-
-// Stencil record of one particle, in registers.  Octant-firsts and the
-// kept members of the cut sub-bucket are list indices (-1 when absent).
+// Stencil record of one particle, in registers: kept rows, ghost mask,
+// mode and the keep bitmask over its neighbour-list entries.
 struct Rec {
-    int m, gm, mode, b, s;
-    int32_t first[8];
-    int32_t cut[LIST_CAP];
+    int m, gm, mode;
+    uint64_t mask[MASK_WORDS];
 };
 
 __device__ __forceinline__ Rec load_rec(const View& v, int64_t i)
@@ -109,43 +101,17 @@ __device__ __forceinline__ Rec load_rec(const View& v, int64_t i)
     r.m = q[REC_M * n + i];
     r.gm = q[REC_GM * n + i];
     r.mode = q[REC_MODE * n + i];
-    r.b = q[REC_B * n + i];
-    r.s = q[REC_S * n + i];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) r.first[o] = q[(REC_FIRST + o) * n + i];
-#pragma unroll
-    for (int o = 0; o < LIST_CAP; ++o) r.cut[o] = q[(REC_CUT + o) * n + i];
+    for (int w = 0; w < MASK_WORDS; ++w) r.mask[w] = v.kmask[w * n + i];
     return r;
 }
 
-// Whether list entry k, a candidate with key r2, belongs to the stencil.
-__device__ __forceinline__ bool keep_entry(const Rec& r, int k, double r2,
-                                           double scale)
-{
-    if (r.mode & MODE_ALL) return true;
-    bool f = false;
-#pragma unroll
-    for (int o = 0; o < 8; ++o) f = f || (r.first[o] == k);
-    if (f) return true;
-    const int b = bucket_of(r2, scale);
-    if (b != r.b) return b < r.b;
-    if (!(r.mode & MODE_PARTIAL)) return true;
-    const int sb = sub_of(r2, scale, b);
-    if (sb != r.s) return sb < r.s;
-    if (!(r.mode & MODE_PARTIAL2)) return true;
-    bool c = false;
-#pragma unroll
-    for (int o = 0; o < LIST_CAP; ++o) c = c || (r.cut[o] == k);
-    return c;
-}
-
-// Calls f(pt, dx, dy, dz) for every stencil row of real particle i (the
-// ghost rows are not visited: they follow from r.gm).  cr2 holds the
-// candidate key r^2 of every list entry (+inf for non-candidates), as
-// stored by the selection.
+// Calls f(pt, dx, dy, dz) for every stencil row of real particle i, in
+// ascending list order (the ghost rows are not visited: they follow from
+// r.gm).  Each lane walks only its own kept entries, so a wave runs as
+// many iterations as its largest stencil.
 template <class F>
 __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
-                                              const double* __restrict__ cr2,
                                               int64_t i, const Rec& r, F&& f)
 {
     const int64_t n = v.n;
@@ -157,12 +123,20 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
         }
         return;
     }
-    const double R2 = g.R2;
-    const double scale = (double)HIST_BUCKETS / R2;
-    const int cnt = v.vcnt[i];
-    for (int k = 0; k < cnt; ++k) {
-        const double r2 = cr2[(int64_t)k * n + i];
-        if (!(r2 < R2) || !keep_entry(r, k, r2, scale)) continue;
+    static_assert(MASK_WORDS == 3, "keep mask walk assumes three words");
+    uint64_t b0 = r.mask[0], b1 = r.mask[1], b2 = r.mask[2];
+    for (int t = 0; t < r.m; ++t) {
+        int k;
+        if (b0) {
+            k = __builtin_ctzll(b0);
+            b0 &= b0 - 1;
+        } else if (b1) {
+            k = 64 + __builtin_ctzll(b1);
+            b1 &= b1 - 1;
+        } else {
+            k = 128 + __builtin_ctzll(b2);
+            b2 &= b2 - 1;
+        }
         const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
         f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
     }
