@@ -74,7 +74,7 @@ void free_work(Work& w)
     for (int a = 0; a < 3; ++a) f(w.xref[a]);
     f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
     f(w.vl); f(w.vcnt); f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
-    f(w.hard_r2); f(w.hard_id); f(w.redo); f(w.redo_n); f(w.qr_scratch);
+    f(w.redo); f(w.redo_n); f(w.qr_scratch);
     f(w.P); f(w.eta); f(w.hand); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
@@ -203,8 +203,6 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.kmask, (int64_t)MASK_WORDS * n_max);
     A(w.rec, (int64_t)REC_FIELDS * n_max); A(w.hsten, (int64_t)mm * n_max);
     A(w.hard, n_max); A(w.hard_n, 1);
-    A(w.hard_r2, (int64_t)HARD_SLOTS * HARD_CAP);
-    A(w.hard_id, (int64_t)HARD_SLOTS * HARD_CAP);
     A(w.redo, n_max); A(w.redo_n, 1);
     A(w.qr_scratch, (int64_t)QR_SLOTS * MAXROWS * 17);
     A(w.P, n_max); A(w.eta, n_max); A(w.hand, (int64_t)HAND * n_max);

@@ -27,7 +27,7 @@ constexpr int REC_M = 0, REC_GM = 1, REC_MODE = 2, REC_FIELDS = 3;
 constexpr int MODE_ALL = 1, MODE_SORTED = 8;
 constexpr uint8_t NO_CAND = 0xFF; // key code of a list entry outside R
 constexpr int HARD_CAP = 256;     // candidates the sorted stencil path holds
-constexpr int HARD_SLOTS = 16384; // concurrent sorted-path threads
+constexpr int HARD_BLOCKS = 1024; // blocks of the sorted path (a wave per particle)
 constexpr int QR_SLOTS = 16384;   // concurrent QR-refit threads
 constexpr int HAND = 37;          // pass-1 -> pass-2 handoff doubles
 constexpr int BLOCK = 256;        // threads per block of per-particle kernels
@@ -140,8 +140,6 @@ struct Work {
     int32_t* hsten = nullptr;
     int32_t* hard = nullptr;
     unsigned int* hard_n = nullptr;
-    double* hard_r2 = nullptr;            // HARD_SLOTS x HARD_CAP
-    int32_t* hard_id = nullptr;
     // fits
     int32_t* redo = nullptr;
     unsigned int* redo_n = nullptr;

@@ -289,19 +289,16 @@ __device__ __forceinline__ void for_candidates(const View& v, const GridInfo& g,
     }
 }
 
-// candidate id of list entry e (valid candidate assumed)
-__device__ __forceinline__ int32_t entry_id(const View& v, int32_t e)
-{
-    return (e & MBIT) ? (int32_t)v.n + v.mirror_of[e & ~MBIT] : e;
-}
-
 __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
                                                   unsigned int* hard_n,
                                                   int force_sorted)
 {
     __shared__ uint32_t hist[HIST_BUCKETS / 4][BLOCK];
-    __shared__ double lr2[LIST_CAP][BLOCK];
-    __shared__ uint8_t lk[LIST_CAP][BLOCK];
+    // cut-bucket members, one word each: r^2 rounded to float with its
+    // low 8 bits replaced by the list index.  Rounding and truncation are
+    // monotone, so a smaller word means a smaller r^2; equal truncated
+    // keys take the exact keys again.
+    __shared__ uint32_t lkey[LIST_CAP][BLOCK];
     const int t = threadIdx.x;
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + t;
     if (i >= v.n) return;
@@ -397,86 +394,175 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
         if (kc < bstar || (kc == bstar && whole)) {
             set_bit(m0, m1, m2, k);
         } else if (kc == bstar && !has_bit(f0, f1, f2, k)) {
-            // member of the cut bucket: its exact key again
+            // member of the cut bucket
             const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
-            lr2[nl][t] = dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
-            lk[nl][t] = (uint8_t)k;
+            const float f = (float)dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
+            lkey[nl][t] = (__float_as_uint(f) & ~0xFFu) | (uint32_t)k;
             ++nl;
         }
     }
     // the `need` smallest keys (r^2, id) of the cut bucket
+    auto exact_key = [&](int k, double& r2, int32_t& id) {
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        r2 = dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
+        id = p.id;
+    };
     for (int a = 0; a < nl; ++a) {
-        const double ra = lr2[a][t];
+        const uint32_t ka = lkey[a][t];
+        const int la = (int)(ka & 0xFFu);
         int rank = 0;
-        int32_t ida = -1;
+        bool have_a = false;
+        double ra = 0.0;
+        int32_t ida = 0;
         for (int b = 0; b < nl; ++b) {
-            const double rb = lr2[b][t];
-            if (rb < ra) {
+            const uint32_t kb = lkey[b][t];
+            if ((kb >> 8) < (ka >> 8)) {
                 ++rank;
-            } else if (rb == ra && b != a) {
-                if (ida < 0) ida = entry_id(v, v.vl[(int64_t)lk[a][t] * n + i]);
-                const int32_t idb = entry_id(v, v.vl[(int64_t)lk[b][t] * n + i]);
-                if (idb < ida) ++rank;
+            } else if ((kb >> 8) == (ka >> 8) && b != a) {
+                if (!have_a) {
+                    exact_key(la, ra, ida);
+                    have_a = true;
+                }
+                double rb;
+                int32_t idb;
+                exact_key((int)(kb & 0xFFu), rb, idb);
+                if (key_less(rb, idb, ra, ida)) ++rank;
             }
         }
-        if (rank < need) set_bit(m0, m1, m2, lk[a][t]);
+        if (rank < need) set_bit(m0, m1, m2, la);
     }
     write_rec(v, i, m_max, gm, 0, m0, m1, m2);
 }
 
-// Exact path: collect all candidates, sort by key, take octant-firsts then
-// the nearest others (the stencil rule written out directly).
-__global__ __launch_bounds__(BLOCK) void k_select_sorted(
-    View v, const int32_t* hard, const unsigned int* hard_n, double* sr2,
-    int32_t* sid, ErrWord* err, Counters* cnt)
+// Exact path, one wavefront per particle: the candidates are collected
+// into LDS, each is ranked by key (r^2, id) against all others, and the
+// stencil rule is applied directly (octant-firsts in octant order, then
+// the others in key order, m_max in all).
+__device__ __forceinline__ void wave_sync()
 {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+__global__ __launch_bounds__(BLOCK) void k_select_sorted(
+    View v, const int32_t* hard, const unsigned int* hard_n, ErrWord* err,
+    Counters* cnt)
+{
+    constexpr int WPB = BLOCK / 64;
+    constexpr int PER_LANE = HARD_CAP / 64;
+    __shared__ double sr2[WPB][HARD_CAP];
+    __shared__ int32_t sid[WPB][HARD_CAP];   // id | octant << 28
+    __shared__ double fr2[WPB][8];
+    __shared__ int32_t fid[WPB][8];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const unsigned int total = *hard_n;
-    if (slot == 0) atomicAdd(&cnt->hard_stencils, (unsigned long long)total);
-    double* r2s = sr2 + slot * HARD_CAP;
-    int32_t* ids = sid + slot * HARD_CAP;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd(&cnt->hard_stencils, (unsigned long long)total);
     const int64_t n = v.n;
-    for (int64_t tt = slot; tt < (int64_t)total; tt += nthreads) {
+    const int m_max = v.m_max;
+    const uint64_t below = (1ull << lane) - 1;
+    for (int64_t tt = (int64_t)blockIdx.x * WPB + wv; tt < (int64_t)total;
+         tt += (int64_t)gridDim.x * WPB) {
         const int64_t i = hard[tt];
         const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
+        const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+        const double R2 = g.R2;
+        const int cnt_i = v.vcnt[i];
+        // ---- collect (ballot compaction, list order)
         int nc = 0;
-        for_candidates(v, g, i, [&](const Pt& p, double dx, double dy, double dz,
-                                    double r2) {
-            if (nc < HARD_CAP) {
-                int q = nc;
-                while (q > 0 && key_less(r2, p.id, r2s[q - 1], ids[q - 1] & 0x0FFFFFFF)) {
-                    r2s[q] = r2s[q - 1];
-                    ids[q] = ids[q - 1];
-                    --q;
+        for (int k0 = 0; k0 < cnt_i; k0 += 64) {
+            const int k = k0 + lane;
+            bool cand = false;
+            double r2 = 0.0;
+            int32_t key = 0;
+            if (k < cnt_i) {
+                const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+                if (p.valid) {
+                    const double dx = dsub(p.x, xi), dy = dsub(p.y, yi),
+                                 dz = dsub(p.z, zi);
+                    r2 = dist2(dx, dy, dz);
+                    cand = r2 < R2;
+                    key = p.id | (octant_of(dx, dy, dz) << 28);
                 }
-                r2s[q] = r2;
-                ids[q] = p.id | (octant_of(dx, dy, dz) << 28);
             }
-            ++nc;
-        });
+            const uint64_t bal = __ballot(cand);
+            const int pos = nc + __popcll(bal & below);
+            if (cand && pos < HARD_CAP) {
+                sr2[wv][pos] = r2;
+                sid[wv][pos] = key;
+            }
+            nc += __popcll(bal);
+        }
         if (nc > HARD_CAP) {
-            raise_error(err, ERR_CAPACITY, i);
-            v.rec[REC_M * n + i] = 0;
+            if (lane == 0) {
+                raise_error(err, ERR_CAPACITY, i);
+                v.rec[REC_M * n + i] = 0;
+            }
             continue;
         }
-        int firstpos[8];
-        for (int o = 0; o < 8; ++o) firstpos[o] = -1;
-        for (int q = 0; q < nc; ++q) {
-            const int o = (ids[q] >> 28) & 7;
-            if (firstpos[o] < 0) firstpos[o] = q;
+        if (lane < 8) {
+            fr2[wv][lane] = INFINITY;
+            fid[wv][lane] = -1;
         }
-        int k = 0;
-        const int m_max = v.m_max;
+        wave_sync();
+        // ---- rank of each candidate, overall and within its octant
+        int rk[PER_LANE], ork[PER_LANE];
+#pragma unroll
+        for (int q = 0; q < PER_LANE; ++q) {
+            const int c = lane + 64 * q;
+            rk[q] = 0;
+            ork[q] = 1;
+            if (c < nc) {
+                const double rc = sr2[wv][c];
+                const int32_t kc = sid[wv][c];
+                const int32_t idc = kc & 0x0FFFFFFF;
+                const int oc = (kc >> 28) & 7;
+                int r = 0, o = 0;
+                for (int j = 0; j < nc; ++j) {
+                    const int32_t kj = sid[wv][j];
+                    const bool less = key_less(sr2[wv][j], kj & 0x0FFFFFFF, rc, idc);
+                    r += less ? 1 : 0;
+                    o += (less && ((kj >> 28) & 7) == oc) ? 1 : 0;
+                }
+                rk[q] = r;
+                ork[q] = o;
+                if (o == 0) {
+                    fr2[wv][oc] = rc;
+                    fid[wv][oc] = idc;
+                }
+            }
+        }
+        wave_sync();
+        // ---- output slot of each candidate
+        int octmask = 0;
+#pragma unroll
         for (int o = 0; o < 8; ++o)
-            if (firstpos[o] >= 0 && k < m_max)
-                v.hsten[(int64_t)k++ * n + i] = ids[firstpos[o]] & 0x0FFFFFFF;
-        for (int q = 0; q < nc && k < m_max; ++q) {
-            bool f = false;
-            for (int o = 0; o < 8; ++o) f = f || (firstpos[o] == q);
-            if (!f) v.hsten[(int64_t)k++ * n + i] = ids[q] & 0x0FFFFFFF;
+            if (fid[wv][o] >= 0) octmask |= 1 << o;
+        const int n_oct = __popc(octmask);
+#pragma unroll
+        for (int q = 0; q < PER_LANE; ++q) {
+            const int c = lane + 64 * q;
+            if (c >= nc) continue;
+            const double rc = sr2[wv][c];
+            const int32_t kc = sid[wv][c];
+            const int32_t idc = kc & 0x0FFFFFFF;
+            const int oc = (kc >> 28) & 7;
+            int slot;
+            if (ork[q] == 0) {
+                slot = __popc(octmask & ((1 << oc) - 1));
+            } else {
+                int fl = 0;
+#pragma unroll
+                for (int o = 0; o < 8; ++o)
+                    if (fid[wv][o] >= 0 && key_less(fr2[wv][o], fid[wv][o], rc, idc)) ++fl;
+                slot = n_oct + rk[q] - fl;
+            }
+            if (slot < m_max) v.hsten[(int64_t)slot * n + i] = idc;
         }
-        v.rec[REC_M * n + i] = k;
+        if (lane == 0) v.rec[REC_M * n + i] = nc < m_max ? nc : m_max;
+        wave_sync();
     }
 }
 
@@ -609,9 +695,8 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7])
                            w.hard, w.hard_n, force);
         prof_mark(c, 1, true);
         prof_mark(c, 2, false);
-        hipLaunchKernelGGL(k_select_sorted, dim3(HARD_SLOTS / BLOCK), dim3(BLOCK), 0,
-                           s, v, w.hard, w.hard_n, w.hard_r2, w.hard_id, w.err,
-                           w.cnt);
+        hipLaunchKernelGGL(k_select_sorted, dim3(HARD_BLOCKS), dim3(BLOCK), 0, s, v,
+                           w.hard, w.hard_n, w.err, w.cnt);
         prof_mark(c, 2, true);
     }
     hipError_t e = hipGetLastError();

@@ -51,8 +51,18 @@ def _ragged(wl, drop=37):
     return wl
 
 
+def _exact_lattice(nx=12, ny=10, nz=9):
+    """Unjittered lattice: many exactly equal distances, so every stencil
+    cut is decided by the id tie-break."""
+    h = 1.0 / 16.0
+    p = lpgen.default_params(h)
+    st = lpgen.lattice_column(nx, ny, nz, h, seed=7, jitter=0.0, params=p)
+    return lpgen.Workload("lattice_exact", st, np.array([0, st.n]), [p], 1e-4, 1)
+
+
 CASES = {
     "column16": lambda: lpgen.column_small(),
+    "lattice_exact": lambda: _with_flow(_exact_lattice()),
     "column16_flow_ragged": lambda: _ragged(_with_flow(lpgen.column_small())),
     "sheared_20x20x12": lambda: lpgen.column_sheared(nx=20, ny=20, nz=12),
     "ensemble_3": lambda: _with_flow(lpgen.ensemble(n_sys=3, n_lo=600, n_hi=3000)),
@@ -138,7 +148,8 @@ def test_neighbours_stencils_ghosts_bit_exact(lp, case):
     _log("stats %s" % ctx.stats())
 
 
-@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12"])
+@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
+                                  "lattice_exact"])
 def test_sorted_stencil_path_bit_exact(lp, case):
     """The exact sorted-candidate path (used for overflowing cut buckets)
     gives the same stencils when forced for every particle."""
