@@ -1,6 +1,6 @@
 """Throughput of the LP granular-flow step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32r]
 
 A step is one lp_step over the whole 64 x 64 x 128 = 524,288-particle
 granular column (h = 0.5/64 m, jitter 0.05 h, hydrostatic density, resting
@@ -49,7 +49,7 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -134,54 +134,56 @@ def main():
 
     torch.cuda.set_device(0)
     wl = lpgen.column_bench()
-    ctx = lp.make_context(wl)
-    st = lp.DeviceState.from_host(wl.state)
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        ctx.lp_step(st, wl.dt)
-    ctx.sync_status()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.lp_step(st, wl.dt)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ctx.sync_status()
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = wl.n * args.steps / elapsed
 
-    # phase durations from HIP events on the library's stream
-    ctx.profile(True)
-    ctx.profile_read()
-    for _ in range(args.steps):
-        ctx.lp_step(st, wl.dt)
-    torch.cuda.synchronize()
-    ph = ctx.profile_read()
-    ctx.profile(False)
-    ctx.sync_status()
-    nst = max(ph.pop("steps"), 1)
-    phases = {k: v / nst for k, v in ph.items()}
-    stats = ctx.stats()
+    def run(steps, warmup, **cfg):
+        """Times `steps` lp_step calls after `warmup`, then the same number
+        again with phase events; returns (ms/step, phases, stats)."""
+        ctx = lp.make_context(wl, **cfg)
+        st = lp.DeviceState.from_host(wl.state)
+        torch.cuda.synchronize()
+        for _ in range(warmup):
+            ctx.lp_step(st, wl.dt)
+        ctx.sync_status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.lp_step(st, wl.dt)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        ctx.sync_status()
+        ctx.profile(True)
+        ctx.profile_read()
+        for _ in range(steps):
+            ctx.lp_step(st, wl.dt)
+        torch.cuda.synchronize()
+        ph = ctx.profile_read()
+        ctx.profile(False)
+        ctx.sync_status()
+        nst = max(ph.pop("steps"), 1)
+        return 1e3 * elapsed / steps, {k: v / nst for k, v in ph.items()}, ctx.stats()
+
+    main_prec = lp.LP_FP64 if args.precision == "fp64" else lp.LP_FP32_REFINED
+    ms_per_step, phases, stats = run(args.steps, args.warmup, precision=main_prec)
+    value = wl.n / (ms_per_step * 1e-3)
     dominant = max(("select", "pass1", "pass2"), key=lambda k: phases[k])
-
+    # the other precision on the same column
+    other = "fp32r" if args.precision == "fp64" else "fp64"
+    ms_o, ph_o, st_o = run(args.steps, args.warmup,
+                           precision=lp.LP_FP32_REFINED if other == "fp32r" else lp.LP_FP64)
+    ms64 = ms_per_step if args.precision == "fp64" else ms_o
+    ms32 = ms_o if args.precision == "fp64" else ms_per_step
+    compare = {"precision": other, "value": wl.n / (ms_o * 1e-3),
+               "ms_per_step": ms_o, "phases_ms": ph_o, "stats": st_o,
+               "fp32r_speedup_vs_fp64": ms64 / ms32}
     # the same steps with the neighbour list rebuilt (and the column
     # re-sorted) at every step
-    ctx0 = lp.make_context(wl, skin=0.0)
-    st0 = lp.DeviceState.from_host(wl.state)
-    for _ in range(args.warmup):
-        ctx0.lp_step(st0, wl.dt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     k0 = max(2, args.steps // 2)
-    for _ in range(k0):
-        ctx0.lp_step(st0, wl.dt)
-    torch.cuda.synchronize()
-    ms_rebuild = 1e3 * (time.perf_counter() - t0) / k0
-    ctx0.sync_status()
+    ms_rebuild, _, _ = run(k0, args.warmup, precision=main_prec, skin=0.0)
     t_pass1 = phases["pass1"] * 1e-3
     achieved = PASS1_FLOP_PER_PARTICLE * wl.n / t_pass1 / 1e12
     executed = PASS1_FLOP_EXECUTED * wl.n / t_pass1 / 1e12
-    roof = {"kernel": "k_pass1 (fit of u, v, w + mu(I) closure)",
+    roof = {"kernel": ("k_pass1" if args.precision == "fp64" else "k_pass1_ref")
+                      + " (fit of u, v, w + mu(I) closure)",
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": pass1_traffic(), "avg_launch_ms": phases["pass1"],
@@ -191,12 +193,13 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "particle-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32+f64",
            "data": "synthetic",
            "config": {"workload": wl.name, "particles": wl.n, "dt": wl.dt,
                       "precision": args.precision, "m_max": 60,
                       "R_over_h": 2.5, "skin": 0.1, "parallelism": "none"},
-           "phases_ms": phases, "stats": stats,
+           "phases_ms": phases, "stats": stats, "other_precision": compare,
            "ms_per_step_rebuild_every_step": ms_rebuild,
            "roofline": roof}
     if not args.no_cpu_baseline:

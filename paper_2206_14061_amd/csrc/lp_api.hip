@@ -75,7 +75,7 @@ void free_work(Work& w)
     f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
     f(w.vl); f(w.vcnt); f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
     f(w.redo); f(w.redo_n); f(w.qr_scratch);
-    f(w.P); f(w.eta); f(w.hand); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
+    f(w.P); f(w.eta); f(w.hand); f(w.uf); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
     w.n_max = w.cells_max = 0;
@@ -206,6 +206,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.redo, n_max); A(w.redo_n, 1);
     A(w.qr_scratch, (int64_t)QR_SLOTS * MAXROWS * 17);
     A(w.P, n_max); A(w.eta, n_max); A(w.hand, (int64_t)HAND * n_max);
+    A(w.uf, (int64_t)45 * n_max);
     A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
     A(w.coff, n_max + 1);
     if (e == hipSuccess) e = hipHostMalloc((void**)&w.h_summary, sizeof(Summary));

@@ -1,6 +1,7 @@
 // Morton-sorted cell list and mirror particles (the paper's octree of
 // Sec. 3.1 step 4 / Sec. 3.2 replaced by a uniform cell list sorted in
 // Z order; mirrors of Sec. 3.1 step 9).
+#include <algorithm>
 #include <cstring>
 
 #include "lp_internal.h"
@@ -323,22 +324,32 @@ __global__ void k_iota(int64_t n, int32_t* p)
 }
 
 // Largest (displacement / (skin R))^2 since the list build.
-__global__ void k_disp(int64_t n, int n_sys, const int64_t* off,
-                       const GridInfo* grid, const double* x, const double* y,
-                       const double* z, const double* rx, const double* ry,
-                       const double* rz, Summary* sum)
+// Largest squared displacement since the list build, in units of
+// (skin R)^2; grid-stride, one atomic per block.
+__global__ __launch_bounds__(BLOCK) void k_disp(int64_t n, int n_sys, const int64_t* off,
+                                                const GridInfo* grid, const double* x,
+                                                const double* y, const double* z,
+                                                const double* rx, const double* ry,
+                                                const double* rz, Summary* sum)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double part[BLOCK / 64];
     double r = 0.0;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
         const GridInfo& g = grid[sys_of(off, n_sys, i)];
         const double dx = x[i] - rx[i], dy = y[i] - ry[i], dz = z[i] - rz[i];
         const double d2 = dx * dx + dy * dy + dz * dz;
-        r = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
-        if (!(r == r)) r = INFINITY;   // non-finite positions force a rebuild
+        double q = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
+        if (!(q == q)) q = INFINITY;   // non-finite positions force a rebuild
+        r = fmax(r, q);
     }
     for (int d = 32; d > 0; d >>= 1) r = fmax(r, __shfl_xor(r, d));
-    if ((threadIdx.x & 63) == 0) atomicMax(&sum->disp, ord_enc(r));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLOCK / 64; ++w) r = fmax(r, part[w]);
+        atomicMax(&sum->disp, ord_enc(r));
+    }
 }
 
 __global__ void k_disp_init(Summary* sum) { sum->disp = ord_enc(0.0); }
@@ -484,7 +495,8 @@ lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio)
     if (!c->list_ok) return LP_OK;
     hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
     if (n > 0)
-        hipLaunchKernelGGL(k_disp, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
+        hipLaunchKernelGGL(k_disp, dim3(std::min(blocks_for(n), 1024u)), dim3(BLOCK), 0,
+                           c->stream, n,
                            c->n_sys, w.off, w.grid, st[0], st[1], st[2], w.xref[0],
                            w.xref[1], w.xref[2], w.summary);
     hipError_t e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary),

@@ -87,24 +87,24 @@ __device__ __forceinline__ void point_velocity(const View& v, const Pt& p,
 
 // G = U^T U in place (packed upper); returns min U_jj / max U_jj, or -1
 // when a pivot is not positive.
-template <int N>
-__device__ __forceinline__ double cholesky(double (&G)[45])
+template <int N, class T>
+__device__ __forceinline__ T cholesky(T (&G)[45])
 {
-    double dmin = INFINITY, dmax = 0.0;
+    T dmin = INFINITY, dmax = 0;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        double s = G[uix(j, j)];
+        T s = G[uix(j, j)];
 #pragma unroll
         for (int k = 0; k < j; ++k) s -= G[uix(k, j)] * G[uix(k, j)];
-        if (!(s > 0.0)) return -1.0;
-        const double d = sqrt(s);
-        const double inv = 1.0 / d;
+        if (!(s > T(0))) return T(-1);
+        const T d = sqrt(s);
+        const T inv = T(1) / d;
         G[uix(j, j)] = d;
         dmin = fmin(dmin, d);
         dmax = fmax(dmax, d);
 #pragma unroll
         for (int l = j + 1; l < N; ++l) {
-            double t = G[uix(j, l)];
+            T t = G[uix(j, l)];
 #pragma unroll
             for (int k = 0; k < j; ++k) t -= G[uix(k, j)] * G[uix(k, l)];
             G[uix(j, l)] = t * inv;
@@ -114,19 +114,19 @@ __device__ __forceinline__ double cholesky(double (&G)[45])
 }
 
 // Solves U^T U c = b in place (b -> c).
-template <int N>
-__device__ __forceinline__ void chol_solve(const double (&U)[45], double (&b)[9])
+template <int N, class T>
+__device__ __forceinline__ void chol_solve(const T (&U)[45], T (&b)[9])
 {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        double t = b[j];
+        T t = b[j];
 #pragma unroll
         for (int k = 0; k < j; ++k) t -= U[uix(k, j)] * b[k];
         b[j] = t / U[uix(j, j)];
     }
 #pragma unroll
     for (int j = N - 1; j >= 0; --j) {
-        double t = b[j];
+        T t = b[j];
 #pragma unroll
         for (int k = j + 1; k < N; ++k) t -= U[uix(j, k)] * b[k];
         b[j] = t / U[uix(j, j)];
@@ -407,13 +407,13 @@ __device__ __forceinline__ bool gram_solve(double (&G)[45], const double (&B)[NF
 //   6 xxx 7 yyy 8 zzz 9 xxy 10 xxz 11 xyy 12 yyz 13 xzz 14 yzz 15 xyz
 //   16 xxxx 17 yyyy 18 zzzz 19 xxyy 20 xxzz 21 yyzz 22 xxxy 23 xxxz
 //   24 xyyy 25 yyyz 26 xzzz 27 yzzz 28 xxyz 29 xyyz 30 xyzz
-__device__ __forceinline__ void moments_add(double (&M)[31], const double* a,
-                                            double w)
+template <class T>
+__device__ __forceinline__ void moments_add(T (&M)[31], const T* a, T w)
 {
-    const double x = a[0], y = a[1], z = a[2];
-    const double xx = x * x, yy = y * y, zz = z * z;
-    const double xy = a[6], xz = a[7], yz = a[8];
-    const double wxx = w * xx, wyy = w * yy, wzz = w * zz, wxy = w * xy;
+    const T x = a[0], y = a[1], z = a[2];
+    const T xx = x * x, yy = y * y, zz = z * z;
+    const T xy = a[6], xz = a[7], yz = a[8];
+    const T wxx = w * xx, wyy = w * yy, wzz = w * zz, wxy = w * xy;
     M[0] += wxx;
     M[1] += wyy;
     M[2] += wzz;
@@ -447,33 +447,33 @@ __device__ __forceinline__ void moments_add(double (&M)[31], const double* a,
     M[30] += wzz * xy;
 }
 
-__device__ __forceinline__ void gram_from_moments(const double (&M)[31],
-                                                  double (&G)[45])
+template <class T>
+__device__ __forceinline__ void gram_from_moments(const T (&M)[31], T (&G)[45])
 {
     // row 0: x
     G[uix(0, 0)] = M[0];  G[uix(0, 1)] = M[3];  G[uix(0, 2)] = M[4];
-    G[uix(0, 3)] = 0.5 * M[6];  G[uix(0, 4)] = 0.5 * M[11];
-    G[uix(0, 5)] = 0.5 * M[13]; G[uix(0, 6)] = M[9];  G[uix(0, 7)] = M[10];
+    G[uix(0, 3)] = T(0.5) * M[6];  G[uix(0, 4)] = T(0.5) * M[11];
+    G[uix(0, 5)] = T(0.5) * M[13]; G[uix(0, 6)] = M[9];  G[uix(0, 7)] = M[10];
     G[uix(0, 8)] = M[15];
     // row 1: y
-    G[uix(1, 1)] = M[1];  G[uix(1, 2)] = M[5];  G[uix(1, 3)] = 0.5 * M[9];
-    G[uix(1, 4)] = 0.5 * M[7];  G[uix(1, 5)] = 0.5 * M[14];
+    G[uix(1, 1)] = M[1];  G[uix(1, 2)] = M[5];  G[uix(1, 3)] = T(0.5) * M[9];
+    G[uix(1, 4)] = T(0.5) * M[7];  G[uix(1, 5)] = T(0.5) * M[14];
     G[uix(1, 6)] = M[11]; G[uix(1, 7)] = M[15]; G[uix(1, 8)] = M[12];
     // row 2: z
-    G[uix(2, 2)] = M[2];  G[uix(2, 3)] = 0.5 * M[10]; G[uix(2, 4)] = 0.5 * M[12];
-    G[uix(2, 5)] = 0.5 * M[8];  G[uix(2, 6)] = M[15]; G[uix(2, 7)] = M[13];
+    G[uix(2, 2)] = M[2];  G[uix(2, 3)] = T(0.5) * M[10]; G[uix(2, 4)] = T(0.5) * M[12];
+    G[uix(2, 5)] = T(0.5) * M[8];  G[uix(2, 6)] = M[15]; G[uix(2, 7)] = M[13];
     G[uix(2, 8)] = M[14];
     // row 3: x^2/2
-    G[uix(3, 3)] = 0.25 * M[16]; G[uix(3, 4)] = 0.25 * M[19];
-    G[uix(3, 5)] = 0.25 * M[20]; G[uix(3, 6)] = 0.5 * M[22];
-    G[uix(3, 7)] = 0.5 * M[23];  G[uix(3, 8)] = 0.5 * M[28];
+    G[uix(3, 3)] = T(0.25) * M[16]; G[uix(3, 4)] = T(0.25) * M[19];
+    G[uix(3, 5)] = T(0.25) * M[20]; G[uix(3, 6)] = T(0.5) * M[22];
+    G[uix(3, 7)] = T(0.5) * M[23];  G[uix(3, 8)] = T(0.5) * M[28];
     // row 4: y^2/2
-    G[uix(4, 4)] = 0.25 * M[17]; G[uix(4, 5)] = 0.25 * M[21];
-    G[uix(4, 6)] = 0.5 * M[24];  G[uix(4, 7)] = 0.5 * M[29];
-    G[uix(4, 8)] = 0.5 * M[25];
+    G[uix(4, 4)] = T(0.25) * M[17]; G[uix(4, 5)] = T(0.25) * M[21];
+    G[uix(4, 6)] = T(0.5) * M[24];  G[uix(4, 7)] = T(0.5) * M[29];
+    G[uix(4, 8)] = T(0.5) * M[25];
     // row 5: z^2/2
-    G[uix(5, 5)] = 0.25 * M[18]; G[uix(5, 6)] = 0.5 * M[30];
-    G[uix(5, 7)] = 0.5 * M[26];  G[uix(5, 8)] = 0.5 * M[27];
+    G[uix(5, 5)] = T(0.25) * M[18]; G[uix(5, 6)] = T(0.5) * M[30];
+    G[uix(5, 7)] = T(0.5) * M[26];  G[uix(5, 8)] = T(0.5) * M[27];
     // rows 6-8: xy, xz, yz
     G[uix(6, 6)] = M[19]; G[uix(6, 7)] = M[28]; G[uix(6, 8)] = M[29];
     G[uix(7, 7)] = M[20]; G[uix(7, 8)] = M[30];
@@ -861,6 +861,234 @@ __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
     finish_rhs(v, prm, i, hv, gP, gE, o);
 }
 
+// ---- refined FP32 fits ----------------------------------------------------
+//
+// The Gram moments and right-hand sides are accumulated and factored in
+// float32; one sweep then forms the float64 residual r = b - A c of every
+// row and corrects c by the float32 factor applied to A^T r.  The factor
+// (45 floats) is kept for pass 2, which refines the same way.  A stencil
+// whose float32 pivot ratio falls below the refit threshold takes the
+// float64 Householder refit of the float64 path.
+
+template <int N>
+__device__ __forceinline__ void store_factor(const float (&U)[45], float* uf, int64_t n,
+                                             int64_t i)
+{
+#pragma unroll
+    for (int q = 0; q < 45; ++q) uf[(int64_t)q * n + i] = U[q];
+}
+
+__device__ __forceinline__ void load_factor(float (&U)[45], const float* uf, int64_t n,
+                                            int64_t i)
+{
+#pragma unroll
+    for (int q = 0; q < 45; ++q) U[q] = uf[(int64_t)q * n + i];
+}
+
+// c += U^-1 U^-T d (the correction step), d in float64, solved in float32
+template <int N, int NF>
+__device__ __forceinline__ void refine_step(const float (&U)[45], const double (&d)[NF][9],
+                                            double (&c)[NF][9])
+{
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        float e[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) e[q] = q < N ? (float)d[f][q] : 0.0f;
+        chol_solve<N>(U, e);
+#pragma unroll
+        for (int q = 0; q < N; ++q) c[f][q] += (double)e[q];
+    }
+}
+
+__global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float* uf,
+                                                        int32_t* redo,
+                                                        unsigned int* redo_n)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= v.n) return;
+    const int64_t n = v.n;
+    const int s = sys_of(v.off, v.n_sys, i);
+    const GridInfo& g = v.grid[s];
+    const Rec r = load_rec(v, i);
+    const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
+    // ---- float32 moments and right-hand sides
+    float M[31], B[3][9];
+#pragma unroll
+    for (int q = 0; q < 31; ++q) M[q] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) B[0][q] = B[1][q] = B[2][q] = 0.0f;
+    const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+        float af[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) af[q] = (float)a[q];
+        moments_add(M, af, (float)w);
+        if (!p) return;
+        double uj, vj, wj;
+        point_velocity(v, *p, uj, vj, wj);
+        const float b0 = (float)(w * (uj - ui)), b1 = (float)(w * (vj - vi)),
+                    b2 = (float)(w * (wj - wi));
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            B[0][q] += af[q] * b0;
+            B[1][q] += af[q] * b1;
+            B[2][q] += af[q] * b2;
+        }
+    });
+    float U[45];
+    gram_from_moments(M, U);
+    const bool lin = mt < 9;
+    const float ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
+    if (!(ratio >= (float)v.redo_ratio)) {
+        redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
+        o.flags[i] = FLAG_QR;
+        return;
+    }
+    double c[3][9];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        float e[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) e[q] = (lin && q >= 3) ? 0.0f : B[f][q];
+        if (lin) chol_solve<3>(U, e);
+        else chol_solve<9>(U, e);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) c[f][q] = (lin && q >= 3) ? 0.0 : (double)e[q];
+    }
+    // the factor goes to memory: pass 2 needs it, and it is dead here
+    // until the correction
+    if (lin) store_factor<3>(U, uf, n, i);
+    else store_factor<9>(U, uf, n, i);
+    // ---- float64 residual sweep: d = A^T W (b - A c)
+    double d[3][9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) d[0][q] = d[1][q] = d[2][q] = 0.0;
+    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0;   // ghosts carry u_i
+        if (p) {
+            double uj, vj, wj;
+            point_velocity(v, *p, uj, vj, wj);
+            b0 = uj - ui;
+            b1 = vj - vi;
+            b2 = wj - wi;
+        }
+        double r0 = b0, r1 = b1, r2 = b2;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            r0 -= a[q] * c[0][q];
+            r1 -= a[q] * c[1][q];
+            r2 -= a[q] * c[2][q];
+        }
+        r0 *= w;
+        r1 *= w;
+        r2 *= w;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            d[0][q] += a[q] * r0;
+            d[1][q] += a[q] * r1;
+            d[2][q] += a[q] * r2;
+        }
+    });
+    load_factor(U, uf, n, i);
+    if (lin) refine_step<3, 3>(U, d, c);
+    else refine_step<9, 3>(U, d, c);
+    double cs[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q)
+        cs[q] = c[q / 9][q % 9] * ((q % 9) < 3 ? g.inv_h : g.inv_h * g.inv_h);
+    const double none[27] = {};
+    finish_pass1(v, v.prm[s], i, cs, none, false, lin ? FLAG_LINEAR : 0, o);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pass2_ref(View v, const double* P,
+                                                     const double* eta,
+                                                     const double* hand,
+                                                     const float* uf,
+                                                     const uint8_t* flags, RhsOut o)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= v.n) return;
+    const uint8_t fl = flags[i];
+    if (fl & FLAG_QR) return;
+    const int64_t n = v.n;
+    const int s = sys_of(v.off, v.n_sys, i);
+    const GridInfo& g = v.grid[s];
+    const lp_params& prm = v.prm[s];
+    const Rec r = load_rec(v, i);
+    const bool lin = fl & FLAG_LINEAR;
+    const double Pi = P[i], Ei = eta[i];
+    // ---- float32 right-hand sides and solve
+    float yP[9], yE[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) yP[q] = yE[q] = 0.0f;
+    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+        double Pj, Ej;
+        pass2_values(v, P, eta, p, prm, Pj, Ej);
+        const float bP = (float)(w * (Pj - Pi)), bE = (float)(w * (Ej - Ei));
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const float aq = (float)a[q];
+            yP[q] += aq * bP;
+            yE[q] += aq * bE;
+        }
+    });
+    float U[45];
+    load_factor(U, uf, n, i);
+    double c[2][9];
+    {
+        float e0[9], e1[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            e0[q] = (lin && q >= 3) ? 0.0f : yP[q];
+            e1[q] = (lin && q >= 3) ? 0.0f : yE[q];
+        }
+        if (lin) {
+            chol_solve<3>(U, e0);
+            chol_solve<3>(U, e1);
+        } else {
+            chol_solve<9>(U, e0);
+            chol_solve<9>(U, e1);
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            c[0][q] = (lin && q >= 3) ? 0.0 : (double)e0[q];
+            c[1][q] = (lin && q >= 3) ? 0.0 : (double)e1[q];
+        }
+    }
+    // ---- float64 residual sweep and correction
+    double d[2][9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) d[0][q] = d[1][q] = 0.0;
+    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+        double Pj, Ej;
+        pass2_values(v, P, eta, p, prm, Pj, Ej);
+        double rP = Pj - Pi, rE = Ej - Ei;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            rP -= a[q] * c[0][q];
+            rE -= a[q] * c[1][q];
+        }
+        rP *= w;
+        rE *= w;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            d[0][q] += a[q] * rP;
+            d[1][q] += a[q] * rE;
+        }
+    });
+    if (lin) refine_step<3, 2>(U, d, c);
+    else refine_step<9, 2>(U, d, c);
+    double gP[3], gE[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        gP[q] = c[0][q] * g.inv_h;
+        gE[q] = c[1][q] * g.inv_h;
+    }
+    double hv[11];
+    load_hand_tail(hand, n, i, Ei, hv);
+    finish_rhs(v, prm, i, hv, gP, gE, o);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_pass2_qr(View v, const double* P,
                                                     const double* eta,
                                                     const double* hand,
@@ -1011,8 +1239,12 @@ lp_status step_rhs(lp_ctx* c, const double* const st[7])
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
     if (n > 0) {
         prof_mark(c, 3, false);
-        hipLaunchKernelGGL(k_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
-                           v, so, w.redo, w.redo_n, fq);
+        if (c->cfg.precision == LP_FP32_REFINED && !fq)
+            hipLaunchKernelGGL(k_pass1_ref, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, so, w.uf, w.redo, w.redo_n);
+        else
+            hipLaunchKernelGGL(k_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
+                               v, so, w.redo, w.redo_n, fq);
         prof_mark(c, 3, true);
         prof_mark(c, 4, false);
         hipLaunchKernelGGL(k_pass1_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
@@ -1036,9 +1268,15 @@ lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
     o.dt = dt;
     if (n > 0) {
         prof_mark(c, 5, false);
-        hipLaunchKernelGGL(k_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
-                           v, (const double*)w.P, (const double*)w.eta,
-                           (const double*)w.hand, (const uint8_t*)w.flags, o);
+        if (c->cfg.precision == LP_FP32_REFINED)
+            hipLaunchKernelGGL(k_pass2_ref, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, (const double*)w.P, (const double*)w.eta,
+                               (const double*)w.hand, (const float*)w.uf,
+                               (const uint8_t*)w.flags, o);
+        else
+            hipLaunchKernelGGL(k_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
+                               v, (const double*)w.P, (const double*)w.eta,
+                               (const double*)w.hand, (const uint8_t*)w.flags, o);
         prof_mark(c, 5, true);
         prof_mark(c, 6, false);
         hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,

@@ -146,6 +146,7 @@ struct Work {
     double* qr_scratch = nullptr;         // QR_SLOTS x MAXROWS x (9 + 8)
     double *P = nullptr, *eta = nullptr;
     double* hand = nullptr;               // HAND x n
+    float* uf = nullptr;                  // 45 x n float32 factors (refined mode)
     double* acc = nullptr;                // 3 x n
     double* dVdt = nullptr;
     uint8_t* flags = nullptr;
