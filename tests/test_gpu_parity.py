@@ -13,6 +13,7 @@ import pytest
 
 import lpgen
 import oracle
+from cases import CASES
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -30,43 +31,6 @@ def lp():
     import paper_2206_14061_amd as lp_mod
     lp_mod._lib.load()
     return lp_mod
-
-
-def _with_flow(wl):
-    """Smooth velocities and a density field visiting all three regimes."""
-    st = wl.state
-    st.u = 0.3 * np.sin(3.1 * st.y / wl.params[0].h * 0.0625 + 1.0) * np.cos(2.0 * st.z)
-    st.v = 0.2 * np.cos(2.3 * st.x) * np.sin(1.7 * st.z + 0.4)
-    st.w = 0.25 * np.sin(2.9 * st.x + 1.1 * st.y)
-    st.V = 1.0 / (0.47 + 0.15 * np.sin(4.0 * st.z / (wl.params[0].h * 16) + 2.0 * st.y))
-    return wl
-
-
-def _ragged(wl, drop=37):
-    """Drops `drop` seeded particles so the count is not a tile multiple."""
-    rng = np.random.default_rng(5)
-    keep = np.sort(rng.choice(wl.n, wl.n - drop, replace=False))
-    wl.state = wl.state.take(keep)
-    wl.offsets = np.array([0, wl.state.n])
-    return wl
-
-
-def _exact_lattice(nx=12, ny=10, nz=9):
-    """Unjittered lattice: many exactly equal distances, so every stencil
-    cut is decided by the id tie-break."""
-    h = 1.0 / 16.0
-    p = lpgen.default_params(h)
-    st = lpgen.lattice_column(nx, ny, nz, h, seed=7, jitter=0.0, params=p)
-    return lpgen.Workload("lattice_exact", st, np.array([0, st.n]), [p], 1e-4, 1)
-
-
-CASES = {
-    "column16": lambda: lpgen.column_small(),
-    "lattice_exact": lambda: _with_flow(_exact_lattice()),
-    "column16_flow_ragged": lambda: _ragged(_with_flow(lpgen.column_small())),
-    "sheared_20x20x12": lambda: lpgen.column_sheared(nx=20, ny=20, nz=12),
-    "ensemble_3": lambda: _with_flow(lpgen.ensemble(n_sys=3, n_lo=600, n_hi=3000)),
-}
 
 
 def _relerr(a, b):

@@ -8,7 +8,8 @@ import pytest
 
 import lpgen
 import oracle
-from test_gpu_parity import (CASES, _incr_ok, _log, _relerr, _trajectory_gpu,
+from cases import CASES
+from test_gpu_parity import (_incr_ok, _log, _relerr, _trajectory_gpu,
                              _trajectory_oracle, lp)  # noqa: F401
 
 pytestmark = pytest.mark.gpu
