@@ -212,9 +212,28 @@ lp_status lp_rheology_rhs(lp_ctx* ctx, const lp_state* s,
  * dt > 0.  A non-finite result latches LP_E_NUMERIC (lp_sync_status). */
 lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
 
-/* Adjoint of lp_step (not available in this version: returns
- * LP_E_STATE). */
-lp_status lp_step_adjoint(lp_ctx* ctx);
+/* Adjoint (reverse-mode derivative) of one step, for gradients of a loss
+ * through the method (Sec. 3.1 steps 5-10 with the closure of Sec. 2.2 and
+ * 2.2.1 and the right-hand side of Sec. 2.1).  The step differentiated is
+ * lp_build_cells followed by lp_step on s: s is re-sorted by the context's
+ * cells (perm[new] = old, written to perm if not null), then stepped.  Its
+ * stencils, ghost masks, linear-fallback choices and regime branches are
+ * held fixed (they are piecewise constant in the state); the shear-rate
+ * norm is given zero derivative where it is zero.
+ *   s:          the state before the step (device, caller's order; read);
+ *   adj_out:    dL/d(state after the step), in the step's output order;
+ *   adj_in:     receives dL/d(s) in s's order (overwritten; must not
+ *               alias adj_out or s);
+ *   adj_params: device double[n_sys x 3], dL/d(mu_s, mu_2, I0) per system
+ *               is ADDED to it.
+ * Computes in float64 whatever the precision setting; requires unit
+ * weights (LP_E_ARG otherwise).  Neighbour contributions are accumulated
+ * with float64 atomics (summation order varies between runs).  Leaves the
+ * context without a neighbour list: the next lp_step rebuilds.  A
+ * degenerate Gram matrix latches LP_E_NUMERIC (lp_sync_status). */
+lp_status lp_step_adjoint(lp_ctx* ctx, const lp_state* s, double dt,
+                          const lp_state* adj_out, lp_state* adj_in,
+                          double* adj_params, int32_t* perm);
 
 /* Synchronises the context's stream and returns the first latched device
  * error (LP_OK if none), then clears it.  *index (host, optional)

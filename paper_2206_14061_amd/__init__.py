@@ -210,8 +210,20 @@ class Context:
         s = st.struct()
         self._check(self.lib.lp_step(self.h, C.byref(s), float(dt), _ptr(perm)))
 
-    def lp_step_adjoint(self):
-        self._check(self.lib.lp_step_adjoint(self.h))
+    def lp_step_adjoint(self, st: DeviceState, dt: float, adj_out: DeviceState,
+                        adj_params=None, want_perm: bool = False):
+        """Reverse of lp_build_cells + lp_step at st: returns dL/d(st) for
+        dL/d(output) = adj_out (and the permutation, if asked); adds
+        dL/d(mu_s, mu_2, I0) into adj_params (n_sys x 3, float64, device)."""
+        torch = _torch()
+        adj_in = DeviceState([torch.empty_like(a) for a in st.t])
+        if adj_params is None:
+            adj_params = torch.zeros(self.n_sys, 3, dtype=torch.float64, device="cuda")
+        perm = torch.empty(st.n, dtype=torch.int32, device="cuda") if want_perm else None
+        s, ao, ai = st.struct(), adj_out.struct(), adj_in.struct()
+        self._check(self.lib.lp_step_adjoint(self.h, C.byref(s), float(dt), C.byref(ao),
+                                             C.byref(ai), _ptr(adj_params), _ptr(perm)))
+        return (adj_in, perm) if want_perm else adj_in
 
     def sync_status(self):
         idx = C.c_int64(-1)

@@ -91,7 +91,8 @@ def load():
     lib.lp_rheology_rhs.restype = C.c_int
     lib.lp_step.argtypes = [P, pp(LPState), C.c_double, P]
     lib.lp_step.restype = C.c_int
-    lib.lp_step_adjoint.argtypes = [P]
+    lib.lp_step_adjoint.argtypes = [P, pp(LPState), C.c_double, pp(LPState),
+                                    pp(LPState), P, P]
     lib.lp_step_adjoint.restype = C.c_int
     lib.lp_sync_status.argtypes = [P, pp(C.c_int64)]
     lib.lp_sync_status.restype = C.c_int

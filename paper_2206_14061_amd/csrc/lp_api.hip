@@ -75,7 +75,9 @@ void free_work(Work& w)
     f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
     f(w.vl); f(w.vcnt); f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
     f(w.redo); f(w.redo_n); f(w.qr_scratch);
-    f(w.P); f(w.eta); f(w.hand); f(w.uf); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
+    f(w.P); f(w.eta); f(w.hand); f(w.uf);
+    for (int a = 0; a < 7; ++a) f(w.adj[a]);
+    f(w.adj_P); f(w.adj_E); f(w.adj_stash); f(w.coefu); f(w.adj_perm); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
     w.n_max = w.cells_max = 0;
@@ -207,6 +209,9 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.qr_scratch, (int64_t)QR_SLOTS * MAXROWS * 17);
     A(w.P, n_max); A(w.eta, n_max); A(w.hand, (int64_t)HAND * n_max);
     A(w.uf, (int64_t)45 * n_max);
+    for (int a = 0; a < 7; ++a) A(w.adj[a], n_max);
+    A(w.adj_P, n_max); A(w.adj_E, n_max); A(w.adj_stash, (int64_t)11 * n_max);
+    A(w.coefu, (int64_t)27 * n_max); A(w.adj_perm, n_max);
     A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
     A(w.coff, n_max + 1);
     if (e == hipSuccess) e = hipHostMalloc((void**)&w.h_summary, sizeof(Summary));
@@ -428,10 +433,45 @@ lp_status lp_profile_read(lp_ctx* c, double* ms8, int64_t* steps)
     return LP_OK;
 }
 
-lp_status lp_step_adjoint(lp_ctx* c)
+lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
+                          const lp_state* adj_out, lp_state* adj_in,
+                          double* adj_params, int32_t* perm)
 {
-    if (c) c->err = "lp_step_adjoint is not available in this version";
-    return LP_E_STATE;
+    if (!s || !adj_out || !adj_in || !adj_params || !(dt > 0.0) || !std::isfinite(dt)) {
+        if (c) c->err = "lp_step_adjoint: null argument or dt not positive";
+        return LP_E_ARG;
+    }
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    if (c->cfg.weight != LP_W_UNIT) {
+        c->err = "lp_step_adjoint supports unit weights only";
+        return LP_E_ARG;
+    }
+    double* in[7];
+    state_arrays(s, in);
+    r = cells_build(c, in, c->w.adj_perm);
+    const double* sorted[7];
+    for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
+    if (r == LP_OK) r = stencils_build(c, sorted);
+    if (r == LP_OK) r = step_pass1_coef(c, sorted);
+    double* lam_in[7];
+    double* out[7];
+    state_arrays(adj_out, lam_in);
+    state_arrays(adj_in, out);
+    const double* lam[7];
+    for (int a = 0; a < 7; ++a) lam[a] = lam_in[a];
+    if (r == LP_OK)
+        r = step_adjoint(c, sorted, dt, lam, out, adj_params, c->w.adj_perm);
+    if (r == LP_OK && perm) {
+        hipError_t e = hipMemcpyAsync(perm, c->w.adj_perm, sizeof(int32_t) * c->n,
+                                      hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) r = hip_fail(c, e, "adjoint perm copy");
+    }
+    // the working state now belongs to this call: the next lp_step rebuilds
+    c->list_ok = false;
+    c->stencils_ok = false;
+    c->built_x = nullptr;
+    return r;
 }
 
 lp_status lp_sync_status(lp_ctx* c, int64_t* index)

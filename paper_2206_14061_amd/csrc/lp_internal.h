@@ -147,6 +147,13 @@ struct Work {
     double *P = nullptr, *eta = nullptr;
     double* hand = nullptr;               // HAND x n
     float* uf = nullptr;                  // 45 x n float32 factors (refined mode)
+    // adjoint
+    double* adj[7] = {nullptr};           // state cotangent accumulators
+    double* adj_P = nullptr;
+    double* adj_E = nullptr;
+    double* adj_stash = nullptr;          // 11 x n
+    double* coefu = nullptr;              // 27 x n forward velocity coefficients
+    int32_t* adj_perm = nullptr;
     double* acc = nullptr;                // 3 x n
     double* dVdt = nullptr;
     uint8_t* flags = nullptr;
@@ -290,6 +297,14 @@ lp_status rhs_from_coef(lp_ctx* c, const double* const st[7],
                         const double* coef_u, double* dVdt, double* acc,
                         double* diag, double* grad, uint8_t* flags);
 lp_status step_rhs(lp_ctx* c, const double* const st[7]);
+// pass 1 in float64 with the velocity coefficients stored (adjoint input)
+lp_status step_pass1_coef(lp_ctx* c, const double* const st[7]);
+// reverse of the step on the sorted state st (after step_pass1_coef);
+// lam: cotangent of the step's output (sorted order); out: cotangent of
+// the input in its order (perm[new] = old); dparams += parameter cotangents
+lp_status step_adjoint(lp_ctx* c, const double* const st[7], double dt,
+                       const double* const lam[7], double* const out[7],
+                       double* dparams, const int32_t* perm);
 lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
                       double* const out[7]);
 View make_view(lp_ctx* c, const double* const st[7]);

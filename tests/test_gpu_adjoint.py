@@ -1,0 +1,123 @@
+"""GPU parity of lp_step_adjoint against the FP64 adjoint oracle
+(oracle/adjoint.py, itself pinned by central differences of the C oracle),
+and of the checkpointed trajectory gradient against the composed oracle
+adjoint.  Arrays agree within 1e-10 of the largest oracle entry (FP64; the
+GPU accumulates neighbour contributions with atomics)."""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from cases import CASES
+from oracle import adjoint
+from test_gpu_parity import _log, _relerr, lp  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _lam(wl, seed):
+    rng = np.random.default_rng(seed)
+    n, h = wl.n, wl.params[0].h
+    return [h * rng.standard_normal(n) for _ in range(3)] + \
+           [0.1 * rng.standard_normal(n) for _ in range(3)] + \
+           [0.01 * rng.standard_normal(n)]
+
+
+def _dev(arrs):
+    import torch
+    import paper_2206_14061_amd as lpm
+    return lpm.DeviceState([torch.tensor(np.ascontiguousarray(a), device="cuda")
+                            for a in arrs])
+
+
+@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
+                                  "ensemble_3", "lattice_exact"])
+def test_step_adjoint_parity(lp, case):
+    import torch
+    wl = CASES[case]()
+    _log("case %s n=%d (adjoint)" % (case, wl.n))
+    lam = _lam(wl, 41)
+    want, wth, operm = adjoint.step_vjp(wl.state, wl.offsets, wl.params, wl.dt, lam)
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    dth = torch.zeros(len(wl.params), 3, dtype=torch.float64, device="cuda")
+    got, perm = ctx.lp_step_adjoint(st, wl.dt, _dev(lam), dth, want_perm=True)
+    ctx.sync_status()
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    for k, (a, b) in enumerate(zip(got.to_host().arrays(), want)):
+        e = _relerr(a, b)
+        _log("  d/d%s rel err %.3e" % (lp.DeviceState.NAMES[k], e))
+        assert e <= TOL, (lp.DeviceState.NAMES[k], e)
+    gth = dth.cpu().numpy()
+    e = np.max(np.abs(gth - wth)) / max(np.max(np.abs(wth)), 1e-300)
+    _log("  d/dtheta rel err %.3e (max |dtheta| %.3e)" % (e, np.max(np.abs(wth))))
+    assert e <= 1e-9
+
+
+def test_step_adjoint_dot_product_with_gpu_differences(lp):
+    """<lam, J v> by central differences of the GPU step (lp_build_cells +
+    lp_step) against <J^T lam, v> from lp_step_adjoint, for directions in
+    the velocities and volumes (no structural change under them)."""
+    import torch
+    wl = CASES["column16_flow_ragged"]()
+    rng = np.random.default_rng(3)
+    lam = _lam(wl, 43)
+    v = [np.zeros(wl.n)] * 3 + [0.1 * rng.standard_normal(wl.n) for _ in range(3)] + \
+        [0.01 * wl.state.V * rng.standard_normal(wl.n)]
+    ctx = lp.make_context(wl)
+
+    def fwd(eps):
+        st = _dev([a + eps * d for a, d in zip(wl.state.arrays(), v)])
+        ctx.lp_build_cells(st, want_perm=False)
+        ctx.lp_step(st, wl.dt)
+        return st.to_host().arrays()
+
+    eps = 1e-6
+    fp, fm = fwd(eps), fwd(-eps)
+    fd = sum(float(np.dot(l, (a - b) / (2 * eps))) for l, a, b in zip(lam, fp, fm))
+    st = lp.DeviceState.from_host(wl.state)
+    g = ctx.lp_step_adjoint(st, wl.dt, _dev(lam)).to_host().arrays()
+    ad = sum(float(np.dot(a, d)) for a, d in zip(g, v))
+    ctx.sync_status()
+    _log("  fd %.12e ad %.12e" % (fd, ad))
+    assert abs(fd - ad) <= 1e-6 * abs(fd)
+
+
+def test_trajectory_gradient_matches_composed_oracle_adjoint(lp):
+    """Four steps with checkpoints every two, runout loss
+    L = sum softplus((x - x*)/h): gradients with respect to the initial
+    state and (mu_s, mu_2, I0) from torch.autograd over the library's
+    adjoint, against the oracle's step adjoints composed in reverse."""
+    import torch
+    from paper_2206_14061_amd.autograd import simulate
+    wl = CASES["column16_flow_ragged"]()
+    h, xs, steps = wl.params[0].h, 0.6, 4
+    ctx = lp.make_context(wl)
+    state = [torch.tensor(a, device="cuda", requires_grad=True)
+             for a in wl.state.arrays()]
+    theta = torch.tensor(adjoint.theta_of(wl.params), device="cuda", requires_grad=True)
+    out = simulate(ctx, wl.offsets, wl.params, state, theta, wl.dt, steps,
+                   checkpoint_every=2)
+    loss = torch.nn.functional.softplus((out[0] - xs) / h).sum()
+    loss.backward()
+    ctx.sync_status()
+    # oracle: forward states, then reverse
+    st, states = wl.state, []
+    for _ in range(steps):
+        states.append(st)
+        st, _, _ = oracle.step(st, wl.offsets, wl.params, wl.dt)
+    t = (st.x - xs) / h
+    lamo = [1.0 / (1.0 + np.exp(-t)) / h] + [np.zeros(wl.n) for _ in range(6)]
+    gth = np.zeros((1, 3))
+    for s in reversed(states):
+        lamo, g, _ = adjoint.step_vjp(s, wl.offsets, wl.params, wl.dt, lamo)
+        gth += g
+    assert abs(loss.item() - float(np.sum(np.logaddexp(0.0, t)))) <= 1e-9 * loss.item()
+    for k, (a, b) in enumerate(zip(state, lamo)):
+        e = _relerr(a.grad.cpu().numpy(), b)
+        _log("  dL/d%s0 rel err %.3e" % (lp.DeviceState.NAMES[k], e))
+        assert e <= 1e-9
+    e = np.max(np.abs(theta.grad.cpu().numpy() - gth)) / np.max(np.abs(gth))
+    _log("  dL/dtheta rel err %.3e" % e)
+    assert e <= 1e-8

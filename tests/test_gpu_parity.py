@@ -346,8 +346,12 @@ def test_error_paths_report_cleanly(lp):
         ctx.lp_neighbors(st)
     assert e.value.status == 5
     with pytest.raises(lp.LPError) as e:
-        ctx.lp_step_adjoint()
-    assert e.value.status == 5
+        ctx.lp_step_adjoint(st, -1.0, st)
+    assert e.value.status == 1
+    gauss = lp.make_context(wl, weight=lp.LP_W_GAUSS)
+    with pytest.raises(lp.LPError) as e:
+        gauss.lp_step_adjoint(st, 1e-4, st)
+    assert e.value.status == 1
     small = lp.Context()
     small.reserve(100)
     with pytest.raises(lp.LPError) as e:
