@@ -10,9 +10,11 @@ mu(I) closure, fit of P and eta, right-hand side and explicit update.
 The state is resident in HBM before the timed region; K consecutive steps
 are timed between device synchronisations.
 
-Printed (one JSON line): particle-updates/s, the dominant kernel's
-achieved rate against the FP64 vector roof (phase events on the library's
-stream), and the FP64 CPU oracle timed on the host as a baseline.
+Printed (one JSON line): particle-updates/s in FP64 (and the refined-FP32
+mode beside it), the dominant kernel's achieved rate against the FP64
+vector roof (phase events on the library's stream), adjoint step-pairs/s
+of a 50-step gradient on the 131,072-particle column, and the FP64 CPU
+oracle timed on the host as a baseline.
 """
 from __future__ import annotations
 
@@ -52,6 +54,8 @@ def _parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--adjoint-steps", type=int, default=50)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three 1 GiB device-to-device copies, the "
                          "reference for the HBM byte counters")
@@ -92,6 +96,47 @@ def pass1_traffic():
         return None
     return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"]
                      + rec["write_kib"] * rec["write_scale"])
+
+
+def adjoint_bench(torch, lp, lpgen, steps: int, warmup: int = 1):
+    """Gradient of the runout loss L = sum softplus((x - 0.3 m)/h) after
+    `steps` steps of the 32 x 32 x 128 column (131,072 particles, dt =
+    5e-5 s) with respect to the initial state and (mu_s, mu_2, I0), with a
+    checkpoint every 10 steps: forward with checkpoints, then recompute and
+    reverse.  Returns adjoint step-pairs/s and the split."""
+    from paper_2206_14061_amd.autograd import simulate
+    wl = lpgen.column_adjoint()
+    h = wl.params[0].h
+    ctx = lp.make_context(wl)
+    theta0 = [[p.mu_s, p.mu_2, p.I0] for p in wl.params]
+
+    def once():
+        state = [torch.tensor(a, device="cuda", requires_grad=True)
+                 for a in wl.state.arrays()]
+        theta = torch.tensor(theta0, dtype=torch.float64, device="cuda",
+                             requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = simulate(ctx, wl.offsets, wl.params, state, theta, wl.dt, steps,
+                       checkpoint_every=10)
+        loss = torch.nn.functional.softplus((out[0] - 0.3) / h).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ctx.sync_status()
+        return t1 - t0, t2 - t1, loss.item(), theta.grad, state[3].grad
+
+    for _ in range(warmup):
+        once()
+    tf, tb, loss, gth, gu = once()
+    return {"workload": wl.name, "particles": wl.n, "steps": steps,
+            "checkpoint_every": 10, "dt": wl.dt,
+            "step_pairs_per_s": steps / (tf + tb),
+            "ms_forward": 1e3 * tf, "ms_backward": 1e3 * tb, "loss": loss,
+            "dL_dtheta": gth.cpu().tolist(),
+            "max_abs_dL_du0": float(gu.abs().max().item())}
 
 
 def copy_calibration(torch):
@@ -202,6 +247,8 @@ def main():
            "phases_ms": phases, "stats": stats, "other_precision": compare,
            "ms_per_step_rebuild_every_step": ms_rebuild,
            "roofline": roof}
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     if args.copy_calibration:
