@@ -212,6 +212,24 @@ lp_status lp_rheology_rhs(lp_ctx* ctx, const lp_state* s,
  * dt > 0.  A non-finite result latches LP_E_NUMERIC (lp_sync_status). */
 lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
 
+/* nsteps consecutive lp_step calls as one HIP graph, for callers that
+ * replay fixed step sequences without host work between steps.  Every
+ * step decides on the device whether to re-sort and rebuild its neighbour
+ * list (same rule as lp_step) and synchronises nothing.  The sequence is
+ * captured on the first call (on a stream the library creates) and
+ * replayed on the context's stream by later calls with the same state
+ * arrays, ids, dt and nsteps (any change recaptures; lp_reserve drops the
+ * capture).  ids (device int32[n], optional) are permuted along with the
+ * state at every re-sort, so they track particle identity.  If the
+ * context has no neighbour list, the state (and ids) are first re-sorted
+ * in place as by lp_build_cells.  Between re-sorts the grid keeps the bit
+ * budget it had at capture plus one bit per axis; beyond that cells are
+ * enlarged (same results, more candidates tested).  dt > 0,
+ * 1 <= nsteps <= 4096.  Asynchronous; device errors latch as for lp_step
+ * (lp_sync_status). */
+lp_status lp_step_graph(lp_ctx* ctx, lp_state* s, int32_t* ids, double dt,
+                        int32_t nsteps);
+
 /* Adjoint (reverse-mode derivative) of one step, for gradients of a loss
  * through the method (Sec. 3.1 steps 5-10 with the closure of Sec. 2.2 and
  * 2.2.1 and the right-hand side of Sec. 2.1).  The step differentiated is

@@ -210,6 +210,13 @@ class Context:
         s = st.struct()
         self._check(self.lib.lp_step(self.h, C.byref(s), float(dt), _ptr(perm)))
 
+    def lp_step_graph(self, st: DeviceState, dt: float, nsteps: int, ids=None):
+        """nsteps steps replayed as one HIP graph (captured on first use);
+        ids (int32 device tensor, optional) follow the particles."""
+        s = st.struct()
+        self._check(self.lib.lp_step_graph(self.h, C.byref(s), _ptr(ids), float(dt),
+                                           int(nsteps)))
+
     def lp_step_adjoint(self, st: DeviceState, dt: float, adj_out: DeviceState,
                         adj_params=None, want_perm: bool = False):
         """Reverse of lp_build_cells + lp_step at st: returns dL/d(st) for

@@ -77,7 +77,8 @@ void free_work(Work& w)
     f(w.redo); f(w.redo_n); f(w.qr_scratch);
     f(w.P); f(w.eta); f(w.hand); f(w.uf);
     for (int a = 0; a < 7; ++a) f(w.adj[a]);
-    f(w.adj_P); f(w.adj_E); f(w.adj_stash); f(w.coefu); f(w.adj_perm); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
+    f(w.adj_P); f(w.adj_E); f(w.adj_stash); f(w.coefu); f(w.adj_perm);
+    f(w.gate); f(w.ids_tmp); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
     w.n_max = w.cells_max = 0;
@@ -114,6 +115,32 @@ void state_arrays(const lp_state* s, double* st[7])
 {
     st[0] = s->x; st[1] = s->y; st[2] = s->z;
     st[3] = s->u; st[4] = s->v; st[5] = s->w; st[6] = s->V;
+}
+
+void drop_graph(lp_ctx* c)
+{
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
+// One step with no host synchronisation: device-side rebuild decision,
+// gated re-sort + list rebuild or state copy, stencils, fits, update into
+// the caller's arrays.
+lp_status step_device(lp_ctx* c, double* const in[7], int32_t* ids, double dt, int bits)
+{
+    const double* cin[7];
+    for (int a = 0; a < 7; ++a) cin[a] = in[a];
+    lp_status r = rebuild_decision(c, cin, c->cfg.skin > 0.0 ? 0 : 1);
+    if (r == LP_OK) r = cells_build_device(c, in, ids, c->w.gate, bits);
+    if (r == LP_OK) r = state_copy(c, in, nullptr, c->w.gate + 1);
+    const double* sorted[7];
+    for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
+    if (r == LP_OK) r = stencils_build(c, sorted);
+    if (r == LP_OK) r = step_rhs(c, sorted);
+    if (r == LP_OK) r = step_update(c, sorted, dt, in);
+    return r;
 }
 
 }  // namespace
@@ -165,6 +192,8 @@ void lp_destroy(lp_ctx* c)
 {
     if (!c) return;
     hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (int q = 0; q < 16; ++q)
         if (c->ev[q]) hipEventDestroy(c->ev[q]);
     free_work(c->w);
@@ -179,6 +208,7 @@ const char* lp_last_error(const lp_ctx* c)
 
 lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
 {
+    if (c) drop_graph(c);
     if (!c || n_max < 1 || cells_max < 1 || n_max >= (1ll << 27)) {
         if (c) c->err = "lp_reserve: n_max in [1, 2^27), cells_max >= 1";
         return LP_E_ARG;
@@ -212,6 +242,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     for (int a = 0; a < 7; ++a) A(w.adj[a], n_max);
     A(w.adj_P, n_max); A(w.adj_E, n_max); A(w.adj_stash, (int64_t)11 * n_max);
     A(w.coefu, (int64_t)27 * n_max); A(w.adj_perm, n_max);
+    A(w.gate, 4); A(w.ids_tmp, n_max);
     A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
     A(w.coff, n_max + 1);
     if (e == hipSuccess) e = hipHostMalloc((void**)&w.h_summary, sizeof(Summary));
@@ -433,6 +464,74 @@ lp_status lp_profile_read(lp_ctx* c, double* ms8, int64_t* steps)
     return LP_OK;
 }
 
+lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,
+                        int32_t nsteps)
+{
+    if (!s || !(dt > 0.0) || !std::isfinite(dt) || nsteps < 1 || nsteps > 4096) {
+        if (c) c->err = "lp_step_graph: dt > 0 and 1 <= nsteps <= 4096";
+        return LP_E_ARG;
+    }
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    double* in[7];
+    state_arrays(s, in);
+    Work& w = c->w;
+    if (!c->list_ok) {
+        // first build, eagerly, into the caller's arrays (as lp_build_cells)
+        r = cells_build(c, in, w.adj_perm);
+        if (r == LP_OK) r = state_write_back(c, in);
+        if (r == LP_OK && ids) r = permute_ids(c, w.adj_perm, ids);
+        if (r != LP_OK) return r;
+    }
+    const int bits = std::min(16, c->axis_bits + 1);
+    lp_ctx::GraphKey key{};
+    for (int a = 0; a < 7; ++a) key.st[a] = in[a];
+    key.ids = ids;
+    key.dt = dt;
+    key.nsteps = nsteps;
+    key.bits = bits;
+    key.n = c->n;
+    key.n_sys = c->n_sys;
+    if (!c->gexec || !(key == c->gkey)) {
+        drop_graph(c);
+        hipError_t e = hipSuccess;
+        if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(c, e, "capture stream");
+        hipStream_t saved = c->stream;
+        const bool prof = c->prof;
+        c->prof = false;
+        c->stream = c->cap_stream;
+        e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            c->stream = saved;
+            c->prof = prof;
+            return hip_fail(c, e, "begin capture");
+        }
+        for (int k = 0; k < nsteps && r == LP_OK; ++k) r = step_device(c, in, ids, dt, bits);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->cap_stream, &g);
+        c->stream = saved;
+        c->prof = prof;
+        if (r != LP_OK) {
+            if (g) hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "end capture");
+        c->graph = g;
+        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(c);
+            return hip_fail(c, e, "graph instantiate");
+        }
+        c->gkey = key;
+    }
+    hipError_t e = hipGraphLaunch(c->gexec, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+    c->stencils_ok = false;
+    c->built_x = nullptr;
+    return LP_OK;
+}
+
 lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
                           const lp_state* adj_out, lp_state* adj_in,
                           double* adj_params, int32_t* perm)
@@ -519,7 +618,7 @@ lp_status lp_stats(lp_ctx* c, int64_t* out8)
     out8[2] = (int64_t)k.qr_refits;
     out8[3] = (int64_t)k.hard_stencils;
     out8[4] = (int64_t)k.below_wall;
-    out8[5] = c->rebuilds;
+    out8[5] = c->rebuilds + (int64_t)k.rebuilds;
     c->rebuilds = 0;
     Counters z{};
     e = hipMemcpyAsync(c->w.cnt, &z, sizeof(z), hipMemcpyHostToDevice, c->stream);

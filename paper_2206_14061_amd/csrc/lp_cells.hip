@@ -10,6 +10,12 @@ namespace lp {
 
 namespace {
 
+// Kernels of the re-sort and list rebuild take a gate word: when it is
+// given and zero the kernel does nothing (device-side choice between a
+// rebuild and a plain state copy, needed by captured step sequences).
+#define LP_GATE(gate) \
+    if ((gate) && *(gate) == 0) return
+
 __device__ __forceinline__ unsigned long long ord_enc(double d)
 {
     unsigned long long b = (unsigned long long)__double_as_longlong(d);
@@ -22,8 +28,9 @@ __device__ __forceinline__ double ord_dec(unsigned long long e)
     return __longlong_as_double((long long)b);
 }
 
-__global__ void k_bbox_init(unsigned long long* bbox, int n_sys)
+__global__ void k_bbox_init(unsigned long long* bbox, int n_sys, const int32_t* gate)
 {
+    LP_GATE(gate);
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 6 * n_sys) bbox[t] = (t % 6) < 3 ? ~0ull : 0ull;
 }
@@ -42,8 +49,9 @@ __device__ void bbox_flush(unsigned long long* bbox, int s, const double* lo,
 // Per-system bounding box of the real particles.
 __global__ void k_bbox(int64_t n, int n_sys, const int64_t* off,
                        const double* x, const double* y, const double* z,
-                       unsigned long long* bbox)
+                       unsigned long long* bbox, const int32_t* gate)
 {
+    LP_GATE(gate);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = t * BBOX_CHUNK;
     const int lane = threadIdx.x & 63;
@@ -84,67 +92,93 @@ __global__ void k_bbox(int64_t n, int n_sys, const int64_t* off,
 }
 
 // Grid of each system from its bounding box; totals for the host.  Cell
-// edge c = R (1 + skin) (1 + 2^-20) >= the list radius.
+// edge c = R (1 + skin) (1 + 2^-20) >= the list radius.  With max_bits > 0
+// (captured steps, no host check) every edge is scaled up by a common
+// factor until each axis needs at most max_bits bits and all cells fit in
+// max_cells: any edge at least the list radius finds the same pairs.
 __global__ void k_grid(int n_sys, const int64_t* off, const lp_params* prm,
                        double skin, const unsigned long long* bbox,
-                       GridInfo* grid, Summary* sum)
+                       GridInfo* grid, Summary* sum, int max_bits,
+                       int64_t max_cells, ErrWord* err, const int32_t* gate)
 {
+    LP_GATE(gate);
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t base = 0;
-    int bits = 0, bad = 0;
-    for (int s = 0; s < n_sys; ++s) {
-        const lp_params& p = prm[s];
-        GridInfo g;
-        g.pbeg = off[s];
-        g.pend = off[s + 1];
-        g.R = p.R;
-        g.R2 = dmul(p.R, p.R);
-        g.h = p.h;
-        g.inv_h = 1.0 / p.h;
-        g.wall = p.wall_z;
-        g.Rv = dmul(p.R, 1.0 + skin);
-        g.Rv2 = dmul(g.Rv, g.Rv);
-        g.inv_skin2 = skin > 0.0 ? 1.0 / ((skin * p.R) * (skin * p.R)) : 0.0;
-        const double c = dmul(g.Rv, 1.0 + 1.0 / 1048576.0);
-        g.inv_c = 1.0 / c;
-        if (g.pend > g.pbeg) {
-            double lo[3], hi[3];
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = ord_dec(bbox[6 * s + a]);
-                hi[a] = ord_dec(bbox[6 * s + 3 + a]);
-            }
-            g.x0 = lo[0];
-            g.y0 = lo[1];
-            const double zl = dsub(p.wall_z, p.R);
-            g.z0 = zl < lo[2] ? zl : lo[2];
-            const double ex = dmul(dsub(hi[0], g.x0), g.inv_c);
-            const double ey = dmul(dsub(hi[1], g.y0), g.inv_c);
-            const double ez = dmul(dsub(hi[2], g.z0), g.inv_c);
-            if (!(ex < 65535.0 && ey < 65535.0 && ez < 65535.0)) {
-                bad = 1;
-                g.nx = g.ny = g.nz = 1;
+    double scale = 1.0;
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        int64_t base = 0;
+        int bits = 0, bad = 0;
+        for (int s = 0; s < n_sys; ++s) {
+            const lp_params& p = prm[s];
+            GridInfo g;
+            g.pbeg = off[s];
+            g.pend = off[s + 1];
+            g.R = p.R;
+            g.R2 = dmul(p.R, p.R);
+            g.h = p.h;
+            g.inv_h = 1.0 / p.h;
+            g.wall = p.wall_z;
+            g.Rv = dmul(p.R, 1.0 + skin);
+            g.Rv2 = dmul(g.Rv, g.Rv);
+            g.inv_skin2 = skin > 0.0 ? 1.0 / ((skin * p.R) * (skin * p.R)) : 0.0;
+            const double c = dmul(dmul(g.Rv, 1.0 + 1.0 / 1048576.0), scale);
+            g.inv_c = 1.0 / c;
+            if (g.pend > g.pbeg) {
+                double lo[3], hi[3];
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = ord_dec(bbox[6 * s + a]);
+                    hi[a] = ord_dec(bbox[6 * s + 3 + a]);
+                }
+                g.x0 = lo[0];
+                g.y0 = lo[1];
+                const double zl = dsub(p.wall_z, p.R);
+                g.z0 = zl < lo[2] ? zl : lo[2];
+                const double ex = dmul(dsub(hi[0], g.x0), g.inv_c);
+                const double ey = dmul(dsub(hi[1], g.y0), g.inv_c);
+                const double ez = dmul(dsub(hi[2], g.z0), g.inv_c);
+                if (!(ex < 65535.0 && ey < 65535.0 && ez < 65535.0)) {
+                    bad = 1;
+                    g.nx = g.ny = g.nz = 1;
+                } else {
+                    g.nx = (int)ex + 1;
+                    g.ny = (int)ey + 1;
+                    g.nz = (int)ez + 1;
+                }
             } else {
-                g.nx = (int)ex + 1;
-                g.ny = (int)ey + 1;
-                g.nz = (int)ez + 1;
+                g.x0 = g.y0 = g.z0 = 0.0;
+                g.nx = g.ny = g.nz = 1;
             }
-        } else {
-            g.x0 = g.y0 = g.z0 = 0.0;
-            g.nx = g.ny = g.nz = 1;
+            int m = g.nx > g.ny ? g.nx : g.ny;
+            m = m > g.nz ? m : g.nz;
+            int b = 0;
+            while ((1 << b) < m) ++b;
+            bits = b > bits ? b : bits;
+            g.cell_base = base;
+            g.pad = 0;
+            base += (int64_t)g.nx * g.ny * g.nz;
+            grid[s] = g;
         }
-        int m = g.nx > g.ny ? g.nx : g.ny;
-        m = m > g.nz ? m : g.nz;
-        int b = 0;
-        while ((1 << b) < m) ++b;
-        bits = b > bits ? b : bits;
-        g.cell_base = base;
-        g.pad = 0;
-        base += (int64_t)g.nx * g.ny * g.nz;
-        grid[s] = g;
+        const bool fits = !bad && bits <= max_bits && base <= max_cells;
+        if (max_bits <= 0 || fits) {
+            sum->total_cells = base;
+            sum->axis_bits = bits;
+            sum->bad = bad;
+            return;
+        }
+        if (attempt == 63) {
+            // cannot happen for any state that fits in memory; keep every
+            // later kernel in bounds and report it
+            for (int s2 = 0; s2 < n_sys; ++s2) {
+                grid[s2].nx = grid[s2].ny = grid[s2].nz = 1;
+                grid[s2].cell_base = s2;
+            }
+            sum->total_cells = n_sys;
+            sum->axis_bits = 0;
+            sum->bad = 1;
+            raise_error(err, ERR_CAPACITY, 0);
+            return;
+        }
+        scale *= 1.25;
     }
-    sum->total_cells = base;
-    sum->axis_bits = bits;
-    sum->bad = bad;
 }
 
 __device__ __forceinline__ void cell_of(const GridInfo& g, double x, double y,
@@ -162,8 +196,9 @@ __device__ __forceinline__ void cell_of(const GridInfo& g, double x, double y,
 __global__ void k_keys(int64_t n, int n_sys, const int64_t* off,
                        const GridInfo* grid, const double* x, const double* y,
                        const double* z, int shift_sys,
-                       unsigned long long* keys, int32_t* vals)
+                       unsigned long long* keys, int32_t* vals, const int32_t* gate)
 {
+    LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int s = sys_of(off, n_sys, i);
@@ -177,8 +212,9 @@ __global__ void k_keys(int64_t n, int n_sys, const int64_t* off,
 // ---- stable LSD radix sort, 8-bit digits ------------------------------
 
 __global__ void k_radix_hist(const unsigned long long* keys, int64_t n,
-                             int shift, uint32_t* hist, int64_t nblk)
+                             int shift, uint32_t* hist, int64_t nblk, const int32_t* gate)
 {
+    LP_GATE(gate);
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -192,8 +228,9 @@ __global__ void k_radix_hist(const unsigned long long* keys, int64_t n,
 }
 
 // Exclusive scan in place of a uint32 array (single block of 1024).
-__global__ void k_scan_u32(uint32_t* a, int64_t total)
+__global__ void k_scan_u32(uint32_t* a, int64_t total, const int32_t* gate)
 {
+    LP_GATE(gate);
     __shared__ uint32_t part[1024];
     const int t = threadIdx.x;
     const int64_t chunk = (total + 1023) / 1024;
@@ -220,8 +257,9 @@ __global__ void k_scan_u32(uint32_t* a, int64_t total)
 __global__ void k_radix_scatter(const unsigned long long* kin,
                                 const int32_t* vin, unsigned long long* kout,
                                 int32_t* vout, int64_t n, int shift,
-                                const uint32_t* hist, int64_t nblk)
+                                const uint32_t* hist, int64_t nblk, const int32_t* gate)
 {
+    LP_GATE(gate);
     __shared__ uint32_t base[256];
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[BLOCK / 64][256];
@@ -268,8 +306,9 @@ __global__ void k_gather7(int64_t n, const int32_t* perm,
                           const double* i0, const double* i1, const double* i2,
                           const double* i3, const double* i4, const double* i5,
                           const double* i6, double* o0, double* o1, double* o2,
-                          double* o3, double* o4, double* o5, double* o6)
+                          double* o3, double* o4, double* o5, double* o6, const int32_t* gate)
 {
+    LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t j = perm[i];
@@ -277,22 +316,30 @@ __global__ void k_gather7(int64_t n, const int32_t* perm,
     o4[i] = i4[j]; o5[i] = i5[j]; o6[i] = i6[j];
 }
 
-__global__ void k_copy_i32(int64_t n, const int32_t* a, int32_t* b)
+__global__ void k_copy_i32(int64_t n, const int32_t* a, int32_t* b, const int32_t* gate)
 {
+    LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
 }
 
-__global__ void k_copy_f64(int64_t n, const double* a, double* b)
+__global__ void k_copy_f64(int64_t n, const double* a, double* b, const int32_t* gate)
 {
+    LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
 }
 
-__global__ void k_fill_i32(int64_t n, int32_t* a, int32_t v)
+// a[0..count) = v, with count = *count_dev when given (grid-stride)
+__global__ void k_fill_i32(int64_t n, int32_t* a, int32_t v, const int64_t* count_dev,
+                           const int32_t* gate)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = v;
+    LP_GATE(gate);
+    int64_t m = n;
+    if (count_dev) m = *count_dev < n ? *count_dev : n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
 }
 
 // Cell start/end from sorted keys; positions give the linear cell index.
@@ -300,8 +347,9 @@ __global__ void k_cell_bounds(int64_t cnt, int n_sys, const int64_t* off,
                               const GridInfo* grid,
                               const unsigned long long* keys,
                               const double* x, const double* y,
-                              const double* z, int32_t* cs, int32_t* ce)
+                              const double* z, int32_t* cs, int32_t* ce, const int32_t* gate)
 {
+    LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt) return;
     const unsigned long long k = keys[i];
@@ -317,8 +365,9 @@ __global__ void k_cell_bounds(int64_t cnt, int n_sys, const int64_t* off,
     if (last) ce[c] = (int32_t)(i + 1);
 }
 
-__global__ void k_iota(int64_t n, int32_t* p)
+__global__ void k_iota(int64_t n, int32_t* p, const int32_t* gate)
 {
+    LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = (int32_t)i;
 }
@@ -362,7 +411,7 @@ inline unsigned int blocks_for(int64_t n, int per = BLOCK)
 // Sorts (keys, vals) of length cnt over `bits` bits; returns the buffers
 // holding the result through kr / vr.
 void radix_sort(lp_ctx* c, int64_t cnt, int bits, unsigned long long*& kr,
-                int32_t*& vr)
+                int32_t*& vr, const int32_t* gate)
 {
     Work& w = c->w;
     unsigned long long* kin = w.keys0;
@@ -374,12 +423,12 @@ void radix_sort(lp_ctx* c, int64_t cnt, int bits, unsigned long long*& kr,
     for (int p = 0; p < passes && cnt > 0; ++p) {
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(BLOCK), 0,
-                           c->stream, kin, cnt, shift, w.hist, nblk);
+                           c->stream, kin, cnt, shift, w.hist, nblk, gate);
         hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream,
-                           w.hist, 256 * nblk);
+                           w.hist, 256 * nblk, gate);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(BLOCK),
                            0, c->stream, kin, vin, kout, vout, cnt, shift,
-                           w.hist, nblk);
+                           w.hist, nblk, gate);
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
@@ -387,45 +436,74 @@ void radix_sort(lp_ctx* c, int64_t cnt, int bits, unsigned long long*& kr,
     vr = vin;
 }
 
-}  // namespace
+// Rebuild decision of a captured step: gate[0] = rebuild, gate[1] = keep
+// the list (copy the state); rebuild when some particle has moved skin R /
+// 2 since the last build (or always when `force`).
+__global__ void k_decide(const Summary* sum, int32_t* gate, Counters* cnt, int force)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double r = ord_dec(sum->disp);
+    const bool rebuild = force || !(sqrt(r) < 0.49);
+    gate[0] = rebuild ? 1 : 0;
+    gate[1] = rebuild ? 0 : 1;
+    if (rebuild) atomicAdd(&cnt->rebuilds, 1ull);
+}
 
-lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out)
+__global__ void k_gather_i32(int64_t n, const int32_t* perm, const int32_t* a,
+                             int32_t* b, const int32_t* gate)
+{
+    LP_GATE(gate);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[perm[i]];
+}
+
+// Re-sort + cell tables (+ list): eagerly with one host synchronisation for
+// the grid sizes (gate == nullptr), or entirely on the device behind a
+// gate with the grid held to `dev_bits` bits per axis.
+lp_status rebuild(lp_ctx* c, double* const st[7], int32_t* perm_out, int32_t* ids,
+                  const int32_t* gate, int dev_bits)
 {
     Work& w = c->w;
     const int64_t n = c->n;
     const int ns = c->n_sys;
     hipStream_t s = c->stream;
-    c->cells_ok = false;
-    c->stencils_ok = false;
-    c->list_ok = false;
-
+    const bool dev = gate != nullptr;
+    if (!dev) {
+        c->cells_ok = false;
+        c->stencils_ok = false;
+        c->list_ok = false;
+    }
     hipLaunchKernelGGL(k_bbox_init, dim3(blocks_for(6 * ns)), dim3(BLOCK), 0,
-                       s, w.bbox, ns);
+                       s, w.bbox, ns, gate);
     if (n > 0)
         hipLaunchKernelGGL(k_bbox, dim3(blocks_for((n + BBOX_CHUNK - 1) / BBOX_CHUNK)),
                            dim3(BLOCK), 0, s, n, ns, w.off, st[0], st[1], st[2],
-                           w.bbox);
+                           w.bbox, gate);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, ns, w.off, w.prm,
-                       c->cfg.skin, w.bbox, w.grid, w.summary);
-    hipError_t e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary),
-                                  hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(c, e, "grid summary");
-    const Summary sm = *w.h_summary;
-    if (sm.bad) {
-        c->err = "a system spans more than 65535 cells along one axis";
-        return LP_E_CAPACITY;
+                       c->cfg.skin, w.bbox, w.grid, w.summary, dev ? dev_bits : 0,
+                       w.cells_max, w.err, gate);
+    int axis_bits = dev_bits;
+    if (!dev) {
+        hipError_t e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary),
+                                      hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(c, e, "grid summary");
+        const Summary sm = *w.h_summary;
+        if (sm.bad) {
+            c->err = "a system spans more than 65535 cells along one axis";
+            return LP_E_CAPACITY;
+        }
+        if (sm.total_cells > w.cells_max) {
+            c->err = "cell tables need " + std::to_string(sm.total_cells) +
+                     " cells, reserved " + std::to_string(w.cells_max);
+            return LP_E_CAPACITY;
+        }
+        c->axis_bits = axis_bits = sm.axis_bits;
+        c->total_cells = sm.total_cells;
     }
-    if (sm.total_cells > w.cells_max) {
-        c->err = "cell tables need " + std::to_string(sm.total_cells) +
-                 " cells, reserved " + std::to_string(w.cells_max);
-        return LP_E_CAPACITY;
-    }
-    c->axis_bits = sm.axis_bits;
-    c->total_cells = sm.total_cells;
     int sys_bits = 0;
     while ((1 << sys_bits) < ns) ++sys_bits;
-    const int shift_sys = 3 * sm.axis_bits;
+    const int shift_sys = 3 * axis_bits;
     const int bits = shift_sys + sys_bits;
 
     unsigned long long* kr = nullptr;
@@ -433,46 +511,98 @@ lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out)
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, ns,
                            w.off, w.grid, st[0], st[1], st[2], shift_sys, w.keys0,
-                           w.vals0);
-        radix_sort(c, n, bits, kr, vr);
+                           w.vals0, gate);
+        radix_sort(c, n, bits, kr, vr, gate);
         hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
                            vr, st[0], st[1], st[2], st[3], st[4], st[5], st[6],
                            w.sst[0], w.sst[1], w.sst[2], w.sst[3], w.sst[4],
-                           w.sst[5], w.sst[6]);
+                           w.sst[5], w.sst[6], gate);
         if (perm_out)
             hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
-                               n, vr, perm_out);
+                               n, vr, perm_out, gate);
+        if (ids) {
+            hipLaunchKernelGGL(k_gather_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
+                               n, vr, ids, w.ids_tmp, gate);
+            hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
+                               n, w.ids_tmp, ids, gate);
+        }
         for (int a = 0; a < 3; ++a)
             hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
-                               n, w.sst[a], w.xref[a]);
+                               n, w.sst[a], w.xref[a], gate);
     }
-    const int64_t tc = sm.total_cells;
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(tc)), dim3(BLOCK), 0, s, tc, w.cs, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(tc)), dim3(BLOCK), 0, s, tc, w.ce, 0);
+    // cell tables: the whole used range (read on the device in captured
+    // steps)
+    const int64_t tc = dev ? w.cells_max : c->total_cells;
+    const int64_t* tdev = dev ? &w.summary->total_cells : nullptr;
+    const unsigned fb = std::min(blocks_for(tc), 8192u);
+    hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(BLOCK), 0, s, tc, w.cs, 0, tdev, gate);
+    hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(BLOCK), 0, s, tc, w.ce, 0, tdev, gate);
     if (n > 0)
         hipLaunchKernelGGL(k_cell_bounds, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
                            n, ns, w.off, w.grid, kr, w.sst[0], w.sst[1], w.sst[2],
-                           w.cs, w.ce);
-    e = hipGetLastError();
+                           w.cs, w.ce, gate);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "cell build launch");
-    c->cells_ok = true;
-    return list_build(c);
+    if (!dev) c->cells_ok = true;
+    return list_build(c, gate);
 }
 
-lp_status state_copy(lp_ctx* c, double* const st[7], int32_t* perm_out)
+}  // namespace
+
+lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out)
+{
+    return rebuild(c, st, perm_out, nullptr, nullptr, 0);
+}
+
+lp_status cells_build_device(lp_ctx* c, double* const st[7], int32_t* ids,
+                             const int32_t* gate, int bits)
+{
+    return rebuild(c, st, nullptr, ids, gate, bits);
+}
+
+lp_status state_copy(lp_ctx* c, double* const st[7], int32_t* perm_out,
+                     const int32_t* gate)
 {
     Work& w = c->w;
     const int64_t n = c->n;
     if (n > 0) {
         for (int a = 0; a < 7; ++a)
             hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, n, st[a], w.sst[a]);
+                               c->stream, n, st[a], w.sst[a], gate);
         if (perm_out)
             hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, n, perm_out);
+                               c->stream, n, perm_out, gate);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "state copy");
+}
+
+lp_status permute_ids(lp_ctx* c, const int32_t* perm, int32_t* ids)
+{
+    const int64_t n = c->n;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_gather_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
+                           n, perm, ids, c->w.ids_tmp, nullptr);
+        hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
+                           n, c->w.ids_tmp, ids, nullptr);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "id permutation");
+}
+
+lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
+    if (n > 0)
+        hipLaunchKernelGGL(k_disp, dim3(std::min(blocks_for(n), 1024u)), dim3(BLOCK), 0,
+                           c->stream, n, c->n_sys, w.off, w.grid, st[0], st[1], st[2],
+                           w.xref[0], w.xref[1], w.xref[2], w.summary);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(1), 0, c->stream, w.summary, w.gate,
+                       w.cnt, force);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "rebuild decision");
 }
 
 lp_status state_write_back(lp_ctx* c, double* const out[7])
@@ -482,7 +612,7 @@ lp_status state_write_back(lp_ctx* c, double* const out[7])
     if (n > 0)
         for (int a = 0; a < 7; ++a)
             hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, n, w.sst[a], out[a]);
+                               c->stream, n, w.sst[a], out[a], nullptr);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "state write-back");
 }

@@ -74,7 +74,8 @@ struct Counters {
     unsigned long long qr_refits;
     unsigned long long hard_stencils;
     unsigned long long below_wall;
-    unsigned long long pad[5];
+    unsigned long long rebuilds;    // list rebuilds decided on the device
+    unsigned long long pad[4];
 };
 
 // Everything a per-particle kernel needs to find neighbours and states.
@@ -154,6 +155,9 @@ struct Work {
     double* adj_stash = nullptr;          // 11 x n
     double* coefu = nullptr;              // 27 x n forward velocity coefficients
     int32_t* adj_perm = nullptr;
+    // captured step sequences
+    int32_t* gate = nullptr;              // [0] rebuild, [1] keep
+    int32_t* ids_tmp = nullptr;
     double* acc = nullptr;                // 3 x n
     double* dVdt = nullptr;
     uint8_t* flags = nullptr;
@@ -186,6 +190,25 @@ struct lp_ctx {
     const double* built_x = nullptr;
     bool cells_ok = false;
     bool stencils_ok = false;
+    // captured step sequence (lp_step_graph) and what it was captured for
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        const double* st[7];
+        const int32_t* ids;
+        double dt;
+        int32_t nsteps, bits;
+        int64_t n;
+        int32_t n_sys;
+        bool operator==(const GraphKey& o) const
+        {
+            for (int a = 0; a < 7; ++a)
+                if (st[a] != o.st[a]) return false;
+            return ids == o.ids && dt == o.dt && nsteps == o.nsteps && bits == o.bits &&
+                   n == o.n && n_sys == o.n_sys;
+        }
+    } gkey{};
     std::string err;
 };
 
@@ -276,7 +299,16 @@ namespace lp {
 // list with skin and reference positions.
 lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out);
 // Copies the input into the working copy in the same order (no rebuild).
-lp_status state_copy(lp_ctx* c, double* const st[7], int32_t* perm_out);
+lp_status state_copy(lp_ctx* c, double* const st[7], int32_t* perm_out,
+                     const int32_t* gate = nullptr);
+// Re-sort + list rebuild entirely on the device, skipped unless *gate;
+// ids (optional) are permuted with the state; `bits` per grid axis.
+lp_status cells_build_device(lp_ctx* c, double* const st[7], int32_t* ids,
+                             const int32_t* gate, int bits);
+// ids[i] = ids[perm[i]]
+lp_status permute_ids(lp_ctx* c, const int32_t* perm, int32_t* ids);
+// Device-side rebuild decision into w.gate (no synchronisation).
+lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force);
 // Copies the working copy back into the caller's arrays.
 lp_status state_write_back(lp_ctx* c, double* const out[7]);
 // Largest displacement since the list build in units of the skin
@@ -289,7 +321,7 @@ lp_status stencils_export(lp_ctx* c, const double* const st[7],
                           int64_t* needed, int32_t* sten_cnt,
                           int32_t* sten_idx, uint8_t* ghost_mask,
                           int64_t* n_mirror);
-lp_status list_build(lp_ctx* c);
+lp_status list_build(lp_ctx* c, const int32_t* gate = nullptr);
 lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
                       int k, const int32_t* msign, const int32_t* gzero,
                       double* coef, uint8_t* flags);

@@ -61,8 +61,10 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
     const GridInfo* __restrict__ grid, const double* __restrict__ x,
     const double* __restrict__ y, const double* __restrict__ z,
     const int32_t* __restrict__ cs, const int32_t* __restrict__ ce,
-    int32_t* __restrict__ vl, int32_t* __restrict__ vcnt, ErrWord* err)
+    int32_t* __restrict__ vl, int32_t* __restrict__ vcnt, ErrWord* err,
+    const int32_t* gate)
 {
+    if (gate && *gate == 0) return;
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     if (i >= n) return;
     const GridInfo& g = grid[sys_of(off, n_sys, i)];
@@ -652,15 +654,15 @@ __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 }  // namespace
 
-lp_status list_build(lp_ctx* c)
+lp_status list_build(lp_ctx* c, const int32_t* gate)
 {
     Work& w = c->w;
     const int64_t n = c->n;
-    c->list_ok = false;
+    if (!gate) c->list_ok = false;
     if (n > 0)
         hipLaunchKernelGGL(k_list_build, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
-                           w.sst[2], w.cs, w.ce, w.vl, w.vcnt, w.err);
+                           w.sst[2], w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "list build launch");
     c->list_ok = true;
