@@ -25,6 +25,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -55,6 +57,9 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--adjoint-steps", type=int, default=50)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=20)
+    ap.add_argument("--ensemble-adjoint-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three 1 GiB device-to-device copies, the "
@@ -137,6 +142,62 @@ def adjoint_bench(torch, lp, lpgen, steps: int, warmup: int = 1):
             "ms_forward": 1e3 * tf, "ms_backward": 1e3 * tb, "loss": loss,
             "dL_dtheta": gth.cpu().tolist(),
             "max_abs_dL_du0": float(gu.abs().max().item())}
+
+
+def ensemble_bench(torch, lp, lpgen, steps: int, adjoint_steps: int):
+    """64 independent columns (8k-200k particles each, their own mu(I)
+    parameters; 6.7M particles) advanced in the same launches: `steps`
+    steps captured in one HIP graph, FP64 and refined FP32, then the
+    gradient of a runout loss through `adjoint_steps` steps."""
+    from paper_2206_14061_amd.autograd import simulate
+    wl = lpgen.ensemble()
+    out = {"workload": "ensemble_64_columns", "systems": len(wl.params),
+           "particles": wl.n, "graph_steps": steps, "dt": wl.dt}
+    for name, prec in (("fp64", lp.LP_FP64), ("fp32r", lp.LP_FP32_REFINED)):
+        ctx = lp.make_context(wl, precision=prec)
+        st = lp.DeviceState.from_host(wl.state)
+        ids = torch.arange(wl.n, dtype=torch.int32, device="cuda")
+        ctx.lp_step_graph(st, wl.dt, steps, ids)     # capture + first replay
+        ctx.sync_status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.lp_step_graph(st, wl.dt, steps, ids)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.sync_status()
+        out[name] = {"value": wl.n * steps / t, "unit": "particle-updates/s",
+                     "ms_per_step": 1e3 * t / steps, "stats": ctx.stats()}
+        del ctx, st, ids
+    out["fp32r_speedup_vs_fp64"] = out["fp32r"]["value"] / out["fp64"]["value"]
+    # forward + adjoint (checkpointed, eager steps).  Runout target of each
+    # column: 5 cm beyond its initial right face; particles stay in their
+    # system's index range through re-sorts, so targets are set by index.
+    ctx = lp.make_context(wl)
+    h = wl.params[0].h
+    off = wl.offsets
+    xt = np.empty(wl.n)
+    for c in range(len(wl.params)):
+        xt[off[c]:off[c + 1]] = wl.state.x[off[c]:off[c + 1]].max() + 0.05
+    xt = torch.tensor(xt, device="cuda")
+    state = [torch.tensor(a, device="cuda", requires_grad=True) for a in wl.state.arrays()]
+    theta = torch.tensor([[p.mu_s, p.mu_2, p.I0] for p in wl.params],
+                         dtype=torch.float64, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fin = simulate(ctx, wl.offsets, wl.params, state, theta, wl.dt, adjoint_steps,
+                   checkpoint_every=10)
+    loss = torch.nn.functional.softplus((fin[0] - xt) / h).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.sync_status()
+    out["adjoint"] = {"steps": adjoint_steps, "checkpoint_every": 10,
+                      "step_pairs_per_s": adjoint_steps / (t2 - t0),
+                      "ms_forward": 1e3 * (t1 - t0), "ms_backward": 1e3 * (t2 - t1),
+                      "max_abs_dL_dtheta": float(theta.grad.abs().max().item())}
+    return out
 
 
 def copy_calibration(torch):
@@ -249,6 +310,9 @@ def main():
            "roofline": roof}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_bench(torch, lp, lpgen, args.ensemble_steps,
+                                         args.ensemble_adjoint_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     if args.copy_calibration:
