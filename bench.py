@@ -58,6 +58,7 @@ def _parse():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--adjoint-steps", type=int, default=50)
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-sheared", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--ensemble-adjoint-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true")
@@ -142,6 +143,48 @@ def adjoint_bench(torch, lp, lpgen, steps: int, warmup: int = 1):
             "ms_forward": 1e3 * tf, "ms_backward": 1e3 * tb, "loss": loss,
             "dL_dtheta": gth.cpu().tolist(),
             "max_abs_dL_du0": float(gu.abs().max().item())}
+
+
+def sheared_bench(torch, lp, lpgen, steps: int):
+    """The 128 x 128 x 64 column after a seeded shear (1,048,576 particles,
+    uneven stencils): stencil-size histogram, autotuned lanes per particle,
+    FP64 and refined-FP32 step rates and the share of stencils refitted in
+    float64."""
+    wl = lpgen.column_sheared()
+    out = {"workload": wl.name, "particles": wl.n, "steps": steps, "dt": wl.dt}
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    ctx.lp_build_cells(st, want_perm=False)
+    nb = ctx.lp_neighbors(st, candidates=False)
+    rows = nb["sten_cnt"].to(torch.int64) + \
+        torch.stack([(nb["ghost_mask"].to(torch.int64) >> o) & 1 for o in range(8)]).sum(0)
+    edges = list(range(0, 73, 8))
+    hist = torch.histc(rows.to(torch.float64), bins=9, min=0, max=72).cpu().tolist()
+    out["rows_histogram"] = {"bin_edges": edges, "counts": [int(c) for c in hist]}
+    del ctx, st
+    for name, prec in (("fp64", lp.LP_FP64), ("fp32r", lp.LP_FP32_REFINED)):
+        ctx = lp.make_context(wl, precision=prec)
+        st = lp.DeviceState.from_host(wl.state)
+        lanes = ctx.lp_autotune(st)
+        for _ in range(2):
+            ctx.lp_step(st, wl.dt)
+        ctx.sync_status()
+        ctx.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.lp_step(st, wl.dt)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.sync_status()
+        stt = ctx.stats()
+        out[name] = {"value": wl.n * steps / t, "unit": "particle-updates/s",
+                     "ms_per_step": 1e3 * t / steps, "lanes_per_particle": list(lanes),
+                     "fp64_refit_fraction": stt["qr_refits"] / (wl.n * steps),
+                     "stats": stt}
+        del ctx, st
+    out["fp32r_speedup_vs_fp64"] = out["fp32r"]["value"] / out["fp64"]["value"]
+    return out
 
 
 def ensemble_bench(torch, lp, lpgen, steps: int, adjoint_steps: int):
@@ -310,6 +353,8 @@ def main():
            "roofline": roof}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
+    if not args.no_sheared:
+        out["sheared"] = sheared_bench(torch, lp, lpgen, 20)
     if not args.no_ensemble:
         out["ensemble"] = ensemble_bench(torch, lp, lpgen, args.ensemble_steps,
                                          args.ensemble_adjoint_steps)

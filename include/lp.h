@@ -50,8 +50,10 @@ typedef enum {
 enum { LP_FP64 = 0, LP_FP32_REFINED = 1 };
 enum { LP_W_UNIT = 0, LP_W_GAUSS = 1 };
 
-/* debug_flags: route every particle through the exact slow paths */
-enum { LP_DEBUG_SORTED_STENCIL = 1, LP_DEBUG_QR_FIT = 2 };
+/* debug_flags: route every particle through the exact slow paths, or fix
+ * the lanes per particle of the fits (see lp_autotune) */
+enum { LP_DEBUG_SORTED_STENCIL = 1, LP_DEBUG_QR_FIT = 2, LP_DEBUG_LANES2 = 4,
+       LP_DEBUG_LANES4 = 8 };
 
 /* Physical constants of one system (Sec. 2.2, 2.2.1 and Sec. 4).
  * rho_s: grain material density (the paper's phi_s); d: grain diameter;
@@ -76,7 +78,9 @@ typedef struct {
  * LP_W_GAUSS (w = exp(-4 r^2 / R^2)).  ghost_margin: an octant is covered
  * when a neighbour lies beyond ghost_margin * h on every axis (0.5).
  * fallback_tol: stencils with min|r_jj|/max|r_jj| below it (or fewer than 9
- * rows) use a linear fit (1e-12).  debug_flags: LP_DEBUG_* bits.
+ * rows) use a linear fit (1e-12).  debug_flags: LP_DEBUG_* bits (sorted
+ * stencil path for every particle, Householder refit for every stencil,
+ * 2 or 4 lanes per particle in the fits).
  * skin: neighbour-list margin in units of R (default 0.1): the list holds
  * every pair within R (1 + skin) and is rebuilt (with a Morton re-sort)
  * once a particle has moved skin R / 2 since the last build; 0 rebuilds
@@ -211,6 +215,17 @@ lp_status lp_rheology_rhs(lp_ctx* ctx, const lp_state* s,
  * The state must keep the order of the previous lp_step between calls.
  * dt > 0.  A non-finite result latches LP_E_NUMERIC (lp_sync_status). */
 lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
+
+/* Chooses how many adjacent lanes of a wavefront share one particle in
+ * each of the two least-squares fit kernels (1, 2 or 4: each lane takes
+ * every 1st, 2nd or 4th stencil row and the Gram moments are summed across
+ * the lanes), by timing every choice on the stencils of s (not modified).
+ * lp_step, lp_step_graph and lp_rheology_rhs use the choice afterwards.
+ * choice (host int32[2], optional) receives the lanes per particle of the
+ * first (u, v, w) and second (P, eta) fit.  Synchronises; leaves the
+ * context without a neighbour list and drops a captured graph.  Results
+ * differ between choices only by summation order. */
+lp_status lp_autotune(lp_ctx* ctx, const lp_state* s, int32_t* choice);
 
 /* nsteps consecutive lp_step calls as one HIP graph, for callers that
  * replay fixed step sequences without host work between steps.  Every

@@ -12,7 +12,8 @@ import ctypes as C
 from typing import Dict, List, Optional, Sequence
 
 from . import _lib
-from ._lib import (LP_DEBUG_QR_FIT, LP_DEBUG_SORTED_STENCIL, LP_FP32_REFINED,
+from ._lib import (LP_DEBUG_LANES2, LP_DEBUG_LANES4, LP_DEBUG_QR_FIT,
+                   LP_DEBUG_SORTED_STENCIL, LP_FP32_REFINED,
                    LP_FP64, LP_W_GAUSS, LP_W_UNIT, LPConfig, LPError,
                    LPParams, LPState)
 
@@ -209,6 +210,14 @@ class Context:
     def lp_step(self, st: DeviceState, dt: float, perm=None):
         s = st.struct()
         self._check(self.lib.lp_step(self.h, C.byref(s), float(dt), _ptr(perm)))
+
+    def lp_autotune(self, st: DeviceState):
+        """Times 1, 2 and 4 lanes per particle in both fits on st's stencils
+        and keeps the fastest; returns (lanes pass 1, lanes pass 2)."""
+        ch = (C.c_int32 * 2)()
+        s = st.struct()
+        self._check(self.lib.lp_autotune(self.h, C.byref(s), ch))
+        return int(ch[0]), int(ch[1])
 
     def lp_step_graph(self, st: DeviceState, dt: float, nsteps: int, ids=None):
         """nsteps steps replayed as one HIP graph (captured on first use);

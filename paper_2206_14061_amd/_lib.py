@@ -17,6 +17,7 @@ LP_OK, LP_E_ARG, LP_E_CAPACITY, LP_E_NUMERIC, LP_E_HIP, LP_E_STATE = range(6)
 LP_FP64, LP_FP32_REFINED = 0, 1
 LP_W_UNIT, LP_W_GAUSS = 0, 1
 LP_DEBUG_SORTED_STENCIL, LP_DEBUG_QR_FIT = 1, 2
+LP_DEBUG_LANES2, LP_DEBUG_LANES4 = 4, 8
 
 STATUS_NAMES = {0: "LP_OK", 1: "LP_E_ARG", 2: "LP_E_CAPACITY",
                 3: "LP_E_NUMERIC", 4: "LP_E_HIP", 5: "LP_E_STATE"}
@@ -24,7 +25,7 @@ STATUS_NAMES = {0: "LP_OK", 1: "LP_E_ARG", 2: "LP_E_CAPACITY",
 # every symbol include/lp.h declares
 EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_last_error",
            "lp_reserve", "lp_set_systems", "lp_build_cells", "lp_neighbors",
-           "lp_fit_derivs", "lp_rheology_rhs", "lp_step", "lp_step_graph",
+           "lp_fit_derivs", "lp_rheology_rhs", "lp_step", "lp_autotune", "lp_step_graph",
            "lp_step_adjoint",
            "lp_sync_status", "lp_stats", "lp_profile", "lp_profile_read"]
 
@@ -92,6 +93,8 @@ def load():
     lib.lp_rheology_rhs.restype = C.c_int
     lib.lp_step.argtypes = [P, pp(LPState), C.c_double, P]
     lib.lp_step.restype = C.c_int
+    lib.lp_autotune.argtypes = [P, pp(LPState), pp(C.c_int32)]
+    lib.lp_autotune.restype = C.c_int
     lib.lp_step_graph.argtypes = [P, pp(LPState), P, C.c_double, i32]
     lib.lp_step_graph.restype = C.c_int
     lib.lp_step_adjoint.argtypes = [P, pp(LPState), C.c_double, pp(LPState),

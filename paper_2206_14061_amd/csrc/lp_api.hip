@@ -180,6 +180,8 @@ lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
     if (!c) return LP_E_ARG;
     c->stream = (hipStream_t)stream;
     c->cfg = c0;
+    if (c0.debug_flags & LP_DEBUG_LANES2) c->lpp1 = c->lpp2 = 2;
+    if (c0.debug_flags & LP_DEBUG_LANES4) c->lpp1 = c->lpp2 = 4;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return LP_E_HIP;
@@ -462,6 +464,29 @@ lp_status lp_profile_read(lp_ctx* c, double* ms8, int64_t* steps)
     if (steps) *steps = c->prof_steps;
     c->prof_steps = 0;
     return LP_OK;
+}
+
+lp_status lp_autotune(lp_ctx* c, const lp_state* s, int32_t* choice)
+{
+    if (!s) {
+        if (c) c->err = "lp_autotune: null state";
+        return LP_E_ARG;
+    }
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    double* in[7];
+    state_arrays(s, in);
+    r = cells_build(c, in, nullptr);
+    const double* sorted[7];
+    for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
+    if (r == LP_OK) r = stencils_build(c, sorted);
+    if (r == LP_OK) r = autotune_fits(c, sorted, choice);
+    // the working copy is a sorted copy of s, not the caller's order
+    c->list_ok = false;
+    c->stencils_ok = false;
+    c->built_x = nullptr;
+    drop_graph(c);
+    return r;
 }
 
 lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,

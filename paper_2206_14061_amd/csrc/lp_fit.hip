@@ -282,12 +282,17 @@ __device__ __forceinline__ void finish_pass1(const View& v, const lp_params& p,
     }
 }
 
+// LPP lanes per particle: each lane accumulates every LPP-th row; the
+// moments are summed across the lanes, every lane solves, lane 0 stores.
+template <int LPP>
 __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
                                                     int32_t* redo,
                                                     unsigned int* redo_n,
                                                     int force_qr)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const int64_t gt = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const int64_t i = gt / LPP;
+    const int sub = (int)(gt % LPP);
     if (i >= v.n) return;
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
@@ -298,7 +303,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
     for (int q = 0; q < 31; ++q) M[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) B[0][q] = B[1][q] = B[2][q] = 0.0;
-    const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+    int mt = for_rows_sub<LPP>(v, g, i, r, sub, [&](const double* a, double w,
+                                                    const Pt* p) {
         moments_add(M, a, w);
         if (!p) return;   // ghosts carry u_i (b = 0)
         double uj, vj, wj;
@@ -311,14 +317,28 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
             B[2][q] += a[q] * b2;
         }
     });
+    if (LPP > 1) {
+        mt = lane_sum<LPP>(mt);
+#pragma unroll
+        for (int q = 0; q < 31; ++q) M[q] = lane_sum<LPP>(M[q]);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            B[0][q] = lane_sum<LPP>(B[0][q]);
+            B[1][q] = lane_sum<LPP>(B[1][q]);
+            B[2][q] = lane_sum<LPP>(B[2][q]);
+        }
+    }
     double G[45], c3[3][9], none[27];
     gram_from_moments(M, G);
     uint8_t fl;
     if (!gram_solve<3>(G, B, mt, v.redo_ratio, force_qr != 0, c3, none, false, fl)) {
-        redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
-        o.flags[i] = FLAG_QR;
+        if (sub == 0) {
+            redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
+            o.flags[i] = FLAG_QR;
+        }
         return;
     }
+    if (sub != 0) return;
     double c[27];
 #pragma unroll
     for (int q = 0; q < 27; ++q)
@@ -469,12 +489,15 @@ __device__ __forceinline__ void load_hand_tail(const double* hand, int64_t n,
     for (int q = 0; q < 3; ++q) hv[8 + q] = hand[(int64_t)(34 + q) * n + i];
 }
 
+template <int LPP>
 __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
                                                  const double* eta,
                                                  const double* hand,
                                                  const uint8_t* flags, RhsOut o)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const int64_t gt = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const int64_t i = gt / LPP;
+    const int sub = (int)(gt % LPP);
     if (i >= v.n) return;
     if (flags[i] & FLAG_QR) return;
     const int64_t n = v.n;
@@ -486,7 +509,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
     double yP[9], yE[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) yP[q] = yE[q] = 0.0;
-    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+    for_rows_sub<LPP>(v, g, i, r, sub, [&](const double* a, double w, const Pt* p) {
         double Pj, Ej;
         pass2_values(v, P, eta, p, prm, Pj, Ej);
         const double bP = w * (Pj - Pi), bE = w * (Ej - Ei);
@@ -496,6 +519,14 @@ __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
             yE[q] += a[q] * bE;
         }
     });
+    if (LPP > 1) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            yP[q] = lane_sum<LPP>(yP[q]);
+            yE[q] = lane_sum<LPP>(yE[q]);
+        }
+    }
+    if (sub != 0) return;
     double gP[3], gE[3];
 #pragma unroll
     for (int rr = 0; rr < 3; ++rr) {
@@ -795,6 +826,52 @@ static lp_status need_stencils(lp_ctx* c)
     return LP_OK;
 }
 
+namespace {
+
+void launch_pass1(lp_ctx* c, int lpp, const View& v, const StepOut& so, int fq)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    switch (lpp) {
+    case 4:
+        hipLaunchKernelGGL((k_pass1<4>), dim3(blocks_for(4 * n)), dim3(BLOCK), 0,
+                           c->stream, v, so, w.redo, w.redo_n, fq);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_pass1<2>), dim3(blocks_for(2 * n)), dim3(BLOCK), 0,
+                           c->stream, v, so, w.redo, w.redo_n, fq);
+        break;
+    default:
+        hipLaunchKernelGGL((k_pass1<1>), dim3(blocks_for(n)), dim3(BLOCK), 0,
+                           c->stream, v, so, w.redo, w.redo_n, fq);
+    }
+}
+
+void launch_pass2(lp_ctx* c, int lpp, const View& v, const RhsOut& o)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    const double* P = w.P;
+    const double* E = w.eta;
+    const double* H = w.hand;
+    const uint8_t* F = w.flags;
+    switch (lpp) {
+    case 4:
+        hipLaunchKernelGGL((k_pass2<4>), dim3(blocks_for(4 * n)), dim3(BLOCK), 0,
+                           c->stream, v, P, E, H, F, o);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_pass2<2>), dim3(blocks_for(2 * n)), dim3(BLOCK), 0,
+                           c->stream, v, P, E, H, F, o);
+        break;
+    default:
+        hipLaunchKernelGGL((k_pass2<1>), dim3(blocks_for(n)), dim3(BLOCK), 0,
+                           c->stream, v, P, E, H, F, o);
+    }
+}
+
+}  // namespace
+
 lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
                       int k, const int32_t* msign, const int32_t* gzero,
                       double* coef, uint8_t* flags)
@@ -866,9 +943,7 @@ lp_status rhs_from_coef(lp_ctx* c, const double* const st[7],
         hipLaunchKernelGGL(k_closure_coef, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, v, coef_u, so, w.redo, w.redo_n, fq);
         RhsOut o = rhs_out(c, acc, dVdt, grad);
-        hipLaunchKernelGGL(k_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
-                           v, (const double*)w.P, (const double*)w.eta,
-                           (const double*)w.hand, (const uint8_t*)w.flags, o);
+        launch_pass2(c, c->lpp2, v, o);
         hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
                            c->stream, v, (const double*)w.P, (const double*)w.eta,
                            (const double*)w.hand, (const int32_t*)w.redo,
@@ -896,8 +971,7 @@ lp_status step_rhs(lp_ctx* c, const double* const st[7])
             hipLaunchKernelGGL(k_pass1_ref, dim3(blocks_for(n)), dim3(BLOCK), 0,
                                c->stream, v, so, w.uf, w.redo, w.redo_n);
         else
-            hipLaunchKernelGGL(k_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
-                               v, so, w.redo, w.redo_n, fq);
+            launch_pass1(c, c->lpp1, v, so, fq);
         prof_mark(c, 3, true);
         prof_mark(c, 4, false);
         hipLaunchKernelGGL(k_pass1_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
@@ -918,8 +992,7 @@ lp_status step_pass1_coef(lp_ctx* c, const double* const st[7])
     StepOut so{w.P, w.eta, w.hand, w.flags, nullptr, w.coefu};
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
     if (n > 0) {
-        hipLaunchKernelGGL(k_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
-                           v, so, w.redo, w.redo_n, 0);
+        launch_pass1(c, c->lpp1, v, so, 0);
         hipLaunchKernelGGL(k_pass1_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
                            c->stream, v, so, (const int32_t*)w.redo,
                            (const unsigned int*)w.redo_n, w.qr_scratch, w.cnt);
@@ -946,9 +1019,7 @@ lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
                                (const double*)w.hand, (const float*)w.uf,
                                (const uint8_t*)w.flags, o);
         else
-            hipLaunchKernelGGL(k_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
-                               v, (const double*)w.P, (const double*)w.eta,
-                               (const double*)w.hand, (const uint8_t*)w.flags, o);
+            launch_pass2(c, c->lpp2, v, o);
         prof_mark(c, 5, true);
         prof_mark(c, 6, false);
         hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
@@ -959,6 +1030,55 @@ lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "pass-2 launch");
+    return LP_OK;
+}
+
+lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    View v = make_view(c, st);
+    StepOut so{w.P, w.eta, w.hand, w.flags, nullptr, nullptr};
+    RhsOut o = rhs_out(c, w.acc, w.dVdt, nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int cand[3] = {1, 2, 4};
+    float best1 = 1e30f, best2 = 1e30f;
+    int pick1 = 1, pick2 = 1;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+            float t = 1e30f;
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+                e = hipEventRecord(e0, c->stream);
+                if (pass == 0) launch_pass1(c, cand[q], v, so, 0);
+                else launch_pass2(c, cand[q], v, o);
+                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                t = ms < t ? ms : t;
+            }
+            if (pass == 0 && t < best1) { best1 = t; pick1 = cand[q]; }
+            if (pass == 1 && t < best2) { best2 = t; pick2 = cand[q]; }
+        }
+        if (pass == 0 && e == hipSuccess) {
+            // pass 2 needs the pass-1 outputs of the chosen variant
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+            launch_pass1(c, pick1, v, so, 0);
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune");
+    (void)n;
+    c->lpp1 = pick1;
+    c->lpp2 = pick2;
+    if (choice) {
+        choice[0] = pick1;
+        choice[1] = pick2;
+    }
     return LP_OK;
 }
 

@@ -255,6 +255,32 @@ __device__ __forceinline__ int for_rows(const View& v, const GridInfo& g,
     return m;
 }
 
+// for_rows with the rows spread over LPP lanes (stencil rows as in
+// visit_stencil_sub, ghost o to lane o mod LPP); returns this lane's rows.
+template <int LPP, class F>
+__device__ __forceinline__ int for_rows_sub(const View& v, const GridInfo& g, int64_t i,
+                                            const Rec& r, int sub, F&& f)
+{
+    if (LPP == 1) return for_rows(v, g, i, r, f);
+    int m = 0;
+    visit_stencil_sub<LPP>(v, g, i, r, sub, [&](const Pt& p, double dx, double dy,
+                                                double dz) {
+        double a[9];
+        const double w = point_row(v, g, dx, dy, dz, a);
+        f(a, w, &p);
+        ++m;
+    });
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+        if (((r.gm >> o) & 1) && (o % LPP) == sub) {
+            double a[9];
+            const double w = ghost_row(v, g, o, a);
+            f(a, w, (const Pt*)nullptr);
+            ++m;
+        }
+    return m;
+}
+
 // The Gram matrix of the Taylor rows a = (x, y, z, x^2/2, y^2/2, z^2/2,
 // xy, xz, yz) has 31 distinct entries: the weighted sums of the monomials
 // of degree 2, 3 and 4 in (x, y, z).  They are accumulated row by row

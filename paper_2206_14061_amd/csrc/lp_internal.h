@@ -16,7 +16,7 @@ constexpr int MMAX_LIMIT = 64;    // largest supported stencil cap
 constexpr int MAXROWS = MMAX_LIMIT + 8;
 constexpr int HIST_BUCKETS = 64;  // r^2 histogram of the stencil selection
 constexpr int LIST_CAP = 16;      // cut-bucket members ranked per thread
-constexpr int VCAP = 192;         // neighbour-list entries per particle
+constexpr int VCAP = 256;         // neighbour-list entries per particle
 constexpr int MASK_WORDS = VCAP / 64;  // keep bitmask words per particle
 constexpr int32_t MBIT = 0x40000000;  // list entry: mirror of the real id
 constexpr int32_t NOID = 0x7FFFFFFF;
@@ -180,6 +180,7 @@ struct lp_ctx {
     int64_t total_cells = 0;
     int64_t n_mirror = 0;
     bool list_ok = false;       // neighbour list valid for the working state
+    int lpp1 = 1, lpp2 = 1;     // lanes per particle of the two fit kernels
     int64_t rebuilds = 0;       // list rebuilds since the last lp_stats
     // phase timing (lp_profile)
     bool prof = false;
@@ -329,6 +330,9 @@ lp_status rhs_from_coef(lp_ctx* c, const double* const st[7],
                         const double* coef_u, double* dVdt, double* acc,
                         double* diag, double* grad, uint8_t* flags);
 lp_status step_rhs(lp_ctx* c, const double* const st[7]);
+// times each lanes-per-particle variant of the two fit kernels on the
+// stencils of st and keeps the fastest (choice: host int32[2], optional)
+lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice);
 // pass 1 in float64 with the velocity coefficients stored (adjoint input)
 lp_status step_pass1_coef(lp_ctx* c, const double* const st[7]);
 // reverse of the step on the sorted state st (after step_pass1_coef);

@@ -241,36 +241,41 @@ __device__ __forceinline__ int cut_bucket(const uint32_t (*hist)[BLOCK], int t,
     return HIST_BUCKETS;
 }
 
+// keep mask over the list entries of one particle (VCAP bits)
+struct Mask4 {
+    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    __device__ __forceinline__ void set(int k)
+    {
+        const uint64_t b = 1ull << (k & 63);
+        if (k < 64)
+            w0 |= b;
+        else if (k < 128)
+            w1 |= b;
+        else if (k < 192)
+            w2 |= b;
+        else
+            w3 |= b;
+    }
+    __device__ __forceinline__ bool has(int k) const
+    {
+        const uint64_t w = k < 64 ? w0 : (k < 128 ? w1 : (k < 192 ? w2 : w3));
+        return (w >> (k & 63)) & 1ull;
+    }
+};
+
 __device__ __forceinline__ void write_rec(const View& v, int64_t i, int m, int gm,
-                                          int mode, uint64_t m0, uint64_t m1,
-                                          uint64_t m2)
+                                          int mode, const Mask4& mk)
 {
+    static_assert(MASK_WORDS == 4, "four keep-mask words");
     const int64_t n = v.n;
     int32_t* q = v.rec;
     q[REC_M * n + i] = m;
     q[REC_GM * n + i] = gm;
     q[REC_MODE * n + i] = mode;
-    v.kmask[i] = m0;
-    v.kmask[n + i] = m1;
-    v.kmask[2 * n + i] = m2;
-}
-
-__device__ __forceinline__ void set_bit(uint64_t& m0, uint64_t& m1, uint64_t& m2,
-                                        int k)
-{
-    const uint64_t b = 1ull << (k & 63);
-    if (k < 64)
-        m0 |= b;
-    else if (k < 128)
-        m1 |= b;
-    else
-        m2 |= b;
-}
-
-__device__ __forceinline__ bool has_bit(uint64_t m0, uint64_t m1, uint64_t m2, int k)
-{
-    const uint64_t w = k < 64 ? m0 : (k < 128 ? m1 : m2);
-    return (w >> (k & 63)) & 1ull;
+    v.kmask[i] = mk.w0;
+    v.kmask[n + i] = mk.w1;
+    v.kmask[2 * n + i] = mk.w2;
+    v.kmask[3 * n + i] = mk.w3;
 }
 
 // Calls f(pt, dx, dy, dz, r2) for every candidate of particle i.
@@ -318,7 +323,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     // ---- pass 1: exact test of every list entry; its bucket is stored
     // (entry k of all lanes at once: coalesced)
     int nc = 0, covered = 0;
-    uint64_t c0 = 0, c1 = 0, c2 = 0;   // candidate entries
+    Mask4 cm;                          // candidate entries
     double br0 = INFINITY, br1 = INFINITY, br2_ = INFINITY, br3 = INFINITY,
            br4 = INFINITY, br5 = INFINITY, br6 = INFINITY, br7 = INFINITY;
     int32_t bi0 = NOID, bi1 = NOID, bi2 = NOID, bi3 = NOID, bi4 = NOID, bi5 = NOID,
@@ -333,7 +338,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
             const double d2 = dist2(dx, dy, dz);
             if (d2 < R2) {
                 ++nc;
-                set_bit(c0, c1, c2, k);
+                cm.set(k);
                 covered |= cover_bit(dx, dy, dz, margin);
                 const int oct = octant_of(dx, dy, dz);
                 const int32_t id = p.id;
@@ -358,30 +363,30 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     const int gm = ~covered & 0xFF;
     const int m_max = v.m_max;
     if (force_sorted || nc > 255) {
-        write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, 0);
+        write_rec(v, i, 0, gm, MODE_SORTED, Mask4());
         hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
         return;
     }
     if (nc <= m_max) {
-        write_rec(v, i, nc, gm, MODE_ALL, c0, c1, c2);
+        write_rec(v, i, nc, gm, MODE_ALL, cm);
         return;
     }
     const int32_t first[8] = {bk0, bk1, bk2, bk3, bk4, bk5, bk6, bk7};
     const double brs[8] = {br0, br1, br2_, br3, br4, br5, br6, br7};
-    uint64_t f0 = 0, f1 = 0, f2 = 0;   // octant-first entries
+    Mask4 fm;                          // octant-first entries
     int n_oct = 0;
 #pragma unroll
     for (int o = 0; o < 8; ++o)
         if (first[o] >= 0) {
             ++n_oct;
-            set_bit(f0, f1, f2, first[o]);
+            fm.set(first[o]);
             hist_add(hist, bucket_of(brs[o], scale), t, -1);
         }
     const int K = m_max - n_oct;
     int need = 0, hc = 0;
     const int bstar = K < 0 ? 0 : cut_bucket(hist, t, K, need, hc);
     if (K < 0 || (need < hc && hc > LIST_CAP)) {
-        write_rec(v, i, 0, gm, MODE_SORTED, 0, 0, 0);
+        write_rec(v, i, 0, gm, MODE_SORTED, Mask4());
         hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
         return;
     }
@@ -389,13 +394,13 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     // ---- pass 2: keep the octant-firsts and every lower bucket; collect
     // the members of the cut bucket when only some of them are kept
     const bool whole = need == hc;
-    uint64_t m0 = f0, m1 = f1, m2 = f2;
+    Mask4 mk = fm;
     int nl = 0;
     for (int k = 0; k < cnt; ++k) {
         const int kc = code[(int64_t)k * n + i];
         if (kc < bstar || (kc == bstar && whole)) {
-            set_bit(m0, m1, m2, k);
-        } else if (kc == bstar && !has_bit(f0, f1, f2, k)) {
+            mk.set(k);
+        } else if (kc == bstar && !fm.has(k)) {
             // member of the cut bucket
             const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
             const float f = (float)dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
@@ -431,9 +436,9 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
                 if (key_less(rb, idb, ra, ida)) ++rank;
             }
         }
-        if (rank < need) set_bit(m0, m1, m2, la);
+        if (rank < need) mk.set(la);
     }
-    write_rec(v, i, m_max, gm, 0, m0, m1, m2);
+    write_rec(v, i, m_max, gm, 0, mk);
 }
 
 // Exact path, one wavefront per particle: the candidates are collected

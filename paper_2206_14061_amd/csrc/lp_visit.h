@@ -106,6 +106,33 @@ __device__ __forceinline__ Rec load_rec(const View& v, int64_t i)
     return r;
 }
 
+// Set bits of a keep mask in ascending order (list indices).
+struct MaskWalk {
+    static_assert(MASK_WORDS == 4, "keep mask walk assumes four words");
+    uint64_t b0, b1, b2, b3;
+    __device__ __forceinline__ explicit MaskWalk(const Rec& r)
+        : b0(r.mask[0]), b1(r.mask[1]), b2(r.mask[2]), b3(r.mask[3]) {}
+    // next set bit; the caller pops at most popcount times
+    __device__ __forceinline__ int pop()
+    {
+        int k;
+        if (b0) {
+            k = __builtin_ctzll(b0);
+            b0 &= b0 - 1;
+        } else if (b1) {
+            k = 64 + __builtin_ctzll(b1);
+            b1 &= b1 - 1;
+        } else if (b2) {
+            k = 128 + __builtin_ctzll(b2);
+            b2 &= b2 - 1;
+        } else {
+            k = 192 + __builtin_ctzll(b3);
+            b3 &= b3 - 1;
+        }
+        return k;
+    }
+};
+
 // Calls f(pt, dx, dy, dz) for every stencil row of real particle i, in
 // ascending list order (the ghost rows are not visited: they follow from
 // r.gm).  Each lane walks only its own kept entries, so a wave runs as
@@ -123,23 +150,51 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
         }
         return;
     }
-    static_assert(MASK_WORDS == 3, "keep mask walk assumes three words");
-    uint64_t b0 = r.mask[0], b1 = r.mask[1], b2 = r.mask[2];
+    MaskWalk mw(r);
     for (int t = 0; t < r.m; ++t) {
-        int k;
-        if (b0) {
-            k = __builtin_ctzll(b0);
-            b0 &= b0 - 1;
-        } else if (b1) {
-            k = 64 + __builtin_ctzll(b1);
-            b1 &= b1 - 1;
-        } else {
-            k = 128 + __builtin_ctzll(b2);
-            b2 &= b2 - 1;
-        }
+        const int k = mw.pop();
         const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
         f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
     }
+}
+
+// visit_stencil with the rows of particle i spread over LPP adjacent
+// lanes: lane `sub` takes kept rows sub, sub + LPP, sub + 2 LPP, ...
+template <int LPP, class F>
+__device__ __forceinline__ void visit_stencil_sub(const View& v, const GridInfo& g,
+                                                  int64_t i, const Rec& r, int sub, F&& f)
+{
+    if (LPP == 1) {
+        visit_stencil(v, g, i, r, f);
+        return;
+    }
+    const int64_t n = v.n;
+    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    if (r.mode & MODE_SORTED) {
+        for (int k = sub; k < r.m; k += LPP) {
+            const Pt p = id_point(v, g, v.hsten[(int64_t)k * n + i]);
+            f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
+        }
+        return;
+    }
+    MaskWalk mw(r);
+    for (int t = 0; t < sub && t < r.m; ++t) mw.pop();
+    for (int t = sub; t < r.m; t += LPP) {
+        const int k = mw.pop();
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
+        for (int u = 1; u < LPP && t + u < r.m; ++u) mw.pop();
+    }
+}
+
+// sum of x over the LPP adjacent lanes of a particle (the same value in
+// every one of them: the butterfly adds the same operands in each lane)
+template <int LPP, class T>
+__device__ __forceinline__ T lane_sum(T x)
+{
+#pragma unroll
+    for (int off = 1; off < LPP; off <<= 1) x += __shfl_xor(x, off);
+    return x;
 }
 
 }  // namespace lp

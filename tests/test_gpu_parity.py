@@ -178,15 +178,20 @@ def test_rheology_rhs_parity(lp, case):
     assert np.array_equal(gf & 7, r["flags"] & 7)
 
 
+_STEP_PATHS = {"gram": {}, "qr": dict(debug_flags=1 << 1),
+               "lanes2": dict(debug_flags=1 << 2), "lanes4": dict(debug_flags=1 << 3)}
+
+
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("path", ["gram", "qr"])
+@pytest.mark.parametrize("path", list(_STEP_PATHS))
 def test_step_parity(lp, case, path):
     """lp_step against the oracle step: permutation exact; increments of
-    position, velocity and volume within 1e-10 of the oracle's."""
+    position, velocity and volume within 1e-10 of the oracle's.  Paths:
+    Gram fits, forced Householder refits, 2 and 4 lanes per particle."""
     wl = CASES[case]()
     _log("case %s path %s n=%d" % (case, path, wl.n))
     import torch
-    cfg = {} if path == "gram" else dict(debug_flags=lp.LP_DEBUG_QR_FIT)
+    cfg = _STEP_PATHS[path]
     ctx = lp.make_context(wl, **cfg)
     st = lp.DeviceState.from_host(wl.state)
     perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
@@ -197,6 +202,27 @@ def test_step_parity(lp, case, path):
     old = wl.state.take(operm)
     got = st.to_host()
     for k, (a, b, c) in enumerate(zip(got.arrays(), ost.arrays(), old.arrays())):
+        ok, e = _incr_ok(a, b, c)
+        assert ok, (lp.DeviceState.NAMES[k], e)
+
+
+def test_autotune_choice_and_step_parity(lp):
+    """lp_autotune picks 1, 2 or 4 lanes per particle for each fit; steps
+    afterwards still match the oracle."""
+    import torch
+    wl = CASES["sheared_20x20x12"]()
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    choice = ctx.lp_autotune(st)
+    _log("autotune choice %s" % (choice,))
+    assert choice[0] in (1, 2, 4) and choice[1] in (1, 2, 4)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    ctx.lp_step(st, wl.dt, perm)
+    ctx.sync_status()
+    ost, operm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt)
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = wl.state.take(operm)
+    for k, (a, b, c) in enumerate(zip(st.to_host().arrays(), ost.arrays(), old.arrays())):
         ok, e = _incr_ok(a, b, c)
         assert ok, (lp.DeviceState.NAMES[k], e)
 
@@ -332,6 +358,28 @@ def test_full_size_column_step_parity(lp):
         _log("  %s increment rel err %.3e; array rel err %.3e"
              % (lp.DeviceState.NAMES[k], e, _relerr(a, b)))
         assert ok and _relerr(a, b) <= TOL
+
+
+def test_full_size_sheared_column_step_parity(lp):
+    """The 128 x 128 x 64 sheared column (1,048,576 particles, stencils of
+    8 to 60 rows, some particles with up to 193 list entries), one step,
+    every particle against the oracle."""
+    import torch
+    wl = lpgen.column_sheared()
+    _log("column_sheared n=%d" % wl.n)
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    ctx.lp_step(st, wl.dt, perm)
+    ctx.sync_status()
+    _log("gpu stats %s" % ctx.stats())
+    ost, operm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt, brute=False)
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = wl.state.take(operm)
+    for k, (a, b, c) in enumerate(zip(st.to_host().arrays(), ost.arrays(), old.arrays())):
+        ok, e = _incr_ok(a, b, c)
+        _log("  %s increment rel err %.3e" % (lp.DeviceState.NAMES[k], e))
+        assert ok
 
 
 def test_error_paths_report_cleanly(lp):
