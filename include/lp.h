@@ -261,7 +261,9 @@ lp_status lp_step_graph(lp_ctx* ctx, lp_state* s, int32_t* ids, double dt,
  *               is ADDED to it.
  * Computes in float64 whatever the precision setting; requires unit
  * weights (LP_E_ARG otherwise).  Neighbour contributions are accumulated
- * with float64 atomics (summation order varies between runs).  Leaves the
+ * in per-row slots grouped by receiving particle (the slot order, and so
+ * the summation order, varies between runs).  m_max x particles must stay
+ * below 2^31 (LP_E_CAPACITY).  Leaves the
  * context without a neighbour list: the next lp_step rebuilds.  A
  * degenerate Gram matrix latches LP_E_NUMERIC (lp_sync_status). */
 lp_status lp_step_adjoint(lp_ctx* ctx, const lp_state* s, double dt,

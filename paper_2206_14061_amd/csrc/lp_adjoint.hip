@@ -24,8 +24,11 @@
 //             shear-rate norm has zero derivative where it is zero.
 //
 // Contributions to other particles (neighbour values and positions,
-// mirror sources) are scattered with float64 atomics, so sums are
-// accumulated in a run-dependent order.
+// mirror sources) are written, one record of six doubles per stencil row,
+// into slots grouped by receiving particle (a counting sort of the rows by
+// their point, built once per call with integer atomics); a gather pass
+// then adds each particle's slots.  The order of the slots of one particle
+// varies between runs, so sums are accumulated in a run-dependent order.
 #include <cmath>
 
 #include "lp_fitcore.h"
@@ -56,7 +59,22 @@ struct AdjBufs {
     double* dparams;     // n_sys x 3
     ErrWord* err;
     double dt;
+    const int32_t* slot; // m_max x n: slot of stencil row t of particle i
+    double* contrib;     // 6 per slot
 };
+
+// six contributions of one stencil row to the particle its point stands
+// for (a mirror's source)
+__device__ __forceinline__ void put_row(const AdjBufs& B, int64_t n, int64_t i, int t,
+                                        double c0, double c1, double c2, double c3,
+                                        double c4, double c5)
+{
+    const int64_t sl = B.slot[(int64_t)t * n + i];
+    double2* q = reinterpret_cast<double2*>(B.contrib + 6 * sl);
+    q[0] = make_double2(c0, c1);
+    q[1] = make_double2(c2, c3);
+    q[2] = make_double2(c4, c5);
+}
 
 // d(Taylor row)/d(xi) applied to a row cotangent Abar: returns xibar
 __device__ __forceinline__ void row_xi_bar(const double (&A)[9], double ex, double ey,
@@ -68,14 +86,145 @@ __device__ __forceinline__ void row_xi_bar(const double (&A)[9], double ex, doub
     gz = A[2] + A[5] * ez + A[7] * ex + A[8] * ey;
 }
 
-// position cotangent of a stencil point: reals take it, mirrors pass it to
-// their source with the z component reflected
-__device__ __forceinline__ void scatter_pos(const AdjBufs& B, const Pt& p, double dx,
-                                            double dy, double dz)
+// zero records in the slots of particle i (a particle whose reverse step
+// failed still owns its slots)
+__device__ __forceinline__ void zero_rows(const AdjBufs& B, const View& v,
+                                          const GridInfo& g, int64_t i, const Rec& r)
 {
-    atomicAdd(&B.a[0][p.src], dx);
-    atomicAdd(&B.a[1][p.src], dy);
-    atomicAdd(&B.a[2][p.src], p.mirror ? -dz : dz);
+    int t = 0;
+    visit_stencil(v, g, i, r, [&](const Pt&, double, double, double) {
+        put_row(B, v.n, i, t, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0);
+        ++t;
+    });
+}
+
+// ---- slots: rows grouped by the particle they contribute to ------------
+
+// cnt[j] = number of stencil rows (of all particles) whose point is j or
+// a mirror of j
+__global__ __launch_bounds__(BLOCK) void k_slot_count(View v, int32_t* cnt)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= v.n) return;
+    const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
+    const Rec r = load_rec(v, i);
+    visit_stencil(v, g, i, r, [&](const Pt& p, double, double, double) {
+        atomicAdd(&cnt[p.src], 1);
+    });
+}
+
+// exclusive scan of a[0..n) into b[0..n], tiles of BLOCK (three kernels)
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(int64_t n, const int32_t* a,
+                                                      int32_t* b, int32_t* tile)
+{
+    __shared__ int32_t ws[BLOCK / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + t;
+    const int32_t x = i < n ? a[i] : 0;
+    int32_t inc = x;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t o = __shfl_up(inc, d);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) ws[wave] = inc;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) {
+        if (w < wave) pre += ws[w];
+        tot += ws[w];
+    }
+    if (i < n) b[i] = pre + inc - x;
+    if (t == 0) tile[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_tile_sums(int64_t nt, int32_t* tile)
+{
+    // single block of 1024: each thread scans a contiguous chunk
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (nt + 1023) / 1024;
+    const int64_t b = t * chunk;
+    const int64_t e = (b + chunk < nt) ? b + chunk : nt;
+    int32_t sum = 0;
+    for (int64_t q = b; q < e; ++q) sum += tile[q];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int32_t o = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += o;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+    for (int64_t q = b; q < e; ++q) {
+        const int32_t x = tile[q];
+        tile[q] = run;
+        run += x;
+    }
+    if (t == 1023) tile[nt] = part[1023];
+}
+
+__global__ void k_scan_add(int64_t n, int32_t* b, const int32_t* tile)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) b[i] += tile[blockIdx.x];
+    if (i == 0) b[n] = tile[(n + BLOCK - 1) / BLOCK];
+}
+
+// slot of every stencil row: start of its point's range plus a place
+// taken with an atomic counter
+__global__ __launch_bounds__(BLOCK) void k_slot_assign(View v, const int32_t* off,
+                                                       int32_t* fill, int32_t* slot)
+{
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= v.n) return;
+    const int64_t n = v.n;
+    const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
+    const Rec r = load_rec(v, i);
+    int t = 0;
+    visit_stencil(v, g, i, r, [&](const Pt& p, double, double, double) {
+        slot[(int64_t)t * n + i] = off[p.src] + atomicAdd(&fill[p.src], 1);
+        ++t;
+    });
+}
+
+__global__ void k_zero_i32(int64_t n, int32_t* a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+// adds the records of each particle's slots: pass 2 (P, eta, V, x, y, z)
+// or pass 1 (u, v, w, x, y, z)
+__global__ __launch_bounds__(BLOCK) void k_slot_gather(int64_t n, const int32_t* off,
+                                                       AdjBufs B, int pass)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int32_t e = off[j + 1];
+    for (int32_t sl = off[j]; sl < e; ++sl) {
+        const double2* q = reinterpret_cast<const double2*>(B.contrib + 6 * (int64_t)sl);
+        const double2 a = q[0], b = q[1], d = q[2];
+        c[0] += a.x;
+        c[1] += a.y;
+        c[2] += b.x;
+        c[3] += b.y;
+        c[4] += d.x;
+        c[5] += d.y;
+    }
+    if (pass == 2) {
+        B.aP[j] += c[0];
+        B.aE[j] += c[1];
+        B.a[6][j] += c[2];
+    } else {
+        B.a[3][j] += c[0];
+        B.a[4][j] += c[1];
+        B.a[5][j] += c[2];
+    }
+    B.a[0][j] += c[3];
+    B.a[1][j] += c[4];
+    B.a[2][j] += c[5];
 }
 
 __global__ void k_adj_init(int64_t n, Ptr7 lam, double dt, AdjBufs B)
@@ -129,6 +278,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, Ptr7 lam, AdjBufs B
     if (!(ratio > 0.0)) {
         raise_error(B.err, ERR_NUMERIC, i);
         for (int q = 0; q < 11; ++q) B.stash[(int64_t)q * n + i] = 0.0;
+        zero_rows(B, v, g, i, r);
         return;
     }
     double cP[9], cE[9];
@@ -169,8 +319,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, Ptr7 lam, AdjBufs B
     const double T1 = -gP[1] + gd[3] * gE[0] + gd[1] * gE[1] + gd[5] * gE[2] + Ei * vis[1];
     const double T2 = -gP[2] + gd[4] * gE[0] + gd[5] * gE[1] + gd[2] * gE[2] + Ei * vis[2];
     const double inv_rho = 1.0 / prm.rho_s;
-    atomicAdd(&B.a[6][i], (abar[0] * T0 + abar[1] * T1 + abar[2] * T2) * inv_rho +
-                              dVbar * div);
+    B.a[6][i] += (abar[0] * T0 + abar[1] * T1 + abar[2] * T2) * inv_rho + dVbar * div;
     const double Tb[3] = {abar[0] * V * inv_rho, abar[1] * V * inv_rho,
                           abar[2] * V * inv_rho};
     double gPb[3], gEb[3];
@@ -206,6 +355,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, Ptr7 lam, AdjBufs B
         chol_solve<9>(U, yE);
     }
     double sP = 0.0, sE = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    int t = 0;
     for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
         double Pj, Ej;
         pass2_values(v, B.P, B.eta, p, prm, Pj, Ej);
@@ -220,15 +370,6 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, Ptr7 lam, AdjBufs B
         sP -= bP;
         sE -= bE;
         if (!p) return;   // ghost rows: constant rows, value 0
-        if (!p->mirror) {
-            atomicAdd(&B.aP[p->src], bP);
-            atomicAdd(&B.aE[p->src], bE);
-        } else {
-            // mirror pressure P(phi_src) of the quasi-static law
-            const double Vs = v.V[p->src];
-            if (1.0 / Vs > prm.phi_max)
-                atomicAdd(&B.a[6][p->src], -bP * prm.rho_s * prm.beta / (Vs * Vs));
-        }
         double Ab[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q)
@@ -238,16 +379,26 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, Ptr7 lam, AdjBufs B
         gx *= ih;
         gy *= ih;
         gz *= ih;
-        scatter_pos(B, *p, gx, gy, gz);
         sx -= gx;
         sy -= gy;
         sz -= gz;
+        if (!p->mirror) {
+            put_row(B, n, i, t, bP, bE, 0.0, gx, gy, gz);
+        } else {
+            // mirror pressure P(phi_src) of the quasi-static law; no eta
+            const double Vs = v.V[p->src];
+            const double dV = 1.0 / Vs > prm.phi_max
+                                  ? -bP * prm.rho_s * prm.beta / (Vs * Vs) : 0.0;
+            put_row(B, n, i, t, 0.0, 0.0, dV, gx, gy, -gz);
+        }
+        ++t;
     });
-    atomicAdd(&B.aP[i], sP);
-    atomicAdd(&B.aE[i], sE);
-    atomicAdd(&B.a[0][i], sx);
-    atomicAdd(&B.a[1][i], sy);
-    atomicAdd(&B.a[2][i], sz);
+    // this particle's own terms: no other thread writes them in this pass
+    B.aP[i] += sP;
+    B.aE[i] += sE;
+    B.a[0][i] += sx;
+    B.a[1][i] += sy;
+    B.a[2][i] += sz;
 }
 
 // ---- reverse of the closure and of the fit of u, v, w ----------------------
@@ -302,7 +453,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
         } else if (cl.branch == 2) {
             phib = Pb * prm.rho_s * prm.beta;
         }
-        atomicAdd(&B.a[6][i], -phib / (V * V));
+        B.a[6][i] += -phib / (V * V);
         if (cl.gn > 0.0) {
             const double q = gnb / cl.gn;
             gdb[0] += 0.5 * q * cl.gd[0];
@@ -357,6 +508,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
         const double ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
         if (!(ratio > 0.0)) {
             raise_error(B.err, ERR_NUMERIC, i);
+            zero_rows(B, v, g, i, r);
         } else {
             double y[3][9], cu[3][9];
 #pragma unroll
@@ -372,6 +524,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
             }
             const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
             double su[3] = {0.0, 0.0, 0.0}, sx = 0.0, sy = 0.0, sz = 0.0;
+            int t = 0;
             for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
                 double b[3] = {0.0, 0.0, 0.0};   // ghosts carry u_i
                 if (p) {
@@ -398,9 +551,6 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
                     for (int q = 0; q < 9; ++q) Ab[q] += rr * y[f][q] - yy * cu[f][q];
                 }
                 if (!p) return;   // ghost rows: constant, value u_i
-                atomicAdd(&B.a[3][p->src], bb[0]);
-                atomicAdd(&B.a[4][p->src], bb[1]);
-                atomicAdd(&B.a[5][p->src], p->mirror ? -bb[2] : bb[2]);
                 su[0] -= bb[0];
                 su[1] -= bb[1];
                 su[2] -= bb[2];
@@ -409,17 +559,19 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
                 gx *= ih;
                 gy *= ih;
                 gz *= ih;
-                scatter_pos(B, *p, gx, gy, gz);
                 sx -= gx;
                 sy -= gy;
                 sz -= gz;
+                const double sg = p->mirror ? -1.0 : 1.0;
+                put_row(B, n, i, t, bb[0], bb[1], sg * bb[2], gx, gy, sg * gz);
+                ++t;
             });
-            atomicAdd(&B.a[3][i], su[0]);
-            atomicAdd(&B.a[4][i], su[1]);
-            atomicAdd(&B.a[5][i], su[2]);
-            atomicAdd(&B.a[0][i], sx);
-            atomicAdd(&B.a[1][i], sy);
-            atomicAdd(&B.a[2][i], sz);
+            B.a[3][i] += su[0];
+            B.a[4][i] += su[1];
+            B.a[5][i] += su[2];
+            B.a[0][i] += sx;
+            B.a[1][i] += sy;
+            B.a[2][i] += sz;
         }
     }
     // parameter cotangents: one atomic per block when the block lies in
@@ -488,14 +640,30 @@ lp_status step_adjoint(lp_ctx* c, const double* const st[7], double dt,
         dlam.p[a] = lam[a];
         dout.p[a] = out[a];
     }
-    hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
-                       dlam, dt, B);
-    hipLaunchKernelGGL(k_adj_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, v,
-                       dlam, B);
-    hipLaunchKernelGGL(k_adj_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, v,
-                       B);
-    hipLaunchKernelGGL(k_adj_unpermute, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
-                       n, perm, B, dout);
+    // slots of the stencil rows, grouped by receiving particle
+    hipStream_t s = c->stream;
+    const int64_t nt = (n + BLOCK - 1) / BLOCK;
+    B.slot = w.adj_slot;
+    B.contrib = w.adj_contrib;
+    hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, w.adj_cnt);
+    hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, w.adj_fill);
+    hipLaunchKernelGGL(k_slot_count, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, w.adj_cnt);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(BLOCK), 0, s, n, w.adj_cnt,
+                       w.adj_off, w.adj_tile);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(1024), 0, s, nt, w.adj_tile);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(BLOCK), 0, s, n, w.adj_off,
+                       w.adj_tile);
+    hipLaunchKernelGGL(k_slot_assign, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v,
+                       w.adj_off, w.adj_fill, w.adj_slot);
+    hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, dlam, dt, B);
+    hipLaunchKernelGGL(k_adj_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, dlam, B);
+    hipLaunchKernelGGL(k_slot_gather, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
+                       (const int32_t*)w.adj_off, B, 2);
+    hipLaunchKernelGGL(k_adj_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, B);
+    hipLaunchKernelGGL(k_slot_gather, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
+                       (const int32_t*)w.adj_off, B, 1);
+    hipLaunchKernelGGL(k_adj_unpermute, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, perm, B,
+                       dout);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
     return LP_OK;

@@ -78,6 +78,8 @@ void free_work(Work& w)
     f(w.P); f(w.eta); f(w.hand); f(w.uf);
     for (int a = 0; a < 7; ++a) f(w.adj[a]);
     f(w.adj_P); f(w.adj_E); f(w.adj_stash); f(w.coefu); f(w.adj_perm);
+    f(w.adj_slot); f(w.adj_contrib); f(w.adj_cnt); f(w.adj_fill); f(w.adj_off);
+    f(w.adj_tile);
     f(w.gate); f(w.ids_tmp); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
@@ -244,6 +246,9 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     for (int a = 0; a < 7; ++a) A(w.adj[a], n_max);
     A(w.adj_P, n_max); A(w.adj_E, n_max); A(w.adj_stash, (int64_t)11 * n_max);
     A(w.coefu, (int64_t)27 * n_max); A(w.adj_perm, n_max);
+    A(w.adj_slot, (int64_t)mm * n_max); A(w.adj_contrib, (int64_t)6 * mm * n_max);
+    A(w.adj_cnt, n_max); A(w.adj_fill, n_max); A(w.adj_off, n_max + 1);
+    A(w.adj_tile, n_max / BLOCK + 2);
     A(w.gate, 4); A(w.ids_tmp, n_max);
     A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
     A(w.coff, n_max + 1);
@@ -570,6 +575,10 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
     if (c->cfg.weight != LP_W_UNIT) {
         c->err = "lp_step_adjoint supports unit weights only";
         return LP_E_ARG;
+    }
+    if ((int64_t)c->cfg.m_max * c->n >= (1ll << 31)) {
+        c->err = "lp_step_adjoint: m_max x particles must stay below 2^31";
+        return LP_E_CAPACITY;
     }
     double* in[7];
     state_arrays(s, in);

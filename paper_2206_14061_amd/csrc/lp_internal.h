@@ -155,6 +155,10 @@ struct Work {
     double* adj_stash = nullptr;          // 11 x n
     double* coefu = nullptr;              // 27 x n forward velocity coefficients
     int32_t* adj_perm = nullptr;
+    int32_t* adj_slot = nullptr;          // m_max x n
+    double* adj_contrib = nullptr;        // 6 x m_max x n
+    int32_t *adj_cnt = nullptr, *adj_fill = nullptr;   // n
+    int32_t *adj_off = nullptr, *adj_tile = nullptr;   // n + 1, n / BLOCK + 2
     // captured step sequences
     int32_t* gate = nullptr;              // [0] rebuild, [1] keep
     int32_t* ids_tmp = nullptr;
