@@ -13,13 +13,16 @@
 // others by key (r^2, id), m_max in all), one thread per particle, without
 // storing or sorting the candidates:
 //   pass 1: exact test of every list entry, count, octant coverage bits,
-//           nearest candidate per octant and a histogram of r^2 in 64
-//           buckets of R^2/64 (byte counters in LDS); each entry's bucket
-//           is stored as one byte; the bucket holding the cut follows from
-//           the histogram;
-//   pass 2: entries of lower buckets and the octant-firsts are kept; when
-//           the cut falls inside its bucket, that bucket's few members are
-//           ranked exactly by key in a per-thread LDS list.
+//           a histogram of r^2 in 64 buckets of R^2/64 (byte counters in
+//           LDS) and the lowest bucket of each octant (which holds the
+//           octant's first); each entry's bucket is stored as one byte;
+//           the bucket holding the cut follows from the histogram;
+//   pass 2: entries of lower buckets are kept (with them every octant
+//           first below the cut); when the cut falls inside its bucket,
+//           that bucket's few members are collected in a per-thread LDS
+//           list, the firsts among them found and the rest ranked exactly
+//           by key; an octant whose first lies above the cut (rare) gets
+//           it from a scan of that one bucket.
 // The result is a keep bitmask over the list entries (plus row count and
 // ghost mask); the fits walk its set bits.  Bucketing is monotone in r^2,
 // so the kept set equals the one a full sort by (r^2, id) gives.
@@ -304,8 +307,10 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     // cut-bucket members, one word each: r^2 rounded to float with its
     // low 8 bits replaced by the list index.  Rounding and truncation are
     // monotone, so a smaller word means a smaller r^2; equal truncated
-    // keys take the exact keys again.
+    // keys take the exact keys again.  loct: their octants (bit 7: the
+    // member is its octant's first).
     __shared__ uint32_t lkey[LIST_CAP][BLOCK];
+    __shared__ uint8_t loct[LIST_CAP][BLOCK];
     const int t = threadIdx.x;
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + t;
     if (i >= v.n) return;
@@ -321,15 +326,12 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     for (int q = 0; q < HIST_BUCKETS / 4; ++q) hist[q][t] = 0u;
 
     // ---- pass 1: exact test of every list entry; its bucket is stored
-    // (entry k of all lanes at once: coalesced)
+    // (entry k of all lanes at once: coalesced).  Per octant only the
+    // lowest bucket is tracked (a byte each in mb_lo / mb_hi): it holds
+    // the octant's first.
     int nc = 0, covered = 0;
     Mask4 cm;                          // candidate entries
-    double br0 = INFINITY, br1 = INFINITY, br2_ = INFINITY, br3 = INFINITY,
-           br4 = INFINITY, br5 = INFINITY, br6 = INFINITY, br7 = INFINITY;
-    int32_t bi0 = NOID, bi1 = NOID, bi2 = NOID, bi3 = NOID, bi4 = NOID, bi5 = NOID,
-            bi6 = NOID, bi7 = NOID;
-    int32_t bk0 = -1, bk1 = -1, bk2 = -1, bk3 = -1, bk4 = -1, bk5 = -1, bk6 = -1,
-            bk7 = -1;
+    uint32_t mb_lo = 0xFFFFFFFFu, mb_hi = 0xFFFFFFFFu;
     for (int k = 0; k < cnt; ++k) {
         const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
         uint8_t kc = NO_CAND;
@@ -341,20 +343,15 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
                 cm.set(k);
                 covered |= cover_bit(dx, dy, dz, margin);
                 const int oct = octant_of(dx, dy, dz);
-                const int32_t id = p.id;
-#define LP_UPD(o, BR, BI, BK)                                              \
-    if (oct == o && key_less(d2, id, BR, BI)) {                            \
-        BR = d2;                                                           \
-        BI = id;                                                           \
-        BK = k;                                                            \
-    }
-                LP_UPD(0, br0, bi0, bk0) LP_UPD(1, br1, bi1, bk1)
-                LP_UPD(2, br2_, bi2, bk2) LP_UPD(3, br3, bi3, bk3)
-                LP_UPD(4, br4, bi4, bk4) LP_UPD(5, br5, bi5, bk5)
-                LP_UPD(6, br6, bi6, bk6) LP_UPD(7, br7, bi7, bk7)
-#undef LP_UPD
-                const int b = bucket_of(d2, scale);
-                hist_add(hist, b, t, 1);
+                const uint32_t b = (uint32_t)bucket_of(d2, scale);
+                const bool hiw = oct >= 4;
+                const uint32_t sh = 8u * (uint32_t)(oct & 3);
+                const uint32_t word = hiw ? mb_hi : mb_lo;
+                const uint32_t nw = b < ((word >> sh) & 0xFFu)
+                                        ? (word & ~(0xFFu << sh)) | (b << sh) : word;
+                mb_hi = hiw ? nw : mb_hi;
+                mb_lo = hiw ? mb_lo : nw;
+                hist_add(hist, (int)b, t, 1);
                 kc = (uint8_t)b;
             }
         }
@@ -371,72 +368,115 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
         write_rec(v, i, nc, gm, MODE_ALL, cm);
         return;
     }
-    const int32_t first[8] = {bk0, bk1, bk2, bk3, bk4, bk5, bk6, bk7};
-    const double brs[8] = {br0, br1, br2_, br3, br4, br5, br6, br7};
-    Mask4 fm;                          // octant-first entries
+    auto minb = [&](int o) -> uint32_t {
+        return ((o < 4 ? mb_lo : mb_hi) >> (8 * (o & 3))) & 0xFFu;
+    };
     int n_oct = 0;
 #pragma unroll
     for (int o = 0; o < 8; ++o)
-        if (first[o] >= 0) {
+        if (minb(o) != 0xFFu) {
             ++n_oct;
-            fm.set(first[o]);
-            hist_add(hist, bucket_of(brs[o], scale), t, -1);
+            hist_add(hist, (int)minb(o), t, -1);
         }
     const int K = m_max - n_oct;
     int need = 0, hc = 0;
     const int bstar = K < 0 ? 0 : cut_bucket(hist, t, K, need, hc);
-    if (K < 0 || (need < hc && hc > LIST_CAP)) {
+    // octants whose first lies in the cut bucket (B) or above it (C); the
+    // others' firsts lie below the cut and are kept with their buckets
+    uint32_t octB = 0, octC = 0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const uint32_t mo = minb(o);
+        if (mo == (uint32_t)bstar) octB |= 1u << o;
+        else if (mo != 0xFFu && mo > (uint32_t)bstar) octC |= 1u << o;
+    }
+    const int nB = __popc(octB);
+    const bool partial = need < hc;
+    if (K < 0 || (partial && hc + nB > LIST_CAP)) {
         write_rec(v, i, 0, gm, MODE_SORTED, Mask4());
         hard[atomicAdd(hard_n, 1u)] = (int32_t)i;
         return;
     }
 
-    // ---- pass 2: keep the octant-firsts and every lower bucket; collect
-    // the members of the cut bucket when only some of them are kept
-    const bool whole = need == hc;
-    Mask4 mk = fm;
+    // ---- pass 2: keep every lower bucket; the cut bucket whole, or its
+    // members collected for exact ranking
+    Mask4 mk;
     int nl = 0;
     for (int k = 0; k < cnt; ++k) {
         const int kc = code[(int64_t)k * n + i];
-        if (kc < bstar || (kc == bstar && whole)) {
+        if (kc < bstar || (kc == bstar && !partial)) {
             mk.set(k);
-        } else if (kc == bstar && !fm.has(k)) {
-            // member of the cut bucket
+        } else if (kc == bstar) {
             const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
-            const float f = (float)dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
+            const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
+            const float f = (float)dist2(dx, dy, dz);
             lkey[nl][t] = (__float_as_uint(f) & ~0xFFu) | (uint32_t)k;
+            loct[nl][t] = (uint8_t)octant_of(dx, dy, dz);
             ++nl;
         }
     }
-    // the `need` smallest keys (r^2, id) of the cut bucket
     auto exact_key = [&](int k, double& r2, int32_t& id) {
         const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
         r2 = dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
         id = p.id;
     };
-    for (int a = 0; a < nl; ++a) {
-        const uint32_t ka = lkey[a][t];
-        const int la = (int)(ka & 0xFFu);
-        int rank = 0;
-        bool have_a = false;
-        double ra = 0.0;
-        int32_t ida = 0;
-        for (int b = 0; b < nl; ++b) {
-            const uint32_t kb = lkey[b][t];
-            if ((kb >> 8) < (ka >> 8)) {
-                ++rank;
-            } else if ((kb >> 8) == (ka >> 8) && b != a) {
-                if (!have_a) {
-                    exact_key(la, ra, ida);
-                    have_a = true;
+    // is member b's key (r^2, id) below member a's?
+    auto below = [&](int b, int a) {
+        const uint32_t ka = lkey[a][t], kb = lkey[b][t];
+        if ((kb >> 8) != (ka >> 8)) return (kb >> 8) < (ka >> 8);
+        double ra, rb;
+        int32_t ia, ib;
+        exact_key((int)(ka & 0xFFu), ra, ia);
+        exact_key((int)(kb & 0xFFu), rb, ib);
+        return key_less(rb, ib, ra, ia);
+    };
+    if (partial) {
+        // firsts of the B octants among the members: kept, not ranked
+        if (octB) {
+            for (int a = 0; a < nl; ++a) {
+                const int o = loct[a][t];
+                if (!((octB >> o) & 1u)) continue;
+                bool first = true;
+                for (int b = 0; b < nl && first; ++b)
+                    if (b != a && (loct[b][t] & 7) == o && below(b, a)) first = false;
+                if (first) {
+                    loct[a][t] = (uint8_t)(o | 0x80);
+                    mk.set((int)(lkey[a][t] & 0xFFu));
                 }
-                double rb;
-                int32_t idb;
-                exact_key((int)(kb & 0xFFu), rb, idb);
-                if (key_less(rb, idb, ra, ida)) ++rank;
             }
         }
-        if (rank < need) mk.set(la);
+        // the `need` smallest keys of the other members
+        for (int a = 0; a < nl; ++a) {
+            if (loct[a][t] & 0x80) continue;
+            int rank = 0;
+            for (int b = 0; b < nl; ++b)
+                if (b != a && !(loct[b][t] & 0x80) && below(b, a)) ++rank;
+            if (rank < need) mk.set((int)(lkey[a][t] & 0xFFu));
+        }
+    }
+    // firsts of the C octants (rare): the smallest key of the octant in
+    // its lowest bucket
+    if (octC) {
+        for (int o = 0; o < 8; ++o) {
+            if (!((octC >> o) & 1u)) continue;
+            const int mo = (int)minb(o);
+            double br = INFINITY;
+            int32_t bi = NOID;
+            int bk = -1;
+            for (int k = 0; k < cnt; ++k) {
+                if (code[(int64_t)k * n + i] != mo) continue;
+                const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+                const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
+                if (octant_of(dx, dy, dz) != o) continue;
+                const double r2 = dist2(dx, dy, dz);
+                if (key_less(r2, p.id, br, bi)) {
+                    br = r2;
+                    bi = p.id;
+                    bk = k;
+                }
+            }
+            if (bk >= 0) mk.set(bk);
+        }
     }
     write_rec(v, i, m_max, gm, 0, mk);
 }
