@@ -83,7 +83,7 @@ class Context:
     """An lp_ctx bound to the current CUDA device and stream."""
 
     def __init__(self, m_max: int = 60, precision: int = LP_FP64,
-                 cond_max: float = 100.0, weight: int = LP_W_UNIT,
+                 cond_max: float = 20.0, weight: int = LP_W_UNIT,
                  ghost_margin: float = 0.5, fallback_tol: float = 1e-12,
                  debug_flags: int = 0, skin: float = 0.1, stream=None):
         torch = _torch()

@@ -157,7 +157,7 @@ void lp_config_default(lp_config* cfg)
     if (!cfg) return;
     cfg->m_max = 60;
     cfg->precision = LP_FP64;
-    cfg->cond_max = 100.0;
+    cfg->cond_max = 20.0;
     cfg->weight = LP_W_UNIT;
     cfg->ghost_margin = 0.5;
     cfg->fallback_tol = 1e-12;

@@ -623,7 +623,9 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float
     gram_from_moments(M, U);
     const bool lin = mt < 9;
     const float ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
-    if (!(ratio >= (float)v.redo_ratio)) {
+    // one float32 correction step needs a better conditioned factor than
+    // the float64 path: four times the pivot-ratio threshold
+    if (!(ratio >= 4.0f * (float)v.redo_ratio)) {
         redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
         o.flags[i] = FLAG_QR;
         return;

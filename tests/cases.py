@@ -33,10 +33,25 @@ def _exact_lattice(nx=12, ny=10, nz=9):
     return lpgen.Workload("lattice_exact", st, np.array([0, st.n]), [p], 1e-4, 1)
 
 
+def _sparse_cloud(n=1500, seed=11):
+    """Seeded random cloud of 1500 particles in a 1.5 m box on the wall,
+    about 7 neighbours each within R: many particles have fewer than 9 rows
+    (linear fallback), uncovered octants (ghosts) and gas-regime volumes."""
+    h = 1.0 / 16.0
+    p = lpgen.default_params(h)
+    u = lpgen.uniform01(seed, np.arange(7 * n, dtype=np.uint64)).reshape(7, n)
+    side = 1.5
+    st = lpgen.State(side * u[0], side * u[1], side * u[2] + 0.001,
+                     0.2 * (u[3] - 0.5), 0.2 * (u[4] - 0.5), 0.2 * (u[5] - 0.5),
+                     1.0 / (0.30 + 0.32 * u[6]))
+    return lpgen.Workload("sparse_cloud", st, np.array([0, n]), [p], 1e-4, 1)
+
+
 CASES = {
     "column16": lambda: lpgen.column_small(),
     "lattice_exact": lambda: _with_flow(_exact_lattice()),
     "column16_flow_ragged": lambda: _ragged(_with_flow(lpgen.column_small())),
     "sheared_20x20x12": lambda: lpgen.column_sheared(nx=20, ny=20, nz=12),
     "ensemble_3": lambda: _with_flow(lpgen.ensemble(n_sys=3, n_lo=600, n_hi=3000)),
+    "sparse_cloud": lambda: _sparse_cloud(),
 }

@@ -32,7 +32,7 @@ def _dev(arrs):
 
 
 @pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
-                                  "ensemble_3", "lattice_exact"])
+                                  "ensemble_3", "lattice_exact", "sparse_cloud"])
 def test_step_adjoint_parity(lp, case):
     import torch
     wl = CASES[case]()

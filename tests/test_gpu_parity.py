@@ -206,6 +206,44 @@ def test_step_parity(lp, case, path):
         assert ok, (lp.DeviceState.NAMES[k], e)
 
 
+@pytest.mark.parametrize("m_max", [9, 20, 64])
+def test_step_parity_other_stencil_caps(lp, m_max):
+    """The stencil cap m_max (9 = the unknowns, 64 = the largest supported)
+    changes which candidates are kept; the step still matches the oracle
+    run with the same cap."""
+    import torch
+    wl = CASES["column16_flow_ragged"]()
+    _log("m_max %d" % m_max)
+    ctx = lp.make_context(wl, m_max=m_max)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    ctx.lp_step(st, wl.dt, perm)
+    ctx.sync_status()
+    ost, operm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt,
+                                cfg=dict(m_max=m_max))
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = wl.state.take(operm)
+    for k, (a, b, c) in enumerate(zip(st.to_host().arrays(), ost.arrays(), old.arrays())):
+        ok, e = _incr_ok(a, b, c)
+        assert ok, (lp.DeviceState.NAMES[k], e)
+
+
+def test_neighbour_list_overflow_is_reported(lp):
+    """A cluster denser than the neighbour list holds (more than 256
+    entries within the list radius) latches LP_E_CAPACITY; every kernel
+    stays within its buffers and the call returns normally."""
+    h = 1.0 / 16.0
+    p = lpgen.default_params(h)
+    st0 = lpgen.lattice_column(8, 8, 8, h / 4, seed=9, params=p)   # spacing h/4
+    wl = lpgen.Workload("cluster", st0, np.array([0, st0.n]), [p], 1e-5, 1)
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(st0)
+    ctx.lp_step(st, wl.dt)
+    with pytest.raises(lp.LPError) as e:
+        ctx.sync_status()
+    assert e.value.status == 2
+
+
 def test_autotune_choice_and_step_parity(lp):
     """lp_autotune picks 1, 2 or 4 lanes per particle for each fit; steps
     afterwards still match the oracle."""
