@@ -55,7 +55,7 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--adjoint-steps", type=int, default=50)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-sheared", action="store_true")
