@@ -55,6 +55,30 @@ def test_step_adjoint_parity(lp, case):
     assert e <= 1e-9
 
 
+def test_full_size_adjoint_step_parity(lp):
+    """The 32 x 32 x 128 column (131,072 particles) of the gradient
+    benchmark: one step adjoint, every particle against the oracle."""
+    import torch
+    wl = lpgen.column_adjoint()
+    _log("column_adjoint n=%d (adjoint)" % wl.n)
+    lam = _lam(wl, 45)
+    want, wth, operm = adjoint.step_vjp(wl.state, wl.offsets, wl.params, wl.dt, lam)
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    dth = torch.zeros(1, 3, dtype=torch.float64, device="cuda")
+    got, perm = ctx.lp_step_adjoint(st, wl.dt, _dev(lam), dth, want_perm=True)
+    ctx.sync_status()
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    for k, (a, b) in enumerate(zip(got.to_host().arrays(), want)):
+        e = _relerr(a, b)
+        _log("  d/d%s rel err %.3e" % (lp.DeviceState.NAMES[k], e))
+        assert e <= TOL, (lp.DeviceState.NAMES[k], e)
+    gth = dth.cpu().numpy()
+    scale = max(np.max(np.abs(wth)), 1e-300)
+    _log("  d/dtheta %s vs %s" % (gth.tolist(), wth.tolist()))
+    assert np.max(np.abs(gth - wth)) <= 1e-9 * scale or np.max(np.abs(wth)) == 0.0
+
+
 def test_step_adjoint_dot_product_with_gpu_differences(lp):
     """<lam, J v> by central differences of the GPU step (lp_build_cells +
     lp_step) against <J^T lam, v> from lp_step_adjoint, for directions in
