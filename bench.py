@@ -62,6 +62,7 @@ def _parse():
     ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--ensemble-adjoint-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-second-order", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three 1 GiB device-to-device copies, the "
                          "reference for the HBM byte counters")
@@ -185,6 +186,30 @@ def sheared_bench(torch, lp, lpgen, steps: int):
         del ctx, st
     out["fp32r_speedup_vs_fp64"] = out["fp32r"]["value"] / out["fp64"]["value"]
     return out
+
+
+def second_order_bench(torch, lp, wl, steps: int, warmup: int, precision: int,
+                       ms_first_order: float):
+    """lp_step2 (Heun: two right-hand-side evaluations per step) on the
+    benchmark column: steps per second and RHS evaluations per second."""
+    ctx = lp.make_context(wl, precision=precision)
+    st = lp.DeviceState.from_host(wl.state)
+    for _ in range(warmup):
+        ctx.lp_step2(st, wl.dt)
+    ctx.sync_status()
+    ctx.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.lp_step2(st, wl.dt)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ctx.sync_status()
+    ms = 1e3 * t / steps
+    return {"ms_per_step": ms, "value": wl.n / (ms * 1e-3), "unit": "particle-updates/s",
+            "rhs_evals_per_step": 2, "particle_rhs_evals_per_s": 2 * wl.n / (ms * 1e-3),
+            "cost_vs_first_order_step": ms / ms_first_order, "steps": steps,
+            "stats": ctx.stats()}
 
 
 def ensemble_bench(torch, lp, lpgen, steps: int, adjoint_steps: int):
@@ -351,6 +376,9 @@ def main():
            "phases_ms": phases, "stats": stats, "other_precision": compare,
            "ms_per_step_rebuild_every_step": ms_rebuild,
            "roofline": roof}
+    if not args.no_second_order:
+        out["second_order"] = second_order_bench(torch, lp, wl, args.steps, args.warmup,
+                                                 main_prec, ms_per_step)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
     if not args.no_sheared:

@@ -219,6 +219,22 @@ lp_status lp_rheology_rhs(lp_ctx* ctx, const lp_state* s,
  * dt > 0.  A non-finite result latches LP_E_NUMERIC (lp_sync_status). */
 lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
 
+/* One second-order step (Heun's predictor-corrector; the higher-order time
+ * integration the conclusions list as further work, built from two
+ * evaluations of the right-hand side f of Sec. 2.1 / Sec. 3.1 step 7):
+ *   s* = s + dt f(s)   (x* = x + dt u, u* = u + dt acc, V* = V + dt dVdt)
+ *   x' = x + dt (u + u*)/2,  u' = u + dt (acc(s) + acc(s*))/2,
+ *   V' = V + dt (dVdt(s) + dVdt(s*))/2.
+ * Mirrors and stencils are re-selected at s*, from the neighbour list of s.
+ * Re-sort and list rebuild as in lp_step, but already once some particle
+ * has moved 0.4 skin R since the build, so that the predictor stays within
+ * half the skin; if some particle of s* is not, the step latches an error
+ * that lp_sync_status reports as LP_E_STATE (reduce dt or raise skin).
+ * Needs skin > 0 (LP_E_ARG otherwise).  State order, perm, dt and
+ * non-finite results as for lp_step; the two kinds of step may alternate
+ * on one state. */
+lp_status lp_step2(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
+
 /* Chooses how many adjacent lanes of a wavefront share one particle in
  * each of the two least-squares fit kernels (1, 2 or 4: each lane takes
  * every 1st, 2nd or 4th stencil row and the Gram moments are summed across

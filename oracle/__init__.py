@@ -274,3 +274,35 @@ def step(state: State, offsets, params: Sequence[Params], dt: float,
     r = o.evaluate()
     update(st, offsets, params, dt, r["acc"], r["dVdt"])
     return st, perm, r
+
+
+def step2(state: State, offsets, params: Sequence[Params], dt: float,
+          cfg: Optional[dict] = None, brute: Optional[bool] = None,
+          skin: float = SKIN_DEFAULT, sort: bool = True):
+    """One second-order step by Heun's method (the explicit trapezoidal
+    rule), the higher-order time integration the paper's conclusions leave
+    for later, applied to the right-hand side f of Sec. 2.1 as evaluated in
+    Sec. 3.1 step 7:  s* = s + dt f(s),  s' = s + dt (f(s) + f(s*)) / 2,
+    with f = (u, acc, dVdt) for (x, V u, V) read as (x, u, V).  The predictor
+    is evaluated in the order of s (neighbours and stencils selected afresh
+    at s*).  Returns (new state, perm new->old, (RHS at s, RHS at s*))."""
+    if sort:
+        perm, _ = sort_perm(state, offsets, params, skin)
+    else:
+        perm = np.arange(state.n, dtype=np.int32)
+    st = state.take(perm)
+    st = State(*[np.ascontiguousarray(a, dtype=np.float64) for a in st.arrays()])
+    r1 = Oracle(st, offsets, params, cfg, brute).evaluate()
+    a1, d1 = r1["acc"], r1["dVdt"]
+    vel = (st.u, st.v, st.w)
+    pred = State(st.x + dt * st.u, st.y + dt * st.v, st.z + dt * st.w,
+                 st.u + dt * a1[0], st.v + dt * a1[1], st.w + dt * a1[2],
+                 st.V + dt * d1)
+    r2 = Oracle(pred, offsets, params, cfg, brute).evaluate()
+    a2, d2 = r2["acc"], r2["dVdt"]
+    pvel = (pred.u, pred.v, pred.w)
+    half = 0.5 * dt
+    pos = [p + half * (q + qs) for p, q, qs in zip((st.x, st.y, st.z), vel, pvel)]
+    new_vel = [q + half * (a1[k] + a2[k]) for k, q in enumerate(vel)]
+    out = State(*pos, *new_vel, st.V + half * (d1 + d2))
+    return out, perm, (r1, r2)

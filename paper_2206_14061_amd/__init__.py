@@ -4,7 +4,7 @@ The method's work runs in the HIP library ``liblp_gfx950.so`` behind the C
 ABI of ``include/lp.h``; this module only marshals torch CUDA tensors
 (device memory and the current stream) into those calls.  Function names
 follow the C ABI: ``lp_build_cells``, ``lp_neighbors``, ``lp_fit_derivs``,
-``lp_rheology_rhs``, ``lp_step``, ``lp_step_adjoint``.
+``lp_rheology_rhs``, ``lp_step``, ``lp_step2``, ``lp_step_adjoint``.
 """
 from __future__ import annotations
 
@@ -210,6 +210,11 @@ class Context:
     def lp_step(self, st: DeviceState, dt: float, perm=None):
         s = st.struct()
         self._check(self.lib.lp_step(self.h, C.byref(s), float(dt), _ptr(perm)))
+
+    def lp_step2(self, st: DeviceState, dt: float, perm=None):
+        """Second-order (Heun) step; same state order and perm as lp_step."""
+        s = st.struct()
+        self._check(self.lib.lp_step2(self.h, C.byref(s), float(dt), _ptr(perm)))
 
     def lp_autotune(self, st: DeviceState):
         """Times 1, 2 and 4 lanes per particle in both fits on st's stencils

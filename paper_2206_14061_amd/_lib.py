@@ -25,8 +25,8 @@ STATUS_NAMES = {0: "LP_OK", 1: "LP_E_ARG", 2: "LP_E_CAPACITY",
 # every symbol include/lp.h declares
 EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_last_error",
            "lp_reserve", "lp_set_systems", "lp_build_cells", "lp_neighbors",
-           "lp_fit_derivs", "lp_rheology_rhs", "lp_step", "lp_autotune", "lp_step_graph",
-           "lp_step_adjoint",
+           "lp_fit_derivs", "lp_rheology_rhs", "lp_step", "lp_step2", "lp_autotune",
+           "lp_step_graph", "lp_step_adjoint",
            "lp_sync_status", "lp_stats", "lp_profile", "lp_profile_read"]
 
 
@@ -93,6 +93,8 @@ def load():
     lib.lp_rheology_rhs.restype = C.c_int
     lib.lp_step.argtypes = [P, pp(LPState), C.c_double, P]
     lib.lp_step.restype = C.c_int
+    lib.lp_step2.argtypes = [P, pp(LPState), C.c_double, P]
+    lib.lp_step2.restype = C.c_int
     lib.lp_autotune.argtypes = [P, pp(LPState), pp(C.c_int32)]
     lib.lp_autotune.restype = C.c_int
     lib.lp_step_graph.argtypes = [P, pp(LPState), P, C.c_double, i32]

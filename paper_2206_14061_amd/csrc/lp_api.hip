@@ -80,7 +80,9 @@ void free_work(Work& w)
     f(w.adj_P); f(w.adj_E); f(w.adj_stash); f(w.coefu); f(w.adj_perm);
     f(w.adj_slot); f(w.adj_contrib); f(w.adj_cnt); f(w.adj_fill); f(w.adj_off);
     f(w.adj_tile);
-    f(w.gate); f(w.ids_tmp); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
+    f(w.gate); f(w.ids_tmp);
+    for (int a = 0; a < 7; ++a) f(w.sst2[a]);
+    f(w.acc2); f(w.dVdt2); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
     w.n_max = w.cells_max = 0;
@@ -250,6 +252,8 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.adj_cnt, n_max); A(w.adj_fill, n_max); A(w.adj_off, n_max + 1);
     A(w.adj_tile, n_max / BLOCK + 2);
     A(w.gate, 4); A(w.ids_tmp, n_max);
+    for (int a = 0; a < 7; ++a) A(w.sst2[a], n_max);
+    A(w.acc2, 3 * n_max); A(w.dVdt2, n_max);
     A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
     A(w.coff, n_max + 1);
     if (e == hipSuccess) e = hipHostMalloc((void**)&w.h_summary, sizeof(Summary));
@@ -447,6 +451,44 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
     return r;
 }
 
+lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
+{
+    if (!s || !(dt > 0.0) || !std::isfinite(dt)) {
+        if (c) c->err = "lp_step2: dt must be positive and finite";
+        return LP_E_ARG;
+    }
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    if (!(c->cfg.skin > 0.0)) {
+        c->err = "lp_step2 needs a neighbour-list skin > 0 (its predictor stage "
+                 "reuses the list)";
+        return LP_E_ARG;
+    }
+    double* in[7];
+    state_arrays(s, in);
+    // rebuild earlier than lp_step: the predictor stage moves particles a
+    // further dt |u| on the same list and must stay within half the skin
+    bool rebuild = !c->list_ok;
+    if (!rebuild) {
+        double ratio = -1.0;
+        r = list_displacement(c, in, &ratio);
+        if (r != LP_OK) return r;
+        rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.4);
+    }
+    r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm);
+    if (r != LP_OK) return r;
+    if (rebuild) ++c->rebuilds;
+    const double* sorted[7];
+    for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
+    r = stencils_build(c, sorted);
+    if (r == LP_OK) r = step_rhs(c, sorted);
+    if (r == LP_OK) r = step_pass2(c, sorted, dt, nullptr, c->w.acc, c->w.dVdt);
+    if (r == LP_OK) r = step_heun(c, dt, in);
+    c->stencils_ok = false;
+    c->built_x = nullptr;
+    return r;
+}
+
 lp_status lp_profile(lp_ctx* c, int32_t enable)
 {
     if (!c) return LP_E_ARG;
@@ -623,6 +665,12 @@ lp_status lp_sync_status(lp_ctx* c, int64_t* index)
                        c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (index) *index = (int64_t)ew.index;
+    if (ew.code & ERR_LIST) {
+        c->err = "the predictor stage of a second-order step moved particle " +
+                 std::to_string(ew.index) +
+                 " beyond the neighbour-list skin: reduce dt or increase skin";
+        return LP_E_STATE;
+    }
     if (ew.code & ERR_CAPACITY) {
         c->err = "device capacity exceeded (too many candidates for the sorted "
                  "stencil path) at particle " + std::to_string(ew.index);

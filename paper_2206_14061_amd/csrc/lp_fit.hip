@@ -1004,14 +1004,14 @@ lp_status step_pass1_coef(lp_ctx* c, const double* const st[7])
     return LP_OK;
 }
 
-lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
-                      double* const out[7])
+lp_status step_pass2(lp_ctx* c, const double* const st[7], double dt,
+                     double* const out[7], double* acc, double* dVdt)
 {
     Work& w = c->w;
     const int64_t n = c->n;
     View v = make_view(c, st);
-    RhsOut o = rhs_out(c, w.acc, w.dVdt, nullptr);
-    for (int a = 0; a < 7; ++a) o.out[a] = out[a];
+    RhsOut o = rhs_out(c, acc, dVdt, nullptr);
+    for (int a = 0; a < 7; ++a) o.out[a] = out ? out[a] : nullptr;
     o.dt = dt;
     if (n > 0) {
         prof_mark(c, 5, false);
@@ -1033,6 +1033,12 @@ lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "pass-2 launch");
     return LP_OK;
+}
+
+lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
+                      double* const out[7])
+{
+    return step_pass2(c, st, dt, out, c->w.acc, c->w.dVdt);
 }
 
 lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice)

@@ -41,6 +41,7 @@ constexpr uint8_t FLAG_QR = 8;
 // device error codes (bit set in the error word)
 constexpr int ERR_CAPACITY = 1;
 constexpr int ERR_NUMERIC = 2;
+constexpr int ERR_LIST = 4;       // a predictor stage left the neighbour list
 
 // Per-system grid, built on the device from the bounding box.
 struct GridInfo {
@@ -161,6 +162,10 @@ struct Work {
     int32_t *adj_off = nullptr, *adj_tile = nullptr;   // n + 1, n / BLOCK + 2
     // captured step sequences
     int32_t* gate = nullptr;              // [0] rebuild, [1] keep
+    // second-order steps: predictor state and its right-hand side
+    double* sst2[7] = {nullptr};
+    double* acc2 = nullptr;               // 3 x n
+    double* dVdt2 = nullptr;
     int32_t* ids_tmp = nullptr;
     double* acc = nullptr;                // 3 x n
     double* dVdt = nullptr;
@@ -337,6 +342,12 @@ lp_status step_rhs(lp_ctx* c, const double* const st[7]);
 // times each lanes-per-particle variant of the two fit kernels on the
 // stencils of st and keeps the fastest (choice: host int32[2], optional)
 lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice);
+// pass 2 with acc / dVdt stored and, when out is given, the explicit
+// update written to out
+lp_status step_pass2(lp_ctx* c, const double* const st[7], double dt,
+                     double* const out[7], double* acc, double* dVdt);
+// second-order (Heun) step on the sorted working state (lp_step2)
+lp_status step_heun(lp_ctx* c, double dt, double* const out[7]);
 // pass 1 in float64 with the velocity coefficients stored (adjoint input)
 lp_status step_pass1_coef(lp_ctx* c, const double* const st[7]);
 // reverse of the step on the sorted state st (after step_pass1_coef);
