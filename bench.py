@@ -105,12 +105,13 @@ def pass1_traffic():
                      + rec["write_kib"] * rec["write_scale"])
 
 
-def adjoint_bench(torch, lp, lpgen, steps: int, warmup: int = 1):
+def adjoint_bench(torch, lp, lpgen, steps: int, warmup: int = 1, order: int = 1):
     """Gradient of the runout loss L = sum softplus((x - 0.3 m)/h) after
-    `steps` steps of the 32 x 32 x 128 column (131,072 particles, dt =
-    5e-5 s) with respect to the initial state and (mu_s, mu_2, I0), with a
-    checkpoint every 10 steps: forward with checkpoints, then recompute and
-    reverse.  Returns adjoint step-pairs/s and the split."""
+    `steps` steps (explicit, or second-order with order 2) of the 32 x 32 x
+    128 column (131,072 particles, dt = 5e-5 s) with respect to the initial
+    state and (mu_s, mu_2, I0), with a checkpoint every 10 steps: forward
+    with checkpoints, then recompute and reverse.  Returns adjoint
+    step-pairs/s and the split."""
     from paper_2206_14061_amd.autograd import simulate
     wl = lpgen.column_adjoint()
     h = wl.params[0].h
@@ -125,7 +126,7 @@ def adjoint_bench(torch, lp, lpgen, steps: int, warmup: int = 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = simulate(ctx, wl.offsets, wl.params, state, theta, wl.dt, steps,
-                       checkpoint_every=10)
+                       checkpoint_every=10, order=order)
         loss = torch.nn.functional.softplus((out[0] - 0.3) / h).sum()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -138,7 +139,7 @@ def adjoint_bench(torch, lp, lpgen, steps: int, warmup: int = 1):
     for _ in range(warmup):
         once()
     tf, tb, loss, gth, gu = once()
-    return {"workload": wl.name, "particles": wl.n, "steps": steps,
+    return {"workload": wl.name, "particles": wl.n, "steps": steps, "order": order,
             "checkpoint_every": 10, "dt": wl.dt,
             "step_pairs_per_s": steps / (tf + tb),
             "ms_forward": 1e3 * tf, "ms_backward": 1e3 * tb, "loss": loss,
@@ -381,6 +382,9 @@ def main():
                                                  main_prec, ms_per_step)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
+        if not args.no_second_order:
+            out["adjoint_second_order"] = adjoint_bench(torch, lp, lpgen,
+                                                        args.adjoint_steps, order=2)
     if not args.no_sheared:
         out["sheared"] = sheared_bench(torch, lp, lpgen, 20)
     if not args.no_ensemble:

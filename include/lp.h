@@ -146,7 +146,7 @@ lp_status lp_set_systems(lp_ctx* ctx, int32_t n_sys, const int64_t* offsets,
  * (x, y, 2 wall_z - z), velocity (u, v, -w), same V, id n + k in
  * ascending source order).  Synchronises the stream once (grid sizes).
  * LP_E_CAPACITY if the cells exceed the reservation or a cell coordinate
- * needs more than 16 bits; more than 192 list entries for a particle
+ * needs more than 16 bits; more than 256 list entries for a particle
  * latch LP_E_CAPACITY (lp_sync_status). */
 lp_status lp_build_cells(lp_ctx* ctx, lp_state* s, int32_t* perm);
 
@@ -288,6 +288,21 @@ lp_status lp_step_graph(lp_ctx* ctx, lp_state* s, int32_t* ids, double dt,
 lp_status lp_step_adjoint(lp_ctx* ctx, const lp_state* s, double dt,
                           const lp_state* adj_out, lp_state* adj_in,
                           double* adj_params, int32_t* perm);
+
+/* Adjoint of one second-order step: lp_build_cells followed by lp_step2 on
+ * s, reversed through both stages of Heun's rule with the stencils of s and
+ * of the predictor s* held fixed (as lp_step_adjoint holds those of its
+ * step):  with f = (u, acc, dVdt) and lam' = dL/d(s'),
+ *   lam* = dL/d(s*) = J_f(s*)^T (dt/2 lam'),
+ *   dL/d(s) = lam' + lam* + J_f(s)^T (dt (lam'/2 + lam*)).
+ * Arguments, orders, float64 arithmetic, unit weights, capacity limit and
+ * the effect on the context as for lp_step_adjoint; needs skin > 0, and the
+ * predictor must stay within half the skin (else the error latches as in
+ * lp_step2).  Recomputes the forward stages (pass 1 at s twice, once at
+ * s*). */
+lp_status lp_step2_adjoint(lp_ctx* ctx, const lp_state* s, double dt,
+                           const lp_state* adj_out, lp_state* adj_in,
+                           double* adj_params, int32_t* perm);
 
 /* Synchronises the context's stream and returns the first latched device
  * error (LP_OK if none), then clears it.  *index (host, optional)

@@ -101,6 +101,20 @@ class FrozenStep:
         return torch.linalg.solve(G, R)
 
     def forward(self, x, y, z, u, v, w, V, theta):
+        acc, dVdt = self.rhs(x, y, z, u, v, w, V, theta)
+        dt = self.dt
+        un = u + dt * acc[0]
+        vn = v + dt * acc[1]
+        wn = w + dt * acc[2]
+        xn = x + dt * (0.5 * (u + un))
+        yn = y + dt * (0.5 * (v + vn))
+        zn = z + dt * (0.5 * (w + wn))
+        Vn = V + dt * dVdt
+        return xn, yn, zn, un, vn, wn, Vn
+
+    def rhs(self, x, y, z, u, v, w, V, theta):
+        """Acceleration (3 tensors) and dV/dt of Sec. 2.1 (Form E) on the
+        frozen stencils."""
         n = self.n
         h = self._per(_H)
         wall = self._per(_WALL)
@@ -180,15 +194,7 @@ class FrozenStep:
             force = -gP[:, a] + tg + eta * (0.5 * lap + gdiv / 6.0)
             acc.append(V * force / rho + self._per(_GX + a))
         dVdt = V * div
-        dt = self.dt
-        un = u + dt * acc[0]
-        vn = v + dt * acc[1]
-        wn = w + dt * acc[2]
-        xn = x + dt * (0.5 * (u + un))
-        yn = y + dt * (0.5 * (v + vn))
-        zn = z + dt * (0.5 * (w + wn))
-        Vn = V + dt * dVdt
-        return xn, yn, zn, un, vn, wn, Vn
+        return acc, dVdt
 
     def run(self, state: State, theta: np.ndarray) -> State:
         t = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
@@ -209,6 +215,53 @@ class FrozenStep:
         res = [np.zeros(state.n) if gi is None else gi.numpy() for gi in g[:7]]
         gth = np.zeros_like(theta) if g[7] is None else g[7].numpy()
         return res, gth
+
+
+class FrozenStep2(FrozenStep):
+    """One second-order oracle step (oracle.step2: Heun's rule on the
+    right-hand side f = (u, acc, dVdt)) of a state already in the step's
+    order, differentiable in (state, theta): stencils of s and of the
+    predictor s* = s + dt f(s) (as the C oracle selects them) held fixed."""
+
+    def __init__(self, state: State, offsets, params: Sequence[Params], dt: float,
+                 cfg=None, brute=None):
+        super().__init__(state, offsets, params, dt, cfg, brute)
+        ev = self.ref
+        a, d = ev["acc"], ev["dVdt"]
+        pred = State(state.x + dt * state.u, state.y + dt * state.v,
+                     state.z + dt * state.w, state.u + dt * a[0],
+                     state.v + dt * a[1], state.w + dt * a[2], state.V + dt * d)
+        self.stage2 = FrozenStep(pred, offsets, params, dt, cfg, brute)
+
+    def forward(self, x, y, z, u, v, w, V, theta):
+        dt = self.dt
+        a1, d1 = self.rhs(x, y, z, u, v, w, V, theta)
+        pos, vel = (x, y, z), (u, v, w)
+        ps = [p + dt * q for p, q in zip(pos, vel)]
+        vs = [q + dt * a for q, a in zip(vel, a1)]
+        Vs = V + dt * d1
+        a2, d2 = self.stage2.rhs(*ps, *vs, Vs, theta)
+        half = 0.5 * dt
+        xn = [p + half * (q + qs) for p, q, qs in zip(pos, vel, vs)]
+        un = [q + half * (b1 + b2) for q, b1, b2 in zip(vel, a1, a2)]
+        return (*xn, *un, V + half * (d1 + d2))
+
+
+def step2_vjp(state: State, offsets, params: Sequence[Params], dt: float,
+              lam: Sequence[np.ndarray], skin: float = SKIN_DEFAULT, brute=None):
+    """Adjoint of oracle.step2 (Morton re-sort, Heun step) at `state`, with
+    the conventions of step_vjp."""
+    perm, _ = sort_perm(state, offsets, params, skin)
+    st = state.take(perm)
+    st = State(*[np.ascontiguousarray(a) for a in st.arrays()])
+    fs = FrozenStep2(st, offsets, params, dt, brute=brute)
+    g, gth = fs.vjp(st, theta_of(params), lam)
+    out = []
+    for a in g:
+        b = np.empty_like(a)
+        b[perm] = a
+        out.append(b)
+    return out, gth, perm
 
 
 def step_vjp(state: State, offsets, params: Sequence[Params], dt: float,

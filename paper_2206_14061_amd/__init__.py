@@ -4,7 +4,8 @@ The method's work runs in the HIP library ``liblp_gfx950.so`` behind the C
 ABI of ``include/lp.h``; this module only marshals torch CUDA tensors
 (device memory and the current stream) into those calls.  Function names
 follow the C ABI: ``lp_build_cells``, ``lp_neighbors``, ``lp_fit_derivs``,
-``lp_rheology_rhs``, ``lp_step``, ``lp_step2``, ``lp_step_adjoint``.
+``lp_rheology_rhs``, ``lp_step``, ``lp_step2``, ``lp_step_adjoint``,
+``lp_step2_adjoint``.
 """
 from __future__ import annotations
 
@@ -236,14 +237,25 @@ class Context:
         """Reverse of lp_build_cells + lp_step at st: returns dL/d(st) for
         dL/d(output) = adj_out (and the permutation, if asked); adds
         dL/d(mu_s, mu_2, I0) into adj_params (n_sys x 3, float64, device)."""
+        return self._adjoint(self.lib.lp_step_adjoint, st, dt, adj_out, adj_params,
+                             want_perm)
+
+    def lp_step2_adjoint(self, st: DeviceState, dt: float, adj_out: DeviceState,
+                         adj_params=None, want_perm: bool = False):
+        """Reverse of lp_build_cells + lp_step2 at st (arguments as for
+        lp_step_adjoint)."""
+        return self._adjoint(self.lib.lp_step2_adjoint, st, dt, adj_out, adj_params,
+                             want_perm)
+
+    def _adjoint(self, fn, st, dt, adj_out, adj_params, want_perm):
         torch = _torch()
         adj_in = DeviceState([torch.empty_like(a) for a in st.t])
         if adj_params is None:
             adj_params = torch.zeros(self.n_sys, 3, dtype=torch.float64, device="cuda")
         perm = torch.empty(st.n, dtype=torch.int32, device="cuda") if want_perm else None
         s, ao, ai = st.struct(), adj_out.struct(), adj_in.struct()
-        self._check(self.lib.lp_step_adjoint(self.h, C.byref(s), float(dt), C.byref(ao),
-                                             C.byref(ai), _ptr(adj_params), _ptr(perm)))
+        self._check(fn(self.h, C.byref(s), float(dt), C.byref(ao), C.byref(ai),
+                       _ptr(adj_params), _ptr(perm)))
         return (adj_in, perm) if want_perm else adj_in
 
     def sync_status(self):

@@ -1,9 +1,10 @@
 """Gradients through LP trajectories with torch.autograd.
 
 ``simulate`` runs ``steps`` LP steps (each: re-sort by the context's cells,
-then one step; lp_build_cells + lp_step) and returns the final state as
-torch tensors that take part in autograd.  The backward pass runs the
-library's lp_step_adjoint step by step in reverse.  Only every
+then one step; lp_build_cells + lp_step, or lp_step2 for the second-order
+step) and returns the final state as torch tensors that take part in
+autograd.  The backward pass runs the library's lp_step_adjoint (or
+lp_step2_adjoint) step by step in reverse.  Only every
 ``checkpoint_every``-th state is kept during the forward pass; each segment
 is recomputed from its checkpoint during the backward pass, which
 reproduces the forward states exactly (the steps are deterministic).
@@ -38,22 +39,25 @@ def _make_function():
 
     class _Trajectory(torch.autograd.Function):
         @staticmethod
-        def forward(fctx, ctx: Context, offsets, params, dt, steps, every, theta,
+        def forward(fctx, ctx: Context, offsets, params, dt, steps, every, order, theta,
                     *state):
             ctx.set_systems(offsets, _params_with(params, theta.detach().cpu().tolist()))
             st = DeviceState([a.detach().clone() for a in state])
+            step = ctx.lp_step2 if order == 2 else ctx.lp_step
             ckpts = {}
             for k in range(steps):
                 if k % every == 0:
                     ckpts[k] = st.clone()
                 ctx.lp_build_cells(st, want_perm=False)
-                ctx.lp_step(st, dt)
-            fctx.lp = (ctx, dt, steps, every, ckpts, theta.device, theta.dtype)
+                step(st, dt)
+            fctx.lp = (ctx, dt, steps, every, order, ckpts, theta.device, theta.dtype)
             return tuple(st.t)
 
         @staticmethod
         def backward(fctx, *gout):
-            ctx, dt, steps, every, ckpts, tdev, tdt = fctx.lp
+            ctx, dt, steps, every, order, ckpts, tdev, tdt = fctx.lp
+            step = ctx.lp_step2 if order == 2 else ctx.lp_step
+            adjoint = ctx.lp_step2_adjoint if order == 2 else ctx.lp_step_adjoint
             ref = next(iter(ckpts.values())).t[0]
             lam = DeviceState([torch.zeros_like(ref) if g is None else
                                g.detach().to(torch.float64).contiguous()
@@ -66,11 +70,11 @@ def _make_function():
                 for _ in range(k0, k1):
                     inputs.append(st.clone())
                     ctx.lp_build_cells(st, want_perm=False)
-                    ctx.lp_step(st, dt)
+                    step(st, dt)
                 for s_in in reversed(inputs):
-                    lam = ctx.lp_step_adjoint(s_in, dt, lam, dtheta)
+                    lam = adjoint(s_in, dt, lam, dtheta)
             fctx.lp = None
-            return (None, None, None, None, None, None,
+            return (None, None, None, None, None, None, None,
                     dtheta.to(device=tdev, dtype=tdt)) + tuple(lam.t)
 
     return _Trajectory
@@ -80,15 +84,18 @@ _FN = None
 
 
 def simulate(ctx: Context, offsets, params: Sequence, state: Sequence, theta, dt: float,
-             steps: int, checkpoint_every: int = 10):
+             steps: int, checkpoint_every: int = 10, order: int = 1):
     """Final state (7 tensors, the order after the last re-sort) of `steps`
     steps from `state` (7 float64 device tensors) with friction-law
     parameters `theta` (n_sys x 3 tensor: mu_s, mu_2, I0); differentiable
-    with respect to both."""
+    with respect to both.  order 1: the explicit step (lp_step); order 2:
+    the second-order step (lp_step2)."""
     global _FN
     if _FN is None:
         _FN = _make_function()
     if steps < 1 or checkpoint_every < 1:
         raise ValueError("steps and checkpoint_every must be positive")
+    if order not in (1, 2):
+        raise ValueError("order must be 1 or 2")
     return _FN.apply(ctx, list(offsets), list(params), float(dt), int(steps),
-                     int(checkpoint_every), theta, *state)
+                     int(checkpoint_every), int(order), theta, *state)

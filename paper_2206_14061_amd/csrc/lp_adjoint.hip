@@ -8,7 +8,9 @@
 // explicit update (Sec. 3.1 steps 8, 10).  Its reverse, in reverse order:
 //
 //   update:   xbar += x'bar, ubar += u'bar + dt x'bar, Vbar += V'bar,
-//             abar = dt (u'bar + dt x'bar / 2), dVbar = dt V'bar;
+//             abar = dt (u'bar + dt x'bar / 2), dVbar = dt V'bar
+//             (the seeds of the reverse right-hand side; the two stages of
+//             the second-order step use other linear seeds, see AdjSeed);
 //   RHS:      a = V T / rho_s + g with T = -grad P + gd grad eta + eta vis,
 //             dV/dt = V div;
 //   a least-squares fit c = G^-1 A^T b (G = A^T A) with cbar:
@@ -58,7 +60,6 @@ struct AdjBufs {
     const uint8_t* flags;
     double* dparams;     // n_sys x 3
     ErrWord* err;
-    double dt;
     const int32_t* slot; // m_max x n: slot of stencil row t of particle i
     double* contrib;     // 6 per slot
 };
@@ -227,24 +228,36 @@ __global__ __launch_bounds__(BLOCK) void k_slot_gather(int64_t n, const int32_t*
     B.a[2][j] += c[5];
 }
 
-__global__ void k_adj_init(int64_t n, Ptr7 lam, double dt, AdjBufs B)
+// N = nA A + nB B at particle i, component a (B optional)
+__device__ __forceinline__ double seed_n(const AdjSeed& S, int a, int64_t i)
+{
+    const double v = S.nA * S.A[a][i];
+    return S.B[0] ? v + S.nB * S.B[a][i] : v;
+}
+
+__global__ void k_adj_init(int64_t n, AdjSeed S, AdjBufs B)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    B.a[0][i] = lam.p[0][i];
-    B.a[1][i] = lam.p[1][i];
-    B.a[2][i] = lam.p[2][i];
-    B.a[3][i] = lam.p[3][i] + dt * lam.p[0][i];
-    B.a[4][i] = lam.p[4][i] + dt * lam.p[1][i];
-    B.a[5][i] = lam.p[5][i] + dt * lam.p[2][i];
-    B.a[6][i] = lam.p[6][i];
+    double id[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+        const double v = S.iA * S.A[a][i];
+        id[a] = S.B[0] ? v + S.iB * S.B[a][i] : v;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        B.a[a][i] = id[a];
+        B.a[3 + a][i] = id[3 + a] + S.c_ux * seed_n(S, a, i);
+    }
+    B.a[6][i] = id[6];
     B.aP[i] = 0.0;
     B.aE[i] = 0.0;
 }
 
 // ---- reverse of the update, the RHS and the fit of P and eta -------------
 
-__global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, Ptr7 lam, AdjBufs B)
+__global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, AdjSeed S, AdjBufs B)
 {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     if (i >= v.n) return;
@@ -309,12 +322,12 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, Ptr7 lam, AdjBufs B
 #pragma unroll
     for (int q = 0; q < 3; ++q) vis[q] = B.hand[(int64_t)(34 + q) * n + i];
     // ---- reverse of the update and the RHS (this particle's own terms)
-    const double dt = B.dt;
     const double V = v.V[i];
     double abar[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) abar[a] = dt * (lam.p[3 + a][i] + 0.5 * dt * lam.p[a][i]);
-    const double dVbar = dt * lam.p[6][i];
+    for (int a = 0; a < 3; ++a)
+        abar[a] = S.c_a * (seed_n(S, 3 + a, i) + S.k_x * seed_n(S, a, i));
+    const double dVbar = S.c_d * seed_n(S, 6, i);
     const double T0 = -gP[0] + gd[0] * gE[0] + gd[3] * gE[1] + gd[4] * gE[2] + Ei * vis[0];
     const double T1 = -gP[1] + gd[3] * gE[0] + gd[1] * gE[1] + gd[5] * gE[2] + Ei * vis[1];
     const double T2 = -gP[2] + gd[4] * gE[0] + gd[5] * gE[1] + gd[2] * gE[2] + Ei * vis[2];
@@ -602,21 +615,20 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
     }
 }
 
-// adj_in[perm[j]] = acc[j]
+// adj_in[perm[j]] = acc[j] (perm null: adj_in[j] = acc[j])
 __global__ void k_adj_unpermute(int64_t n, const int32_t* perm, AdjBufs B, Ptr7 out)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const int64_t o = perm[j];
+    const int64_t o = perm ? perm[j] : j;
 #pragma unroll
     for (int a = 0; a < 7; ++a) const_cast<double*>(out.p[a])[o] = B.a[a][j];
 }
 
 }  // namespace
 
-lp_status step_adjoint(lp_ctx* c, const double* const st[7], double dt,
-                       const double* const lam[7], double* const out[7],
-                       double* dparams, const int32_t* perm)
+lp_status step_adjoint(lp_ctx* c, const double* const st[7], const AdjSeed& seed,
+                       double* const out[7], double* dparams, const int32_t* perm)
 {
     Work& w = c->w;
     const int64_t n = c->n;
@@ -634,12 +646,8 @@ lp_status step_adjoint(lp_ctx* c, const double* const st[7], double dt,
     B.flags = w.flags;
     B.dparams = dparams;
     B.err = w.err;
-    B.dt = dt;
-    Ptr7 dlam, dout;
-    for (int a = 0; a < 7; ++a) {
-        dlam.p[a] = lam[a];
-        dout.p[a] = out[a];
-    }
+    Ptr7 dout;
+    for (int a = 0; a < 7; ++a) dout.p[a] = out[a];
     // slots of the stencil rows, grouped by receiving particle
     hipStream_t s = c->stream;
     const int64_t nt = (n + BLOCK - 1) / BLOCK;
@@ -655,8 +663,8 @@ lp_status step_adjoint(lp_ctx* c, const double* const st[7], double dt,
                        w.adj_tile);
     hipLaunchKernelGGL(k_slot_assign, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v,
                        w.adj_off, w.adj_fill, w.adj_slot);
-    hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, dlam, dt, B);
-    hipLaunchKernelGGL(k_adj_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, dlam, B);
+    hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, seed, B);
+    hipLaunchKernelGGL(k_adj_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, seed, B);
     hipLaunchKernelGGL(k_slot_gather, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
                        (const int32_t*)w.adj_off, B, 2);
     hipLaunchKernelGGL(k_adj_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, B);

@@ -82,6 +82,7 @@ void free_work(Work& w)
     f(w.adj_tile);
     f(w.gate); f(w.ids_tmp);
     for (int a = 0; a < 7; ++a) f(w.sst2[a]);
+    for (int a = 0; a < 7; ++a) f(w.adj2[a]);
     f(w.acc2); f(w.dVdt2); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
@@ -253,6 +254,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.adj_tile, n_max / BLOCK + 2);
     A(w.gate, 4); A(w.ids_tmp, n_max);
     for (int a = 0; a < 7; ++a) A(w.sst2[a], n_max);
+    for (int a = 0; a < 7; ++a) A(w.adj2[a], n_max);
     A(w.acc2, 3 * n_max); A(w.dVdt2, n_max);
     A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
     A(w.coff, n_max + 1);
@@ -633,16 +635,92 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
     double* out[7];
     state_arrays(adj_out, lam_in);
     state_arrays(adj_in, out);
-    const double* lam[7];
-    for (int a = 0; a < 7; ++a) lam[a] = lam_in[a];
-    if (r == LP_OK)
-        r = step_adjoint(c, sorted, dt, lam, out, adj_params, c->w.adj_perm);
+    AdjSeed seed;
+    for (int a = 0; a < 7; ++a) seed.A[a] = lam_in[a];
+    seed.c_ux = seed.c_a = seed.c_d = dt;
+    seed.k_x = 0.5 * dt;
+    if (r == LP_OK) r = step_adjoint(c, sorted, seed, out, adj_params, c->w.adj_perm);
     if (r == LP_OK && perm) {
         hipError_t e = hipMemcpyAsync(perm, c->w.adj_perm, sizeof(int32_t) * c->n,
                                       hipMemcpyDeviceToDevice, c->stream);
         if (e != hipSuccess) r = hip_fail(c, e, "adjoint perm copy");
     }
     // the working state now belongs to this call: the next lp_step rebuilds
+    c->list_ok = false;
+    c->stencils_ok = false;
+    c->built_x = nullptr;
+    return r;
+}
+
+lp_status lp_step2_adjoint(lp_ctx* c, const lp_state* s, double dt,
+                           const lp_state* adj_out, lp_state* adj_in,
+                           double* adj_params, int32_t* perm)
+{
+    if (!s || !adj_out || !adj_in || !adj_params || !(dt > 0.0) || !std::isfinite(dt)) {
+        if (c) c->err = "lp_step2_adjoint: null argument or dt not positive";
+        return LP_E_ARG;
+    }
+    lp_status r = check_ready(c, s);
+    if (r != LP_OK) return r;
+    if (c->cfg.weight != LP_W_UNIT) {
+        c->err = "lp_step2_adjoint supports unit weights only";
+        return LP_E_ARG;
+    }
+    if (!(c->cfg.skin > 0.0)) {
+        c->err = "lp_step2_adjoint needs a neighbour-list skin > 0";
+        return LP_E_ARG;
+    }
+    if ((int64_t)c->cfg.m_max * c->n >= (1ll << 31)) {
+        c->err = "lp_step2_adjoint: m_max x particles must stay below 2^31";
+        return LP_E_CAPACITY;
+    }
+    Work& w = c->w;
+    double* in[7];
+    state_arrays(s, in);
+    double* lam_in[7];
+    double* out[7];
+    state_arrays(adj_out, lam_in);
+    state_arrays(adj_in, out);
+    const double* sorted[7];
+    const double* pred[7];
+    for (int a = 0; a < 7; ++a) {
+        sorted[a] = w.sst[a];
+        pred[a] = w.sst2[a];
+    }
+    // forward: s (re-sorted), f(s) in float64, predictor s*, its stencils
+    r = cells_build(c, in, w.adj_perm);
+    if (r == LP_OK) r = stencils_build(c, sorted);
+    if (r == LP_OK) r = step_pass1_coef(c, sorted);
+    if (r == LP_OK) r = step_pass2(c, sorted, 0.0, nullptr, w.acc, w.dVdt, true);
+    if (r == LP_OK) r = heun_predictor(c, dt);
+    if (r == LP_OK) r = stencils_build(c, pred);
+    if (r == LP_OK) r = step_pass1_coef(c, pred);
+    // corrector stage: s' = s + dt/2 (f(s) + f(s*)) seen from s*: its
+    // cotangent lam* = J_f(s*)^T (dt/2 lam') lands in adj2
+    AdjSeed s2;
+    for (int a = 0; a < 7; ++a) s2.A[a] = lam_in[a];
+    s2.iA = 0.0;
+    s2.c_ux = s2.c_a = s2.c_d = 0.5 * dt;
+    if (r == LP_OK) r = step_adjoint(c, pred, s2, w.adj2, adj_params, nullptr);
+    // predictor stage seen from s: identity lam' + lam*, and f(s) with
+    // cotangent dt (lam'/2 + lam*)
+    if (r == LP_OK) r = stencils_build(c, sorted);
+    if (r == LP_OK) r = step_pass1_coef(c, sorted);
+    AdjSeed s1;
+    for (int a = 0; a < 7; ++a) {
+        s1.A[a] = lam_in[a];
+        s1.B[a] = w.adj2[a];
+    }
+    s1.iA = s1.iB = 1.0;
+    s1.nA = 0.5;
+    s1.nB = 1.0;
+    s1.c_ux = s1.c_a = s1.c_d = dt;
+    if (r == LP_OK) r = step_adjoint(c, sorted, s1, out, adj_params, w.adj_perm);
+    if (r == LP_OK && perm) {
+        hipError_t e = hipMemcpyAsync(perm, w.adj_perm, sizeof(int32_t) * c->n,
+                                      hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) r = hip_fail(c, e, "adjoint perm copy");
+    }
     c->list_ok = false;
     c->stencils_ok = false;
     c->built_x = nullptr;

@@ -1005,7 +1005,7 @@ lp_status step_pass1_coef(lp_ctx* c, const double* const st[7])
 }
 
 lp_status step_pass2(lp_ctx* c, const double* const st[7], double dt,
-                     double* const out[7], double* acc, double* dVdt)
+                     double* const out[7], double* acc, double* dVdt, bool fp64)
 {
     Work& w = c->w;
     const int64_t n = c->n;
@@ -1015,7 +1015,7 @@ lp_status step_pass2(lp_ctx* c, const double* const st[7], double dt,
     o.dt = dt;
     if (n > 0) {
         prof_mark(c, 5, false);
-        if (c->cfg.precision == LP_FP32_REFINED)
+        if (c->cfg.precision == LP_FP32_REFINED && !fp64)
             hipLaunchKernelGGL(k_pass2_ref, dim3(blocks_for(n)), dim3(BLOCK), 0,
                                c->stream, v, (const double*)w.P, (const double*)w.eta,
                                (const double*)w.hand, (const float*)w.uf,

@@ -166,6 +166,7 @@ struct Work {
     double* sst2[7] = {nullptr};
     double* acc2 = nullptr;               // 3 x n
     double* dVdt2 = nullptr;
+    double* adj2[7] = {nullptr};          // cotangent of the predictor state
     int32_t* ids_tmp = nullptr;
     double* acc = nullptr;                // 3 x n
     double* dVdt = nullptr;
@@ -343,19 +344,36 @@ lp_status step_rhs(lp_ctx* c, const double* const st[7]);
 // stencils of st and keeps the fastest (choice: host int32[2], optional)
 lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice);
 // pass 2 with acc / dVdt stored and, when out is given, the explicit
-// update written to out
+// update written to out (fp64: float64 kernels whatever the precision)
 lp_status step_pass2(lp_ctx* c, const double* const st[7], double dt,
-                     double* const out[7], double* acc, double* dVdt);
-// second-order (Heun) step on the sorted working state (lp_step2)
+                     double* const out[7], double* acc, double* dVdt,
+                     bool fp64 = false);
+// predictor of the second-order step: w.sst2 = w.sst + dt (u, acc, dVdt)
+// from w.acc / w.dVdt, with the device check that it stays within half
+// the list skin (ERR_LIST)
+lp_status heun_predictor(lp_ctx* c, double dt);
+// second-order (Heun) step on the sorted working state (lp_step2), after
+// pass 1 and pass 2 at w.sst
 lp_status step_heun(lp_ctx* c, double dt, double* const out[7]);
 // pass 1 in float64 with the velocity coefficients stored (adjoint input)
 lp_status step_pass1_coef(lp_ctx* c, const double* const st[7]);
-// reverse of the step on the sorted state st (after step_pass1_coef);
-// lam: cotangent of the step's output (sorted order); out: cotangent of
-// the input in its order (perm[new] = old); dparams += parameter cotangents
-lp_status step_adjoint(lp_ctx* c, const double* const st[7], double dt,
-                       const double* const lam[7], double* const out[7],
-                       double* dparams, const int32_t* perm);
+// Cotangent seeds of one reverse right-hand-side evaluation.  With
+// N = nA A + nB B (B optional), the state accumulators start at
+// iA A + iB B with c_ux N_(x,y,z) added to (u, v, w), and the cotangents of
+// the acceleration and of dV/dt are c_a (N_(u,v,w) + k_x N_(x,y,z)) and
+// c_d N_V.  One explicit step: A = lam, c_ux = c_a = c_d = dt, k_x = dt/2.
+struct AdjSeed {
+    const double* A[7] = {nullptr};
+    const double* B[7] = {nullptr};
+    double iA = 1.0, iB = 0.0, nA = 1.0, nB = 0.0;
+    double c_ux = 0.0, c_a = 0.0, k_x = 0.0, c_d = 0.0;
+};
+// reverse of the right-hand side (and the update the seed describes) on
+// the sorted state st (after stencils_build and step_pass1_coef on st);
+// out: cotangent of the input in its order (perm[new] = old; perm null:
+// st's order); dparams += parameter cotangents
+lp_status step_adjoint(lp_ctx* c, const double* const st[7], const AdjSeed& seed,
+                       double* const out[7], double* dparams, const int32_t* perm);
 lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
                       double* const out[7]);
 View make_view(lp_ctx* c, const double* const st[7]);

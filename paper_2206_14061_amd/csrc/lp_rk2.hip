@@ -90,38 +90,51 @@ __global__ void k_heun(int64_t n, int n_sys, const int64_t* off, const lp_params
 
 }  // namespace
 
-lp_status step_heun(lp_ctx* c, double dt, double* const out[7])
+lp_status heun_predictor(lp_ctx* c, double dt)
 {
     Work& w = c->w;
     const int64_t n = c->n;
     if (n == 0) return LP_OK;
     hipStream_t st = c->stream;
-    S7 s1, s2;
-    O7 o2, oo;
+    S7 s1;
+    O7 o2;
     for (int a = 0; a < 7; ++a) {
         s1.p[a] = w.sst[a];
-        s2.p[a] = w.sst2[a];
         o2.p[a] = w.sst2[a];
-        oo.p[a] = out[a];
     }
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(n)), dim3(BLOCK), 0, st, n, s1,
                        (const double*)w.acc, (const double*)w.dVdt, dt, o2);
     hipLaunchKernelGGL(k_stage_check, dim3(blocks_for(n)), dim3(BLOCK), 0, st, n,
                        c->n_sys, w.off, w.grid, w.sst2[0], w.sst2[1], w.sst2[2], w.xref[0],
                        w.xref[1], w.xref[2], w.err);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(c, e, "predictor launch");
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "predictor launch");
+}
+
+lp_status step_heun(lp_ctx* c, double dt, double* const out[7])
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    if (n == 0) return LP_OK;
+    lp_status r = heun_predictor(c, dt);
     const double* pred[7];
     for (int a = 0; a < 7; ++a) pred[a] = w.sst2[a];
-    lp_status r = stencils_build(c, pred);
+    if (r == LP_OK) r = stencils_build(c, pred);
     if (r == LP_OK) r = step_rhs(c, pred);
     if (r == LP_OK) r = step_pass2(c, pred, dt, nullptr, w.acc2, w.dVdt2);
     if (r != LP_OK) return r;
-    hipLaunchKernelGGL(k_heun, dim3(blocks_for(n)), dim3(BLOCK), 0, st, n, c->n_sys,
+    S7 s1, s2;
+    O7 oo;
+    for (int a = 0; a < 7; ++a) {
+        s1.p[a] = w.sst[a];
+        s2.p[a] = w.sst2[a];
+        oo.p[a] = out[a];
+    }
+    hipLaunchKernelGGL(k_heun, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n, c->n_sys,
                        w.off, w.prm, s1, s2, (const double*)w.acc, (const double*)w.acc2,
                        (const double*)w.dVdt, (const double*)w.dVdt2, dt, oo, w.err,
                        w.cnt);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "corrector launch");
 }
 
