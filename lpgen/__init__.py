@@ -61,7 +61,10 @@ class Params:
     threshold solid fractions, ``alpha, beta`` the quasi-static pressure
     constants of P = rho_s (alpha + beta phi), ``g`` gravity, ``h`` the
     inter-particle spacing, ``R`` the neighbour radius and ``wall_z`` the
-    height of the solid wall plane z = wall_z.
+    height of the solid wall plane z = wall_z.  ``box_lo`` and ``box_len``
+    give the periodic box along x and y: an axis with ``box_len`` > 0 is
+    periodic with period ``box_len`` over [box_lo, box_lo + box_len); 0
+    leaves it open.
     """
     rho_s: float = 2450.0
     d: float = 5e-4
@@ -77,14 +80,18 @@ class Params:
     h: float = 1.0 / 16.0
     R: float = 2.5 / 16.0
     wall_z: float = 0.0
+    box_lo: tuple = (0.0, 0.0)
+    box_len: tuple = (0.0, 0.0)
 
     def as_vector(self) -> np.ndarray:
         """Flat float64 record in the order rho_s, d, mu_s, mu_2, I0, phi_c,
-        phi_min, phi_max, alpha, beta, gx, gy, gz, h, R, wall_z."""
+        phi_min, phi_max, alpha, beta, gx, gy, gz, h, R, wall_z, x_lo, y_lo,
+        Lx, Ly."""
         return np.array([self.rho_s, self.d, self.mu_s, self.mu_2, self.I0,
                          self.phi_c, self.phi_min, self.phi_max, self.alpha,
                          self.beta, self.g[0], self.g[1], self.g[2], self.h,
-                         self.R, self.wall_z], dtype=np.float64)
+                         self.R, self.wall_z, self.box_lo[0], self.box_lo[1],
+                         self.box_len[0], self.box_len[1]], dtype=np.float64)
 
 
 def default_params(h: float, **kw) -> Params:

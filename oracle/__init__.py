@@ -69,6 +69,7 @@ def _load():
     lib.orc_eval.restype = C.c_int
     lib.orc_update.argtypes = [i64, i32, P, P, C.c_double] + [P] * 9
     lib.orc_update.restype = i64
+    lib.orc_wrap.argtypes = [i64, i32, P, P, P, P]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_lsq.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P]
     lib.orc_lsq.restype = C.c_double
@@ -305,4 +306,15 @@ def step2(state: State, offsets, params: Sequence[Params], dt: float,
     pos = [p + half * (q + qs) for p, q, qs in zip((st.x, st.y, st.z), vel, pvel)]
     new_vel = [q + half * (a1[k] + a2[k]) for k, q in enumerate(vel)]
     out = State(*pos, *new_vel, st.V + half * (d1 + d2))
+    wrap(out, offsets, params)
     return out, perm, (r1, r2)
+
+
+def wrap(state: State, offsets, params: Sequence[Params]):
+    """Maps x and y along periodic axes into their box, in place."""
+    lib = _load()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    prm = prm_matrix(params)
+    for a in (state.x, state.y):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib.orc_wrap(state.n, len(params), _ptr(off), _ptr(prm), _ptr(state.x), _ptr(state.y))

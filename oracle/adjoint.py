@@ -32,6 +32,7 @@ from . import Oracle, sort_perm, SKIN_DEFAULT
 # parameter record order (16 doubles per system)
 _RHO, _D, _MUS, _MU2, _I0, _PHIC, _PHIMIN, _PHIMAX, _ALPHA, _BETA = range(10)
 _GX, _H, _WALL = 10, 13, 15
+_XLO, _YLO, _LX, _LY = 16, 17, 18, 19
 # second-derivative index of the pair (a, b)
 _HIDX = ((3, 6, 7), (6, 4, 8), (7, 8, 5))
 _SIGNS = torch.tensor([[(1.0 if (o & 1) else -1.0), (1.0 if (o & 2) else -1.0),
@@ -77,6 +78,18 @@ class FrozenStep:
         self.gmask = torch.from_numpy(((gm[:, None] >> np.arange(8)[None, :]) & 1)
                                       .astype(bool))
         self.msrc = torch.from_numpy(nb.mirror_src.astype(np.int64))
+        # periodic axes: the copy of each stencil point nearest to the
+        # particle (shift -L when x_j - x_i > L/2, +L below -L/2), frozen
+        pts = np.concatenate([np.arange(n), nb.mirror_src.astype(np.int64)])
+        prm = self.prm.numpy()
+        self.shift = []
+        for coord, lcol in ((state.x, _LX), (state.y, _LY)):
+            L = prm[sys, lcol][:, None]
+            c = np.asarray(coord, dtype=np.float64)
+            d = c[pts][idx] - c[:, None]
+            sh = np.where((L > 0) & (d > 0.5 * L), -L,
+                          np.where((L > 0) & (d < -0.5 * L), L, 0.0))
+            self.shift.append(torch.from_numpy(np.ascontiguousarray(sh)))
         self.lin = torch.from_numpy((ev["flags"] & 1).astype(bool))
         nrows = cnt + self.gmask.numpy().sum(axis=1)
         self.few = torch.from_numpy(nrows < 3)
@@ -106,11 +119,20 @@ class FrozenStep:
         un = u + dt * acc[0]
         vn = v + dt * acc[1]
         wn = w + dt * acc[2]
-        xn = x + dt * (0.5 * (u + un))
-        yn = y + dt * (0.5 * (v + vn))
+        xn = self.wrap(x + dt * (0.5 * (u + un)), 0)
+        yn = self.wrap(y + dt * (0.5 * (v + vn)), 1)
         zn = z + dt * (0.5 * (w + wn))
         Vn = V + dt * dVdt
         return xn, yn, zn, un, vn, wn, Vn
+
+    def wrap(self, c, axis):
+        """Coordinate along axis 0 (x) or 1 (y) mapped into the periodic box
+        (a shift by a constant: derivative 1)."""
+        lo = self._per(_XLO + axis)
+        L = self._per(_LX + axis)
+        per = L > 0
+        c = torch.where(per & (c >= lo + L), c - L, c)
+        return torch.where(per & (c < lo), c + L, c)
 
     def rhs(self, x, y, z, u, v, w, V, theta):
         """Acceleration (3 tensors) and dV/dt of Sec. 2.1 (Form E) on the
@@ -128,8 +150,8 @@ class FrozenStep:
         Wa = torch.cat([w, -w[ms]])
         S, mk = self.sten, self.mask
         mkf = mk.to(torch.float64)
-        ex = (X[S] - x[:, None]) / h[:, None]
-        ey = (Y[S] - y[:, None]) / h[:, None]
+        ex = ((X[S] + self.shift[0]) - x[:, None]) / h[:, None]
+        ey = ((Y[S] + self.shift[1]) - y[:, None]) / h[:, None]
         ez = (Z[S] - z[:, None]) / h[:, None]
         As = _taylor(ex, ey, ez) * mkf[..., None]
         Ag = _taylor(_SIGNS[:, 0], _SIGNS[:, 1], _SIGNS[:, 2])[None, :, :] * \
@@ -243,6 +265,7 @@ class FrozenStep2(FrozenStep):
         a2, d2 = self.stage2.rhs(*ps, *vs, Vs, theta)
         half = 0.5 * dt
         xn = [p + half * (q + qs) for p, q, qs in zip(pos, vel, vs)]
+        xn = [self.wrap(xn[0], 0), self.wrap(xn[1], 1), xn[2]]
         un = [q + half * (b1 + b2) for q, b1, b2 in zip(vel, a1, a2)]
         return (*xn, *un, V + half * (d1 + d2))
 

@@ -45,7 +45,8 @@
 #endif
 
 enum { P_RHO, P_D, P_MUS, P_MU2, P_I0, P_PHIC, P_PHIMIN, P_PHIMAX, P_ALPHA,
-       P_BETA, P_GX, P_GY, P_GZ, P_H, P_R, P_WALL, P_NPRM };
+       P_BETA, P_GX, P_GY, P_GZ, P_H, P_R, P_WALL, P_XLO, P_YLO, P_LX, P_LY,
+       P_NPRM };
 enum { C_MMAX, C_GMARGIN, C_PHIG, C_FTOL, C_WEIGHT, C_NCFG };
 
 #define NC 9          /* unknowns of the 2nd-order 3D fit            */
@@ -73,6 +74,37 @@ static uint64_t spread3(uint64_t v)
     return r;
 }
 
+/* Periodic axes (Sec. 3.1, boundary conditions): an axis with period
+ * L > 0 over [lo, lo + L) identifies x with x + L.  wrap_coord maps a
+ * coordinate within one period of the box into it (one correction);
+ * image_coord gives the copy of x_j nearest to x_i (x_j - L when
+ * x_j - x_i > L/2, x_j + L when below -L/2). */
+static double wrap_coord(double x, double lo, double L)
+{
+    if (L > 0.0) {
+        if (x >= lo + L) return x - L;
+        if (x < lo) return x + L;
+    }
+    return x;
+}
+
+static double image_coord(double xj, double xi, double L)
+{
+    if (L > 0.0) {
+        double d = xj - xi;
+        if (d > 0.5 * L) return xj - L;
+        if (d < -0.5 * L) return xj + L;
+    }
+    return xj;
+}
+
+/* cells along a periodic axis: floor(L / c) (at least 1) of edge L / n */
+static int64_t periodic_cells(double L, double ic)
+{
+    int64_t nc = (int64_t)(L * ic);
+    return nc < 1 ? 1 : nc;
+}
+
 typedef struct { uint64_t key; int64_t idx; } KeyIdx;
 
 static int cmp_keyidx(const void* a, const void* b)
@@ -86,7 +118,9 @@ static int cmp_keyidx(const void* a, const void* b)
 /* Cell edge c = R (1 + skin) (1 + 2^-20), origin (min x, min y,
  * min(min z, wall - R)) per system; cell coordinate floor((x - origin)/c)
  * computed as (x - origin) * (1/c); key = bit interleave (x -> 3k,
- * y -> 3k+1, z -> 3k+2).  Particles are ordered by (key, old index) inside
+ * y -> 3k+1, z -> 3k+2).  A periodic axis starts at its box and has
+ * n = floor(L/c) cells: coordinate (wrap(x) - lo) * (n / L), clamped to
+ * [0, n - 1].  Particles are ordered by (key, old index) inside
  * each system.  perm[new] = old.  Returns -1 if a cell coordinate needs
  * more than 21 bits.  (The order only affects which particle gets which
  * id; skin is the neighbour-list margin of the GPU library, whose cells
@@ -111,10 +145,29 @@ int orc_sort(int64_t n, int32_t n_sys, const int64_t* off, const double* prm,
         if (zl < z0) z0 = zl;
         double c = (p[P_R] * (1.0 + skin)) * (1.0 + 1.0 / 1048576.0);
         double ic = 1.0 / c;
+        double Lx = p[P_LX], Ly = p[P_LY];
+        double icx = ic, icy = ic;
+        int64_t npx = 0, npy = 0;
+        if (Lx > 0.0) { x0 = p[P_XLO]; npx = periodic_cells(Lx, ic); icx = (double)npx / Lx; }
+        if (Ly > 0.0) { y0 = p[P_YLO]; npy = periodic_cells(Ly, ic); icy = (double)npy / Ly; }
         for (int64_t i = a; i < b; ++i) {
-            double fx = (x[i] - x0) * ic, fy = (y[i] - y0) * ic,
+            double xw = wrap_coord(x[i], p[P_XLO], Lx);
+            double yw = wrap_coord(y[i], p[P_YLO], Ly);
+            double fx = (xw - x0) * icx, fy = (yw - y0) * icy,
                    fz = (z[i] - z0) * ic;
-            uint64_t cx = (uint64_t)fx, cy = (uint64_t)fy, cz = (uint64_t)fz;
+            uint64_t cx, cy, cz = (uint64_t)fz;
+            if (Lx > 0.0) {
+                int64_t t = (int64_t)fx;
+                cx = (uint64_t)(t < 0 ? 0 : (t >= npx ? npx - 1 : t));
+            } else {
+                cx = (uint64_t)fx;
+            }
+            if (Ly > 0.0) {
+                int64_t t = (int64_t)fy;
+                cy = (uint64_t)(t < 0 ? 0 : (t >= npy ? npy - 1 : t));
+            } else {
+                cy = (uint64_t)fy;
+            }
             if (cx >= (1u << 21) || cy >= (1u << 21) || cz >= (1u << 21)) bad = 1;
             t[i].key = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
             t[i].idx = i;
@@ -156,14 +209,24 @@ static int32_t point_sys(const OrcNbr* h, int64_t j)
     return j < h->n ? h->sys[j] : h->sys[h->msrc[j - h->n]];
 }
 
+/* displacement from real i to point j, through the nearest periodic image
+ * of j along periodic axes */
+static void disp(const OrcNbr* h, int64_t i, int64_t j, double* dx, double* dy,
+                 double* dz)
+{
+    const double* p = h->prm + (size_t)h->sys[i] * P_NPRM;
+    *dx = image_coord(h->px[j], h->px[i], p[P_LX]) - h->px[i];
+    *dy = image_coord(h->py[j], h->py[i], p[P_LY]) - h->py[i];
+    *dz = h->pz[j] - h->pz[i];
+}
+
 /* candidate test of Sec. 3.1 step 5: strict r2 < R2, r2 summed left to
  * right, no fused multiply-add (the file is built with contraction off) */
 static int is_candidate(const OrcNbr* h, int64_t i, int64_t j, double R2,
                         double* r2o)
 {
-    double dx = h->px[j] - h->px[i];
-    double dy = h->py[j] - h->py[i];
-    double dz = h->pz[j] - h->pz[i];
+    double dx, dy, dz;
+    disp(h, i, j, &dx, &dy, &dz);
     double r2 = dx * dx + dy * dy;
     r2 = r2 + dz * dz;
     *r2o = r2;
@@ -180,7 +243,8 @@ static int cmp_i32(const void* a, const void* b)
  * point of the system.  Otherwise a uniform bucket grid (edge 1.01 R, so
  * every point within R lies in the 27 surrounding buckets). */
 typedef struct {
-    double x0, y0, z0, ic;
+    double x0, y0, z0, ic, icx, icy;
+    double xlo, ylo, Lx, Ly;  /* periodic box (L = 0: open axis) */
     int64_t nx, ny, nz;
     int64_t* start;   /* bucket start in items, size nx*ny*nz + 1 */
     int64_t* items;   /* point ids grouped by bucket             */
@@ -189,8 +253,10 @@ typedef struct {
 static int64_t grid_cell(const Grid* g, double x, double y, double z,
                          int64_t* cx, int64_t* cy, int64_t* cz)
 {
-    *cx = (int64_t)floor((x - g->x0) * g->ic);
-    *cy = (int64_t)floor((y - g->y0) * g->ic);
+    x = wrap_coord(x, g->xlo, g->Lx);
+    y = wrap_coord(y, g->ylo, g->Ly);
+    *cx = (int64_t)floor((x - g->x0) * g->icx);
+    *cy = (int64_t)floor((y - g->y0) * g->icy);
     *cz = (int64_t)floor((z - g->z0) * g->ic);
     if (*cx < 0) *cx = 0;
     if (*cy < 0) *cy = 0;
@@ -220,12 +286,23 @@ static void build_grids(OrcNbr* h, Grid* grids)
             ++cnt;
         }
         double edge = 1.01 * p[P_R];
-        g->ic = 1.0 / edge;
+        g->ic = g->icx = g->icy = 1.0 / edge;
         if (cnt == 0) { lo[0] = lo[1] = lo[2] = 0; hi[0] = hi[1] = hi[2] = 0; }
         g->x0 = lo[0]; g->y0 = lo[1]; g->z0 = lo[2];
         g->nx = (int64_t)floor((hi[0] - lo[0]) * g->ic) + 1;
         g->ny = (int64_t)floor((hi[1] - lo[1]) * g->ic) + 1;
         g->nz = (int64_t)floor((hi[2] - lo[2]) * g->ic) + 1;
+        g->xlo = p[P_XLO]; g->ylo = p[P_YLO]; g->Lx = p[P_LX]; g->Ly = p[P_LY];
+        if (g->Lx > 0.0) {
+            g->x0 = g->xlo;
+            g->nx = periodic_cells(g->Lx, g->ic);
+            g->icx = (double)g->nx / g->Lx;
+        }
+        if (g->Ly > 0.0) {
+            g->y0 = g->ylo;
+            g->ny = periodic_cells(g->Ly, g->ic);
+            g->icy = (double)g->ny / g->Ly;
+        }
         int64_t nc = g->nx * g->ny * g->nz;
         g->start = (int64_t*)calloc((size_t)nc + 1, sizeof(int64_t));
         g->items = (int64_t*)malloc(sizeof(int64_t) * (size_t)(cnt > 0 ? cnt : 1));
@@ -272,9 +349,22 @@ static int collect(const OrcNbr* h, const Grid* grids, int brute, int64_t i,
     const Grid* g = &grids[s];
     int64_t cx, cy, cz;
     grid_cell(g, h->px[i], h->py[i], h->pz[i], &cx, &cy, &cz);
+    /* along a periodic axis the neighbouring cells wrap around; with fewer
+     * than three cells each is visited once */
     for (int64_t z = cz - 1; z <= cz + 1; ++z)
-        for (int64_t y = cy - 1; y <= cy + 1; ++y)
-            for (int64_t x = cx - 1; x <= cx + 1; ++x) {
+        for (int64_t ya = cy - 1; ya <= cy + 1; ++ya)
+            for (int64_t xa = cx - 1; xa <= cx + 1; ++xa) {
+                int64_t x = xa, y = ya;
+                if (g->Lx > 0.0) {
+                    if (xa - cx >= g->nx || cx - xa >= g->nx) continue;
+                    if (g->nx == 2 && xa == cx - 1) continue;
+                    x = (xa % g->nx + g->nx) % g->nx;
+                }
+                if (g->Ly > 0.0) {
+                    if (ya - cy >= g->ny || cy - ya >= g->ny) continue;
+                    if (g->ny == 2 && ya == cy - 1) continue;
+                    y = (ya % g->ny + g->ny) % g->ny;
+                }
                 if (x < 0 || y < 0 || z < 0 || x >= g->nx || y >= g->ny || z >= g->nz)
                     continue;
                 int64_t c = x + g->nx * (y + g->ny * z);
@@ -316,9 +406,8 @@ static void make_stencil(const OrcNbr* h, int64_t i, const int32_t* cand,
     unsigned covered = 0;
     for (int t = 0; t < nc; ++t) {
         int64_t j = cand[t];
-        double dx = h->px[j] - h->px[i];
-        double dy = h->py[j] - h->py[i];
-        double dz = h->pz[j] - h->pz[i];
+        double dx, dy, dz;
+        disp(h, i, j, &dx, &dy, &dz);
         double r2 = dx * dx + dy * dy;
         r2 = r2 + dz * dz;
         c[t].r2 = r2;
@@ -581,8 +670,8 @@ static unsigned fit_point(const OrcNbr* h, int64_t i, int nf, field_fn val,
     int r = 0;
     for (int t = 0; t < ns; ++t, ++r) {
         int64_t j = st[t];
-        double dx = h->px[j] - h->px[i], dy = h->py[j] - h->py[i],
-               dz = h->pz[j] - h->pz[i];
+        double dx, dy, dz;
+        disp(h, i, j, &dx, &dy, &dz);
         double wt = 1.0;
         if (h->cfg[C_WEIGHT] == 1.0) {
             double r2 = dx * dx + dy * dy + dz * dz;
@@ -902,8 +991,8 @@ int64_t orc_update(int64_t n, int32_t n_sys, const int64_t* off,
             double un = u[i] + dt * acc[i];
             double vn = v[i] + dt * acc[n + i];
             double wn = w[i] + dt * acc[2 * n + i];
-            x[i] = x[i] + dt * (0.5 * (u[i] + un));
-            y[i] = y[i] + dt * (0.5 * (v[i] + vn));
+            x[i] = wrap_coord(x[i] + dt * (0.5 * (u[i] + un)), p[P_XLO], p[P_LX]);
+            y[i] = wrap_coord(y[i] + dt * (0.5 * (v[i] + vn)), p[P_YLO], p[P_LY]);
             z[i] = z[i] + dt * (0.5 * (w[i] + wn));
             u[i] = un; v[i] = vn; w[i] = wn;
             V[i] = V[i] + dt * dVdt[i];
@@ -911,6 +1000,20 @@ int64_t orc_update(int64_t n, int32_t n_sys, const int64_t* off,
         }
     }
     return below;
+}
+
+/* Wraps positions along the periodic axes into their box (used by the
+ * second-order step's corrector). */
+void orc_wrap(int64_t n, int32_t n_sys, const int64_t* off, const double* prm,
+              double* x, double* y)
+{
+    for (int s = 0; s < n_sys; ++s) {
+        const double* p = prm + (size_t)s * P_NPRM;
+        for (int64_t i = off[s]; i < off[s + 1]; ++i) {
+            x[i] = wrap_coord(x[i], p[P_XLO], p[P_LX]);
+            y[i] = wrap_coord(y[i], p[P_YLO], p[P_LY]);
+        }
+    }
 }
 
 /* ------------------------------------------------------------------ */

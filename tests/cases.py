@@ -47,6 +47,24 @@ def _sparse_cloud(n=1500, seed=11):
     return lpgen.Workload("sparse_cloud", st, np.array([0, n]), [p], 1e-4, 1)
 
 
+def _periodic_layer(nx=12, ny=10, nz=8, axes=(True, True), seed=13):
+    """Layer periodic along x and/or y (box [0, nx h) x [0, ny h)) with
+    velocities and volumes that are smooth across the periodic faces, so
+    that stencils there reach through them."""
+    h = 1.0 / 16.0
+    Lx, Ly = nx * h, ny * h
+    p = lpgen.default_params(h, box_lo=(0.0, 0.0),
+                             box_len=(Lx if axes[0] else 0.0, Ly if axes[1] else 0.0))
+    st = lpgen.lattice_column(nx, ny, nz, h, seed=seed, params=p)
+    kx, ky = 2.0 * np.pi / Lx, 2.0 * np.pi / Ly
+    st.u = 0.3 * np.sin(kx * st.x) * np.cos(2.0 * st.z)
+    st.v = 0.2 * np.cos(ky * st.y + 0.3) * np.sin(1.7 * st.z + 0.4)
+    st.w = 0.25 * np.sin(kx * st.x + ky * st.y)
+    st.V = 1.0 / (0.47 + 0.15 * np.sin(4.0 * st.z / (h * 16) + ky * st.y))
+    name = "periodic_xy" if all(axes) else "periodic_x"
+    return lpgen.Workload(name, st, np.array([0, st.n]), [p], 1e-4, 1)
+
+
 CASES = {
     "column16": lambda: lpgen.column_small(),
     "lattice_exact": lambda: _with_flow(_exact_lattice()),
@@ -54,4 +72,6 @@ CASES = {
     "sheared_20x20x12": lambda: lpgen.column_sheared(nx=20, ny=20, nz=12),
     "ensemble_3": lambda: _with_flow(lpgen.ensemble(n_sys=3, n_lo=600, n_hi=3000)),
     "sparse_cloud": lambda: _sparse_cloud(),
+    "periodic_xy": lambda: _periodic_layer(),
+    "periodic_x": lambda: _periodic_layer(12, 9, 11, axes=(True, False), seed=17),
 }

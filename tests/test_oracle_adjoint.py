@@ -47,7 +47,8 @@ def _with_params(params, q, delta):
 
 
 @pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
-                                  "ensemble_3", "lattice_exact"])
+                                  "ensemble_3", "lattice_exact", "periodic_xy",
+                                  "periodic_x"])
 def test_frozen_forward_reproduces_oracle_step(case):
     wl = CASES[case]()
     ost, perm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt)
@@ -85,7 +86,8 @@ def _fd_step(wl, lam, v):
     raise AssertionError("stencils change at every eps")
 
 
-@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12"])
+@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
+                                  "periodic_xy"])
 @pytest.mark.parametrize("part", ["positions", "velocities", "volumes"])
 def test_state_adjoint_matches_central_differences(case, part):
     wl = CASES[case]()

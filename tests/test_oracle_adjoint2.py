@@ -20,7 +20,8 @@ from test_oracle_adjoint import _dot, _shift, _state_dir, _with_params
 
 
 @pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
-                                  "ensemble_3", "lattice_exact"])
+                                  "ensemble_3", "lattice_exact", "periodic_xy",
+                                  "periodic_x"])
 def test_frozen_forward_reproduces_oracle_step2(case):
     wl = CASES[case]()
     ost, perm, _ = oracle.step2(wl.state, wl.offsets, wl.params, wl.dt)
@@ -66,7 +67,8 @@ def _fd_step2(wl, lam, v):
     raise AssertionError("stencils change at every eps")
 
 
-@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12"])
+@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
+                                  "periodic_xy"])
 @pytest.mark.parametrize("part", ["positions", "velocities", "volumes"])
 def test_step2_state_adjoint_matches_central_differences(case, part):
     wl = CASES[case]()
