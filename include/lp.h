@@ -63,12 +63,20 @@ enum { LP_DEBUG_SORTED_STENCIL = 1, LP_DEBUG_QR_FIT = 2, LP_DEBUG_LANES2 = 4,
  * quasi-static branch; alpha, beta: quasi-static pressure
  * P = rho_s (alpha + beta phi) (eq. CST2); g: body force; h: particle
  * spacing (fit scaling, ghost offset); R: neighbour radius; wall_z: solid
- * wall plane z = wall_z (mirror boundary).  Requires
- * phi_min < phi_max < phi_c, beta > 0, R > 0, h > 0. */
+ * wall plane z = wall_z (mirror boundary).  box_lo, box_len: periodic
+ * boundary (Sec. 3.1, boundary conditions) along x (index 0) and y
+ * (index 1): an axis with box_len > 0 identifies x with x + box_len;
+ * particles see the copy of each neighbour nearest to them (x_j - L when
+ * x_j - x_i > L/2, x_j + L when below -L/2), and the steps map positions
+ * back into [box_lo, box_lo + box_len).  box_len = 0 leaves the axis open.
+ * Requires phi_min < phi_max < phi_c, beta > 0, R > 0, h > 0, and on a
+ * periodic axis box_len >= 3 R (1 + skin) (1 + 2^-20) with positions
+ * within one period of the box. */
 typedef struct {
     double rho_s, d, mu_s, mu_2, I0, phi_c, phi_min, phi_max, alpha, beta;
     double g[3];
     double h, R, wall_z;
+    double box_lo[2], box_len[2];
 } lp_params;
 
 /* Numerical configuration of a context.

@@ -35,6 +35,11 @@ def params_struct(p) -> LPParams:
         setattr(s, k, float(getattr(p, k)))
     for a in range(3):
         s.g[a] = float(p.g[a])
+    lo = getattr(p, "box_lo", (0.0, 0.0))
+    ln = getattr(p, "box_len", (0.0, 0.0))
+    for a in range(2):
+        s.box_lo[a] = float(lo[a])
+        s.box_len[a] = float(ln[a])
     return s
 
 

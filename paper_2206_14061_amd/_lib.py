@@ -35,7 +35,8 @@ class LPParams(C.Structure):
                 ("rho_s", "d", "mu_s", "mu_2", "I0", "phi_c", "phi_min",
                  "phi_max", "alpha", "beta")] + \
                [("g", C.c_double * 3)] + \
-               [(k, C.c_double) for k in ("h", "R", "wall_z")]
+               [(k, C.c_double) for k in ("h", "R", "wall_z")] + \
+               [("box_lo", C.c_double * 2), ("box_len", C.c_double * 2)]
 
 
 class LPConfig(C.Structure):

@@ -313,6 +313,19 @@ lp_status lp_set_systems(lp_ctx* c, int32_t n_sys, const int64_t* offsets,
             c->err = "invalid parameters of system " + std::to_string(s);
             return LP_E_ARG;
         }
+        // a periodic axis holds at least three list cells, so that each
+        // pair in the list has one nearest copy
+        const double cmin = p.R * (1.0 + c->cfg.skin) * (1.0 + 1.0 / 1048576.0);
+        for (int a = 0; a < 2; ++a) {
+            const double L = p.box_len[a];
+            if (!(L >= 0.0) || !std::isfinite(L) || !std::isfinite(p.box_lo[a]) ||
+                (L > 0.0 && !(L >= 3.0 * cmin))) {
+                c->err = "system " + std::to_string(s) +
+                         ": a periodic period must be 0 (open) or at least "
+                         "3 R (1 + skin)";
+                return LP_E_ARG;
+            }
+        }
     }
     if (offsets[n_sys] >= (1ll << 27)) {
         c->err = "at most 2^27 - 1 particles";
@@ -743,6 +756,11 @@ lp_status lp_sync_status(lp_ctx* c, int64_t* index)
                        c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (index) *index = (int64_t)ew.index;
+    if (ew.code & ERR_BOX) {
+        c->err = "particle " + std::to_string(ew.index) +
+                 " lies more than one period outside its periodic box";
+        return LP_E_ARG;
+    }
     if (ew.code & ERR_LIST) {
         c->err = "the predictor stage of a second-order step moved particle " +
                  std::to_string(ew.index) +

@@ -122,6 +122,13 @@ __global__ void k_grid(int n_sys, const int64_t* off, const lp_params* prm,
             g.inv_skin2 = skin > 0.0 ? 1.0 / ((skin * p.R) * (skin * p.R)) : 0.0;
             const double c = dmul(dmul(g.Rv, 1.0 + 1.0 / 1048576.0), scale);
             g.inv_c = 1.0 / c;
+            g.inv_cx = g.inv_cy = g.inv_c;
+            g.xlo = p.box_lo[0];
+            g.ylo = p.box_lo[1];
+            g.Lx = p.box_len[0];
+            g.Ly = p.box_len[1];
+            g.hLx = 0.5 * g.Lx;
+            g.hLy = 0.5 * g.Ly;
             if (g.pend > g.pbeg) {
                 double lo[3], hi[3];
                 for (int a = 0; a < 3; ++a) {
@@ -142,6 +149,24 @@ __global__ void k_grid(int n_sys, const int64_t* off, const lp_params* prm,
                     g.nx = (int)ex + 1;
                     g.ny = (int)ey + 1;
                     g.nz = (int)ez + 1;
+                }
+                // a periodic axis starts at its box and holds floor(L / c)
+                // cells of edge L / n (at least c)
+                if (g.Lx > 0.0) {
+                    const double e = dmul(g.Lx, g.inv_c);
+                    if (!(e < 65535.0)) bad = 1;
+                    const int np = e < 65535.0 ? (int)e : 1;
+                    g.nx = np < 1 ? 1 : np;
+                    g.x0 = g.xlo;
+                    g.inv_cx = (double)g.nx / g.Lx;
+                }
+                if (g.Ly > 0.0) {
+                    const double e = dmul(g.Ly, g.inv_c);
+                    if (!(e < 65535.0)) bad = 1;
+                    const int np = e < 65535.0 ? (int)e : 1;
+                    g.ny = np < 1 ? 1 : np;
+                    g.y0 = g.ylo;
+                    g.inv_cy = (double)g.ny / g.Ly;
                 }
             } else {
                 g.x0 = g.y0 = g.z0 = 0.0;
@@ -184,8 +209,9 @@ __global__ void k_grid(int n_sys, const int64_t* off, const lp_params* prm,
 __device__ __forceinline__ void cell_of(const GridInfo& g, double x, double y,
                                         double z, int& cx, int& cy, int& cz)
 {
-    int ix = (int)dmul(dsub(x, g.x0), g.inv_c);
-    int iy = (int)dmul(dsub(y, g.y0), g.inv_c);
+    const double xw = wrap_coord(x, g.xlo, g.Lx), yw = wrap_coord(y, g.ylo, g.Ly);
+    int ix = (int)dmul(dsub(xw, g.x0), g.inv_cx);
+    int iy = (int)dmul(dsub(yw, g.y0), g.inv_cy);
     int iz = (int)dmul(dsub(z, g.z0), g.inv_c);
     cx = ix < 0 ? 0 : (ix >= g.nx ? g.nx - 1 : ix);
     cy = iy < 0 ? 0 : (iy >= g.ny ? g.ny - 1 : iy);
@@ -196,7 +222,8 @@ __device__ __forceinline__ void cell_of(const GridInfo& g, double x, double y,
 __global__ void k_keys(int64_t n, int n_sys, const int64_t* off,
                        const GridInfo* grid, const double* x, const double* y,
                        const double* z, int shift_sys,
-                       unsigned long long* keys, int32_t* vals, const int32_t* gate)
+                       unsigned long long* keys, int32_t* vals, ErrWord* err,
+                       const int32_t* gate)
 {
     LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -207,6 +234,12 @@ __global__ void k_keys(int64_t n, int n_sys, const int64_t* off,
     cell_of(g, x[i], y[i], z[i], cx, cy, cz);
     keys[i] = ((unsigned long long)s << shift_sys) | morton3(cx, cy, cz);
     vals[i] = (int32_t)i;
+    // positions along a periodic axis must lie within one period of the box
+    const bool outx = g.Lx > 0.0 && !(x[i] >= dsub(g.xlo, g.Lx) &&
+                                      x[i] < dadd(g.xlo, dmul(2.0, g.Lx)));
+    const bool outy = g.Ly > 0.0 && !(y[i] >= dsub(g.ylo, g.Ly) &&
+                                      y[i] < dadd(g.ylo, dmul(2.0, g.Ly)));
+    if (outx || outy) raise_error(err, ERR_BOX, i);
 }
 
 // ---- stable LSD radix sort, 8-bit digits ------------------------------
@@ -386,7 +419,9 @@ __global__ __launch_bounds__(BLOCK) void k_disp(int64_t n, int n_sys, const int6
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const GridInfo& g = grid[sys_of(off, n_sys, i)];
-        const double dx = x[i] - rx[i], dy = y[i] - ry[i], dz = z[i] - rz[i];
+        const double dx = image_coord(x[i], rx[i], g.Lx, g.hLx) - rx[i];
+        const double dy = image_coord(y[i], ry[i], g.Ly, g.hLy) - ry[i];
+        const double dz = z[i] - rz[i];
         const double d2 = dx * dx + dy * dy + dz * dz;
         double q = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
         if (!(q == q)) q = INFINITY;   // non-finite positions force a rebuild
@@ -511,7 +546,7 @@ lp_status rebuild(lp_ctx* c, double* const st[7], int32_t* perm_out, int32_t* id
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, ns,
                            w.off, w.grid, st[0], st[1], st[2], shift_sys, w.keys0,
-                           w.vals0, gate);
+                           w.vals0, w.err, gate);
         radix_sort(c, n, bits, kr, vr, gate);
         hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
                            vr, st[0], st[1], st[2], st[3], st[4], st[5], st[6],

@@ -459,8 +459,10 @@ __device__ __forceinline__ void finish_rhs(const View& v, const lp_params& p,
         const double un = v.u[i] + dt * a[0];
         const double vn = v.v[i] + dt * a[1];
         const double wn = v.w[i] + dt * a[2];
-        const double xn = v.x[i] + dt * (0.5 * (v.u[i] + un));
-        const double yn = v.y[i] + dt * (0.5 * (v.v[i] + vn));
+        const double xn = wrap_coord(v.x[i] + dt * (0.5 * (v.u[i] + un)), p.box_lo[0],
+                                     p.box_len[0]);
+        const double yn = wrap_coord(v.y[i] + dt * (0.5 * (v.v[i] + vn)), p.box_lo[1],
+                                     p.box_len[1]);
         const double zn = v.z[i] + dt * (0.5 * (v.w[i] + wn));
         const double Vn = V + dt * dV;
         o.out[0][i] = xn;

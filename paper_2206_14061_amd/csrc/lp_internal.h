@@ -42,10 +42,14 @@ constexpr uint8_t FLAG_QR = 8;
 constexpr int ERR_CAPACITY = 1;
 constexpr int ERR_NUMERIC = 2;
 constexpr int ERR_LIST = 4;       // a predictor stage left the neighbour list
+constexpr int ERR_BOX = 8;        // a position lies beyond one period of its box
 
 // Per-system grid, built on the device from the bounding box.
 struct GridInfo {
     double x0, y0, z0, inv_c;   // origin, 1 / cell edge
+    double inv_cx, inv_cy;      // 1 / cell edge along x, y (periodic: n / L)
+    double xlo, ylo, Lx, Ly;    // periodic box (L = 0: open axis)
+    double hLx, hLy;            // L / 2
     double R2, h, inv_h, R, wall;
     double Rv, Rv2;             // list radius R (1 + skin) and its square
     double inv_skin2;           // 1 / (skin R)^2 (0 when skin = 0)
@@ -282,6 +286,27 @@ __device__ __forceinline__ double dadd(double a, double b)
 {
 #pragma clang fp contract(off)
     return a + b;
+}
+
+// Periodic axes (period L > 0; L = 0 leaves a coordinate unchanged): the
+// copy of xj nearest to xi (xj - L when xj - xi > L/2, xj + L when below
+// -L/2), and a coordinate within one period mapped into [lo, lo + L).
+__device__ __forceinline__ double image_coord(double xj, double xi, double L, double hL)
+{
+    if (L > 0.0) {
+        const double d = dsub(xj, xi);
+        if (d > hL) return dsub(xj, L);
+        if (d < -hL) return dadd(xj, L);
+    }
+    return xj;
+}
+__device__ __forceinline__ double wrap_coord(double x, double lo, double L)
+{
+    if (L > 0.0) {
+        if (x >= dadd(lo, L)) return dsub(x, L);
+        if (x < lo) return dadd(x, L);
+    }
+    return x;
 }
 
 // r^2 exactly as the method defines it: (dx*dx + dy*dy) + dz*dz, each

@@ -55,7 +55,9 @@ __global__ void k_stage_check(int64_t n, int n_sys, const int64_t* off,
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const GridInfo& g = grid[sys_of(off, n_sys, i)];
-    const double dx = x[i] - rx[i], dy = y[i] - ry[i], dz = z[i] - rz[i];
+    const double dx = image_coord(x[i], rx[i], g.Lx, g.hLx) - rx[i];
+    const double dy = image_coord(y[i], ry[i], g.Ly, g.hLy) - ry[i];
+    const double dz = z[i] - rz[i];
     const double q = (dx * dx + dy * dy + dz * dz) * g.inv_skin2;
     if (!(q < 0.25)) raise_error(err, ERR_LIST, i);
 }
@@ -67,9 +69,12 @@ __global__ void k_heun(int64_t n, int n_sys, const int64_t* off, const lp_params
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const lp_params& p = prm[sys_of(off, n_sys, i)];
     const double hdt = 0.5 * dt;
-    const double xn = s.p[0][i] + hdt * (s.p[3][i] + s2.p[3][i]);
-    const double yn = s.p[1][i] + hdt * (s.p[4][i] + s2.p[4][i]);
+    const double xn = wrap_coord(s.p[0][i] + hdt * (s.p[3][i] + s2.p[3][i]), p.box_lo[0],
+                                 p.box_len[0]);
+    const double yn = wrap_coord(s.p[1][i] + hdt * (s.p[4][i] + s2.p[4][i]), p.box_lo[1],
+                                 p.box_len[1]);
     const double zn = s.p[2][i] + hdt * (s.p[5][i] + s2.p[5][i]);
     const double un = s.p[3][i] + hdt * (acc1[i] + acc2[i]);
     const double vn = s.p[4][i] + hdt * (acc1[n + i] + acc2[n + i]);
@@ -85,7 +90,7 @@ __global__ void k_heun(int64_t n, int n_sys, const int64_t* off, const lp_params
     const bool finite = isfinite(xn) && isfinite(yn) && isfinite(zn) && isfinite(un) &&
                         isfinite(vn) && isfinite(wn) && isfinite(Vn);
     if (!finite) raise_error(err, ERR_NUMERIC, i);
-    if (zn < prm[sys_of(off, n_sys, i)].wall_z) atomicAdd(&cnt->below_wall, 1ull);
+    if (zn < p.wall_z) atomicAdd(&cnt->below_wall, 1ull);
 }
 
 }  // namespace

@@ -49,8 +49,9 @@ __device__ __forceinline__ int cover_bit(double dx, double dy, double dz,
 __device__ __forceinline__ void cell_clamp(const GridInfo& g, double x, double y,
                                            double z, int& cx, int& cy, int& cz)
 {
-    const int ix = (int)dmul(dsub(x, g.x0), g.inv_c);
-    const int iy = (int)dmul(dsub(y, g.y0), g.inv_c);
+    const double xw = wrap_coord(x, g.xlo, g.Lx), yw = wrap_coord(y, g.ylo, g.Ly);
+    const int ix = (int)dmul(dsub(xw, g.x0), g.inv_cx);
+    const int iy = (int)dmul(dsub(yw, g.y0), g.inv_cy);
     const int iz = (int)dmul(dsub(z, g.z0), g.inv_c);
     cx = ix < 0 ? 0 : (ix >= g.nx ? g.nx - 1 : ix);
     cy = iy < 0 ? 0 : (iy >= g.ny ? g.ny - 1 : iy);
@@ -74,21 +75,33 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
     const double Rv2 = g.Rv2 * (1.0 + 1e-12);
     const double xi = x[i], yi = y[i], zi = z[i];
     int cnt = 0;
+    // neighbouring cell d in {-1, 0, 1} of cell c along an axis of nc
+    // cells: clipped on an open axis; wrapped on a periodic one, where
+    // fewer than three cells are each visited once
+    auto nb_cell = [](int c, int d, int nc, bool periodic) {
+        if (!periodic) return (c + d < 0 || c + d >= nc) ? -1 : c + d;
+        if (nc < 3 && (d == -1 || (nc == 1 && d == 1))) return -1;
+        return (c + d + nc) % nc;
+    };
+    const bool px = g.Lx > 0.0, py = g.Ly > 0.0;
     auto scan = [&](double qx, double qy, double qz, bool mirror) {
         int cx, cy, cz;
         cell_clamp(g, qx, qy, qz, cx, cy, cz);
         for (int zz = cz - 1; zz <= cz + 1; ++zz) {
             if (zz < 0 || zz >= g.nz) continue;
-            for (int yy = cy - 1; yy <= cy + 1; ++yy) {
-                if (yy < 0 || yy >= g.ny) continue;
+            for (int dy0 = -1; dy0 <= 1; ++dy0) {
+                const int yy = nb_cell(cy, dy0, g.ny, py);
+                if (yy < 0) continue;
                 const int64_t row = g.cell_base + (int64_t)g.nx * (yy + (int64_t)g.ny * zz);
-                const int x0 = cx > 0 ? cx - 1 : 0;
-                const int x1 = cx + 1 < g.nx ? cx + 1 : g.nx - 1;
-                for (int xx = x0; xx <= x1; ++xx) {
+                for (int dx0 = -1; dx0 <= 1; ++dx0) {
+                    const int xx = nb_cell(cx, dx0, g.nx, px);
+                    if (xx < 0) continue;
                     const int64_t c = row + xx;
                     for (int32_t j = cs[c]; j < ce[c]; ++j) {
                         if (!mirror && j == (int32_t)i) continue;
-                        const double dx = x[j] - qx, dy = y[j] - qy, dz = z[j] - qz;
+                        const double dx = image_coord(x[j], qx, g.Lx, g.hLx) - qx;
+                        const double dy = image_coord(y[j], qy, g.Ly, g.hLy) - qy;
+                        const double dz = z[j] - qz;
                         if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
                         if (mirror && !(z[j] - g.wall < g.Rv)) continue;
                         if (cnt < VCAP)
@@ -291,7 +304,7 @@ __device__ __forceinline__ void for_candidates(const View& v, const GridInfo& g,
     const double R2 = g.R2;
     const int cnt = v.vcnt[i];
     for (int k = 0; k < cnt; ++k) {
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
         if (!p.valid) continue;
         const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
         const double r2 = dist2(dx, dy, dz);
@@ -333,7 +346,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     Mask4 cm;                          // candidate entries
     uint32_t mb_lo = 0xFFFFFFFFu, mb_hi = 0xFFFFFFFFu;
     for (int k = 0; k < cnt; ++k) {
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
         uint8_t kc = NO_CAND;
         if (p.valid) {
             const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
@@ -407,7 +420,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
         if (kc < bstar || (kc == bstar && !partial)) {
             mk.set(k);
         } else if (kc == bstar) {
-            const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+            const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
             const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
             const float f = (float)dist2(dx, dy, dz);
             lkey[nl][t] = (__float_as_uint(f) & ~0xFFu) | (uint32_t)k;
@@ -416,7 +429,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
         }
     }
     auto exact_key = [&](int k, double& r2, int32_t& id) {
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
         r2 = dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
         id = p.id;
     };
@@ -465,7 +478,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
             int bk = -1;
             for (int k = 0; k < cnt; ++k) {
                 if (code[(int64_t)k * n + i] != mo) continue;
-                const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+                const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
                 const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
                 if (octant_of(dx, dy, dz) != o) continue;
                 const double r2 = dist2(dx, dy, dz);
@@ -525,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_sorted(
             double r2 = 0.0;
             int32_t key = 0;
             if (k < cnt_i) {
-                const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+                const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
                 if (p.valid) {
                     const double dx = dsub(p.x, xi), dy = dsub(p.y, yi),
                                  dz = dsub(p.z, zi);

@@ -15,11 +15,19 @@ struct Pt {
     bool valid;
 };
 
+// Along periodic axes a point stands for its copy nearest to the particle
+// at (xi, yi).
+__device__ __forceinline__ void to_image(const GridInfo& g, Pt& p, double xi, double yi)
+{
+    p.x = image_coord(p.x, xi, g.Lx, g.hLx);
+    p.y = image_coord(p.y, yi, g.Ly, g.hLy);
+}
+
 // Point of neighbour-list entry e (a real id, or MBIT | source of a
 // potential mirror; the mirror exists while its source is within R of the
-// wall, and is placed at (x, y, 2 wall - z)).
+// wall, and is placed at (x, y, 2 wall - z)), seen from (xi, yi).
 __device__ __forceinline__ Pt list_point(const View& v, const GridInfo& g,
-                                         int32_t e)
+                                         int32_t e, double xi, double yi)
 {
     Pt p;
     if (e & MBIT) {
@@ -41,12 +49,14 @@ __device__ __forceinline__ Pt list_point(const View& v, const GridInfo& g,
         p.src = e;
         p.mirror = false;
     }
+    to_image(g, p, xi, yi);
     return p;
 }
 
-// Point of a stencil id (real id, or n + k for mirror k).
+// Point of a stencil id (real id, or n + k for mirror k), seen from
+// (xi, yi).
 __device__ __forceinline__ Pt id_point(const View& v, const GridInfo& g,
-                                       int32_t id)
+                                       int32_t id, double xi, double yi)
 {
     Pt p;
     p.valid = true;
@@ -65,6 +75,7 @@ __device__ __forceinline__ Pt id_point(const View& v, const GridInfo& g,
         p.src = j;
         p.mirror = true;
     }
+    to_image(g, p, xi, yi);
     return p;
 }
 
@@ -145,7 +156,7 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
     const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
     if (r.mode & MODE_SORTED) {
         for (int k = 0; k < r.m; ++k) {
-            const Pt p = id_point(v, g, v.hsten[(int64_t)k * n + i]);
+            const Pt p = id_point(v, g, v.hsten[(int64_t)k * n + i], xi, yi);
             f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
         }
         return;
@@ -153,7 +164,7 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
     MaskWalk mw(r);
     for (int t = 0; t < r.m; ++t) {
         const int k = mw.pop();
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
         f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
     }
 }
@@ -172,7 +183,7 @@ __device__ __forceinline__ void visit_stencil_sub(const View& v, const GridInfo&
     const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
     if (r.mode & MODE_SORTED) {
         for (int k = sub; k < r.m; k += LPP) {
-            const Pt p = id_point(v, g, v.hsten[(int64_t)k * n + i]);
+            const Pt p = id_point(v, g, v.hsten[(int64_t)k * n + i], xi, yi);
             f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
         }
         return;
@@ -181,7 +192,7 @@ __device__ __forceinline__ void visit_stencil_sub(const View& v, const GridInfo&
     for (int t = 0; t < sub && t < r.m; ++t) mw.pop();
     for (int t = sub; t < r.m; t += LPP) {
         const int k = mw.pop();
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i]);
+        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
         f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
         for (int u = 1; u < LPP && t + u < r.m; ++u) mw.pop();
     }

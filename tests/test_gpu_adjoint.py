@@ -32,7 +32,8 @@ def _dev(arrs):
 
 
 @pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
-                                  "ensemble_3", "lattice_exact", "sparse_cloud"])
+                                  "ensemble_3", "lattice_exact", "sparse_cloud",
+                                  "periodic_xy", "periodic_x"])
 def test_step_adjoint_parity(lp, case):
     import torch
     wl = CASES[case]()
@@ -148,7 +149,8 @@ def test_trajectory_gradient_matches_composed_oracle_adjoint(lp):
 
 
 @pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12",
-                                  "ensemble_3", "lattice_exact", "sparse_cloud"])
+                                  "ensemble_3", "lattice_exact", "sparse_cloud",
+                                  "periodic_xy"])
 def test_step2_adjoint_parity(lp, case):
     """lp_step2_adjoint (reverse of lp_build_cells + lp_step2) against the
     oracle's adjoint of the second-order step."""

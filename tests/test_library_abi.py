@@ -44,9 +44,9 @@ def test_binding_lists_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     """ctypes mirrors of lp_params / lp_config / lp_state have the C sizes
-    (16 doubles; natural alignment; 7 pointers)."""
+    (20 doubles; natural alignment; 7 pointers)."""
     from paper_2206_14061_amd import _lib
-    assert ctypes.sizeof(_lib.LPParams) == 16 * 8
+    assert ctypes.sizeof(_lib.LPParams) == 20 * 8
     assert ctypes.sizeof(_lib.LPConfig) == 56
     assert ctypes.sizeof(_lib.LPState) == 7 * 8
 
