@@ -291,10 +291,46 @@ def ensemble(seed: int = BASE_SEED + 5, n_sys: int = 64,
                     np.array(offs, dtype=np.int64), params, 2e-5, 20)
 
 
+def validation_params(h: float, **kw) -> Params:
+    """Grain constants of the paper's validation runs (Sec. 4): mu_s =
+    tan 30 deg, mu_2 = tan 50 deg, I0 = 2.65, d = 0.32 mm, rho_s = 2600
+    kg/m^3; phi_c = 0.60, phi_min = 0.35; the quasi-static law as in
+    default_params; R = 2.5 h."""
+    base = dict(mu_s=math.tan(math.radians(30.0)), mu_2=math.tan(math.radians(50.0)),
+                I0=2.65, d=0.32e-3, rho_s=2600.0)
+    base.update(kw)
+    return default_params(h, **base)
+
+
+def layer_profile(z: np.ndarray, H0: float, phi_bottom: float = 0.51,
+                  phi_top: float = 0.49) -> np.ndarray:
+    """Initial solid fraction of the compression layer: linear in height
+    from phi_bottom at the wall to phi_top at z = H0 (mean 0.5, so that
+    compaction to phi_c = 0.6 would leave 5/6 of the height)."""
+    return phi_bottom + (phi_top - phi_bottom) * np.asarray(z) / H0
+
+
+def layer_periodic(seed: int = BASE_SEED + 40, nx: int = 12, nz: int = 40,
+                   H0: float = 0.03) -> Workload:
+    """Granular layer of height H0 = 0.03 m on the wall z = 0, periodic in
+    x and y (box nx h x nx h, h = H0 / nz), at rest, with the solid
+    fraction of layer_profile (zero pressure: the inertial branch at zero
+    shear rate) and the grain constants of validation_params: the
+    compression test of the paper's Sec. 4.1.  dt = 5e-6 s; 0.05 s of
+    physical time settle it."""
+    h = H0 / nz
+    L = nx * h
+    p = validation_params(h, box_lo=(0.0, 0.0), box_len=(L, L))
+    st = lattice_column(nx, nx, nz, h, seed, params=p)
+    st.V = 1.0 / layer_profile(st.z, H0)
+    return Workload(f"layer_{nx}x{nx}x{nz}", st, np.array([0, st.n]), [p], 5e-6, 10000)
+
+
 WORKLOADS = {
     "column_small": column_small,
     "column_bench": column_bench,
     "column_sheared": column_sheared,
     "column_adjoint": column_adjoint,
     "ensemble": ensemble,
+    "layer_periodic": layer_periodic,
 }
