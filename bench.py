@@ -64,6 +64,9 @@ def _parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-second-order", action="store_true")
     ap.add_argument("--no-layer", action="store_true")
+    ap.add_argument("--collapse", action="store_true",
+                    help="also run the a = 0.6 column collapse (Sec. 4.2.1) and "
+                         "report its runout against the empirical fits")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three 1 GiB device-to-device copies, the "
                          "reference for the HBM byte counters")
@@ -251,6 +254,50 @@ def layer_bench(torch, lp, lpgen, t_end: float = 0.05, every: float = 0.005):
             "steps_per_s": nchunks * per / t}
 
 
+def collapse_run(torch, lp, lpgen, t_end: float = 0.17, every: float = 0.01,
+                 u_stop: float = 20.0):
+    """Axisymmetric column collapse, a = 0.6 (r_i = 0.05 m, h_i = 0.03 m,
+    120,631 particles, h = 1.25 mm): second-order steps with the reflecting
+    wall, the hydrostatic mirror pressure and a linear-fallback tolerance of
+    5e-2.  Reports the runout radius (99th percentile of the particle
+    radius), the centre height and the largest speed every `every` s, and
+    the empirical fits r_inf = r_i (1 + 1.24 a), h_inf = a r_i, t_inf =
+    3 sqrt(h_i / g).  Stops early once some particle exceeds u_stop m/s."""
+    wl = lpgen.column_cylinder()
+    p = wl.params[0]
+    ctx = lp.make_context(wl, wall_reflect=1, wall_pressure=1, fallback_tol=5e-2)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    per = int(round(every / wl.dt))
+    rows, stop = [], "t_end"
+    q = torch.tensor([0.99], dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    for c in range(int(round(t_end / every)) + 1):
+        if c:
+            try:
+                for _ in range(per):
+                    ctx.lp_step2(st, wl.dt, perm)
+                ctx.sync_status()
+            except lp.LPError as e:
+                stop = "error: %s" % e
+                break
+        r = torch.sqrt(st.t[0] ** 2 + st.t[1] ** 2)
+        u = torch.sqrt(st.t[3] ** 2 + st.t[4] ** 2 + st.t[5] ** 2)
+        core = r < 0.2 * 0.05
+        rows.append({"t": c * every, "r99_m": float(torch.quantile(r, q)),
+                     "h_center_m": float(st.t[2][core].max()) if bool(core.any()) else None,
+                     "u_max": float(u.max())})
+        if rows[-1]["u_max"] > u_stop:
+            stop = "u_max above %g m/s" % u_stop
+            break
+    a, r_i, h_i = 0.6, 0.05, 0.03
+    return {"workload": wl.name, "particles": wl.n, "dt": wl.dt, "series": rows,
+            "stopped": stop, "seconds": time.perf_counter() - t0,
+            "lube_r_inf_m": r_i * (1.0 + 1.24 * a), "lube_h_inf_m": a * r_i,
+            "lube_t_inf_s": 3.0 * (h_i / abs(p.g[2])) ** 0.5,
+            "paper_r_m": 0.085, "paper_h_m": 0.027}
+
+
 def ensemble_bench(torch, lp, lpgen, steps: int, adjoint_steps: int):
     """64 independent columns (8k-200k particles each, their own mu(I)
     parameters; 6.7M particles) advanced in the same launches: `steps`
@@ -427,6 +474,8 @@ def main():
         out["sheared"] = sheared_bench(torch, lp, lpgen, 20)
     if not args.no_layer:
         out["layer_compression"] = layer_bench(torch, lp, lpgen)
+    if args.collapse:
+        out["collapse"] = collapse_run(torch, lp, lpgen)
     if not args.no_ensemble:
         out["ensemble"] = ensemble_bench(torch, lp, lpgen, args.ensemble_steps,
                                          args.ensemble_adjoint_steps)

@@ -96,7 +96,18 @@ typedef struct {
  * every pair within R (1 + skin) and is rebuilt (with a Morton re-sort)
  * once a particle has moved skin R / 2 since the last build; 0 rebuilds
  * at every step.  Results do not depend on it except through the particle
- * order (ids), which changes only at rebuilds. */
+ * order (ids), which changes only at rebuilds.
+ * wall_reflect (default 0): with 1, a step that leaves a particle below the
+ * wall plane reflects it across the plane (z -> 2 wall_z - z, w -> -w);
+ * the paper states only the mirror boundary, through which particles can
+ * sink when the mirror pressure under-supports them.
+ * wall_pressure (default 0): with 1, a mirror's pressure (Sec. 3.1 step 9:
+ * P(phi_src) at zero shear rate) gains the hydrostatic weight of the layer
+ * between mirror and source, rho_s phi_src |g_z| (z_src - z_mirror)
+ * (the generalized wall condition of Adami, Hu & Adams, J. Comput. Phys.
+ * 231 (2012)); with the literal mirror a column at rest carries only about
+ * a third of its bottom row's weight.  The adjoint entry points require
+ * both options at 0. */
 typedef struct {
     int32_t m_max;
     int32_t precision;
@@ -106,6 +117,8 @@ typedef struct {
     double fallback_tol;
     int32_t debug_flags;
     double skin;
+    int32_t wall_reflect;
+    int32_t wall_pressure;
 } lp_config;
 
 /* Structure-of-arrays particle state, device float64 arrays of length n

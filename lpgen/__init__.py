@@ -326,6 +326,26 @@ def layer_periodic(seed: int = BASE_SEED + 40, nx: int = 12, nz: int = 40,
     return Workload(f"layer_{nx}x{nx}x{nz}", st, np.array([0, st.n]), [p], 5e-6, 10000)
 
 
+def column_cylinder(seed: int = BASE_SEED + 50, r_i: float = 0.05, h_i: float = 0.03,
+                    h: float = 1.25e-3) -> Workload:
+    """Axisymmetric column of radius r_i and height h_i (aspect a =
+    h_i / r_i = 0.6 by default) standing on the wall z = 0 and released
+    at rest: the collapse test of the paper's Sec. 4.2.1.  Jittered lattice
+    of spacing h on [-r_i, r_i]^2 x [0, h_i] (lattice_column), keeping the
+    particles with x^2 + y^2 <= r_i^2 (lattice order); hydrostatic
+    quasi-static solid fraction; grain constants of validation_params.
+    dt = 0.2 h / 35 m/s (the quasi-static sound speed is sqrt(beta))."""
+    n = int(round(2.0 * r_i / h))
+    nz = int(round(h_i / h))
+    p = validation_params(h)
+    st = lattice_column(n, n, nz, h, seed, x0=-r_i, y0=-r_i, params=p)
+    keep = np.nonzero(st.x * st.x + st.y * st.y <= r_i * r_i)[0]
+    st = st.take(keep)
+    dt = 0.2 * h / math.sqrt(p.beta)
+    return Workload(f"cylinder_a{h_i / r_i:.2f}_h{h * 1e3:.2f}mm", st,
+                    np.array([0, st.n]), [p], dt, int(math.ceil(0.17 / dt)))
+
+
 WORKLOADS = {
     "column_small": column_small,
     "column_bench": column_bench,

@@ -28,7 +28,7 @@ _lock = threading.Lock()
 _lib = None
 
 CFG_DEFAULT = dict(m_max=60, ghost_margin=0.5, phi_ghost_frac=0.99,
-                   fallback_tol=1e-12, weight=0)
+                   fallback_tol=1e-12, weight=0, wall_reflect=0, wall_pressure=0)
 
 FLAG_LINEAR = 1
 BR_GAS, BR_INERTIAL, BR_QUASI = 0, 1, 2
@@ -67,9 +67,9 @@ def _load():
     lib.orc_fit.restype = C.c_int
     lib.orc_eval.argtypes = [P] * 8
     lib.orc_eval.restype = C.c_int
-    lib.orc_update.argtypes = [i64, i32, P, P, C.c_double] + [P] * 9
+    lib.orc_update.argtypes = [i64, i32, P, P, C.c_double] + [P] * 9 + [C.c_int]
     lib.orc_update.restype = i64
-    lib.orc_wrap.argtypes = [i64, i32, P, P, P, P]
+    lib.orc_boundary.argtypes = [i64, i32, P, P, P, P, P, P, C.c_int]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_lsq.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P]
     lib.orc_lsq.restype = C.c_double
@@ -96,7 +96,7 @@ def cfg_vector(cfg: Optional[dict] = None) -> np.ndarray:
     if cfg:
         c.update(cfg)
     return np.array([c["m_max"], c["ghost_margin"], c["phi_ghost_frac"],
-                     c["fallback_tol"], c["weight"]], dtype=np.float64)
+                     c["fallback_tol"], c["weight"], c["wall_pressure"]], dtype=np.float64)
 
 
 def prm_matrix(params: Sequence[Params]) -> np.ndarray:
@@ -243,10 +243,15 @@ class Oracle:
         return out
 
 
+def _reflect(cfg: Optional[dict]) -> int:
+    return int(bool((cfg or {}).get("wall_reflect", 0)))
+
+
 def update(state: State, offsets, params: Sequence[Params], dt: float,
-           acc: np.ndarray, dVdt: np.ndarray):
-    """Explicit update in place; returns the count of particles below the
-    wall afterwards."""
+           acc: np.ndarray, dVdt: np.ndarray, reflect: int = 0):
+    """Explicit update in place (with `reflect`, particles ending below the
+    wall are reflected across it); returns the count of particles below
+    the wall afterwards."""
     lib = _load()
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     prm = prm_matrix(params)
@@ -257,7 +262,7 @@ def update(state: State, offsets, params: Sequence[Params], dt: float,
         assert a.dtype == np.float64 and a.flags.c_contiguous
     return int(lib.orc_update(state.n, len(params), _ptr(off), _ptr(prm),
                               float(dt), *[_ptr(a) for a in arrs], _ptr(acc),
-                              _ptr(dVdt)))
+                              _ptr(dVdt), int(reflect)))
 
 
 def step(state: State, offsets, params: Sequence[Params], dt: float,
@@ -273,7 +278,7 @@ def step(state: State, offsets, params: Sequence[Params], dt: float,
     st = State(*[np.ascontiguousarray(a) for a in st.arrays()])
     o = Oracle(st, offsets, params, cfg, brute)
     r = o.evaluate()
-    update(st, offsets, params, dt, r["acc"], r["dVdt"])
+    update(st, offsets, params, dt, r["acc"], r["dVdt"], _reflect(cfg))
     return st, perm, r
 
 
@@ -306,15 +311,17 @@ def step2(state: State, offsets, params: Sequence[Params], dt: float,
     pos = [p + half * (q + qs) for p, q, qs in zip((st.x, st.y, st.z), vel, pvel)]
     new_vel = [q + half * (a1[k] + a2[k]) for k, q in enumerate(vel)]
     out = State(*pos, *new_vel, st.V + half * (d1 + d2))
-    wrap(out, offsets, params)
+    wrap(out, offsets, params, _reflect(cfg))
     return out, perm, (r1, r2)
 
 
-def wrap(state: State, offsets, params: Sequence[Params]):
-    """Maps x and y along periodic axes into their box, in place."""
+def wrap(state: State, offsets, params: Sequence[Params], reflect: int = 0):
+    """Maps x and y along periodic axes into their box, in place; with
+    `reflect`, particles below the wall are reflected across it."""
     lib = _load()
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     prm = prm_matrix(params)
-    for a in (state.x, state.y):
+    for a in (state.x, state.y, state.z, state.w):
         assert a.dtype == np.float64 and a.flags.c_contiguous
-    lib.orc_wrap(state.n, len(params), _ptr(off), _ptr(prm), _ptr(state.x), _ptr(state.y))
+    lib.orc_boundary(state.n, len(params), _ptr(off), _ptr(prm), _ptr(state.x),
+                     _ptr(state.y), _ptr(state.z), _ptr(state.w), int(reflect))

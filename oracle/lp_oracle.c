@@ -33,8 +33,9 @@
  *
  * Parameter record (per system, 16 doubles):
  *   rho_s d mu_s mu_2 I0 phi_c phi_min phi_max alpha beta gx gy gz h R wall_z
- * Config record (5 doubles):
+ * Config record (6 doubles):
  *   m_max ghost_margin(*h) phi_ghost_frac fallback_tol weight(0 unit,1 gauss)
+ *   wall_pressure(0 mirror P(phi_src), 1 plus the hydrostatic weight)
  */
 #include <math.h>
 #include <stdint.h>
@@ -47,7 +48,7 @@
 enum { P_RHO, P_D, P_MUS, P_MU2, P_I0, P_PHIC, P_PHIMIN, P_PHIMAX, P_ALPHA,
        P_BETA, P_GX, P_GY, P_GZ, P_H, P_R, P_WALL, P_XLO, P_YLO, P_LX, P_LY,
        P_NPRM };
-enum { C_MMAX, C_GMARGIN, C_PHIG, C_FTOL, C_WEIGHT, C_NCFG };
+enum { C_MMAX, C_GMARGIN, C_PHIG, C_FTOL, C_WEIGHT, C_WALLP, C_NCFG };
 
 #define NC 9          /* unknowns of the 2nd-order 3D fit            */
 #define MAXROWS 256   /* rows the oracle can hold for one stencil    */
@@ -836,7 +837,14 @@ static double p2_val(const void* c, int64_t j, int f)
     if (j < n) return f == 0 ? q->P[j] : q->eta[j];
     if (f == 1) return 0.0;
     int64_t s = q->h->msrc[j - n];
-    return mirror_pressure(q->h->prm + (size_t)q->h->sys[s] * P_NPRM, q->h->pV[j]);
+    const double* p = q->h->prm + (size_t)q->h->sys[s] * P_NPRM;
+    double Pm = mirror_pressure(p, q->h->pV[j]);
+    /* hydrostatic wall pressure (an option, after Adami, Hu & Adams 2012):
+     * the mirror also carries the weight of the layer between it and its
+     * source, rho_s phi_src |g_z| (z_src - z_mirror) */
+    if (q->h->cfg[C_WALLP] == 1.0)
+        Pm = Pm + p[P_RHO] * (1.0 / q->h->pV[j]) * (-p[P_GZ]) * (q->h->pz[s] - q->h->pz[j]);
+    return Pm;
 }
 
 static const int HIDX[3][3] = {{3, 6, 7}, {6, 4, 8}, {7, 8, 5}};
@@ -979,10 +987,21 @@ int orc_eval(void* hp, double* coef_u, double* diag, double* grad,
 /* Explicit update (Sec. 3.1 step 8 and step 10):
  *   V' = V + dt dV/dt,  u' = u + dt a,  x' = x + dt (u + u') / 2.
  * Returns the number of particles that end below their wall plane. */
+/* Reflecting wall (an option; the paper states only the mirror boundary):
+ * a particle that ends a step below the wall plane is reflected across it,
+ * z -> 2 wall - z, w -> -w. */
+static void reflect_wall(double wall, double* z, double* w)
+{
+    if (*z < wall) {
+        *z = 2.0 * wall - *z;
+        *w = -*w;
+    }
+}
+
 int64_t orc_update(int64_t n, int32_t n_sys, const int64_t* off,
                    const double* prm, double dt, double* x, double* y,
                    double* z, double* u, double* v, double* w, double* V,
-                   const double* acc, const double* dVdt)
+                   const double* acc, const double* dVdt, int reflect)
 {
     int64_t below = 0;
     for (int s = 0; s < n_sys; ++s) {
@@ -996,22 +1015,25 @@ int64_t orc_update(int64_t n, int32_t n_sys, const int64_t* off,
             z[i] = z[i] + dt * (0.5 * (w[i] + wn));
             u[i] = un; v[i] = vn; w[i] = wn;
             V[i] = V[i] + dt * dVdt[i];
+            if (reflect) reflect_wall(p[P_WALL], &z[i], &w[i]);
             if (z[i] < p[P_WALL]) ++below;
         }
     }
     return below;
 }
 
-/* Wraps positions along the periodic axes into their box (used by the
- * second-order step's corrector). */
-void orc_wrap(int64_t n, int32_t n_sys, const int64_t* off, const double* prm,
-              double* x, double* y)
+/* Boundary treatment of a step's result (used by the second-order step's
+ * corrector): positions wrapped along the periodic axes into their box,
+ * and with `reflect` the reflecting wall. */
+void orc_boundary(int64_t n, int32_t n_sys, const int64_t* off, const double* prm,
+                  double* x, double* y, double* z, double* w, int reflect)
 {
     for (int s = 0; s < n_sys; ++s) {
         const double* p = prm + (size_t)s * P_NPRM;
         for (int64_t i = off[s]; i < off[s + 1]; ++i) {
             x[i] = wrap_coord(x[i], p[P_XLO], p[P_LX]);
             y[i] = wrap_coord(y[i], p[P_YLO], p[P_LY]);
+            if (reflect) reflect_wall(p[P_WALL], &z[i], &w[i]);
         }
     }
 }

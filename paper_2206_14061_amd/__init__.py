@@ -91,7 +91,8 @@ class Context:
     def __init__(self, m_max: int = 60, precision: int = LP_FP64,
                  cond_max: float = 20.0, weight: int = LP_W_UNIT,
                  ghost_margin: float = 0.5, fallback_tol: float = 1e-12,
-                 debug_flags: int = 0, skin: float = 0.1, stream=None):
+                 debug_flags: int = 0, skin: float = 0.1, wall_reflect: int = 0,
+                 wall_pressure: int = 0, stream=None):
         torch = _torch()
         self.lib = _lib.load()
         cfg = LPConfig()
@@ -100,6 +101,8 @@ class Context:
         cfg.weight, cfg.ghost_margin = weight, ghost_margin
         cfg.fallback_tol, cfg.debug_flags = fallback_tol, debug_flags
         cfg.skin = skin
+        cfg.wall_reflect = int(wall_reflect)
+        cfg.wall_pressure = int(wall_pressure)
         self.cfg = cfg
         if stream is None:
             stream = torch.cuda.current_stream()

@@ -46,6 +46,7 @@ View make_view(lp_ctx* c, const double* const st[7])
     v.redo_ratio = 1.0 / c->cfg.cond_max;
     v.weight = c->cfg.weight;
     v.debug = c->cfg.debug_flags;
+    v.wall_pressure = c->cfg.wall_pressure;
     return v;
 }
 
@@ -166,6 +167,8 @@ void lp_config_default(lp_config* cfg)
     cfg->fallback_tol = 1e-12;
     cfg->debug_flags = 0;
     cfg->skin = 0.1;
+    cfg->wall_reflect = 0;
+    cfg->wall_pressure = 0;
 }
 
 lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
@@ -179,7 +182,9 @@ lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
         !(c0.ghost_margin >= 0.0) || !(c0.fallback_tol >= 0.0) ||
         (c0.weight != LP_W_UNIT && c0.weight != LP_W_GAUSS) ||
         (c0.precision != LP_FP64 && c0.precision != LP_FP32_REFINED) ||
-        !(c0.skin >= 0.0 && c0.skin <= 1.0))
+        !(c0.skin >= 0.0 && c0.skin <= 1.0) ||
+        (c0.wall_reflect != 0 && c0.wall_reflect != 1) ||
+        (c0.wall_pressure != 0 && c0.wall_pressure != 1))
         return LP_E_ARG;
     lp_ctx* c = new (std::nothrow) lp_ctx();
     if (!c) return LP_E_ARG;
@@ -629,8 +634,8 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
     }
     lp_status r = check_ready(c, s);
     if (r != LP_OK) return r;
-    if (c->cfg.weight != LP_W_UNIT) {
-        c->err = "lp_step_adjoint supports unit weights only";
+    if (c->cfg.weight != LP_W_UNIT || c->cfg.wall_reflect || c->cfg.wall_pressure) {
+        c->err = "lp_step_adjoint supports unit weights and the mirror wall only";
         return LP_E_ARG;
     }
     if ((int64_t)c->cfg.m_max * c->n >= (1ll << 31)) {
@@ -675,8 +680,8 @@ lp_status lp_step2_adjoint(lp_ctx* c, const lp_state* s, double dt,
     }
     lp_status r = check_ready(c, s);
     if (r != LP_OK) return r;
-    if (c->cfg.weight != LP_W_UNIT) {
-        c->err = "lp_step2_adjoint supports unit weights only";
+    if (c->cfg.weight != LP_W_UNIT || c->cfg.wall_reflect || c->cfg.wall_pressure) {
+        c->err = "lp_step2_adjoint supports unit weights and the mirror wall only";
         return LP_E_ARG;
     }
     if (!(c->cfg.skin > 0.0)) {

@@ -422,6 +422,7 @@ struct RhsOut {
     double dt;
     ErrWord* err;
     Counters* cnt;
+    int reflect;        // reflecting wall (step mode)
 };
 
 __device__ __forceinline__ void finish_rhs(const View& v, const lp_params& p,
@@ -463,14 +464,19 @@ __device__ __forceinline__ void finish_rhs(const View& v, const lp_params& p,
                                      p.box_len[0]);
         const double yn = wrap_coord(v.y[i] + dt * (0.5 * (v.v[i] + vn)), p.box_lo[1],
                                      p.box_len[1]);
-        const double zn = v.z[i] + dt * (0.5 * (v.w[i] + wn));
+        double zn = v.z[i] + dt * (0.5 * (v.w[i] + wn));
         const double Vn = V + dt * dV;
+        double wr = wn;
+        if (o.reflect && zn < p.wall_z) {
+            zn = dsub(dmul(2.0, p.wall_z), zn);
+            wr = -wn;
+        }
         o.out[0][i] = xn;
         o.out[1][i] = yn;
         o.out[2][i] = zn;
         o.out[3][i] = un;
         o.out[4][i] = vn;
-        o.out[5][i] = wn;
+        o.out[5][i] = wr;
         o.out[6][i] = Vn;
         const bool finite = isfinite(xn) && isfinite(yn) && isfinite(zn) &&
                             isfinite(un) && isfinite(vn) && isfinite(wn) &&
@@ -928,6 +934,7 @@ static RhsOut rhs_out(lp_ctx* c, double* acc, double* dVdt, double* grad)
     o.dt = 0.0;
     o.err = c->w.err;
     o.cnt = c->w.cnt;
+    o.reflect = c->cfg.wall_reflect;
     return o;
 }
 

@@ -377,7 +377,12 @@ __device__ __forceinline__ void pass2_values(const View& v, const double* P,
         Pj = P[p->src];
         Ej = eta[p->src];
     } else {
-        Pj = mirror_pressure(prm, v.V[p->src]);
+        const double Vs = v.V[p->src];
+        Pj = mirror_pressure(prm, Vs);
+        // hydrostatic wall pressure (option): plus the weight of the layer
+        // between the mirror and its source
+        if (v.wall_pressure)
+            Pj = Pj + prm.rho_s * (1.0 / Vs) * (-prm.g[2]) * (v.z[p->src] - p->z);
         Ej = 0.0;
     }
 }

@@ -109,6 +109,7 @@ struct View {
     double redo_ratio;          // Gram pivot ratio that triggers a QR refit
     int32_t weight;
     int32_t debug;
+    int32_t wall_pressure;      // hydrostatic mirror pressure
 };
 
 struct Work {

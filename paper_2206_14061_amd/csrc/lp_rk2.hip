@@ -65,7 +65,7 @@ __global__ void k_stage_check(int64_t n, int n_sys, const int64_t* off,
 __global__ void k_heun(int64_t n, int n_sys, const int64_t* off, const lp_params* prm,
                        S7 s, S7 s2, const double* acc1, const double* acc2,
                        const double* dV1, const double* dV2, double dt, O7 o,
-                       ErrWord* err, Counters* cnt)
+                       ErrWord* err, Counters* cnt, int reflect)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -75,10 +75,14 @@ __global__ void k_heun(int64_t n, int n_sys, const int64_t* off, const lp_params
                                  p.box_len[0]);
     const double yn = wrap_coord(s.p[1][i] + hdt * (s.p[4][i] + s2.p[4][i]), p.box_lo[1],
                                  p.box_len[1]);
-    const double zn = s.p[2][i] + hdt * (s.p[5][i] + s2.p[5][i]);
+    double zn = s.p[2][i] + hdt * (s.p[5][i] + s2.p[5][i]);
     const double un = s.p[3][i] + hdt * (acc1[i] + acc2[i]);
     const double vn = s.p[4][i] + hdt * (acc1[n + i] + acc2[n + i]);
-    const double wn = s.p[5][i] + hdt * (acc1[2 * n + i] + acc2[2 * n + i]);
+    double wn = s.p[5][i] + hdt * (acc1[2 * n + i] + acc2[2 * n + i]);
+    if (reflect && zn < p.wall_z) {
+        zn = dsub(dmul(2.0, p.wall_z), zn);
+        wn = -wn;
+    }
     const double Vn = s.p[6][i] + hdt * (dV1[i] + dV2[i]);
     o.p[0][i] = xn;
     o.p[1][i] = yn;
@@ -138,7 +142,7 @@ lp_status step_heun(lp_ctx* c, double dt, double* const out[7])
     hipLaunchKernelGGL(k_heun, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n, c->n_sys,
                        w.off, w.prm, s1, s2, (const double*)w.acc, (const double*)w.acc2,
                        (const double*)w.dVdt, (const double*)w.dVdt2, dt, oo, w.err,
-                       w.cnt);
+                       w.cnt, c->cfg.wall_reflect);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "corrector launch");
 }

@@ -444,3 +444,59 @@ def test_error_paths_report_cleanly(lp):
         small.set_systems([0, wl.n], wl.params)
         small.lp_step(st, 1e-4)
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("case", ["column16", "column16_flow_ragged", "sheared_20x20x12",
+                                  "periodic_xy", "ensemble_3"])
+def test_hydrostatic_wall_pressure_parity(lp, case):
+    """wall_pressure = 1 (mirrors carry the hydrostatic weight between them
+    and their source): a step against the oracle with the same option."""
+    import torch
+    wl = CASES[case]()
+    ctx = lp.make_context(wl, wall_pressure=1)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    ctx.lp_step(st, wl.dt, perm)
+    ctx.sync_status()
+    want, operm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt,
+                                 cfg=dict(wall_pressure=1))
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = wl.state.take(operm)
+    for k, (a, b, c) in enumerate(zip(st.to_host().arrays(), want.arrays(), old.arrays())):
+        ok, e = _incr_ok(a, b, c)
+        assert ok, (lp.DeviceState.NAMES[k], e)
+
+
+@pytest.mark.parametrize("kind", ["step", "step2"])
+def test_reflecting_wall_parity(lp, kind):
+    """wall_reflect = 1: the ragged flowing column lowered so that its
+    bottom row sits 2-8 mm above the wall and pushed down at 10 m/s for
+    1 ms, so that this row crosses the wall in one step; both step kinds
+    against the oracle with the same option (skin 0.3 keeps the
+    second-order predictor inside the list)."""
+    import torch
+    wl = CASES["column16_flow_ragged"]()
+    st0 = wl.state.copy()
+    st0.z = st0.z - 0.026
+    st0.w = st0.w - 10.0
+    dt, skin = 1e-3, 0.3
+    ctx = lp.make_context(wl, wall_reflect=1, wall_pressure=1, skin=skin)
+    st = lp.DeviceState.from_host(st0)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    (ctx.lp_step2 if kind == "step2" else ctx.lp_step)(st, dt, perm)
+    ctx.sync_status()
+    fn = oracle.step2 if kind == "step2" else oracle.step
+    want, operm, _ = fn(st0, wl.offsets, wl.params, dt, skin=skin,
+                        cfg=dict(wall_reflect=1, wall_pressure=1))
+    free, _, _ = fn(st0, wl.offsets, wl.params, dt, skin=skin,
+                    cfg=dict(wall_pressure=1))
+    crossed = int(np.sum(free.z < 0.0))
+    _log("%s: %d particles reflected" % (kind, crossed))
+    assert crossed > 50 and np.all(want.z >= 0.0)
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = st0.take(operm)
+    got = st.to_host()
+    for k, (a, b, c) in enumerate(zip(got.arrays(), want.arrays(), old.arrays())):
+        ok, e = _incr_ok(a, b, c)
+        assert ok, (lp.DeviceState.NAMES[k], e)
+    assert ctx.stats()["below_wall"] == 0
