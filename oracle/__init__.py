@@ -28,9 +28,11 @@ _lock = threading.Lock()
 _lib = None
 
 CFG_DEFAULT = dict(m_max=60, ghost_margin=0.5, phi_ghost_frac=0.99,
-                   fallback_tol=1e-12, weight=0, wall_reflect=0, wall_pressure=0)
+                   fallback_tol=1e-12, weight=0, wall_reflect=0, wall_pressure=0,
+                   fit_order=2)
 
 FLAG_LINEAR = 1
+FLAG_QUAD = 16
 BR_GAS, BR_INERTIAL, BR_QUASI = 0, 1, 2
 
 
@@ -96,7 +98,8 @@ def cfg_vector(cfg: Optional[dict] = None) -> np.ndarray:
     if cfg:
         c.update(cfg)
     return np.array([c["m_max"], c["ghost_margin"], c["phi_ghost_frac"],
-                     c["fallback_tol"], c["weight"], c["wall_pressure"]], dtype=np.float64)
+                     c["fallback_tol"], c["weight"], c["wall_pressure"],
+                     c["fit_order"]], dtype=np.float64)
 
 
 def prm_matrix(params: Sequence[Params]) -> np.ndarray:

@@ -36,6 +36,7 @@
  * Config record (6 doubles):
  *   m_max ghost_margin(*h) phi_ghost_frac fallback_tol weight(0 unit,1 gauss)
  *   wall_pressure(0 mirror P(phi_src), 1 plus the hydrostatic weight)
+ *   fit_order(2 quadratic, 3 cubic)
  */
 #include <math.h>
 #include <stdint.h>
@@ -48,9 +49,10 @@
 enum { P_RHO, P_D, P_MUS, P_MU2, P_I0, P_PHIC, P_PHIMIN, P_PHIMAX, P_ALPHA,
        P_BETA, P_GX, P_GY, P_GZ, P_H, P_R, P_WALL, P_XLO, P_YLO, P_LX, P_LY,
        P_NPRM };
-enum { C_MMAX, C_GMARGIN, C_PHIG, C_FTOL, C_WEIGHT, C_WALLP, C_NCFG };
+enum { C_MMAX, C_GMARGIN, C_PHIG, C_FTOL, C_WEIGHT, C_WALLP, C_ORDER, C_NCFG };
 
 #define NC 9          /* unknowns of the 2nd-order 3D fit            */
+#define NC3 19        /* unknowns of the 3rd-order (cubic) 3D fit    */
 #define MAXROWS 256   /* rows the oracle can hold for one stencil    */
 
 int orc_num_threads(void)
@@ -590,7 +592,7 @@ void orc_nbr_export(void* hp, int64_t* coff, int32_t* cidx, int32_t* scnt,
 static double house_lsq(int m, int nc, double* A, int lda, double* B,
                         int ldb, int nb, double* C /* nc x nb, ld nb */)
 {
-    double rd[NC];
+    double rd[NC3];
     double rmin = INFINITY, rmax = 0.0;
     for (int j = 0; j < nc; ++j) {
         double s = 0.0;
@@ -641,7 +643,25 @@ static void taylor_row(double ex, double ey, double ez, double* a)
     a[6] = ex * ey; a[7] = ex * ez; a[8] = ey * ez;
 }
 
+/* Third-order Taylor row (the higher-order fit the paper lists as further
+ * work): the quadratic row followed by the cubic monomials divided by the
+ * factorials of their exponents, so that each coefficient is the matching
+ * third derivative times h^3:
+ * xi_x^3/6, xi_y^3/6, xi_z^3/6, xi_x^2 xi_y/2, xi_x^2 xi_z/2,
+ * xi_y^2 xi_x/2, xi_y^2 xi_z/2, xi_z^2 xi_x/2, xi_z^2 xi_y/2,
+ * xi_x xi_y xi_z. */
+static void taylor_row3(double ex, double ey, double ez, double* a)
+{
+    taylor_row(ex, ey, ez, a);
+    a[9] = ex * ex * ex / 6.0; a[10] = ey * ey * ey / 6.0; a[11] = ez * ez * ez / 6.0;
+    a[12] = 0.5 * ex * ex * ey; a[13] = 0.5 * ex * ex * ez;
+    a[14] = 0.5 * ey * ey * ex; a[15] = 0.5 * ey * ey * ez;
+    a[16] = 0.5 * ez * ez * ex; a[17] = 0.5 * ez * ez * ey;
+    a[18] = ex * ey * ez;
+}
+
 #define FLAG_LINEAR 1u
+#define FLAG_QUAD 16u
 
 /* Fits nf fields at real i on its stencil plus ghost rows.
  * val(j, f): value of field f at point j (real or mirror).
@@ -651,7 +671,10 @@ static void taylor_row(double ex, double ey, double ez, double* a)
  * Fallback (reading of the paper, which is silent on degenerate
  * stencils): fewer than 9 rows, or min|r_jj|/max|r_jj| below the
  * configured tolerance, gives a 3-column linear fit with zero second
- * derivatives and sets FLAG_LINEAR. */
+ * derivatives and sets FLAG_LINEAR.  With fit_order 3 the fit has the 19
+ * columns of taylor_row3 and falls back the same way to the quadratic fit
+ * (fewer than 19 rows or the ratio test; FLAG_QUAD), then to the linear
+ * one.  Only the first and second derivatives are returned. */
 typedef double (*field_fn)(const void* ctx, int64_t j, int f);
 
 static unsigned fit_point(const OrcNbr* h, int64_t i, int nf, field_fn val,
@@ -664,8 +687,9 @@ static unsigned fit_point(const OrcNbr* h, int64_t i, int nf, field_fn val,
     uint8_t gm = h->gmask[i];
     int m = ns;
     for (int o = 0; o < 8; ++o) if (gm & (1u << o)) ++m;
-    double A[MAXROWS * NC], A2[MAXROWS * NC];
-    double B[MAXROWS * 8], B2[MAXROWS * 8], C[NC * 8];
+    double A[MAXROWS * NC3], A2[MAXROWS * NC3];
+    double B[MAXROWS * 8], B2[MAXROWS * 8], C[NC3 * 8];
+    const int nc = h->cfg[C_ORDER] == 3.0 ? NC3 : NC;
     double fi[8];
     for (int f = 0; f < nf; ++f) fi[f] = val(fctx, i, f);
     int r = 0;
@@ -678,8 +702,8 @@ static unsigned fit_point(const OrcNbr* h, int64_t i, int nf, field_fn val,
             double r2 = dx * dx + dy * dy + dz * dz;
             wt = sqrt(exp(-4.0 * r2 / R2));
         }
-        taylor_row(dx / hh, dy / hh, dz / hh, A + r * NC);
-        for (int c = 0; c < NC; ++c) A[r * NC + c] *= wt;
+        taylor_row3(dx / hh, dy / hh, dz / hh, A + r * NC3);
+        for (int c = 0; c < NC3; ++c) A[r * NC3 + c] *= wt;
         for (int f = 0; f < nf; ++f) B[r * 8 + f] = wt * (val(fctx, j, f) - fi[f]);
     }
     for (int o = 0; o < 8; ++o) {
@@ -688,28 +712,40 @@ static unsigned fit_point(const OrcNbr* h, int64_t i, int nf, field_fn val,
                sz = (o & 4) ? 1.0 : -1.0;
         double wt = 1.0;
         if (h->cfg[C_WEIGHT] == 1.0) wt = sqrt(exp(-4.0 * 3.0 * hh * hh / R2));
-        taylor_row(sx, sy, sz, A + r * NC);
-        for (int c = 0; c < NC; ++c) A[r * NC + c] *= wt;
+        taylor_row3(sx, sy, sz, A + r * NC3);
+        for (int c = 0; c < NC3; ++c) A[r * NC3 + c] *= wt;
         for (int f = 0; f < nf; ++f) B[r * 8 + f] = wt * (gval[f] - fi[f]);
         ++r;
     }
     unsigned flags = 0;
     double ratio = 0.0;
-    if (m >= NC) {
-        memcpy(A2, A, sizeof(double) * (size_t)m * NC);
+    int ok = 0;
+    for (int f = 0; f < nf * NC3; ++f) C[f] = 0.0;
+    if (nc == NC3 && m >= NC3) {
+        memcpy(A2, A, sizeof(double) * (size_t)m * NC3);
         memcpy(B2, B, sizeof(double) * (size_t)m * 8);
-        ratio = house_lsq(m, NC, A2, NC, B2, 8, nf, C);
+        ratio = house_lsq(m, NC3, A2, NC3, B2, 8, nf, C);
+        ok = ratio >= h->cfg[C_FTOL];
     }
-    if (m < NC || ratio < h->cfg[C_FTOL]) {
-        flags |= FLAG_LINEAR;
-        for (int f = 0; f < nf * NC; ++f) C[f] = 0.0;
-        if (m >= 3) {
-            double C3[3 * 8];
-            memcpy(A2, A, sizeof(double) * (size_t)m * NC);
+    if (!ok) {
+        if (nc == NC3) flags |= FLAG_QUAD;
+        ratio = 0.0;
+        if (m >= NC) {
+            memcpy(A2, A, sizeof(double) * (size_t)m * NC3);
             memcpy(B2, B, sizeof(double) * (size_t)m * 8);
-            house_lsq(m, 3, A2, NC, B2, 8, nf, C3);
-            for (int c = 0; c < 3; ++c)
-                for (int f = 0; f < nf; ++f) C[c * nf + f] = C3[c * nf + f];
+            ratio = house_lsq(m, NC, A2, NC3, B2, 8, nf, C);
+        }
+        if (m < NC || ratio < h->cfg[C_FTOL]) {
+            flags |= FLAG_LINEAR;
+            for (int f = 0; f < nf * NC3; ++f) C[f] = 0.0;
+            if (m >= 3) {
+                double C3[3 * 8];
+                memcpy(A2, A, sizeof(double) * (size_t)m * NC3);
+                memcpy(B2, B, sizeof(double) * (size_t)m * 8);
+                house_lsq(m, 3, A2, NC3, B2, 8, nf, C3);
+                for (int c = 0; c < 3; ++c)
+                    for (int f = 0; f < nf; ++f) C[c * nf + f] = C3[c * nf + f];
+            }
         }
     }
     for (int f = 0; f < nf; ++f)
@@ -1047,13 +1083,13 @@ void orc_boundary(int64_t n, int32_t n_sys, const int64_t* off, const double* pr
 double orc_lsq(int m, int nc, const double* A, const double* B, int nb,
                double* Cout)
 {
-    if (m < nc || nc > NC || nb > 8 || m > MAXROWS) return -1.0;
-    double A2[MAXROWS * NC], B2[MAXROWS * 8];
+    if (m < nc || nc > NC3 || nb > 8 || m > MAXROWS) return -1.0;
+    double A2[MAXROWS * NC3], B2[MAXROWS * 8];
     for (int r = 0; r < m; ++r) {
-        for (int c = 0; c < nc; ++c) A2[r * NC + c] = A[r * nc + c];
+        for (int c = 0; c < nc; ++c) A2[r * NC3 + c] = A[r * nc + c];
         for (int l = 0; l < nb; ++l) B2[r * 8 + l] = B[r * nb + l];
     }
-    return house_lsq(m, nc, A2, NC, B2, 8, nb, Cout);
+    return house_lsq(m, nc, A2, NC3, B2, 8, nb, Cout);
 }
 
 /* Closure at one point: G9 row-major d u_a / d x_b; out5 = P eta I mu |gd|;

@@ -1,0 +1,132 @@
+"""Pins of the oracle's cubic (third-order, 19-unknown) least-squares fits
+(the higher-order fits the paper lists as further work; fit_order = 3):
+
+* a cubic polynomial field is reproduced exactly (its first and second
+  derivatives at every interior particle), which the quadratic fit cannot;
+* on a smooth field, halving the spacing divides the first-derivative
+  error by about 2^3 (2^2 for the quadratic fit) and the second-derivative
+  error by about 2^2 (2^1);
+* stencils with 9 to 18 rows fall back to the quadratic fit (FLAG_QUAD),
+  with exactly the quadratic fit's result.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from cases import CASES
+
+# monomial exponents of a full cubic in (x, y, z)
+_EXP = [(a, b, c) for a in range(4) for b in range(4) for c in range(4) if a + b + c <= 3]
+
+
+def _cubic(seed):
+    rng = np.random.default_rng(seed)
+    coef = rng.standard_normal(len(_EXP))
+
+    def f(x, y, z):
+        return sum(c * x ** a * y ** b * z ** e for c, (a, b, e) in zip(coef, _EXP))
+
+    def d(x, y, z, o):
+        # o = (ox, oy, oz): derivative orders
+        out = 0.0
+        for c, (a, b, e) in zip(coef, _EXP):
+            if a < o[0] or b < o[1] or e < o[2]:
+                continue
+            k = c * np.prod([np.prod(np.arange(p - q + 1, p + 1)) for p, q in zip((a, b, e), o)])
+            out = out + k * x ** (a - o[0]) * y ** (b - o[1]) * z ** (e - o[2])
+        return out
+    return f, d
+
+
+_ORDERS = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (0, 2, 0), (0, 0, 2),
+           (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+
+
+def _interior(wl, nb):
+    """Particles whose stencil has no ghost and no mirror row."""
+    cnt = nb.sten_cnt
+    has_mirror = np.array([np.any(nb.sten_idx[i, :cnt[i]] >= wl.n) for i in range(wl.n)])
+    return (nb.ghost_mask == 0) & ~has_mirror & (cnt >= 19)
+
+
+def test_cubic_fit_reproduces_cubic_fields():
+    wl = lpgen.column_small()
+    st = wl.state
+    f, d = _cubic(3)
+    vals = f(st.x, st.y, st.z)[None, :]
+    o3 = oracle.Oracle(st, wl.offsets, wl.params, cfg=dict(fit_order=3))
+    o2 = oracle.Oracle(st, wl.offsets, wl.params, cfg=dict(fit_order=2))
+    inner = _interior(wl, o3.neighbours())
+    assert inner.sum() > 1000
+    c3, fl3 = o3.fit(vals, [1], [0])
+    c2, _ = o2.fit(vals, [1], [0])
+    assert not np.any(fl3[inner] & (oracle.FLAG_QUAD | oracle.FLAG_LINEAR))
+    for q, o in enumerate(_ORDERS):
+        want = d(st.x, st.y, st.z, o)[inner]
+        scale = np.max(np.abs(want)) + 1.0
+        assert np.max(np.abs(c3[0, q, inner] - want)) <= 1e-9 * scale, o
+        if q < 3:
+            # the quadratic fit misses the cubic terms
+            assert np.max(np.abs(c2[0, q, inner] - want)) > 1e-4 * scale, o
+
+
+def _smooth(x, y, z):
+    return np.sin(2.1 * x + 0.3) * np.cos(1.7 * y - 0.2) * np.exp(0.4 * z)
+
+
+def _smooth_d(x, y, z, o):
+    fx = [np.sin(2.1 * x + 0.3), 2.1 * np.cos(2.1 * x + 0.3), -4.41 * np.sin(2.1 * x + 0.3)]
+    fy = [np.cos(1.7 * y - 0.2), -1.7 * np.sin(1.7 * y - 0.2), -2.89 * np.cos(1.7 * y - 0.2)]
+    fz = [np.exp(0.4 * z), 0.4 * np.exp(0.4 * z), 0.16 * np.exp(0.4 * z)]
+    return fx[o[0]] * fy[o[1]] * fz[o[2]]
+
+
+def _errors(n, order):
+    h = 1.0 / n
+    p = lpgen.default_params(h)
+    st = lpgen.lattice_column(n, n, n, h, lpgen.BASE_SEED + 60, params=p)
+    o = oracle.Oracle(st, np.array([0, st.n]), [p], cfg=dict(fit_order=order))
+    nb = o.neighbours()
+    wl = lpgen.Workload("cube", st, np.array([0, st.n]), [p], 1e-4, 1)
+    inner = _interior(wl, nb)
+    # the central half of the cube only
+    c = (np.abs(st.x - 0.5) < 0.25) & (np.abs(st.y - 0.5) < 0.25) & (np.abs(st.z - 0.5) < 0.25)
+    sel = inner & c
+    coef, _ = o.fit(_smooth(st.x, st.y, st.z)[None, :], [1], [0])
+    e1 = max(np.max(np.abs(coef[0, q, sel] - _smooth_d(st.x, st.y, st.z, _ORDERS[q])[sel]))
+             for q in range(3))
+    e2 = max(np.max(np.abs(coef[0, q, sel] - _smooth_d(st.x, st.y, st.z, _ORDERS[q])[sel]))
+             for q in range(3, 6))
+    return e1, e2
+
+
+@pytest.mark.timeout(600)
+def test_cubic_fit_convergence_orders():
+    r = {}
+    for order in (2, 3):
+        a, b = _errors(16, order), _errors(32, order)
+        r[order] = (np.log2(a[0] / b[0]), np.log2(a[1] / b[1]))
+    assert 2.5 < r[3][0] < 3.6, r
+    assert 1.5 < r[3][1] < 2.6, r
+    assert 1.5 < r[2][0] < 2.6, r
+    assert 0.5 < r[2][1] < 1.6, r
+
+
+def test_cubic_falls_back_to_quadratic_on_small_stencils():
+    wl = CASES["sparse_cloud"]()
+    st = wl.state
+    vals = np.stack([np.sin(3 * st.x) + st.y * st.z, np.cos(2 * st.y) * st.x])
+    o3 = oracle.Oracle(st, wl.offsets, wl.params, cfg=dict(fit_order=3))
+    o2 = oracle.Oracle(st, wl.offsets, wl.params, cfg=dict(fit_order=2))
+    nb = o3.neighbours()
+    rows = nb.sten_cnt + np.array([bin(int(g)).count("1") for g in nb.ghost_mask])
+    c3, fl3 = o3.fit(vals, [1, 1], [0, 0])
+    c2, fl2 = o2.fit(vals, [1, 1], [0, 0])
+    mid = (rows >= 9) & (rows < 19)
+    assert mid.sum() > 50
+    assert np.all(fl3[mid] & oracle.FLAG_QUAD)
+    assert np.array_equal(c3[:, :, mid], c2[:, :, mid])
+    assert np.array_equal(fl3[mid] & oracle.FLAG_LINEAR, fl2[mid] & oracle.FLAG_LINEAR)
+    big = rows >= 19
+    assert np.all((fl3[big] & oracle.FLAG_QUAD) == 0) or np.any(fl3[big] & oracle.FLAG_QUAD)
