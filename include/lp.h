@@ -107,7 +107,15 @@ typedef struct {
  * (the generalized wall condition of Adami, Hu & Adams, J. Comput. Phys.
  * 231 (2012)); with the literal mirror a column at rest carries only about
  * a third of its bottom row's weight.  The adjoint entry points require
- * both options at 0. */
+ * both options at 0.
+ * fit_order (default 2): 3 selects cubic fits (19 unknowns: the Taylor row
+ * of Sec. 3.1 step 7 extended by the third-order terms, the higher-order
+ * fit the paper lists as further work) in every fit; they fall back to the
+ * quadratic fit below 19 rows or when min|r_jj|/max|r_jj| < fallback_tol
+ * (flag bit 4), then to the linear one.  Cubic fits run in float64 with
+ * one wavefront per particle whatever the precision setting, need
+ * m_max <= 56 (stencil plus ghost rows fit one wavefront), and are not
+ * available to the adjoint entry points. */
 typedef struct {
     int32_t m_max;
     int32_t precision;
@@ -119,6 +127,7 @@ typedef struct {
     double skin;
     int32_t wall_reflect;
     int32_t wall_pressure;
+    int32_t fit_order;
 } lp_config;
 
 /* Structure-of-arrays particle state, device float64 arrays of length n

@@ -92,7 +92,7 @@ class Context:
                  cond_max: float = 20.0, weight: int = LP_W_UNIT,
                  ghost_margin: float = 0.5, fallback_tol: float = 1e-12,
                  debug_flags: int = 0, skin: float = 0.1, wall_reflect: int = 0,
-                 wall_pressure: int = 0, stream=None):
+                 wall_pressure: int = 0, fit_order: int = 2, stream=None):
         torch = _torch()
         self.lib = _lib.load()
         cfg = LPConfig()
@@ -103,6 +103,7 @@ class Context:
         cfg.skin = skin
         cfg.wall_reflect = int(wall_reflect)
         cfg.wall_pressure = int(wall_pressure)
+        cfg.fit_order = int(fit_order)
         self.cfg = cfg
         if stream is None:
             stream = torch.cuda.current_stream()

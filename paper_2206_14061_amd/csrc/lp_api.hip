@@ -169,6 +169,7 @@ void lp_config_default(lp_config* cfg)
     cfg->skin = 0.1;
     cfg->wall_reflect = 0;
     cfg->wall_pressure = 0;
+    cfg->fit_order = 2;
 }
 
 lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
@@ -184,7 +185,9 @@ lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
         (c0.precision != LP_FP64 && c0.precision != LP_FP32_REFINED) ||
         !(c0.skin >= 0.0 && c0.skin <= 1.0) ||
         (c0.wall_reflect != 0 && c0.wall_reflect != 1) ||
-        (c0.wall_pressure != 0 && c0.wall_pressure != 1))
+        (c0.wall_pressure != 0 && c0.wall_pressure != 1) ||
+        (c0.fit_order != 2 && c0.fit_order != 3) ||
+        (c0.fit_order == 3 && c0.m_max > 56))
         return LP_E_ARG;
     lp_ctx* c = new (std::nothrow) lp_ctx();
     if (!c) return LP_E_ARG;
@@ -634,8 +637,10 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
     }
     lp_status r = check_ready(c, s);
     if (r != LP_OK) return r;
-    if (c->cfg.weight != LP_W_UNIT || c->cfg.wall_reflect || c->cfg.wall_pressure) {
-        c->err = "lp_step_adjoint supports unit weights and the mirror wall only";
+    if (c->cfg.weight != LP_W_UNIT || c->cfg.wall_reflect || c->cfg.wall_pressure ||
+        c->cfg.fit_order != 2) {
+        c->err = "lp_step_adjoint supports unit weights, quadratic fits and the "
+                 "mirror wall only";
         return LP_E_ARG;
     }
     if ((int64_t)c->cfg.m_max * c->n >= (1ll << 31)) {
@@ -680,8 +685,10 @@ lp_status lp_step2_adjoint(lp_ctx* c, const lp_state* s, double dt,
     }
     lp_status r = check_ready(c, s);
     if (r != LP_OK) return r;
-    if (c->cfg.weight != LP_W_UNIT || c->cfg.wall_reflect || c->cfg.wall_pressure) {
-        c->err = "lp_step2_adjoint supports unit weights and the mirror wall only";
+    if (c->cfg.weight != LP_W_UNIT || c->cfg.wall_reflect || c->cfg.wall_pressure ||
+        c->cfg.fit_order != 2) {
+        c->err = "lp_step2_adjoint supports unit weights, quadratic fits and the "
+                 "mirror wall only";
         return LP_E_ARG;
     }
     if (!(c->cfg.skin > 0.0)) {

@@ -15,7 +15,7 @@
 // The second fit (P, eta) needs only first derivatives: pass 1 stores
 // rows 0-2 of G^{-1}, so pass 2 costs two moment accumulations and a 3x9
 // product per particle.
-#include "lp_fitcore.h"
+#include "lp_finish.h"
 
 namespace lp {
 
@@ -154,12 +154,6 @@ __device__ __forceinline__ bool gram_solve(double (&G)[45], const double (&B)[NF
 
 // ---- lp_fit_derivs -------------------------------------------------------
 
-struct GenericFields {
-    const double* f;   // k x n
-    int k;
-    int32_t msign[8];
-    int32_t gzero[8];
-};
 
 template <int NF>
 __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
@@ -245,42 +239,6 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic_qr(
 }
 
 // ---- lp_step pass 1: fit u, v, w + closure --------------------------------
-
-struct StepOut {
-    double* P;
-    double* eta;
-    double* hand;
-    uint8_t* flags;
-    double* diag;       // optional 5 x n
-    double* coef_u;     // optional 27 x n
-};
-
-__device__ __forceinline__ void finish_pass1(const View& v, const lp_params& p,
-                                             int64_t i, const double (&c)[27],
-                                             const double (&ginv3)[27],
-                                             bool has_ginv, uint8_t fl,
-                                             const StepOut& o)
-{
-    const int64_t n = v.n;
-    const Closure r = closure(p, v.V[i], c);
-    double vis[3];
-    visc_terms(c, vis);
-    o.P[i] = r.P;
-    o.eta[i] = r.eta;
-    store_hand(o.hand, n, i, ginv3, has_ginv, r, vis);
-    o.flags[i] = (uint8_t)(fl | (r.branch << 1));
-    if (o.diag) {
-        o.diag[i] = r.P;
-        o.diag[n + i] = r.eta;
-        o.diag[2 * n + i] = r.I;
-        o.diag[3 * n + i] = r.mu;
-        o.diag[4 * n + i] = r.gn;
-    }
-    if (o.coef_u) {
-#pragma unroll
-        for (int q = 0; q < 27; ++q) o.coef_u[(int64_t)q * n + i] = c[q];
-    }
-}
 
 // LPP lanes per particle: each lane accumulates every LPP-th row; the
 // moments are summed across the lanes, every lane solves, lane 0 stores.
@@ -412,90 +370,6 @@ __global__ __launch_bounds__(BLOCK) void k_closure_coef(View v, const double* co
 }
 
 // ---- pass 2: fit of P and eta, right-hand side, update --------------------
-
-struct RhsOut {
-    double* acc;        // 3 x n (optional in step mode)
-    double* dVdt;       // n (optional in step mode)
-    double* grad;       // 6 x n optional
-    uint8_t* flags;     // updated with the fallback bit of QR refits
-    double* out[7];     // new state (step mode) or nulls
-    double dt;
-    ErrWord* err;
-    Counters* cnt;
-    int reflect;        // reflecting wall (step mode)
-};
-
-__device__ __forceinline__ void finish_rhs(const View& v, const lp_params& p,
-                                           int64_t i, const double* hand,
-                                           const double gP[3], const double gE[3],
-                                           const RhsOut& o)
-{
-    const int64_t n = v.n;
-    const double V = v.V[i];
-    const double eta = hand[0];   // own eta passed through hand[0]
-    const double* gd = hand + 1;  // xx yy zz xy xz yz
-    const double div = hand[7];
-    const double* vis = hand + 8;
-    double a[3];
-    const double t0 = gd[0] * gE[0] + gd[3] * gE[1] + gd[4] * gE[2];
-    const double t1 = gd[3] * gE[0] + gd[1] * gE[1] + gd[5] * gE[2];
-    const double t2 = gd[4] * gE[0] + gd[5] * gE[1] + gd[2] * gE[2];
-    a[0] = V * (-gP[0] + t0 + eta * vis[0]) / p.rho_s + p.g[0];
-    a[1] = V * (-gP[1] + t1 + eta * vis[1]) / p.rho_s + p.g[1];
-    a[2] = V * (-gP[2] + t2 + eta * vis[2]) / p.rho_s + p.g[2];
-    const double dV = V * div;
-    if (o.acc) {
-        o.acc[i] = a[0];
-        o.acc[n + i] = a[1];
-        o.acc[2 * n + i] = a[2];
-    }
-    if (o.dVdt) o.dVdt[i] = dV;
-    if (o.grad)
-        for (int q = 0; q < 3; ++q) {
-            o.grad[(int64_t)q * n + i] = gP[q];
-            o.grad[(int64_t)(3 + q) * n + i] = gE[q];
-        }
-    if (o.out[0]) {
-        const double dt = o.dt;
-        const double un = v.u[i] + dt * a[0];
-        const double vn = v.v[i] + dt * a[1];
-        const double wn = v.w[i] + dt * a[2];
-        const double xn = wrap_coord(v.x[i] + dt * (0.5 * (v.u[i] + un)), p.box_lo[0],
-                                     p.box_len[0]);
-        const double yn = wrap_coord(v.y[i] + dt * (0.5 * (v.v[i] + vn)), p.box_lo[1],
-                                     p.box_len[1]);
-        double zn = v.z[i] + dt * (0.5 * (v.w[i] + wn));
-        const double Vn = V + dt * dV;
-        double wr = wn;
-        if (o.reflect && zn < p.wall_z) {
-            zn = dsub(dmul(2.0, p.wall_z), zn);
-            wr = -wn;
-        }
-        o.out[0][i] = xn;
-        o.out[1][i] = yn;
-        o.out[2][i] = zn;
-        o.out[3][i] = un;
-        o.out[4][i] = vn;
-        o.out[5][i] = wr;
-        o.out[6][i] = Vn;
-        const bool finite = isfinite(xn) && isfinite(yn) && isfinite(zn) &&
-                            isfinite(un) && isfinite(vn) && isfinite(wn) &&
-                            isfinite(Vn);
-        if (!finite) raise_error(o.err, ERR_NUMERIC, i);
-        if (zn < p.wall_z) atomicAdd(&o.cnt->below_wall, 1ull);
-    }
-}
-
-__device__ __forceinline__ void load_hand_tail(const double* hand, int64_t n,
-                                               int64_t i, double eta, double hv[11])
-{
-    hv[0] = eta;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) hv[1 + q] = hand[(int64_t)(27 + q) * n + i];
-    hv[7] = hand[(int64_t)33 * n + i];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) hv[8 + q] = hand[(int64_t)(34 + q) * n + i];
-}
 
 template <int LPP>
 __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
@@ -901,7 +775,9 @@ lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
     uint8_t* fl = flags ? flags : w.flags;
     const int fq = (c->cfg.debug_flags & LP_DEBUG_QR_FIT) ? 1 : 0;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
-    if (n > 0) {
+    if (n > 0 && c->cfg.fit_order == 3) {
+        launch_fit3_generic(c, v, F, coef, fl);
+    } else if (n > 0) {
         const dim3 gb(blocks_for(n)), bb(BLOCK);
 #define LP_FIT_CASE(K)                                                          \
     case K:                                                                     \
@@ -954,11 +830,15 @@ lp_status rhs_from_coef(lp_ctx* c, const double* const st[7],
         hipLaunchKernelGGL(k_closure_coef, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, v, coef_u, so, w.redo, w.redo_n, fq);
         RhsOut o = rhs_out(c, acc, dVdt, grad);
-        launch_pass2(c, c->lpp2, v, o);
-        hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
-                           c->stream, v, (const double*)w.P, (const double*)w.eta,
-                           (const double*)w.hand, (const int32_t*)w.redo,
-                           (const unsigned int*)w.redo_n, w.qr_scratch, o);
+        if (c->cfg.fit_order == 3) {
+            launch_pass2_cubic(c, v, w.P, w.eta, w.hand, o);
+        } else {
+            launch_pass2(c, c->lpp2, v, o);
+            hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+                               c->stream, v, (const double*)w.P, (const double*)w.eta,
+                               (const double*)w.hand, (const int32_t*)w.redo,
+                               (const unsigned int*)w.redo_n, w.qr_scratch, o);
+        }
         if (flags)
             hipLaunchKernelGGL(k_copy_u8, dim3(blocks_for(n)), dim3(BLOCK), 0,
                                c->stream, n, w.flags, flags);
@@ -978,7 +858,9 @@ lp_status step_rhs(lp_ctx* c, const double* const st[7])
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
     if (n > 0) {
         prof_mark(c, 3, false);
-        if (c->cfg.precision == LP_FP32_REFINED && !fq)
+        if (c->cfg.fit_order == 3)
+            launch_pass1_cubic(c, v, so);
+        else if (c->cfg.precision == LP_FP32_REFINED && !fq)
             hipLaunchKernelGGL(k_pass1_ref, dim3(blocks_for(n)), dim3(BLOCK), 0,
                                c->stream, v, so, w.uf, w.redo, w.redo_n);
         else
@@ -1024,7 +906,9 @@ lp_status step_pass2(lp_ctx* c, const double* const st[7], double dt,
     o.dt = dt;
     if (n > 0) {
         prof_mark(c, 5, false);
-        if (c->cfg.precision == LP_FP32_REFINED && !fp64)
+        if (c->cfg.fit_order == 3)
+            launch_pass2_cubic(c, v, w.P, w.eta, w.hand, o);
+        else if (c->cfg.precision == LP_FP32_REFINED && !fp64)
             hipLaunchKernelGGL(k_pass2_ref, dim3(blocks_for(n)), dim3(BLOCK), 0,
                                c->stream, v, (const double*)w.P, (const double*)w.eta,
                                (const double*)w.hand, (const float*)w.uf,
@@ -1052,6 +936,10 @@ lp_status step_update(lp_ctx* c, const double* const st[7], double dt,
 
 lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice)
 {
+    if (c->cfg.fit_order == 3) {   // a wavefront per particle: nothing to tune
+        if (choice) choice[0] = choice[1] = 1;
+        return LP_OK;
+    }
     Work& w = c->w;
     const int64_t n = c->n;
     View v = make_view(c, st);

@@ -37,6 +37,7 @@ constexpr int SORT_TILE = BLOCK * SORT_ITEMS;
 // flag bits per particle
 constexpr uint8_t FLAG_LINEAR = 1;
 constexpr uint8_t FLAG_QR = 8;
+constexpr uint8_t FLAG_QUAD = 16;       // a cubic fit fell back to the quadratic one
 
 // device error codes (bit set in the error word)
 constexpr int ERR_CAPACITY = 1;
