@@ -64,6 +64,7 @@ def _parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-second-order", action="store_true")
     ap.add_argument("--no-layer", action="store_true")
+    ap.add_argument("--no-cubic", action="store_true")
     ap.add_argument("--collapse", action="store_true",
                     help="also run the a = 0.6 column collapse (Sec. 4.2.1) and "
                          "report its runout against the empirical fits")
@@ -215,6 +216,39 @@ def second_order_bench(torch, lp, wl, steps: int, warmup: int, precision: int,
             "rhs_evals_per_step": 2, "particle_rhs_evals_per_s": 2 * wl.n / (ms * 1e-3),
             "cost_vs_first_order_step": ms / ms_first_order, "steps": steps,
             "stats": ctx.stats()}
+
+
+def cubic_bench(torch, lp, wl, steps: int, warmup: int):
+    """lp_step with cubic (19-unknown) fits on the benchmark column (m_max
+    56 so that stencil and ghost rows fill one wavefront), with the phase
+    split; against the quadratic fits at the same m_max."""
+    out = {"m_max": 56}
+    for name, order in (("cubic", 3), ("quadratic", 2)):
+        ctx = lp.make_context(wl, fit_order=order, m_max=56)
+        st = lp.DeviceState.from_host(wl.state)
+        for _ in range(warmup):
+            ctx.lp_step(st, wl.dt)
+        ctx.sync_status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.lp_step(st, wl.dt)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.profile(True)
+        ctx.profile_read()
+        for _ in range(steps):
+            ctx.lp_step(st, wl.dt)
+        torch.cuda.synchronize()
+        ph = ctx.profile_read()
+        ctx.profile(False)
+        ctx.sync_status()
+        nst = max(ph.pop("steps"), 1)
+        out[name] = {"ms_per_step": 1e3 * t / steps, "value": wl.n * steps / t,
+                     "unit": "particle-updates/s",
+                     "phases_ms": {k: v / nst for k, v in ph.items()}}
+    out["cost_vs_quadratic"] = out["cubic"]["ms_per_step"] / out["quadratic"]["ms_per_step"]
+    return out
 
 
 def layer_bench(torch, lp, lpgen, t_end: float = 0.05, every: float = 0.005):
@@ -465,6 +499,8 @@ def main():
     if not args.no_second_order:
         out["second_order"] = second_order_bench(torch, lp, wl, args.steps, args.warmup,
                                                  main_prec, ms_per_step)
+    if not args.no_cubic:
+        out["cubic_fits"] = cubic_bench(torch, lp, wl, args.steps, args.warmup)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
         if not args.no_second_order:

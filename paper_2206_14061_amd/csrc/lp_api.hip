@@ -47,6 +47,7 @@ View make_view(lp_ctx* c, const double* const st[7])
     v.weight = c->cfg.weight;
     v.debug = c->cfg.debug_flags;
     v.wall_pressure = c->cfg.wall_pressure;
+    v.periodic = c->periodic ? 1 : 0;
     return v;
 }
 
@@ -341,6 +342,9 @@ lp_status lp_set_systems(lp_ctx* c, int32_t n_sys, const int64_t* offsets,
     }
     c->h_off.assign(offsets, offsets + n_sys + 1);
     c->h_prm.assign(params, params + n_sys);
+    c->periodic = false;
+    for (const lp_params& p : c->h_prm)
+        if (p.box_len[0] > 0.0 || p.box_len[1] > 0.0) c->periodic = true;
     c->n_sys = n_sys;
     c->n = offsets[n_sys];
     c->cells_ok = c->stencils_ok = c->list_ok = false;

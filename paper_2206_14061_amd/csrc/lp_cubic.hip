@@ -27,13 +27,36 @@ inline unsigned int blocks_for_waves(int64_t n)
     return (unsigned int)((n + WAVES - 1) / WAVES);
 }
 
-// sum over the 64 lanes; every lane receives the same value (each
-// butterfly stage adds the same two operands in both partner lanes)
+// one DPP lane permutation of a double (both halves), within rows of 16
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi2, lo2);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same value in every lane.  Within each row
+// of 16 lanes: neighbour and pair swaps inside quads, then the half-row
+// and row mirrors (each stage adds the same two operands in both partner
+// lanes); the four row sums are then read as scalars and added in one
+// fixed order.
 __device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    return x;
+    x += dpp_f64<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+    x += dpp_f64<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+    x += dpp_f64<0x141>(x);   // row_half_mirror
+    x += dpp_f64<0x140>(x);   // row_mirror
+    return (readlane_f64(x, 0) + readlane_f64(x, 16)) +
+           (readlane_f64(x, 32) + readlane_f64(x, 48));
 }
 
 // list index of the k-th set bit (0-based) of the keep mask, -1 if none

@@ -111,6 +111,7 @@ struct View {
     int32_t weight;
     int32_t debug;
     int32_t wall_pressure;      // hydrostatic mirror pressure
+    int32_t periodic;           // some system has a periodic axis
 };
 
 struct Work {
@@ -191,6 +192,7 @@ struct lp_ctx {
     int64_t n = 0;
     std::vector<int64_t> h_off;
     std::vector<lp_params> h_prm;
+    bool periodic = false;                // some system has a periodic axis
     lp::Work w;
     int axis_bits = 0;
     int64_t total_cells = 0;

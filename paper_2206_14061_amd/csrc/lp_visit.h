@@ -17,8 +17,10 @@ struct Pt {
 
 // Along periodic axes a point stands for its copy nearest to the particle
 // at (xi, yi).
-__device__ __forceinline__ void to_image(const GridInfo& g, Pt& p, double xi, double yi)
+__device__ __forceinline__ void to_image(const View& v, const GridInfo& g, Pt& p,
+                                         double xi, double yi)
 {
+    if (!v.periodic) return;
     p.x = image_coord(p.x, xi, g.Lx, g.hLx);
     p.y = image_coord(p.y, yi, g.Ly, g.hLy);
 }
@@ -49,7 +51,7 @@ __device__ __forceinline__ Pt list_point(const View& v, const GridInfo& g,
         p.src = e;
         p.mirror = false;
     }
-    to_image(g, p, xi, yi);
+    to_image(v, g, p, xi, yi);
     return p;
 }
 
@@ -75,7 +77,7 @@ __device__ __forceinline__ Pt id_point(const View& v, const GridInfo& g,
         p.src = j;
         p.mirror = true;
     }
-    to_image(g, p, xi, yi);
+    to_image(v, g, p, xi, yi);
     return p;
 }
 
