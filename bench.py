@@ -77,6 +77,8 @@ def _parse():
 # Sources that make up the pass-1 kernel; its committed byte counts hold only
 # while they are unchanged.
 PASS1_SOURCES = ("paper_2206_14061_amd/csrc/lp_fit.hip",
+                 "paper_2206_14061_amd/csrc/lp_finish.h",
+                 "paper_2206_14061_amd/csrc/lp_fitcore.h",
                  "paper_2206_14061_amd/csrc/lp_visit.h",
                  "paper_2206_14061_amd/csrc/lp_internal.h",
                  "paper_2206_14061_amd/build.py")
@@ -456,16 +458,37 @@ def main():
         nst = max(ph.pop("steps"), 1)
         return 1e3 * elapsed / steps, {k: v / nst for k, v in ph.items()}, ctx.stats()
 
+    def run_graph(steps, warmup, **cfg):
+        """The same steps captured as one HIP graph (lp_step_graph: device-side
+        re-sort decisions, no host synchronisation between steps): one
+        warm-up call captures and runs `steps` steps, the timed call replays
+        them.  Returns ms/step."""
+        ctx = lp.make_context(wl, **cfg)
+        st = lp.DeviceState.from_host(wl.state)
+        ids = torch.arange(wl.n, dtype=torch.int32, device="cuda")
+        for _ in range(max(warmup, 1)):
+            ctx.lp_step_graph(st, wl.dt, steps, ids)
+        ctx.sync_status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.lp_step_graph(st, wl.dt, steps, ids)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        ctx.sync_status()
+        return 1e3 * elapsed / steps
+
     main_prec = lp.LP_FP64 if args.precision == "fp64" else lp.LP_FP32_REFINED
-    ms_per_step, phases, stats = run(args.steps, args.warmup, precision=main_prec)
+    ms_eager, phases, stats = run(args.steps, args.warmup, precision=main_prec)
+    ms_graph = run_graph(args.steps, args.warmup, precision=main_prec)
+    ms_per_step = ms_eager
     value = wl.n / (ms_per_step * 1e-3)
     dominant = max(("select", "pass1", "pass2"), key=lambda k: phases[k])
     # the other precision on the same column
     other = "fp32r" if args.precision == "fp64" else "fp64"
     ms_o, ph_o, st_o = run(args.steps, args.warmup,
                            precision=lp.LP_FP32_REFINED if other == "fp32r" else lp.LP_FP64)
-    ms64 = ms_per_step if args.precision == "fp64" else ms_o
-    ms32 = ms_o if args.precision == "fp64" else ms_per_step
+    ms64 = ms_eager if args.precision == "fp64" else ms_o
+    ms32 = ms_o if args.precision == "fp64" else ms_eager
     compare = {"precision": other, "value": wl.n / (ms_o * 1e-3),
                "ms_per_step": ms_o, "phases_ms": ph_o, "stats": st_o,
                "fp32r_speedup_vs_fp64": ms64 / ms32}
@@ -494,11 +517,12 @@ def main():
                       "precision": args.precision, "m_max": 60,
                       "R_over_h": 2.5, "skin": 0.1, "parallelism": "none"},
            "phases_ms": phases, "stats": stats, "other_precision": compare,
+           "ms_per_step_graph": ms_graph,
            "ms_per_step_rebuild_every_step": ms_rebuild,
            "roofline": roof}
     if not args.no_second_order:
         out["second_order"] = second_order_bench(torch, lp, wl, args.steps, args.warmup,
-                                                 main_prec, ms_per_step)
+                                                 main_prec, ms_eager)
     if not args.no_cubic:
         out["cubic_fits"] = cubic_bench(torch, lp, wl, args.steps, args.warmup)
     if not args.no_adjoint:
