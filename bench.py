@@ -46,6 +46,20 @@ PASS1_FLOP_PER_PARTICLE = 16.2e3
 # 60 x (45 Gram + 27 moment FMAs = 144 flop + 12 row flop) + ~1.4k for the
 # Cholesky factor, 3 solves, 3 rows of G^-1 and the closure.
 PASS1_FLOP_EXECUTED = 60 * 156 + 1.4e3
+# Average neighbour-list length of the benchmark column (reals within
+# R (1 + skin) plus potential mirror sources; mean over 20,000 sampled
+# particles of lpgen.column_bench()).
+LIST_ENTRIES = 77.5
+# Algorithmic HBM bytes per particle of the selection kernel: own position
+# (24) and list count (4), the list (4 per entry), every neighbour position
+# once (24), a bucket code per entry (1 per entry), the stencil record (12)
+# and keep mask (32).
+SELECT_BYTES_PER_PARTICLE = 24 + 4 + 4 * LIST_ENTRIES + 24 + LIST_ENTRIES + 12 + 32
+# ... of the pass-2 kernel on a 60-row stencil: own state (56), P, eta and
+# flags (17), record and mask (44), the kept list entries (4 x 60), the
+# pass-1 hand-off (296), every neighbour's P, eta and position once (40),
+# the new state written (56).
+PASS2_BYTES_PER_PARTICLE = 56 + 17 + 44 + 4 * 60 + 296 + 40 + 56
 
 
 def _parse():
@@ -83,6 +97,13 @@ PASS1_SOURCES = ("paper_2206_14061_amd/csrc/lp_fit.hip",
                  "paper_2206_14061_amd/csrc/lp_internal.h",
                  "paper_2206_14061_amd/build.py")
 PASS1_PROFILE = "profiles/k_pass1_column_64x64x128.md"
+SELECT_SOURCES = ("paper_2206_14061_amd/csrc/lp_stencil.hip",
+                  "paper_2206_14061_amd/csrc/lp_visit.h",
+                  "paper_2206_14061_amd/csrc/lp_internal.h",
+                  "paper_2206_14061_amd/build.py")
+SELECT_PROFILE = "profiles/k_select_column_64x64x128.md"
+PASS2_SOURCES = PASS1_SOURCES
+PASS2_PROFILE = "profiles/k_pass2_column_64x64x128.md"
 
 
 def sources_digest(paths) -> str:
@@ -94,19 +115,19 @@ def sources_digest(paths) -> str:
     return h.hexdigest()
 
 
-def pass1_traffic():
-    """HBM bytes per k_pass1 launch from the committed FETCH_SIZE and
+def kernel_traffic(profile, sources):
+    """HBM bytes per launch of a kernel from its committed FETCH_SIZE and
     WRITE_SIZE counts, each scaled by what the counter reads for a plain
     copy of known size; None when the kernel's sources have changed since
     the counters were taken."""
-    path = os.path.join(ROOT, PASS1_PROFILE)
+    path = os.path.join(ROOT, profile)
     if not os.path.exists(path):
         return None
     m = re.search(r"^traffic-record: (\{.*\})\s*$", open(path).read(), re.M)
     if not m:
         return None
     rec = json.loads(m.group(1))
-    if rec.get("source_sha256") != sources_digest(PASS1_SOURCES):
+    if rec.get("source_sha256") != sources_digest(sources):
         return None
     return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"]
                      + rec["write_kib"] * rec["write_scale"])
@@ -496,17 +517,35 @@ def main():
     # re-sorted) at every step
     k0 = max(2, args.steps // 2)
     ms_rebuild, _, _ = run(k0, args.warmup, precision=main_prec, skin=0.0)
+    fp64 = args.precision == "fp64"
     t_pass1 = phases["pass1"] * 1e-3
     achieved = PASS1_FLOP_PER_PARTICLE * wl.n / t_pass1 / 1e12
     executed = PASS1_FLOP_EXECUTED * wl.n / t_pass1 / 1e12
-    roof = {"kernel": ("k_pass1" if args.precision == "fp64" else "k_pass1_ref")
-                      + " (fit of u, v, w + mu(I) closure)",
-            "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": pass1_traffic(), "avg_launch_ms": phases["pass1"],
-            "executed_tflops": executed,
-            "executed_frac": executed / PEAK_FP64_TFLOPS,
-            "dominant_phase": dominant}
+    roofs = {
+        "pass1": {"kernel": ("k_pass1" if fp64 else "k_pass1_ref")
+                            + " (fit of u, v, w + mu(I) closure)",
+                  "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                  "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                  "traffic": kernel_traffic(PASS1_PROFILE, PASS1_SOURCES) if fp64 else None,
+                  "avg_launch_ms": phases["pass1"],
+                  "per_particle": PASS1_FLOP_PER_PARTICLE,
+                  "executed_tflops": executed,
+                  "executed_frac": executed / PEAK_FP64_TFLOPS},
+    }
+    for ph, name, per, prof, src in (
+            ("select", "k_select (exact candidate test, octant firsts, ghosts, keep mask)",
+             SELECT_BYTES_PER_PARTICLE, SELECT_PROFILE, SELECT_SOURCES),
+            ("pass2", ("k_pass2" if fp64 else "k_pass2_ref")
+             + " (fit of P, eta; right-hand side; update)",
+             PASS2_BYTES_PER_PARTICLE, PASS2_PROFILE, PASS2_SOURCES)):
+        gbs = per * wl.n / (phases[ph] * 1e-3) / 1e9
+        roofs[ph] = {"kernel": name, "bound": "hbm", "achieved": gbs,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                     "traffic": kernel_traffic(prof, src) if (fp64 or ph == "select")
+                     else None,
+                     "avg_launch_ms": phases[ph], "per_particle": per}
+    roof = dict(roofs[dominant])
+    roof["dominant_phase"] = dominant
     out = {"metric": METRIC, "value": value, "unit": "particle-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True,
@@ -519,7 +558,7 @@ def main():
            "phases_ms": phases, "stats": stats, "other_precision": compare,
            "ms_per_step_graph": ms_graph,
            "ms_per_step_rebuild_every_step": ms_rebuild,
-           "roofline": roof}
+           "roofline": roof, "roofline_by_kernel": roofs}
     if not args.no_second_order:
         out["second_order"] = second_order_bench(torch, lp, wl, args.steps, args.warmup,
                                                  main_prec, ms_eager)
