@@ -4,15 +4,19 @@
 // their exponents (each coefficient is the matching third derivative times
 // h^3); the step uses the first and second derivatives as before.
 //
-// One wavefront per particle: lane t holds fit row t (the stencil rows in
-// the order of the stencil walk, then the ghost rows), so a stencil of up
-// to 64 rows is one register column per unknown.  Householder QR runs
-// across the lanes (each reflector: one wave-wide sum per remaining
-// column and right-hand side), the back substitution broadcasts one
-// coefficient per step.  Stencils with fewer than 19 rows, or whose
-// min |r_jj| / max |r_jj| is below the fallback tolerance, are refitted
-// with the 9 quadratic columns (FLAG_QUAD), then with the 3 linear ones
-// (FLAG_LINEAR), as the quadratic fit does.
+// Sixteen lanes per particle (one DPP row; four particles per wavefront):
+// lane s of a particle's group holds fit rows s, s + 16, s + 32 and s + 48
+// (the stencil rows in the order of the stencil walk, then the ghost
+// rows), so a stencil of up to 64 rows is four register columns per
+// unknown.  Householder QR runs across the group: each reflector sums over
+// the lane's four rows, then over the sixteen lanes with DPP steps inside
+// the row; the pivot and, in the back substitution, each coefficient are
+// broadcast from the lane that holds their row.  Stencils with fewer than
+// 19 rows, or whose min |r_jj| / max |r_jj| is below the fallback
+// tolerance, are refitted with the 9 quadratic columns (FLAG_QUAD), then
+// with the 3 linear ones (FLAG_LINEAR), as the quadratic fit does.
+#include <type_traits>
+
 #include "lp_finish.h"
 
 namespace lp {
@@ -20,11 +24,13 @@ namespace lp {
 namespace {
 
 constexpr int NC3 = 19;
-constexpr int WAVES = BLOCK / 64;
+constexpr int GROUP = 16;             // lanes per particle
+constexpr int SLOTS = 4;              // rows per lane: up to 64 rows
+constexpr int PPB = BLOCK / GROUP;    // particles per block
 
-inline unsigned int blocks_for_waves(int64_t n)
+inline unsigned int blocks_for_groups(int64_t n)
 {
-    return (unsigned int)((n + WAVES - 1) / WAVES);
+    return (unsigned int)((n + PPB - 1) / PPB);
 }
 
 // one DPP lane permutation of a double (both halves), within rows of 16
@@ -37,26 +43,33 @@ __device__ __forceinline__ double dpp_f64(double x)
     return __hiloint2double(hi2, lo2);
 }
 
-__device__ __forceinline__ double readlane_f64(double x, int lane)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the 64 lanes, the same value in every lane.  Within each row
-// of 16 lanes: neighbour and pair swaps inside quads, then the half-row
-// and row mirrors (each stage adds the same two operands in both partner
-// lanes); the four row sums are then read as scalars and added in one
-// fixed order.
-__device__ __forceinline__ double wave_sum(double x)
+// Sum over the 16 lanes of a group, the same value in every lane: swaps
+// of neighbours and pairs inside quads, then the half-row and row mirrors
+// (each stage adds the same two operands in both partner lanes).
+__device__ __forceinline__ double group_sum(double x)
 {
     x += dpp_f64<0xB1>(x);    // quad_perm [1, 0, 3, 2]
     x += dpp_f64<0x4E>(x);    // quad_perm [2, 3, 0, 1]
     x += dpp_f64<0x141>(x);   // row_half_mirror
     x += dpp_f64<0x140>(x);   // row_mirror
-    return (readlane_f64(x, 0) + readlane_f64(x, 16)) +
-           (readlane_f64(x, 32) + readlane_f64(x, 48));
+    return x;
+}
+
+// f(integral_constant<int, K>) for K = B .. E-1, in order
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// lane SRC's value in every lane of the group (row broadcast)
+template <int SRC>
+__device__ __forceinline__ double group_bcast(double x)
+{
+    return dpp_f64<0x150 + SRC>(x);
 }
 
 // list index of the k-th set bit (0-based) of the keep mask, -1 if none
@@ -99,22 +112,22 @@ __device__ __forceinline__ void taylor_row3(double ex, double ey, double ez,
     a[18] = ex * ey * ez;
 }
 
-// Row `lane` of particle i's fit: the weighted Taylor row and the point
-// (nullptr for a ghost row; rows beyond the last are zero).  Returns the
+// Fit row `row` of particle i: the weighted Taylor row and its point
+// (ghost rows: ghost = true; rows beyond the last are zero).  Returns the
 // square root of the weight (0 for an empty row).
-__device__ __forceinline__ double lane_row(const View& v, const GridInfo& g, int64_t i,
-                                           const Rec& r, int lane, double (&a)[NC3],
-                                           Pt& pt, bool& ghost)
+__device__ __forceinline__ double fit_row(const View& v, const GridInfo& g, int64_t i,
+                                          const Rec& r, int row, double (&a)[NC3], Pt& pt,
+                                          bool& ghost)
 {
     const int64_t n = v.n;
     const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
     ghost = false;
     const int ng = __popc((unsigned)r.gm & 0xFFu);
-    if (lane < r.m) {
+    if (row < r.m) {
         if (r.mode & MODE_SORTED) {
-            pt = id_point(v, g, v.hsten[(int64_t)lane * n + i], xi, yi);
+            pt = id_point(v, g, v.hsten[(int64_t)row * n + i], xi, yi);
         } else {
-            const int k = mask_select(r, lane);
+            const int k = mask_select(r, row);
             pt = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
         }
         const double dx = dsub(pt.x, xi), dy = dsub(pt.y, yi), dz = dsub(pt.z, zi);
@@ -125,10 +138,10 @@ __device__ __forceinline__ double lane_row(const View& v, const GridInfo& g, int
         for (int q = 0; q < NC3; ++q) a[q] *= sw;
         return sw;
     }
-    if (lane < r.m + ng) {
+    if (row < r.m + ng) {
         // ghost rows in ascending octant order
         unsigned gm = (unsigned)r.gm & 0xFFu;
-        for (int s = 0; s < lane - r.m; ++s) gm &= gm - 1;
+        for (int s = 0; s < row - r.m; ++s) gm &= gm - 1;
         const int o = __builtin_ctz(gm);
         double sx, sy, sz;
         ghost_offset(o, sx, sy, sz);
@@ -145,114 +158,140 @@ __device__ __forceinline__ double lane_row(const View& v, const GridInfo& g, int
     return 0.0;
 }
 
-// Householder QR of the first NC columns of the lane-distributed rows
-// (rows 0..m-1 in lanes 0..m-1) applied to NF right-hand sides; R and
-// Q^T b stay in place (row j of R in lane j).  rd: diagonal of R (the
-// same in every lane).  Returns min |r_jj| / max |r_jj| (0 when a column
-// vanishes).
+// Householder QR of the first NC columns of the group's rows (row
+// 16 q + s in slot q of lane s) applied to NF right-hand sides; R and
+// Q^T b stay in place, r_jj in rdiag of the lane holding row j.  Returns
+// min |r_jj| / max |r_jj| (0 when a column vanishes), the same in every
+// lane of the group.
 template <int NC, int NF>
-__device__ __forceinline__ double wave_house(int lane, int m, double (&a)[NC3],
-                                             double (&b)[NF], double (&rd)[NC3])
+__device__ __forceinline__ double group_house(int sl, int m, double (&a)[SLOTS][NC3],
+                                              double (&b)[SLOTS][NF],
+                                              double (&rdiag)[SLOTS])
 {
     double rmin = INFINITY, rmax = 0.0;
+    static_for<0, NC>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        bool act[SLOTS];
+        double part = 0.0;
 #pragma unroll
-    for (int j = 0; j < NC; ++j) {
-        const bool act = lane >= j && lane < m;
-        const double s = wave_sum(act ? a[j] * a[j] : 0.0);
-        const double nrm = sqrt(s);
-        const double ajj = __shfl(a[j], j);
+        for (int q = 0; q < SLOTS; ++q) {
+            const int row = GROUP * q + sl;
+            act[q] = row >= j && row < m;
+            part += act[q] ? a[q][j] * a[q][j] : 0.0;
+        }
+        const double nrm = sqrt(group_sum(part));
+        const double ajj = group_bcast<j % GROUP>(a[j / GROUP][j]);
         if (nrm == 0.0) {
-            rd[j] = 0.0;
+            if (sl == j % GROUP) rdiag[j / GROUP] = 0.0;
             rmin = 0.0;
-            continue;
+            return;
         }
         const double alpha = ajj >= 0.0 ? -nrm : nrm;
-        if (lane == j) a[j] = ajj - alpha;
+        if (sl == j % GROUP) a[j / GROUP][j] = ajj - alpha;
         const double vtv = 2.0 * nrm * (nrm + fabs(ajj));
-        const double vj = act ? a[j] : 0.0;
+        double vj[SLOTS];
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) vj[q] = act[q] ? a[q][j] : 0.0;
 #pragma unroll
         for (int l = j + 1; l < NC; ++l) {
-            const double f = 2.0 * wave_sum(vj * a[l]) / vtv;
-            if (act) a[l] -= f * vj;
+            double d = 0.0;
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) d += vj[q] * a[q][l];
+            const double f = 2.0 * group_sum(d) / vtv;
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q)
+                if (act[q]) a[q][l] -= f * vj[q];
         }
 #pragma unroll
         for (int l = 0; l < NF; ++l) {
-            const double f = 2.0 * wave_sum(vj * b[l]) / vtv;
-            if (act) b[l] -= f * vj;
+            double d = 0.0;
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q) d += vj[q] * b[q][l];
+            const double f = 2.0 * group_sum(d) / vtv;
+#pragma unroll
+            for (int q = 0; q < SLOTS; ++q)
+                if (act[q]) b[q][l] -= f * vj[q];
         }
-        rd[j] = alpha;
+        if (sl == j % GROUP) rdiag[j / GROUP] = alpha;
         const double ar = fabs(alpha);
         rmin = fmin(rmin, ar);
         rmax = fmax(rmax, ar);
-    }
+    });
     return rmax > 0.0 ? rmin / rmax : 0.0;
 }
 
-// R x = Q^T b for right-hand side `f` after wave_house; x (per unit h) is
-// the same in every lane.
+// R x = Q^T b for right-hand side `f` after group_house; x (per unit h) is
+// the same in every lane of the group.
 template <int NC, int NF>
-__device__ __forceinline__ void wave_backsolve(int lane, const double (&a)[NC3],
-                                               const double (&b)[NF], int f,
-                                               const double (&rd)[NC3], double (&x)[NC3])
+__device__ __forceinline__ void group_backsolve(const double (&a)[SLOTS][NC3],
+                                                const double (&b)[SLOTS][NF], int f,
+                                                const double (&rdiag)[SLOTS],
+                                                double (&x)[NC3])
 {
 #pragma unroll
     for (int q = 0; q < NC3; ++q) x[q] = 0.0;
+    static_for<0, NC>([&](auto K) {
+        constexpr int c = NC - 1 - decltype(K)::value;
+        // computed in every lane; the lane holding row c has the right one
+        double acc = b[c / GROUP][f];
 #pragma unroll
-    for (int c = NC - 1; c >= 0; --c) {
-        double acc = b[f];
-#pragma unroll
-        for (int q = c + 1; q < NC; ++q) acc -= a[q] * x[q];
-        const double xc = __shfl(acc, c);
-        x[c] = rd[c] != 0.0 ? xc / rd[c] : 0.0;
-    }
+        for (int q = c + 1; q < NC; ++q) acc -= a[c / GROUP][q] * x[q];
+        const double rc = rdiag[c / GROUP];
+        x[c] = group_bcast<c % GROUP>(rc != 0.0 ? acc / rc : 0.0);
+    });
 }
 
 // The fit of NF fields at particle i with the 19 -> 9 -> 3 column
-// fallback.  vals(pt, ghost, out): the NF field values of the row's point
-// minus the particle's own (ghost rows: the ghost values minus the own).
-// coef[f][q]: derivative q (first 9) of field f, scaled by 1/h, 1/h^2.
+// fallback.  vals(pt or nullptr for a ghost, out): the NF field values of
+// the row's point minus the particle's own.  coef[f][q]: derivative q
+// (first 9) of field f, scaled by 1/h, 1/h^2.
 template <int NF, class Vals>
-__device__ __forceinline__ uint8_t wave_fit3(const View& v, const GridInfo& g,
-                                             int64_t i, const Rec& r, int lane,
-                                             Vals&& vals, double (&coef)[NF][9])
+__device__ __forceinline__ uint8_t group_fit3(const View& v, const GridInfo& g,
+                                              int64_t i, const Rec& r, int sl,
+                                              Vals&& vals, double (&coef)[NF][9])
 {
     const int m = r.m + __popc((unsigned)r.gm & 0xFFu);
-    double a[NC3], b[NF], rd[NC3], x[NC3];
+    double a[SLOTS][NC3], b[SLOTS][NF], rdiag[SLOTS], x[NC3];
     auto load = [&]() {
-        Pt pt;
-        bool ghost;
-        const double sw = lane_row(v, g, i, r, lane, a, pt, ghost);
-        double d[NF];
-        if (lane < m) vals(ghost ? nullptr : &pt, d);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) b[f] = lane < m ? sw * d[f] : 0.0;
+        for (int q = 0; q < SLOTS; ++q) {
+            const int row = GROUP * q + sl;
+            Pt pt;
+            bool ghost;
+            const double sw = fit_row(v, g, i, r, row, a[q], pt, ghost);
+            double d[NF];
+            if (row < m) vals(ghost ? nullptr : &pt, d);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) b[q][f] = row < m ? sw * d[f] : 0.0;
+            rdiag[q] = 0.0;
+        }
     };
     uint8_t fl = 0;
     int nc = 0;
     if (m >= NC3) {
         load();
-        if (wave_house<NC3, NF>(lane, m, a, b, rd) >= v.fallback_tol) nc = NC3;
+        if (group_house<NC3, NF>(sl, m, a, b, rdiag) >= v.fallback_tol) nc = NC3;
     }
     if (nc == 0) {
         fl |= FLAG_QUAD;
         if (m >= 9) {
             load();
-            if (wave_house<9, NF>(lane, m, a, b, rd) >= v.fallback_tol) nc = 9;
+            if (group_house<9, NF>(sl, m, a, b, rdiag) >= v.fallback_tol) nc = 9;
         }
     }
     if (nc == 0) {
         fl |= FLAG_LINEAR;
         if (m >= 3) {
             load();
-            wave_house<3, NF>(lane, m, a, b, rd);
+            group_house<3, NF>(sl, m, a, b, rdiag);
             nc = 3;
         }
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        if (nc == NC3) wave_backsolve<NC3, NF>(lane, a, b, f, rd, x);
-        else if (nc == 9) wave_backsolve<9, NF>(lane, a, b, f, rd, x);
-        else if (nc == 3) wave_backsolve<3, NF>(lane, a, b, f, rd, x);
+        if (nc == NC3) group_backsolve<NC3, NF>(a, b, f, rdiag, x);
+        else if (nc == 9) group_backsolve<9, NF>(a, b, f, rdiag, x);
+        else if (nc == 3) group_backsolve<3, NF>(a, b, f, rdiag, x);
         else
 #pragma unroll
             for (int q = 0; q < NC3; ++q) x[q] = 0.0;
@@ -262,14 +301,20 @@ __device__ __forceinline__ uint8_t wave_fit3(const View& v, const GridInfo& g,
     return fl;
 }
 
+__device__ __forceinline__ int64_t group_particle(int& sl)
+{
+    sl = threadIdx.x % GROUP;
+    return xcd_block(blockIdx.x, gridDim.x) * PPB + threadIdx.x / GROUP;
+}
+
 // ---- lp_fit_derivs -------------------------------------------------------
 
 template <int NF>
 __global__ __launch_bounds__(BLOCK) void k_fit3_generic(View v, GenericFields F,
                                                         double* coef, uint8_t* flags)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * WAVES + threadIdx.x / 64;
-    const int lane = threadIdx.x & 63;
+    int sl;
+    const int64_t i = group_particle(sl);
     if (i >= v.n) return;
     const int64_t n = v.n;
     const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
@@ -288,8 +333,8 @@ __global__ __launch_bounds__(BLOCK) void k_fit3_generic(View v, GenericFields F,
         }
     };
     double c[NF][9];
-    const uint8_t fl = wave_fit3<NF>(v, g, i, r, lane, vals, c);
-    if (lane != 0) return;
+    const uint8_t fl = group_fit3<NF>(v, g, i, r, sl, vals, c);
+    if (sl != 0) return;
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -301,8 +346,8 @@ __global__ __launch_bounds__(BLOCK) void k_fit3_generic(View v, GenericFields F,
 
 __global__ __launch_bounds__(BLOCK) void k_pass1_cubic(View v, StepOut o)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * WAVES + threadIdx.x / 64;
-    const int lane = threadIdx.x & 63;
+    int sl;
+    const int64_t i = group_particle(sl);
     if (i >= v.n) return;
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
@@ -320,8 +365,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass1_cubic(View v, StepOut o)
         d[2] = wj - wi;
     };
     double c3[3][9];
-    const uint8_t fl = wave_fit3<3>(v, g, i, r, lane, vals, c3);
-    if (lane != 0) return;
+    const uint8_t fl = group_fit3<3>(v, g, i, r, sl, vals, c3);
+    if (sl != 0) return;
     double c[27], ginv3[27];
 #pragma unroll
     for (int f = 0; f < 3; ++f)
@@ -338,8 +383,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_cubic(View v, const double* P,
                                                        const double* eta,
                                                        const double* hand, RhsOut o)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * WAVES + threadIdx.x / 64;
-    const int lane = threadIdx.x & 63;
+    int sl;
+    const int64_t i = group_particle(sl);
     if (i >= v.n) return;
     const int64_t n = v.n;
     const int s = sys_of(v.off, v.n_sys, i);
@@ -354,8 +399,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_cubic(View v, const double* P,
         d[1] = Ej - Ei;
     };
     double c2[2][9];
-    const uint8_t fl = wave_fit3<2>(v, g, i, r, lane, vals, c2);
-    if (lane != 0) return;
+    const uint8_t fl = group_fit3<2>(v, g, i, r, sl, vals, c2);
+    if (sl != 0) return;
     // the fit's fallback bits next to the regime of the closure
     o.flags[i] = (uint8_t)((o.flags[i] & 6) | fl);
     const double gP[3] = {c2[0][0], c2[0][1], c2[0][2]};
@@ -370,7 +415,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_cubic(View v, const double* P,
 void launch_fit3_generic(lp_ctx* c, const View& v, const GenericFields& F, double* coef,
                          uint8_t* flags)
 {
-    const dim3 gb(blocks_for_waves(c->n)), bb(BLOCK);
+    const dim3 gb(blocks_for_groups(c->n)), bb(BLOCK);
 #define LP_FIT3_CASE(K)                                                              \
     case K:                                                                          \
         hipLaunchKernelGGL(k_fit3_generic<K>, gb, bb, 0, c->stream, v, F, coef, flags); \
@@ -385,14 +430,14 @@ void launch_fit3_generic(lp_ctx* c, const View& v, const GenericFields& F, doubl
 
 void launch_pass1_cubic(lp_ctx* c, const View& v, const StepOut& o)
 {
-    hipLaunchKernelGGL(k_pass1_cubic, dim3(blocks_for_waves(c->n)), dim3(BLOCK), 0,
+    hipLaunchKernelGGL(k_pass1_cubic, dim3(blocks_for_groups(c->n)), dim3(BLOCK), 0,
                        c->stream, v, o);
 }
 
 void launch_pass2_cubic(lp_ctx* c, const View& v, const double* P, const double* eta,
                         const double* hand, const RhsOut& o)
 {
-    hipLaunchKernelGGL(k_pass2_cubic, dim3(blocks_for_waves(c->n)), dim3(BLOCK), 0,
+    hipLaunchKernelGGL(k_pass2_cubic, dim3(blocks_for_groups(c->n)), dim3(BLOCK), 0,
                        c->stream, v, P, eta, hand, o);
 }
 
