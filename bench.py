@@ -546,6 +546,23 @@ def main():
                      "avg_launch_ms": phases[ph], "per_particle": per}
     roof = dict(roofs[dominant])
     roof["dominant_phase"] = dominant
+    # neighbour gathers of the two fits (48 B per row in pass 1: position
+    # and velocity; 40 B in pass 2: position, P and eta), over the mean
+    # kept rows of the column's stencils (ghost rows gather nothing); and
+    # the least-squares work of both fits at the survey's Householder count
+    ctx_n = lp.make_context(wl)
+    st_n = lp.DeviceState.from_host(wl.state)
+    ctx_n.lp_build_cells(st_n, want_perm=False)
+    nb = ctx_n.lp_neighbors(st_n, candidates=False, ghosts=False)
+    rows = float(nb["sten_cnt"].to(torch.float64).mean().item())
+    del ctx_n, st_n, nb
+    t_fit = (phases["pass1"] + phases["pass2"]) * 1e-3
+    ncol = 9
+    qr_flop = sum(2 * rows * ncol * ncol - 2.0 * ncol ** 3 / 3 + k * (4 * rows * ncol - ncol * ncol)
+                  for k in (3, 2))
+    fit_rates = {"mean_stencil_rows": rows,
+                 "gathers_gbs": wl.n * rows * (48 + 40) / t_fit / 1e9,
+                 "qr_tflops": wl.n * qr_flop / t_fit / 1e12}
     out = {"metric": METRIC, "value": value, "unit": "particle-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True,
@@ -558,7 +575,7 @@ def main():
            "phases_ms": phases, "stats": stats, "other_precision": compare,
            "ms_per_step_graph": ms_graph,
            "ms_per_step_rebuild_every_step": ms_rebuild,
-           "roofline": roof, "roofline_by_kernel": roofs}
+           "roofline": roof, "roofline_by_kernel": roofs, "fit_rates": fit_rates}
     if not args.no_second_order:
         out["second_order"] = second_order_bench(torch, lp, wl, args.steps, args.warmup,
                                                  main_prec, ms_eager)
