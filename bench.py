@@ -69,7 +69,7 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--adjoint-steps", type=int, default=50)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-sheared", action="store_true")
@@ -423,15 +423,20 @@ def copy_calibration(torch):
     return 8 * n
 
 
-def cpu_baseline(wl, steps: int):
+def cpu_baseline(wl, seconds: float):
     """The FP64 oracle as it stands on the host cores: full steps of the
-    same column (cell-list neighbours, OpenMP over particles)."""
+    same column (cell-list neighbours, OpenMP over particles), repeated
+    until at least `seconds` of wall time have passed."""
     import oracle
     st = wl.state
+    steps = 0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    while True:
         st, _, _ = oracle.step(st, wl.offsets, wl.params, wl.dt, brute=False)
-    dt = time.perf_counter() - t0
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
     return {"value": wl.n * steps / dt, "unit": "particle-updates/s",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "%d full oracle step(s) of the %d-particle column "
@@ -596,7 +601,7 @@ def main():
         out["ensemble"] = ensemble_bench(torch, lp, lpgen, args.ensemble_steps,
                                          args.ensemble_adjoint_steps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     if args.copy_calibration:
         out["copy_calibration_bytes"] = copy_calibration(torch)
     print(json.dumps(out), flush=True)
