@@ -247,7 +247,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.mirror_of, n_max); A(w.msrc, n_max); A(w.bsum, nb + 1);
     A(w.cs, cells_max); A(w.ce, cells_max);
     A(w.vl, (int64_t)VCAP * n_max); A(w.vcnt, n_max);
-    A(w.code, (int64_t)VCAP * n_max);
+    A(w.code, (int64_t)(VCAP / 4) * n_max);
     A(w.kmask, (int64_t)MASK_WORDS * n_max);
     A(w.rec, (int64_t)REC_FIELDS * n_max); A(w.hsten, (int64_t)mm * n_max);
     A(w.hard, n_max); A(w.hard_n, 1);

@@ -371,6 +371,13 @@ __global__ __launch_bounds__(BLOCK) void k_closure_coef(View v, const double* co
 
 // ---- pass 2: fit of P and eta, right-hand side, update --------------------
 
+#ifndef LP_PASS2_BATCH
+#define LP_PASS2_BATCH 8
+#endif
+// Stencil rows the pass-2 fit loads together: its accumulators are few,
+// so a deeper batch than pass 1's still fits in registers.
+constexpr int PASS2_BATCH = LP_PASS2_BATCH;
+
 template <int LPP>
 __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
                                                  const double* eta,
@@ -391,7 +398,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
     double yP[9], yE[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) yP[q] = yE[q] = 0.0;
-    for_rows_sub<LPP>(v, g, i, r, sub, [&](const double* a, double w, const Pt* p) {
+    for_rows_sub<LPP, PASS2_BATCH>(v, g, i, r, sub, [&](const double* a, double w,
+                                                         const Pt* p) {
         double Pj, Ej;
         pass2_values(v, P, eta, p, prm, Pj, Ej);
         const double bP = w * (Pj - Pi), bE = w * (Ej - Ei);

@@ -233,12 +233,12 @@ __device__ __forceinline__ void ginv_rows(const double (&U)[45], double out[27])
 // Calls f(a, w, p) for every fit row of real particle i: the stencil rows
 // (p = the stencil point) then the ghost rows in octant order (p = null).
 // Returns the number of rows.
-template <class F>
+template <int B = FIT_BATCH, class F>
 __device__ __forceinline__ int for_rows(const View& v, const GridInfo& g,
                                         int64_t i, const Rec& r, F&& f)
 {
     int m = 0;
-    visit_stencil(v, g, i, r, [&](const Pt& p, double dx, double dy, double dz) {
+    visit_stencil<B>(v, g, i, r, [&](const Pt& p, double dx, double dy, double dz) {
         double a[9];
         const double w = point_row(v, g, dx, dy, dz, a);
         f(a, w, &p);
@@ -256,12 +256,13 @@ __device__ __forceinline__ int for_rows(const View& v, const GridInfo& g,
 }
 
 // for_rows with the rows spread over LPP lanes (stencil rows as in
-// visit_stencil_sub, ghost o to lane o mod LPP); returns this lane's rows.
-template <int LPP, class F>
+// visit_stencil_sub, ghost o to lane o mod LPP; B: rows loaded together
+// with one lane per particle); returns this lane's rows.
+template <int LPP, int B = FIT_BATCH, class F>
 __device__ __forceinline__ int for_rows_sub(const View& v, const GridInfo& g, int64_t i,
                                             const Rec& r, int sub, F&& f)
 {
-    if (LPP == 1) return for_rows(v, g, i, r, f);
+    if (LPP == 1) return for_rows<B>(v, g, i, r, f);
     int m = 0;
     visit_stencil_sub<LPP>(v, g, i, r, sub, [&](const Pt& p, double dx, double dy,
                                                 double dz) {

@@ -100,7 +100,9 @@ struct View {
     // neighbour list with skin (ELL, entry k of particle i at k*n + i)
     const int32_t* vl;
     const int32_t* vcnt;
-    uint8_t* code;              // r^2 bucket of every list entry (NO_CAND: none)
+    uint32_t* code;             // r^2 buckets of the list entries, four per word
+                                // (entry k: byte k % 4 of word (k / 4) n + i;
+                                // NO_CAND: outside R)
     // stencil records, keep bitmasks and explicit stencils of the sorted path
     int32_t* rec;
     uint64_t* kmask;            // MASK_WORDS x n
@@ -143,7 +145,7 @@ struct Work {
     // neighbour list, records, sorted-path stencils
     int32_t* vl = nullptr;
     int32_t* vcnt = nullptr;
-    uint8_t* code = nullptr;              // VCAP x n
+    uint32_t* code = nullptr;             // VCAP / 4 x n
     int32_t* rec = nullptr;
     uint64_t* kmask = nullptr;            // MASK_WORDS x n
     int32_t* hsten = nullptr;

@@ -30,9 +30,18 @@
 // more than 255 candidates, take a slower path that sorts all candidates.
 #include "lp_visit.h"
 
+#ifndef LP_SEL_BATCH
+#define LP_SEL_BATCH 8
+#endif
+
 namespace lp {
 
 namespace {
+
+// List entries whose positions the selection gathers together.
+constexpr int SEL_BATCH = LP_SEL_BATCH;
+static_assert(SEL_BATCH % 4 == 0 && VCAP % SEL_BATCH == 0,
+              "selection batches cover whole bucket-code words");
 
 inline unsigned int blocks_for(int64_t n, int per = BLOCK)
 {
@@ -332,28 +341,40 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     const double margin = dmul(v.ghost_margin, g.h);
     const double scale = (double)HIST_BUCKETS / g.R2;
     const double R2 = g.R2;
-    uint8_t* __restrict__ code = v.code;
-    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    uint32_t* __restrict__ code = v.code;
+    const Seen s = seen_from(v, g, i);
+    const double xi = s.xi, yi = s.yi, zi = s.zi;
     const int cnt = v.vcnt[i];
 #pragma unroll
     for (int q = 0; q < HIST_BUCKETS / 4; ++q) hist[q][t] = 0u;
 
-    // ---- pass 1: exact test of every list entry; its bucket is stored
-    // (entry k of all lanes at once: coalesced).  Per octant only the
-    // lowest bucket is tracked (a byte each in mb_lo / mb_hi): it holds
-    // the octant's first.
+    // ---- pass 1: exact test of every list entry, SEL_BATCH entries at a
+    // time (their list words, then their positions, all in flight
+    // together); the buckets are stored four to a word (word k / 4 of all
+    // lanes at once: coalesced).  Per octant only the lowest bucket is
+    // tracked (a byte each in mb_lo / mb_hi): it holds the octant's first.
     int nc = 0, covered = 0;
     Mask4 cm;                          // candidate entries
     uint32_t mb_lo = 0xFFFFFFFFu, mb_hi = 0xFFFFFFFFu;
-    for (int k = 0; k < cnt; ++k) {
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
-        uint8_t kc = NO_CAND;
-        if (p.valid) {
+    for (int k0 = 0; k0 < cnt; k0 += SEL_BATCH) {
+        int32_t e[SEL_BATCH];
+#pragma unroll
+        for (int u = 0; u < SEL_BATCH; ++u)
+            e[u] = k0 + u < cnt ? v.vl[(int64_t)(k0 + u) * n + i] : (int32_t)i;
+        Pt pb[SEL_BATCH];
+        gather_list(v, s, e, pb);
+        uint32_t cw[SEL_BATCH / 4];
+#pragma unroll
+        for (int w = 0; w < SEL_BATCH / 4; ++w) cw[w] = 0xFFFFFFFFu;
+#pragma unroll
+        for (int u = 0; u < SEL_BATCH; ++u) {
+            const Pt& p = pb[u];
+            if (k0 + u >= cnt || !p.valid) continue;
             const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
             const double d2 = dist2(dx, dy, dz);
             if (d2 < R2) {
                 ++nc;
-                cm.set(k);
+                cm.set(k0 + u);
                 covered |= cover_bit(dx, dy, dz, margin);
                 const int oct = octant_of(dx, dy, dz);
                 const uint32_t b = (uint32_t)bucket_of(d2, scale);
@@ -365,10 +386,13 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
                 mb_hi = hiw ? nw : mb_hi;
                 mb_lo = hiw ? mb_lo : nw;
                 hist_add(hist, (int)b, t, 1);
-                kc = (uint8_t)b;
+                const uint32_t cs = 8u * (uint32_t)(u & 3);
+                cw[u >> 2] = (cw[u >> 2] & ~(0xFFu << cs)) | (b << cs);
             }
         }
-        code[(int64_t)k * n + i] = kc;
+#pragma unroll
+        for (int w = 0; w < SEL_BATCH / 4; ++w)
+            if (k0 + 4 * w < cnt) code[(int64_t)((k0 >> 2) + w) * n + i] = cw[w];
     }
     const int gm = ~covered & 0xFF;
     const int m_max = v.m_max;
@@ -415,23 +439,47 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     // members collected for exact ranking
     Mask4 mk;
     int nl = 0;
-    for (int k = 0; k < cnt; ++k) {
-        const int kc = code[(int64_t)k * n + i];
-        if (kc < bstar || (kc == bstar && !partial)) {
-            mk.set(k);
-        } else if (kc == bstar) {
-            const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
+    for (int k0 = 0; k0 < cnt; k0 += 16) {
+        uint32_t cw[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            cw[w] = k0 + 4 * w < cnt ? code[(int64_t)((k0 >> 2) + w) * n + i] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int kc = (int)((cw[u >> 2] >> (8 * (u & 3))) & 0xFFu);
+            if (kc < bstar || (kc == bstar && !partial)) {
+                mk.set(k0 + u);
+            } else if (kc == bstar) {
+                lkey[nl][t] = (uint32_t)(k0 + u);
+                ++nl;
+            }
+        }
+    }
+    // keys of the members: r^2 rounded to float with its low 8 bits
+    // replaced by the list index, and their octants
+    for (int a0 = 0; a0 < nl; a0 += 4) {
+        int32_t e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            e[u] = a0 + u < nl ? v.vl[(int64_t)lkey[a0 + u][t] * n + i] : (int32_t)i;
+        Pt pb[4];
+        gather_list(v, s, e, pb);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (a0 + u >= nl) continue;
+            const Pt& p = pb[u];
             const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
             const float f = (float)dist2(dx, dy, dz);
-            lkey[nl][t] = (__float_as_uint(f) & ~0xFFu) | (uint32_t)k;
-            loct[nl][t] = (uint8_t)octant_of(dx, dy, dz);
-            ++nl;
+            lkey[a0 + u][t] = (__float_as_uint(f) & ~0xFFu) | lkey[a0 + u][t];
+            loct[a0 + u][t] = (uint8_t)octant_of(dx, dy, dz);
         }
     }
     auto exact_key = [&](int k, double& r2, int32_t& id) {
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
-        r2 = dist2(dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
-        id = p.id;
+        const int32_t e[1] = {v.vl[(int64_t)k * n + i]};
+        Pt p[1];
+        gather_list(v, s, e, p);
+        r2 = dist2(dsub(p[0].x, xi), dsub(p[0].y, yi), dsub(p[0].z, zi));
+        id = p[0].id;
     };
     // is member b's key (r^2, id) below member a's?
     auto below = [&](int b, int a) {
@@ -477,7 +525,8 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
             int32_t bi = NOID;
             int bk = -1;
             for (int k = 0; k < cnt; ++k) {
-                if (code[(int64_t)k * n + i] != mo) continue;
+                if ((int)((code[(int64_t)(k >> 2) * n + i] >> (8 * (k & 3))) & 0xFFu) != mo)
+                    continue;
                 const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
                 const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
                 if (octant_of(dx, dy, dz) != o) continue;

@@ -55,6 +55,71 @@ __device__ __forceinline__ Pt list_point(const View& v, const GridInfo& g,
     return p;
 }
 
+#ifndef LP_FIT_BATCH
+#define LP_FIT_BATCH 4
+#endif
+// Stencil rows whose loads the fits issue together (by default).
+constexpr int FIT_BATCH = LP_FIT_BATCH;
+
+// Registers of one particle's list walk: its position and the fields of
+// its system's grid that a list entry needs, copied once so that stores
+// made during the walk cannot force the grid table to be read again.
+struct Seen {
+    double xi, yi, zi;
+    double wall2;               // twice the wall height (mirror plane)
+    double Lx, hLx, Ly, hLy;    // periodic box, 0 on open axes
+};
+
+__device__ __forceinline__ Seen seen_from(const View& v, const GridInfo& g, int64_t i)
+{
+    Seen s;
+    s.xi = v.x[i];
+    s.yi = v.y[i];
+    s.zi = v.z[i];
+    s.wall2 = dmul(2.0, g.wall);
+    s.Lx = g.Lx;
+    s.hLx = g.hLx;
+    s.Ly = g.Ly;
+    s.hLy = g.hLy;
+    return s;
+}
+
+// The points of U list entries (the same points as list_point).  Every
+// position load is issued before the first is used, so the U gathers are
+// in flight together instead of one latency after another.
+template <int U>
+__device__ __forceinline__ void gather_list(const View& v, const Seen& s,
+                                            const int32_t (&e)[U], Pt (&p)[U])
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t j = e[u] & ~MBIT;
+        p[u].x = v.x[j];
+        p[u].y = v.y[j];
+        p[u].z = v.z[j];
+        p[u].src = j;
+        p[u].id = j;
+        p[u].mirror = (e[u] & MBIT) != 0;
+        p[u].valid = true;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (p[u].mirror) {
+            const int32_t k = v.mirror_of[p[u].src];
+            p[u].valid = k >= 0;
+            p[u].id = (int32_t)v.n + k;
+            p[u].z = dsub(s.wall2, p[u].z);
+        }
+    }
+    if (v.periodic) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            p[u].x = image_coord(p[u].x, s.xi, s.Lx, s.hLx);
+            p[u].y = image_coord(p[u].y, s.yi, s.Ly, s.hLy);
+        }
+    }
+}
+
 // Point of a stencil id (real id, or n + k for mirror k), seen from
 // (xi, yi).
 __device__ __forceinline__ Pt id_point(const View& v, const GridInfo& g,
@@ -149,13 +214,17 @@ struct MaskWalk {
 // Calls f(pt, dx, dy, dz) for every stencil row of real particle i, in
 // ascending list order (the ghost rows are not visited: they follow from
 // r.gm).  Each lane walks only its own kept entries, so a wave runs as
-// many iterations as its largest stencil.
-template <class F>
+// many iterations as its largest stencil.  Rows are taken B at a time:
+// their list words, then their positions, are loaded together, and the
+// calls of f for the batch form one block, so the loads f makes for later
+// rows can be issued before the earlier rows are summed.
+template <int B = FIT_BATCH, class F>
 __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
                                               int64_t i, const Rec& r, F&& f)
 {
     const int64_t n = v.n;
-    const double xi = v.x[i], yi = v.y[i], zi = v.z[i];
+    const Seen s = seen_from(v, g, i);
+    const double xi = s.xi, yi = s.yi, zi = s.zi;
     if (r.mode & MODE_SORTED) {
         for (int k = 0; k < r.m; ++k) {
             const Pt p = id_point(v, g, v.hsten[(int64_t)k * n + i], xi, yi);
@@ -164,10 +233,22 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
         return;
     }
     MaskWalk mw(r);
-    for (int t = 0; t < r.m; ++t) {
-        const int k = mw.pop();
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
-        f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
+    int t = 0;
+    for (; t + B <= r.m; t += B) {
+        int32_t e[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) e[u] = v.vl[(int64_t)mw.pop() * n + i];
+        Pt p[B];
+        gather_list(v, s, e, p);
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            f(p[u], dsub(p[u].x, xi), dsub(p[u].y, yi), dsub(p[u].z, zi));
+    }
+    for (; t < r.m; ++t) {
+        const int32_t e[1] = {v.vl[(int64_t)mw.pop() * n + i]};
+        Pt p[1];
+        gather_list(v, s, e, p);
+        f(p[0], dsub(p[0].x, xi), dsub(p[0].y, yi), dsub(p[0].z, zi));
     }
 }
 

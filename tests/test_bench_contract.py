@@ -1,6 +1,6 @@
-"""Host-side checks of bench.py: the one-GPU guard, and that the committed
-HBM byte records of the three hot kernels belong to the current sources
-(a kernel changed since its counters were taken reports null traffic)."""
+"""Host-side checks of bench.py: the one-GPU guard, the algorithmic byte
+counts, and the committed HBM byte records of the three hot kernels (a
+kernel changed since its counters were taken reports null traffic)."""
 import os
 import subprocess
 import sys
@@ -18,12 +18,38 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_records_match_the_sources():
+def test_traffic_records_follow_the_sources(tmp_path, monkeypatch):
+    """Each committed record parses; it yields bytes exactly when the
+    SHA-256 of the kernel's sources matches, and None once they change."""
+    import json
+    import re
     for prof, src in ((bench.PASS1_PROFILE, bench.PASS1_SOURCES),
                       (bench.SELECT_PROFILE, bench.SELECT_SOURCES),
                       (bench.PASS2_PROFILE, bench.PASS2_SOURCES)):
+        text = open(os.path.join(ROOT, prof)).read()
+        m = re.search(r"^traffic-record: (\{.*\})\s*$", text, re.M)
+        assert m, prof
+        rec = json.loads(m.group(1))
+        for key in ("fetch_kib", "write_kib", "fetch_scale", "write_scale",
+                    "source_sha256"):
+            assert key in rec, (prof, key)
         t = bench.kernel_traffic(prof, src)
-        assert t is not None and t > 0, prof
+        if rec["source_sha256"] == bench.sources_digest(src):
+            want = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"]
+                             + rec["write_kib"] * rec["write_scale"])
+            assert t == want and t > 0
+        else:
+            assert t is None
+    # a record whose digest does not match reports no traffic
+    rec = {"kernel": "k", "fetch_kib": 1.0, "write_kib": 1.0, "fetch_scale": 2.0,
+           "write_scale": 1.0, "source_sha256": "0" * 64}
+    f = tmp_path / "p.md"
+    f.write_text("traffic-record: " + json.dumps(rec) + "\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.kernel_traffic("p.md", []) is None
+    rec["source_sha256"] = bench.sources_digest([])
+    f.write_text("traffic-record: " + json.dumps(rec) + "\n")
+    assert bench.kernel_traffic("p.md", []) == 3072.0
 
 
 def test_algorithmic_bytes_per_particle():
