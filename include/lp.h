@@ -50,10 +50,12 @@ typedef enum {
 enum { LP_FP64 = 0, LP_FP32_REFINED = 1 };
 enum { LP_W_UNIT = 0, LP_W_GAUSS = 1 };
 
-/* debug_flags: route every particle through the exact slow paths, or fix
- * the lanes per particle of the fits (see lp_autotune) */
+/* debug_flags: route every particle through the exact slow paths, fix
+ * the lanes per particle of the fits (see lp_autotune), or make the fits
+ * read every neighbour from global memory instead of from the tile's
+ * neighbours staged in LDS (results agree to rounding) */
 enum { LP_DEBUG_SORTED_STENCIL = 1, LP_DEBUG_QR_FIT = 2, LP_DEBUG_LANES2 = 4,
-       LP_DEBUG_LANES4 = 8 };
+       LP_DEBUG_LANES4 = 8, LP_DEBUG_GLOBAL_GATHER = 16 };
 
 /* Physical constants of one system (Sec. 2.2, 2.2.1 and Sec. 4).
  * rho_s: grain material density (the paper's phi_s); d: grain diameter;
@@ -342,7 +344,11 @@ lp_status lp_sync_status(lp_ctx* ctx, int64_t* index);
 /* Diagnostics accumulated since the last call (host int64[8]):
  * particles, mirrors (last stencil build), QR refits, sorted-path stencils,
  * particles below the wall after updates, neighbour-list rebuilds by
- * lp_step, 0, 0; then resets them.  Synchronises. */
+ * lp_step; then resets them.  Entries 6 and 7 describe the current
+ * neighbour list (0 when there is none): tiles of BLOCK = 256 consecutive
+ * particles whose neighbours the fits cannot stage in LDS (more than 1536
+ * distinct list sources, or LP_DEBUG_GLOBAL_GATHER), and all tiles.
+ * Synchronises. */
 lp_status lp_stats(lp_ctx* ctx, int64_t* out8);
 
 /* Phase timing (instrumentation).  lp_profile(ctx, 1) makes lp_step

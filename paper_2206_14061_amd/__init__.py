@@ -13,8 +13,8 @@ import ctypes as C
 from typing import Dict, List, Optional, Sequence
 
 from . import _lib
-from ._lib import (LP_DEBUG_LANES2, LP_DEBUG_LANES4, LP_DEBUG_QR_FIT,
-                   LP_DEBUG_SORTED_STENCIL, LP_FP32_REFINED,
+from ._lib import (LP_DEBUG_GLOBAL_GATHER, LP_DEBUG_LANES2, LP_DEBUG_LANES4,
+                   LP_DEBUG_QR_FIT, LP_DEBUG_SORTED_STENCIL, LP_FP32_REFINED,
                    LP_FP64, LP_W_GAUSS, LP_W_UNIT, LPConfig, LPError,
                    LPParams, LPState)
 
@@ -291,7 +291,8 @@ class Context:
         out = (C.c_int64 * 8)()
         self._check(self.lib.lp_stats(self.h, out))
         return dict(particles=out[0], mirrors=out[1], qr_refits=out[2],
-                    sorted_stencils=out[3], below_wall=out[4], rebuilds=out[5])
+                    sorted_stencils=out[3], below_wall=out[4], rebuilds=out[5],
+                    unstaged_tiles=out[6], tiles=out[7])
 
 
 def make_context(workload, **cfg) -> Context:

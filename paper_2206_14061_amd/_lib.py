@@ -17,7 +17,7 @@ LP_OK, LP_E_ARG, LP_E_CAPACITY, LP_E_NUMERIC, LP_E_HIP, LP_E_STATE = range(6)
 LP_FP64, LP_FP32_REFINED = 0, 1
 LP_W_UNIT, LP_W_GAUSS = 0, 1
 LP_DEBUG_SORTED_STENCIL, LP_DEBUG_QR_FIT = 1, 2
-LP_DEBUG_LANES2, LP_DEBUG_LANES4 = 4, 8
+LP_DEBUG_LANES2, LP_DEBUG_LANES4, LP_DEBUG_GLOBAL_GATHER = 4, 8, 16
 
 STATUS_NAMES = {0: "LP_OK", 1: "LP_E_ARG", 2: "LP_E_CAPACITY",
                 3: "LP_E_NUMERIC", 4: "LP_E_HIP", 5: "LP_E_STATE"}

@@ -1,5 +1,6 @@
 // C ABI entry points, context and workspace of the LP granular-step library.
 #include <cmath>
+#include <vector>
 #include <cstring>
 #include <new>
 
@@ -37,6 +38,9 @@ View make_view(lp_ctx* c, const double* const st[7])
     v.msrc = w.msrc;
     v.vl = w.vl;
     v.vcnt = w.vcnt;
+    v.tile_src = w.tile_src;
+    v.tile_cnt = w.tile_cnt;
+    v.vs = w.vs;
     v.code = w.code;
     v.rec = w.rec;
     v.kmask = w.kmask;
@@ -75,7 +79,7 @@ void free_work(Work& w)
     for (int a = 0; a < 7; ++a) f(w.sst[a]);
     for (int a = 0; a < 3; ++a) f(w.xref[a]);
     f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
-    f(w.vl); f(w.vcnt); f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
+    f(w.vl); f(w.vcnt); f(w.tile_src); f(w.tile_cnt); f(w.vs); f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
     f(w.redo); f(w.redo_n); f(w.qr_scratch);
     f(w.P); f(w.eta); f(w.hand); f(w.uf);
     for (int a = 0; a < 7; ++a) f(w.adj[a]);
@@ -247,6 +251,9 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.mirror_of, n_max); A(w.msrc, n_max); A(w.bsum, nb + 1);
     A(w.cs, cells_max); A(w.ce, cells_max);
     A(w.vl, (int64_t)VCAP * n_max); A(w.vcnt, n_max);
+    A(w.tile_src, (int64_t)STAGE_CAP * ((n_max + BLOCK - 1) / BLOCK));
+    A(w.tile_cnt, (n_max + BLOCK - 1) / BLOCK);
+    A(w.vs, (int64_t)VCAP * n_max);
     A(w.code, (int64_t)(VCAP / 4) * n_max);
     A(w.kmask, (int64_t)MASK_WORDS * n_max);
     A(w.rec, (int64_t)REC_FIELDS * n_max); A(w.hsten, (int64_t)mm * n_max);
@@ -271,6 +278,9 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     if (e == hipSuccess) e = hipMemset(w.err, 0, sizeof(ErrWord));
     if (e == hipSuccess) e = hipMemset(w.cnt, 0, sizeof(Counters));
     if (e == hipSuccess) e = hipMemset(w.summary, 0, sizeof(Summary));
+    // no tile is staged until a neighbour list is built
+    if (e == hipSuccess)
+        e = hipMemset(w.tile_cnt, 0xFF, sizeof(int32_t) * ((n_max + BLOCK - 1) / BLOCK));
     if (e == hipSuccess) {
         ErrWord ew{0, 0, ~0ull};
         e = hipMemcpy(w.err, &ew, sizeof(ew), hipMemcpyHostToDevice);
@@ -814,6 +824,18 @@ lp_status lp_stats(lp_ctx* c, int64_t* out8)
     out8[4] = (int64_t)k.below_wall;
     out8[5] = c->rebuilds + (int64_t)k.rebuilds;
     c->rebuilds = 0;
+    // tiles of the current neighbour list, and those the fits cannot stage
+    if (c->list_ok && c->n > 0) {
+        const int64_t tiles = (c->n + BLOCK - 1) / BLOCK;
+        std::vector<int32_t> tc((size_t)tiles);
+        e = hipMemcpy(tc.data(), c->w.tile_cnt, sizeof(int32_t) * tiles,
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(c, e, "lp_stats");
+        int64_t off = 0;
+        for (int32_t v : tc) off += (v < 0 || v > STAGE_CAP) ? 1 : 0;
+        out8[6] = off;
+        out8[7] = tiles;
+    }
     Counters z{};
     e = hipMemcpyAsync(c->w.cnt, &z, sizeof(z), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -240,6 +240,36 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic_qr(
 
 // ---- lp_step pass 1: fit u, v, w + closure --------------------------------
 
+// Factor, solve and store one particle's pass-1 fit from its Gram moments
+// M and right-hand sides B (mt rows): coefficients, closure and the rows of
+// G^-1 for pass 2, or a queued QR refit when the Gram matrix is too ill
+// conditioned.  Only the lead lane of the particle writes.
+__device__ __forceinline__ void pass1_solve(const View& v, const StepOut& o,
+                                            const GridInfo& g, int s, int64_t i,
+                                            const double (&M)[31], double (&B)[3][9],
+                                            int mt, bool lead, int32_t* redo,
+                                            unsigned int* redo_n, int force_qr)
+{
+    double G[45], c3[3][9], none[27];
+    gram_from_moments(M, G);
+    uint8_t fl;
+    if (!gram_solve<3>(G, B, mt, v.redo_ratio, force_qr != 0, c3, none, false, fl)) {
+        if (lead) {
+            redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
+            o.flags[i] = FLAG_QR;
+        }
+        return;
+    }
+    if (!lead) return;
+    double c[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q)
+        c[q] = c3[q / 9][q % 9] * ((q % 9) < 3 ? g.inv_h : g.inv_h * g.inv_h);
+    finish_pass1(v, v.prm[s], i, c, none, false, fl, o);
+    if (mt < 9) store_ginv_rows<3>(G, o.hand, v.n, i);
+    else store_ginv_rows<9>(G, o.hand, v.n, i);
+}
+
 // LPP lanes per particle: each lane accumulates every LPP-th row; the
 // moments are summed across the lanes, every lane solves, lane 0 stores.
 template <int LPP>
@@ -286,24 +316,76 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
             B[2][q] = lane_sum<LPP>(B[2][q]);
         }
     }
-    double G[45], c3[3][9], none[27];
-    gram_from_moments(M, G);
-    uint8_t fl;
-    if (!gram_solve<3>(G, B, mt, v.redo_ratio, force_qr != 0, c3, none, false, fl)) {
-        if (sub == 0) {
-            redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
-            o.flags[i] = FLAG_QR;
+    pass1_solve(v, o, g, s, i, M, B, mt, sub == 0, redo, redo_n, force_qr);
+}
+
+// Pass 1 with the neighbours of the block's tile staged in LDS (one lane
+// per particle): the positions and velocities of the tile's list sources
+// are loaded once, coalesced, and every stencil row reads them from LDS.
+// A tile that is not staged, and a particle on the sorted path, read their
+// neighbours from global memory as k_pass1<1> does.
+__global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
+                                                       int32_t* redo,
+                                                       unsigned int* redo_n,
+                                                       int force_qr)
+{
+    __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
+    __shared__ double su[STAGE_CAP], sv[STAGE_CAP], sw[STAGE_CAP];
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = tile * BLOCK + threadIdx.x;
+    const int tc = v.tile_cnt[tile];
+    const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
+    if (S >= 0) {
+        const int32_t* src = v.tile_src + tile * STAGE_CAP;
+        for (int q = threadIdx.x; q < S; q += BLOCK) {
+            const int32_t j = src[q];
+            sx[q] = v.x[j];
+            sy[q] = v.y[j];
+            sz[q] = v.z[j];
+            su[q] = v.u[j];
+            sv[q] = v.v[j];
+            sw[q] = v.w[j];
         }
-        return;
+        __syncthreads();
     }
-    if (sub != 0) return;
-    double c[27];
+    if (i >= v.n) return;
+    const int s = sys_of(v.off, v.n_sys, i);
+    const GridInfo& g = v.grid[s];
+    const Rec r = load_rec(v, i);
+    const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
+    double M[31], B[3][9];
 #pragma unroll
-    for (int q = 0; q < 27; ++q)
-        c[q] = c3[q / 9][q % 9] * ((q % 9) < 3 ? g.inv_h : g.inv_h * g.inv_h);
-    finish_pass1(v, v.prm[s], i, c, none, false, fl, o);
-    if (mt < 9) store_ginv_rows<3>(G, o.hand, v.n, i);
-    else store_ginv_rows<9>(G, o.hand, v.n, i);
+    for (int q = 0; q < 31; ++q) M[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) B[0][q] = B[1][q] = B[2][q] = 0.0;
+    auto add_b = [&](const double* a, double w, double uj, double vj, double wj) {
+        const double b0 = w * (uj - ui), b1 = w * (vj - vi), b2 = w * (wj - wi);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            B[0][q] += a[q] * b0;
+            B[1][q] += a[q] * b1;
+            B[2][q] += a[q] * b2;
+        }
+    };
+    int mt;
+    if (S >= 0 && !(r.mode & MODE_SORTED)) {
+        mt = for_rows_staged<FIT_BATCH>(v, g, i, r, sx, sy, sz,
+                                        [&](const double* a, double w, const Pt* p) {
+            moments_add(M, a, w);
+            if (!p) return;   // ghosts carry u_i (b = 0)
+            const int q = p->src;
+            add_b(a, w, su[q], sv[q], p->mirror ? -sw[q] : sw[q]);
+        });
+    } else {
+        mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+            moments_add(M, a, w);
+            if (!p) return;
+            double uj, vj, wj;
+            point_velocity(v, *p, uj, vj, wj);
+            add_b(a, w, uj, vj, wj);
+        });
+    }
+    pass1_solve(v, o, g, s, i, M, B, mt, true, redo, redo_n, force_qr);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pass1_qr(View v, StepOut o,
@@ -371,6 +453,33 @@ __global__ __launch_bounds__(BLOCK) void k_closure_coef(View v, const double* co
 
 // ---- pass 2: fit of P and eta, right-hand side, update --------------------
 
+// Gradients of P and eta from the pass-2 right-hand sides (the stored rows
+// of G^-1), then the right-hand side and update of particle i.
+__device__ __forceinline__ void pass2_finish(const View& v, const lp_params& prm,
+                                             const GridInfo& g, int64_t i,
+                                             const double* hand, const double (&yP)[9],
+                                             const double (&yE)[9], double Ei,
+                                             const RhsOut& o)
+{
+    const int64_t n = v.n;
+    double gP[3], gE[3];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr) {
+        double sp = 0.0, se = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const double gi = hand[(int64_t)(rr * 9 + q) * n + i];
+            sp += gi * yP[q];
+            se += gi * yE[q];
+        }
+        gP[rr] = sp * g.inv_h;
+        gE[rr] = se * g.inv_h;
+    }
+    double hv[11];
+    load_hand_tail(hand, n, i, Ei, hv);
+    finish_rhs(v, prm, i, hv, gP, gE, o);
+}
+
 #ifndef LP_PASS2_BATCH
 #define LP_PASS2_BATCH 8
 #endif
@@ -417,22 +526,80 @@ __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
         }
     }
     if (sub != 0) return;
-    double gP[3], gE[3];
+    pass2_finish(v, prm, g, i, hand, yP, yE, Ei, o);
+}
+
+// Pass 2 with the neighbours of the block's tile staged in LDS (one lane
+// per particle): positions, P, eta and the pressure a mirror of each list
+// source carries are loaded once, coalesced, and every stencil row reads
+// them from LDS.  A tile that is not staged, and a particle on the sorted
+// path, read their neighbours from global memory as k_pass2<1> does.
+__global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
+                                                    const double* eta,
+                                                    const double* hand,
+                                                    const uint8_t* flags, RhsOut o)
+{
+    __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
+    __shared__ double sP[STAGE_CAP], sE[STAGE_CAP], sM[STAGE_CAP];
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = tile * BLOCK + threadIdx.x;
+    const int tc = v.tile_cnt[tile];
+    const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
+    if (S >= 0) {
+        const int32_t* src = v.tile_src + tile * STAGE_CAP;
+        for (int q = threadIdx.x; q < S; q += BLOCK) {
+            const int32_t j = src[q];
+            sx[q] = v.x[j];
+            sy[q] = v.y[j];
+            sz[q] = v.z[j];
+            sP[q] = P[j];
+            sE[q] = eta[j];
+            // what a mirror of j carries (pass2_values); j's system is
+            // that of every particle listing it
+            const int sj = sys_of(v.off, v.n_sys, j);
+            Pt m;
+            m.mirror = true;
+            m.src = j;
+            m.z = dsub(dmul(2.0, v.grid[sj].wall), v.z[j]);
+            double pm, em;
+            pass2_values(v, P, eta, &m, v.prm[sj], pm, em);
+            sM[q] = pm;
+        }
+        __syncthreads();
+    }
+    if (i >= v.n) return;
+    if (flags[i] & FLAG_QR) return;
+    const int s = sys_of(v.off, v.n_sys, i);
+    const GridInfo& g = v.grid[s];
+    const lp_params& prm = v.prm[s];
+    const Rec r = load_rec(v, i);
+    const double Pi = P[i], Ei = eta[i];
+    double yP[9], yE[9];
 #pragma unroll
-    for (int rr = 0; rr < 3; ++rr) {
-        double sp = 0.0, se = 0.0;
+    for (int q = 0; q < 9; ++q) yP[q] = yE[q] = 0.0;
+    auto add_y = [&](const double* a, double w, double Pj, double Ej) {
+        const double bP = w * (Pj - Pi), bE = w * (Ej - Ei);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            const double gi = hand[(int64_t)(rr * 9 + q) * n + i];
-            sp += gi * yP[q];
-            se += gi * yE[q];
+            yP[q] += a[q] * bP;
+            yE[q] += a[q] * bE;
         }
-        gP[rr] = sp * g.inv_h;
-        gE[rr] = se * g.inv_h;
+    };
+    if (S >= 0 && !(r.mode & MODE_SORTED)) {
+        for_rows_staged<PASS2_BATCH>(v, g, i, r, sx, sy, sz,
+                                     [&](const double* a, double w, const Pt* p) {
+            if (!p) add_y(a, w, 0.0, 0.0);
+            else if (p->mirror) add_y(a, w, sM[p->src], 0.0);
+            else add_y(a, w, sP[p->src], sE[p->src]);
+        });
+    } else {
+        for_rows<PASS2_BATCH>(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+            double Pj, Ej;
+            pass2_values(v, P, eta, p, prm, Pj, Ej);
+            add_y(a, w, Pj, Ej);
+        });
     }
-    double hv[11];
-    load_hand_tail(hand, n, i, Ei, hv);
-    finish_rhs(v, prm, i, hv, gP, gE, o);
+    pass2_finish(v, prm, g, i, hand, yP, yE, Ei, o);
 }
 
 // ---- refined FP32 fits ----------------------------------------------------
@@ -734,7 +901,7 @@ void launch_pass1(lp_ctx* c, int lpp, const View& v, const StepOut& so, int fq)
                            c->stream, v, so, w.redo, w.redo_n, fq);
         break;
     default:
-        hipLaunchKernelGGL((k_pass1<1>), dim3(blocks_for(n)), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_pass1_st, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, v, so, w.redo, w.redo_n, fq);
     }
 }
@@ -757,7 +924,7 @@ void launch_pass2(lp_ctx* c, int lpp, const View& v, const RhsOut& o)
                            c->stream, v, P, E, H, F, o);
         break;
     default:
-        hipLaunchKernelGGL((k_pass2<1>), dim3(blocks_for(n)), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_pass2_st, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, v, P, E, H, F, o);
     }
 }

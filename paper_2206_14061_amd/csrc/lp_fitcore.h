@@ -255,6 +255,33 @@ __device__ __forceinline__ int for_rows(const View& v, const GridInfo& g,
     return m;
 }
 
+// for_rows for a particle of a staged tile: stencil rows from the LDS
+// copies (sx, sy, sz) through visit_staged, then the ghost rows.
+template <int B, class F>
+__device__ __forceinline__ int for_rows_staged(const View& v, const GridInfo& g,
+                                               int64_t i, const Rec& r, const double* sx,
+                                               const double* sy, const double* sz, F&& f)
+{
+    int m = 0;
+    const Seen s = seen_from(v, g, i);
+    visit_staged<B>(v, s, i, r, sx, sy, sz,
+                    [&](const Pt& p, double dx, double dy, double dz) {
+        double a[9];
+        const double w = point_row(v, g, dx, dy, dz, a);
+        f(a, w, &p);
+        ++m;
+    });
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+        if ((r.gm >> o) & 1) {
+            double a[9];
+            const double w = ghost_row(v, g, o, a);
+            f(a, w, (const Pt*)nullptr);
+            ++m;
+        }
+    return m;
+}
+
 // for_rows with the rows spread over LPP lanes (stencil rows as in
 // visit_stencil_sub, ghost o to lane o mod LPP; B: rows loaded together
 // with one lane per particle); returns this lane's rows.

@@ -15,9 +15,18 @@ constexpr int NCOEF = 9;          // unknowns of the 2nd-order 3D fit
 constexpr int MMAX_LIMIT = 64;    // largest supported stencil cap
 constexpr int MAXROWS = MMAX_LIMIT + 8;
 constexpr int HIST_BUCKETS = 64;  // r^2 histogram of the stencil selection
-constexpr int LIST_CAP = 16;      // cut-bucket members ranked per thread
+#ifndef LP_LIST_CAP
+#define LP_LIST_CAP 16
+#endif
+constexpr int LIST_CAP = LP_LIST_CAP;  // cut-bucket members ranked per thread
 constexpr int VCAP = 256;         // neighbour-list entries per particle
 constexpr int MASK_WORDS = VCAP / 64;  // keep bitmask words per particle
+// A tile is BLOCK consecutive particles.  The fits stage the fields of the
+// distinct sources of a tile's neighbour lists in LDS (at most STAGE_CAP
+// of them); a list entry names its source's slot in a 16-bit word whose
+// top bit marks a mirror entry.
+constexpr int STAGE_CAP = 1536;
+constexpr uint32_t SLOT_MIRROR = 0x8000u;
 constexpr int32_t MBIT = 0x40000000;  // list entry: mirror of the real id
 constexpr int32_t NOID = 0x7FFFFFFF;
 // per-particle stencil record (int32 fields, field f of particle i at
@@ -100,6 +109,11 @@ struct View {
     // neighbour list with skin (ELL, entry k of particle i at k*n + i)
     const int32_t* vl;
     const int32_t* vcnt;
+    // per tile: its list sources in ascending order (STAGE_CAP per tile)
+    // and their count (-1: not staged); slot of every list entry
+    const int32_t* tile_src;
+    const int32_t* tile_cnt;
+    const uint16_t* vs;
     uint32_t* code;             // r^2 buckets of the list entries, four per word
                                 // (entry k: byte k % 4 of word (k / 4) n + i;
                                 // NO_CAND: outside R)
@@ -145,6 +159,9 @@ struct Work {
     // neighbour list, records, sorted-path stencils
     int32_t* vl = nullptr;
     int32_t* vcnt = nullptr;
+    int32_t* tile_src = nullptr;          // tiles x STAGE_CAP
+    int32_t* tile_cnt = nullptr;          // tiles
+    uint16_t* vs = nullptr;               // VCAP x n
     uint32_t* code = nullptr;             // VCAP / 4 x n
     int32_t* rec = nullptr;
     uint64_t* kmask = nullptr;            // MASK_WORDS x n

@@ -757,6 +757,119 @@ __global__ void k_export_stencils(View v, int32_t* cnt_out, int32_t* idx_out,
     if (cnt_out) cnt_out[i] = m;
 }
 
+// ---- tile map: the distinct list sources of each tile ------------------
+//
+// One block per tile of BLOCK consecutive particles.  The sources of all
+// list entries of the tile are inserted in an LDS hash set, compacted,
+// sorted ascending (bitonic, SORT_N keys) and stored; every list entry
+// then gets the slot of its source in that order (a 16-bit word, with
+// SLOT_MIRROR for a mirror entry).  A tile with more than STAGE_CAP
+// sources, or whose hash set fills, is marked -1 (not staged).
+
+constexpr int HASH_SIZE = 4096;        // LDS hash slots per tile (power of 2)
+constexpr int SORT_N = 2048;           // keys sorted per tile (>= STAGE_CAP)
+static_assert(STAGE_CAP <= SORT_N && SORT_N <= HASH_SIZE, "tile map sizes");
+static_assert(STAGE_CAP <= (int)SLOT_MIRROR, "slots fit below the mirror bit");
+
+__device__ __forceinline__ uint32_t src_hash(int32_t j)
+{
+    return ((uint32_t)j * 2654435761u) >> 20;   // top 12 bits: HASH_SIZE
+}
+
+// hash slot holding key j (present), found within HASH_SIZE probes
+__device__ __forceinline__ int hash_find(const int32_t* hkey, int32_t j)
+{
+    uint32_t h = src_hash(j);
+    for (int probe = 0; probe < HASH_SIZE; ++probe) {
+        if (hkey[h] == j) return (int)h;
+        h = (h + 1) & (HASH_SIZE - 1);
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_tile_map(
+    int64_t n, const int32_t* __restrict__ vl, const int32_t* __restrict__ vcnt,
+    int32_t* __restrict__ tile_src, int32_t* __restrict__ tile_cnt,
+    uint16_t* __restrict__ vs, int disable, const int32_t* gate)
+{
+    static_assert(HASH_SIZE == 1 << 12, "src_hash keeps 12 bits");
+    if (gate && *gate == 0) return;
+    __shared__ int32_t hkey[HASH_SIZE];
+    __shared__ uint16_t hslot[HASH_SIZE];
+    __shared__ int32_t keys[SORT_N];
+    __shared__ uint32_t wsum[BLOCK / 64];
+    __shared__ int full;
+    const int t = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t i = tile * BLOCK + t;
+    const int cnt = i < n ? vcnt[i] : 0;
+    for (int h = t; h < HASH_SIZE; h += BLOCK) hkey[h] = -1;
+    if (t == 0) full = disable;
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k) {
+        const int32_t j = vl[(int64_t)k * n + i] & ~MBIT;
+        uint32_t h = src_hash(j);
+        int probe = 0;
+        for (; probe < HASH_SIZE; ++probe) {
+            const int32_t old = atomicCAS(&hkey[h], -1, j);
+            if (old == -1 || old == j) break;
+            h = (h + 1) & (HASH_SIZE - 1);
+        }
+        if (probe == HASH_SIZE) full = 1;
+    }
+    __syncthreads();
+    // compact: thread t takes hash slots [t PER, (t + 1) PER)
+    constexpr int PER = HASH_SIZE / BLOCK;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) mine += hkey[t * PER + q] >= 0 ? 1u : 0u;
+    uint32_t total = 0;
+    uint32_t at = block_excl_scan(mine, wsum, total);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int32_t j = hkey[t * PER + q];
+        if (j >= 0) {
+            if (at < (uint32_t)SORT_N) keys[at] = j;
+            ++at;
+        }
+    }
+    const int S = (int)total;
+    if (full || S > STAGE_CAP) {
+        if (t == 0) tile_cnt[tile] = -1;
+        return;
+    }
+    for (int q = S + t; q < SORT_N; q += BLOCK) keys[q] = INT32_MAX;
+    __syncthreads();
+    for (int size = 2; size <= SORT_N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int q = t; q < SORT_N / 2; q += BLOCK) {
+                const int lo = 2 * q - (q & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const int32_t a = keys[lo], b = keys[hi];
+                if ((a > b) == up) {
+                    keys[lo] = b;
+                    keys[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = t; q < S; q += BLOCK) {
+        tile_src[tile * STAGE_CAP + q] = keys[q];
+        const int h = hash_find(hkey, keys[q]);
+        if (h >= 0) hslot[h] = (uint16_t)q;
+    }
+    if (t == 0) tile_cnt[tile] = S;
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k) {
+        const int32_t e = vl[(int64_t)k * n + i];
+        const int h = hash_find(hkey, e & ~MBIT);
+        const uint32_t q = h >= 0 ? hslot[h] : 0u;
+        vs[(int64_t)k * n + i] = (uint16_t)(q | ((e & MBIT) ? SLOT_MIRROR : 0u));
+    }
+}
+
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 }  // namespace
@@ -770,6 +883,10 @@ lp_status list_build(lp_ctx* c, const int32_t* gate)
         hipLaunchKernelGGL(k_list_build, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
                            w.sst[2], w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
+    if (n > 0)
+        hipLaunchKernelGGL(k_tile_map, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
+                           n, w.vl, w.vcnt, w.tile_src, w.tile_cnt, w.vs,
+                           (c->cfg.debug_flags & LP_DEBUG_GLOBAL_GATHER) ? 1 : 0, gate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "list build launch");
     c->list_ok = true;

@@ -252,6 +252,45 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
     }
 }
 
+// visit_stencil for a particle of a staged tile (not on the sorted path):
+// the fields of the tile's list sources sit in LDS in slot order, and a
+// row's point is read from there through the slot word of its list entry.
+// The Pt handed to f carries the slot in `src` (and no id).  Rows come in
+// the same order as from visit_stencil.
+template <int B, class F>
+__device__ __forceinline__ void visit_staged(const View& v, const Seen& s, int64_t i,
+                                             const Rec& r, const double* sx,
+                                             const double* sy, const double* sz, F&& f)
+{
+    const int64_t n = v.n;
+    auto row = [&](uint32_t word) {
+        Pt p;
+        const int q = (int)(word & (SLOT_MIRROR - 1u));
+        p.mirror = (word & SLOT_MIRROR) != 0u;
+        p.valid = true;
+        p.src = q;
+        p.id = -1;
+        p.x = sx[q];
+        p.y = sy[q];
+        p.z = p.mirror ? dsub(s.wall2, sz[q]) : sz[q];
+        if (v.periodic) {
+            p.x = image_coord(p.x, s.xi, s.Lx, s.hLx);
+            p.y = image_coord(p.y, s.yi, s.Ly, s.hLy);
+        }
+        f(p, dsub(p.x, s.xi), dsub(p.y, s.yi), dsub(p.z, s.zi));
+    };
+    MaskWalk mw(r);
+    int t = 0;
+    for (; t + B <= r.m; t += B) {
+        uint32_t w[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) w[u] = v.vs[(int64_t)mw.pop() * n + i];
+#pragma unroll
+        for (int u = 0; u < B; ++u) row(w[u]);
+    }
+    for (; t < r.m; ++t) row(v.vs[(int64_t)mw.pop() * n + i]);
+}
+
 // visit_stencil with the rows of particle i spread over LPP adjacent
 // lanes: lane `sub` takes kept rows sub, sub + LPP, sub + 2 LPP, ...
 template <int LPP, class F>
