@@ -240,6 +240,21 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic_qr(
 
 // ---- lp_step pass 1: fit u, v, w + closure --------------------------------
 
+// Staged sources per thread of a block, and this thread's source ids in
+// the tile (slot threadIdx.x + u BLOCK; -1 past the tile's S sources).
+constexpr int STAGE_PER = (STAGE_CAP + BLOCK - 1) / BLOCK;
+
+__device__ __forceinline__ void stage_ids(const View& v, int64_t tile, int S,
+                                          int32_t (&js)[STAGE_PER])
+{
+    const int32_t* src = v.tile_src + tile * STAGE_CAP;
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        const int q = (int)threadIdx.x + u * BLOCK;
+        js[u] = q < S ? src[q] : -1;
+    }
+}
+
 // Factor, solve and store one particle's pass-1 fit from its Gram moments
 // M and right-hand sides B (mt rows): coefficients, closure and the rows of
 // G^-1 for pass 2, or a queued QR refit when the Gram matrix is too ill
@@ -336,15 +351,30 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
     const int tc = v.tile_cnt[tile];
     const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
     if (S >= 0) {
-        const int32_t* src = v.tile_src + tile * STAGE_CAP;
-        for (int q = threadIdx.x; q < S; q += BLOCK) {
-            const int32_t j = src[q];
-            sx[q] = v.x[j];
-            sy[q] = v.y[j];
-            sz[q] = v.z[j];
-            su[q] = v.u[j];
-            sv[q] = v.v[j];
-            sw[q] = v.w[j];
+        // all of this thread's sources at once: their ids, then their fields
+        int32_t js[STAGE_PER];
+        stage_ids(v, tile, S, js);
+        double f[6][STAGE_PER];
+#pragma unroll
+        for (int u = 0; u < STAGE_PER; ++u) {
+            const int32_t j = js[u] < 0 ? 0 : js[u];
+            f[0][u] = v.x[j];
+            f[1][u] = v.y[j];
+            f[2][u] = v.z[j];
+            f[3][u] = v.u[j];
+            f[4][u] = v.v[j];
+            f[5][u] = v.w[j];
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_PER; ++u) {
+            if (js[u] < 0) continue;
+            const int q = (int)threadIdx.x + u * BLOCK;
+            sx[q] = f[0][u];
+            sy[q] = f[1][u];
+            sz[q] = f[2][u];
+            su[q] = f[3][u];
+            sv[q] = f[4][u];
+            sw[q] = f[5][u];
         }
         __syncthreads();
     }
@@ -546,21 +576,36 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
     const int tc = v.tile_cnt[tile];
     const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
     if (S >= 0) {
-        const int32_t* src = v.tile_src + tile * STAGE_CAP;
-        for (int q = threadIdx.x; q < S; q += BLOCK) {
-            const int32_t j = src[q];
-            sx[q] = v.x[j];
-            sy[q] = v.y[j];
-            sz[q] = v.z[j];
-            sP[q] = P[j];
-            sE[q] = eta[j];
+        // all of this thread's sources at once: their ids, then their fields
+        int32_t js[STAGE_PER];
+        stage_ids(v, tile, S, js);
+        double f[5][STAGE_PER];
+#pragma unroll
+        for (int u = 0; u < STAGE_PER; ++u) {
+            const int32_t j = js[u] < 0 ? 0 : js[u];
+            f[0][u] = v.x[j];
+            f[1][u] = v.y[j];
+            f[2][u] = v.z[j];
+            f[3][u] = P[j];
+            f[4][u] = eta[j];
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_PER; ++u) {
+            if (js[u] < 0) continue;
+            const int q = (int)threadIdx.x + u * BLOCK;
+            const int32_t j = js[u];
+            sx[q] = f[0][u];
+            sy[q] = f[1][u];
+            sz[q] = f[2][u];
+            sP[q] = f[3][u];
+            sE[q] = f[4][u];
             // what a mirror of j carries (pass2_values); j's system is
             // that of every particle listing it
             const int sj = sys_of(v.off, v.n_sys, j);
             Pt m;
             m.mirror = true;
             m.src = j;
-            m.z = dsub(dmul(2.0, v.grid[sj].wall), v.z[j]);
+            m.z = dsub(dmul(2.0, v.grid[sj].wall), f[2][u]);
             double pm, em;
             pass2_values(v, P, eta, &m, v.prm[sj], pm, em);
             sM[q] = pm;
