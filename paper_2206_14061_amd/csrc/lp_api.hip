@@ -457,12 +457,13 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
     // the skin since the last build
     bool rebuild = !c->list_ok || !(c->cfg.skin > 0.0);
     if (!rebuild) {
+        // the check also copies the state, which a rebuild then overwrites
         double ratio = -1.0;
-        r = list_displacement(c, in, &ratio);
+        r = list_displacement(c, in, &ratio, true);
         if (r != LP_OK) return r;
         rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.49);
     }
-    r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm);
+    r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm, nullptr, false);
     prof_mark(c, 0, true);
     if (r != LP_OK) return r;
     if (rebuild) ++c->rebuilds;
@@ -507,12 +508,13 @@ lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
     // further dt |u| on the same list and must stay within half the skin
     bool rebuild = !c->list_ok;
     if (!rebuild) {
+        // the check also copies the state, which a rebuild then overwrites
         double ratio = -1.0;
-        r = list_displacement(c, in, &ratio);
+        r = list_displacement(c, in, &ratio, true);
         if (r != LP_OK) return r;
         rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.4);
     }
-    r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm);
+    r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm, nullptr, false);
     if (r != LP_OK) return r;
     if (rebuild) ++c->rebuilds;
     const double* sorted[7];

@@ -438,6 +438,48 @@ __global__ __launch_bounds__(BLOCK) void k_disp(int64_t n, int n_sys, const int6
 
 __global__ void k_disp_init(Summary* sum) { sum->disp = ord_enc(0.0); }
 
+struct State7 {
+    const double* a[7];
+};
+struct Dest7 {
+    double* a[7];
+};
+
+// k_disp fused with the copy of the seven state arrays into the working
+// state (one pass over the state; one thread per particle).
+__global__ __launch_bounds__(BLOCK) void k_copy_disp(int64_t n, int n_sys,
+                                                     const int64_t* off,
+                                                     const GridInfo* grid, State7 st,
+                                                     Dest7 dst, const double* rx,
+                                                     const double* ry, const double* rz,
+                                                     Summary* sum)
+{
+    __shared__ double part[BLOCK / 64];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (i < n) {
+        double f[7];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) f[a] = st.a[a][i];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) dst.a[a][i] = f[a];
+        const GridInfo& g = grid[sys_of(off, n_sys, i)];
+        const double dx = image_coord(f[0], rx[i], g.Lx, g.hLx) - rx[i];
+        const double dy = image_coord(f[1], ry[i], g.Ly, g.hLy) - ry[i];
+        const double dz = f[2] - rz[i];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        r = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
+        if (!(r == r)) r = INFINITY;   // non-finite positions force a rebuild
+    }
+    for (int d = 32; d > 0; d >>= 1) r = fmax(r, __shfl_xor(r, d));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLOCK / 64; ++w) r = fmax(r, part[w]);
+        atomicMax(&sum->disp, ord_enc(r));
+    }
+}
+
 inline unsigned int blocks_for(int64_t n, int per = BLOCK)
 {
     return (unsigned int)((n + per - 1) / per);
@@ -596,12 +638,12 @@ lp_status cells_build_device(lp_ctx* c, double* const st[7], int32_t* ids,
 }
 
 lp_status state_copy(lp_ctx* c, double* const st[7], int32_t* perm_out,
-                     const int32_t* gate)
+                     const int32_t* gate, bool arrays)
 {
     Work& w = c->w;
     const int64_t n = c->n;
     if (n > 0) {
-        for (int a = 0; a < 7; ++a)
+        for (int a = 0; a < 7 && arrays; ++a)
             hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0,
                                c->stream, n, st[a], w.sst[a], gate);
         if (perm_out)
@@ -652,18 +694,30 @@ lp_status state_write_back(lp_ctx* c, double* const out[7])
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "state write-back");
 }
 
-lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio)
+lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
+                            bool copy)
 {
     Work& w = c->w;
     const int64_t n = c->n;
     *ratio = -1.0;
     if (!c->list_ok) return LP_OK;
     hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
-    if (n > 0)
+    if (n > 0 && copy) {
+        State7 s7;
+        Dest7 d7;
+        for (int a = 0; a < 7; ++a) {
+            s7.a[a] = st[a];
+            d7.a[a] = w.sst[a];
+        }
+        hipLaunchKernelGGL(k_copy_disp, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
+                           c->n_sys, w.off, w.grid, s7, d7, w.xref[0], w.xref[1],
+                           w.xref[2], w.summary);
+    } else if (n > 0) {
         hipLaunchKernelGGL(k_disp, dim3(std::min(blocks_for(n), 1024u)), dim3(BLOCK), 0,
                            c->stream, n,
                            c->n_sys, w.off, w.grid, st[0], st[1], st[2], w.xref[0],
                            w.xref[1], w.xref[2], w.summary);
+    }
     hipError_t e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary),
                                   hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

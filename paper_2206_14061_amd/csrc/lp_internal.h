@@ -357,9 +357,10 @@ namespace lp {
 // Morton sort of the input into the working copy, cell tables, neighbour
 // list with skin and reference positions.
 lp_status cells_build(lp_ctx* c, double* const st[7], int32_t* perm_out);
-// Copies the input into the working copy in the same order (no rebuild).
+// Copies the input into the working copy in the same order (no rebuild);
+// with arrays = false only the identity permutation is written.
 lp_status state_copy(lp_ctx* c, double* const st[7], int32_t* perm_out,
-                     const int32_t* gate = nullptr);
+                     const int32_t* gate = nullptr, bool arrays = true);
 // Re-sort + list rebuild entirely on the device, skipped unless *gate;
 // ids (optional) are permuted with the state; `bits` per grid axis.
 lp_status cells_build_device(lp_ctx* c, double* const st[7], int32_t* ids,
@@ -371,8 +372,11 @@ lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force);
 // Copies the working copy back into the caller's arrays.
 lp_status state_write_back(lp_ctx* c, double* const out[7]);
 // Largest displacement since the list build in units of the skin
-// (synchronises); returns a negative value when no list exists.
-lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio);
+// (synchronises); returns a negative value when no list exists.  With
+// copy, the same pass also copies st into the working copy (as
+// state_copy does) when a list exists.
+lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
+                            bool copy = false);
 // Mirror ids of the current state, stencil records.
 lp_status stencils_build(lp_ctx* c, const double* const st[7]);
 lp_status stencils_export(lp_ctx* c, const double* const st[7],
