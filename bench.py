@@ -56,10 +56,10 @@ LIST_ENTRIES = 77.5
 # and keep mask (32).
 SELECT_BYTES_PER_PARTICLE = 24 + 4 + 4 * LIST_ENTRIES + 24 + LIST_ENTRIES + 12 + 32
 # ... of the pass-2 kernel on a 60-row stencil: own state (56), P, eta and
-# flags (17), record and mask (44), the kept list entries (4 x 60), the
-# pass-1 hand-off (296), every neighbour's P, eta and position once (40),
-# the new state written (56).
-PASS2_BYTES_PER_PARTICLE = 56 + 17 + 44 + 4 * 60 + 296 + 40 + 56
+# flags (17), record and mask (44), the slot words of the kept rows
+# (2 x 60), the pass-1 hand-off (296), every neighbour's P, eta and
+# position once (40), the new state written (56).
+PASS2_BYTES_PER_PARTICLE = 56 + 17 + 44 + 2 * 60 + 296 + 40 + 56
 
 
 def _parse():
@@ -96,14 +96,14 @@ PASS1_SOURCES = ("paper_2206_14061_amd/csrc/lp_fit.hip",
                  "paper_2206_14061_amd/csrc/lp_visit.h",
                  "paper_2206_14061_amd/csrc/lp_internal.h",
                  "paper_2206_14061_amd/build.py")
-PASS1_PROFILE = "profiles/k_pass1_column_64x64x128.md"
+PASS1_PROFILE = "profiles/k_pass1_st_column_64x64x128.md"
 SELECT_SOURCES = ("paper_2206_14061_amd/csrc/lp_stencil.hip",
                   "paper_2206_14061_amd/csrc/lp_visit.h",
                   "paper_2206_14061_amd/csrc/lp_internal.h",
                   "paper_2206_14061_amd/build.py")
 SELECT_PROFILE = "profiles/k_select_column_64x64x128.md"
 PASS2_SOURCES = PASS1_SOURCES
-PASS2_PROFILE = "profiles/k_pass2_column_64x64x128.md"
+PASS2_PROFILE = "profiles/k_pass2_st_column_64x64x128.md"
 
 
 def sources_digest(paths) -> str:
@@ -527,7 +527,7 @@ def main():
     achieved = PASS1_FLOP_PER_PARTICLE * wl.n / t_pass1 / 1e12
     executed = PASS1_FLOP_EXECUTED * wl.n / t_pass1 / 1e12
     roofs = {
-        "pass1": {"kernel": ("k_pass1" if fp64 else "k_pass1_ref")
+        "pass1": {"kernel": ("k_pass1_st" if fp64 else "k_pass1_ref")
                             + " (fit of u, v, w + mu(I) closure)",
                   "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                   "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
@@ -540,7 +540,7 @@ def main():
     for ph, name, per, prof, src in (
             ("select", "k_select (exact candidate test, octant firsts, ghosts, keep mask)",
              SELECT_BYTES_PER_PARTICLE, SELECT_PROFILE, SELECT_SOURCES),
-            ("pass2", ("k_pass2" if fp64 else "k_pass2_ref")
+            ("pass2", ("k_pass2_st" if fp64 else "k_pass2_ref")
              + " (fit of P, eta; right-hand side; update)",
              PASS2_BYTES_PER_PARTICLE, PASS2_PROFILE, PASS2_SOURCES)):
         gbs = per * wl.n / (phases[ph] * 1e-3) / 1e9
@@ -551,10 +551,11 @@ def main():
                      "avg_launch_ms": phases[ph], "per_particle": per}
     roof = dict(roofs[dominant])
     roof["dominant_phase"] = dominant
-    # neighbour gathers of the two fits (48 B per row in pass 1: position
-    # and velocity; 40 B in pass 2: position, P and eta), over the mean
-    # kept rows of the column's stencils (ghost rows gather nothing); and
-    # the least-squares work of both fits at the survey's Householder count
+    # neighbour data the rows of the two fits consume (48 B per row in
+    # pass 1: position and velocity; 40 B in pass 2: position, P and eta;
+    # read from LDS in staged tiles), over the mean kept rows of the
+    # column's stencils (ghost rows read nothing); and the least-squares
+    # work of both fits at the survey's Householder count
     ctx_n = lp.make_context(wl)
     st_n = lp.DeviceState.from_host(wl.state)
     ctx_n.lp_build_cells(st_n, want_perm=False)
@@ -566,7 +567,7 @@ def main():
     qr_flop = sum(2 * rows * ncol * ncol - 2.0 * ncol ** 3 / 3 + k * (4 * rows * ncol - ncol * ncol)
                   for k in (3, 2))
     fit_rates = {"mean_stencil_rows": rows,
-                 "gathers_gbs": wl.n * rows * (48 + 40) / t_fit / 1e9,
+                 "row_data_gbs": wl.n * rows * (48 + 40) / t_fit / 1e9,
                  "qr_tflops": wl.n * qr_flop / t_fit / 1e12}
     out = {"metric": METRIC, "value": value, "unit": "particle-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

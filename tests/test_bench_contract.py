@@ -55,4 +55,4 @@ def test_traffic_records_follow_the_sources(tmp_path, monkeypatch):
 def test_algorithmic_bytes_per_particle():
     # 24 + 4 + 4 L + 24 + L + 12 + 32 with L = 77.5 list entries
     assert abs(bench.SELECT_BYTES_PER_PARTICLE - 483.5) < 1e-9
-    assert bench.PASS2_BYTES_PER_PARTICLE == 749
+    assert bench.PASS2_BYTES_PER_PARTICLE == 629
