@@ -346,7 +346,7 @@ lp_status lp_sync_status(lp_ctx* ctx, int64_t* index);
  * particles below the wall after updates, neighbour-list rebuilds by
  * lp_step; then resets them.  Entries 6 and 7 describe the current
  * neighbour list (0 when there is none): tiles of BLOCK = 256 consecutive
- * particles whose neighbours the fits cannot stage in LDS (more than 1536
+ * particles whose neighbours the fits cannot stage in LDS (more than 1664
  * distinct list sources, or LP_DEBUG_GLOBAL_GATHER), and all tiles.
  * Synchronises. */
 lp_status lp_stats(lp_ctx* ctx, int64_t* out8);

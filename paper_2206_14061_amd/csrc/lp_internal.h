@@ -25,7 +25,10 @@ constexpr int MASK_WORDS = VCAP / 64;  // keep bitmask words per particle
 // distinct sources of a tile's neighbour lists in LDS (at most STAGE_CAP
 // of them); a list entry names its source's slot in a 16-bit word whose
 // top bit marks a mirror entry.
-constexpr int STAGE_CAP = 1536;
+#ifndef LP_STAGE_CAP
+#define LP_STAGE_CAP 1664
+#endif
+constexpr int STAGE_CAP = LP_STAGE_CAP;
 constexpr uint32_t SLOT_MIRROR = 0x8000u;
 constexpr int32_t MBIT = 0x40000000;  // list entry: mirror of the real id
 constexpr int32_t NOID = 0x7FFFFFFF;

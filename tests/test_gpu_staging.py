@@ -59,7 +59,7 @@ def test_staged_wall_options(lp, opt):
 
 def test_staged_full_column(lp):
     """One step of the 64 x 64 x 128 column (524,288 particles): all but a
-    few tiles (at most 1 %, those with more than 1536 distinct list
+    few tiles (at most 1 %, those with more than 1664 distinct list
     sources) are staged, and the state equals the global-gather step's."""
     wl = lpgen.column_bench()
     print("case column_bench n", wl.n, flush=True)
