@@ -40,19 +40,12 @@ namespace {
 
 // List entries whose positions the selection gathers together.
 constexpr int SEL_BATCH = LP_SEL_BATCH;
-static_assert(SEL_BATCH % 4 == 0 && VCAP % SEL_BATCH == 0,
-              "selection batches cover whole bucket-code words");
+static_assert(SEL_BATCH % 4 == 0 && SEL_BATCH <= 8 && VCAP % SEL_BATCH == 0,
+              "selection batches cover whole bucket-code words and one mask byte");
 
 inline unsigned int blocks_for(int64_t n, int per = BLOCK)
 {
     return (unsigned int)((n + per - 1) / per);
-}
-
-__device__ __forceinline__ int cover_bit(double dx, double dy, double dz,
-                                         double margin)
-{
-    const bool far = fabs(dx) > margin && fabs(dy) > margin && fabs(dz) > margin;
-    return far ? 1 << ((dx > 0.0 ? 1 : 0) + (dy > 0.0 ? 2 : 0) + (dz > 0.0 ? 4 : 0)) : 0;
 }
 
 __device__ __forceinline__ void cell_clamp(const GridInfo& g, double x, double y,
@@ -281,6 +274,19 @@ struct Mask4 {
         else
             w3 |= b;
     }
+    // bits of `bits` at entries k0, k0 + 1, ... (k0 a multiple of 8)
+    __device__ __forceinline__ void set_bits(int k0, uint32_t bits)
+    {
+        const uint64_t b = (uint64_t)(bits & 0xFFu) << (k0 & 63);
+        if (k0 < 64)
+            w0 |= b;
+        else if (k0 < 128)
+            w1 |= b;
+        else if (k0 < 192)
+            w2 |= b;
+        else
+            w3 |= b;
+    }
     __device__ __forceinline__ bool has(int k) const
     {
         const uint64_t w = k < 64 ? w0 : (k < 128 ? w1 : (k < 192 ? w2 : w3));
@@ -366,30 +372,37 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
         uint32_t cw[SEL_BATCH / 4];
 #pragma unroll
         for (int w = 0; w < SEL_BATCH / 4; ++w) cw[w] = 0xFFFFFFFFu;
+        // Every entry of the batch takes the same instructions, predicated
+        // on being a candidate (no divergent branches): the histogram gets
+        // a no-return LDS add of 0 or 1, the other updates are selects.
+        uint32_t bm = 0;               // candidates among the batch
 #pragma unroll
         for (int u = 0; u < SEL_BATCH; ++u) {
             const Pt& p = pb[u];
-            if (k0 + u >= cnt || !p.valid) continue;
             const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
             const double d2 = dist2(dx, dy, dz);
-            if (d2 < R2) {
-                ++nc;
-                cm.set(k0 + u);
-                covered |= cover_bit(dx, dy, dz, margin);
-                const int oct = octant_of(dx, dy, dz);
-                const uint32_t b = (uint32_t)bucket_of(d2, scale);
-                const bool hiw = oct >= 4;
-                const uint32_t sh = 8u * (uint32_t)(oct & 3);
-                const uint32_t word = hiw ? mb_hi : mb_lo;
-                const uint32_t nw = b < ((word >> sh) & 0xFFu)
-                                        ? (word & ~(0xFFu << sh)) | (b << sh) : word;
-                mb_hi = hiw ? nw : mb_hi;
-                mb_lo = hiw ? mb_lo : nw;
-                hist_add(hist, (int)b, t, 1);
-                const uint32_t cs = 8u * (uint32_t)(u & 3);
-                cw[u >> 2] = (cw[u >> 2] & ~(0xFFu << cs)) | (b << cs);
-            }
+            const bool c = k0 + u < cnt && p.valid && d2 < R2;
+            nc += c ? 1 : 0;
+            bm |= c ? 1u << u : 0u;
+            // a candidate farther than margin (>= 0) from i on every axis
+            // covers its octant (no zero component, so octant_of is exact)
+            const int oct = octant_of(dx, dy, dz);
+            const bool far = fabs(dx) > margin && fabs(dy) > margin && fabs(dz) > margin;
+            covered |= (c && far) ? 1 << oct : 0;
+            const int bi = bucket_of(d2, scale);
+            const uint32_t b = (uint32_t)(bi < 0 ? 0 : bi);
+            const bool hiw = oct >= 4;
+            const uint32_t sh = 8u * (uint32_t)(oct & 3);
+            const uint32_t word = hiw ? mb_hi : mb_lo;
+            const uint32_t nw = (c && b < ((word >> sh) & 0xFFu))
+                                    ? (word & ~(0xFFu << sh)) | (b << sh) : word;
+            mb_hi = hiw ? nw : mb_hi;
+            mb_lo = hiw ? mb_lo : nw;
+            atomicAdd(&hist[b >> 2][t], (c ? 1u : 0u) << (8u * (b & 3u)));
+            const uint32_t cs = 8u * (uint32_t)(u & 3);
+            cw[u >> 2] = c ? (cw[u >> 2] & ~(0xFFu << cs)) | (b << cs) : cw[u >> 2];
         }
+        cm.set_bits(k0, bm);
 #pragma unroll
         for (int w = 0; w < SEL_BATCH / 4; ++w)
             if (k0 + 4 * w < cnt) code[(int64_t)((k0 >> 2) + w) * n + i] = cw[w];
