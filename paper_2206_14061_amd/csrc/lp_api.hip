@@ -79,7 +79,8 @@ void free_work(Work& w)
     for (int a = 0; a < 7; ++a) f(w.sst[a]);
     for (int a = 0; a < 3; ++a) f(w.xref[a]);
     f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
-    f(w.vl); f(w.vcnt); f(w.tile_src); f(w.tile_cnt); f(w.vs); f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
+    f(w.vl); f(w.vcnt); f(w.tile_src); f(w.tile_cnt); f(w.vs);
+    f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
     f(w.redo); f(w.redo_n); f(w.qr_scratch);
     f(w.P); f(w.eta); f(w.hand); f(w.uf);
     for (int a = 0; a < 7; ++a) f(w.adj[a]);

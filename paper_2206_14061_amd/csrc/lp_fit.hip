@@ -338,7 +338,9 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
 // per particle): the positions and velocities of the tile's list sources
 // are loaded once, coalesced, and every stencil row reads them from LDS.
 // A tile that is not staged, and a particle on the sorted path, read their
-// neighbours from global memory as k_pass1<1> does.
+// neighbours from global memory as k_pass1<1> does.  UNIT: the weights are
+// unit (known at compile time).
+template <bool UNIT>
 __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
                                                        int32_t* redo,
                                                        unsigned int* redo_n,
@@ -399,7 +401,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
     };
     int mt;
     if (S >= 0 && !(r.mode & MODE_SORTED)) {
-        mt = for_rows_staged<FIT_BATCH>(v, g, i, r, sx, sy, sz,
+        mt = for_rows_staged<FIT_BATCH, UNIT>(v, g, i, r, sx, sy, sz,
                                         [&](const double* a, double w, const Pt* p) {
             moments_add(M, a, w);
             if (!p) return;   // ghosts carry u_i (b = 0)
@@ -564,6 +566,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
 // source carries are loaded once, coalesced, and every stencil row reads
 // them from LDS.  A tile that is not staged, and a particle on the sorted
 // path, read their neighbours from global memory as k_pass2<1> does.
+// UNIT: the weights are unit (known at compile time).
+template <bool UNIT>
 __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
                                                     const double* eta,
                                                     const double* hand,
@@ -631,7 +635,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
         }
     };
     if (S >= 0 && !(r.mode & MODE_SORTED)) {
-        for_rows_staged<PASS2_BATCH>(v, g, i, r, sx, sy, sz,
+        for_rows_staged<PASS2_BATCH, UNIT>(v, g, i, r, sx, sy, sz,
                                      [&](const double* a, double w, const Pt* p) {
             if (!p) add_y(a, w, 0.0, 0.0);
             else if (p->mirror) add_y(a, w, sM[p->src], 0.0);
@@ -946,8 +950,12 @@ void launch_pass1(lp_ctx* c, int lpp, const View& v, const StepOut& so, int fq)
                            c->stream, v, so, w.redo, w.redo_n, fq);
         break;
     default:
-        hipLaunchKernelGGL(k_pass1_st, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                           c->stream, v, so, w.redo, w.redo_n, fq);
+        if (c->cfg.weight == LP_W_UNIT)
+            hipLaunchKernelGGL(k_pass1_st<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, so, w.redo, w.redo_n, fq);
+        else
+            hipLaunchKernelGGL(k_pass1_st<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, so, w.redo, w.redo_n, fq);
     }
 }
 
@@ -969,8 +977,12 @@ void launch_pass2(lp_ctx* c, int lpp, const View& v, const RhsOut& o)
                            c->stream, v, P, E, H, F, o);
         break;
     default:
-        hipLaunchKernelGGL(k_pass2_st, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                           c->stream, v, P, E, H, F, o);
+        if (c->cfg.weight == LP_W_UNIT)
+            hipLaunchKernelGGL(k_pass2_st<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, P, E, H, F, o);
+        else
+            hipLaunchKernelGGL(k_pass2_st<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, P, E, H, F, o);
     }
 }
 

@@ -257,7 +257,8 @@ __device__ __forceinline__ int for_rows(const View& v, const GridInfo& g,
 
 // for_rows for a particle of a staged tile: stencil rows from the LDS
 // copies (sx, sy, sz) through visit_staged, then the ghost rows.
-template <int B, class F>
+// UNIT: the weights are unit (LP_W_UNIT), so f receives the constant 1.
+template <int B, bool UNIT, class F>
 __device__ __forceinline__ int for_rows_staged(const View& v, const GridInfo& g,
                                                int64_t i, const Rec& r, const double* sx,
                                                const double* sy, const double* sz, F&& f)
@@ -268,7 +269,7 @@ __device__ __forceinline__ int for_rows_staged(const View& v, const GridInfo& g,
                     [&](const Pt& p, double dx, double dy, double dz) {
         double a[9];
         const double w = point_row(v, g, dx, dy, dz, a);
-        f(a, w, &p);
+        f(a, UNIT ? 1.0 : w, &p);
         ++m;
     });
 #pragma unroll
@@ -276,7 +277,7 @@ __device__ __forceinline__ int for_rows_staged(const View& v, const GridInfo& g,
         if ((r.gm >> o) & 1) {
             double a[9];
             const double w = ghost_row(v, g, o, a);
-            f(a, w, (const Pt*)nullptr);
+            f(a, UNIT ? 1.0 : w, (const Pt*)nullptr);
             ++m;
         }
     return m;
