@@ -99,16 +99,31 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
                     const int xx = nb_cell(cx, dx0, g.nx, px);
                     if (xx < 0) continue;
                     const int64_t c = row + xx;
-                    for (int32_t j = cs[c]; j < ce[c]; ++j) {
-                        if (!mirror && j == (int32_t)i) continue;
-                        const double dx = image_coord(x[j], qx, g.Lx, g.hLx) - qx;
-                        const double dy = image_coord(y[j], qy, g.Ly, g.hLy) - qy;
-                        const double dz = z[j] - qz;
-                        if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
-                        if (mirror && !(z[j] - g.wall < g.Rv)) continue;
-                        if (cnt < VCAP)
-                            vl[(int64_t)cnt * n + i] = mirror ? (j | MBIT) : j;
-                        ++cnt;
+                    const int32_t cb = cs[c], cend = ce[c];
+                    // four candidates' positions loaded together, then
+                    // tested in order
+                    for (int32_t j0 = cb; j0 < cend; j0 += 4) {
+                        double px[4], py[4], pz[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int32_t j = j0 + u < cend ? j0 + u : j0;
+                            px[u] = x[j];
+                            py[u] = y[j];
+                            pz[u] = z[j];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int32_t j = j0 + u;
+                            if (j >= cend || (!mirror && j == (int32_t)i)) continue;
+                            const double dx = image_coord(px[u], qx, g.Lx, g.hLx) - qx;
+                            const double dy = image_coord(py[u], qy, g.Ly, g.hLy) - qy;
+                            const double dz = pz[u] - qz;
+                            if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
+                            if (mirror && !(pz[u] - g.wall < g.Rv)) continue;
+                            if (cnt < VCAP)
+                                vl[(int64_t)cnt * n + i] = mirror ? (j | MBIT) : j;
+                            ++cnt;
+                        }
                     }
                 }
             }
