@@ -835,6 +835,8 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
     if (t == 0) full = disable;
     __syncthreads();
     for (int k = 0; k < cnt; ++k) {
+        // a full set ends the insertions (the tile is not staged)
+        if (*(volatile int*)&full) break;
         const int32_t j = vl[(int64_t)k * n + i] & ~MBIT;
         uint32_t h = src_hash(j);
         int probe = 0;
