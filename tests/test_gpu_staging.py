@@ -60,7 +60,8 @@ def test_staged_wall_options(lp, opt):
 def test_staged_full_column(lp):
     """One step of the 64 x 64 x 128 column (524,288 particles): all but a
     few tiles (at most 1 %, those with more than 1664 distinct list
-    sources) are staged, and the state equals the global-gather step's."""
+    sources) are staged, and the state agrees with the global-gather
+    step's to rounding."""
     wl = lpgen.column_bench()
     print("case column_bench n", wl.n, flush=True)
     got, st_s = _run(lp, wl, 1)
@@ -68,3 +69,37 @@ def test_staged_full_column(lp):
     _log("stats staged %s" % st_s)
     assert st_s["tiles"] == 2048 and st_s["unstaged_tiles"] <= 20
     _compare(got, ref, "column_bench")
+
+
+def test_mixed_staged_tiles(lp):
+    """A 24^3 column with h = 1.25 lattice spacings (about 145 list entries
+    per particle): some inner tiles have more than 1664 distinct list
+    sources and are not staged, the others are.  In one launch both kinds
+    match the global-gather step to rounding, and the step matches the
+    oracle's."""
+    import dataclasses
+
+    import oracle
+    import torch
+    from test_gpu_parity import _incr_ok
+
+    wl = lpgen.column_bench(nx=24, ny=24, nz=24)
+    h = wl.params[0].h * 1.25
+    wl.params = [dataclasses.replace(p, h=h, R=2.5 * h) for p in wl.params]
+    print("case column 24^3, h x1.25, n", wl.n, flush=True)
+    got, st_s = _run(lp, wl, 1)
+    ref, _ = _run(lp, wl, 1, debug_flags=lp.LP_DEBUG_GLOBAL_GATHER)
+    _log("stats %s" % st_s)
+    assert 0 < st_s["unstaged_tiles"] < st_s["tiles"]
+    _compare(got, ref, "mixed")
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    ctx.lp_step(st, wl.dt, perm)
+    ctx.sync_status()
+    ost, operm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt)
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = wl.state.take(operm)
+    for k, (a, b, c) in enumerate(zip(st.to_host().arrays(), ost.arrays(), old.arrays())):
+        ok, e = _incr_ok(a, b, c)
+        assert ok, (lp.DeviceState.NAMES[k], e)
