@@ -347,7 +347,10 @@ lp_status lp_sync_status(lp_ctx* ctx, int64_t* index);
  * lp_step; then resets them.  Entries 6 and 7 describe the current
  * neighbour list (0 when there is none): tiles of BLOCK = 256 consecutive
  * particles whose neighbours the fits cannot stage in LDS (more than 1664
- * distinct list sources, or LP_DEBUG_GLOBAL_GATHER), and all tiles.
+ * distinct list sources, LP_DEBUG_GLOBAL_GATHER, or every tile while the
+ * list has no tile map: the map is built by lp_step, lp_step2 and
+ * lp_step_graph, not by lp_build_cells or the adjoint entry points), and
+ * all tiles.
  * Synchronises. */
 lp_status lp_stats(lp_ctx* ctx, int64_t* out8);
 

@@ -146,6 +146,7 @@ lp_status step_device(lp_ctx* c, double* const in[7], int32_t* ids, double dt, i
     for (int a = 0; a < 7; ++a) cin[a] = in[a];
     lp_status r = rebuild_decision(c, cin, c->cfg.skin > 0.0 ? 0 : 1);
     if (r == LP_OK) r = cells_build_device(c, in, ids, c->w.gate, bits);
+    if (r == LP_OK) r = tile_map_build(c, c->w.gate);
     if (r == LP_OK) r = state_copy(c, in, nullptr, c->w.gate + 1);
     const double* sorted[7];
     for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
@@ -294,7 +295,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     w.cells_max = cells_max;
     w.m_max = mm;
     w.hist_cap = 256 * nb;
-    c->cells_ok = c->stencils_ok = c->list_ok = false;
+    c->cells_ok = c->stencils_ok = c->list_ok = c->map_ok = false;
     if (c->n_sys > 0) {
         // re-upload the systems into the new buffers
         std::vector<int64_t> off = c->h_off;
@@ -358,7 +359,7 @@ lp_status lp_set_systems(lp_ctx* c, int32_t n_sys, const int64_t* offsets,
         if (p.box_len[0] > 0.0 || p.box_len[1] > 0.0) c->periodic = true;
     c->n_sys = n_sys;
     c->n = offsets[n_sys];
-    c->cells_ok = c->stencils_ok = c->list_ok = false;
+    c->cells_ok = c->stencils_ok = c->list_ok = c->map_ok = false;
     if (c->w.n_max == 0) return LP_OK;   // uploaded by lp_reserve
     hipError_t e = hipMemcpyAsync(c->w.off, c->h_off.data(),
                                   sizeof(int64_t) * (n_sys + 1),
@@ -465,6 +466,7 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
         rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.49);
     }
     r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm, nullptr, false);
+    if (r == LP_OK && !c->map_ok) r = tile_map_build(c);
     prof_mark(c, 0, true);
     if (r != LP_OK) return r;
     if (rebuild) ++c->rebuilds;
@@ -516,6 +518,7 @@ lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
         rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.4);
     }
     r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm, nullptr, false);
+    if (r == LP_OK && !c->map_ok) r = tile_map_build(c);
     if (r != LP_OK) return r;
     if (rebuild) ++c->rebuilds;
     const double* sorted[7];
@@ -593,6 +596,12 @@ lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,
         r = cells_build(c, in, w.adj_perm);
         if (r == LP_OK) r = state_write_back(c, in);
         if (r == LP_OK && ids) r = permute_ids(c, w.adj_perm, ids);
+        if (r != LP_OK) return r;
+    }
+    // the captured steps keep list and tile map together; a list built
+    // since by another entry point gets its map here
+    if (!c->map_ok) {
+        r = tile_map_build(c);
         if (r != LP_OK) return r;
     }
     const int bits = std::min(16, c->axis_bits + 1);
@@ -828,7 +837,10 @@ lp_status lp_stats(lp_ctx* c, int64_t* out8)
     out8[5] = c->rebuilds + (int64_t)k.rebuilds;
     c->rebuilds = 0;
     // tiles of the current neighbour list, and those the fits cannot stage
-    if (c->list_ok && c->n > 0) {
+    if (c->list_ok && c->n > 0 && !c->map_ok) {
+        // no tile map for this list: the fits read every neighbour globally
+        out8[6] = out8[7] = (c->n + BLOCK - 1) / BLOCK;
+    } else if (c->list_ok && c->n > 0) {
         const int64_t tiles = (c->n + BLOCK - 1) / BLOCK;
         std::vector<int32_t> tc((size_t)tiles);
         e = hipMemcpy(tc.data(), c->w.tile_cnt, sizeof(int32_t) * tiles,

@@ -338,19 +338,20 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
 // per particle): the positions and velocities of the tile's list sources
 // are loaded once, coalesced, and every stencil row reads them from LDS.
 // A tile that is not staged, and a particle on the sorted path, read their
-// neighbours from global memory as k_pass1<1> does.  UNIT: the weights are
-// unit (known at compile time).
+// neighbours from global memory as k_pass1<1> does, and so does every
+// tile when the tile map is stale (map_ok = 0).  UNIT: the weights are unit
+// (known at compile time).
 template <bool UNIT>
 __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
                                                        int32_t* redo,
                                                        unsigned int* redo_n,
-                                                       int force_qr)
+                                                       int force_qr, int map_ok)
 {
     __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
     __shared__ double su[STAGE_CAP], sv[STAGE_CAP], sw[STAGE_CAP];
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
     const int64_t i = tile * BLOCK + threadIdx.x;
-    const int tc = v.tile_cnt[tile];
+    const int tc = map_ok ? v.tile_cnt[tile] : -1;
     const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
     if (S >= 0) {
         // all of this thread's sources at once: their ids, then their fields
@@ -565,19 +566,21 @@ __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
 // per particle): positions, P, eta and the pressure a mirror of each list
 // source carries are loaded once, coalesced, and every stencil row reads
 // them from LDS.  A tile that is not staged, and a particle on the sorted
-// path, read their neighbours from global memory as k_pass2<1> does.
-// UNIT: the weights are unit (known at compile time).
+// path, read their neighbours from global memory as k_pass2<1> does, and
+// so does every tile when the tile map is stale (map_ok = 0).  UNIT: the
+// weights are unit (known at compile time).
 template <bool UNIT>
 __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
                                                     const double* eta,
                                                     const double* hand,
-                                                    const uint8_t* flags, RhsOut o)
+                                                    const uint8_t* flags, RhsOut o,
+                                                    int map_ok)
 {
     __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
     __shared__ double sP[STAGE_CAP], sE[STAGE_CAP], sM[STAGE_CAP];
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
     const int64_t i = tile * BLOCK + threadIdx.x;
-    const int tc = v.tile_cnt[tile];
+    const int tc = map_ok ? v.tile_cnt[tile] : -1;
     const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
     if (S >= 0) {
         // all of this thread's sources at once: their ids, then their fields
@@ -952,10 +955,10 @@ void launch_pass1(lp_ctx* c, int lpp, const View& v, const StepOut& so, int fq)
     default:
         if (c->cfg.weight == LP_W_UNIT)
             hipLaunchKernelGGL(k_pass1_st<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, so, w.redo, w.redo_n, fq);
+                               c->stream, v, so, w.redo, w.redo_n, fq, c->map_ok ? 1 : 0);
         else
             hipLaunchKernelGGL(k_pass1_st<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, so, w.redo, w.redo_n, fq);
+                               c->stream, v, so, w.redo, w.redo_n, fq, c->map_ok ? 1 : 0);
     }
 }
 
@@ -979,10 +982,10 @@ void launch_pass2(lp_ctx* c, int lpp, const View& v, const RhsOut& o)
     default:
         if (c->cfg.weight == LP_W_UNIT)
             hipLaunchKernelGGL(k_pass2_st<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, P, E, H, F, o);
+                               c->stream, v, P, E, H, F, o, c->map_ok ? 1 : 0);
         else
             hipLaunchKernelGGL(k_pass2_st<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, P, E, H, F, o);
+                               c->stream, v, P, E, H, F, o, c->map_ok ? 1 : 0);
     }
 }
 

@@ -215,6 +215,7 @@ struct lp_ctx {
     std::vector<int64_t> h_off;
     std::vector<lp_params> h_prm;
     bool periodic = false;                // some system has a periodic axis
+    bool map_ok = false;                  // the tile map matches the current list
     lp::Work w;
     int axis_bits = 0;
     int64_t total_cells = 0;
@@ -388,6 +389,10 @@ lp_status stencils_export(lp_ctx* c, const double* const st[7],
                           int32_t* sten_idx, uint8_t* ghost_mask,
                           int64_t* n_mirror);
 lp_status list_build(lp_ctx* c, const int32_t* gate = nullptr);
+// Tile map of the current list (the fits' LDS staging); skipped unless
+// *gate when gate is given.  A new list leaves the fits on global
+// gathers until this is called.
+lp_status tile_map_build(lp_ctx* c, const int32_t* gate = nullptr);
 lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
                       int k, const int32_t* msign, const int32_t* gzero,
                       double* coef, uint8_t* flags);

@@ -913,13 +913,30 @@ lp_status list_build(lp_ctx* c, const int32_t* gate)
         hipLaunchKernelGGL(k_list_build, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
                            w.sst[2], w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "list build launch");
+    c->list_ok = true;
+    // an eager build leaves the tile map stale (captured steps rebuild the
+    // map under the same gate right after the list)
+    if (!gate) c->map_ok = false;
+    return LP_OK;
+}
+
+lp_status tile_map_build(lp_ctx* c, const int32_t* gate)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    if (!c->list_ok) {
+        c->err = "the neighbour list has not been built";
+        return LP_E_STATE;
+    }
     if (n > 0)
         hipLaunchKernelGGL(k_tile_map, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream,
                            n, w.vl, w.vcnt, w.tile_src, w.tile_cnt, w.vs,
                            (c->cfg.debug_flags & LP_DEBUG_GLOBAL_GATHER) ? 1 : 0, gate);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(c, e, "list build launch");
-    c->list_ok = true;
+    if (e != hipSuccess) return hip_fail(c, e, "tile map launch");
+    c->map_ok = true;
     return LP_OK;
 }
 
