@@ -446,7 +446,7 @@ struct Dest7 {
 };
 
 // k_disp fused with the copy of the seven state arrays into the working
-// state (one pass over the state; one thread per particle).
+// state (one pass over the state).
 __global__ __launch_bounds__(BLOCK) void k_copy_disp(int64_t n, int n_sys,
                                                      const int64_t* off,
                                                      const GridInfo* grid, State7 st,
@@ -455,9 +455,11 @@ __global__ __launch_bounds__(BLOCK) void k_copy_disp(int64_t n, int n_sys,
                                                      Summary* sum)
 {
     __shared__ double part[BLOCK / 64];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double r = 0.0;
-    if (i < n) {
+    // grid-stride over particles (a few hundred blocks, so that few blocks
+    // contend for the one atomic below)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
         double f[7];
 #pragma unroll
         for (int a = 0; a < 7; ++a) f[a] = st.a[a][i];
@@ -468,8 +470,9 @@ __global__ __launch_bounds__(BLOCK) void k_copy_disp(int64_t n, int n_sys,
         const double dy = image_coord(f[1], ry[i], g.Ly, g.hLy) - ry[i];
         const double dz = f[2] - rz[i];
         const double d2 = dx * dx + dy * dy + dz * dz;
-        r = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
-        if (!(r == r)) r = INFINITY;   // non-finite positions force a rebuild
+        double q = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
+        if (!(q == q)) q = INFINITY;   // non-finite positions force a rebuild
+        r = fmax(r, q);
     }
     for (int d = 32; d > 0; d >>= 1) r = fmax(r, __shfl_xor(r, d));
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = r;
@@ -709,7 +712,8 @@ lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
             s7.a[a] = st[a];
             d7.a[a] = w.sst[a];
         }
-        hipLaunchKernelGGL(k_copy_disp, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
+        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), 512u)), dim3(BLOCK), 0,
+                           c->stream, n,
                            c->n_sys, w.off, w.grid, s7, d7, w.xref[0], w.xref[1],
                            w.xref[2], w.summary);
     } else if (n > 0) {
