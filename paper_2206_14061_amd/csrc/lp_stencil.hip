@@ -171,17 +171,40 @@ __device__ __forceinline__ bool wall_flag(const int64_t* off, int n_sys,
     return dsub(z[i], g.wall) < g.R;
 }
 
+// Wall flags of the SORT_ITEMS particles b, b + 1, ... of one thread (0
+// past n), loaded together; the system is looked up once when all of them
+// share one.
+__device__ __forceinline__ uint32_t wall_flags(int64_t n, int n_sys, const int64_t* off,
+                                               const GridInfo* grid, const double* z,
+                                               int64_t b)
+{
+    static_assert(SORT_ITEMS <= 32, "one flag bit per item");
+    const int64_t last = b + SORT_ITEMS - 1 < n ? b + SORT_ITEMS - 1 : n - 1;
+    uint32_t bits = 0;
+    if (b >= n) return 0;
+    const int s0 = sys_of(off, n_sys, b);
+    if (s0 == sys_of(off, n_sys, last)) {
+        const double wall = grid[s0].wall, R = grid[s0].R;
+        double zz[SORT_ITEMS];
+#pragma unroll
+        for (int r = 0; r < SORT_ITEMS; ++r) zz[r] = b + r < n ? z[b + r] : INFINITY;
+#pragma unroll
+        for (int r = 0; r < SORT_ITEMS; ++r)
+            bits |= (dsub(zz[r], wall) < R ? 1u : 0u) << r;
+    } else {
+        for (int r = 0; r < SORT_ITEMS; ++r)
+            if (b + r < n && wall_flag(off, n_sys, grid, z, b + r)) bits |= 1u << r;
+    }
+    return bits;
+}
+
 __global__ void k_mirror_count(int64_t n, int n_sys, const int64_t* off,
                                const GridInfo* grid, const double* z,
                                int32_t* bsum)
 {
     __shared__ uint32_t wsum[BLOCK / 64];
     const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
-    uint32_t c = 0;
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        const int64_t i = b + r;
-        if (i < n && wall_flag(off, n_sys, grid, z, i)) ++c;
-    }
+    const uint32_t c = __popc(wall_flags(n, n_sys, off, grid, z, b));
     uint32_t tot;
     block_excl_scan(c, wsum, tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = (int32_t)tot;
@@ -222,17 +245,14 @@ __global__ void k_mirror_write(int64_t n, int n_sys, const int64_t* off,
 {
     __shared__ uint32_t wsum[BLOCK / 64];
     const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
-    uint32_t c = 0;
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        const int64_t i = b + r;
-        if (i < n && wall_flag(off, n_sys, grid, z, i)) ++c;
-    }
+    const uint32_t bits = wall_flags(n, n_sys, off, grid, z, b);
     uint32_t tot;
-    uint32_t k = block_excl_scan(c, wsum, tot) + (uint32_t)bsum[blockIdx.x];
+    uint32_t k = block_excl_scan(__popc(bits), wsum, tot) + (uint32_t)bsum[blockIdx.x];
+#pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const int64_t i = b + r;
         if (i >= n) break;
-        if (wall_flag(off, n_sys, grid, z, i)) {
+        if ((bits >> r) & 1u) {
             mirror_of[i] = (int32_t)k;
             msrc[k] = (int32_t)i;
             ++k;
