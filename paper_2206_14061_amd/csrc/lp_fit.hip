@@ -243,6 +243,9 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic_qr(
 // Staged sources per thread of a block, and this thread's source ids in
 // the tile (slot threadIdx.x + u BLOCK; -1 past the tile's S sources).
 constexpr int STAGE_PER = (STAGE_CAP + BLOCK - 1) / BLOCK;
+// six staged FP64 fields per source; two blocks must fit one CU's 160 KB
+static_assert(2 * 6 * STAGE_CAP * (int)sizeof(double) <= 160 * 1024,
+              "two staged fit blocks per CU");
 
 __device__ __forceinline__ void stage_ids(const View& v, int64_t tile, int S,
                                           int32_t (&js)[STAGE_PER])
