@@ -38,9 +38,9 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 # Algorithmic work of the pass-1 kernel per particle (fit of u, v, w on a
-# 60-row, 9-column stencil plus closure), from the survey's count for a
-# Householder least-squares solve: 0.5k row build + 9.2k QR + 3 x 2.1k
-# (Q^T b and back substitution) + 0.2k closure.
+# 60-row, 9-column stencil plus closure), counted as for a Householder
+# least-squares solve: 0.5k row build + 9.2k QR (2 m n^2 - 2 n^3 / 3) +
+# 3 x 2.1k (Q^T b and back substitution) + 0.2k closure.
 PASS1_FLOP_PER_PARTICLE = 16.2e3
 # What the kernel actually executes per particle with 60 stencil rows:
 # 60 x (45 Gram + 27 moment FMAs = 144 flop + 12 row flop) + ~1.4k for the
@@ -555,7 +555,8 @@ def main():
     # pass 1: position and velocity; 40 B in pass 2: position, P and eta;
     # read from LDS in staged tiles), over the mean kept rows of the
     # column's stencils (ghost rows read nothing); and the least-squares
-    # work of both fits at the survey's Householder count
+    # work of both fits at the Householder count (2 m n^2 - 2 n^3 / 3 for
+    # the factor, 4 m n - n^2 per right-hand side)
     ctx_n = lp.make_context(wl)
     st_n = lp.DeviceState.from_host(wl.state)
     ctx_n.lp_build_cells(st_n, want_perm=False)
