@@ -133,3 +133,44 @@ def test_ensemble_systems_evolve_as_if_alone(lp):
         for k, (x, y) in enumerate(zip(full.arrays(), alone.arrays())):
             assert np.array_equal(x[a:b], y), (c, k)
         _log("  column %d (%d particles): identical" % (c, b - a))
+
+
+def test_graph_replay_after_a_list_without_tile_map(lp):
+    """lp_build_cells between replays builds a new list without a tile map;
+    the next replay (no recapture) first builds the map for it, so the
+    captured staged fits read the current list: replay, re-sort, replay
+    equals the same eager sequence exactly."""
+    import torch
+    wl = CASES["column16_flow_ragged"]()
+    k = 4
+
+    def run(graph):
+        ctx = lp.make_context(wl)
+        st = lp.DeviceState.from_host(wl.state)
+        ids = torch.arange(wl.n, dtype=torch.int32, device="cuda")
+        perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+
+        def steps():
+            nonlocal ids
+            if graph:
+                ctx.lp_step_graph(st, wl.dt, k, ids)
+            else:
+                for _ in range(k):
+                    ctx.lp_step(st, wl.dt, perm)
+                    ids = ids[perm.long()]
+
+        steps()
+        ids = ids[ctx.lp_build_cells(st).long()]
+        # the new list has no tile map yet
+        s = ctx.stats()
+        assert s["unstaged_tiles"] == s["tiles"] > 0
+        steps()
+        ctx.sync_status()
+        stats = ctx.stats()
+        return _by_id(st, ids.cpu().numpy()), stats
+
+    got, gstats = run(True)
+    want, wstats = run(False)
+    _log("graph %s / eager %s" % (gstats, wstats))
+    assert gstats["unstaged_tiles"] == 0 and wstats["unstaged_tiles"] == 0
+    assert _same(got, want)
