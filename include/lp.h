@@ -356,10 +356,11 @@ lp_status lp_stats(lp_ctx* ctx, int64_t* out8);
 
 /* Phase timing (instrumentation).  lp_profile(ctx, 1) makes lp_step
  * record HIP events on the context's stream around its kernel groups:
- * 0 displacement check and re-sort + list rebuild or state copy, 1 mirrors
- * and stencil selection (k_select), 2 exact sorted-stencil path, 3 pass-1
- * fit + closure (k_pass1), 4 pass-1 QR refits, 5 pass-2 fit + RHS +
- * update (k_pass2), 6 pass-2 QR refits; each lp_step then
+ * 0 displacement check and re-sort + list rebuild (with its tile map) or
+ * state copy, 1 stencil selection (k_select alone; the mirror kernels
+ * before it are in no phase), 2 exact sorted-stencil path, 3 pass-1 fit +
+ * closure (k_pass1_st), 4 pass-1 QR refits, 5 pass-2 fit + RHS + update
+ * (k_pass2_st), 6 pass-2 QR refits; each lp_step then
  * waits for its last event.  lp_profile_read (host double[8], int64 steps)
  * returns the summed milliseconds per phase and the number of profiled
  * steps, then resets them.  lp_profile(ctx, 0) stops recording. */
