@@ -271,6 +271,30 @@ def cubic_bench(torch, lp, wl, steps: int, warmup: int):
                      "unit": "particle-updates/s",
                      "phases_ms": {k: v / nst for k, v in ph.items()}}
     out["cost_vs_quadratic"] = out["cubic"]["ms_per_step"] / out["quadratic"]["ms_per_step"]
+    # roofline of the two cubic fits against the FP64 vector peak: Householder
+    # QR of the m x 19 row matrix (2 m n^2 - 2 n^3 / 3) in each pass, with 3
+    # right-hand sides in pass 1 and 2 in pass 2 (4 m n - n^2 each), m the
+    # mean rows (kept stencil rows plus ghost rows at m_max 56)
+    ctx = lp.make_context(wl, fit_order=3, m_max=56)
+    st = lp.DeviceState.from_host(wl.state)
+    ctx.lp_build_cells(st, want_perm=False)
+    nb = ctx.lp_neighbors(st, candidates=False, ghosts=True)
+    ghosts = torch.zeros_like(nb["ghost_mask"], dtype=torch.int64)
+    gm = nb["ghost_mask"].to(torch.int64)
+    for o in range(8):
+        ghosts += (gm >> o) & 1
+    m = float((nb["sten_cnt"].to(torch.float64) + ghosts.to(torch.float64)).mean().item())
+    del ctx, st, nb
+    ncol = 19
+    flop = (2 * (2 * m * ncol * ncol - 2.0 * ncol ** 3 / 3)
+            + 5 * (4 * m * ncol - ncol * ncol))
+    ph = out["cubic"]["phases_ms"]
+    t = (ph["pass1"] + ph["pass2"]) * 1e-3
+    achieved = flop * wl.n / t / 1e12
+    out["roofline"] = {"kernel": "k_pass1_cubic + k_pass2_cubic (16 lanes per particle)",
+                       "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                       "traffic": None, "mean_rows": m, "per_particle": flop}
     return out
 
 
