@@ -189,6 +189,7 @@ __device__ __forceinline__ double group_house(int sl, int m, double (&a)[SLOTS][
         const double alpha = ajj >= 0.0 ? -nrm : nrm;
         if (sl == j % GROUP) a[j / GROUP][j] = ajj - alpha;
         const double vtv = 2.0 * nrm * (nrm + fabs(ajj));
+        const double s2 = 2.0 / vtv;   // one division per column step
         double vj[SLOTS];
 #pragma unroll
         for (int q = 0; q < SLOTS; ++q) vj[q] = act[q] ? a[q][j] : 0.0;
@@ -197,20 +198,20 @@ __device__ __forceinline__ double group_house(int sl, int m, double (&a)[SLOTS][
             double d = 0.0;
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) d += vj[q] * a[q][l];
-            const double f = 2.0 * group_sum(d) / vtv;
+            const double f = group_sum(d) * s2;
+            // vj is 0 on the inactive rows, which the update leaves as
+            // they are
 #pragma unroll
-            for (int q = 0; q < SLOTS; ++q)
-                if (act[q]) a[q][l] -= f * vj[q];
+            for (int q = 0; q < SLOTS; ++q) a[q][l] -= f * vj[q];
         }
 #pragma unroll
         for (int l = 0; l < NF; ++l) {
             double d = 0.0;
 #pragma unroll
             for (int q = 0; q < SLOTS; ++q) d += vj[q] * b[q][l];
-            const double f = 2.0 * group_sum(d) / vtv;
+            const double f = group_sum(d) * s2;
 #pragma unroll
-            for (int q = 0; q < SLOTS; ++q)
-                if (act[q]) b[q][l] -= f * vj[q];
+            for (int q = 0; q < SLOTS; ++q) b[q][l] -= f * vj[q];
         }
         if (sl == j % GROUP) rdiag[j / GROUP] = alpha;
         const double ar = fabs(alpha);
@@ -230,14 +231,16 @@ __device__ __forceinline__ void group_backsolve(const double (&a)[SLOTS][NC3],
 {
 #pragma unroll
     for (int q = 0; q < NC3; ++q) x[q] = 0.0;
+    double rinv[SLOTS];
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) rinv[q] = rdiag[q] != 0.0 ? 1.0 / rdiag[q] : 0.0;
     static_for<0, NC>([&](auto K) {
         constexpr int c = NC - 1 - decltype(K)::value;
         // computed in every lane; the lane holding row c has the right one
         double acc = b[c / GROUP][f];
 #pragma unroll
         for (int q = c + 1; q < NC; ++q) acc -= a[c / GROUP][q] * x[q];
-        const double rc = rdiag[c / GROUP];
-        x[c] = group_bcast<c % GROUP>(rc != 0.0 ? acc / rc : 0.0);
+        x[c] = group_bcast<c % GROUP>(acc * rinv[c / GROUP]);
     });
 }
 
