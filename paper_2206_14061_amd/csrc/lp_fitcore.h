@@ -68,8 +68,9 @@ __device__ __forceinline__ void point_velocity(const View& v, const Pt& p,
     w = p.mirror ? -v.w[p.src] : v.w[p.src];
 }
 
-// G = U^T U in place (packed upper); returns min U_jj / max U_jj, or -1
-// when a pivot is not positive.
+// G = U^T U in place (packed upper, with 1 / U_jj stored on the diagonal
+// for chol_solve); returns min U_jj / max U_jj, or -1 when a pivot is not
+// positive.
 template <int N, class T>
 __device__ __forceinline__ T cholesky(T (&G)[45])
 {
@@ -82,7 +83,7 @@ __device__ __forceinline__ T cholesky(T (&G)[45])
         if (!(s > T(0))) return T(-1);
         const T d = sqrt(s);
         const T inv = T(1) / d;
-        G[uix(j, j)] = d;
+        G[uix(j, j)] = inv;   // the solves multiply by the reciprocal pivot
         dmin = fmin(dmin, d);
         dmax = fmax(dmax, d);
 #pragma unroll
@@ -96,7 +97,8 @@ __device__ __forceinline__ T cholesky(T (&G)[45])
     return dmin / dmax;
 }
 
-// Solves U^T U c = b in place (b -> c).
+// Solves U^T U c = b in place (b -> c); U as cholesky leaves it (reciprocal
+// pivots on the diagonal).
 template <int N, class T>
 __device__ __forceinline__ void chol_solve(const T (&U)[45], T (&b)[9])
 {
@@ -105,14 +107,14 @@ __device__ __forceinline__ void chol_solve(const T (&U)[45], T (&b)[9])
         T t = b[j];
 #pragma unroll
         for (int k = 0; k < j; ++k) t -= U[uix(k, j)] * b[k];
-        b[j] = t / U[uix(j, j)];
+        b[j] = t * U[uix(j, j)];
     }
 #pragma unroll
     for (int j = N - 1; j >= 0; --j) {
         T t = b[j];
 #pragma unroll
         for (int k = j + 1; k < N; ++k) t -= U[uix(j, k)] * b[k];
-        b[j] = t / U[uix(j, j)];
+        b[j] = t * U[uix(j, j)];
     }
 }
 
