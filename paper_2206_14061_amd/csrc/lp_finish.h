@@ -78,9 +78,10 @@ __device__ __forceinline__ void finish_rhs(const View& v, const lp_params& p,
     const double t0 = gd[0] * gE[0] + gd[3] * gE[1] + gd[4] * gE[2];
     const double t1 = gd[3] * gE[0] + gd[1] * gE[1] + gd[5] * gE[2];
     const double t2 = gd[4] * gE[0] + gd[5] * gE[1] + gd[2] * gE[2];
-    a[0] = V * (-gP[0] + t0 + eta * vis[0]) / p.rho_s + p.g[0];
-    a[1] = V * (-gP[1] + t1 + eta * vis[1]) / p.rho_s + p.g[1];
-    a[2] = V * (-gP[2] + t2 + eta * vis[2]) / p.rho_s + p.g[2];
+    const double inv_rho = 1.0 / p.rho_s;
+    a[0] = V * (-gP[0] + t0 + eta * vis[0]) * inv_rho + p.g[0];
+    a[1] = V * (-gP[1] + t1 + eta * vis[1]) * inv_rho + p.g[1];
+    a[2] = V * (-gP[2] + t2 + eta * vis[2]) * inv_rho + p.g[2];
     const double dV = V * div;
     if (o.acc) {
         o.acc[i] = a[0];

@@ -610,14 +610,19 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
             sP[q] = f[3][u];
             sE[q] = f[4][u];
             // what a mirror of j carries (pass2_values); j's system is
-            // that of every particle listing it
+            // that of every particle listing it.  Only a source within R
+            // of the wall has a mirror (the rule that sets mirror_of).
             const int sj = sys_of(v.off, v.n_sys, j);
-            Pt m;
-            m.mirror = true;
-            m.src = j;
-            m.z = dsub(dmul(2.0, v.grid[sj].wall), f[2][u]);
-            double pm, em;
-            pass2_values(v, P, eta, &m, v.prm[sj], pm, em);
+            const GridInfo& gj = v.grid[sj];
+            double pm = 0.0;
+            if (dsub(f[2][u], gj.wall) < gj.R) {
+                Pt m;
+                m.mirror = true;
+                m.src = j;
+                m.z = dsub(dmul(2.0, gj.wall), f[2][u]);
+                double em;
+                pass2_values(v, P, eta, &m, v.prm[sj], pm, em);
+            }
             sM[q] = pm;
         }
         __syncthreads();
