@@ -854,18 +854,29 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
     for (int h = t; h < HASH_SIZE; h += BLOCK) hkey[h] = -1;
     if (t == 0) full = disable;
     __syncthreads();
-    for (int k = 0; k < cnt; ++k) {
+    // list words are loaded MAP_BATCH at a time (one memory latency per
+    // batch instead of per entry)
+    constexpr int MAP_BATCH = 8;
+    for (int k0 = 0; k0 < cnt; k0 += MAP_BATCH) {
         // a full set ends the insertions (the tile is not staged)
         if (*(volatile int*)&full) break;
-        const int32_t j = vl[(int64_t)k * n + i] & ~MBIT;
-        uint32_t h = src_hash(j);
-        int probe = 0;
-        for (; probe < HASH_SIZE; ++probe) {
-            const int32_t old = atomicCAS(&hkey[h], -1, j);
-            if (old == -1 || old == j) break;
-            h = (h + 1) & (HASH_SIZE - 1);
+        int32_t jb[MAP_BATCH];
+#pragma unroll
+        for (int u = 0; u < MAP_BATCH; ++u)
+            jb[u] = k0 + u < cnt ? vl[(int64_t)(k0 + u) * n + i] & ~MBIT : -1;
+#pragma unroll
+        for (int u = 0; u < MAP_BATCH; ++u) {
+            const int32_t j = jb[u];
+            if (j < 0) continue;
+            uint32_t h = src_hash(j);
+            int probe = 0;
+            for (; probe < HASH_SIZE; ++probe) {
+                const int32_t old = atomicCAS(&hkey[h], -1, j);
+                if (old == -1 || old == j) break;
+                h = (h + 1) & (HASH_SIZE - 1);
+            }
+            if (probe == HASH_SIZE) full = 1;
         }
-        if (probe == HASH_SIZE) full = 1;
     }
     __syncthreads();
     // compact: thread t takes hash slots [t PER, (t + 1) PER)
@@ -912,11 +923,19 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
     }
     if (t == 0) tile_cnt[tile] = S;
     __syncthreads();
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t e = vl[(int64_t)k * n + i];
-        const int h = hash_find(hkey, e & ~MBIT);
-        const uint32_t q = h >= 0 ? hslot[h] : 0u;
-        vs[(int64_t)k * n + i] = (uint16_t)(q | ((e & MBIT) ? SLOT_MIRROR : 0u));
+    for (int k0 = 0; k0 < cnt; k0 += MAP_BATCH) {
+        int32_t eb[MAP_BATCH];
+#pragma unroll
+        for (int u = 0; u < MAP_BATCH; ++u)
+            eb[u] = k0 + u < cnt ? vl[(int64_t)(k0 + u) * n + i] : 0;
+#pragma unroll
+        for (int u = 0; u < MAP_BATCH; ++u) {
+            if (k0 + u >= cnt) continue;
+            const int32_t e = eb[u];
+            const int h = hash_find(hkey, e & ~MBIT);
+            const uint32_t q = h >= 0 ? hslot[h] : 0u;
+            vs[(int64_t)(k0 + u) * n + i] = (uint16_t)(q | ((e & MBIT) ? SLOT_MIRROR : 0u));
+        }
     }
 }
 
