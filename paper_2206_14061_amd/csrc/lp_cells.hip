@@ -261,29 +261,67 @@ __global__ void k_radix_hist(const unsigned long long* keys, int64_t n,
 }
 
 // Exclusive scan in place of a uint32 array (single block of 1024).
-__global__ void k_scan_u32(uint32_t* a, int64_t total, const int32_t* gate)
+// In-place exclusive prefix sum of a[0, total) by one block of 1024
+// threads, SCAN_TILE values at a time: a tile is loaded coalesced into LDS
+// (padded against bank conflicts), each thread scans SCAN_PER consecutive
+// values, the block scans the thread sums, and the tile is written back
+// coalesced with the running total of the tiles before it added.
+constexpr int SCAN_THREADS = 1024, SCAN_PER = 8, SCAN_TILE = SCAN_THREADS * SCAN_PER;
+
+__device__ __forceinline__ int scan_pad(int q) { return q + (q >> 5); }
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_u32(uint32_t* a, int64_t total,
+                                                           const int32_t* gate)
 {
     LP_GATE(gate);
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t chunk = (total + 1023) / 1024;
-    const int64_t b = t * chunk;
-    const int64_t e = (b + chunk < total) ? b + chunk : total;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += a[i];
-    part[t] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        uint32_t v = t >= d ? part[t - d] : 0u;
+    __shared__ uint32_t buf[SCAN_TILE + SCAN_TILE / 32];
+    __shared__ uint32_t wsum[SCAN_THREADS / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < total; base += SCAN_TILE) {
+        uint32_t v[SCAN_PER];
+#pragma unroll
+        for (int r = 0; r < SCAN_PER; ++r) {
+            const int64_t q = base + t + (int64_t)r * SCAN_THREADS;
+            v[r] = q < total ? a[q] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < SCAN_PER; ++r) buf[scan_pad(t + r * SCAN_THREADS)] = v[r];
         __syncthreads();
-        part[t] += v;
+        uint32_t loc[SCAN_PER];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int r = 0; r < SCAN_PER; ++r) {
+            loc[r] = buf[scan_pad(t * SCAN_PER + r)];
+            sum += loc[r];
+        }
+        // exclusive scan of the thread sums: within each wave, then across
+        uint32_t inc = sum;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(inc, d);
+            if (lane >= d) inc += o;
+        }
+        if (lane == 63) wsum[wave] = inc;
         __syncthreads();
-    }
-    uint32_t run = part[t] - s;
-    for (int64_t i = b; i < e; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+        uint32_t pre = carry + inc - sum, tile_total = 0;
+        for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+            if (w < wave) pre += wsum[w];
+            tile_total += wsum[w];
+        }
+#pragma unroll
+        for (int r = 0; r < SCAN_PER; ++r) {
+            buf[scan_pad(t * SCAN_PER + r)] = pre;
+            pre += loc[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SCAN_PER; ++r) {
+            const int ql = t + r * SCAN_THREADS;
+            const int64_t q = base + ql;
+            if (q < total) a[q] = buf[scan_pad(ql)];
+        }
+        carry += tile_total;
+        __syncthreads();   // buf and wsum are reused by the next tile
     }
 }
 
@@ -504,7 +542,7 @@ void radix_sort(lp_ctx* c, int64_t cnt, int bits, unsigned long long*& kr,
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(BLOCK), 0,
                            c->stream, kin, cnt, shift, w.hist, nblk, gate);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream,
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(SCAN_THREADS), 0, c->stream,
                            w.hist, 256 * nblk, gate);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(BLOCK),
                            0, c->stream, kin, vin, kout, vout, cnt, shift,
