@@ -52,14 +52,16 @@ __global__ void k_bbox(int64_t n, int n_sys, const int64_t* off,
                        unsigned long long* bbox, const int32_t* gate)
 {
     LP_GATE(gate);
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t b = t * BBOX_CHUNK;
+    // block b covers BLOCK x BBOX_CHUNK consecutive particles; thread t
+    // takes every BLOCK-th of them from b's start + t (coalesced loads, and
+    // increasing indices, so the systems it meets come in order)
+    const int64_t b = (int64_t)blockIdx.x * BLOCK * BBOX_CHUNK + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int cur = -1;
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     if (b < n) {
-        const int64_t e = (b + BBOX_CHUNK < n) ? b + BBOX_CHUNK : n;
-        for (int64_t i = b; i < e; ++i) {
+        const int64_t e = b + (int64_t)BLOCK * BBOX_CHUNK;
+        for (int64_t i = b; i < e && i < n; i += BLOCK) {
             int s = cur;
             if (s < 0 || i >= off[s + 1]) s = sys_of(off, n_sys, i);
             if (s != cur) {
