@@ -81,7 +81,7 @@ void free_work(Work& w)
     f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
     f(w.vl); f(w.vcnt); f(w.tile_src); f(w.tile_cnt); f(w.vs);
     f(w.code); f(w.rec); f(w.kmask); f(w.hsten); f(w.hard); f(w.hard_n);
-    f(w.redo); f(w.redo_n); f(w.qr_scratch);
+    f(w.redo); f(w.redo_n);
     f(w.P); f(w.eta); f(w.hand); f(w.uf);
     for (int a = 0; a < 7; ++a) f(w.adj[a]);
     f(w.adj_P); f(w.adj_E); f(w.adj_stash); f(w.coefu); f(w.adj_perm);
@@ -261,7 +261,6 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     A(w.rec, (int64_t)REC_FIELDS * n_max); A(w.hsten, (int64_t)mm * n_max);
     A(w.hard, n_max); A(w.hard_n, 1);
     A(w.redo, n_max); A(w.redo_n, 1);
-    A(w.qr_scratch, (int64_t)QR_SLOTS * MAXROWS * 17);
     A(w.P, n_max); A(w.eta, n_max); A(w.hand, (int64_t)HAND * n_max);
     A(w.uf, (int64_t)45 * n_max);
     for (int a = 0; a < 7; ++a) A(w.adj[a], n_max);

@@ -9,7 +9,7 @@
 // stencil (the pivot ratio min U_jj / max U_jj is checked); this needs no
 // cross-lane reductions and keeps every accumulator in registers.  A
 // stencil whose pivot ratio falls below the refit threshold is refitted
-// by float64 Householder QR (one thread, matrix in global scratch), which
+// by float64 Householder QR (one thread, matrix in LDS), which
 // also applies the rank test min|r_jj|/max|r_jj| < fallback_tol.
 //
 // The second fit (P, eta) needs only first derivatives: pass 1 stores
@@ -29,7 +29,7 @@ inline unsigned int blocks_for(int64_t n, int per = BLOCK)
 // ---- Householder QR for refits -----------------------------------------
 
 // min || A c - B || for A (mt x nc, leading dim 9) and nf right-hand sides
-// (leading dim 8) in scratch; C (nc x nf) receives the solution.  Returns
+// (leading dim 8) in the refit's LDS; C (nc x nf) receives the solution.  Returns
 // min|r_jj| / max|r_jj|.
 __device__ double qr_solve(double* A, double* B, int mt, int nc, int nf,
                            double* C)
@@ -73,6 +73,12 @@ __device__ double qr_solve(double* A, double* B, int mt, int nc, int nf,
         }
     return rmax > 0.0 ? rmin / rmax : 0.0;
 }
+
+// QR refits: a thread per refitted particle, its rows and right-hand
+// sides (MAXROWS x 17 doubles, 9.8 KB) in LDS; QR_TPB threads per block
+// (39 KB), QR_BLOCKS blocks, all resident at once, walk the refit list.
+constexpr int QR_TPB = 4;
+constexpr int QR_BLOCKS = 1024;
 
 // Householder least squares of particle i's rows (QR refit path).  vals(p,
 // out) gives the nf field values at a stencil point (p != null) or at the
@@ -207,15 +213,16 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
     if (flags) flags[i] = fl;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_fit_generic_qr(
+__global__ __launch_bounds__(QR_TPB) void k_fit_generic_qr(
     View v, GenericFields F, double* coef, uint8_t* flags, const int32_t* redo,
-    const unsigned int* redo_n, double* scratch, Counters* cnt)
+    const unsigned int* redo_n, Counters* cnt)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     const unsigned int total = *redo_n;
     if (slot == 0) atomicAdd(&cnt->qr_refits, (unsigned long long)total);
-    double* scr = scratch + slot * (MAXROWS * 17);
+    __shared__ double sscr[QR_TPB][MAXROWS * 17];
+    double* scr = sscr[threadIdx.x];
     const int64_t n = v.n;
     for (int64_t t = slot; t < (int64_t)total; t += nth) {
         const int64_t i = redo[t];
@@ -337,6 +344,85 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
     pass1_solve(v, o, g, s, i, M, B, mt, sub == 0, redo, redo_n, force_qr);
 }
 
+// Loads the positions and velocities of the tile's S list sources into
+// LDS (slot q holds the q-th source of the tile's sorted set): every
+// thread takes its sources at once, their ids first, then their fields.
+__device__ __forceinline__ void stage_pass1(const View& v, int64_t tile, int S, double* sx,
+                                            double* sy, double* sz, double* su,
+                                            double* sv, double* sw)
+{
+    int32_t js[STAGE_PER];
+    stage_ids(v, tile, S, js);
+    double f[6][STAGE_PER];
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        const int32_t j = js[u] < 0 ? 0 : js[u];
+        f[0][u] = v.x[j];
+        f[1][u] = v.y[j];
+        f[2][u] = v.z[j];
+        f[3][u] = v.u[j];
+        f[4][u] = v.v[j];
+        f[5][u] = v.w[j];
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        if (js[u] < 0) continue;
+        const int q = (int)threadIdx.x + u * BLOCK;
+        sx[q] = f[0][u];
+        sy[q] = f[1][u];
+        sz[q] = f[2][u];
+        su[q] = f[3][u];
+        sv[q] = f[4][u];
+        sw[q] = f[5][u];
+    }
+}
+
+// Loads the positions, P and eta of the tile's S list sources into LDS,
+// with the pressure a mirror of each source carries (pass2_values).
+__device__ __forceinline__ void stage_pass2(const View& v, const double* P,
+                                            const double* eta, int64_t tile, int S,
+                                            double* sx, double* sy, double* sz,
+                                            double* sP, double* sE, double* sM)
+{
+    int32_t js[STAGE_PER];
+    stage_ids(v, tile, S, js);
+    double f[5][STAGE_PER];
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        const int32_t j = js[u] < 0 ? 0 : js[u];
+        f[0][u] = v.x[j];
+        f[1][u] = v.y[j];
+        f[2][u] = v.z[j];
+        f[3][u] = P[j];
+        f[4][u] = eta[j];
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        if (js[u] < 0) continue;
+        const int q = (int)threadIdx.x + u * BLOCK;
+        const int32_t j = js[u];
+        sx[q] = f[0][u];
+        sy[q] = f[1][u];
+        sz[q] = f[2][u];
+        sP[q] = f[3][u];
+        sE[q] = f[4][u];
+        // j's system is that of every particle listing it.  Only a source
+        // within R of the wall has a mirror (the rule that sets mirror_of).
+        const int sj = sys_of(v.off, v.n_sys, j);
+        const GridInfo& gj = v.grid[sj];
+        double pm = 0.0;
+        if (dsub(f[2][u], gj.wall) < gj.R) {
+            Pt m;
+            m.mirror = true;
+            m.src = j;
+            m.z = dsub(dmul(2.0, gj.wall), f[2][u]);
+            double em;
+            pass2_values(v, P, eta, &m, v.prm[sj], pm, em);
+        }
+        sM[q] = pm;
+    }
+}
+
 // Pass 1 with the neighbours of the block's tile staged in LDS (one lane
 // per particle): the positions and velocities of the tile's list sources
 // are loaded once, coalesced, and every stencil row reads them from LDS.
@@ -357,31 +443,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
     const int tc = map_ok ? v.tile_cnt[tile] : -1;
     const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
     if (S >= 0) {
-        // all of this thread's sources at once: their ids, then their fields
-        int32_t js[STAGE_PER];
-        stage_ids(v, tile, S, js);
-        double f[6][STAGE_PER];
-#pragma unroll
-        for (int u = 0; u < STAGE_PER; ++u) {
-            const int32_t j = js[u] < 0 ? 0 : js[u];
-            f[0][u] = v.x[j];
-            f[1][u] = v.y[j];
-            f[2][u] = v.z[j];
-            f[3][u] = v.u[j];
-            f[4][u] = v.v[j];
-            f[5][u] = v.w[j];
-        }
-#pragma unroll
-        for (int u = 0; u < STAGE_PER; ++u) {
-            if (js[u] < 0) continue;
-            const int q = (int)threadIdx.x + u * BLOCK;
-            sx[q] = f[0][u];
-            sy[q] = f[1][u];
-            sz[q] = f[2][u];
-            su[q] = f[3][u];
-            sv[q] = f[4][u];
-            sw[q] = f[5][u];
-        }
+        stage_pass1(v, tile, S, sx, sy, sz, su, sv, sw);
         __syncthreads();
     }
     if (i >= v.n) return;
@@ -424,16 +486,17 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
     pass1_solve(v, o, g, s, i, M, B, mt, true, redo, redo_n, force_qr);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_pass1_qr(View v, StepOut o,
+__global__ __launch_bounds__(QR_TPB) void k_pass1_qr(View v, StepOut o,
                                                     const int32_t* redo,
                                                     const unsigned int* redo_n,
-                                                    double* scratch, Counters* cnt)
+                                                    Counters* cnt)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     const unsigned int total = *redo_n;
     if (slot == 0) atomicAdd(&cnt->qr_refits, (unsigned long long)total);
-    double* scr = scratch + slot * (MAXROWS * 17);
+    __shared__ double sscr[QR_TPB][MAXROWS * 17];
+    double* scr = sscr[threadIdx.x];
     for (int64_t t = slot; t < (int64_t)total; t += nth) {
         const int64_t i = redo[t];
         const int s = sys_of(v.off, v.n_sys, i);
@@ -586,45 +649,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
     const int tc = map_ok ? v.tile_cnt[tile] : -1;
     const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
     if (S >= 0) {
-        // all of this thread's sources at once: their ids, then their fields
-        int32_t js[STAGE_PER];
-        stage_ids(v, tile, S, js);
-        double f[5][STAGE_PER];
-#pragma unroll
-        for (int u = 0; u < STAGE_PER; ++u) {
-            const int32_t j = js[u] < 0 ? 0 : js[u];
-            f[0][u] = v.x[j];
-            f[1][u] = v.y[j];
-            f[2][u] = v.z[j];
-            f[3][u] = P[j];
-            f[4][u] = eta[j];
-        }
-#pragma unroll
-        for (int u = 0; u < STAGE_PER; ++u) {
-            if (js[u] < 0) continue;
-            const int q = (int)threadIdx.x + u * BLOCK;
-            const int32_t j = js[u];
-            sx[q] = f[0][u];
-            sy[q] = f[1][u];
-            sz[q] = f[2][u];
-            sP[q] = f[3][u];
-            sE[q] = f[4][u];
-            // what a mirror of j carries (pass2_values); j's system is
-            // that of every particle listing it.  Only a source within R
-            // of the wall has a mirror (the rule that sets mirror_of).
-            const int sj = sys_of(v.off, v.n_sys, j);
-            const GridInfo& gj = v.grid[sj];
-            double pm = 0.0;
-            if (dsub(f[2][u], gj.wall) < gj.R) {
-                Pt m;
-                m.mirror = true;
-                m.src = j;
-                m.z = dsub(dmul(2.0, gj.wall), f[2][u]);
-                double em;
-                pass2_values(v, P, eta, &m, v.prm[sj], pm, em);
-            }
-            sM[q] = pm;
-        }
+        stage_pass2(v, P, eta, tile, S, sx, sy, sz, sP, sE, sM);
         __syncthreads();
     }
     if (i >= v.n) return;
@@ -671,6 +696,17 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
 // whose float32 pivot ratio falls below the refit threshold takes the
 // float64 Householder refit of the float64 path.
 
+// rows per batch (measured at the 524,288-particle column): the moment
+// sweeps take those of the float64 fits; pass 1's float64 residual sweep,
+// which also holds three fields' coefficients and corrections, takes 2,
+// pass 2's (two fields) 4
+template <int B>
+struct RowBatch {
+    static constexpr int value = B;
+};
+constexpr int REF1_SWEEP_BATCH = 2;
+constexpr int REF2_SWEEP_BATCH = 4;
+
 template <int N>
 __device__ __forceinline__ void store_factor(const float (&U)[45], float* uf, int64_t n,
                                              int64_t i)
@@ -702,31 +738,64 @@ __device__ __forceinline__ void refine_step(const float (&U)[45], const double (
     }
 }
 
+// Both sweeps read their rows from the tile's LDS stage when the tile is
+// staged (as k_pass1_st does), else from global memory.  UNIT: the
+// weights are unit (known at compile time).
+template <bool UNIT>
 __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float* uf,
                                                         int32_t* redo,
-                                                        unsigned int* redo_n)
+                                                        unsigned int* redo_n, int map_ok)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
+    __shared__ double su[STAGE_CAP], sv[STAGE_CAP], sw[STAGE_CAP];
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = tile * BLOCK + threadIdx.x;
+    const int tc = map_ok ? v.tile_cnt[tile] : -1;
+    const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
+    if (S >= 0) {
+        stage_pass1(v, tile, S, sx, sy, sz, su, sv, sw);
+        __syncthreads();
+    }
     if (i >= v.n) return;
     const int64_t n = v.n;
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
     const Rec r = load_rec(v, i);
     const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
+    const bool staged = S >= 0 && !(r.mode & MODE_SORTED);
+    // body(a, w, has, uj, vj, wj) for every row, bt.value rows at a time:
+    // has is false for a ghost row, which carries u_i
+    auto rows = [&](auto bt, auto&& body) -> int {
+        constexpr int RB = decltype(bt)::value;
+        if (staged)
+            return for_rows_staged<RB, UNIT>(v, g, i, r, sx, sy, sz,
+                                            [&](const double* a, double w, const Pt* p) {
+                if (!p) {
+                    body(a, w, false, ui, vi, wi);
+                    return;
+                }
+                const int q = p->src;
+                body(a, w, true, su[q], sv[q], p->mirror ? -sw[q] : sw[q]);
+            });
+        return for_rows<RB>(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+            double uj = ui, vj = vi, wj = wi;
+            if (p) point_velocity(v, *p, uj, vj, wj);
+            body(a, w, p != nullptr, uj, vj, wj);
+        });
+    };
     // ---- float32 moments and right-hand sides
     float M[31], B[3][9];
 #pragma unroll
     for (int q = 0; q < 31; ++q) M[q] = 0.0f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) B[0][q] = B[1][q] = B[2][q] = 0.0f;
-    const int mt = for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+    const int mt = rows(RowBatch<FIT_BATCH>{}, [&](const double* a, double w, bool has,
+                                                   double uj, double vj, double wj) {
         float af[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) af[q] = (float)a[q];
         moments_add(M, af, (float)w);
-        if (!p) return;
-        double uj, vj, wj;
-        point_velocity(v, *p, uj, vj, wj);
+        if (!has) return;
         const float b0 = (float)(w * (uj - ui)), b1 = (float)(w * (vj - vi)),
                     b2 = (float)(w * (wj - wi));
 #pragma unroll
@@ -747,7 +816,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float
         o.flags[i] = FLAG_QR;
         return;
     }
-    double c[3][9];
+    // the float32 solution; the residual sweep widens it exactly to float64
+    float cf[3][9];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         float e[9];
@@ -756,7 +826,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float
         if (lin) chol_solve<3>(U, e);
         else chol_solve<9>(U, e);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) c[f][q] = (lin && q >= 3) ? 0.0 : (double)e[q];
+        for (int q = 0; q < 9; ++q) cf[f][q] = (lin && q >= 3) ? 0.0f : e[q];
     }
     // the factor goes to memory: pass 2 needs it, and it is dead here
     // until the correction
@@ -766,11 +836,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float
     double d[3][9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) d[0][q] = d[1][q] = d[2][q] = 0.0;
-    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+    rows(RowBatch<REF1_SWEEP_BATCH>{}, [&](const double* a, double w, bool has, double uj,
+                                           double vj, double wj) {
         double b0 = 0.0, b1 = 0.0, b2 = 0.0;   // ghosts carry u_i
-        if (p) {
-            double uj, vj, wj;
-            point_velocity(v, *p, uj, vj, wj);
+        if (has) {
             b0 = uj - ui;
             b1 = vj - vi;
             b2 = wj - wi;
@@ -778,9 +847,9 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float
         double r0 = b0, r1 = b1, r2 = b2;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            r0 -= a[q] * c[0][q];
-            r1 -= a[q] * c[1][q];
-            r2 -= a[q] * c[2][q];
+            r0 -= a[q] * (double)cf[0][q];
+            r1 -= a[q] * (double)cf[1][q];
+            r2 -= a[q] * (double)cf[2][q];
         }
         r0 *= w;
         r1 *= w;
@@ -793,6 +862,11 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float
         }
     });
     load_factor(U, uf, n, i);
+    double c[3][9];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) c[f][q] = (double)cf[f][q];
     if (lin) refine_step<3, 3>(U, d, c);
     else refine_step<9, 3>(U, d, c);
     double cs[27];
@@ -803,13 +877,26 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float
     finish_pass1(v, v.prm[s], i, cs, none, false, lin ? FLAG_LINEAR : 0, o);
 }
 
+// Both sweeps read their rows from the tile's LDS stage when the tile is
+// staged (as k_pass2_st does), else from global memory.
+template <bool UNIT>
 __global__ __launch_bounds__(BLOCK) void k_pass2_ref(View v, const double* P,
                                                      const double* eta,
                                                      const double* hand,
                                                      const float* uf,
-                                                     const uint8_t* flags, RhsOut o)
+                                                     const uint8_t* flags, RhsOut o,
+                                                     int map_ok)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
+    __shared__ double sP[STAGE_CAP], sE[STAGE_CAP], sM[STAGE_CAP];
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = tile * BLOCK + threadIdx.x;
+    const int tc = map_ok ? v.tile_cnt[tile] : -1;
+    const int S = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
+    if (S >= 0) {
+        stage_pass2(v, P, eta, tile, S, sx, sy, sz, sP, sE, sM);
+        __syncthreads();
+    }
     if (i >= v.n) return;
     const uint8_t fl = flags[i];
     if (fl & FLAG_QR) return;
@@ -820,13 +907,30 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_ref(View v, const double* P,
     const Rec r = load_rec(v, i);
     const bool lin = fl & FLAG_LINEAR;
     const double Pi = P[i], Ei = eta[i];
+    const bool staged = S >= 0 && !(r.mode & MODE_SORTED);
+    // body(a, w, Pj, Ej) for every row (what pass2_values gives), bt.value
+    // rows at a time
+    auto rows = [&](auto bt, auto&& body) {
+        constexpr int RB = decltype(bt)::value;
+        if (staged)
+            for_rows_staged<RB, UNIT>(v, g, i, r, sx, sy, sz,
+                                             [&](const double* a, double w, const Pt* p) {
+                if (!p) body(a, w, 0.0, 0.0);
+                else if (p->mirror) body(a, w, sM[p->src], 0.0);
+                else body(a, w, sP[p->src], sE[p->src]);
+            });
+        else
+            for_rows<RB>(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+                double Pj, Ej;
+                pass2_values(v, P, eta, p, prm, Pj, Ej);
+                body(a, w, Pj, Ej);
+            });
+    };
     // ---- float32 right-hand sides and solve
     float yP[9], yE[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) yP[q] = yE[q] = 0.0f;
-    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
-        double Pj, Ej;
-        pass2_values(v, P, eta, p, prm, Pj, Ej);
+    rows(RowBatch<PASS2_BATCH>{}, [&](const double* a, double w, double Pj, double Ej) {
         const float bP = (float)(w * (Pj - Pi)), bE = (float)(w * (Ej - Ei));
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -862,9 +966,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_ref(View v, const double* P,
     double d[2][9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) d[0][q] = d[1][q] = 0.0;
-    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
-        double Pj, Ej;
-        pass2_values(v, P, eta, p, prm, Pj, Ej);
+    rows(RowBatch<REF2_SWEEP_BATCH>{}, [&](const double* a, double w, double Pj, double Ej) {
         double rP = Pj - Pi, rE = Ej - Ei;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -892,17 +994,18 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_ref(View v, const double* P,
     finish_rhs(v, prm, i, hv, gP, gE, o);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_pass2_qr(View v, const double* P,
+__global__ __launch_bounds__(QR_TPB) void k_pass2_qr(View v, const double* P,
                                                     const double* eta,
                                                     const double* hand,
                                                     const int32_t* redo,
                                                     const unsigned int* redo_n,
-                                                    double* scratch, RhsOut o)
+                                                    RhsOut o)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     const unsigned int total = *redo_n;
-    double* scr = scratch + slot * (MAXROWS * 17);
+    __shared__ double sscr[QR_TPB][MAXROWS * 17];
+    double* scr = sscr[threadIdx.x];
     const int64_t n = v.n;
     for (int64_t t = slot; t < (int64_t)total; t += nth) {
         const int64_t i = redo[t];
@@ -1033,9 +1136,9 @@ lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
         default: break;
         }
 #undef LP_FIT_CASE
-        hipLaunchKernelGGL(k_fit_generic_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_fit_generic_qr, dim3(QR_BLOCKS), dim3(QR_TPB), 0,
                            c->stream, v, F, coef, fl, w.redo, w.redo_n,
-                           w.qr_scratch, w.cnt);
+                           w.cnt);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "fit launch");
@@ -1077,10 +1180,10 @@ lp_status rhs_from_coef(lp_ctx* c, const double* const st[7],
             launch_pass2_cubic(c, v, w.P, w.eta, w.hand, o);
         } else {
             launch_pass2(c, c->lpp2, v, o);
-            hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+            hipLaunchKernelGGL(k_pass2_qr, dim3(QR_BLOCKS), dim3(QR_TPB), 0,
                                c->stream, v, (const double*)w.P, (const double*)w.eta,
                                (const double*)w.hand, (const int32_t*)w.redo,
-                               (const unsigned int*)w.redo_n, w.qr_scratch, o);
+                               (const unsigned int*)w.redo_n, o);
         }
         if (flags)
             hipLaunchKernelGGL(k_copy_u8, dim3(blocks_for(n)), dim3(BLOCK), 0,
@@ -1103,16 +1206,22 @@ lp_status step_rhs(lp_ctx* c, const double* const st[7])
         prof_mark(c, 3, false);
         if (c->cfg.fit_order == 3)
             launch_pass1_cubic(c, v, so);
-        else if (c->cfg.precision == LP_FP32_REFINED && !fq)
-            hipLaunchKernelGGL(k_pass1_ref, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, so, w.uf, w.redo, w.redo_n);
+        else if (c->cfg.precision == LP_FP32_REFINED && !fq) {
+            const int mo = c->map_ok ? 1 : 0;
+            if (c->cfg.weight == LP_W_UNIT)
+                hipLaunchKernelGGL(k_pass1_ref<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                                   c->stream, v, so, w.uf, w.redo, w.redo_n, mo);
+            else
+                hipLaunchKernelGGL(k_pass1_ref<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                                   c->stream, v, so, w.uf, w.redo, w.redo_n, mo);
+        }
         else
             launch_pass1(c, c->lpp1, v, so, fq);
         prof_mark(c, 3, true);
         prof_mark(c, 4, false);
-        hipLaunchKernelGGL(k_pass1_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_pass1_qr, dim3(QR_BLOCKS), dim3(QR_TPB), 0,
                            c->stream, v, so, (const int32_t*)w.redo,
-                           (const unsigned int*)w.redo_n, w.qr_scratch, w.cnt);
+                           (const unsigned int*)w.redo_n, w.cnt);
         prof_mark(c, 4, true);
     }
     hipError_t e = hipGetLastError();
@@ -1129,9 +1238,9 @@ lp_status step_pass1_coef(lp_ctx* c, const double* const st[7])
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
     if (n > 0) {
         launch_pass1(c, c->lpp1, v, so, 0);
-        hipLaunchKernelGGL(k_pass1_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_pass1_qr, dim3(QR_BLOCKS), dim3(QR_TPB), 0,
                            c->stream, v, so, (const int32_t*)w.redo,
-                           (const unsigned int*)w.redo_n, w.qr_scratch, w.cnt);
+                           (const unsigned int*)w.redo_n, w.cnt);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "adjoint pass-1 launch");
@@ -1151,19 +1260,27 @@ lp_status step_pass2(lp_ctx* c, const double* const st[7], double dt,
         prof_mark(c, 5, false);
         if (c->cfg.fit_order == 3)
             launch_pass2_cubic(c, v, w.P, w.eta, w.hand, o);
-        else if (c->cfg.precision == LP_FP32_REFINED && !fp64)
-            hipLaunchKernelGGL(k_pass2_ref, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, (const double*)w.P, (const double*)w.eta,
-                               (const double*)w.hand, (const float*)w.uf,
-                               (const uint8_t*)w.flags, o);
+        else if (c->cfg.precision == LP_FP32_REFINED && !fp64) {
+            const int mo = c->map_ok ? 1 : 0;
+            if (c->cfg.weight == LP_W_UNIT)
+                hipLaunchKernelGGL(k_pass2_ref<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                                   c->stream, v, (const double*)w.P, (const double*)w.eta,
+                                   (const double*)w.hand, (const float*)w.uf,
+                                   (const uint8_t*)w.flags, o, mo);
+            else
+                hipLaunchKernelGGL(k_pass2_ref<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                                   c->stream, v, (const double*)w.P, (const double*)w.eta,
+                                   (const double*)w.hand, (const float*)w.uf,
+                                   (const uint8_t*)w.flags, o, mo);
+        }
         else
             launch_pass2(c, c->lpp2, v, o);
         prof_mark(c, 5, true);
         prof_mark(c, 6, false);
-        hipLaunchKernelGGL(k_pass2_qr, dim3(QR_SLOTS / BLOCK), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_pass2_qr, dim3(QR_BLOCKS), dim3(QR_TPB), 0,
                            c->stream, v, (const double*)w.P, (const double*)w.eta,
                            (const double*)w.hand, (const int32_t*)w.redo,
-                           (const unsigned int*)w.redo_n, w.qr_scratch, o);
+                           (const unsigned int*)w.redo_n, o);
         prof_mark(c, 6, true);
     }
     hipError_t e = hipGetLastError();

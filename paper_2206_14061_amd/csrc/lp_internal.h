@@ -40,7 +40,6 @@ constexpr int MODE_ALL = 1, MODE_SORTED = 8;
 constexpr uint8_t NO_CAND = 0xFF; // key code of a list entry outside R
 constexpr int HARD_CAP = 256;     // candidates the sorted stencil path holds
 constexpr int HARD_BLOCKS = 1024; // blocks of the sorted path (a wave per particle)
-constexpr int QR_SLOTS = 16384;   // concurrent QR-refit threads
 constexpr int HAND = 37;          // pass-1 -> pass-2 handoff doubles
 constexpr int BLOCK = 256;        // threads per block of per-particle kernels
 constexpr int SORT_ITEMS = 16;    // keys per thread in a radix tile
@@ -174,7 +173,6 @@ struct Work {
     // fits
     int32_t* redo = nullptr;
     unsigned int* redo_n = nullptr;
-    double* qr_scratch = nullptr;         // QR_SLOTS x MAXROWS x (9 + 8)
     double *P = nullptr, *eta = nullptr;
     double* hand = nullptr;               // HAND x n
     float* uf = nullptr;                  // 45 x n float32 factors (refined mode)

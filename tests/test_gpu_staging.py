@@ -23,12 +23,13 @@ def _run(lp, wl, steps, order=1, **cfg):
     return st.to_host(), ctx.stats()
 
 
-def _compare(a, b, tag):
+def _compare(a, b, tag, rtol=1e-12):
     for q, (x, y) in enumerate(zip(a.arrays(), b.arrays())):
         scale = max(float(np.max(np.abs(y))), 1e-300)
         d = float(np.max(np.abs(x - y))) if x.size else 0.0
         _log("%s array %d: max |staged - global| = %.3g (scale %.3g)" % (tag, q, d, scale))
-        np.testing.assert_allclose(x, y, rtol=1e-12, atol=1e-13 * scale, err_msg="%s %d" % (tag, q))
+        np.testing.assert_allclose(x, y, rtol=rtol, atol=0.1 * rtol * scale,
+                                   err_msg="%s %d" % (tag, q))
 
 
 @pytest.mark.parametrize("case", ["column16", "column16_flow_ragged", "lattice_exact",
@@ -45,6 +46,25 @@ def test_staged_matches_global(lp, case, order):
     assert st_s["unstaged_tiles"] == 0
     assert st_g["unstaged_tiles"] == st_g["tiles"]
     _compare(got, ref, case)
+
+
+@pytest.mark.parametrize("case", ["column16_flow_ragged", "sheared_20x20x12", "ensemble_3",
+                                  "periodic_xy"])
+def test_staged_matches_global_refined(lp, case):
+    """The refined FP32 fits read staged rows in both sweeps (float32
+    moments, float64 residuals).  The float32 sums may round differently
+    where the compiler schedules the two paths differently; one float64
+    correction leaves that at the square of float32 rounding, so the states
+    agree to 1e-10."""
+    wl = CASES[case]()
+    print("case", case, "refined n", wl.n, flush=True)
+    got, st_s = _run(lp, wl, 2, precision=lp.LP_FP32_REFINED)
+    ref, st_g = _run(lp, wl, 2, precision=lp.LP_FP32_REFINED,
+                     debug_flags=lp.LP_DEBUG_GLOBAL_GATHER)
+    _log("stats staged %s global %s" % (st_s, st_g))
+    assert st_s["unstaged_tiles"] == 0
+    assert st_g["unstaged_tiles"] == st_g["tiles"]
+    _compare(got, ref, case, rtol=1e-10)
 
 
 @pytest.mark.parametrize("opt", ["wall_pressure", "wall_reflect"])
