@@ -9,7 +9,7 @@
 // stencil (the pivot ratio min U_jj / max U_jj is checked); this needs no
 // cross-lane reductions and keeps every accumulator in registers.  A
 // stencil whose pivot ratio falls below the refit threshold is refitted
-// by float64 Householder QR (one thread, matrix in LDS), which
+// by float64 Householder QR (a wavefront per stencil), which
 // also applies the rank test min|r_jj|/max|r_jj| < fallback_tol.
 //
 // The second fit (P, eta) needs only first derivatives: pass 1 stores
@@ -27,100 +27,149 @@ inline unsigned int blocks_for(int64_t n, int per = BLOCK)
 }
 
 // ---- Householder QR for refits -----------------------------------------
+//
+// One wavefront refits one particle.  Stencil row k (k < MAXROWS) lives in
+// lane k % 64, register slot k / 64.  The column norm and the dot products
+// of each Householder step are wavefront sums (a xor butterfly leaves the
+// same value in every lane, so every branch on them is uniform); R's rows
+// and Q^T b are read by broadcast, and every lane back-substitutes (nine
+// unknowns at most), so each lane ends with the same coefficients.
 
-// min || A c - B || for A (mt x nc, leading dim 9) and nf right-hand sides
-// (leading dim 8) in the refit's LDS; C (nc x nf) receives the solution.  Returns
-// min|r_jj| / max|r_jj|.
-__device__ double qr_solve(double* A, double* B, int mt, int nc, int nf,
-                           double* C)
+constexpr int QR_TPB = 256;     // four wavefronts per block, one refit each
+constexpr int QR_BLOCKS = 256;  // 1,024 refits in flight
+
+__device__ __forceinline__ double wave_sum(double x)
 {
-    double rd[9];
-    double rmin = INFINITY, rmax = 0.0;
-    for (int j = 0; j < nc; ++j) {
-        double s = 0.0;
-        for (int r = j; r < mt; ++r) s += A[r * 9 + j] * A[r * 9 + j];
-        const double nrm = sqrt(s);
-        const double ajj = A[j * 9 + j];
-        if (nrm == 0.0) {
-            rd[j] = 0.0;
-            rmin = 0.0;
-            continue;
-        }
-        const double alpha = ajj >= 0.0 ? -nrm : nrm;
-        A[j * 9 + j] = ajj - alpha;             // Householder vector in column j
-        const double beta = 1.0 / (nrm * (nrm + fabs(ajj)));  // 2 / v^T v
-        for (int l = j + 1; l < nc; ++l) {
-            double dot = 0.0;
-            for (int r = j; r < mt; ++r) dot += A[r * 9 + j] * A[r * 9 + l];
-            const double f = beta * dot;
-            for (int r = j; r < mt; ++r) A[r * 9 + l] -= f * A[r * 9 + j];
-        }
-        for (int l = 0; l < nf; ++l) {
-            double dot = 0.0;
-            for (int r = j; r < mt; ++r) dot += A[r * 9 + j] * B[r * 8 + l];
-            const double f = beta * dot;
-            for (int r = j; r < mt; ++r) B[r * 8 + l] -= f * A[r * 9 + j];
-        }
-        rd[j] = alpha;
-        rmin = fmin(rmin, fabs(alpha));
-        rmax = fmax(rmax, fabs(alpha));
-    }
-    for (int l = 0; l < nf; ++l)
-        for (int j = nc - 1; j >= 0; --j) {
-            double t = B[j * 8 + l];
-            for (int q = j + 1; q < nc; ++q) t -= A[j * 9 + q] * C[q * 8 + l];
-            C[j * 8 + l] = rd[j] != 0.0 ? t / rd[j] : 0.0;
-        }
-    return rmax > 0.0 ? rmin / rmax : 0.0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);
+    return x;
 }
 
-// QR refits: a thread per refitted particle, its rows and right-hand
-// sides (MAXROWS x 17 doubles, 9.8 KB) in LDS; QR_TPB threads per block
-// (39 KB), QR_BLOCKS blocks, all resident at once, walk the refit list.
-constexpr int QR_TPB = 4;
-constexpr int QR_BLOCKS = 1024;
-
-// Householder least squares of particle i's rows (QR refit path).  vals(p,
-// out) gives the nf field values at a stencil point (p != null) or at the
-// ghosts (p == null); own: the values at the particle.  coef (nf x 9, ld
-// 9) receives derivative estimates.  Returns FLAG_QR plus FLAG_LINEAR
-// when the linear fallback was taken.
+// Householder least squares of particle i's rows, called by all 64 lanes
+// of a wavefront together.  vals(p, out) gives the nf (<= 8) field values
+// at a stencil point (p != null) or at the ghosts (p == null); own: the
+// values at the particle.  coef (nf x 9, ld 9) receives derivative
+// estimates in every lane.  Returns FLAG_QR plus FLAG_LINEAR when the
+// linear fallback (fewer than 9 rows, or the rank test
+// min|r_jj| / max|r_jj| < fallback_tol) was taken.
 template <class Vals>
 __device__ uint8_t qr_fit_point(const View& v, const GridInfo& g, int64_t i,
                                 const Rec& r, int nf, const double* own,
-                                Vals&& vals, double* scratch, double* coef)
+                                Vals&& vals, double* coef)
 {
-    double* A = scratch;
-    double* B = scratch + MAXROWS * 9;
+    static_assert(MAXROWS <= 128, "two rows per lane");
+    const int lane = (int)(threadIdx.x & 63u);
+    double A[2][9], B[2][8];
     auto build = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) A[h][q] = 0.0;
+#pragma unroll
+            for (int f = 0; f < 8; ++f) B[h][f] = 0.0;
+        }
         int k = 0;
         return for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
             if (k >= MAXROWS) return;
-            const double sw = sqrt(w);
-            double fj[8];
-            vals(p, fj);
-            for (int q = 0; q < 9; ++q) A[k * 9 + q] = sw * a[q];
-            for (int f = 0; f < nf; ++f) B[k * 8 + f] = sw * (fj[f] - own[f]);
+            if ((k & 63) == lane) {
+                const double sw = sqrt(w);
+                double fj[8];
+                vals(p, fj);
+                const bool hi = k >= 64;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const double x = sw * a[q];
+                    A[0][q] = hi ? A[0][q] : x;
+                    A[1][q] = hi ? x : A[1][q];
+                }
+#pragma unroll
+                for (int f = 0; f < 8; ++f) {
+                    if (f >= nf) break;
+                    const double y = sw * (fj[f] - own[f]);
+                    B[0][f] = hi ? B[0][f] : y;
+                    B[1][f] = hi ? y : B[1][f];
+                }
+            }
             ++k;
         });
     };
-    double C[9 * 8];
+    // QR of the first nc columns, applied to B; rd: the diagonal of R
+    double rd[9];
+    auto factor = [&](int nc) -> double {
+        double rmin = INFINITY, rmax = 0.0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            if (j >= nc) break;
+            const double x0 = lane >= j ? A[0][j] : 0.0, x1 = A[1][j];
+            const double nrm = sqrt(wave_sum(x0 * x0 + x1 * x1));
+            const double ajj = __shfl(A[0][j], j);
+            if (nrm == 0.0) {
+                rd[j] = 0.0;
+                rmin = 0.0;
+                continue;
+            }
+            const double alpha = ajj >= 0.0 ? -nrm : nrm;
+            if (lane == j) A[0][j] = ajj - alpha;   // Householder vector in column j
+            const double beta = 1.0 / (nrm * (nrm + fabs(ajj)));  // 2 / v^T v
+            const double v0 = lane >= j ? A[0][j] : 0.0, v1 = A[1][j];
+#pragma unroll
+            for (int l = j + 1; l < 9; ++l) {
+                if (l >= nc) break;
+                const double f = beta * wave_sum(v0 * A[0][l] + v1 * A[1][l]);
+                if (lane >= j) A[0][l] -= f * v0;
+                A[1][l] -= f * v1;
+            }
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                if (l >= nf) break;
+                const double f = beta * wave_sum(v0 * B[0][l] + v1 * B[1][l]);
+                if (lane >= j) B[0][l] -= f * v0;
+                B[1][l] -= f * v1;
+            }
+            rd[j] = alpha;
+            rmin = fmin(rmin, fabs(alpha));
+            rmax = fmax(rmax, fabs(alpha));
+        }
+        return rmax > 0.0 ? rmin / rmax : 0.0;
+    };
+    // R c = Q^T b per field (rows j < nc of R and Q^T b sit in lanes j)
+    auto solve = [&](int nc) {
+#pragma unroll
+        for (int f = 0; f < 8; ++f) {
+            if (f >= nf) break;
+            double cf[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) cf[q] = 0.0;
+#pragma unroll
+            for (int j = 8; j >= 0; --j) {
+                if (j >= nc) continue;
+                double t = __shfl(B[0][f], j);
+#pragma unroll
+                for (int q = j + 1; q < 9; ++q)
+                    if (q < nc) t -= __shfl(A[0][q], j) * cf[q];
+                cf[j] = rd[j] != 0.0 ? t / rd[j] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                coef[f * 9 + q] = cf[q] * (q < 3 ? g.inv_h : g.inv_h * g.inv_h);
+        }
+    };
     uint8_t flags = FLAG_QR;
-    double ratio = 0.0;
     int mt = build();
     if (mt > MAXROWS) mt = MAXROWS;
-    if (mt >= 9) ratio = qr_solve(A, B, mt, 9, nf, C);
-    if (mt < 9 || ratio < v.fallback_tol) {
-        flags |= FLAG_LINEAR;
-        for (int q = 0; q < 72; ++q) C[q] = 0.0;
-        if (mt >= 3) {
-            build();
-            qr_solve(A, B, mt, 3, nf, C);
-        }
+    const double ratio = mt >= 9 ? factor(9) : 0.0;
+    if (mt >= 9 && ratio >= v.fallback_tol) {
+        solve(9);
+        return flags;
     }
-    for (int f = 0; f < nf; ++f)
-        for (int q = 0; q < 9; ++q)
-            coef[f * 9 + q] = C[q * 8 + f] * (q < 3 ? g.inv_h : g.inv_h * g.inv_h);
+    flags |= FLAG_LINEAR;
+    if (mt >= 3) {
+        build();
+        factor(3);
+        solve(3);
+    } else {
+        for (int q = 0; q < nf * 9; ++q) coef[q] = 0.0;
+    }
     return flags;
 }
 
@@ -217,14 +266,15 @@ __global__ __launch_bounds__(QR_TPB) void k_fit_generic_qr(
     View v, GenericFields F, double* coef, uint8_t* flags, const int32_t* redo,
     const unsigned int* redo_n, Counters* cnt)
 {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    // a wavefront per refit
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const unsigned int total = *redo_n;
-    if (slot == 0) atomicAdd(&cnt->qr_refits, (unsigned long long)total);
-    __shared__ double sscr[QR_TPB][MAXROWS * 17];
-    double* scr = sscr[threadIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd(&cnt->qr_refits, (unsigned long long)total);
     const int64_t n = v.n;
-    for (int64_t t = slot; t < (int64_t)total; t += nth) {
+    for (int64_t t = wave; t < (int64_t)total; t += nw) {
         const int64_t i = redo[t];
         const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
         const Rec r = load_rec(v, i);
@@ -238,10 +288,12 @@ __global__ __launch_bounds__(QR_TPB) void k_fit_generic_qr(
             }
         };
         double c[8 * 9];
-        const uint8_t fl = qr_fit_point(v, g, i, r, F.k, own, vals, scr, c);
-        for (int f = 0; f < F.k; ++f)
-            for (int q = 0; q < 9; ++q) coef[((int64_t)f * 9 + q) * n + i] = c[f * 9 + q];
-        if (flags) flags[i] = fl;
+        const uint8_t fl = qr_fit_point(v, g, i, r, F.k, own, vals, c);
+        if (lane == 0) {
+            for (int f = 0; f < F.k; ++f)
+                for (int q = 0; q < 9; ++q) coef[((int64_t)f * 9 + q) * n + i] = c[f * 9 + q];
+            if (flags) flags[i] = fl;
+        }
     }
 }
 
@@ -491,13 +543,14 @@ __global__ __launch_bounds__(QR_TPB) void k_pass1_qr(View v, StepOut o,
                                                     const unsigned int* redo_n,
                                                     Counters* cnt)
 {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    // a wavefront per refit
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const unsigned int total = *redo_n;
-    if (slot == 0) atomicAdd(&cnt->qr_refits, (unsigned long long)total);
-    __shared__ double sscr[QR_TPB][MAXROWS * 17];
-    double* scr = sscr[threadIdx.x];
-    for (int64_t t = slot; t < (int64_t)total; t += nth) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd(&cnt->qr_refits, (unsigned long long)total);
+    for (int64_t t = wave; t < (int64_t)total; t += nw) {
         const int64_t i = redo[t];
         const int s = sys_of(v.off, v.n_sys, i);
         const GridInfo& g = v.grid[s];
@@ -511,8 +564,8 @@ __global__ __launch_bounds__(QR_TPB) void k_pass1_qr(View v, StepOut o,
             }
         };
         double c[27], none[27];
-        const uint8_t fl = qr_fit_point(v, g, i, r, 3, own, vals, scr, c);
-        finish_pass1(v, v.prm[s], i, c, none, false, fl, o);
+        const uint8_t fl = qr_fit_point(v, g, i, r, 3, own, vals, c);
+        if (lane == 0) finish_pass1(v, v.prm[s], i, c, none, false, fl, o);
     }
 }
 
@@ -1001,13 +1054,13 @@ __global__ __launch_bounds__(QR_TPB) void k_pass2_qr(View v, const double* P,
                                                     const unsigned int* redo_n,
                                                     RhsOut o)
 {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    // a wavefront per refit
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const unsigned int total = *redo_n;
-    __shared__ double sscr[QR_TPB][MAXROWS * 17];
-    double* scr = sscr[threadIdx.x];
     const int64_t n = v.n;
-    for (int64_t t = slot; t < (int64_t)total; t += nth) {
+    for (int64_t t = wave; t < (int64_t)total; t += nw) {
         const int64_t i = redo[t];
         const int s = sys_of(v.off, v.n_sys, i);
         const GridInfo& g = v.grid[s];
@@ -1018,14 +1071,16 @@ __global__ __launch_bounds__(QR_TPB) void k_pass2_qr(View v, const double* P,
             pass2_values(v, P, eta, p, prm, out[0], out[1]);
         };
         double c[18];
-        const uint8_t fl = qr_fit_point(v, g, i, r, 2, own, vals, scr, c);
-        if (o.flags)
-            o.flags[i] = (uint8_t)((o.flags[i] & ~FLAG_LINEAR) | (fl & FLAG_LINEAR) | FLAG_QR);
-        const double gP[3] = {c[0], c[1], c[2]};
-        const double gE[3] = {c[9], c[10], c[11]};
-        double hv[11];
-        load_hand_tail(hand, n, i, eta[i], hv);
-        finish_rhs(v, prm, i, hv, gP, gE, o);
+        const uint8_t fl = qr_fit_point(v, g, i, r, 2, own, vals, c);
+        if (lane == 0) {
+            if (o.flags)
+                o.flags[i] = (uint8_t)((o.flags[i] & ~FLAG_LINEAR) | (fl & FLAG_LINEAR) | FLAG_QR);
+            const double gP[3] = {c[0], c[1], c[2]};
+            const double gE[3] = {c[9], c[10], c[11]};
+            double hv[11];
+            load_hand_tail(hand, n, i, eta[i], hv);
+            finish_rhs(v, prm, i, hv, gP, gE, o);
+        }
     }
 }
 
