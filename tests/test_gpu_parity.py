@@ -228,6 +228,44 @@ def test_step_parity_other_stencil_caps(lp, m_max):
         assert ok, (lp.DeviceState.NAMES[k], e)
 
 
+def test_qr_refit_rows_beyond_one_wavefront(lp):
+    """The QR refit holds stencil row k in lane k mod 64 of a wavefront, so
+    rows 64 and above sit in a second register slot.  At m_max = 64 on a
+    24^3 column with h = 1.35 lattice spacings, top-layer particles keep 64
+    rows plus ghost rows; with every stencil sent through the refit, the
+    step matches the oracle's run with the same cap."""
+    import dataclasses
+
+    import torch
+    wl = lpgen.column_bench(nx=24, ny=24, nz=24)
+    h = wl.params[0].h * 1.35
+    wl.params = [dataclasses.replace(p, h=h, R=2.5 * h) for p in wl.params]
+    print("case column 24^3, h x1.35, m_max 64, QR refit, n", wl.n, flush=True)
+    chk = lp.make_context(wl, m_max=64)
+    s2 = lp.DeviceState.from_host(wl.state)
+    chk.lp_build_cells(s2, want_perm=False)
+    nb = chk.lp_neighbors(s2, candidates=False)
+    rows = nb["sten_cnt"].to(torch.int64) + torch.stack(
+        [(nb["ghost_mask"].to(torch.int64) >> o) & 1 for o in range(8)]).sum(0)
+    n_big = int((rows > 64).sum())
+    _log("rows max %d, %d stencils above 64 rows" % (int(rows.max()), n_big))
+    assert n_big > 0
+    del chk, s2
+    ctx = lp.make_context(wl, m_max=64, debug_flags=lp.LP_DEBUG_QR_FIT)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    ctx.lp_step(st, wl.dt, perm)
+    ctx.sync_status()
+    assert ctx.stats()["qr_refits"] == wl.n
+    ost, operm, _ = oracle.step(wl.state, wl.offsets, wl.params, wl.dt,
+                                cfg=dict(m_max=64))
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    old = wl.state.take(operm)
+    for k, (a, b, c) in enumerate(zip(st.to_host().arrays(), ost.arrays(), old.arrays())):
+        ok, e = _incr_ok(a, b, c)
+        assert ok, (lp.DeviceState.NAMES[k], e)
+
+
 def test_neighbour_list_overflow_is_reported(lp):
     """A cluster denser than the neighbour list holds (more than 256
     entries within the list radius) latches LP_E_CAPACITY; every kernel
