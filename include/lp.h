@@ -239,6 +239,27 @@ lp_status lp_rheology_rhs(lp_ctx* ctx, const lp_state* s,
                           const double* coef_u, double* dVdt, double* acc,
                           double* diag, double* grad, uint8_t* flags);
 
+/* Record of one step (lp_step or lp_step2) for its adjoint: which
+ * particle order and which neighbour list the step used, so that
+ * lp_step_adjoint / lp_step2_adjoint can differentiate that same step
+ * without re-sorting or rebuilding the list.  Host struct owned by the
+ * caller; perm is a caller-owned device array.
+ *   force_sort (in):  1 makes the step re-sort and rebuild the list first
+ *                     whatever the skin allows (a trajectory starts each
+ *                     checkpointed segment this way, so that recomputing
+ *                     the segment from its checkpoint reproduces it);
+ *   resorted (out):   1 if the step re-sorted the state first, else 0;
+ *   list_gen (out):   generation of the neighbour list the step used
+ *                     (every list build makes a new generation);
+ *   perm (device int32[n], required): receives perm[new] = old of the
+ *                     re-sort when resorted = 1 (unwritten otherwise). */
+typedef struct {
+    int32_t force_sort;
+    int32_t resorted;
+    int64_t list_gen;
+    int32_t* perm;
+} lp_step_record;
+
 /* One explicit step (Sec. 3.1 steps 5-10): when the context has no
  * neighbour list yet, or some particle has moved skin R / 2 since it was
  * built (checked on the device; one synchronisation), the state is
@@ -248,8 +269,11 @@ lp_status lp_rheology_rhs(lp_ctx* ctx, const lp_state* s,
  * right-hand side, and
  *   V' = V + dt dVdt,  u' = u + dt acc,  x' = x + dt (u + u')/2.
  * The state must keep the order of the previous lp_step between calls.
+ * rec (optional, null to skip): filled as described at lp_step_record;
+ * with rec->force_sort = 1 the step re-sorts first.
  * dt > 0.  A non-finite result latches LP_E_NUMERIC (lp_sync_status). */
-lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
+lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm,
+                  lp_step_record* rec);
 
 /* One second-order step (Heun's predictor-corrector; the higher-order time
  * integration the conclusions list as further work, built from two
@@ -264,8 +288,9 @@ lp_status lp_step(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
  * that lp_sync_status reports as LP_E_STATE (reduce dt or raise skin).
  * Needs skin > 0 (LP_E_ARG otherwise).  State order, perm, dt and
  * non-finite results as for lp_step; the two kinds of step may alternate
- * on one state. */
-lp_status lp_step2(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm);
+ * on one state.  rec (optional) as for lp_step. */
+lp_status lp_step2(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm,
+                   lp_step_record* rec);
 
 /* Chooses how many adjacent lanes of a wavefront share one particle in
  * each of the two least-squares fit kernels (1, 2 or 4: each lane takes
@@ -298,9 +323,19 @@ lp_status lp_step_graph(lp_ctx* ctx, lp_state* s, int32_t* ids, double dt,
 
 /* Adjoint (reverse-mode derivative) of one step, for gradients of a loss
  * through the method (Sec. 3.1 steps 5-10 with the closure of Sec. 2.2 and
- * 2.2.1 and the right-hand side of Sec. 2.1).  The step differentiated is
- * lp_build_cells followed by lp_step on s: s is re-sorted by the context's
- * cells (perm[new] = old, written to perm if not null), then stepped.  Its
+ * 2.2.1 and the right-hand side of Sec. 2.1).
+ * Without a record (rec null) the step differentiated is lp_build_cells
+ * followed by lp_step on s: s is re-sorted by the context's cells
+ * (perm[new] = old, written to perm if not null), then stepped; the list
+ * is rebuilt for this call and the next lp_step rebuilds again.
+ * With the record of an lp_step (rec filled by lp_step on the same state
+ * s), the step differentiated is that lp_step: s is put into the order
+ * the step used (rec->perm when rec->resorted, else kept; perm receives
+ * that permutation or the identity) and the step's neighbour list is
+ * reused, which must still be the context's current list
+ * (rec->list_gen; LP_E_STATE otherwise, e.g. after a later re-sort or
+ * another call that rebuilt the list); the list stays valid afterwards.
+ * Either way its
  * stencils, ghost masks, linear-fallback choices and regime branches are
  * held fixed (they are piecewise constant in the state); the shear-rate
  * norm is given zero derivative where it is zero.
@@ -314,27 +349,30 @@ lp_status lp_step_graph(lp_ctx* ctx, lp_state* s, int32_t* ids, double dt,
  * weights (LP_E_ARG otherwise).  Neighbour contributions are accumulated
  * in per-row slots grouped by receiving particle (the slot order, and so
  * the summation order, varies between runs).  m_max x particles must stay
- * below 2^31 (LP_E_CAPACITY).  Leaves the
- * context without a neighbour list: the next lp_step rebuilds.  A
- * degenerate Gram matrix latches LP_E_NUMERIC (lp_sync_status). */
+ * below 2^31 (LP_E_CAPACITY).  A degenerate Gram matrix latches
+ * LP_E_NUMERIC (lp_sync_status). */
 lp_status lp_step_adjoint(lp_ctx* ctx, const lp_state* s, double dt,
                           const lp_state* adj_out, lp_state* adj_in,
-                          double* adj_params, int32_t* perm);
+                          double* adj_params, int32_t* perm,
+                          const lp_step_record* rec);
 
 /* Adjoint of one second-order step: lp_build_cells followed by lp_step2 on
- * s, reversed through both stages of Heun's rule with the stencils of s and
+ * s (rec null), or the lp_step2 that filled rec, reversed through both
+ * stages of Heun's rule with the stencils of s and
  * of the predictor s* held fixed (as lp_step_adjoint holds those of its
  * step):  with f = (u, acc, dVdt) and lam' = dL/d(s'),
  *   lam* = dL/d(s*) = J_f(s*)^T (dt/2 lam'),
  *   dL/d(s) = lam' + lam* + J_f(s)^T (dt (lam'/2 + lam*)).
- * Arguments, orders, float64 arithmetic, unit weights, capacity limit and
- * the effect on the context as for lp_step_adjoint; needs skin > 0, and the
+ * Arguments, orders, records, float64 arithmetic, unit weights, capacity
+ * limit and the effect on the context as for lp_step_adjoint; needs
+ * skin > 0, and the
  * predictor must stay within half the skin (else the error latches as in
  * lp_step2).  Recomputes the forward stages (pass 1 at s twice, once at
  * s*). */
 lp_status lp_step2_adjoint(lp_ctx* ctx, const lp_state* s, double dt,
                            const lp_state* adj_out, lp_state* adj_in,
-                           double* adj_params, int32_t* perm);
+                           double* adj_params, int32_t* perm,
+                           const lp_step_record* rec);
 
 /* Synchronises the context's stream and returns the first latched device
  * error (LP_OK if none), then clears it.  *index (host, optional)

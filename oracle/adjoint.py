@@ -270,11 +270,18 @@ class FrozenStep2(FrozenStep):
         return (*xn, *un, V + half * (d1 + d2))
 
 
+def _order(state, offsets, params, skin, sort):
+    if sort:
+        return sort_perm(state, offsets, params, skin)[0]
+    return np.arange(state.n, dtype=np.int32)
+
+
 def step2_vjp(state: State, offsets, params: Sequence[Params], dt: float,
-              lam: Sequence[np.ndarray], skin: float = SKIN_DEFAULT, brute=None):
+              lam: Sequence[np.ndarray], skin: float = SKIN_DEFAULT, brute=None,
+              sort: bool = True):
     """Adjoint of oracle.step2 (Morton re-sort, Heun step) at `state`, with
     the conventions of step_vjp."""
-    perm, _ = sort_perm(state, offsets, params, skin)
+    perm = _order(state, offsets, params, skin, sort)
     st = state.take(perm)
     st = State(*[np.ascontiguousarray(a) for a in st.arrays()])
     fs = FrozenStep2(st, offsets, params, dt, brute=brute)
@@ -288,11 +295,14 @@ def step2_vjp(state: State, offsets, params: Sequence[Params], dt: float,
 
 
 def step_vjp(state: State, offsets, params: Sequence[Params], dt: float,
-             lam: Sequence[np.ndarray], skin: float = SKIN_DEFAULT, brute=None):
+             lam: Sequence[np.ndarray], skin: float = SKIN_DEFAULT, brute=None,
+             sort: bool = True):
     """Adjoint of oracle.step (Morton re-sort, RHS, update) at `state`:
     lam is dL/d(new state) in the step's output order; returns
-    (dL/d(state) in the input order, dL/dtheta (n_sys x 3), perm)."""
-    perm, _ = sort_perm(state, offsets, params, skin)
+    (dL/d(state) in the input order, dL/dtheta (n_sys x 3), perm).  With
+    ``sort`` false the step keeps the given order (perm is the identity),
+    as oracle.step(sort=False) does."""
+    perm = _order(state, offsets, params, skin, sort)
     st = state.take(perm)
     st = State(*[np.ascontiguousarray(a) for a in st.arrays()])
     fs = FrozenStep(st, offsets, params, dt, brute=brute)

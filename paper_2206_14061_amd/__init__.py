@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (LP_DEBUG_GLOBAL_GATHER, LP_DEBUG_LANES2, LP_DEBUG_LANES4,
                    LP_DEBUG_QR_FIT, LP_DEBUG_SORTED_STENCIL, LP_FP32_REFINED,
                    LP_FP64, LP_W_GAUSS, LP_W_UNIT, LPConfig, LPError,
-                   LPParams, LPState)
+                   LPParams, LPState, LPStepRecord)
 
 FLAG_LINEAR = 1
 FLAG_QR = 8
@@ -85,6 +85,34 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+class StepRecord:
+    """lp_step_record of one step plus its device permutation array:
+    ``force_sort`` (set before the step), ``resorted`` and ``list_gen``
+    (filled by the step), ``perm`` (int32 device tensor, written when the
+    step re-sorted)."""
+
+    def __init__(self, n: int, force_sort: bool = False):
+        torch = _torch()
+        self.perm = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        self.s = LPStepRecord()
+        self.s.force_sort = 1 if force_sort else 0
+        self.s.resorted = 0
+        self.s.list_gen = -1
+        self.s.perm = self.perm.data_ptr()
+
+    @property
+    def resorted(self) -> bool:
+        return bool(self.s.resorted)
+
+    @property
+    def list_gen(self) -> int:
+        return int(self.s.list_gen)
+
+
+def _rec(rec: Optional[StepRecord]):
+    return None if rec is None else C.byref(rec.s)
+
+
 class Context:
     """An lp_ctx bound to the current CUDA device and stream."""
 
@@ -144,6 +172,8 @@ class Context:
         self._check(self.lib.lp_set_systems(self.h, ns, off, prm))
         self.n = int(offsets[-1])
         self.n_sys = ns
+        self.offsets = [int(v) for v in offsets]
+        self.params = list(params)
 
     # ---- entry points (names of the C ABI) --------------------------------
     def lp_build_cells(self, st: DeviceState, want_perm: bool = True):
@@ -217,14 +247,20 @@ class Context:
             out["flags"].data_ptr()))
         return out
 
-    def lp_step(self, st: DeviceState, dt: float, perm=None):
+    def lp_step(self, st: DeviceState, dt: float, perm=None,
+                rec: Optional[StepRecord] = None):
+        """One step in place; rec (optional) records it for lp_step_adjoint."""
         s = st.struct()
-        self._check(self.lib.lp_step(self.h, C.byref(s), float(dt), _ptr(perm)))
+        self._check(self.lib.lp_step(self.h, C.byref(s), float(dt), _ptr(perm),
+                                     _rec(rec)))
 
-    def lp_step2(self, st: DeviceState, dt: float, perm=None):
-        """Second-order (Heun) step; same state order and perm as lp_step."""
+    def lp_step2(self, st: DeviceState, dt: float, perm=None,
+                 rec: Optional[StepRecord] = None):
+        """Second-order (Heun) step; same state order, perm and record as
+        lp_step."""
         s = st.struct()
-        self._check(self.lib.lp_step2(self.h, C.byref(s), float(dt), _ptr(perm)))
+        self._check(self.lib.lp_step2(self.h, C.byref(s), float(dt), _ptr(perm),
+                                      _rec(rec)))
 
     def lp_autotune(self, st: DeviceState):
         """Times 1, 2 and 4 lanes per particle in both fits on st's stencils
@@ -242,21 +278,24 @@ class Context:
                                            int(nsteps)))
 
     def lp_step_adjoint(self, st: DeviceState, dt: float, adj_out: DeviceState,
-                        adj_params=None, want_perm: bool = False):
-        """Reverse of lp_build_cells + lp_step at st: returns dL/d(st) for
-        dL/d(output) = adj_out (and the permutation, if asked); adds
-        dL/d(mu_s, mu_2, I0) into adj_params (n_sys x 3, float64, device)."""
+                        adj_params=None, want_perm: bool = False,
+                        rec: Optional[StepRecord] = None):
+        """Reverse of lp_build_cells + lp_step at st (rec None), or of the
+        lp_step that filled rec: returns dL/d(st) for dL/d(output) = adj_out
+        (and the step's permutation, if asked); adds dL/d(mu_s, mu_2, I0)
+        into adj_params (n_sys x 3, float64, device)."""
         return self._adjoint(self.lib.lp_step_adjoint, st, dt, adj_out, adj_params,
-                             want_perm)
+                             want_perm, rec)
 
     def lp_step2_adjoint(self, st: DeviceState, dt: float, adj_out: DeviceState,
-                         adj_params=None, want_perm: bool = False):
-        """Reverse of lp_build_cells + lp_step2 at st (arguments as for
-        lp_step_adjoint)."""
+                         adj_params=None, want_perm: bool = False,
+                         rec: Optional[StepRecord] = None):
+        """Reverse of lp_build_cells + lp_step2 at st, or of the lp_step2
+        that filled rec (arguments as for lp_step_adjoint)."""
         return self._adjoint(self.lib.lp_step2_adjoint, st, dt, adj_out, adj_params,
-                             want_perm)
+                             want_perm, rec)
 
-    def _adjoint(self, fn, st, dt, adj_out, adj_params, want_perm):
+    def _adjoint(self, fn, st, dt, adj_out, adj_params, want_perm, rec=None):
         torch = _torch()
         adj_in = DeviceState([torch.empty_like(a) for a in st.t])
         if adj_params is None:
@@ -264,7 +303,7 @@ class Context:
         perm = torch.empty(st.n, dtype=torch.int32, device="cuda") if want_perm else None
         s, ao, ai = st.struct(), adj_out.struct(), adj_in.struct()
         self._check(fn(self.h, C.byref(s), float(dt), C.byref(ao), C.byref(ai),
-                       _ptr(adj_params), _ptr(perm)))
+                       _ptr(adj_params), _ptr(perm), _rec(rec)))
         return (adj_in, perm) if want_perm else adj_in
 
     def sync_status(self):

@@ -52,6 +52,11 @@ class LPState(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("x", "y", "z", "u", "v", "w", "V")]
 
 
+class LPStepRecord(C.Structure):
+    _fields_ = [("force_sort", C.c_int32), ("resorted", C.c_int32),
+                ("list_gen", C.c_int64), ("perm", C.c_void_p)]
+
+
 class LPError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
@@ -94,16 +99,16 @@ def load():
     lib.lp_fit_derivs.restype = C.c_int
     lib.lp_rheology_rhs.argtypes = [P, pp(LPState), P, P, P, P, P, P]
     lib.lp_rheology_rhs.restype = C.c_int
-    lib.lp_step.argtypes = [P, pp(LPState), C.c_double, P]
+    lib.lp_step.argtypes = [P, pp(LPState), C.c_double, P, pp(LPStepRecord)]
     lib.lp_step.restype = C.c_int
-    lib.lp_step2.argtypes = [P, pp(LPState), C.c_double, P]
+    lib.lp_step2.argtypes = [P, pp(LPState), C.c_double, P, pp(LPStepRecord)]
     lib.lp_step2.restype = C.c_int
     lib.lp_autotune.argtypes = [P, pp(LPState), pp(C.c_int32)]
     lib.lp_autotune.restype = C.c_int
     lib.lp_step_graph.argtypes = [P, pp(LPState), P, C.c_double, i32]
     lib.lp_step_graph.restype = C.c_int
     lib.lp_step_adjoint.argtypes = [P, pp(LPState), C.c_double, pp(LPState),
-                                    pp(LPState), P, P]
+                                    pp(LPState), P, P, pp(LPStepRecord)]
     lib.lp_step_adjoint.restype = C.c_int
     lib.lp_step2_adjoint.argtypes = lib.lp_step_adjoint.argtypes
     lib.lp_step2_adjoint.restype = C.c_int

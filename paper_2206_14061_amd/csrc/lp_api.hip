@@ -137,6 +137,46 @@ void drop_graph(lp_ctx* c)
     c->graph = nullptr;
 }
 
+// perm copy on the context's stream
+lp_status copy_perm(lp_ctx* c, const int32_t* src, int32_t* dst)
+{
+    if (!dst || src == dst || c->n == 0) return LP_OK;
+    hipError_t e = hipMemcpyAsync(dst, src, sizeof(int32_t) * c->n,
+                                  hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "permutation copy");
+}
+
+// Working copy of the state an adjoint differentiates, in the order of the
+// step it reverses.  Without a record: re-sorted and a list built as by
+// lp_build_cells (*order = that permutation).  With a record: the step's
+// own order (*order = rec->perm, or null for the identity) and its list,
+// which must still be current.
+lp_status adjoint_order(lp_ctx* c, double* const in[7], const lp_step_record* rec,
+                        const int32_t** order)
+{
+    if (!rec) {
+        *order = c->w.adj_perm;
+        return cells_build(c, in, c->w.adj_perm);
+    }
+    if (!c->list_ok || rec->list_gen != c->list_gen) {
+        c->err = "the neighbour list of the recorded step is no longer current "
+                 "(the list was rebuilt since): recompute the step";
+        return LP_E_STATE;
+    }
+    const double* cin[7];
+    for (int a = 0; a < 7; ++a) cin[a] = in[a];
+    if (rec->resorted) {
+        if (!rec->perm) {
+            c->err = "a re-sorted step record needs its perm array";
+            return LP_E_ARG;
+        }
+        *order = rec->perm;
+        return state_gather(c, cin, rec->perm);
+    }
+    *order = nullptr;
+    return state_copy(c, in, nullptr, nullptr, true);
+}
+
 // One step with no host synchronisation: device-side rebuild decision,
 // gated re-sort + list rebuild or state copy, stencils, fits, update into
 // the caller's arrays.
@@ -443,10 +483,15 @@ lp_status lp_rheology_rhs(lp_ctx* c, const lp_state* s, const double* coef_u,
     return rhs_from_coef(c, st, coef_u, dVdt, acc, diag, grad, flags);
 }
 
-lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
+lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
+                  lp_step_record* rec)
 {
     if (!s || !(dt > 0.0) || !std::isfinite(dt)) {
         if (c) c->err = "lp_step: dt must be positive and finite";
+        return LP_E_ARG;
+    }
+    if (rec && !rec->perm) {
+        if (c) c->err = "lp_step: a step record needs its perm array";
         return LP_E_ARG;
     }
     lp_status r = check_ready(c, s);
@@ -456,7 +501,7 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
     prof_mark(c, 0, false);
     // the neighbour list stays valid until some particle has moved half
     // the skin since the last build
-    bool rebuild = !c->list_ok || !(c->cfg.skin > 0.0);
+    bool rebuild = !c->list_ok || !(c->cfg.skin > 0.0) || (rec && rec->force_sort);
     if (!rebuild) {
         // the check also copies the state, which a rebuild then overwrites
         double ratio = -1.0;
@@ -464,11 +509,20 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
         if (r != LP_OK) return r;
         rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.49);
     }
-    r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm, nullptr, false);
+    if (rebuild) {
+        r = cells_build(c, in, rec ? rec->perm : perm);
+        if (r == LP_OK && rec && perm) r = copy_perm(c, rec->perm, perm);
+    } else {
+        r = state_copy(c, in, perm, nullptr, false);
+    }
     if (r == LP_OK && !c->map_ok) r = tile_map_build(c);
     prof_mark(c, 0, true);
     if (r != LP_OK) return r;
     if (rebuild) ++c->rebuilds;
+    if (rec) {
+        rec->resorted = rebuild ? 1 : 0;
+        rec->list_gen = c->list_gen;
+    }
     const double* sorted[7];
     double* const* sst = c->w.sst;
     for (int a = 0; a < 7; ++a) sorted[a] = sst[a];
@@ -491,10 +545,15 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
     return r;
 }
 
-lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
+lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
+                   lp_step_record* rec)
 {
     if (!s || !(dt > 0.0) || !std::isfinite(dt)) {
         if (c) c->err = "lp_step2: dt must be positive and finite";
+        return LP_E_ARG;
+    }
+    if (rec && !rec->perm) {
+        if (c) c->err = "lp_step2: a step record needs its perm array";
         return LP_E_ARG;
     }
     lp_status r = check_ready(c, s);
@@ -508,7 +567,7 @@ lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
     state_arrays(s, in);
     // rebuild earlier than lp_step: the predictor stage moves particles a
     // further dt |u| on the same list and must stay within half the skin
-    bool rebuild = !c->list_ok;
+    bool rebuild = !c->list_ok || (rec && rec->force_sort);
     if (!rebuild) {
         // the check also copies the state, which a rebuild then overwrites
         double ratio = -1.0;
@@ -516,10 +575,19 @@ lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm)
         if (r != LP_OK) return r;
         rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.4);
     }
-    r = rebuild ? cells_build(c, in, perm) : state_copy(c, in, perm, nullptr, false);
+    if (rebuild) {
+        r = cells_build(c, in, rec ? rec->perm : perm);
+        if (r == LP_OK && rec && perm) r = copy_perm(c, rec->perm, perm);
+    } else {
+        r = state_copy(c, in, perm, nullptr, false);
+    }
     if (r == LP_OK && !c->map_ok) r = tile_map_build(c);
     if (r != LP_OK) return r;
     if (rebuild) ++c->rebuilds;
+    if (rec) {
+        rec->resorted = rebuild ? 1 : 0;
+        rec->list_gen = c->list_gen;
+    }
     const double* sorted[7];
     for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
     r = stencils_build(c, sorted);
@@ -647,6 +715,9 @@ lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,
     }
     hipError_t e = hipGraphLaunch(c->gexec, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+    // the replay may have rebuilt the list on the device: records of
+    // earlier steps no longer describe the current list
+    ++c->list_gen;
     c->stencils_ok = false;
     c->built_x = nullptr;
     return LP_OK;
@@ -654,7 +725,8 @@ lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,
 
 lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
                           const lp_state* adj_out, lp_state* adj_in,
-                          double* adj_params, int32_t* perm)
+                          double* adj_params, int32_t* perm,
+                          const lp_step_record* rec)
 {
     if (!s || !adj_out || !adj_in || !adj_params || !(dt > 0.0) || !std::isfinite(dt)) {
         if (c) c->err = "lp_step_adjoint: null argument or dt not positive";
@@ -674,7 +746,8 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
     }
     double* in[7];
     state_arrays(s, in);
-    r = cells_build(c, in, c->w.adj_perm);
+    const int32_t* order = nullptr;
+    r = adjoint_order(c, in, rec, &order);
     const double* sorted[7];
     for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
     if (r == LP_OK) r = stencils_build(c, sorted);
@@ -687,14 +760,12 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
     for (int a = 0; a < 7; ++a) seed.A[a] = lam_in[a];
     seed.c_ux = seed.c_a = seed.c_d = dt;
     seed.k_x = 0.5 * dt;
-    if (r == LP_OK) r = step_adjoint(c, sorted, seed, out, adj_params, c->w.adj_perm);
-    if (r == LP_OK && perm) {
-        hipError_t e = hipMemcpyAsync(perm, c->w.adj_perm, sizeof(int32_t) * c->n,
-                                      hipMemcpyDeviceToDevice, c->stream);
-        if (e != hipSuccess) r = hip_fail(c, e, "adjoint perm copy");
-    }
-    // the working state now belongs to this call: the next lp_step rebuilds
-    c->list_ok = false;
+    if (r == LP_OK) r = step_adjoint(c, sorted, seed, out, adj_params, order);
+    if (r == LP_OK && perm) r = order ? copy_perm(c, order, perm)
+                                      : state_copy(c, nullptr, perm, nullptr, false);
+    // without a record the list was built for this call: the next lp_step
+    // rebuilds
+    if (!rec) c->list_ok = false;
     c->stencils_ok = false;
     c->built_x = nullptr;
     return r;
@@ -702,7 +773,8 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
 
 lp_status lp_step2_adjoint(lp_ctx* c, const lp_state* s, double dt,
                            const lp_state* adj_out, lp_state* adj_in,
-                           double* adj_params, int32_t* perm)
+                           double* adj_params, int32_t* perm,
+                           const lp_step_record* rec)
 {
     if (!s || !adj_out || !adj_in || !adj_params || !(dt > 0.0) || !std::isfinite(dt)) {
         if (c) c->err = "lp_step2_adjoint: null argument or dt not positive";
@@ -737,8 +809,10 @@ lp_status lp_step2_adjoint(lp_ctx* c, const lp_state* s, double dt,
         sorted[a] = w.sst[a];
         pred[a] = w.sst2[a];
     }
-    // forward: s (re-sorted), f(s) in float64, predictor s*, its stencils
-    r = cells_build(c, in, w.adj_perm);
+    // forward: s (in the step's order), f(s) in float64, predictor s*, its
+    // stencils
+    const int32_t* order = nullptr;
+    r = adjoint_order(c, in, rec, &order);
     if (r == LP_OK) r = stencils_build(c, sorted);
     if (r == LP_OK) r = step_pass1_coef(c, sorted);
     if (r == LP_OK) r = step_pass2(c, sorted, 0.0, nullptr, w.acc, w.dVdt, true);
@@ -765,13 +839,10 @@ lp_status lp_step2_adjoint(lp_ctx* c, const lp_state* s, double dt,
     s1.nA = 0.5;
     s1.nB = 1.0;
     s1.c_ux = s1.c_a = s1.c_d = dt;
-    if (r == LP_OK) r = step_adjoint(c, sorted, s1, out, adj_params, w.adj_perm);
-    if (r == LP_OK && perm) {
-        hipError_t e = hipMemcpyAsync(perm, w.adj_perm, sizeof(int32_t) * c->n,
-                                      hipMemcpyDeviceToDevice, c->stream);
-        if (e != hipSuccess) r = hip_fail(c, e, "adjoint perm copy");
-    }
-    c->list_ok = false;
+    if (r == LP_OK) r = step_adjoint(c, sorted, s1, out, adj_params, order);
+    if (r == LP_OK && perm) r = order ? copy_perm(c, order, perm)
+                                      : state_copy(c, nullptr, perm, nullptr, false);
+    if (!rec) c->list_ok = false;
     c->stencils_ok = false;
     c->built_x = nullptr;
     return r;

@@ -710,6 +710,19 @@ lp_status permute_ids(lp_ctx* c, const int32_t* perm, int32_t* ids)
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "id permutation");
 }
 
+lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    if (n > 0)
+        hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
+                           perm, st[0], st[1], st[2], st[3], st[4], st[5], st[6],
+                           w.sst[0], w.sst[1], w.sst[2], w.sst[3], w.sst[4],
+                           w.sst[5], w.sst[6], nullptr);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "state gather");
+}
+
 lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force)
 {
     Work& w = c->w;

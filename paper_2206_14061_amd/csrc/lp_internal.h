@@ -219,6 +219,7 @@ struct lp_ctx {
     int64_t total_cells = 0;
     int64_t n_mirror = 0;
     bool list_ok = false;       // neighbour list valid for the working state
+    int64_t list_gen = 0;       // generation of the current list (one per build)
     int lpp1 = 1, lpp2 = 1;     // lanes per particle of the two fit kernels
     int64_t rebuilds = 0;       // list rebuilds since the last lp_stats
     // phase timing (lp_profile)
@@ -369,6 +370,8 @@ lp_status cells_build_device(lp_ctx* c, double* const st[7], int32_t* ids,
                              const int32_t* gate, int bits);
 // ids[i] = ids[perm[i]]
 lp_status permute_ids(lp_ctx* c, const int32_t* perm, int32_t* ids);
+// working copy of st in the order perm (sst[new] = st[perm[new]])
+lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm);
 // Device-side rebuild decision into w.gate (no synchronisation).
 lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force);
 // Copies the working copy back into the caller's arrays.

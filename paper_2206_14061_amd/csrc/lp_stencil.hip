@@ -955,6 +955,7 @@ lp_status list_build(lp_ctx* c, const int32_t* gate)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "list build launch");
     c->list_ok = true;
+    ++c->list_gen;
     // an eager build leaves the tile map stale (captured steps rebuild the
     // map under the same gate right after the list)
     if (!gate) c->map_ok = false;

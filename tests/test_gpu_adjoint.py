@@ -232,3 +232,172 @@ def test_second_order_trajectory_gradient_matches_composed_oracle_adjoint(lp):
     e = np.max(np.abs(theta.grad.cpu().numpy() - gth)) / np.max(np.abs(gth))
     _log("  dL/dtheta rel err %.3e" % e)
     assert e <= 1e-8
+
+
+@pytest.mark.parametrize("kind", ["step", "step2"])
+@pytest.mark.parametrize("case", ["column16_flow_ragged", "ensemble_3", "periodic_xy"])
+def test_recorded_step_adjoint_parity(lp, case, kind):
+    """Step records: a step that kept the order (its list built by
+    lp_build_cells on the same state) and a step with a forced re-sort,
+    each reversed by the adjoint with the step's record (the recorded list
+    reused, no rebuild), against the oracle's adjoint of the same step (the
+    first with the order kept, the second with the Morton re-sort)."""
+    import torch
+    wl = CASES[case]()
+    _log("case %s %s n=%d (recorded adjoint)" % (case, kind, wl.n))
+    lam = _lam(wl, 51)
+    vjp = adjoint.step2_vjp if kind == "step2" else adjoint.step_vjp
+    ctx = lp.make_context(wl)
+    step = ctx.lp_step2 if kind == "step2" else ctx.lp_step
+    adj = ctx.lp_step2_adjoint if kind == "step2" else ctx.lp_step_adjoint
+    # kept order
+    st = lp.DeviceState.from_host(wl.state)
+    ctx.lp_build_cells(st, want_perm=False)
+    s0 = st.clone()
+    rec = lp.StepRecord(wl.n)
+    step(st, wl.dt, rec=rec)
+    assert not rec.resorted
+    ost = s0.to_host()
+    want, wth, _ = vjp(ost, wl.offsets, wl.params, wl.dt, lam, sort=False)
+    dth = torch.zeros(len(wl.params), 3, dtype=torch.float64, device="cuda")
+    gen = rec.list_gen
+    got, perm = adj(s0, wl.dt, _dev(lam), dth, want_perm=True, rec=rec)
+    ctx.sync_status()
+    assert np.array_equal(perm.cpu().numpy(), np.arange(wl.n))
+    for k, (a, b) in enumerate(zip(got.to_host().arrays(), want)):
+        e = _relerr(a, b)
+        _log("  kept order d/d%s rel err %.3e" % (lp.DeviceState.NAMES[k], e))
+        assert e <= TOL, (lp.DeviceState.NAMES[k], e)
+    e = np.max(np.abs(dth.cpu().numpy() - wth)) / max(np.max(np.abs(wth)), 1e-300)
+    assert e <= 1e-9
+    # the adjoint keeps the list: a second adjoint with the same record
+    # gives the same result, and the next step reuses the list
+    got2 = adj(s0, wl.dt, _dev(lam), None, rec=rec)
+    for a, b in zip(got2.to_host().arrays(), got.to_host().arrays()):
+        assert _relerr(a, b) <= 1e-13
+    rec2 = lp.StepRecord(wl.n)
+    step(st, wl.dt, rec=rec2)
+    assert not rec2.resorted and rec2.list_gen == gen
+    # forced re-sort
+    st = lp.DeviceState.from_host(wl.state)
+    s0 = st.clone()
+    rec = lp.StepRecord(wl.n, force_sort=True)
+    step(st, wl.dt, rec=rec)
+    assert rec.resorted
+    want, wth, operm = vjp(wl.state, wl.offsets, wl.params, wl.dt, lam)
+    assert np.array_equal(rec.perm.cpu().numpy(), operm)
+    dth = torch.zeros(len(wl.params), 3, dtype=torch.float64, device="cuda")
+    got, perm = adj(s0, wl.dt, _dev(lam), dth, want_perm=True, rec=rec)
+    ctx.sync_status()
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    for k, (a, b) in enumerate(zip(got.to_host().arrays(), want)):
+        e = _relerr(a, b)
+        _log("  re-sorted d/d%s rel err %.3e" % (lp.DeviceState.NAMES[k], e))
+        assert e <= TOL, (lp.DeviceState.NAMES[k], e)
+    e = np.max(np.abs(dth.cpu().numpy() - wth)) / max(np.max(np.abs(wth)), 1e-300)
+    assert e <= 1e-9
+
+
+def test_stale_step_record_is_refused(lp):
+    """A record whose list has been rebuilt since (here by lp_build_cells)
+    is refused with LP_E_STATE; the call writes nothing."""
+    wl = CASES["column16_flow_ragged"]()
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    s0 = st.clone()
+    rec = lp.StepRecord(wl.n, force_sort=True)
+    ctx.lp_step(st, wl.dt, rec=rec)
+    ctx.lp_build_cells(st.clone(), want_perm=False)
+    with pytest.raises(lp.LPError) as e:
+        ctx.lp_step_adjoint(s0, wl.dt, _dev(_lam(wl, 3)), rec=rec)
+    assert e.value.status == 5
+    ctx.sync_status()
+
+
+def _trajectory_grads(lp, wl, ctx, steps, every, xs, theta0, between=None):
+    import torch
+    from paper_2206_14061_amd.autograd import simulate
+    h = wl.params[0].h
+    state = [torch.tensor(a, device="cuda", requires_grad=True)
+             for a in wl.state.arrays()]
+    theta = torch.tensor(theta0, device="cuda", requires_grad=True)
+    out = simulate(ctx, wl.offsets, wl.params, state, theta, wl.dt, steps,
+                   checkpoint_every=every)
+    loss = torch.nn.functional.softplus((out[0] - xs) / h).sum()
+    if between is not None:
+        between()
+    loss.backward()
+    ctx.sync_status()
+    return loss.item(), [a.grad.cpu().numpy() for a in state], theta.grad.cpu().numpy()
+
+
+def _oracle_trajectory(wl, steps, xs):
+    h = wl.params[0].h
+    st, states = wl.state, []
+    for _ in range(steps):
+        states.append(st)
+        st, _, _ = oracle.step(st, wl.offsets, wl.params, wl.dt)
+    t = (st.x - xs) / h
+    lamo = [1.0 / (1.0 + np.exp(-t)) / h] + [np.zeros(wl.n) for _ in range(6)]
+    gth = np.zeros((len(wl.params), 3))
+    for s in reversed(states):
+        lamo, g, _ = adjoint.step_vjp(s, wl.offsets, wl.params, wl.dt, lamo)
+        gth += g
+    return float(np.sum(np.logaddexp(0.0, t))), lamo, gth
+
+
+def test_trajectory_with_resorts_inside_segments(lp):
+    """A small skin (0.02 R) and a fast flow make lp_step re-sort inside the
+    checkpointed segments (6 steps, checkpoints every 3): the recorded
+    backward recomputes the part of a segment before its re-sort and still
+    matches the oracle's step adjoints composed in reverse."""
+    wl = CASES["column16_flow_ragged"]()
+    st0 = wl.state
+    for a in (st0.u, st0.v, st0.w):
+        a *= 20.0
+    steps, every, xs = 6, 3, 0.6
+    ctx = lp.make_context(wl, skin=0.02)
+    theta0 = adjoint.theta_of(wl.params)
+    loss, g, gth = _trajectory_grads(lp, wl, ctx, steps, every, xs, theta0)
+    rebuilds = ctx.stats()["rebuilds"]
+    _log("  list rebuilds over forward and backward: %d" % rebuilds)
+    # forward: 2 forced; backward: 2 forced + recomputed parts; more means
+    # re-sorts inside segments
+    assert rebuilds > 4
+    oloss, lamo, ogth = _oracle_trajectory(wl, steps, xs)
+    assert abs(loss - oloss) <= 1e-9 * oloss
+    for k, (a, b) in enumerate(zip(g, lamo)):
+        e = _relerr(a, b)
+        _log("  dL/d%s0 rel err %.3e" % (lp.DeviceState.NAMES[k], e))
+        assert e <= 1e-9
+    e = np.max(np.abs(gth - ogth)) / np.max(np.abs(ogth))
+    _log("  dL/dtheta rel err %.3e" % e)
+    assert e <= 1e-8
+
+
+def test_backward_uses_its_own_forward_parameters(lp):
+    """Another simulate() with other parameters (and another set of systems
+    on the context) between a forward pass and its backward pass leaves the
+    gradients unchanged: the backward pass recomputes with the parameters
+    of its own forward pass."""
+    import torch
+
+    from paper_2206_14061_amd.autograd import simulate
+    wl = CASES["ensemble_3"]()
+    steps, every, xs = 4, 2, 0.3
+    theta0 = adjoint.theta_of(wl.params)
+    ctx = lp.make_context(wl)
+    ref = _trajectory_grads(lp, wl, ctx, steps, every, xs, theta0)
+
+    def other_run():
+        th = torch.tensor(theta0 * 1.3, device="cuda")
+        st = [torch.tensor(a, device="cuda") for a in wl.state.arrays()]
+        simulate(ctx, wl.offsets, wl.params, st, th, wl.dt, 3, checkpoint_every=2)
+        ctx.set_systems([0, wl.n], wl.params[:1])
+
+    got = _trajectory_grads(lp, wl, ctx, steps, every, xs, theta0, between=other_run)
+    assert got[0] == ref[0]
+    for a, b in zip(got[1], ref[1]):
+        assert _relerr(a, b) <= 1e-12
+    assert np.max(np.abs(got[2] - ref[2])) <= 1e-12 * np.max(np.abs(ref[2]))
+    assert ctx.n_sys == 1

@@ -49,6 +49,10 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.LPParams) == 20 * 8
     assert ctypes.sizeof(_lib.LPConfig) == 72
     assert ctypes.sizeof(_lib.LPState) == 7 * 8
+    # lp_step_record: force_sort, resorted (int32), list_gen (int64), perm
+    assert ctypes.sizeof(_lib.LPStepRecord) == 24
+    assert _lib.LPStepRecord.list_gen.offset == 8
+    assert _lib.LPStepRecord.perm.offset == 16
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
