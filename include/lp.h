@@ -374,6 +374,28 @@ lp_status lp_step2_adjoint(lp_ctx* ctx, const lp_state* s, double dt,
                            double* adj_params, int32_t* perm,
                            const lp_step_record* rec);
 
+/* Allocation-free step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): one lp_step on a fresh context with configuration
+ * cfg (null: defaults) and the given systems (n_sys, host offsets and
+ * params as for lp_set_systems) on `stream`, i.e. re-sort and list build
+ * (perm[new] = old, optional), stencils, fits, closure, right-hand side
+ * and update of s in place, then lp_sync_status.  No context is created
+ * and nothing is allocated: the workspace is a static device array of
+ * about 46 MB (44 MiB) that each device the library runs on holds until the
+ * process ends, set up on a device's first call.  Limits: at most 16384
+ * particles, 64 systems and 65536 cells; beyond them LP_E_CAPACITY (the
+ * particle and system counts are checked before any work is enqueued).
+ * Returns LP_E_ARG for invalid arguments or configuration, and the status
+ * lp_sync_status would give for device-side errors (no text: there is no
+ * context to hold it).  Every call on a device shares that device's
+ * array, so calls that overlap on one device race (the library serialises
+ * host threads, not streams); each call clears what it needs and keeps
+ * nothing from the previous call.  Synchronises `stream`. */
+lp_status lp_step_noalloc(void* stream, const lp_config* cfg, int32_t n_sys,
+                          const int64_t* offsets, const lp_params* params,
+                          lp_state* s, double dt, int32_t* perm);
+
 /* Synchronises the context's stream and returns the first latched device
  * error (LP_OK if none), then clears it.  *index (host, optional)
  * receives the first offending particle or -1. */

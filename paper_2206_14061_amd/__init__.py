@@ -334,6 +334,29 @@ class Context:
                     unstaged_tiles=out[6], tiles=out[7])
 
 
+def lp_step_noalloc(offsets: Sequence[int], params: Sequence, st: DeviceState,
+                    dt: float, perm=None, stream=None, **cfg) -> None:
+    """One step of st in place through the allocation-free entry point (no
+    context; a static device workspace of at most 16384 particles); cfg
+    fields as for Context.  Raises LPError on failure."""
+    torch = _torch()
+    lib = _lib.load()
+    c = LPConfig()
+    lib.lp_config_default(C.byref(c))
+    for k, v in cfg.items():
+        setattr(c, k, v)
+    ns = len(params)
+    off = (C.c_int64 * (ns + 1))(*[int(v) for v in offsets])
+    prm = (LPParams * ns)(*[params_struct(p) for p in params])
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    s = st.struct()
+    rc = lib.lp_step_noalloc(C.c_void_p(stream.cuda_stream), C.byref(c), ns, off, prm,
+                             C.byref(s), float(dt), _ptr(perm))
+    if rc != 0:
+        raise LPError(rc, "lp_step_noalloc failed")
+
+
 def make_context(workload, **cfg) -> Context:
     """Context reserved and configured for an lpgen.Workload."""
     ctx = Context(**cfg)

@@ -27,7 +27,8 @@ EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_last_error",
            "lp_reserve", "lp_set_systems", "lp_build_cells", "lp_neighbors",
            "lp_fit_derivs", "lp_rheology_rhs", "lp_step", "lp_step2", "lp_autotune",
            "lp_step_graph", "lp_step_adjoint", "lp_step2_adjoint",
-           "lp_sync_status", "lp_stats", "lp_profile", "lp_profile_read"]
+           "lp_sync_status", "lp_stats", "lp_profile", "lp_profile_read",
+           "lp_step_noalloc"]
 
 
 class LPParams(C.Structure):
@@ -112,6 +113,9 @@ def load():
     lib.lp_step_adjoint.restype = C.c_int
     lib.lp_step2_adjoint.argtypes = lib.lp_step_adjoint.argtypes
     lib.lp_step2_adjoint.restype = C.c_int
+    lib.lp_step_noalloc.argtypes = [P, pp(LPConfig), i32, pp(C.c_int64),
+                                    pp(LPParams), pp(LPState), C.c_double, P]
+    lib.lp_step_noalloc.restype = C.c_int
     lib.lp_sync_status.argtypes = [P, pp(C.c_int64)]
     lib.lp_sync_status.restype = C.c_int
     lib.lp_stats.argtypes = [P, pp(C.c_int64)]

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "liblp_gfx950.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["lp_api.hip", "lp_cells.hip", "lp_stencil.hip", "lp_fit.hip",
+SOURCES = ["lp_api.hip", "lp_cells.hip", "lp_stencil.hip", "lp_fit.hip", "lp_noalloc.hip",
            "lp_adjoint.hip", "lp_rk2.hip", "lp_cubic.hip"]
 # sources whose float64 decisions must round exactly like the plain
 # definitions (cell coordinates, candidate test, keys): no FMA contraction

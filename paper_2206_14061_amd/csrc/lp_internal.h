@@ -202,6 +202,51 @@ struct Work {
     int64_t* coff = nullptr;
 };
 
+// Every workspace buffer and its element count, in one place.  A(p, count)
+// receives each buffer pointer; lp_reserve allocates them, the
+// allocation-free step carves them from a static device array.  With
+// forward_only, the buffers only the adjoints, the second-order step,
+// captured steps and the candidate export use are left out (null).
+template <class F>
+constexpr void work_layout(Work& w, int64_t n_max, int64_t cells_max, int mm,
+                           int sys_cap, bool forward_only, F&& A)
+{
+    const int64_t nb = (n_max + SORT_TILE - 1) / SORT_TILE;
+    const int64_t tiles = (n_max + BLOCK - 1) / BLOCK;
+    A(w.off, sys_cap + 1); A(w.prm, sys_cap); A(w.grid, sys_cap);
+    A(w.bbox, 6 * sys_cap); A(w.summary, 1); A(w.err, 1); A(w.cnt, 1);
+    A(w.keys0, n_max); A(w.keys1, n_max); A(w.vals0, n_max); A(w.vals1, n_max);
+    A(w.hist, 256 * nb);
+    for (int a = 0; a < 7; ++a) A(w.sst[a], n_max);
+    for (int a = 0; a < 3; ++a) A(w.xref[a], n_max);
+    A(w.mirror_of, n_max); A(w.msrc, n_max); A(w.bsum, nb + 1);
+    A(w.cs, cells_max); A(w.ce, cells_max);
+    A(w.vl, (int64_t)VCAP * n_max); A(w.vcnt, n_max);
+    A(w.tile_src, (int64_t)STAGE_CAP * tiles);
+    A(w.tile_cnt, tiles);
+    A(w.vs, (int64_t)VCAP * n_max);
+    A(w.code, (int64_t)(VCAP / 4) * n_max);
+    A(w.kmask, (int64_t)MASK_WORDS * n_max);
+    A(w.rec, (int64_t)REC_FIELDS * n_max); A(w.hsten, (int64_t)mm * n_max);
+    A(w.hard, n_max); A(w.hard_n, 1);
+    A(w.redo, n_max); A(w.redo_n, 1);
+    A(w.P, n_max); A(w.eta, n_max); A(w.hand, (int64_t)HAND * n_max);
+    A(w.uf, (int64_t)45 * n_max);
+    A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
+    if (forward_only) return;
+    for (int a = 0; a < 7; ++a) A(w.adj[a], n_max);
+    A(w.adj_P, n_max); A(w.adj_E, n_max); A(w.adj_stash, (int64_t)11 * n_max);
+    A(w.coefu, (int64_t)27 * n_max); A(w.adj_perm, n_max);
+    A(w.adj_slot, (int64_t)mm * n_max); A(w.adj_contrib, (int64_t)6 * mm * n_max);
+    A(w.adj_cnt, n_max); A(w.adj_fill, n_max); A(w.adj_off, n_max + 1);
+    A(w.adj_tile, n_max / BLOCK + 2);
+    A(w.gate, 4); A(w.ids_tmp, n_max);
+    for (int a = 0; a < 7; ++a) A(w.sst2[a], n_max);
+    for (int a = 0; a < 7; ++a) A(w.adj2[a], n_max);
+    A(w.acc2, 3 * n_max); A(w.dVdt2, n_max);
+    A(w.coff, n_max + 1);
+}
+
 }  // namespace lp
 
 struct lp_ctx {
