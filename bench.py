@@ -33,8 +33,10 @@ if ROOT not in sys.path:
 
 METRIC = "particle-updates/s per RHS eval (FP64 vs refined FP32) + adjoint steps/s"
 
-# Peaks of one MI355X (published): FP64 vector 78.6 TFLOP/s, HBM 8 TB/s.
+# Peaks of one MI355X (published): FP64 vector 78.6 TFLOP/s, FP32 vector
+# 157.3 TFLOP/s, HBM 8 TB/s.
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 # Algorithmic work of the pass-1 kernel per particle (fit of u, v, w on a
@@ -46,6 +48,13 @@ PASS1_FLOP_PER_PARTICLE = 16.2e3
 # 60 x (45 Gram + 27 moment FMAs = 144 flop + 12 row flop) + ~1.4k for the
 # Cholesky factor, 3 solves, 3 rows of G^-1 and the closure.
 PASS1_FLOP_EXECUTED = 60 * 156 + 1.4e3
+# The refined-FP32 pass-1 kernel per particle at 60 rows: a float32 sweep
+# of Gram moments (as the FP64 kernel: 60 x 156 flop plus a float32
+# Cholesky and solves, ~1.0k), and a float64 residual sweep (per row: 12
+# row flop, 3 residuals of 9 FMAs, 3 x 9 FMAs into A^T r = 120 flop) with
+# the correction solves (~0.4k).
+PASS1_REF_FLOP_F32 = 60 * 156 + 1.0e3
+PASS1_REF_FLOP_F64 = 60 * 120 + 0.4e3
 # Average neighbour-list length of the benchmark column (reals within
 # R (1 + skin) plus potential mirror sources; mean over 20,000 sampled
 # particles of lpgen.column_bench()).
@@ -69,7 +78,8 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="time budget of the one-thread oracle runs")
     ap.add_argument("--adjoint-steps", type=int, default=50)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-sheared", action="store_true")
@@ -79,6 +89,8 @@ def _parse():
     ap.add_argument("--no-second-order", action="store_true")
     ap.add_argument("--no-layer", action="store_true")
     ap.add_argument("--no-cubic", action="store_true")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the per-output errors against the oracle")
     ap.add_argument("--collapse", action="store_true",
                     help="also run the a = 0.6 column collapse (Sec. 4.2.1) and "
                          "report its runout against the empirical fits")
@@ -404,9 +416,12 @@ def ensemble_bench(torch, lp, lpgen, steps: int, adjoint_steps: int):
                      "ms_per_step": 1e3 * t / steps, "stats": ctx.stats()}
         del ctx, st, ids
     out["fp32r_speedup_vs_fp64"] = out["fp32r"]["value"] / out["fp64"]["value"]
-    # forward + adjoint (checkpointed, eager steps).  Runout target of each
-    # column: 5 cm beyond its initial right face; particles stay in their
-    # system's index range through re-sorts, so targets are set by index.
+    # forward + adjoint (checkpointed, eager steps), from a seeded smooth
+    # flow (0.5 m/s, wavelength 8h) so that particles leave the
+    # quasi-static branch and mu(I) acts.  Runout target of each column:
+    # 5 cm beyond its initial right face; particles stay in their system's
+    # index range through re-sorts, so targets are set by index.
+    wl = lpgen.with_shear_velocity(wl)
     ctx = lp.make_context(wl)
     h = wl.params[0].h
     off = wl.offsets
@@ -431,7 +446,10 @@ def ensemble_bench(torch, lp, lpgen, steps: int, adjoint_steps: int):
     out["adjoint"] = {"steps": adjoint_steps, "checkpoint_every": 10,
                       "step_pairs_per_s": adjoint_steps / (t2 - t0),
                       "ms_forward": 1e3 * (t1 - t0), "ms_backward": 1e3 * (t2 - t1),
-                      "max_abs_dL_dtheta": float(theta.grad.abs().max().item())}
+                      "initial_velocity": "seeded smooth field, 0.5 m/s, wavelength 8h",
+                      "max_abs_dL_dtheta": float(theta.grad.abs().max().item()),
+                      "systems_with_nonzero_dL_dtheta":
+                          int((theta.grad.abs().amax(dim=1) > 0).sum().item())}
     return out
 
 
@@ -448,23 +466,154 @@ def copy_calibration(torch):
 
 
 def cpu_baseline(wl, seconds: float):
-    """The FP64 oracle as it stands on the host cores: full steps of the
-    same column (cell-list neighbours, OpenMP over particles), repeated
-    until at least `seconds` of wall time have passed."""
+    """The FP64 oracle as it stands on the host: one full step of the same
+    column (Morton order, cell-list neighbours, stencils, fits, closure,
+    update), timed three times on all host cores (OpenMP over particles)
+    and on one thread; the median of the runs.  The one-thread runs stop
+    early once they have used `seconds` (at least one run)."""
     import oracle
-    st = wl.state
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        st, _, _ = oracle.step(st, wl.offsets, wl.params, wl.dt, brute=False)
-        steps += 1
-        dt = time.perf_counter() - t0
-        if dt >= seconds:
-            break
-    return {"value": wl.n * steps / dt, "unit": "particle-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d full oracle step(s) of the %d-particle column "
-                      "(%.1f s)" % (steps, wl.n, dt)}
+
+    def runs(threads, budget):
+        oracle.set_threads(threads)
+        used = oracle.num_threads()
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.step(wl.state, wl.offsets, wl.params, wl.dt, brute=False)
+            times.append(time.perf_counter() - t0)
+            if sum(times) >= budget:
+                break
+        return used, float(np.median(times)), len(times)
+
+    try:
+        cores, t_all, n_all = runs(0, float("inf"))
+        _, t_one, n_one = runs(1, seconds)
+    finally:
+        oracle.set_threads(0)
+    return {"value": wl.n / t_all, "unit": "particle-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "one full oracle step of the %d-particle column, median of "
+                      "%d runs on %d threads (%.2f s per step)" % (wl.n, n_all, cores, t_all),
+            "one_thread": {"value": wl.n / t_one, "cores": 1, "runs": n_one,
+                           "s_per_step": t_one}}
+
+
+def _errors(got, want, scale=None):
+    """max |got - want| / max |want| (or / scale), and the element-wise
+    relative error with a floor of 1e-3 max |want|."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    sc = float(np.max(np.abs(want))) if scale is None else float(scale)
+    if want.size == 0 or sc == 0.0:
+        return {"max_rel": 0.0, "elem_rel": 0.0}
+    d = np.abs(got - want)
+    return {"max_rel": float(np.max(d) / sc),
+            "elem_rel": float(np.max(d / np.maximum(np.abs(want), 1e-3 * sc)))}
+
+
+def errors_vs_oracle(torch, lp, wl):
+    """Every output of one step of `wl` against the FP64
+    oracle on the same input (outside any timed region).  FP64: the
+    velocity derivatives (lp_fit_derivs), P, eta and the closure
+    diagnostics, grad P, grad eta, the acceleration and dV/dt
+    (lp_rheology_rhs on the GPU's velocity derivatives), and the step's new
+    x, u, V (lp_step, as increments new - old).  Refined FP32: the step's
+    new x, u, V (its fits run inside lp_step only); u' - u = dt a and
+    V' - V = dt dV/dt carry the acceleration and volume rate."""
+    import oracle
+    onew, operm, r = oracle.step(wl.state, wl.offsets, wl.params, wl.dt, brute=False)
+    old = wl.state.take(operm)
+    out = {}
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    perm = ctx.lp_build_cells(st)
+    same_order = bool(np.array_equal(perm.cpu().numpy(), operm))
+    ctx.lp_neighbors(st, candidates=False, stencils=False, ghosts=False)
+    U = torch.stack([st.t[3], st.t[4], st.t[5]]).contiguous()
+    coef, _ = ctx.lp_fit_derivs(st, U, [1, 1, -1], [0, 0, 0])
+    g = ctx.lp_rheology_rhs(st, coef.reshape(27, -1))
+    ctx.sync_status()
+    c = coef.cpu().numpy()
+    fp64 = {"grad_u": _errors(c[:, :3], r["coef_u"][:, :3]),
+            "hess_u": _errors(c[:, 3:], r["coef_u"][:, 3:])}
+    diag, grad = g["diag"].cpu().numpy(), g["grad"].cpu().numpy()
+    for k, name in enumerate(("P", "eta", "I", "mu", "shear_rate")):
+        fp64[name] = _errors(diag[k], r["diag"][k])
+    fp64["grad_P"] = _errors(grad[:3], r["grad"][:3])
+    fp64["grad_eta"] = _errors(grad[3:], r["grad"][3:])
+    fp64["acc"] = _errors(g["acc"].cpu().numpy(), r["acc"])
+    fp64["dVdt"] = _errors(g["dVdt"].cpu().numpy(), r["dVdt"])
+    del ctx, st
+    for name, prec in (("fp64", lp.LP_FP64), ("fp32r", lp.LP_FP32_REFINED)):
+        ctx = lp.make_context(wl, precision=prec)
+        st = lp.DeviceState.from_host(wl.state)
+        perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+        ctx.lp_step(st, wl.dt, perm)
+        ctx.sync_status()
+        same_order = same_order and bool(np.array_equal(perm.cpu().numpy(), operm))
+        new = st.to_host()
+        res = fp64 if name == "fp64" else {}
+        for lab, idx in (("x_increment", (0, 1, 2)), ("u_increment", (3, 4, 5)),
+                         ("V_increment", (6,))):
+            a = np.stack([new.arrays()[q] - old.arrays()[q] for q in idx])
+            b = np.stack([onew.arrays()[q] - old.arrays()[q] for q in idx])
+            res[lab] = _errors(a, b)
+            # the new value is stored rounded: the largest difference in
+            # units of the spacing of the largest new value (the GPU rounds
+            # x + dt (u + u')/2 once, the oracle twice)
+            big = max(float(np.max(np.abs(onew.arrays()[q]))) for q in idx)
+            res[lab]["max_abs_in_ulps_of_value"] = float(np.max(np.abs(a - b))
+                                                         / np.spacing(big)) if big else 0.0
+        out[name] = res
+        del ctx, st
+    out["particle_order_equal"] = same_order
+    out["note"] = ("max_rel = max|gpu - oracle| / max|oracle| per output; elem_rel = "
+                   "max_i |gpu_i - oracle_i| / max(|oracle_i|, 1e-3 max|oracle|); "
+                   "step outputs as increments new - old")
+    return out
+
+
+def adjoint_fd_check(torch, lp, lpgen, grad, steps: int):
+    """Central differences of the runout loss of the adjoint benchmark (the
+    131,072-particle column, `steps` steps, L = sum softplus((x - 0.3)/h))
+    in mu_s, mu_2 and I0 against the adjoint gradient `grad`: at eps = 1e-6,
+    and Richardson-extrapolated from eps = 1e-4 and 2e-4
+    ((4 D(eps) - D(2 eps)) / 3), each a full re-run of the steps.  (Steps of
+    1e-3 and more move a particle across the quasi-static threshold in the
+    run, a kink of L that the adjoint, with branches held fixed, does not
+    see.)"""
+    import dataclasses
+    wl = lpgen.column_adjoint()
+    h = wl.params[0].h
+    ctx = lp.make_context(wl)
+    p0 = wl.params[0]
+    th0 = [p0.mu_s, p0.mu_2, p0.I0]
+
+    def loss(q, e):
+        th = list(th0)
+        th[q] += e
+        ctx.set_systems(wl.offsets, [dataclasses.replace(p0, mu_s=th[0], mu_2=th[1],
+                                                        I0=th[2])])
+        st = lp.DeviceState.from_host(wl.state)
+        for _ in range(steps):
+            ctx.lp_step(st, wl.dt)
+        ctx.sync_status()
+        return float(torch.nn.functional.softplus((st.t[0] - 0.3) / h).sum())
+
+    def central(q, e):
+        return (loss(q, e) - loss(q, -e)) / (2.0 * e)
+
+    out = {"steps": steps, "params": ["mu_s", "mu_2", "I0"], "adjoint": list(grad)}
+    fd6, rich = [], []
+    for q in range(3):
+        fd6.append(central(q, 1e-6))
+        rich.append((4.0 * central(q, 1e-4) - central(q, 2e-4)) / 3.0)
+    scale = max(abs(v) for v in grad) or 1.0
+    out["fd_eps_1e-6"] = fd6
+    out["fd_richardson_1e-4_2e-4"] = rich
+    out["rel_err_eps_1e-6"] = max(abs(a - b) for a, b in zip(fd6, grad)) / scale
+    out["rel_err_richardson"] = max(abs(a - b) for a, b in zip(rich, grad)) / scale
+    return out
 
 
 def main():
@@ -548,19 +697,34 @@ def main():
     ms_rebuild, _, _ = run(k0, args.warmup, precision=main_prec, skin=0.0)
     fp64 = args.precision == "fp64"
     t_pass1 = phases["pass1"] * 1e-3
-    achieved = PASS1_FLOP_PER_PARTICLE * wl.n / t_pass1 / 1e12
-    executed = PASS1_FLOP_EXECUTED * wl.n / t_pass1 / 1e12
-    roofs = {
-        "pass1": {"kernel": ("k_pass1_st" if fp64 else "k_pass1_ref")
-                            + " (fit of u, v, w + mu(I) closure)",
-                  "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                  "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                  "traffic": kernel_traffic(PASS1_PROFILE, PASS1_SOURCES) if fp64 else None,
-                  "avg_launch_ms": phases["pass1"],
-                  "per_particle": PASS1_FLOP_PER_PARTICLE,
-                  "executed_tflops": executed,
-                  "executed_frac": executed / PEAK_FP64_TFLOPS},
-    }
+    if fp64:
+        # the work the kernel executes (normal equations), against the FP64
+        # vector peak; the Householder count of the same fit beside it
+        executed = PASS1_FLOP_EXECUTED * wl.n / t_pass1 / 1e12
+        house = PASS1_FLOP_PER_PARTICLE * wl.n / t_pass1 / 1e12
+        roof1 = {"kernel": "k_pass1_st (fit of u, v, w + mu(I) closure)",
+                 "bound": "alu", "achieved": executed, "peak": PEAK_FP64_TFLOPS,
+                 "unit": "TFLOP/s", "frac": executed / PEAK_FP64_TFLOPS,
+                 "per_particle": PASS1_FLOP_EXECUTED,
+                 "householder_equivalent": {"per_particle": PASS1_FLOP_PER_PARTICLE,
+                                            "tflops": house,
+                                            "frac": house / PEAK_FP64_TFLOPS}}
+    else:
+        # float32 moment sweep and float64 residual sweep: the time both
+        # would take at their peaks, over the launch time
+        t_roof = wl.n * (PASS1_REF_FLOP_F32 / (PEAK_FP32_TFLOPS * 1e12)
+                         + PASS1_REF_FLOP_F64 / (PEAK_FP64_TFLOPS * 1e12))
+        roof1 = {"kernel": "k_pass1_ref (float32 fit + float64 residual correction "
+                           "of u, v, w; mu(I) closure)",
+                 "bound": "alu", "achieved": t_roof / t_pass1, "peak": 1.0,
+                 "unit": "fraction of the mixed FP32/FP64 roof",
+                 "frac": t_roof / t_pass1,
+                 "per_particle": {"f32": PASS1_REF_FLOP_F32, "f64": PASS1_REF_FLOP_F64},
+                 "tflops_f32": PASS1_REF_FLOP_F32 * wl.n / t_pass1 / 1e12,
+                 "tflops_f64": PASS1_REF_FLOP_F64 * wl.n / t_pass1 / 1e12}
+    roof1["traffic"] = kernel_traffic(PASS1_PROFILE, PASS1_SOURCES) if fp64 else None
+    roof1["avg_launch_ms"] = phases["pass1"]
+    roofs = {"pass1": roof1}
     for ph, name, per, prof, src in (
             ("select", "k_select (exact candidate test, octant firsts, ghosts, keep mask)",
              SELECT_BYTES_PER_PARTICLE, SELECT_PROFILE, SELECT_SOURCES),
@@ -612,8 +776,17 @@ def main():
                                                  main_prec, ms_eager)
     if not args.no_cubic:
         out["cubic_fits"] = cubic_bench(torch, lp, wl, args.steps, args.warmup)
+    if not args.no_errors:
+        # the benchmark column starts at rest (u = 0: every velocity
+        # derivative, eta and I are exactly 0), so the errors are taken on
+        # the same column with a seeded flow (0.5 m/s, wavelength 8h)
+        wl_flow = lpgen.with_shear_velocity(wl)
+        out["errors_vs_oracle"] = {"workload": wl_flow.name,
+                                   **errors_vs_oracle(torch, lp, wl_flow)}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
+        out["adjoint"]["fd_check"] = adjoint_fd_check(
+            torch, lp, lpgen, out["adjoint"]["dL_dtheta"][0], args.adjoint_steps)
         if not args.no_second_order:
             out["adjoint_second_order"] = adjoint_bench(torch, lp, lpgen,
                                                         args.adjoint_steps, order=2)

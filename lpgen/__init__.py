@@ -291,6 +291,23 @@ def ensemble(seed: int = BASE_SEED + 5, n_sys: int = 64,
                     np.array(offs, dtype=np.int64), params, 2e-5, 20)
 
 
+def with_shear_velocity(wl: Workload, seed: int = BASE_SEED + 60,
+                        amplitude: float = 0.5, wavelength_h: float = 8.0) -> Workload:
+    """Copy of ``wl`` whose initial velocity is the seeded smooth field of
+    ``smooth_field`` (wavelength ``wavelength_h`` times the first system's
+    h, ``amplitude`` m/s per component), positions and volumes unchanged:
+    the divergence of this flow takes particles out of the quasi-static
+    branch within a few steps."""
+    st = wl.state.copy()
+    pts = np.stack([st.x, st.y, st.z], axis=1)
+    f = smooth_field(seed, pts, wavelength_h * wl.params[0].h)
+    st.u = amplitude * f[:, 0]
+    st.v = amplitude * f[:, 1]
+    st.w = amplitude * f[:, 2]
+    return Workload(wl.name + "_sheared_velocity", st, wl.offsets, wl.params,
+                    wl.dt, wl.steps)
+
+
 def validation_params(h: float, **kw) -> Params:
     """Grain constants of the paper's validation runs (Sec. 4): mu_s =
     tan 30 deg, mu_2 = tan 50 deg, I0 = 2.65, d = 0.32 mm, rho_s = 2600

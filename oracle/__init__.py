@@ -73,6 +73,8 @@ def _load():
     lib.orc_update.restype = i64
     lib.orc_boundary.argtypes = [i64, i32, P, P, P, P, P, P, C.c_int]
     lib.orc_num_threads.restype = C.c_int
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_set_threads.restype = None
     lib.orc_lsq.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P]
     lib.orc_lsq.restype = C.c_double
     lib.orc_closure_point.argtypes = [P, C.c_double, P, P, P]
@@ -91,6 +93,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(t: int) -> None:
+    """OpenMP threads of later oracle calls (0: back to the initial count)."""
+    _load().orc_set_threads(int(t))
 
 
 def cfg_vector(cfg: Optional[dict] = None) -> np.ndarray:

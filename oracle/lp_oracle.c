@@ -64,6 +64,19 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of later parallel regions (timing runs at 1 thread and at all
+ * cores); 0 or less restores the count the process started with. */
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    static int initial = 0;
+    if (!initial) initial = omp_get_max_threads();
+    omp_set_num_threads(t > 0 ? t : initial);
+#else
+    (void)t;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Morton order of the particles of each system.                       */
 /* ------------------------------------------------------------------ */
