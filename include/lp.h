@@ -346,11 +346,10 @@ lp_status lp_step_graph(lp_ctx* ctx, lp_state* s, int32_t* ids, double dt,
  *   adj_params: device double[n_sys x 3], dL/d(mu_s, mu_2, I0) per system
  *               is ADDED to it.
  * Computes in float64 whatever the precision setting; requires unit
- * weights (LP_E_ARG otherwise).  Neighbour contributions are accumulated
- * in per-row slots grouped by receiving particle (the slot order, and so
- * the summation order, varies between runs).  m_max x particles must stay
- * below 2^31 (LP_E_CAPACITY).  A degenerate Gram matrix latches
- * LP_E_NUMERIC (lp_sync_status). */
+ * weights (LP_E_ARG otherwise).  Neighbour contributions are summed per
+ * tile of the neighbour list and added with float64 atomics (the
+ * summation order, and so the rounding, varies between runs).  A
+ * degenerate Gram matrix latches LP_E_NUMERIC (lp_sync_status). */
 lp_status lp_step_adjoint(lp_ctx* ctx, const lp_state* s, double dt,
                           const lp_state* adj_out, lp_state* adj_in,
                           double* adj_params, int32_t* perm,

@@ -26,11 +26,13 @@
 //             shear-rate norm has zero derivative where it is zero.
 //
 // Contributions to other particles (neighbour values and positions,
-// mirror sources) are written, one record of six doubles per stencil row,
-// into slots grouped by receiving particle (a counting sort of the rows by
-// their point, built once per call with integer atomics); a gather pass
-// then adds each particle's slots.  The order of the slots of one particle
-// varies between runs, so sums are accumulated in a run-dependent order.
+// mirror sources), six per stencil row, are summed per tile: a block of
+// BLOCK particles whose neighbours are staged in LDS (the tile map's
+// sources) adds each row into LDS accumulators of the row's source slot,
+// then adds every slot once into the receiving particle's global
+// accumulators with float64 atomics; rows that are not staged add into
+// global memory directly.  Atomics make the summation order vary between
+// runs (results agree to rounding).
 #include <cmath>
 
 #include "lp_fitcore.h"
@@ -60,21 +62,54 @@ struct AdjBufs {
     const uint8_t* flags;
     double* dparams;     // n_sys x 3
     ErrWord* err;
-    const int32_t* slot; // m_max x n: slot of stencil row t of particle i
-    double* contrib;     // 6 per slot
+    double* recv;        // 6 x n: contributions received from other particles
 };
 
-// six contributions of one stencil row to the particle its point stands
-// for (a mirror's source)
-__device__ __forceinline__ void put_row(const AdjBufs& B, int64_t n, int64_t i, int t,
-                                        double c0, double c1, double c2, double c3,
-                                        double c4, double c5)
+// LDS accumulators of a tile's staged sources: six per source slot
+constexpr int NRECV = 6;
+
+__device__ __forceinline__ void lds_add(double* p, double v)
 {
-    const int64_t sl = B.slot[(int64_t)t * n + i];
-    double2* q = reinterpret_cast<double2*>(B.contrib + 6 * sl);
-    q[0] = make_double2(c0, c1);
-    q[1] = make_double2(c2, c3);
-    q[2] = make_double2(c4, c5);
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Six contributions of one stencil row to the particle its point stands
+// for (a mirror's source): into the tile's accumulators of slot q when
+// the row was read from the staged sources, else into global memory
+// (receiver j).
+__device__ __forceinline__ void deliver(const AdjBufs& B, int64_t n, double* acc,
+                                        bool staged, int32_t q_or_j, const double (&c)[6])
+{
+    if (staged) {
+#pragma unroll
+        for (int f = 0; f < NRECV; ++f) lds_add(acc + f * STAGE_CAP + q_or_j, c[f]);
+    } else {
+#pragma unroll
+        for (int f = 0; f < NRECV; ++f) unsafeAtomicAdd(B.recv + f * n + q_or_j, c[f]);
+    }
+}
+
+// Zeroes the accumulators of the tile's ns staged slots.
+__device__ __forceinline__ void acc_zero(double* acc, int ns)
+{
+    for (int q = threadIdx.x; q < ns; q += BLOCK)
+#pragma unroll
+        for (int f = 0; f < NRECV; ++f) acc[f * STAGE_CAP + q] = 0.0;
+}
+
+// Adds every staged slot's accumulators into its particle's global
+// accumulators (after the block's rows are done).
+__device__ __forceinline__ void acc_flush(const AdjBufs& B, int64_t n, const double* acc,
+                                          const int32_t* tsrc, int ns)
+{
+    for (int q = threadIdx.x; q < ns; q += BLOCK) {
+        const int64_t j = tsrc[q];
+#pragma unroll
+        for (int f = 0; f < NRECV; ++f) {
+            const double x = acc[f * STAGE_CAP + q];
+            if (x != 0.0) unsafeAtomicAdd(B.recv + f * n + j, x);
+        }
+    }
 }
 
 // d(Taylor row)/d(xi) applied to a row cotangent Abar: returns xibar
@@ -87,145 +122,32 @@ __device__ __forceinline__ void row_xi_bar(const double (&A)[9], double ex, doub
     gz = A[2] + A[5] * ez + A[7] * ex + A[8] * ey;
 }
 
-// zero records in the slots of particle i (a particle whose reverse step
-// failed still owns its slots)
-__device__ __forceinline__ void zero_rows(const AdjBufs& B, const View& v,
-                                          const GridInfo& g, int64_t i, const Rec& r)
-{
-    int t = 0;
-    visit_stencil(v, g, i, r, [&](const Pt&, double, double, double) {
-        put_row(B, v.n, i, t, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0);
-        ++t;
-    });
-}
-
-// ---- slots: rows grouped by the particle they contribute to ------------
-
-// cnt[j] = number of stencil rows (of all particles) whose point is j or
-// a mirror of j
-__global__ __launch_bounds__(BLOCK) void k_slot_count(View v, int32_t* cnt)
-{
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    if (i >= v.n) return;
-    const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
-    const Rec r = load_rec(v, i);
-    visit_stencil(v, g, i, r, [&](const Pt& p, double, double, double) {
-        atomicAdd(&cnt[p.src], 1);
-    });
-}
-
-// exclusive scan of a[0..n) into b[0..n], tiles of BLOCK (three kernels)
-__global__ __launch_bounds__(BLOCK) void k_scan_tiles(int64_t n, const int32_t* a,
-                                                      int32_t* b, int32_t* tile)
-{
-    __shared__ int32_t ws[BLOCK / 64];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + t;
-    const int32_t x = i < n ? a[i] : 0;
-    int32_t inc = x;
-    for (int d = 1; d < 64; d <<= 1) {
-        const int32_t o = __shfl_up(inc, d);
-        if (lane >= d) inc += o;
-    }
-    if (lane == 63) ws[wave] = inc;
-    __syncthreads();
-    int32_t pre = 0, tot = 0;
-    for (int w = 0; w < BLOCK / 64; ++w) {
-        if (w < wave) pre += ws[w];
-        tot += ws[w];
-    }
-    if (i < n) b[i] = pre + inc - x;
-    if (t == 0) tile[blockIdx.x] = tot;
-}
-
-__global__ void k_scan_tile_sums(int64_t nt, int32_t* tile)
-{
-    // single block of 1024: each thread scans a contiguous chunk
-    __shared__ int32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t chunk = (nt + 1023) / 1024;
-    const int64_t b = t * chunk;
-    const int64_t e = (b + chunk < nt) ? b + chunk : nt;
-    int32_t sum = 0;
-    for (int64_t q = b; q < e; ++q) sum += tile[q];
-    part[t] = sum;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const int32_t o = t >= d ? part[t - d] : 0;
-        __syncthreads();
-        part[t] += o;
-        __syncthreads();
-    }
-    int32_t run = part[t] - sum;
-    for (int64_t q = b; q < e; ++q) {
-        const int32_t x = tile[q];
-        tile[q] = run;
-        run += x;
-    }
-    if (t == 1023) tile[nt] = part[1023];
-}
-
-__global__ void k_scan_add(int64_t n, int32_t* b, const int32_t* tile)
-{
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i < n) b[i] += tile[blockIdx.x];
-    if (i == 0) b[n] = tile[(n + BLOCK - 1) / BLOCK];
-}
-
-// slot of every stencil row: start of its point's range plus a place
-// taken with an atomic counter
-__global__ __launch_bounds__(BLOCK) void k_slot_assign(View v, const int32_t* off,
-                                                       int32_t* fill, int32_t* slot)
-{
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    if (i >= v.n) return;
-    const int64_t n = v.n;
-    const GridInfo& g = v.grid[sys_of(v.off, v.n_sys, i)];
-    const Rec r = load_rec(v, i);
-    int t = 0;
-    visit_stencil(v, g, i, r, [&](const Pt& p, double, double, double) {
-        slot[(int64_t)t * n + i] = off[p.src] + atomicAdd(&fill[p.src], 1);
-        ++t;
-    });
-}
-
-__global__ void k_zero_i32(int64_t n, int32_t* a)
+// zeroes n values (any length)
+__global__ void k_zero_f64(int64_t n, double* a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0;
+    if (i < n) a[i] = 0.0;
 }
 
-// adds the records of each particle's slots: pass 2 (P, eta, V, x, y, z)
-// or pass 1 (u, v, w, x, y, z)
-__global__ __launch_bounds__(BLOCK) void k_slot_gather(int64_t n, const int32_t* off,
-                                                       AdjBufs B, int pass)
+// adds the contributions received in a pass to the accumulators: pass 2
+// (P, eta, V, x, y, z) or pass 1 (u, v, w, x, y, z)
+__global__ __launch_bounds__(BLOCK) void k_fold(int64_t n, AdjBufs B, int pass)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int32_t e = off[j + 1];
-    for (int32_t sl = off[j]; sl < e; ++sl) {
-        const double2* q = reinterpret_cast<const double2*>(B.contrib + 6 * (int64_t)sl);
-        const double2 a = q[0], b = q[1], d = q[2];
-        c[0] += a.x;
-        c[1] += a.y;
-        c[2] += b.x;
-        c[3] += b.y;
-        c[4] += d.x;
-        c[5] += d.y;
-    }
+    const double* r = B.recv;
     if (pass == 2) {
-        B.aP[j] += c[0];
-        B.aE[j] += c[1];
-        B.a[6][j] += c[2];
+        B.aP[j] += r[j];
+        B.aE[j] += r[n + j];
+        B.a[6][j] += r[2 * n + j];
     } else {
-        B.a[3][j] += c[0];
-        B.a[4][j] += c[1];
-        B.a[5][j] += c[2];
+        B.a[3][j] += r[j];
+        B.a[4][j] += r[n + j];
+        B.a[5][j] += r[2 * n + j];
     }
-    B.a[0][j] += c[3];
-    B.a[1][j] += c[4];
-    B.a[2][j] += c[5];
+    B.a[0][j] += r[3 * n + j];
+    B.a[1][j] += r[4 * n + j];
+    B.a[2][j] += r[5 * n + j];
 }
 
 // N = nA A + nB B at particle i, component a (B optional)
@@ -257,15 +179,52 @@ __global__ void k_adj_init(int64_t n, AdjSeed S, AdjBufs B)
 
 // ---- reverse of the update, the RHS and the fit of P and eta -------------
 
-__global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, AdjSeed S, AdjBufs B)
+// The stencil rows of particle i with the P and eta their points carry:
+// from the tile's sources staged in LDS (positions, P, eta and mirror
+// pressure, as the forward pass-2 fit reads them) when the tile is
+// staged, else from global memory.  body(a, w, p, Pj, Ej, src): src is the
+// real particle behind the point (a mirror's source).
+template <class F>
+__device__ __forceinline__ void adj_rows2(const View& v, const GridInfo& g,
+                                          const lp_params& prm, const AdjBufs& B,
+                                          int64_t i, const Rec& r, bool staged,
+                                          const int32_t* tsrc, const double* sx,
+                                          const double* sy, const double* sz,
+                                          const double* sP, const double* sE,
+                                          const double* sM, F&& body)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    if (i >= v.n) return;
+    if (staged) {
+        for_rows_staged<FIT_BATCH, true>(v, g, i, r, sx, sy, sz,
+                                         [&](const double* a, double w, const Pt* p) {
+            if (!p) body(a, w, p, 0.0, 0.0, -1);
+            else if (p->mirror) body(a, w, p, sM[p->src], 0.0, tsrc[p->src]);
+            else body(a, w, p, sP[p->src], sE[p->src], tsrc[p->src]);
+        });
+    } else {
+        for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+            double Pj, Ej;
+            pass2_values(v, B.P, B.eta, p, prm, Pj, Ej);
+            body(a, w, p, Pj, Ej, p ? p->src : -1);
+        });
+    }
+}
+
+// Reverse of the update, the RHS and the fit of P and eta at real particle
+// i of the block's tile (ns staged sources, -1: not staged).
+__device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
+                                              const AdjBufs& B, int64_t tile, int64_t i,
+                                              int ns, const double* sx, const double* sy,
+                                              const double* sz, const double* sP,
+                                              const double* sE, const double* sM,
+                                              double* acc)
+{
     const int64_t n = v.n;
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
     const lp_params& prm = v.prm[s];
     const Rec r = load_rec(v, i);
+    const bool staged = ns >= 0 && !(r.mode & MODE_SORTED);
+    const int32_t* tsrc = v.tile_src + tile * STAGE_CAP;
     const bool lin = B.flags[i] & FLAG_LINEAR;
     const double Pi = B.P[i], Ei = B.eta[i];
     // forward fit of P and eta (all nine coefficients)
@@ -274,10 +233,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, AdjSeed S, AdjBufs 
     for (int q = 0; q < 31; ++q) M[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) y0[q] = y1[q] = 0.0;
-    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+    adj_rows2(v, g, prm, B, i, r, staged, tsrc, sx, sy, sz, sP, sE, sM,
+              [&](const double* a, double w, const Pt*, double Pj, double Ej, int32_t) {
         moments_add(M, a, w);
-        double Pj, Ej;
-        pass2_values(v, B.P, B.eta, p, prm, Pj, Ej);
         const double bP = w * (Pj - Pi), bE = w * (Ej - Ei);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -291,7 +249,6 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, AdjSeed S, AdjBufs 
     if (!(ratio > 0.0)) {
         raise_error(B.err, ERR_NUMERIC, i);
         for (int q = 0; q < 11; ++q) B.stash[(int64_t)q * n + i] = 0.0;
-        zero_rows(B, v, g, i, r);
         return;
     }
     double cP[9], cE[9];
@@ -367,11 +324,10 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, AdjSeed S, AdjBufs 
         chol_solve<9>(U, yP);
         chol_solve<9>(U, yE);
     }
-    double sP = 0.0, sE = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-    int t = 0;
-    for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
-        double Pj, Ej;
-        pass2_values(v, B.P, B.eta, p, prm, Pj, Ej);
+    double aPs = 0.0, aEs = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    adj_rows2(v, g, prm, B, i, r, staged, tsrc, sx, sy, sz, sP, sE, sM,
+              [&](const double* a, double, const Pt* p, double Pj, double Ej,
+                  int32_t src) {
         double rP = Pj - Pi, rE = Ej - Ei, bP = 0.0, bE = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -380,8 +336,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, AdjSeed S, AdjBufs 
             bP += a[q] * yP[q];
             bE += a[q] * yE[q];
         }
-        sP -= bP;
-        sE -= bE;
+        aPs -= bP;
+        aEs -= bE;
         if (!p) return;   // ghost rows: constant rows, value 0
         double Ab[9];
 #pragma unroll
@@ -392,35 +348,82 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass2(View v, AdjSeed S, AdjBufs 
         gx *= ih;
         gy *= ih;
         gz *= ih;
-        sx -= gx;
-        sy -= gy;
-        sz -= gz;
+        ax -= gx;
+        ay -= gy;
+        az -= gz;
         if (!p->mirror) {
-            put_row(B, n, i, t, bP, bE, 0.0, gx, gy, gz);
+            const double c[6] = {bP, bE, 0.0, gx, gy, gz};
+            deliver(B, n, acc, staged, staged ? p->src : src, c);
         } else {
             // mirror pressure P(phi_src) of the quasi-static law; no eta
-            const double Vs = v.V[p->src];
+            const double Vs = v.V[src];
             const double dV = 1.0 / Vs > prm.phi_max
                                   ? -bP * prm.rho_s * prm.beta / (Vs * Vs) : 0.0;
-            put_row(B, n, i, t, 0.0, 0.0, dV, gx, gy, -gz);
+            const double c[6] = {0.0, 0.0, dV, gx, gy, -gz};
+            deliver(B, n, acc, staged, staged ? p->src : src, c);
         }
-        ++t;
     });
-    // this particle's own terms: no other thread writes them in this pass
-    B.aP[i] += sP;
-    B.aE[i] += sE;
-    B.a[0][i] += sx;
-    B.a[1][i] += sy;
-    B.a[2][i] += sz;
+    // this particle's own terms (other particles' rows arrive in B.recv)
+    B.aP[i] += aPs;
+    B.aE[i] += aEs;
+    B.a[0][i] += ax;
+    B.a[1][i] += ay;
+    B.a[2][i] += az;
+}
+
+// One block per tile: the tile's sources staged in LDS with their
+// accumulators (all the LDS of a CU), the reverse pass of each particle,
+// then the accumulators added into the global receive buffers.
+__global__ __launch_bounds__(BLOCK, 1) void k_adj_pass2(View v, AdjSeed S, AdjBufs B,
+                                                        int map_ok)
+{
+    __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
+    __shared__ double sP[STAGE_CAP], sE[STAGE_CAP], sM[STAGE_CAP];
+    __shared__ double acc[NRECV * STAGE_CAP];
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = tile * BLOCK + threadIdx.x;
+    const int tc = map_ok ? v.tile_cnt[tile] : -1;
+    const int ns = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
+    if (ns >= 0) {
+        stage_pass2(v, B.P, B.eta, tile, ns, sx, sy, sz, sP, sE, sM);
+        acc_zero(acc, ns);
+        __syncthreads();
+    }
+    if (i < v.n) adj2_particle(v, S, B, tile, i, ns, sx, sy, sz, sP, sE, sM, acc);
+    if (ns >= 0) {
+        __syncthreads();
+        acc_flush(B, v.n, acc, v.tile_src + tile * STAGE_CAP, ns);
+    }
 }
 
 // ---- reverse of the closure and of the fit of u, v, w ----------------------
 
-__global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
+__global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int map_ok)
 {
-    __shared__ double red[3][BLOCK];
+    // the tile's staged sources (positions and velocities, as the forward
+    // pass-1 fit reads them) and their accumulators (all the LDS of a CU);
+    // the block reduction of the parameter cotangents reuses the staging
+    // space once every row has been read
+    __shared__ double lds[6 * STAGE_CAP];
+    __shared__ double acc[NRECV * STAGE_CAP];
+    __shared__ int sys_t[BLOCK];
+    static_assert(3 * BLOCK <= 6 * STAGE_CAP, "reduction fits the staging space");
+    double* sx = lds;
+    double* sy = lds + STAGE_CAP;
+    double* sz = lds + 2 * STAGE_CAP;
+    double* su = lds + 3 * STAGE_CAP;
+    double* sv = lds + 4 * STAGE_CAP;
+    double* sw = lds + 5 * STAGE_CAP;
     const int t = threadIdx.x;
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * BLOCK + t;
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = tile * BLOCK + t;
+    const int tc = map_ok ? v.tile_cnt[tile] : -1;
+    const int ns = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
+    if (ns >= 0) {
+        stage_pass1(v, tile, ns, sx, sy, sz, su, sv, sw);
+        acc_zero(acc, ns);
+        __syncthreads();
+    }
     double th[3] = {0.0, 0.0, 0.0};
     int s = -1;
     if (i < v.n) {
@@ -429,6 +432,28 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
         const GridInfo& g = v.grid[s];
         const lp_params& prm = v.prm[s];
         const Rec r = load_rec(v, i);
+        const bool staged = ns >= 0 && !(r.mode & MODE_SORTED);
+        // rows with the velocities of their points (ghosts: u_i)
+        auto rows = [&](auto&& body) {
+            if (staged) {
+                for_rows_staged<FIT_BATCH, true>(v, g, i, r, sx, sy, sz,
+                                                 [&](const double* a, double w,
+                                                     const Pt* p) {
+                    if (!p) {
+                        body(a, w, p, 0.0, 0.0, 0.0);
+                        return;
+                    }
+                    const int q = p->src;
+                    body(a, w, p, su[q], sv[q], p->mirror ? -sw[q] : sw[q]);
+                });
+            } else {
+                for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+                    double uj = 0.0, vj = 0.0, wj = 0.0;
+                    if (p) point_velocity(v, *p, uj, vj, wj);
+                    body(a, w, p, uj, vj, wj);
+                });
+            }
+        };
         const bool lin = B.flags[i] & FLAG_LINEAR;
         double c[27];
 #pragma unroll
@@ -513,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
         double M[31];
 #pragma unroll
         for (int q = 0; q < 31; ++q) M[q] = 0.0;
-        for_rows(v, g, i, r, [&](const double* a, double w, const Pt*) {
+        rows([&](const double* a, double w, const Pt*, double, double, double) {
             moments_add(M, a, w);
         });
         double U[45];
@@ -521,7 +546,6 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
         const double ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
         if (!(ratio > 0.0)) {
             raise_error(B.err, ERR_NUMERIC, i);
-            zero_rows(B, v, g, i, r);
         } else {
             double y[3][9], cu[3][9];
 #pragma unroll
@@ -536,13 +560,11 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
                 else chol_solve<9>(U, y[f]);
             }
             const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
-            double su[3] = {0.0, 0.0, 0.0}, sx = 0.0, sy = 0.0, sz = 0.0;
-            int t = 0;
-            for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+            double au[3] = {0.0, 0.0, 0.0}, ax = 0.0, ay = 0.0, az = 0.0;
+            rows([&](const double* a, double, const Pt* p, double uj, double vj,
+                     double wj) {
                 double b[3] = {0.0, 0.0, 0.0};   // ghosts carry u_i
                 if (p) {
-                    double uj, vj, wj;
-                    point_velocity(v, *p, uj, vj, wj);
                     b[0] = uj - ui;
                     b[1] = vj - vi;
                     b[2] = wj - wi;
@@ -564,32 +586,39 @@ __global__ __launch_bounds__(BLOCK) void k_adj_pass1(View v, AdjBufs B)
                     for (int q = 0; q < 9; ++q) Ab[q] += rr * y[f][q] - yy * cu[f][q];
                 }
                 if (!p) return;   // ghost rows: constant, value u_i
-                su[0] -= bb[0];
-                su[1] -= bb[1];
-                su[2] -= bb[2];
+                au[0] -= bb[0];
+                au[1] -= bb[1];
+                au[2] -= bb[2];
                 double gx, gy, gz;
                 row_xi_bar(Ab, a[0], a[1], a[2], gx, gy, gz);
                 gx *= ih;
                 gy *= ih;
                 gz *= ih;
-                sx -= gx;
-                sy -= gy;
-                sz -= gz;
+                ax -= gx;
+                ay -= gy;
+                az -= gz;
                 const double sg = p->mirror ? -1.0 : 1.0;
-                put_row(B, n, i, t, bb[0], bb[1], sg * bb[2], gx, gy, sg * gz);
-                ++t;
+                const double cr[6] = {bb[0], bb[1], sg * bb[2], gx, gy, sg * gz};
+                deliver(B, n, acc, staged, p->src, cr);
             });
-            B.a[3][i] += su[0];
-            B.a[4][i] += su[1];
-            B.a[5][i] += su[2];
-            B.a[0][i] += sx;
-            B.a[1][i] += sy;
-            B.a[2][i] += sz;
+            // this particle's own terms (other particles' rows arrive in
+            // B.recv)
+            B.a[3][i] += au[0];
+            B.a[4][i] += au[1];
+            B.a[5][i] += au[2];
+            B.a[0][i] += ax;
+            B.a[1][i] += ay;
+            B.a[2][i] += az;
         }
     }
+    if (ns >= 0) {
+        __syncthreads();
+        acc_flush(B, v.n, acc, v.tile_src + tile * STAGE_CAP, ns);
+    }
     // parameter cotangents: one atomic per block when the block lies in
-    // one system, else one per thread
-    __shared__ int sys_t[BLOCK];
+    // one system, else one per thread (the staged rows are dead once every
+    // thread has passed the first barrier)
+    double (*red)[BLOCK] = reinterpret_cast<double (*)[BLOCK]>(lds);
     sys_t[t] = s;
     __syncthreads();
     const int s0 = sys_t[0];
@@ -648,28 +677,20 @@ lp_status step_adjoint(lp_ctx* c, const double* const st[7], const AdjSeed& seed
     B.err = w.err;
     Ptr7 dout;
     for (int a = 0; a < 7; ++a) dout.p[a] = out[a];
-    // slots of the stencil rows, grouped by receiving particle
+    // contributions to other particles arrive in B.recv (6 x n), cleared
+    // before each reverse pass and added to the accumulators after it
     hipStream_t s = c->stream;
-    const int64_t nt = (n + BLOCK - 1) / BLOCK;
-    B.slot = w.adj_slot;
-    B.contrib = w.adj_contrib;
-    hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, w.adj_cnt);
-    hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, w.adj_fill);
-    hipLaunchKernelGGL(k_slot_count, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, w.adj_cnt);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(BLOCK), 0, s, n, w.adj_cnt,
-                       w.adj_off, w.adj_tile);
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(1024), 0, s, nt, w.adj_tile);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(BLOCK), 0, s, n, w.adj_off,
-                       w.adj_tile);
-    hipLaunchKernelGGL(k_slot_assign, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v,
-                       w.adj_off, w.adj_fill, w.adj_slot);
+    B.recv = w.adj_recv;
+    const int mo = c->map_ok ? 1 : 0;
     hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, seed, B);
-    hipLaunchKernelGGL(k_adj_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, seed, B);
-    hipLaunchKernelGGL(k_slot_gather, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
-                       (const int32_t*)w.adj_off, B, 2);
-    hipLaunchKernelGGL(k_adj_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, B);
-    hipLaunchKernelGGL(k_slot_gather, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
-                       (const int32_t*)w.adj_off, B, 1);
+    hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(NRECV * n)), dim3(BLOCK), 0, s,
+                       NRECV * n, w.adj_recv);
+    hipLaunchKernelGGL(k_adj_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, seed, B, mo);
+    hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B, 2);
+    hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(NRECV * n)), dim3(BLOCK), 0, s,
+                       NRECV * n, w.adj_recv);
+    hipLaunchKernelGGL(k_adj_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, B, mo);
+    hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B, 1);
     hipLaunchKernelGGL(k_adj_unpermute, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, perm, B,
                        dout);
     const hipError_t e = hipGetLastError();

@@ -34,6 +34,7 @@ View make_view(lp_ctx* c, const double* const st[7])
     v.grid = w.grid;
     v.x = st[0]; v.y = st[1]; v.z = st[2];
     v.u = st[3]; v.v = st[4]; v.w = st[5]; v.V = st[6];
+    v.p4 = w.p4;
     v.mirror_of = w.mirror_of;
     v.msrc = w.msrc;
     v.vl = w.vl;
@@ -77,6 +78,7 @@ void free_work(Work& w)
     f(w.off); f(w.prm); f(w.grid); f(w.bbox); f(w.summary); f(w.err); f(w.cnt);
     f(w.keys0); f(w.keys1); f(w.vals0); f(w.vals1); f(w.hist);
     for (int a = 0; a < 7; ++a) f(w.sst[a]);
+    f(w.p4);
     for (int a = 0; a < 3; ++a) f(w.xref[a]);
     f(w.mirror_of); f(w.msrc); f(w.bsum); f(w.cs); f(w.ce);
     f(w.vl); f(w.vcnt); f(w.tile_src); f(w.tile_cnt); f(w.vs);
@@ -85,8 +87,7 @@ void free_work(Work& w)
     f(w.P); f(w.eta); f(w.hand); f(w.uf);
     for (int a = 0; a < 7; ++a) f(w.adj[a]);
     f(w.adj_P); f(w.adj_E); f(w.adj_stash); f(w.coefu); f(w.adj_perm);
-    f(w.adj_slot); f(w.adj_contrib); f(w.adj_cnt); f(w.adj_fill); f(w.adj_off);
-    f(w.adj_tile);
+    f(w.adj_recv);
     f(w.gate); f(w.ids_tmp);
     for (int a = 0; a < 7; ++a) f(w.sst2[a]);
     for (int a = 0; a < 7; ++a) f(w.adj2[a]);
@@ -709,10 +710,6 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
                  "mirror wall only";
         return LP_E_ARG;
     }
-    if ((int64_t)c->cfg.m_max * c->n >= (1ll << 31)) {
-        c->err = "lp_step_adjoint: m_max x particles must stay below 2^31";
-        return LP_E_CAPACITY;
-    }
     double* in[7];
     state_arrays(s, in);
     const int32_t* order = nullptr;
@@ -760,10 +757,6 @@ lp_status lp_step2_adjoint(lp_ctx* c, const lp_state* s, double dt,
     if (!(c->cfg.skin > 0.0)) {
         c->err = "lp_step2_adjoint needs a neighbour-list skin > 0";
         return LP_E_ARG;
-    }
-    if ((int64_t)c->cfg.m_max * c->n >= (1ll << 31)) {
-        c->err = "lp_step2_adjoint: m_max x particles must stay below 2^31";
-        return LP_E_CAPACITY;
     }
     Work& w = c->w;
     double* in[7];

@@ -418,4 +418,103 @@ __device__ __forceinline__ void pass2_values(const View& v, const double* P,
     }
 }
 
+// ---- staging of a tile's list sources in LDS (fits and their adjoints) --
+
+// Staged sources per thread of a block, and this thread's source ids in
+// the tile (slot threadIdx.x + u BLOCK; -1 past the tile's S sources).
+constexpr int STAGE_PER = (STAGE_CAP + BLOCK - 1) / BLOCK;
+// six staged FP64 fields per source; two blocks must fit one CU's 160 KB
+static_assert(2 * 6 * STAGE_CAP * (int)sizeof(double) <= 160 * 1024,
+              "two staged fit blocks per CU");
+
+__device__ __forceinline__ void stage_ids(const View& v, int64_t tile, int S,
+                                          int32_t (&js)[STAGE_PER])
+{
+    const int32_t* src = v.tile_src + tile * STAGE_CAP;
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        const int q = (int)threadIdx.x + u * BLOCK;
+        js[u] = q < S ? src[q] : -1;
+    }
+}
+
+// Loads the positions and velocities of the tile's S list sources into
+// LDS (slot q holds the q-th source of the tile's sorted set): every
+// thread takes its sources at once, their ids first, then their fields.
+__device__ __forceinline__ void stage_pass1(const View& v, int64_t tile, int S, double* sx,
+                                            double* sy, double* sz, double* su,
+                                            double* sv, double* sw)
+{
+    int32_t js[STAGE_PER];
+    stage_ids(v, tile, S, js);
+    double f[6][STAGE_PER];
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        const int32_t j = js[u] < 0 ? 0 : js[u];
+        f[0][u] = v.x[j];
+        f[1][u] = v.y[j];
+        f[2][u] = v.z[j];
+        f[3][u] = v.u[j];
+        f[4][u] = v.v[j];
+        f[5][u] = v.w[j];
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        if (js[u] < 0) continue;
+        const int q = (int)threadIdx.x + u * BLOCK;
+        sx[q] = f[0][u];
+        sy[q] = f[1][u];
+        sz[q] = f[2][u];
+        su[q] = f[3][u];
+        sv[q] = f[4][u];
+        sw[q] = f[5][u];
+    }
+}
+
+// Loads the positions, P and eta of the tile's S list sources into LDS,
+// with the pressure a mirror of each source carries (pass2_values).
+__device__ __forceinline__ void stage_pass2(const View& v, const double* P,
+                                            const double* eta, int64_t tile, int S,
+                                            double* sx, double* sy, double* sz,
+                                            double* sP, double* sE, double* sM)
+{
+    int32_t js[STAGE_PER];
+    stage_ids(v, tile, S, js);
+    double f[5][STAGE_PER];
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        const int32_t j = js[u] < 0 ? 0 : js[u];
+        f[0][u] = v.x[j];
+        f[1][u] = v.y[j];
+        f[2][u] = v.z[j];
+        f[3][u] = P[j];
+        f[4][u] = eta[j];
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_PER; ++u) {
+        if (js[u] < 0) continue;
+        const int q = (int)threadIdx.x + u * BLOCK;
+        const int32_t j = js[u];
+        sx[q] = f[0][u];
+        sy[q] = f[1][u];
+        sz[q] = f[2][u];
+        sP[q] = f[3][u];
+        sE[q] = f[4][u];
+        // j's system is that of every particle listing it.  Only a source
+        // within R of the wall has a mirror (the rule that sets mirror_of).
+        const int sj = sys_of(v.off, v.n_sys, j);
+        const GridInfo& gj = v.grid[sj];
+        double pm = 0.0;
+        if (dsub(f[2][u], gj.wall) < gj.R) {
+            Pt m;
+            m.mirror = true;
+            m.src = j;
+            m.z = dsub(dmul(2.0, gj.wall), f[2][u]);
+            double em;
+            pass2_values(v, P, eta, &m, v.prm[sj], pm, em);
+        }
+        sM[q] = pm;
+    }
+}
+
 }  // namespace lp

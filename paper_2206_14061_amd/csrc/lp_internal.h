@@ -105,6 +105,9 @@ struct View {
     const GridInfo* grid;
     // real particles in cell order (current positions)
     const double *x, *y, *z, *u, *v, *w, *V;
+    // the same positions as 32-byte records (x, y, z, 0), packed when the
+    // stencils are built: one neighbour's position is one cache line
+    const double* p4;
     // mirrors: mirror_of[j] = k (mirror id n + k) or -1; msrc[k] = j
     const int32_t* mirror_of;
     const int32_t* msrc;
@@ -151,6 +154,7 @@ struct Work {
     int64_t hist_cap = 0;
     // working copy of the state (cell order)
     double* sst[7] = {nullptr};
+    double* p4 = nullptr;                 // 4 x n: x y z 0 of the stencils' state
     double* xref[3] = {nullptr};          // positions at the last list build
     // mirrors
     int32_t* mirror_of = nullptr;
@@ -183,10 +187,7 @@ struct Work {
     double* adj_stash = nullptr;          // 11 x n
     double* coefu = nullptr;              // 27 x n forward velocity coefficients
     int32_t* adj_perm = nullptr;
-    int32_t* adj_slot = nullptr;          // m_max x n
-    double* adj_contrib = nullptr;        // 6 x m_max x n
-    int32_t *adj_cnt = nullptr, *adj_fill = nullptr;   // n
-    int32_t *adj_off = nullptr, *adj_tile = nullptr;   // n + 1, n / BLOCK + 2
+    double* adj_recv = nullptr;           // 6 x n: cotangents received from neighbours
     // captured step sequences
     int32_t* gate = nullptr;              // [0] rebuild, [1] keep
     // second-order steps: predictor state and its right-hand side
@@ -218,6 +219,7 @@ constexpr void work_layout(Work& w, int64_t n_max, int64_t cells_max, int mm,
     A(w.keys0, n_max); A(w.keys1, n_max); A(w.vals0, n_max); A(w.vals1, n_max);
     A(w.hist, 256 * nb);
     for (int a = 0; a < 7; ++a) A(w.sst[a], n_max);
+    A(w.p4, 4 * n_max);
     for (int a = 0; a < 3; ++a) A(w.xref[a], n_max);
     A(w.mirror_of, n_max); A(w.msrc, n_max); A(w.bsum, nb + 1);
     A(w.cs, cells_max); A(w.ce, cells_max);
@@ -237,9 +239,7 @@ constexpr void work_layout(Work& w, int64_t n_max, int64_t cells_max, int mm,
     for (int a = 0; a < 7; ++a) A(w.adj[a], n_max);
     A(w.adj_P, n_max); A(w.adj_E, n_max); A(w.adj_stash, (int64_t)11 * n_max);
     A(w.coefu, (int64_t)27 * n_max); A(w.adj_perm, n_max);
-    A(w.adj_slot, (int64_t)mm * n_max); A(w.adj_contrib, (int64_t)6 * mm * n_max);
-    A(w.adj_cnt, n_max); A(w.adj_fill, n_max); A(w.adj_off, n_max + 1);
-    A(w.adj_tile, n_max / BLOCK + 2);
+    A(w.adj_recv, 6 * n_max);
     A(w.gate, 4); A(w.ids_tmp, n_max);
     for (int a = 0; a < 7; ++a) A(w.sst2[a], n_max);
     for (int a = 0; a < 7; ++a) A(w.adj2[a], n_max);

@@ -25,6 +25,17 @@ __device__ __forceinline__ void to_image(const View& v, const GridInfo& g, Pt& p
     p.y = image_coord(p.y, yi, g.Ly, g.hLy);
 }
 
+// Position of real particle j from its 32-byte record.
+__device__ __forceinline__ void packed_pos(const View& v, int32_t j, double& x, double& y,
+                                          double& z)
+{
+    const double* r = v.p4 + 4 * (int64_t)j;
+    const double2 xy = *reinterpret_cast<const double2*>(r);
+    x = xy.x;
+    y = xy.y;
+    z = r[2];
+}
+
 // Point of neighbour-list entry e (a real id, or MBIT | source of a
 // potential mirror; the mirror exists while its source is within R of the
 // wall, and is placed at (x, y, 2 wall - z)), seen from (xi, yi).
@@ -36,17 +47,14 @@ __device__ __forceinline__ Pt list_point(const View& v, const GridInfo& g,
         const int32_t j = e & ~MBIT;
         const int32_t k = v.mirror_of[j];
         p.valid = k >= 0;
-        p.x = v.x[j];
-        p.y = v.y[j];
-        p.z = dsub(dmul(2.0, g.wall), v.z[j]);
+        packed_pos(v, j, p.x, p.y, p.z);
+        p.z = dsub(dmul(2.0, g.wall), p.z);
         p.id = (int32_t)v.n + k;
         p.src = j;
         p.mirror = true;
     } else {
         p.valid = true;
-        p.x = v.x[e];
-        p.y = v.y[e];
-        p.z = v.z[e];
+        packed_pos(v, e, p.x, p.y, p.z);
         p.id = e;
         p.src = e;
         p.mirror = false;
@@ -94,9 +102,7 @@ __device__ __forceinline__ void gather_list(const View& v, const Seen& s,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t j = e[u] & ~MBIT;
-        p[u].x = v.x[j];
-        p[u].y = v.y[j];
-        p[u].z = v.z[j];
+        packed_pos(v, j, p[u].x, p[u].y, p[u].z);
         p[u].src = j;
         p[u].id = j;
         p[u].mirror = (e[u] & MBIT) != 0;
@@ -249,6 +255,36 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
         Pt p[1];
         gather_list(v, s, e, p);
         f(p[0], dsub(p[0].x, xi), dsub(p[0].y, yi), dsub(p[0].z, zi));
+    }
+}
+
+// Calls f(src, mirror) for every stencil row of real particle i, in the
+// order of visit_stencil: the real particle the row's point stands for
+// (a mirror's source) and whether it is a mirror.  Reads no positions.
+template <int B = 8, class F>
+__device__ __forceinline__ void visit_sources(const View& v, int64_t i, const Rec& r, F&& f)
+{
+    const int64_t n = v.n;
+    if (r.mode & MODE_SORTED) {
+        for (int k = 0; k < r.m; ++k) {
+            const int32_t id = v.hsten[(int64_t)k * n + i];
+            if (id < n) f(id, false);
+            else f(v.msrc[id - n], true);
+        }
+        return;
+    }
+    MaskWalk mw(r);
+    int t = 0;
+    for (; t + B <= r.m; t += B) {
+        int32_t e[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) e[u] = v.vl[(int64_t)mw.pop() * n + i];
+#pragma unroll
+        for (int u = 0; u < B; ++u) f(e[u] & ~MBIT, (e[u] & MBIT) != 0);
+    }
+    for (; t < r.m; ++t) {
+        const int32_t e = v.vl[(int64_t)mw.pop() * n + i];
+        f(e & ~MBIT, (e & MBIT) != 0);
     }
 }
 
