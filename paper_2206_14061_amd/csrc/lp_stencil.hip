@@ -362,6 +362,49 @@ __device__ __forceinline__ void for_candidates(const View& v, const GridInfo& g,
     }
 }
 
+// The points of the SEL_BATCH list entries k0, k0 + 1, ... of particle i
+// for the exact candidate test: positions from the 32-byte records, a
+// mirror's position reflected and its existence taken from its source's
+// height (a mirror exists while the source lies within R of the wall, the
+// rule that sets mirror_of); no ids.  Entries past cnt read i itself (the
+// list rows are VCAP deep, so every row read is in bounds) and are not
+// candidates.  The record offset j * 32 stays below 2^32 (j < 2^27).
+template <bool PERIODIC>
+__device__ __forceinline__ void select_gather(const View& v, const Seen& s,
+                                              const GridInfo& g, int64_t i, int k0,
+                                              int cnt, Pt (&p)[SEL_BATCH])
+{
+    const int64_t n = v.n;
+    int32_t e[SEL_BATCH];
+#pragma unroll
+    for (int u = 0; u < SEL_BATCH; ++u) {
+        const int32_t raw = v.vl[(int64_t)(k0 + u) * n + i];
+        e[u] = k0 + u < cnt ? raw : (int32_t)i;
+    }
+    const char* base = reinterpret_cast<const char*>(v.p4);
+#pragma unroll
+    for (int u = 0; u < SEL_BATCH; ++u) {
+        const uint32_t off = (uint32_t)(e[u] & ~MBIT) << 5;
+        const double* r = reinterpret_cast<const double*>(base + off);
+        const double2 xy = *reinterpret_cast<const double2*>(r);
+        p[u].x = xy.x;
+        p[u].y = xy.y;
+        p[u].z = r[2];
+        p[u].mirror = (e[u] & MBIT) != 0;
+    }
+#pragma unroll
+    for (int u = 0; u < SEL_BATCH; ++u) {
+        const double zs = p[u].z;
+        p[u].valid = !p[u].mirror || dsub(zs, g.wall) < g.R;
+        p[u].z = p[u].mirror ? dsub(s.wall2, zs) : zs;
+        if (PERIODIC) {
+            p[u].x = image_coord(p[u].x, s.xi, s.Lx, s.hLx);
+            p[u].y = image_coord(p[u].y, s.yi, s.Ly, s.hLy);
+        }
+    }
+}
+
+template <bool PERIODIC>
 __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
                                                   unsigned int* hard_n,
                                                   int force_sorted)
@@ -398,12 +441,8 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     Mask4 cm;                          // candidate entries
     uint32_t mb_lo = 0xFFFFFFFFu, mb_hi = 0xFFFFFFFFu;
     for (int k0 = 0; k0 < cnt; k0 += SEL_BATCH) {
-        int32_t e[SEL_BATCH];
-#pragma unroll
-        for (int u = 0; u < SEL_BATCH; ++u)
-            e[u] = k0 + u < cnt ? v.vl[(int64_t)(k0 + u) * n + i] : (int32_t)i;
         Pt pb[SEL_BATCH];
-        gather_list(v, s, e, pb);
+        select_gather<PERIODIC>(v, s, g, i, k0, cnt, pb);
         uint32_t cw[SEL_BATCH / 4];
 #pragma unroll
         for (int w = 0; w < SEL_BATCH / 4; ++w) cw[w] = 0xFFFFFFFFu;
@@ -1021,8 +1060,12 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7])
         const int force = (c->cfg.debug_flags & LP_DEBUG_SORTED_STENCIL) ? 1 : 0;
         // the select phase times the selection kernel alone
         prof_mark(c, 1, false);
-        hipLaunchKernelGGL(k_select, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v,
-                           w.hard, w.hard_n, force);
+        if (c->periodic)
+            hipLaunchKernelGGL(k_select<true>, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v,
+                               w.hard, w.hard_n, force);
+        else
+            hipLaunchKernelGGL(k_select<false>, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v,
+                               w.hard, w.hard_n, force);
         prof_mark(c, 1, true);
         prof_mark(c, 2, false);
         hipLaunchKernelGGL(k_select_sorted, dim3(HARD_BLOCKS), dim3(BLOCK), 0, s, v,
