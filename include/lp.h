@@ -117,7 +117,12 @@ typedef struct {
  * (flag bit 4), then to the linear one.  Cubic fits run in float64 with
  * one wavefront per particle whatever the precision setting, need
  * m_max <= 56 (stencil plus ghost rows fit one wavefront), and are not
- * available to the adjoint entry points. */
+ * available to the adjoint entry points.
+ * min_real_rows (default 0, off): a stencil with fewer real or mirror
+ * rows than this (ghost rows not counted) takes the linear fit (flag bit
+ * 0) instead of the quadratic or cubic one; 9 (as many real rows as the
+ * quadratic fit has unknowns) keeps a free-surface particle with a few
+ * neighbours and many ghost rows from an interpolating quadratic fit. */
 typedef struct {
     int32_t m_max;
     int32_t precision;
@@ -130,6 +135,7 @@ typedef struct {
     int32_t wall_reflect;
     int32_t wall_pressure;
     int32_t fit_order;
+    int32_t min_real_rows;
 } lp_config;
 
 /* Structure-of-arrays particle state, device float64 arrays of length n

@@ -29,7 +29,7 @@ _lib = None
 
 CFG_DEFAULT = dict(m_max=60, ghost_margin=0.5, phi_ghost_frac=0.99,
                    fallback_tol=1e-12, weight=0, wall_reflect=0, wall_pressure=0,
-                   fit_order=2)
+                   fit_order=2, min_real_rows=0)
 
 FLAG_LINEAR = 1
 FLAG_QUAD = 16
@@ -106,7 +106,7 @@ def cfg_vector(cfg: Optional[dict] = None) -> np.ndarray:
         c.update(cfg)
     return np.array([c["m_max"], c["ghost_margin"], c["phi_ghost_frac"],
                      c["fallback_tol"], c["weight"], c["wall_pressure"],
-                     c["fit_order"]], dtype=np.float64)
+                     c["fit_order"], c["min_real_rows"]], dtype=np.float64)
 
 
 def prm_matrix(params: Sequence[Params]) -> np.ndarray:

@@ -49,7 +49,7 @@
 enum { P_RHO, P_D, P_MUS, P_MU2, P_I0, P_PHIC, P_PHIMIN, P_PHIMAX, P_ALPHA,
        P_BETA, P_GX, P_GY, P_GZ, P_H, P_R, P_WALL, P_XLO, P_YLO, P_LX, P_LY,
        P_NPRM };
-enum { C_MMAX, C_GMARGIN, C_PHIG, C_FTOL, C_WEIGHT, C_WALLP, C_ORDER, C_NCFG };
+enum { C_MMAX, C_GMARGIN, C_PHIG, C_FTOL, C_WEIGHT, C_WALLP, C_ORDER, C_MINREAL, C_NCFG };
 
 #define NC 9          /* unknowns of the 2nd-order 3D fit            */
 #define NC3 19        /* unknowns of the 3rd-order (cubic) 3D fit    */
@@ -734,7 +734,11 @@ static unsigned fit_point(const OrcNbr* h, int64_t i, int nf, field_fn val,
     double ratio = 0.0;
     int ok = 0;
     for (int f = 0; f < nf * NC3; ++f) C[f] = 0.0;
-    if (nc == NC3 && m >= NC3) {
+    /* a stencil with fewer real (or mirror) rows than min_real_rows takes
+     * the linear fit whatever its ghost rows add (a reading: with as many
+     * ghost rows as real ones the higher-order fit interpolates) */
+    const int enough_real = ns >= h->cfg[C_MINREAL];
+    if (nc == NC3 && m >= NC3 && enough_real) {
         memcpy(A2, A, sizeof(double) * (size_t)m * NC3);
         memcpy(B2, B, sizeof(double) * (size_t)m * 8);
         ratio = house_lsq(m, NC3, A2, NC3, B2, 8, nf, C);
@@ -743,12 +747,12 @@ static unsigned fit_point(const OrcNbr* h, int64_t i, int nf, field_fn val,
     if (!ok) {
         if (nc == NC3) flags |= FLAG_QUAD;
         ratio = 0.0;
-        if (m >= NC) {
+        if (m >= NC && enough_real) {
             memcpy(A2, A, sizeof(double) * (size_t)m * NC3);
             memcpy(B2, B, sizeof(double) * (size_t)m * 8);
             ratio = house_lsq(m, NC, A2, NC3, B2, 8, nf, C);
         }
-        if (m < NC || ratio < h->cfg[C_FTOL]) {
+        if (m < NC || !enough_real || ratio < h->cfg[C_FTOL]) {
             flags |= FLAG_LINEAR;
             for (int f = 0; f < nf * NC3; ++f) C[f] = 0.0;
             if (m >= 3) {

@@ -120,7 +120,8 @@ class Context:
                  cond_max: float = 20.0, weight: int = LP_W_UNIT,
                  ghost_margin: float = 0.5, fallback_tol: float = 1e-12,
                  debug_flags: int = 0, skin: float = 0.1, wall_reflect: int = 0,
-                 wall_pressure: int = 0, fit_order: int = 2, stream=None):
+                 wall_pressure: int = 0, fit_order: int = 2, min_real_rows: int = 0,
+                 stream=None):
         torch = _torch()
         self.lib = _lib.load()
         cfg = LPConfig()
@@ -132,6 +133,7 @@ class Context:
         cfg.wall_reflect = int(wall_reflect)
         cfg.wall_pressure = int(wall_pressure)
         cfg.fit_order = int(fit_order)
+        cfg.min_real_rows = int(min_real_rows)
         self.cfg = cfg
         if stream is None:
             stream = torch.cuda.current_stream()

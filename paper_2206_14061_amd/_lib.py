@@ -46,7 +46,7 @@ class LPConfig(C.Structure):
                 ("ghost_margin", C.c_double), ("fallback_tol", C.c_double),
                 ("debug_flags", C.c_int32), ("skin", C.c_double),
                 ("wall_reflect", C.c_int32), ("wall_pressure", C.c_int32),
-                ("fit_order", C.c_int32)]
+                ("fit_order", C.c_int32), ("min_real_rows", C.c_int32)]
 
 
 class LPState(C.Structure):

@@ -53,6 +53,7 @@ View make_view(lp_ctx* c, const double* const st[7])
     v.debug = c->cfg.debug_flags;
     v.wall_pressure = c->cfg.wall_pressure;
     v.periodic = c->periodic ? 1 : 0;
+    v.min_real = c->cfg.min_real_rows;
     return v;
 }
 
@@ -218,6 +219,7 @@ void lp_config_default(lp_config* cfg)
     cfg->wall_reflect = 0;
     cfg->wall_pressure = 0;
     cfg->fit_order = 2;
+    cfg->min_real_rows = 0;
 }
 
 lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
@@ -235,7 +237,8 @@ lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
         (c0.wall_reflect != 0 && c0.wall_reflect != 1) ||
         (c0.wall_pressure != 0 && c0.wall_pressure != 1) ||
         (c0.fit_order != 2 && c0.fit_order != 3) ||
-        (c0.fit_order == 3 && c0.m_max > 56))
+        (c0.fit_order == 3 && c0.m_max > 56) ||
+        c0.min_real_rows < 0 || c0.min_real_rows > MMAX_LIMIT)
         return LP_E_ARG;
     lp_ctx* c = new (std::nothrow) lp_ctx();
     if (!c) return LP_E_ARG;

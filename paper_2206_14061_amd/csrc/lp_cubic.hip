@@ -271,13 +271,14 @@ __device__ __forceinline__ uint8_t group_fit3(const View& v, const GridInfo& g,
     };
     uint8_t fl = 0;
     int nc = 0;
-    if (m >= NC3) {
+    const bool enough_real = r.m >= v.min_real;   // else the linear fit
+    if (m >= NC3 && enough_real) {
         load();
         if (group_house<NC3, NF>(sl, m, a, b, rdiag) >= v.fallback_tol) nc = NC3;
     }
     if (nc == 0) {
         fl |= FLAG_QUAD;
-        if (m >= 9) {
+        if (m >= 9 && enough_real) {
             load();
             if (group_house<9, NF>(sl, m, a, b, rdiag) >= v.fallback_tol) nc = 9;
         }

@@ -157,8 +157,9 @@ __device__ uint8_t qr_fit_point(const View& v, const GridInfo& g, int64_t i,
     uint8_t flags = FLAG_QR;
     int mt = build();
     if (mt > MAXROWS) mt = MAXROWS;
-    const double ratio = mt >= 9 ? factor(9) : 0.0;
-    if (mt >= 9 && ratio >= v.fallback_tol) {
+    const bool quad = order_rows(v, r, mt) >= 9;
+    const double ratio = quad ? factor(9) : 0.0;
+    if (quad && ratio >= v.fallback_tol) {
         solve(9);
         return flags;
     }
@@ -248,7 +249,8 @@ __global__ __launch_bounds__(BLOCK) void k_fit_generic(View v, GenericFields F,
     double G[45], c[NF][9], ginv3[27];
     gram_from_moments(M, G);
     uint8_t fl;
-    if (!gram_solve<NF>(G, B, mt, v.redo_ratio, force_qr != 0, c, ginv3, false, fl)) {
+    if (!gram_solve<NF>(G, B, order_rows(v, r, mt), v.redo_ratio, force_qr != 0, c, ginv3,
+                        false, fl)) {
         redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
         if (flags) flags[i] = FLAG_QR;
         return;
@@ -375,7 +377,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
             B[2][q] = lane_sum<LPP>(B[2][q]);
         }
     }
-    pass1_solve(v, o, g, s, i, M, B, mt, sub == 0, redo, redo_n, force_qr);
+    pass1_solve(v, o, g, s, i, M, B, order_rows(v, r, mt), sub == 0, redo, redo_n,
+                force_qr);
 }
 
 // Pass 1 with the neighbours of the block's tile staged in LDS (one lane
@@ -438,7 +441,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
             add_b(a, w, uj, vj, wj);
         });
     }
-    pass1_solve(v, o, g, s, i, M, B, mt, true, redo, redo_n, force_qr);
+    pass1_solve(v, o, g, s, i, M, B, order_rows(v, r, mt), true, redo, redo_n, force_qr);
 }
 
 __global__ __launch_bounds__(QR_TPB) void k_pass1_qr(View v, StepOut o,
@@ -497,8 +500,8 @@ __global__ __launch_bounds__(BLOCK) void k_closure_coef(View v, const double* co
     const double B[1][9] = {{0, 0, 0, 0, 0, 0, 0, 0, 0}};
     double c1[1][9], ginv3[27];
     uint8_t fl;
-    const bool ok = gram_solve<1>(G, B, mt, v.redo_ratio, force_qr != 0, c1, ginv3,
-                                  true, fl);
+    const bool ok = gram_solve<1>(G, B, order_rows(v, r, mt), v.redo_ratio, force_qr != 0,
+                                  c1, ginv3, true, fl);
     if (!ok) {
         redo[atomicAdd(redo_n, 1u)] = (int32_t)i;
         fl = FLAG_QR;
@@ -763,7 +766,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_ref(View v, StepOut o, float
     });
     float U[45];
     gram_from_moments(M, U);
-    const bool lin = mt < 9;
+    const bool lin = order_rows(v, r, mt) < 9;
     const float ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
     // one float32 correction step needs a better conditioned factor than
     // the float64 path: four times the pivot-ratio threshold

@@ -232,6 +232,14 @@ __device__ __forceinline__ void ginv_rows(const double (&U)[45], double out[27])
     }
 }
 
+// Rows the fit's order decision sees: a stencil with fewer real (non-ghost)
+// rows than min_real counts as having fewer than 9 rows, so it takes the
+// linear fit, whatever its ghost rows add.
+__device__ __forceinline__ int order_rows(const View& v, const Rec& r, int mt)
+{
+    return (r.m < v.min_real && mt >= 9) ? 8 : mt;
+}
+
 // Calls f(a, w, p) for every fit row of real particle i: the stencil rows
 // (p = the stencil point) then the ghost rows in octant order (p = null).
 // Returns the number of rows.

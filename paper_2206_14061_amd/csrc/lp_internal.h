@@ -133,6 +133,7 @@ struct View {
     int32_t debug;
     int32_t wall_pressure;      // hydrostatic mirror pressure
     int32_t periodic;           // some system has a periodic axis
+    int32_t min_real;           // fewer real stencil rows: linear fit
 };
 
 struct Work {

@@ -131,7 +131,8 @@ extern "C" lp_status lp_step_noalloc(void* stream, const lp_config* cfg, int32_t
         (c0.wall_reflect != 0 && c0.wall_reflect != 1) ||
         (c0.wall_pressure != 0 && c0.wall_pressure != 1) ||
         (c0.fit_order != 2 && c0.fit_order != 3) ||
-        (c0.fit_order == 3 && c0.m_max > 56))
+        (c0.fit_order == 3 && c0.m_max > 56) ||
+        c0.min_real_rows < 0 || c0.min_real_rows > MMAX_LIMIT)
         return LP_E_ARG;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_DEVICES)
