@@ -47,7 +47,8 @@ def test_struct_layouts_match_header():
     (20 doubles; natural alignment; 7 pointers)."""
     from paper_2206_14061_amd import _lib
     assert ctypes.sizeof(_lib.LPParams) == 20 * 8
-    assert ctypes.sizeof(_lib.LPConfig) == 80
+    assert ctypes.sizeof(_lib.LPConfig) == 72
+    assert _lib.LPConfig.min_real_rows.offset == 68
     assert ctypes.sizeof(_lib.LPState) == 7 * 8
     # lp_step_record: force_sort, resorted (int32), list_gen (int64), perm
     assert ctypes.sizeof(_lib.LPStepRecord) == 24
