@@ -208,6 +208,7 @@ def sheared_bench(torch, lp, lpgen, steps: int):
         ctx = lp.make_context(wl, precision=prec)
         st = lp.DeviceState.from_host(wl.state)
         lanes = ctx.lp_autotune(st)
+        plan = ctx.lp_fit_plan()
         for _ in range(2):
             ctx.lp_step(st, wl.dt)
         ctx.sync_status()
@@ -222,10 +223,53 @@ def sheared_bench(torch, lp, lpgen, steps: int):
         stt = ctx.stats()
         out[name] = {"value": wl.n * steps / t, "unit": "particle-updates/s",
                      "ms_per_step": 1e3 * t / steps, "lanes_per_particle": list(lanes),
+                     "fit_plan": plan,
                      "fp64_refit_fraction": stt["qr_refits"] / (wl.n * steps),
                      "stats": stt}
         del ctx, st
     out["fp32r_speedup_vs_fp64"] = out["fp32r"]["value"] / out["fp64"]["value"]
+    return out
+
+
+def graded_bench(torch, lp, lpgen, steps: int):
+    """Uneven stencils batched by size class: a 1,048,576-particle random
+    cloud whose density falls tenfold with height (stencils from a few
+    neighbours plus ghosts to the full 60 rows), FP64 steps with the fits
+    as one launch per fit (LDS-staged, one lane per particle) and with the
+    plan lp_autotune picks (size classes with their own lanes per particle
+    when faster); the plan, the class histogram and the per-class times
+    lp_autotune measured."""
+    wl = lpgen.cloud_graded()
+    out = {"workload": wl.name, "particles": wl.n, "steps": steps, "dt": wl.dt}
+
+    def timed(ctx, st):
+        for _ in range(2):
+            ctx.lp_step(st, wl.dt)
+        ctx.sync_status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.lp_step(st, wl.dt)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.sync_status()
+        return 1e3 * t / steps
+
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    out["ms_per_step_one_launch"] = timed(ctx, st)
+    del ctx, st
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    ctx.lp_autotune(st)
+    out["fit_plan"] = ctx.lp_fit_plan()
+    out["ms_per_step_autotuned"] = timed(ctx, st)
+    del ctx, st
+    ctx = lp.make_context(wl, debug_flags=lp.LP_DEBUG_CLASSES)
+    st = lp.DeviceState.from_host(wl.state)
+    out["ms_per_step_classes_fixed_lanes"] = timed(ctx, st)
+    out["value"] = wl.n / (1e-3 * out["ms_per_step_autotuned"])
+    out["unit"] = "particle-updates/s"
     return out
 
 
@@ -798,6 +842,7 @@ def main():
                                                         args.adjoint_steps, order=2)
     if not args.no_sheared:
         out["sheared"] = sheared_bench(torch, lp, lpgen, 20)
+        out["graded_cloud"] = graded_bench(torch, lp, lpgen, 10)
     if not args.no_layer:
         out["layer_compression"] = layer_bench(torch, lp, lpgen)
     if args.collapse:

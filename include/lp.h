@@ -51,11 +51,14 @@ enum { LP_FP64 = 0, LP_FP32_REFINED = 1 };
 enum { LP_W_UNIT = 0, LP_W_GAUSS = 1 };
 
 /* debug_flags: route every particle through the exact slow paths, fix
- * the lanes per particle of the fits (see lp_autotune), or make the fits
+ * the lanes per particle of the fits (see lp_autotune), make the fits
  * read every neighbour from global memory instead of from the tile's
- * neighbours staged in LDS (results agree to rounding) */
+ * neighbours staged in LDS, or dispatch the fits by stencil size class
+ * (classes of at most 16, at most 32 and more rows; lanes per particle 1,
+ * 4 and the staged tile kernel in the first fit, 4, 2 and 1 in the
+ * second; results agree to rounding) */
 enum { LP_DEBUG_SORTED_STENCIL = 1, LP_DEBUG_QR_FIT = 2, LP_DEBUG_LANES2 = 4,
-       LP_DEBUG_LANES4 = 8, LP_DEBUG_GLOBAL_GATHER = 16 };
+       LP_DEBUG_LANES4 = 8, LP_DEBUG_GLOBAL_GATHER = 16, LP_DEBUG_CLASSES = 32 };
 
 /* Physical constants of one system (Sec. 2.2, 2.2.1 and Sec. 4).
  * rho_s: grain material density (the paper's phi_s); d: grain diameter;
@@ -301,13 +304,33 @@ lp_status lp_step2(lp_ctx* ctx, lp_state* s, double dt, int32_t* perm,
 /* Chooses how many adjacent lanes of a wavefront share one particle in
  * each of the two least-squares fit kernels (1, 2 or 4: each lane takes
  * every 1st, 2nd or 4th stencil row and the Gram moments are summed across
- * the lanes), by timing every choice on the stencils of s (not modified).
- * lp_step, lp_step_graph and lp_rheology_rhs use the choice afterwards.
- * choice (host int32[2], optional) receives the lanes per particle of the
- * first (u, v, w) and second (P, eta) fit.  Synchronises; leaves the
- * context without a neighbour list and drops a captured graph.  Results
- * differ between choices only by summation order. */
+ * the lanes), by timing every choice on the stencils of s (not modified),
+ * and, for float64 quadratic fits, whether to run the fits by stencil size
+ * class with each class's fastest lanes per particle (lp_fit_plan).
+ * lp_step, lp_step2, lp_step_graph and lp_rheology_rhs use the choice
+ * afterwards.  choice (host int32[2], optional) receives the lanes per
+ * particle of the first (u, v, w) and second (P, eta) fit as one launch.
+ * Synchronises; leaves the context without a neighbour list and drops a
+ * captured graph.  Results differ between choices only by summation
+ * order. */
 lp_status lp_autotune(lp_ctx* ctx, const lp_state* s, int32_t* choice);
+
+/* The fit plan in use (batching of uneven stencils).  plan (host
+ * int32[12]): [0], [1] lanes per particle of the first (u, v, w) and
+ * second (P, eta) fit when each runs as one launch; [2] 1 when the float64
+ * quadratic fits run instead by stencil size class (rows, ghosts
+ * included: at most 16, at most 32, more), one launch per class over its
+ * particles; [3..5], [6..8] lanes per particle of each class in the first
+ * and second fit (0 on the largest class: the one-lane kernel over whole
+ * tiles of particles with their neighbours staged in LDS, skipping the
+ * smaller classes); [9..11] particles per class at the last lp_autotune.
+ * ms (host double[8], optional): the best times lp_autotune measured,
+ * milliseconds: [0], [1] one launch of each fit, [2..4], [5..7] each
+ * class of the first and second fit (0 for an empty class).  lp_autotune
+ * sets the plan (size classes when their total is the faster);
+ * LP_DEBUG_CLASSES starts a context with size classes (lanes as listed
+ * with the debug flags). */
+lp_status lp_fit_plan(lp_ctx* ctx, int32_t* plan, double* ms);
 
 /* nsteps consecutive lp_step calls as one HIP graph, for callers that
  * replay fixed step sequences without host work between steps.  Every

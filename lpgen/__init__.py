@@ -291,6 +291,36 @@ def ensemble(seed: int = BASE_SEED + 5, n_sys: int = 64,
                     np.array(offs, dtype=np.int64), params, 2e-5, 20)
 
 
+def cloud_graded(seed: int = BASE_SEED + 70, n: int = 1 << 20, side_h: int = 96,
+                 ratio: float = 0.1) -> Workload:
+    """Seeded random cloud whose number density falls exponentially with
+    height, from that of the h = 0.5/64 m lattice at the wall to `ratio`
+    of it at the top, so that stencils span from full (60 rows) to a few
+    neighbours plus ghost rows: the uneven stencils of a free surface.
+    Box side_h h square; per particle three draws in id order (x, y, and
+    the height by the inverse of the truncated exponential law); solid
+    fraction 0.59 times the relative density (quasi-static at the bottom,
+    gas at the top); a seeded smooth flow of 0.5 m/s (wavelength 8h);
+    dt = 2e-5 s."""
+    h = 0.5 / 64.0
+    p = default_params(h)
+    side = side_h * h
+    # n = side^2 rho0 lam (1 - ratio) with rho0 = 1/h^3
+    lam = n * h ** 3 / (side * side * (1.0 - ratio))
+    top = -lam * math.log(ratio)
+    u = uniform01(seed, np.arange(3 * n, dtype=np.uint64)).reshape(n, 3)
+    x = side * u[:, 0]
+    y = side * u[:, 1]
+    z = -lam * np.log1p(-u[:, 2] * (1.0 - ratio)) + 0.25 * h
+    rel = np.exp(-(z - 0.25 * h) / lam)
+    zero = np.zeros(n)
+    st = State(x, y, z, zero.copy(), zero.copy(), zero.copy(), 1.0 / (0.59 * rel))
+    f = smooth_field(seed + 1, np.stack([x, y, z], axis=1), 8.0 * h)
+    st.u, st.v, st.w = 0.5 * f[:, 0], 0.5 * f[:, 1], 0.5 * f[:, 2]
+    assert top > 0.0
+    return Workload(f"graded_cloud_{n}", st, np.array([0, n]), [p], 2e-5, 20)
+
+
 def with_shear_velocity(wl: Workload, seed: int = BASE_SEED + 60,
                         amplitude: float = 0.5, wavelength_h: float = 8.0) -> Workload:
     """Copy of ``wl`` whose initial velocity is the seeded smooth field of

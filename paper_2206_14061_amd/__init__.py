@@ -13,7 +13,8 @@ import ctypes as C
 from typing import Dict, List, Optional, Sequence
 
 from . import _lib
-from ._lib import (LP_DEBUG_GLOBAL_GATHER, LP_DEBUG_LANES2, LP_DEBUG_LANES4,
+from ._lib import (LP_DEBUG_CLASSES, LP_DEBUG_GLOBAL_GATHER, LP_DEBUG_LANES2,
+                   LP_DEBUG_LANES4,
                    LP_DEBUG_QR_FIT, LP_DEBUG_SORTED_STENCIL, LP_FP32_REFINED,
                    LP_FP64, LP_W_GAUSS, LP_W_UNIT, LPConfig, LPError,
                    LPParams, LPState, LPStepRecord)
@@ -271,6 +272,21 @@ class Context:
         s = st.struct()
         self._check(self.lib.lp_autotune(self.h, C.byref(s), ch))
         return int(ch[0]), int(ch[1])
+
+    def lp_fit_plan(self) -> Dict:
+        """The fit plan (lanes per particle, size classes) and the times the
+        last lp_autotune measured."""
+        plan = (C.c_int32 * 12)()
+        ms = (C.c_double * 8)()
+        self._check(self.lib.lp_fit_plan(self.h, plan, ms))
+        return {"lanes": [plan[0], plan[1]], "size_classes": bool(plan[2]),
+                "class_rows": ["<=16", "<=32", ">32"],
+                "class_lanes_pass1": [plan[3], plan[4], plan[5]],
+                "class_lanes_pass2": [plan[6], plan[7], plan[8]],
+                "class_particles": [plan[9], plan[10], plan[11]],
+                "ms_one_launch": [ms[0], ms[1]],
+                "ms_class_pass1": [ms[2], ms[3], ms[4]],
+                "ms_class_pass2": [ms[5], ms[6], ms[7]]}
 
     def lp_step_graph(self, st: DeviceState, dt: float, nsteps: int, ids=None):
         """nsteps steps replayed as one HIP graph (captured on first use);

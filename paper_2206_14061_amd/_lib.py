@@ -18,6 +18,7 @@ LP_FP64, LP_FP32_REFINED = 0, 1
 LP_W_UNIT, LP_W_GAUSS = 0, 1
 LP_DEBUG_SORTED_STENCIL, LP_DEBUG_QR_FIT = 1, 2
 LP_DEBUG_LANES2, LP_DEBUG_LANES4, LP_DEBUG_GLOBAL_GATHER = 4, 8, 16
+LP_DEBUG_CLASSES = 32
 
 STATUS_NAMES = {0: "LP_OK", 1: "LP_E_ARG", 2: "LP_E_CAPACITY",
                 3: "LP_E_NUMERIC", 4: "LP_E_HIP", 5: "LP_E_STATE"}
@@ -28,7 +29,7 @@ EXPORTS = ["lp_config_default", "lp_create", "lp_destroy", "lp_last_error",
            "lp_fit_derivs", "lp_rheology_rhs", "lp_step", "lp_step2", "lp_autotune",
            "lp_step_graph", "lp_step_adjoint", "lp_step2_adjoint",
            "lp_sync_status", "lp_stats", "lp_profile", "lp_profile_read",
-           "lp_step_noalloc"]
+           "lp_step_noalloc", "lp_fit_plan"]
 
 
 class LPParams(C.Structure):
@@ -106,6 +107,8 @@ def load():
     lib.lp_step2.restype = C.c_int
     lib.lp_autotune.argtypes = [P, pp(LPState), pp(C.c_int32)]
     lib.lp_autotune.restype = C.c_int
+    lib.lp_fit_plan.argtypes = [P, pp(C.c_int32), pp(C.c_double)]
+    lib.lp_fit_plan.restype = C.c_int
     lib.lp_step_graph.argtypes = [P, pp(LPState), P, C.c_double, i32]
     lib.lp_step_graph.restype = C.c_int
     lib.lp_step_adjoint.argtypes = [P, pp(LPState), C.c_double, pp(LPState),

@@ -93,6 +93,7 @@ void free_work(Work& w)
     for (int a = 0; a < 7; ++a) f(w.sst2[a]);
     for (int a = 0; a < 7; ++a) f(w.adj2[a]);
     f(w.acc2); f(w.dVdt2); f(w.acc); f(w.dVdt); f(w.flags); f(w.coff);
+    f(w.cls_idx); f(w.cls_cnt);
     if (w.h_summary) hipHostFree(w.h_summary);
     w.h_summary = nullptr;
     w.n_max = w.cells_max = 0;
@@ -246,6 +247,16 @@ lp_status lp_create(lp_ctx** out, void* stream, const lp_config* cfg)
     c->cfg = c0;
     if (c0.debug_flags & LP_DEBUG_LANES2) c->lpp1 = c->lpp2 = 2;
     if (c0.debug_flags & LP_DEBUG_LANES4) c->lpp1 = c->lpp2 = 4;
+    if (c0.debug_flags & LP_DEBUG_CLASSES) {
+        // every class dispatch form: lanes 1, 4 and the staged tile kernel
+        // in the first fit, 4, 2 and 1 in the second
+        c->classes = true;
+        const int l1[NCLASS] = {1, 4, 0}, l2[NCLASS] = {4, 2, 1};
+        for (int k = 0; k < NCLASS; ++k) {
+            c->cls_lpp1[k] = l1[k];
+            c->cls_lpp2[k] = l2[k];
+        }
+    }
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return LP_E_HIP;
@@ -607,6 +618,8 @@ lp_status lp_autotune(lp_ctx* c, const lp_state* s, int32_t* choice)
     double* in[7];
     state_arrays(s, in);
     r = cells_build(c, in, nullptr);
+    // with the tile map, as the steps run the fits
+    if (r == LP_OK) r = tile_map_build(c);
     const double* sorted[7];
     for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
     if (r == LP_OK) r = stencils_build(c, sorted);
@@ -617,6 +630,22 @@ lp_status lp_autotune(lp_ctx* c, const lp_state* s, int32_t* choice)
     c->built_x = nullptr;
     drop_graph(c);
     return r;
+}
+
+lp_status lp_fit_plan(lp_ctx* c, int32_t* plan, double* ms)
+{
+    if (!c || !plan) return LP_E_ARG;
+    plan[0] = c->lpp1;
+    plan[1] = c->lpp2;
+    plan[2] = (c->classes && c->cfg.fit_order == 2 && c->cfg.precision == LP_FP64) ? 1 : 0;
+    for (int k = 0; k < NCLASS; ++k) {
+        plan[3 + k] = c->cls_lpp1[k];
+        plan[6 + k] = c->cls_lpp2[k];
+        plan[9 + k] = (int32_t)c->cls_count[k];
+    }
+    if (ms)
+        for (int q = 0; q < 8; ++q) ms[q] = c->tune_ms[q];
+    return LP_OK;
 }
 
 lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,

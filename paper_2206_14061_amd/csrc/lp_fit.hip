@@ -333,15 +333,22 @@ __device__ __forceinline__ void pass1_solve(const View& v, const StepOut& o,
 
 // LPP lanes per particle: each lane accumulates every LPP-th row; the
 // moments are summed across the lanes, every lane solves, lane 0 stores.
+// With idx (a stencil size class): thread group t takes particle idx[t]
+// for t < *icnt.
 template <int LPP>
 __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
                                                     int32_t* redo,
                                                     unsigned int* redo_n,
-                                                    int force_qr)
+                                                    int force_qr, const int32_t* idx,
+                                                    const uint32_t* icnt)
 {
     const int64_t gt = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    const int64_t i = gt / LPP;
+    int64_t i = gt / LPP;
     const int sub = (int)(gt % LPP);
+    if (idx) {
+        if (i >= (int64_t)*icnt) return;
+        i = idx[i];
+    }
     if (i >= v.n) return;
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
@@ -389,10 +396,13 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1(View v, StepOut o,
 // tile when the tile map is stale (map_ok = 0).  UNIT: the weights are unit
 // (known at compile time).
 template <bool UNIT>
+// skip_rows > 0: particles whose stencils have at most skip_rows rows
+// (ghosts included) are left to the size-class launches.
 __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
                                                        int32_t* redo,
                                                        unsigned int* redo_n,
-                                                       int force_qr, int map_ok)
+                                                       int force_qr, int map_ok,
+                                                       int skip_rows)
 {
     __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
     __shared__ double su[STAGE_CAP], sv[STAGE_CAP], sw[STAGE_CAP];
@@ -408,6 +418,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pass1_st(View v, StepOut o,
     const int s = sys_of(v.off, v.n_sys, i);
     const GridInfo& g = v.grid[s];
     const Rec r = load_rec(v, i);
+    if (skip_rows > 0 && r.m + __popc((unsigned)r.gm & 0xFFu) <= skip_rows) return;
     const double ui = v.u[i], vi = v.v[i], wi = v.w[i];
     double M[31], B[3][9];
 #pragma unroll
@@ -549,11 +560,16 @@ template <int LPP>
 __global__ __launch_bounds__(BLOCK) void k_pass2(View v, const double* P,
                                                  const double* eta,
                                                  const double* hand,
-                                                 const uint8_t* flags, RhsOut o)
+                                                 const uint8_t* flags, RhsOut o,
+                                                 const int32_t* idx, const uint32_t* icnt)
 {
     const int64_t gt = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    const int64_t i = gt / LPP;
+    int64_t i = gt / LPP;
     const int sub = (int)(gt % LPP);
+    if (idx) {
+        if (i >= (int64_t)*icnt) return;
+        i = idx[i];
+    }
     if (i >= v.n) return;
     if (flags[i] & FLAG_QR) return;
     const int64_t n = v.n;
@@ -599,7 +615,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
                                                     const double* eta,
                                                     const double* hand,
                                                     const uint8_t* flags, RhsOut o,
-                                                    int map_ok)
+                                                    int map_ok, int skip_rows)
 {
     __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
     __shared__ double sP[STAGE_CAP], sE[STAGE_CAP], sM[STAGE_CAP];
@@ -617,6 +633,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass2_st(View v, const double* P,
     const GridInfo& g = v.grid[s];
     const lp_params& prm = v.prm[s];
     const Rec r = load_rec(v, i);
+    if (skip_rows > 0 && r.m + __popc((unsigned)r.gm & 0xFFu) <= skip_rows) return;
     const double Pi = P[i], Ei = eta[i];
     double yP[9], yE[9];
 #pragma unroll
@@ -992,6 +1009,38 @@ __global__ __launch_bounds__(QR_TPB) void k_pass2_qr(View v, const double* P,
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
+__global__ void k_zero_classes(uint32_t* cnt)
+{
+    if (threadIdx.x < NCLASS) cnt[threadIdx.x] = 0u;
+}
+
+// Sorts the real particles into stencil size classes by their rows (kept
+// stencil rows plus ghost rows): class 0 at most CLASS_ROWS0, class 1 at
+// most CLASS_ROWS1, class 2 more.  Appends are wave-aggregated; the order
+// inside a class is immaterial (every particle's fit is its own).
+__global__ __launch_bounds__(BLOCK) void k_classify(View v, int32_t* idx, uint32_t* cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t n = v.n;
+    int cls = -1;
+    if (i < n) {
+        const int m = v.rec[REC_M * n + i] + __popc((unsigned)v.rec[REC_GM * n + i] & 0xFFu);
+        cls = m <= CLASS_ROWS0 ? 0 : (m <= CLASS_ROWS1 ? 1 : 2);
+    }
+    const int lane = (int)(threadIdx.x & 63u);
+#pragma unroll
+    for (int c = 0; c < NCLASS; ++c) {
+        const unsigned long long mask = __ballot(cls == c);
+        if (!mask) continue;
+        const int leader = __ffsll(mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&cnt[c], (uint32_t)__popcll(mask));
+        base = __shfl(base, leader);
+        if (cls == c)
+            idx[(int64_t)c * n + base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)i;
+    }
+}
+
 __global__ void k_copy_u8(int64_t n, const uint8_t* a, uint8_t* b)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1015,22 +1064,26 @@ void launch_pass1(lp_ctx* c, int lpp, const View& v, const StepOut& so, int fq)
 {
     Work& w = c->w;
     const int64_t n = c->n;
+    const int32_t* no = nullptr;
+    const uint32_t* nc = nullptr;
     switch (lpp) {
     case 4:
         hipLaunchKernelGGL((k_pass1<4>), dim3(blocks_for(4 * n)), dim3(BLOCK), 0,
-                           c->stream, v, so, w.redo, w.redo_n, fq);
+                           c->stream, v, so, w.redo, w.redo_n, fq, no, nc);
         break;
     case 2:
         hipLaunchKernelGGL((k_pass1<2>), dim3(blocks_for(2 * n)), dim3(BLOCK), 0,
-                           c->stream, v, so, w.redo, w.redo_n, fq);
+                           c->stream, v, so, w.redo, w.redo_n, fq, no, nc);
         break;
     default:
         if (c->cfg.weight == LP_W_UNIT)
             hipLaunchKernelGGL(k_pass1_st<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, so, w.redo, w.redo_n, fq, c->map_ok ? 1 : 0);
+                               c->stream, v, so, w.redo, w.redo_n, fq, c->map_ok ? 1 : 0,
+                               0);
         else
             hipLaunchKernelGGL(k_pass1_st<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, so, w.redo, w.redo_n, fq, c->map_ok ? 1 : 0);
+                               c->stream, v, so, w.redo, w.redo_n, fq, c->map_ok ? 1 : 0,
+                               0);
     }
 }
 
@@ -1042,22 +1095,131 @@ void launch_pass2(lp_ctx* c, int lpp, const View& v, const RhsOut& o)
     const double* E = w.eta;
     const double* H = w.hand;
     const uint8_t* F = w.flags;
+    const int32_t* no = nullptr;
+    const uint32_t* nc = nullptr;
     switch (lpp) {
     case 4:
         hipLaunchKernelGGL((k_pass2<4>), dim3(blocks_for(4 * n)), dim3(BLOCK), 0,
-                           c->stream, v, P, E, H, F, o);
+                           c->stream, v, P, E, H, F, o, no, nc);
         break;
     case 2:
         hipLaunchKernelGGL((k_pass2<2>), dim3(blocks_for(2 * n)), dim3(BLOCK), 0,
-                           c->stream, v, P, E, H, F, o);
+                           c->stream, v, P, E, H, F, o, no, nc);
         break;
     default:
         if (c->cfg.weight == LP_W_UNIT)
             hipLaunchKernelGGL(k_pass2_st<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, P, E, H, F, o, c->map_ok ? 1 : 0);
+                               c->stream, v, P, E, H, F, o, c->map_ok ? 1 : 0, 0);
         else
             hipLaunchKernelGGL(k_pass2_st<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                               c->stream, v, P, E, H, F, o, c->map_ok ? 1 : 0);
+                               c->stream, v, P, E, H, F, o, c->map_ok ? 1 : 0, 0);
+    }
+}
+
+// The size classes of the current stencils (one classification per
+// stencil build, shared by both fits).
+void classify(lp_ctx* c, const View& v)
+{
+    Work& w = c->w;
+    hipLaunchKernelGGL(k_zero_classes, dim3(1), dim3(64), 0, c->stream, w.cls_cnt);
+    if (c->n > 0)
+        hipLaunchKernelGGL(k_classify, dim3(blocks_for(c->n)), dim3(BLOCK), 0, c->stream,
+                           v, w.cls_idx, w.cls_cnt);
+}
+
+// One class of the pass-1 fit with lpp lanes per particle (the grid covers
+// every particle; threads past the class's count return at once).
+void launch_pass1_class(lp_ctx* c, int cls, int lpp, const View& v, const StepOut& so,
+                        int fq)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    const int32_t* idx = w.cls_idx + (int64_t)cls * n;
+    const uint32_t* cnt = w.cls_cnt + cls;
+    if (lpp == 0) {
+        // the largest class through the LDS-staged tile kernel
+        const int mo = c->map_ok ? 1 : 0;
+        if (c->cfg.weight == LP_W_UNIT)
+            hipLaunchKernelGGL(k_pass1_st<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, so, w.redo, w.redo_n, fq, mo, CLASS_ROWS1);
+        else
+            hipLaunchKernelGGL(k_pass1_st<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, so, w.redo, w.redo_n, fq, mo, CLASS_ROWS1);
+        return;
+    }
+    switch (lpp) {
+    case 4:
+        hipLaunchKernelGGL((k_pass1<4>), dim3(blocks_for(4 * n)), dim3(BLOCK), 0,
+                           c->stream, v, so, w.redo, w.redo_n, fq, idx, cnt);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_pass1<2>), dim3(blocks_for(2 * n)), dim3(BLOCK), 0,
+                           c->stream, v, so, w.redo, w.redo_n, fq, idx, cnt);
+        break;
+    default:
+        hipLaunchKernelGGL((k_pass1<1>), dim3(blocks_for(n)), dim3(BLOCK), 0,
+                           c->stream, v, so, w.redo, w.redo_n, fq, idx, cnt);
+    }
+}
+
+void launch_pass2_class(lp_ctx* c, int cls, int lpp, const View& v, const RhsOut& o)
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    const int32_t* idx = w.cls_idx + (int64_t)cls * n;
+    const uint32_t* cnt = w.cls_cnt + cls;
+    const double* P = w.P;
+    const double* E = w.eta;
+    const double* H = w.hand;
+    const uint8_t* F = w.flags;
+    if (lpp == 0) {
+        const int mo = c->map_ok ? 1 : 0;
+        if (c->cfg.weight == LP_W_UNIT)
+            hipLaunchKernelGGL(k_pass2_st<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, P, E, H, F, o, mo, CLASS_ROWS1);
+        else
+            hipLaunchKernelGGL(k_pass2_st<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, v, P, E, H, F, o, mo, CLASS_ROWS1);
+        return;
+    }
+    switch (lpp) {
+    case 4:
+        hipLaunchKernelGGL((k_pass2<4>), dim3(blocks_for(4 * n)), dim3(BLOCK), 0,
+                           c->stream, v, P, E, H, F, o, idx, cnt);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_pass2<2>), dim3(blocks_for(2 * n)), dim3(BLOCK), 0,
+                           c->stream, v, P, E, H, F, o, idx, cnt);
+        break;
+    default:
+        hipLaunchKernelGGL((k_pass2<1>), dim3(blocks_for(n)), dim3(BLOCK), 0,
+                           c->stream, v, P, E, H, F, o, idx, cnt);
+    }
+}
+
+// Size-class dispatch applies to the float64 quadratic fits.
+bool classes_on(const lp_ctx* c)
+{
+    return c->classes && c->cfg.fit_order == 2 && c->cfg.precision == LP_FP64;
+}
+
+// Pass 1 of a step: the size classes with their lanes, or one launch.
+void run_pass1(lp_ctx* c, const View& v, const StepOut& so, int fq)
+{
+    if (classes_on(c)) {
+        classify(c, v);
+        for (int k = 0; k < NCLASS; ++k) launch_pass1_class(c, k, c->cls_lpp1[k], v, so, fq);
+    } else {
+        launch_pass1(c, c->lpp1, v, so, fq);
+    }
+}
+
+void run_pass2(lp_ctx* c, const View& v, const RhsOut& o)
+{
+    if (classes_on(c)) {
+        for (int k = 0; k < NCLASS; ++k) launch_pass2_class(c, k, c->cls_lpp2[k], v, o);
+    } else {
+        launch_pass2(c, c->lpp2, v, o);
     }
 }
 
@@ -1177,7 +1339,7 @@ lp_status step_rhs(lp_ctx* c, const double* const st[7])
                                    c->stream, v, so, w.uf, w.redo, w.redo_n, mo);
         }
         else
-            launch_pass1(c, c->lpp1, v, so, fq);
+            run_pass1(c, v, so, fq);
         prof_mark(c, 3, true);
         prof_mark(c, 4, false);
         hipLaunchKernelGGL(k_pass1_qr, dim3(QR_BLOCKS), dim3(QR_TPB), 0,
@@ -1198,6 +1360,8 @@ lp_status step_pass1_coef(lp_ctx* c, const double* const st[7])
     StepOut so{w.P, w.eta, w.hand, w.flags, nullptr, w.coefu};
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
     if (n > 0) {
+        // the pass-2 fit of these stencils may run by size class
+        if (classes_on(c)) classify(c, v);
         launch_pass1(c, c->lpp1, v, so, 0);
         hipLaunchKernelGGL(k_pass1_qr, dim3(QR_BLOCKS), dim3(QR_TPB), 0,
                            c->stream, v, so, (const int32_t*)w.redo,
@@ -1235,7 +1399,7 @@ lp_status step_pass2(lp_ctx* c, const double* const st[7], double dt,
                                    (const uint8_t*)w.flags, o, mo);
         }
         else
-            launch_pass2(c, c->lpp2, v, o);
+            run_pass2(c, v, o);
         prof_mark(c, 5, true);
         prof_mark(c, 6, false);
         hipLaunchKernelGGL(k_pass2_qr, dim3(QR_BLOCKS), dim3(QR_TPB), 0,
@@ -1262,45 +1426,103 @@ lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice)
         return LP_OK;
     }
     Work& w = c->w;
-    const int64_t n = c->n;
     View v = make_view(c, st);
     StepOut so{w.P, w.eta, w.hand, w.flags, nullptr, nullptr};
     RhsOut o = rhs_out(c, w.acc, w.dVdt, nullptr);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
+    // best of three timings of one launch sequence
+    auto timed = [&](auto&& launch) -> float {
+        float t = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+            e = hipEventRecord(e0, c->stream);
+            launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            t = ms < t ? ms : t;
+        }
+        return t;
+    };
     const int cand[3] = {1, 2, 4};
+    // one launch over all particles, 1 (LDS-staged when the tile map is
+    // current), 2 or 4 lanes per particle
     float best1 = 1e30f, best2 = 1e30f;
     int pick1 = 1, pick2 = 1;
-    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
-        for (int q = 0; q < 3 && e == hipSuccess; ++q) {
-            float t = 1e30f;
-            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-                hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
-                e = hipEventRecord(e0, c->stream);
-                if (pass == 0) launch_pass1(c, cand[q], v, so, 0);
-                else launch_pass2(c, cand[q], v, o);
-                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                t = ms < t ? ms : t;
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+        const float t = timed([&] { launch_pass1(c, cand[q], v, so, 0); });
+        if (t < best1) { best1 = t; pick1 = cand[q]; }
+    }
+    // pass 2 needs the pass-1 outputs
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+        launch_pass1(c, pick1, v, so, 0);
+    }
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+        const float t = timed([&] { launch_pass2(c, cand[q], v, o); });
+        if (t < best2) { best2 = t; pick2 = cand[q]; }
+    }
+    // by stencil size class (float64 quadratic fits): each class with its
+    // own lanes per particle
+    bool use_classes = false;
+    float cb1[NCLASS] = {0.f, 0.f, 0.f}, cb2[NCLASS] = {0.f, 0.f, 0.f};
+    int cp1[NCLASS] = {1, 1, 1}, cp2[NCLASS] = {1, 1, 1};
+    uint32_t counts[4] = {0, 0, 0, 0};
+    if (e == hipSuccess && c->cfg.precision == LP_FP64 && c->n > 0) {
+        classify(c, v);
+        e = hipMemcpyAsync(counts, w.cls_cnt, sizeof(uint32_t) * NCLASS,
+                           hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        for (int k = 0; k < NCLASS && e == hipSuccess; ++k) {
+            cb1[k] = 1e30f;
+            if (counts[k] == 0) {
+                cb1[k] = 0.f;
+                continue;
             }
-            if (pass == 0 && t < best1) { best1 = t; pick1 = cand[q]; }
-            if (pass == 1 && t < best2) { best2 = t; pick2 = cand[q]; }
+            for (int q = (k == NCLASS - 1 ? -1 : 0); q < 3 && e == hipSuccess; ++q) {
+                const int l = q < 0 ? 0 : cand[q];   // 0: staged tile kernel
+                const float t = timed([&] { launch_pass1_class(c, k, l, v, so, 0); });
+                if (t < cb1[k]) { cb1[k] = t; cp1[k] = l; }
+            }
         }
-        if (pass == 0 && e == hipSuccess) {
-            // pass 2 needs the pass-1 outputs of the chosen variant
+        if (e == hipSuccess) {
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
             launch_pass1(c, pick1, v, so, 0);
         }
+        for (int k = 0; k < NCLASS && e == hipSuccess; ++k) {
+            cb2[k] = 1e30f;
+            if (counts[k] == 0) {
+                cb2[k] = 0.f;
+                continue;
+            }
+            for (int q = (k == NCLASS - 1 ? -1 : 0); q < 3 && e == hipSuccess; ++q) {
+                const int l = q < 0 ? 0 : cand[q];
+                const float t = timed([&] { launch_pass2_class(c, k, l, v, o); });
+                if (t < cb2[k]) { cb2[k] = t; cp2[k] = l; }
+            }
+        }
+        float tot = 0.f;
+        for (int k = 0; k < NCLASS; ++k) tot += cb1[k] + cb2[k];
+        use_classes = tot < best1 + best2;
     }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(c, e, "autotune");
-    (void)n;
     c->lpp1 = pick1;
     c->lpp2 = pick2;
+    c->classes = use_classes;
+    c->tune_ms[0] = best1;
+    c->tune_ms[1] = best2;
+    for (int k = 0; k < NCLASS; ++k) {
+        c->cls_lpp1[k] = cp1[k];
+        c->cls_lpp2[k] = cp2[k];
+        c->cls_count[k] = counts[k];
+        c->tune_ms[2 + k] = cb1[k];
+        c->tune_ms[5 + k] = cb2[k];
+    }
     if (choice) {
         choice[0] = pick1;
         choice[1] = pick2;

@@ -41,6 +41,10 @@ constexpr uint8_t NO_CAND = 0xFF; // key code of a list entry outside R
 constexpr int HARD_CAP = 256;     // candidates the sorted stencil path holds
 constexpr int HARD_BLOCKS = 1024; // blocks of the sorted path (a wave per particle)
 constexpr int HAND = 37;          // pass-1 -> pass-2 handoff doubles
+// stencil size classes of the fits (rows, ghosts included): at most 16,
+// at most 32, more
+constexpr int NCLASS = 3;
+constexpr int CLASS_ROWS0 = 16, CLASS_ROWS1 = 32;
 constexpr int BLOCK = 256;        // threads per block of per-particle kernels
 constexpr int SORT_ITEMS = 16;    // keys per thread in a radix tile
 constexpr int SORT_TILE = BLOCK * SORT_ITEMS;
@@ -200,6 +204,10 @@ struct Work {
     double* acc = nullptr;                // 3 x n
     double* dVdt = nullptr;
     uint8_t* flags = nullptr;
+    // stencil size classes: particles of class c at cls_idx[c n ...],
+    // their count in cls_cnt[c]
+    int32_t* cls_idx = nullptr;
+    uint32_t* cls_cnt = nullptr;
     // export helpers
     int64_t* coff = nullptr;
 };
@@ -236,6 +244,7 @@ constexpr void work_layout(Work& w, int64_t n_max, int64_t cells_max, int mm,
     A(w.P, n_max); A(w.eta, n_max); A(w.hand, (int64_t)HAND * n_max);
     A(w.uf, (int64_t)45 * n_max);
     A(w.acc, 3 * n_max); A(w.dVdt, n_max); A(w.flags, n_max);
+    A(w.cls_idx, NCLASS * n_max); A(w.cls_cnt, 4);
     if (forward_only) return;
     for (int a = 0; a < 7; ++a) A(w.adj[a], n_max);
     A(w.adj_P, n_max); A(w.adj_E, n_max); A(w.adj_stash, (int64_t)11 * n_max);
@@ -267,6 +276,14 @@ struct lp_ctx {
     bool list_ok = false;       // neighbour list valid for the working state
     int64_t list_gen = 0;       // generation of the current list (one per build)
     int lpp1 = 1, lpp2 = 1;     // lanes per particle of the two fit kernels
+    // size-class dispatch of the fits (lp_autotune, LP_DEBUG_CLASSES):
+    // lanes per particle of each class in each fit, and what the last
+    // autotune measured (class counts, best milliseconds)
+    bool classes = false;
+    // (lanes 0 on the largest class: the LDS-staged one-lane tile kernel)
+    int cls_lpp1[lp::NCLASS] = {1, 2, 4}, cls_lpp2[lp::NCLASS] = {1, 2, 4};
+    int64_t cls_count[lp::NCLASS] = {0, 0, 0};
+    double tune_ms[8] = {0};
     int64_t rebuilds = 0;       // list rebuilds since the last lp_stats
     // phase timing (lp_profile)
     bool prof = false;
