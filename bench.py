@@ -666,6 +666,11 @@ def adjoint_fd_check(torch, lp, lpgen, grad, steps: int):
     return out
 
 
+def _progress(msg):
+    """One line on stderr as each block of the benchmark finishes."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     args = _parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -745,6 +750,7 @@ def main():
     # re-sorted) at every step
     k0 = max(2, args.steps // 2)
     ms_rebuild, _, _ = run(k0, args.warmup, precision=main_prec, skin=0.0)
+    _progress("column steps done (%.4f ms/step)" % ms_eager)
     fp64 = args.precision == "fp64"
     t_pass1 = phases["pass1"] * 1e-3
     if fp64:
@@ -824,8 +830,10 @@ def main():
     if not args.no_second_order:
         out["second_order"] = second_order_bench(torch, lp, wl, args.steps, args.warmup,
                                                  main_prec, ms_eager)
+        _progress("second-order steps done")
     if not args.no_cubic:
         out["cubic_fits"] = cubic_bench(torch, lp, wl, args.steps, args.warmup)
+        _progress("cubic fits done")
     if not args.no_errors:
         # the benchmark column starts at rest (u = 0: every velocity
         # derivative, eta and I are exactly 0), so the errors are taken on
@@ -833,25 +841,33 @@ def main():
         wl_flow = lpgen.with_shear_velocity(wl)
         out["errors_vs_oracle"] = {"workload": wl_flow.name,
                                    **errors_vs_oracle(torch, lp, wl_flow)}
+        _progress("errors against the oracle done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
         out["adjoint"]["fd_check"] = adjoint_fd_check(
             torch, lp, lpgen, out["adjoint"]["dL_dtheta"][0], args.adjoint_steps)
+        _progress("adjoint and its central differences done")
         if not args.no_second_order:
             out["adjoint_second_order"] = adjoint_bench(torch, lp, lpgen,
                                                         args.adjoint_steps, order=2)
+            _progress("second-order adjoint done")
     if not args.no_sheared:
         out["sheared"] = sheared_bench(torch, lp, lpgen, 20)
         out["graded_cloud"] = graded_bench(torch, lp, lpgen, 10)
+        _progress("sheared column and graded cloud done")
     if not args.no_layer:
         out["layer_compression"] = layer_bench(torch, lp, lpgen)
+        _progress("layer compression done")
     if args.collapse:
         out["collapse"] = collapse_run(torch, lp, lpgen)
+        _progress("column collapse done")
     if not args.no_ensemble:
         out["ensemble"] = ensemble_bench(torch, lp, lpgen, args.ensemble_steps,
                                          args.ensemble_adjoint_steps)
+        _progress("ensemble done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        _progress("cpu baseline done")
     if args.copy_calibration:
         out["copy_calibration_bytes"] = copy_calibration(torch)
     print(json.dumps(out), flush=True)
