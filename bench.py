@@ -392,15 +392,20 @@ def layer_bench(torch, lp, lpgen, t_end: float = 0.05, every: float = 0.005):
 
 
 def collapse_run(torch, lp, lpgen, t_end: float = 0.17, every: float = 0.01,
-                 u_stop: float = 20.0):
+                 dv_max: float = 0.02, dt_floor: float = 1.0 / 1024):
     """Axisymmetric column collapse, a = 0.6 (r_i = 0.05 m, h_i = 0.03 m,
-    120,631 particles, h = 1.25 mm): second-order steps with the reflecting
-    wall, the hydrostatic mirror pressure, a linear-fallback tolerance of
-    5e-2, the linear fit for stencils of fewer than 9 real rows and a list
-    skin of 0.3.  Reports the runout radius (99th percentile of the particle
-    radius), the centre height and the largest speed every `every` s, and
-    the empirical fits r_inf = r_i (1 + 1.24 a), h_inf = a r_i, t_inf =
-    3 sqrt(h_i / g).  Stops early once some particle exceeds u_stop m/s."""
+    120,631 particles, h = 1.25 mm) to t_end: second-order steps with the
+    reflecting wall, the hydrostatic mirror pressure, a linear-fallback
+    tolerance of 5e-2, the linear fit for stencils of fewer than 9 real rows
+    and a list skin of 0.3, under a step-size control on the relative
+    volume change: a step that changes some particle's V by more than
+    dv_max (relative), or whose predictor leaves the neighbour list, is
+    undone and retried at half the step (re-sorting first); the step grows
+    back by 1.25x, up to the workload's dt, after steps that change V by
+    less than dv_max / 4.  Reports the runout radius (99th percentile of the
+    particle radius), the centre height and the largest speed every `every`
+    s, and the empirical fits r_inf = r_i (1 + 1.24 a), h_inf = a r_i, t_inf
+    = 3 sqrt(h_i / g)."""
     wl = lpgen.column_cylinder()
     p = wl.params[0]
     # skin 0.3: fast front particles leave the predictor inside the list;
@@ -410,32 +415,74 @@ def collapse_run(torch, lp, lpgen, t_end: float = 0.17, every: float = 0.01,
     ctx.reserve(wl.n, 1 << 24)
     ctx.set_systems(list(wl.offsets), wl.params)
     st = lp.DeviceState.from_host(wl.state)
-    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
-    per = int(round(every / wl.dt))
-    rows, stop = [], "t_end"
     q = torch.tensor([0.99], dtype=torch.float64, device="cuda")
-    t0 = time.perf_counter()
-    for c in range(int(round(t_end / every)) + 1):
-        if c:
-            try:
-                for _ in range(per):
-                    ctx.lp_step2(st, wl.dt, perm)
-                ctx.sync_status()
-            except lp.LPError as e:
-                stop = "error: %s" % e
-                break
+    dt0 = wl.dt
+    dt, t, steps, rejected, dt_min = dt0, 0.0, 0, 0, dt0
+    resort = lp.StepRecord(wl.n, force_sort=True)
+    perm = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+    rows, stop = [], "t_end"
+
+    def sample():
         r = torch.sqrt(st.t[0] ** 2 + st.t[1] ** 2)
         u = torch.sqrt(st.t[3] ** 2 + st.t[4] ** 2 + st.t[5] ** 2)
         core = r < 0.2 * 0.05
-        rows.append({"t": c * every, "r99_m": float(torch.quantile(r, q)),
+        rows.append({"t": t, "r99_m": float(torch.quantile(r, q)),
                      "h_center_m": float(st.t[2][core].max()) if bool(core.any()) else None,
-                     "u_max": float(u.max())})
-        if rows[-1]["u_max"] > u_stop:
-            stop = "u_max above %g m/s" % u_stop
-            break
+                     "u_max": float(u.max()), "phi_max": float((1.0 / st.t[6]).max()),
+                     "dt": dt, "steps": steps})
+        _progress("collapse t = %.3f s: r99 %.4f m, u_max %.2f m/s, %d steps, %d undone"
+                  % (t, rows[-1]["r99_m"], rows[-1]["u_max"], steps, rejected))
+
+    sample()
+    t0 = time.perf_counter()
+    retry = False
+    next_sample = every
+    while t < t_end - 1e-12:
+        h_dt = min(dt, t_end - t)
+        prev = st.clone()
+        ok = True
+        try:
+            if retry:
+                ctx.lp_step2(st, h_dt, rec=resort)
+                order = resort.perm[:wl.n].long()
+            else:
+                ctx.lp_step2(st, h_dt, perm)
+                order = perm.long()
+            ctx.sync_status()
+            # the step may re-sort: perm[new] = old
+            dv = float((st.t[6] / prev.t[6][order] - 1.0).abs().max())
+            ok = dv <= dv_max
+        except lp.LPError as e:
+            if e.status != lp._lib.LP_E_STATE:
+                stop = "error: %s" % e
+                break
+            ok, dv = False, float("inf")
+        if not ok:
+            # undo: the previous state, a fresh sort, half the step
+            st = prev
+            rejected += 1
+            dt *= 0.5
+            dt_min = min(dt_min, dt)
+            retry = True
+            if dt < dt_floor * dt0:
+                stop = ("some particle's volume collapses faster than any step "
+                        "resolves (the step fell below %g of dt)" % dt_floor)
+                break
+            continue
+        retry = False
+        t += h_dt
+        steps += 1
+        if dv < 0.25 * dv_max:
+            dt = min(dt0, 1.25 * dt)
+        if t >= next_sample - 1e-12:
+            sample()
+            next_sample += every
+    if rows[-1]["t"] < t:
+        sample()
     a, r_i, h_i = 0.6, 0.05, 0.03
-    return {"workload": wl.name, "particles": wl.n, "dt": wl.dt, "series": rows,
-            "stopped": stop, "seconds": time.perf_counter() - t0,
+    return {"workload": wl.name, "particles": wl.n, "dt": dt0, "series": rows,
+            "stopped": stop, "seconds": time.perf_counter() - t0, "steps": steps,
+            "rejected_steps": rejected, "dt_min": dt_min, "dv_max": dv_max,
             "lube_r_inf_m": r_i * (1.0 + 1.24 * a), "lube_h_inf_m": a * r_i,
             "lube_t_inf_s": 3.0 * (h_i / abs(p.g[2])) ** 0.5,
             "paper_r_m": 0.085, "paper_h_m": 0.027}
