@@ -128,7 +128,7 @@ __device__ __forceinline__ double fit_row(const View& v, const GridInfo& g, int6
             pt = id_point(v, g, v.hsten[(int64_t)row * n + i], xi, yi);
         } else {
             const int k = mask_select(r, row);
-            pt = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
+            pt = list_point(v, g, v.vl[vl_at(n, i, k)], xi, yi);
         }
         const double dx = dsub(pt.x, xi), dy = dsub(pt.y, yi), dz = dsub(pt.z, zi);
         taylor_row3(dx * g.inv_h, dy * g.inv_h, dz * g.inv_h, a);

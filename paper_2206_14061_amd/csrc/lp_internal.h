@@ -21,6 +21,33 @@ constexpr int HIST_BUCKETS = 64;  // r^2 histogram of the stencil selection
 constexpr int LIST_CAP = LP_LIST_CAP;  // cut-bucket members ranked per thread
 constexpr int VCAP = 256;         // neighbour-list entries per particle
 constexpr int MASK_WORDS = VCAP / 64;  // keep bitmask words per particle
+// Neighbour-list layout: a particle's entries come in chunks of VCHUNK
+// consecutive entries (32 bytes, one cache sector), chunk c of every
+// particle before chunk c + 1.  A thread appending entries fills one
+// sector at a time, and reads entries k0 .. k0 + 7 (k0 a multiple of 8)
+// as two 16-byte loads.
+constexpr int VCHUNK = 8;
+__host__ __device__ __forceinline__ int64_t vl_at(int64_t n, int64_t i, int k)
+{
+    return ((int64_t)(k / VCHUNK) * n + i) * VCHUNK + (k % VCHUNK);
+}
+// Entries k0 .. k0 + U - 1 of particle i (U a multiple of 4 dividing
+// VCHUNK, k0 a multiple of U): U / 4 loads of 16 bytes.
+template <int U>
+__device__ __forceinline__ void vl_load(const int32_t* vl, int64_t n, int64_t i, int k0,
+                                        int32_t (&e)[U])
+{
+    static_assert(U % 4 == 0 && VCHUNK % U == 0, "whole 16-byte words of one chunk");
+    const int4* q = reinterpret_cast<const int4*>(vl + vl_at(n, i, k0));
+#pragma unroll
+    for (int w = 0; w < U / 4; ++w) {
+        const int4 a = q[w];
+        e[4 * w] = a.x;
+        e[4 * w + 1] = a.y;
+        e[4 * w + 2] = a.z;
+        e[4 * w + 3] = a.w;
+    }
+}
 // A tile is BLOCK consecutive particles.  The fits stage the fields of the
 // distinct sources of a tile's neighbour lists in LDS (at most STAGE_CAP
 // of them); a list entry names its source's slot in a 16-bit word whose
@@ -115,7 +142,7 @@ struct View {
     // mirrors: mirror_of[j] = k (mirror id n + k) or -1; msrc[k] = j
     const int32_t* mirror_of;
     const int32_t* msrc;
-    // neighbour list with skin (ELL, entry k of particle i at k*n + i)
+    // neighbour list with skin (entry k of particle i at vl_at(n, i, k))
     const int32_t* vl;
     const int32_t* vcnt;
     // per tile: its list sources in ascending order (STAGE_CAP per tile)

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
                             if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
                             if (mirror && !(pz[u] - g.wall < g.Rv)) continue;
                             if (cnt < VCAP)
-                                vl[(int64_t)cnt * n + i] = mirror ? (j | MBIT) : j;
+                                vl[vl_at(n, i, cnt)] = mirror ? (j | MBIT) : j;
                             ++cnt;
                         }
                     }
@@ -354,7 +354,7 @@ __device__ __forceinline__ void for_candidates(const View& v, const GridInfo& g,
     const double R2 = g.R2;
     const int cnt = v.vcnt[i];
     for (int k = 0; k < cnt; ++k) {
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
+        const Pt p = list_point(v, g, v.vl[vl_at(n, i, k)], xi, yi);
         if (!p.valid) continue;
         const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
         const double r2 = dist2(dx, dy, dz);
@@ -366,9 +366,9 @@ __device__ __forceinline__ void for_candidates(const View& v, const GridInfo& g,
 // for the exact candidate test: positions from the 32-byte records, a
 // mirror's position reflected and its existence taken from its source's
 // height (a mirror exists while the source lies within R of the wall, the
-// rule that sets mirror_of); no ids.  Entries past cnt read i itself (the
-// list rows are VCAP deep, so every row read is in bounds) and are not
-// candidates.  The record offset j * 32 stays below 2^32 (j < 2^27).
+// rule that sets mirror_of); no ids.  Entries past cnt are read (every
+// particle holds VCAP list slots, so every read is in bounds) but stand
+// for i itself and are not candidates.  The record offset j * 32 stays below 2^32 (j < 2^27).
 template <bool PERIODIC>
 __device__ __forceinline__ void select_gather(const View& v, const Seen& s,
                                               const GridInfo& g, int64_t i, int k0,
@@ -376,11 +376,9 @@ __device__ __forceinline__ void select_gather(const View& v, const Seen& s,
 {
     const int64_t n = v.n;
     int32_t e[SEL_BATCH];
+    vl_load(v.vl, n, i, k0, e);
 #pragma unroll
-    for (int u = 0; u < SEL_BATCH; ++u) {
-        const int32_t raw = v.vl[(int64_t)(k0 + u) * n + i];
-        e[u] = k0 + u < cnt ? raw : (int32_t)i;
-    }
+    for (int u = 0; u < SEL_BATCH; ++u) e[u] = k0 + u < cnt ? e[u] : (int32_t)i;
     const char* base = reinterpret_cast<const char*>(v.p4);
 #pragma unroll
     for (int u = 0; u < SEL_BATCH; ++u) {
@@ -548,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
         int32_t e[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            e[u] = a0 + u < nl ? v.vl[(int64_t)lkey[a0 + u][t] * n + i] : (int32_t)i;
+            e[u] = a0 + u < nl ? v.vl[vl_at(n, i, lkey[a0 + u][t])] : (int32_t)i;
         Pt pb[4];
         gather_list(v, s, e, pb);
 #pragma unroll
@@ -562,7 +560,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
         }
     }
     auto exact_key = [&](int k, double& r2, int32_t& id) {
-        const int32_t e[1] = {v.vl[(int64_t)k * n + i]};
+        const int32_t e[1] = {v.vl[vl_at(n, i, k)]};
         Pt p[1];
         gather_list(v, s, e, p);
         r2 = dist2(dsub(p[0].x, xi), dsub(p[0].y, yi), dsub(p[0].z, zi));
@@ -614,7 +612,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
             for (int k = 0; k < cnt; ++k) {
                 if ((int)((code[(int64_t)(k >> 2) * n + i] >> (8 * (k & 3))) & 0xFFu) != mo)
                     continue;
-                const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
+                const Pt p = list_point(v, g, v.vl[vl_at(n, i, k)], xi, yi);
                 const double dx = dsub(p.x, xi), dy = dsub(p.y, yi), dz = dsub(p.z, zi);
                 if (octant_of(dx, dy, dz) != o) continue;
                 const double r2 = dist2(dx, dy, dz);
@@ -674,7 +672,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_sorted(
             double r2 = 0.0;
             int32_t key = 0;
             if (k < cnt_i) {
-                const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
+                const Pt p = list_point(v, g, v.vl[vl_at(n, i, k)], xi, yi);
                 if (p.valid) {
                     const double dx = dsub(p.x, xi), dy = dsub(p.y, yi),
                                  dz = dsub(p.z, zi);
@@ -900,9 +898,9 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
         // a full set ends the insertions (the tile is not staged)
         if (*(volatile int*)&full) break;
         int32_t jb[MAP_BATCH];
+        vl_load(vl, n, i, k0, jb);
 #pragma unroll
-        for (int u = 0; u < MAP_BATCH; ++u)
-            jb[u] = k0 + u < cnt ? vl[(int64_t)(k0 + u) * n + i] & ~MBIT : -1;
+        for (int u = 0; u < MAP_BATCH; ++u) jb[u] = k0 + u < cnt ? jb[u] & ~MBIT : -1;
 #pragma unroll
         for (int u = 0; u < MAP_BATCH; ++u) {
             const int32_t j = jb[u];
@@ -964,9 +962,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
     __syncthreads();
     for (int k0 = 0; k0 < cnt; k0 += MAP_BATCH) {
         int32_t eb[MAP_BATCH];
-#pragma unroll
-        for (int u = 0; u < MAP_BATCH; ++u)
-            eb[u] = k0 + u < cnt ? vl[(int64_t)(k0 + u) * n + i] : 0;
+        vl_load(vl, n, i, k0, eb);
 #pragma unroll
         for (int u = 0; u < MAP_BATCH; ++u) {
             if (k0 + u >= cnt) continue;

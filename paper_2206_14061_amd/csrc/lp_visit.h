@@ -243,7 +243,7 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
     for (; t + B <= r.m; t += B) {
         int32_t e[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) e[u] = v.vl[(int64_t)mw.pop() * n + i];
+        for (int u = 0; u < B; ++u) e[u] = v.vl[vl_at(n, i, mw.pop())];
         Pt p[B];
         gather_list(v, s, e, p);
 #pragma unroll
@@ -251,7 +251,7 @@ __device__ __forceinline__ void visit_stencil(const View& v, const GridInfo& g,
             f(p[u], dsub(p[u].x, xi), dsub(p[u].y, yi), dsub(p[u].z, zi));
     }
     for (; t < r.m; ++t) {
-        const int32_t e[1] = {v.vl[(int64_t)mw.pop() * n + i]};
+        const int32_t e[1] = {v.vl[vl_at(n, i, mw.pop())]};
         Pt p[1];
         gather_list(v, s, e, p);
         f(p[0], dsub(p[0].x, xi), dsub(p[0].y, yi), dsub(p[0].z, zi));
@@ -278,12 +278,12 @@ __device__ __forceinline__ void visit_sources(const View& v, int64_t i, const Re
     for (; t + B <= r.m; t += B) {
         int32_t e[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) e[u] = v.vl[(int64_t)mw.pop() * n + i];
+        for (int u = 0; u < B; ++u) e[u] = v.vl[vl_at(n, i, mw.pop())];
 #pragma unroll
         for (int u = 0; u < B; ++u) f(e[u] & ~MBIT, (e[u] & MBIT) != 0);
     }
     for (; t < r.m; ++t) {
-        const int32_t e = v.vl[(int64_t)mw.pop() * n + i];
+        const int32_t e = v.vl[vl_at(n, i, mw.pop())];
         f(e & ~MBIT, (e & MBIT) != 0);
     }
 }
@@ -350,7 +350,7 @@ __device__ __forceinline__ void visit_stencil_sub(const View& v, const GridInfo&
     for (int t = 0; t < sub && t < r.m; ++t) mw.pop();
     for (int t = sub; t < r.m; t += LPP) {
         const int k = mw.pop();
-        const Pt p = list_point(v, g, v.vl[(int64_t)k * n + i], xi, yi);
+        const Pt p = list_point(v, g, v.vl[vl_at(n, i, k)], xi, yi);
         f(p, dsub(p.x, xi), dsub(p.y, yi), dsub(p.z, zi));
         for (int u = 1; u < LPP && t + u < r.m; ++u) mw.pop();
     }
