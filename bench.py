@@ -86,6 +86,8 @@ def _parse():
     ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--ensemble-adjoint-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-step-only", action="store_true",
+                    help="print only the timing of lp_step_adjoint calls (for counter runs)")
     ap.add_argument("--no-second-order", action="store_true")
     ap.add_argument("--no-layer", action="store_true")
     ap.add_argument("--no-cubic", action="store_true")
@@ -116,6 +118,14 @@ SELECT_SOURCES = ("paper_2206_14061_amd/csrc/lp_stencil.hip",
 SELECT_PROFILE = "profiles/k_select_column_64x64x128.md"
 PASS2_SOURCES = PASS1_SOURCES
 PASS2_PROFILE = "profiles/k_pass2_st_column_64x64x128.md"
+# float64 flop one lp_step_adjoint call executes per particle, counted by
+# SQ_INSTS_VALU_FLOPS_FP64 over every kernel of the call (committed record)
+ADJOINT_SOURCES = ("paper_2206_14061_amd/csrc/lp_adjoint.hip",
+                   "paper_2206_14061_amd/csrc/lp_fitcore.h",
+                   "paper_2206_14061_amd/csrc/lp_visit.h",
+                   "paper_2206_14061_amd/csrc/lp_internal.h",
+                   "paper_2206_14061_amd/build.py")
+ADJOINT_PROFILE = "profiles/adjoint_step_column_32x32x128.md"
 
 
 def sources_digest(paths) -> str:
@@ -670,6 +680,65 @@ def errors_vs_oracle(torch, lp, wl):
     return out
 
 
+def flop_record(profile, sources):
+    """Float64 flop per particle of a committed counter record; None when
+    the sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, profile)
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"^flop-record: (\{.*\})\s*$", open(path).read(), re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != sources_digest(sources):
+        return None
+    return rec["flop_per_particle"]
+
+
+def adjoint_step_bench(torch, lp, lpgen, calls: int = 10):
+    """One lp_step_adjoint call on the 32 x 32 x 128 column (131,072
+    particles) after 10 steps from a seeded flow (0.5 m/s, wavelength 8h),
+    reversing a recorded step with a seeded cotangent: mean time per call
+    from HIP events on the library's stream over `calls` calls, and its
+    float64 rate against the vector peak (flop per particle from the
+    committed counter record)."""
+    wl = lpgen.with_shear_velocity(lpgen.column_adjoint())
+    ctx = lp.make_context(wl)
+    st = lp.DeviceState.from_host(wl.state)
+    for _ in range(10):
+        ctx.lp_step(st, wl.dt)
+    rec = lp.StepRecord(wl.n, force_sort=True)
+    inp = st.clone()
+    ctx.lp_step(st, wl.dt, rec=rec)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(220614061)
+    lam = lp.DeviceState([torch.randn(wl.n, dtype=torch.float64, device="cuda",
+                                      generator=gen) for _ in range(7)])
+    dth = torch.zeros(len(wl.params), 3, dtype=torch.float64, device="cuda")
+    ctx.lp_step_adjoint(inp, wl.dt, lam, dth, rec=rec)
+    ctx.sync_status()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(calls):
+        ctx.lp_step_adjoint(inp, wl.dt, lam, dth, rec=rec)
+    ev1.record()
+    torch.cuda.synchronize()
+    ctx.sync_status()
+    ms = ev0.elapsed_time(ev1) / calls
+    out = {"workload": wl.name, "particles": wl.n, "calls": calls, "ms_per_call": ms}
+    fpp = flop_record(ADJOINT_PROFILE, ADJOINT_SOURCES)
+    if fpp is not None:
+        tf = fpp * wl.n / (ms * 1e-3) / 1e12
+        out["roofline"] = {"kernel": "lp_step_adjoint (every kernel of one call)",
+                           "bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS,
+                           "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS,
+                           "per_particle": fpp, "avg_call_ms": ms}
+    else:
+        out["roofline"] = None
+    return out
+
+
 def adjoint_fd_check(torch, lp, lpgen, grad, steps: int):
     """Central differences of the runout loss of the adjoint benchmark (the
     131,072-particle column, `steps` steps, L = sum softplus((x - 0.3)/h))
@@ -730,6 +799,9 @@ def main():
     import paper_2206_14061_amd as lp
 
     torch.cuda.set_device(0)
+    if args.adjoint_step_only:
+        print(json.dumps({"adjoint_step": adjoint_step_bench(torch, lp, lpgen)}), flush=True)
+        return
     wl = lpgen.column_bench()
 
     def run(steps, warmup, **cfg):
@@ -891,6 +963,7 @@ def main():
         _progress("errors against the oracle done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(torch, lp, lpgen, args.adjoint_steps)
+        out["adjoint"]["adjoint_step"] = adjoint_step_bench(torch, lp, lpgen)
         out["adjoint"]["fd_check"] = adjoint_fd_check(
             torch, lp, lpgen, out["adjoint"]["dL_dtheta"][0], args.adjoint_steps)
         _progress("adjoint and its central differences done")
