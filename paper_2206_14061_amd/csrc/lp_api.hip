@@ -183,14 +183,16 @@ lp_status adjoint_order(lp_ctx* c, double* const in[7], const lp_step_record* re
 // One step with no host synchronisation: device-side rebuild decision,
 // gated re-sort + list rebuild or state copy, stencils, fits, update into
 // the caller's arrays.
-lp_status step_device(lp_ctx* c, double* const in[7], int32_t* ids, double dt, int bits)
+lp_status step_device(lp_ctx* c, double* const in[7], int32_t* ids, double dt, int bits,
+                      bool first)
 {
     const double* cin[7];
     for (int a = 0; a < 7; ++a) cin[a] = in[a];
-    lp_status r = rebuild_decision(c, cin, c->cfg.skin > 0.0 ? 0 : 1);
+    // the decision copies the state into the working state, which a
+    // rebuild overwrites in its new order
+    lp_status r = rebuild_decision(c, cin, c->cfg.skin > 0.0 ? 0 : 1, first);
     if (r == LP_OK) r = cells_build_device(c, in, ids, c->w.gate, bits);
     if (r == LP_OK) r = tile_map_build(c, c->w.gate);
-    if (r == LP_OK) r = state_copy(c, in, nullptr, c->w.gate + 1);
     const double* sorted[7];
     for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
     if (r == LP_OK) r = stencils_build(c, sorted);
@@ -697,7 +699,8 @@ lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,
             c->prof = prof;
             return hip_fail(c, e, "begin capture");
         }
-        for (int k = 0; k < nsteps && r == LP_OK; ++k) r = step_device(c, in, ids, dt, bits);
+        for (int k = 0; k < nsteps && r == LP_OK; ++k)
+            r = step_device(c, in, ids, dt, bits, k == 0);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->cap_stream, &g);
         c->stream = saved;

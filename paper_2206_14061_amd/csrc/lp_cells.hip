@@ -375,18 +375,35 @@ __global__ void k_radix_scatter(const unsigned long long* kin,
     }
 }
 
-__global__ void k_gather7(int64_t n, const int32_t* perm,
-                          const double* i0, const double* i1, const double* i2,
-                          const double* i3, const double* i4, const double* i5,
-                          const double* i6, double* o0, double* o1, double* o2,
-                          double* o3, double* o4, double* o5, double* o6, const int32_t* gate)
+struct State7 {
+    const double* a[7];
+};
+struct Dest7 {
+    double* a[7];
+};
+
+// The state in sorted order (perm[new] = old); for a rebuild (rx not
+// null) the positions again as the reference of the next displacement
+// check, and the caller's particle ids (ids, optional) into ids_tmp.
+__global__ void k_gather7(int64_t n, const int32_t* perm, State7 in, Dest7 out,
+                          double* rx, double* ry, double* rz, const int32_t* ids,
+                          int32_t* ids_tmp, const int32_t* gate)
 {
     LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t j = perm[i];
-    o0[i] = i0[j]; o1[i] = i1[j]; o2[i] = i2[j]; o3[i] = i3[j];
-    o4[i] = i4[j]; o5[i] = i5[j]; o6[i] = i6[j];
+    double v[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) v[a] = in.a[a][j];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) out.a[a][i] = v[a];
+    if (rx) {
+        rx[i] = v[0];
+        ry[i] = v[1];
+        rz[i] = v[2];
+    }
+    if (ids) ids_tmp[i] = ids[j];
 }
 
 __global__ void k_copy_i32(int64_t n, const int32_t* a, int32_t* b, const int32_t* gate)
@@ -403,16 +420,19 @@ __global__ void k_copy_f64(int64_t n, const double* a, double* b, const int32_t*
     if (i < n) b[i] = a[i];
 }
 
-// a[0..count) = v, with count = *count_dev when given (grid-stride)
-__global__ void k_fill_i32(int64_t n, int32_t* a, int32_t v, const int64_t* count_dev,
-                           const int32_t* gate)
+// a[0..count) = b[0..count) = v, with count = *count_dev when given
+// (grid-stride)
+__global__ void k_fill2_i32(int64_t n, int32_t* a, int32_t* b, int32_t v,
+                            const int64_t* count_dev, const int32_t* gate)
 {
     LP_GATE(gate);
     int64_t m = n;
     if (count_dev) m = *count_dev < n ? *count_dev : n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * blockDim.x)
+         i += (int64_t)gridDim.x * blockDim.x) {
         a[i] = v;
+        b[i] = v;
+    }
 }
 
 // Cell start/end from sorted keys; positions give the linear cell index.
@@ -420,11 +440,14 @@ __global__ void k_cell_bounds(int64_t cnt, int n_sys, const int64_t* off,
                               const GridInfo* grid,
                               const unsigned long long* keys,
                               const double* x, const double* y,
-                              const double* z, int32_t* cs, int32_t* ce, const int32_t* gate)
+                              const double* z, int32_t* cs, int32_t* ce,
+                              const int32_t* ids_tmp, int32_t* ids, const int32_t* gate)
 {
     LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt) return;
+    // the ids k_gather7 gathered (every gather has completed)
+    if (ids) ids[i] = ids_tmp[i];
     const unsigned long long k = keys[i];
     const bool first = (i == 0) || keys[i - 1] != k;
     const bool last = (i == cnt - 1) || keys[i + 1] != k;
@@ -477,13 +500,6 @@ __global__ __launch_bounds__(BLOCK) void k_disp(int64_t n, int n_sys, const int6
 }
 
 __global__ void k_disp_init(Summary* sum) { sum->disp = ord_enc(0.0); }
-
-struct State7 {
-    const double* a[7];
-};
-struct Dest7 {
-    double* a[7];
-};
 
 // k_disp fused with the copy of the seven state arrays into the working
 // state (one pass over the state).
@@ -559,14 +575,20 @@ void radix_sort(lp_ctx* c, int64_t cnt, int bits, unsigned long long*& kr,
 // Rebuild decision of a captured step: gate[0] = rebuild, gate[1] = keep
 // the list (copy the state); rebuild when some particle has moved skin R /
 // 2 since the last build (or always when `force`).
-__global__ void k_decide(const Summary* sum, int32_t* gate, Counters* cnt, int force)
+__global__ void k_decide(Summary* sum, int32_t* gate, Counters* cnt, int force,
+                         unsigned long long* bbox, int n_sys)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double r = ord_dec(sum->disp);
     const bool rebuild = force || !(sqrt(r) < 0.49);
     gate[0] = rebuild ? 1 : 0;
     gate[1] = rebuild ? 0 : 1;
-    if (rebuild) atomicAdd(&cnt->rebuilds, 1ull);
+    // the next step's displacement check starts from zero
+    sum->disp = ord_enc(0.0);
+    if (!rebuild) return;
+    atomicAdd(&cnt->rebuilds, 1ull);
+    // empty bounding boxes for the rebuild's k_bbox (as k_bbox_init)
+    for (int q = 0; q < 6 * n_sys; ++q) bbox[q] = (q % 6) < 3 ? ~0ull : 0ull;
 }
 
 __global__ void k_gather_i32(int64_t n, const int32_t* perm, const int32_t* a,
@@ -593,8 +615,11 @@ lp_status rebuild(lp_ctx* c, double* const st[7], int32_t* perm_out, int32_t* id
         c->stencils_ok = false;
         c->list_ok = false;
     }
-    hipLaunchKernelGGL(k_bbox_init, dim3(blocks_for(6 * ns)), dim3(BLOCK), 0,
-                       s, w.bbox, ns, gate);
+    // (a captured step's k_decide empties the boxes when it decides to
+    // rebuild)
+    if (!dev)
+        hipLaunchKernelGGL(k_bbox_init, dim3(blocks_for(6 * ns)), dim3(BLOCK), 0,
+                           s, w.bbox, ns, gate);
     if (n > 0)
         hipLaunchKernelGGL(k_bbox, dim3(blocks_for((n + BBOX_CHUNK - 1) / BBOX_CHUNK)),
                            dim3(BLOCK), 0, s, n, ns, w.off, st[0], st[1], st[2],
@@ -633,34 +658,29 @@ lp_status rebuild(lp_ctx* c, double* const st[7], int32_t* perm_out, int32_t* id
                            w.off, w.grid, st[0], st[1], st[2], shift_sys, w.keys0,
                            w.vals0, w.err, gate);
         radix_sort(c, n, bits, kr, vr, gate);
-        hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n,
-                           vr, st[0], st[1], st[2], st[3], st[4], st[5], st[6],
-                           w.sst[0], w.sst[1], w.sst[2], w.sst[3], w.sst[4],
-                           w.sst[5], w.sst[6], gate);
+        State7 s7;
+        Dest7 d7;
+        for (int a = 0; a < 7; ++a) {
+            s7.a[a] = st[a];
+            d7.a[a] = w.sst[a];
+        }
+        hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, vr, s7,
+                           d7, w.xref[0], w.xref[1], w.xref[2], ids, w.ids_tmp, gate);
         if (perm_out)
             hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
                                n, vr, perm_out, gate);
-        if (ids) {
-            hipLaunchKernelGGL(k_gather_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
-                               n, vr, ids, w.ids_tmp, gate);
-            hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
-                               n, w.ids_tmp, ids, gate);
-        }
-        for (int a = 0; a < 3; ++a)
-            hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
-                               n, w.sst[a], w.xref[a], gate);
     }
     // cell tables: the whole used range (read on the device in captured
     // steps)
     const int64_t tc = dev ? w.cells_max : c->total_cells;
     const int64_t* tdev = dev ? &w.summary->total_cells : nullptr;
     const unsigned fb = std::min(blocks_for(tc), 8192u);
-    hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(BLOCK), 0, s, tc, w.cs, 0, tdev, gate);
-    hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(BLOCK), 0, s, tc, w.ce, 0, tdev, gate);
+    hipLaunchKernelGGL(k_fill2_i32, dim3(fb), dim3(BLOCK), 0, s, tc, w.cs, w.ce, 0, tdev,
+                       gate);
     if (n > 0)
         hipLaunchKernelGGL(k_cell_bounds, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
                            n, ns, w.off, w.grid, kr, w.sst[0], w.sst[1], w.sst[2],
-                           w.cs, w.ce, gate);
+                           w.cs, w.ce, w.ids_tmp, ids, gate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "cell build launch");
     if (!dev) c->cells_ok = true;
@@ -715,25 +735,42 @@ lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm
     Work& w = c->w;
     const int64_t n = c->n;
     if (n > 0)
+    {
+        State7 s7;
+        Dest7 d7;
+        for (int a = 0; a < 7; ++a) {
+            s7.a[a] = st[a];
+            d7.a[a] = w.sst[a];
+        }
         hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
-                           perm, st[0], st[1], st[2], st[3], st[4], st[5], st[6],
-                           w.sst[0], w.sst[1], w.sst[2], w.sst[3], w.sst[4],
-                           w.sst[5], w.sst[6], nullptr);
+                           perm, s7, d7, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr);
+    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "state gather");
 }
 
-lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force)
+lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool first)
 {
     Work& w = c->w;
     const int64_t n = c->n;
-    hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
-    if (n > 0)
-        hipLaunchKernelGGL(k_disp, dim3(std::min(blocks_for(n), 1024u)), dim3(BLOCK), 0,
-                           c->stream, n, c->n_sys, w.off, w.grid, st[0], st[1], st[2],
-                           w.xref[0], w.xref[1], w.xref[2], w.summary);
+    // k_decide leaves the maximum at zero for the next captured step
+    if (first) hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
+    if (n > 0) {
+        // the state copied into the working state (in the current order)
+        // with the displacement check; a rebuild then overwrites it
+        State7 s7;
+        Dest7 d7;
+        for (int a = 0; a < 7; ++a) {
+            s7.a[a] = st[a];
+            d7.a[a] = w.sst[a];
+        }
+        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), 512u)), dim3(BLOCK), 0,
+                           c->stream, n, c->n_sys, w.off, w.grid, s7, d7, w.xref[0],
+                           w.xref[1], w.xref[2], w.summary);
+    }
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(1), 0, c->stream, w.summary, w.gate,
-                       w.cnt, force);
+                       w.cnt, force, w.bbox, c->n_sys);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "rebuild decision");
 }

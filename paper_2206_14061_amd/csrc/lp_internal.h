@@ -463,7 +463,7 @@ lp_status permute_ids(lp_ctx* c, const int32_t* perm, int32_t* ids);
 // working copy of st in the order perm (sst[new] = st[perm[new]])
 lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm);
 // Device-side rebuild decision into w.gate (no synchronisation).
-lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force);
+lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool first);
 // Copies the working copy back into the caller's arrays.
 lp_status state_write_back(lp_ctx* c, double* const out[7]);
 // Largest displacement since the list build in units of the skin
