@@ -386,8 +386,8 @@ struct Dest7 {
 // null) the positions again as the reference of the next displacement
 // check, and the caller's particle ids (ids, optional) into ids_tmp.
 __global__ void k_gather7(int64_t n, const int32_t* perm, State7 in, Dest7 out,
-                          double* rx, double* ry, double* rz, const int32_t* ids,
-                          int32_t* ids_tmp, const int32_t* gate)
+                          double* rx, double* ry, double* rz, double* p4,
+                          const int32_t* ids, int32_t* ids_tmp, const int32_t* gate)
 {
     LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -402,6 +402,10 @@ __global__ void k_gather7(int64_t n, const int32_t* perm, State7 in, Dest7 out,
         rx[i] = v[0];
         ry[i] = v[1];
         rz[i] = v[2];
+        // the positions' records, which the list build reads
+        double2* r = reinterpret_cast<double2*>(p4 + 4 * i);
+        r[0] = make_double2(v[0], v[1]);
+        r[1] = make_double2(v[2], 0.0);
     }
     if (ids) ids_tmp[i] = ids[j];
 }
@@ -665,7 +669,8 @@ lp_status rebuild(lp_ctx* c, double* const st[7], int32_t* perm_out, int32_t* id
             d7.a[a] = w.sst[a];
         }
         hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, vr, s7,
-                           d7, w.xref[0], w.xref[1], w.xref[2], ids, w.ids_tmp, gate);
+                           d7, w.xref[0], w.xref[1], w.xref[2], w.p4, ids, w.ids_tmp,
+                           gate);
         if (perm_out)
             hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n)), dim3(BLOCK), 0, s,
                                n, vr, perm_out, gate);
@@ -744,7 +749,7 @@ lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm
         }
         hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
                            perm, s7, d7, nullptr, nullptr, nullptr, nullptr, nullptr,
-                           nullptr);
+                           nullptr, nullptr);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "state gather");

@@ -62,10 +62,16 @@ __device__ __forceinline__ void cell_clamp(const GridInfo& g, double x, double y
 
 // ---- neighbour-list build ---------------------------------------------
 
+// Candidates of the list build whose positions are loaded together.
+constexpr int LIST_BATCH = 8;
+
+// The candidates' positions come from their 32-byte records (x, y, z, 0),
+// which the rebuild's gather writes: two loads per candidate.
 __global__ __launch_bounds__(BLOCK) void k_list_build(
     int64_t n, int n_sys, const int64_t* __restrict__ off,
     const GridInfo* __restrict__ grid, const double* __restrict__ x,
     const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ p4,
     const int32_t* __restrict__ cs, const int32_t* __restrict__ ce,
     int32_t* __restrict__ vl, int32_t* __restrict__ vcnt, ErrWord* err,
     const int32_t* gate)
@@ -95,35 +101,48 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
                 const int yy = nb_cell(cy, dy0, g.ny, py);
                 if (yy < 0) continue;
                 const int64_t row = g.cell_base + (int64_t)g.nx * (yy + (int64_t)g.ny * zz);
-                for (int dx0 = -1; dx0 <= 1; ++dx0) {
-                    const int xx = nb_cell(cx, dx0, g.nx, px);
-                    if (xx < 0) continue;
-                    const int64_t c = row + xx;
+                // the particle ranges of the row's three cells, loaded
+                // together (a clipped or repeated cell is empty)
+                int32_t b[3], len[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int xx = nb_cell(cx, q - 1, g.nx, px);
+                    const int64_t c = row + (xx < 0 ? 0 : xx);
                     const int32_t cb = cs[c], cend = ce[c];
-                    // four candidates' positions loaded together, then
-                    // tested in order
-                    for (int32_t j0 = cb; j0 < cend; j0 += 4) {
-                        double px[4], py[4], pz[4];
+                    b[q] = cb;
+                    len[q] = xx < 0 ? 0 : cend - cb;
+                }
+                const int l01 = len[0] + len[1];
+                const int tot = l01 + len[2];
+                // the row's candidates in cell order, LIST_BATCH at a time:
+                // their positions loaded together, then tested in order
+                for (int t0 = 0; t0 < tot; t0 += LIST_BATCH) {
+                    int32_t jb[LIST_BATCH];
+                    double qxs[LIST_BATCH], qys[LIST_BATCH], qzs[LIST_BATCH];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int32_t j = j0 + u < cend ? j0 + u : j0;
-                            px[u] = x[j];
-                            py[u] = y[j];
-                            pz[u] = z[j];
-                        }
+                    for (int u = 0; u < LIST_BATCH; ++u) {
+                        const int t = t0 + u < tot ? t0 + u : t0;
+                        const int32_t j = t < len[0] ? b[0] + t
+                                          : (t < l01 ? b[1] + (t - len[0]) : b[2] + (t - l01));
+                        jb[u] = j;
+                        const double* r = p4 + 4 * (int64_t)j;
+                        const double2 xy = *reinterpret_cast<const double2*>(r);
+                        qxs[u] = xy.x;
+                        qys[u] = xy.y;
+                        qzs[u] = r[2];
+                    }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int32_t j = j0 + u;
-                            if (j >= cend || (!mirror && j == (int32_t)i)) continue;
-                            const double dx = image_coord(px[u], qx, g.Lx, g.hLx) - qx;
-                            const double dy = image_coord(py[u], qy, g.Ly, g.hLy) - qy;
-                            const double dz = pz[u] - qz;
-                            if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
-                            if (mirror && !(pz[u] - g.wall < g.Rv)) continue;
-                            if (cnt < VCAP)
-                                vl[vl_at(n, i, cnt)] = mirror ? (j | MBIT) : j;
-                            ++cnt;
-                        }
+                    for (int u = 0; u < LIST_BATCH; ++u) {
+                        const int32_t j = jb[u];
+                        if (t0 + u >= tot || (!mirror && j == (int32_t)i)) continue;
+                        const double dx = image_coord(qxs[u], qx, g.Lx, g.hLx) - qx;
+                        const double dy = image_coord(qys[u], qy, g.Ly, g.hLy) - qy;
+                        const double dz = qzs[u] - qz;
+                        if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
+                        if (mirror && !(qzs[u] - g.wall < g.Rv)) continue;
+                        if (cnt < VCAP)
+                            vl[vl_at(n, i, cnt)] = mirror ? (j | MBIT) : j;
+                        ++cnt;
                     }
                 }
             }
@@ -1000,7 +1019,7 @@ lp_status list_build(lp_ctx* c, const int32_t* gate)
     if (n > 0)
         hipLaunchKernelGGL(k_list_build, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
-                           w.sst[2], w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
+                           w.sst[2], w.p4, w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "list build launch");
     c->list_ok = true;
