@@ -68,6 +68,14 @@ struct AdjBufs {
 // LDS accumulators of a tile's staged sources: six per source slot
 constexpr int NRECV = 6;
 
+// Lanes per particle in the two reverse kernels: their LDS (staged
+// sources and accumulators) fills a CU, so a block of BLOCK particles on
+// two lanes each puts two waves on every SIMD instead of one.
+#ifndef LP_ADJ_LPP
+#define LP_ADJ_LPP 2
+#endif
+constexpr int ADJ_LPP = LP_ADJ_LPP;
+
 __device__ __forceinline__ void lds_add(double* p, double v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -89,20 +97,22 @@ __device__ __forceinline__ void deliver(const AdjBufs& B, int64_t n, double* acc
     }
 }
 
-// Zeroes the accumulators of the tile's ns staged slots.
+// Zeroes the accumulators of the tile's ns staged slots (NT threads).
+template <int NT>
 __device__ __forceinline__ void acc_zero(double* acc, int ns)
 {
-    for (int q = threadIdx.x; q < ns; q += BLOCK)
+    for (int q = threadIdx.x; q < ns; q += NT)
 #pragma unroll
         for (int f = 0; f < NRECV; ++f) acc[f * STAGE_CAP + q] = 0.0;
 }
 
 // Adds every staged slot's accumulators into its particle's global
-// accumulators (after the block's rows are done).
+// accumulators (after the block's rows are done; NT threads).
+template <int NT>
 __device__ __forceinline__ void acc_flush(const AdjBufs& B, int64_t n, const double* acc,
                                           const int32_t* tsrc, int ns)
 {
-    for (int q = threadIdx.x; q < ns; q += BLOCK) {
+    for (int q = threadIdx.x; q < ns; q += NT) {
         const int64_t j = tsrc[q];
 #pragma unroll
         for (int f = 0; f < NRECV; ++f) {
@@ -184,24 +194,26 @@ __global__ void k_adj_init(int64_t n, AdjSeed S, AdjBufs B)
 // pressure, as the forward pass-2 fit reads them) when the tile is
 // staged, else from global memory.  body(a, w, p, Pj, Ej, src): src is the
 // real particle behind the point (a mirror's source).
-template <class F>
+// With LPP lanes per particle, lane sub visits its share of the rows.
+template <int LPP, class F>
 __device__ __forceinline__ void adj_rows2(const View& v, const GridInfo& g,
                                           const lp_params& prm, const AdjBufs& B,
-                                          int64_t i, const Rec& r, bool staged,
+                                          int64_t i, const Rec& r, int sub, bool staged,
                                           const int32_t* tsrc, const double* sx,
                                           const double* sy, const double* sz,
                                           const double* sP, const double* sE,
                                           const double* sM, F&& body)
 {
     if (staged) {
-        for_rows_staged<FIT_BATCH, true>(v, g, i, r, sx, sy, sz,
-                                         [&](const double* a, double w, const Pt* p) {
+        for_rows_staged_sub<FIT_BATCH, LPP, true>(v, g, i, r, sub, sx, sy, sz,
+                                                  [&](const double* a, double w,
+                                                      const Pt* p) {
             if (!p) body(a, w, p, 0.0, 0.0, -1);
             else if (p->mirror) body(a, w, p, sM[p->src], 0.0, tsrc[p->src]);
             else body(a, w, p, sP[p->src], sE[p->src], tsrc[p->src]);
         });
     } else {
-        for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+        for_rows_sub<LPP>(v, g, i, r, sub, [&](const double* a, double w, const Pt* p) {
             double Pj, Ej;
             pass2_values(v, B.P, B.eta, p, prm, Pj, Ej);
             body(a, w, p, Pj, Ej, p ? p->src : -1);
@@ -210,13 +222,17 @@ __device__ __forceinline__ void adj_rows2(const View& v, const GridInfo& g,
 }
 
 // Reverse of the update, the RHS and the fit of P and eta at real particle
-// i of the block's tile (ns staged sources, -1: not staged).
+// i of the block's tile (ns staged sources, -1: not staged), on LPP
+// adjacent lanes: each sums its share of the rows (lane sub), the sums are
+// added across the lanes, every lane then solves the same small systems,
+// and lane 0 writes the particle's own results.
+template <int LPP>
 __device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
                                               const AdjBufs& B, int64_t tile, int64_t i,
-                                              int ns, const double* sx, const double* sy,
-                                              const double* sz, const double* sP,
-                                              const double* sE, const double* sM,
-                                              double* acc)
+                                              int sub, int ns, const double* sx,
+                                              const double* sy, const double* sz,
+                                              const double* sP, const double* sE,
+                                              const double* sM, double* acc)
 {
     const int64_t n = v.n;
     const int s = sys_of(v.off, v.n_sys, i);
@@ -233,8 +249,9 @@ __device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
     for (int q = 0; q < 31; ++q) M[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) y0[q] = y1[q] = 0.0;
-    adj_rows2(v, g, prm, B, i, r, staged, tsrc, sx, sy, sz, sP, sE, sM,
-              [&](const double* a, double w, const Pt*, double Pj, double Ej, int32_t) {
+    adj_rows2<LPP>(v, g, prm, B, i, r, sub, staged, tsrc, sx, sy, sz, sP, sE, sM,
+                   [&](const double* a, double w, const Pt*, double Pj, double Ej,
+                       int32_t) {
         moments_add(M, a, w);
         const double bP = w * (Pj - Pi), bE = w * (Ej - Ei);
 #pragma unroll
@@ -243,12 +260,24 @@ __device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
             y1[q] += a[q] * bE;
         }
     });
+    if (LPP > 1) {
+#pragma unroll
+        for (int q = 0; q < 31; ++q) M[q] = lane_sum<LPP>(M[q]);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            y0[q] = lane_sum<LPP>(y0[q]);
+            y1[q] = lane_sum<LPP>(y1[q]);
+        }
+    }
+    const bool lead = sub == 0;
     double U[45];
     gram_from_moments(M, U);
     const double ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
     if (!(ratio > 0.0)) {
-        raise_error(B.err, ERR_NUMERIC, i);
-        for (int q = 0; q < 11; ++q) B.stash[(int64_t)q * n + i] = 0.0;
+        if (lead) {
+            raise_error(B.err, ERR_NUMERIC, i);
+            for (int q = 0; q < 11; ++q) B.stash[(int64_t)q * n + i] = 0.0;
+        }
         return;
     }
     double cP[9], cE[9];
@@ -289,7 +318,7 @@ __device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
     const double T1 = -gP[1] + gd[3] * gE[0] + gd[1] * gE[1] + gd[5] * gE[2] + Ei * vis[1];
     const double T2 = -gP[2] + gd[4] * gE[0] + gd[5] * gE[1] + gd[2] * gE[2] + Ei * vis[2];
     const double inv_rho = 1.0 / prm.rho_s;
-    B.a[6][i] += (abar[0] * T0 + abar[1] * T1 + abar[2] * T2) * inv_rho + dVbar * div;
+    if (lead) B.a[6][i] += (abar[0] * T0 + abar[1] * T1 + abar[2] * T2) * inv_rho + dVbar * div;
     const double Tb[3] = {abar[0] * V * inv_rho, abar[1] * V * inv_rho,
                           abar[2] * V * inv_rho};
     double gPb[3], gEb[3];
@@ -299,17 +328,19 @@ __device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
     gEb[0] = Tb[0] * gd[0] + Tb[1] * gd[3] + Tb[2] * gd[4];
     gEb[1] = Tb[0] * gd[3] + Tb[1] * gd[1] + Tb[2] * gd[5];
     gEb[2] = Tb[0] * gd[4] + Tb[1] * gd[5] + Tb[2] * gd[2];
-    double* st = B.stash;
-    st[(int64_t)0 * n + i] = Tb[0] * gE[0];
-    st[(int64_t)1 * n + i] = Tb[1] * gE[1];
-    st[(int64_t)2 * n + i] = Tb[2] * gE[2];
-    st[(int64_t)3 * n + i] = Tb[0] * gE[1] + Tb[1] * gE[0];
-    st[(int64_t)4 * n + i] = Tb[0] * gE[2] + Tb[2] * gE[0];
-    st[(int64_t)5 * n + i] = Tb[1] * gE[2] + Tb[2] * gE[1];
-    st[(int64_t)6 * n + i] = dVbar * V;
+    if (lead) {
+        double* st = B.stash;
+        st[(int64_t)0 * n + i] = Tb[0] * gE[0];
+        st[(int64_t)1 * n + i] = Tb[1] * gE[1];
+        st[(int64_t)2 * n + i] = Tb[2] * gE[2];
+        st[(int64_t)3 * n + i] = Tb[0] * gE[1] + Tb[1] * gE[0];
+        st[(int64_t)4 * n + i] = Tb[0] * gE[2] + Tb[2] * gE[0];
+        st[(int64_t)5 * n + i] = Tb[1] * gE[2] + Tb[2] * gE[1];
+        st[(int64_t)6 * n + i] = dVbar * V;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) st[(int64_t)(7 + a) * n + i] = Ei * Tb[a];
-    st[(int64_t)10 * n + i] = Tb[0] * vis[0] + Tb[1] * vis[1] + Tb[2] * vis[2];
+        for (int a = 0; a < 3; ++a) st[(int64_t)(7 + a) * n + i] = Ei * Tb[a];
+        st[(int64_t)10 * n + i] = Tb[0] * vis[0] + Tb[1] * vis[1] + Tb[2] * vis[2];
+    }
     // ---- reverse of the fit of P and eta
     double yP[9], yE[9];
 #pragma unroll
@@ -325,9 +356,9 @@ __device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
         chol_solve<9>(U, yE);
     }
     double aPs = 0.0, aEs = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-    adj_rows2(v, g, prm, B, i, r, staged, tsrc, sx, sy, sz, sP, sE, sM,
-              [&](const double* a, double, const Pt* p, double Pj, double Ej,
-                  int32_t src) {
+    adj_rows2<LPP>(v, g, prm, B, i, r, sub, staged, tsrc, sx, sy, sz, sP, sE, sM,
+                   [&](const double* a, double, const Pt* p, double Pj, double Ej,
+                       int32_t src) {
         double rP = Pj - Pi, rE = Ej - Ei, bP = 0.0, bE = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -364,50 +395,66 @@ __device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
         }
     });
     // this particle's own terms (other particles' rows arrive in B.recv)
-    B.aP[i] += aPs;
-    B.aE[i] += aEs;
-    B.a[0][i] += ax;
-    B.a[1][i] += ay;
-    B.a[2][i] += az;
+    if (LPP > 1) {
+        aPs = lane_sum<LPP>(aPs);
+        aEs = lane_sum<LPP>(aEs);
+        ax = lane_sum<LPP>(ax);
+        ay = lane_sum<LPP>(ay);
+        az = lane_sum<LPP>(az);
+    }
+    if (lead) {
+        B.aP[i] += aPs;
+        B.aE[i] += aEs;
+        B.a[0][i] += ax;
+        B.a[1][i] += ay;
+        B.a[2][i] += az;
+    }
 }
 
 // One block per tile: the tile's sources staged in LDS with their
-// accumulators (all the LDS of a CU), the reverse pass of each particle,
-// then the accumulators added into the global receive buffers.
-__global__ __launch_bounds__(BLOCK, 1) void k_adj_pass2(View v, AdjSeed S, AdjBufs B,
-                                                        int map_ok)
+// accumulators (all the LDS of a CU), the reverse pass of each particle
+// (LPP lanes each), then the accumulators added into the global receive
+// buffers.
+template <int LPP>
+__global__ __launch_bounds__(BLOCK * LPP, 1) void k_adj_pass2(View v, AdjSeed S, AdjBufs B,
+                                                              int map_ok)
 {
+    constexpr int NT = BLOCK * LPP;
     __shared__ double sx[STAGE_CAP], sy[STAGE_CAP], sz[STAGE_CAP];
     __shared__ double sP[STAGE_CAP], sE[STAGE_CAP], sM[STAGE_CAP];
     __shared__ double acc[NRECV * STAGE_CAP];
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t i = tile * BLOCK + threadIdx.x;
+    const int64_t i = tile * BLOCK + threadIdx.x / LPP;
+    const int sub = threadIdx.x % LPP;
     const int tc = map_ok ? v.tile_cnt[tile] : -1;
     const int ns = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
     if (ns >= 0) {
-        stage_pass2(v, B.P, B.eta, tile, ns, sx, sy, sz, sP, sE, sM);
-        acc_zero(acc, ns);
+        stage_pass2<NT>(v, B.P, B.eta, tile, ns, sx, sy, sz, sP, sE, sM);
+        acc_zero<NT>(acc, ns);
         __syncthreads();
     }
-    if (i < v.n) adj2_particle(v, S, B, tile, i, ns, sx, sy, sz, sP, sE, sM, acc);
+    if (i < v.n) adj2_particle<LPP>(v, S, B, tile, i, sub, ns, sx, sy, sz, sP, sE, sM, acc);
     if (ns >= 0) {
         __syncthreads();
-        acc_flush(B, v.n, acc, v.tile_src + tile * STAGE_CAP, ns);
+        acc_flush<NT>(B, v.n, acc, v.tile_src + tile * STAGE_CAP, ns);
     }
 }
 
 // ---- reverse of the closure and of the fit of u, v, w ----------------------
 
-__global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int map_ok)
+// LPP lanes per particle, as in k_adj_pass2.
+template <int LPP>
+__global__ __launch_bounds__(BLOCK * LPP, 1) void k_adj_pass1(View v, AdjBufs B, int map_ok)
 {
+    constexpr int NT = BLOCK * LPP;
     // the tile's staged sources (positions and velocities, as the forward
     // pass-1 fit reads them) and their accumulators (all the LDS of a CU);
     // the block reduction of the parameter cotangents reuses the staging
     // space once every row has been read
     __shared__ double lds[6 * STAGE_CAP];
     __shared__ double acc[NRECV * STAGE_CAP];
-    __shared__ int sys_t[BLOCK];
-    static_assert(3 * BLOCK <= 6 * STAGE_CAP, "reduction fits the staging space");
+    __shared__ int sys_t[NT];
+    static_assert(3 * NT <= 6 * STAGE_CAP, "reduction fits the staging space");
     double* sx = lds;
     double* sy = lds + STAGE_CAP;
     double* sz = lds + 2 * STAGE_CAP;
@@ -416,12 +463,14 @@ __global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int m
     double* sw = lds + 5 * STAGE_CAP;
     const int t = threadIdx.x;
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t i = tile * BLOCK + t;
+    const int64_t i = tile * BLOCK + t / LPP;
+    const int sub = t % LPP;
+    const bool lead = sub == 0;
     const int tc = map_ok ? v.tile_cnt[tile] : -1;
     const int ns = tc <= STAGE_CAP ? tc : -1;   // -1: not staged
     if (ns >= 0) {
-        stage_pass1(v, tile, ns, sx, sy, sz, su, sv, sw);
-        acc_zero(acc, ns);
+        stage_pass1<NT>(v, tile, ns, sx, sy, sz, su, sv, sw);
+        acc_zero<NT>(acc, ns);
         __syncthreads();
     }
     double th[3] = {0.0, 0.0, 0.0};
@@ -434,11 +483,12 @@ __global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int m
         const Rec r = load_rec(v, i);
         const bool staged = ns >= 0 && !(r.mode & MODE_SORTED);
         // rows with the velocities of their points (ghosts: u_i)
+        // (this lane's share of them)
         auto rows = [&](auto&& body) {
             if (staged) {
-                for_rows_staged<FIT_BATCH, true>(v, g, i, r, sx, sy, sz,
-                                                 [&](const double* a, double w,
-                                                     const Pt* p) {
+                for_rows_staged_sub<FIT_BATCH, LPP, true>(v, g, i, r, sub, sx, sy, sz,
+                                                          [&](const double* a, double w,
+                                                              const Pt* p) {
                     if (!p) {
                         body(a, w, p, 0.0, 0.0, 0.0);
                         return;
@@ -447,7 +497,8 @@ __global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int m
                     body(a, w, p, su[q], sv[q], p->mirror ? -sw[q] : sw[q]);
                 });
             } else {
-                for_rows(v, g, i, r, [&](const double* a, double w, const Pt* p) {
+                for_rows_sub<LPP>(v, g, i, r, sub, [&](const double* a, double w,
+                                                       const Pt* p) {
                     double uj = 0.0, vj = 0.0, wj = 0.0;
                     if (p) point_velocity(v, *p, uj, vj, wj);
                     body(a, w, p, uj, vj, wj);
@@ -485,13 +536,14 @@ __global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int m
             const double den = prm.I0 + I;
             const double Ib = mub * (prm.mu_2 - prm.mu_s) * prm.I0 / (den * den);
             phib = kb * 2.0 * a * prm.d / (wd * wd) - Ib / a;
-            th[0] = mub * prm.I0 / den;
-            th[1] = mub * I / den;
-            th[2] = -mub * (prm.mu_2 - prm.mu_s) * I / (den * den);
+            // (lane 0's share: every lane computes the closure)
+            th[0] = lead ? mub * prm.I0 / den : 0.0;
+            th[1] = lead ? mub * I / den : 0.0;
+            th[2] = lead ? -mub * (prm.mu_2 - prm.mu_s) * I / (den * den) : 0.0;
         } else if (cl.branch == 2) {
             phib = Pb * prm.rho_s * prm.beta;
         }
-        B.a[6][i] += -phib / (V * V);
+        if (lead) B.a[6][i] += -phib / (V * V);
         if (cl.gn > 0.0) {
             const double q = gnb / cl.gn;
             gdb[0] += 0.5 * q * cl.gd[0];
@@ -541,11 +593,15 @@ __global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int m
         rows([&](const double* a, double w, const Pt*, double, double, double) {
             moments_add(M, a, w);
         });
+        if (LPP > 1) {
+#pragma unroll
+            for (int q = 0; q < 31; ++q) M[q] = lane_sum<LPP>(M[q]);
+        }
         double U[45];
         gram_from_moments(M, U);
         const double ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
         if (!(ratio > 0.0)) {
-            raise_error(B.err, ERR_NUMERIC, i);
+            if (lead) raise_error(B.err, ERR_NUMERIC, i);
         } else {
             double y[3][9], cu[3][9];
 #pragma unroll
@@ -603,22 +659,31 @@ __global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int m
             });
             // this particle's own terms (other particles' rows arrive in
             // B.recv)
-            B.a[3][i] += au[0];
-            B.a[4][i] += au[1];
-            B.a[5][i] += au[2];
-            B.a[0][i] += ax;
-            B.a[1][i] += ay;
-            B.a[2][i] += az;
+            if (LPP > 1) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) au[f] = lane_sum<LPP>(au[f]);
+                ax = lane_sum<LPP>(ax);
+                ay = lane_sum<LPP>(ay);
+                az = lane_sum<LPP>(az);
+            }
+            if (lead) {
+                B.a[3][i] += au[0];
+                B.a[4][i] += au[1];
+                B.a[5][i] += au[2];
+                B.a[0][i] += ax;
+                B.a[1][i] += ay;
+                B.a[2][i] += az;
+            }
         }
     }
     if (ns >= 0) {
         __syncthreads();
-        acc_flush(B, v.n, acc, v.tile_src + tile * STAGE_CAP, ns);
+        acc_flush<NT>(B, v.n, acc, v.tile_src + tile * STAGE_CAP, ns);
     }
     // parameter cotangents: one atomic per block when the block lies in
     // one system, else one per thread (the staged rows are dead once every
     // thread has passed the first barrier)
-    double (*red)[BLOCK] = reinterpret_cast<double (*)[BLOCK]>(lds);
+    double (*red)[NT] = reinterpret_cast<double (*)[NT]>(lds);
     sys_t[t] = s;
     __syncthreads();
     const int s0 = sys_t[0];
@@ -628,7 +693,7 @@ __global__ __launch_bounds__(BLOCK, 1) void k_adj_pass1(View v, AdjBufs B, int m
         red[1][t] = th[1];
         red[2][t] = th[2];
         __syncthreads();
-        for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        for (int w = NT / 2; w > 0; w >>= 1) {
             if (t < w) {
                 red[0][t] += red[0][t + w];
                 red[1][t] += red[1][t + w];
@@ -685,11 +750,13 @@ lp_status step_adjoint(lp_ctx* c, const double* const st[7], const AdjSeed& seed
     hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, seed, B);
     hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(NRECV * n)), dim3(BLOCK), 0, s,
                        NRECV * n, w.adj_recv);
-    hipLaunchKernelGGL(k_adj_pass2, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, seed, B, mo);
+    hipLaunchKernelGGL(k_adj_pass2<ADJ_LPP>, dim3(blocks_for(n)), dim3(BLOCK * ADJ_LPP), 0, s,
+                       v, seed, B, mo);
     hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B, 2);
     hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(NRECV * n)), dim3(BLOCK), 0, s,
                        NRECV * n, w.adj_recv);
-    hipLaunchKernelGGL(k_adj_pass1, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v, B, mo);
+    hipLaunchKernelGGL(k_adj_pass1<ADJ_LPP>, dim3(blocks_for(n)), dim3(BLOCK * ADJ_LPP), 0, s,
+                       v, B, mo);
     hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B, 1);
     hipLaunchKernelGGL(k_adj_unpermute, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, perm, B,
                        dout);

@@ -293,6 +293,35 @@ __device__ __forceinline__ int for_rows_staged(const View& v, const GridInfo& g,
     return m;
 }
 
+// for_rows_staged with the rows spread over LPP adjacent lanes: lane sub
+// takes the kept rows sub, sub + LPP, ... (visit_staged_sub) and the ghost
+// rows o with o mod LPP = sub; returns this lane's rows.
+template <int B, int LPP, bool UNIT, class F>
+__device__ __forceinline__ int for_rows_staged_sub(const View& v, const GridInfo& g,
+                                                   int64_t i, const Rec& r, int sub,
+                                                   const double* sx, const double* sy,
+                                                   const double* sz, F&& f)
+{
+    int m = 0;
+    const Seen s = seen_from(v, g, i);
+    visit_staged_sub<B, LPP>(v, s, i, r, sub, sx, sy, sz,
+                             [&](const Pt& p, double dx, double dy, double dz) {
+        double a[9];
+        const double w = point_row(v, g, dx, dy, dz, a);
+        f(a, UNIT ? 1.0 : w, &p);
+        ++m;
+    });
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+        if (((r.gm >> o) & 1) && (o % LPP) == sub) {
+            double a[9];
+            const double w = ghost_row(v, g, o, a);
+            f(a, UNIT ? 1.0 : w, (const Pt*)nullptr);
+            ++m;
+        }
+    return m;
+}
+
 // for_rows with the rows spread over LPP lanes (stencil rows as in
 // visit_stencil_sub, ghost o to lane o mod LPP; B: rows loaded together
 // with one lane per particle); returns this lane's rows.
@@ -428,20 +457,23 @@ __device__ __forceinline__ void pass2_values(const View& v, const double* P,
 
 // ---- staging of a tile's list sources in LDS (fits and their adjoints) --
 
-// Staged sources per thread of a block, and this thread's source ids in
-// the tile (slot threadIdx.x + u BLOCK; -1 past the tile's S sources).
-constexpr int STAGE_PER = (STAGE_CAP + BLOCK - 1) / BLOCK;
+// Staged sources per thread of a block of NT threads, and this thread's
+// source ids in the tile (slot threadIdx.x + u NT; -1 past the tile's S
+// sources).
+template <int NT = BLOCK>
+constexpr int stage_per() { return (STAGE_CAP + NT - 1) / NT; }
 // six staged FP64 fields per source; two blocks must fit one CU's 160 KB
 static_assert(2 * 6 * STAGE_CAP * (int)sizeof(double) <= 160 * 1024,
               "two staged fit blocks per CU");
 
+template <int NT = BLOCK>
 __device__ __forceinline__ void stage_ids(const View& v, int64_t tile, int S,
-                                          int32_t (&js)[STAGE_PER])
+                                          int32_t (&js)[stage_per<NT>()])
 {
     const int32_t* src = v.tile_src + tile * STAGE_CAP;
 #pragma unroll
-    for (int u = 0; u < STAGE_PER; ++u) {
-        const int q = (int)threadIdx.x + u * BLOCK;
+    for (int u = 0; u < stage_per<NT>(); ++u) {
+        const int q = (int)threadIdx.x + u * NT;
         js[u] = q < S ? src[q] : -1;
     }
 }
@@ -449,15 +481,17 @@ __device__ __forceinline__ void stage_ids(const View& v, int64_t tile, int S,
 // Loads the positions and velocities of the tile's S list sources into
 // LDS (slot q holds the q-th source of the tile's sorted set): every
 // thread takes its sources at once, their ids first, then their fields.
+template <int NT = BLOCK>
 __device__ __forceinline__ void stage_pass1(const View& v, int64_t tile, int S, double* sx,
                                             double* sy, double* sz, double* su,
                                             double* sv, double* sw)
 {
-    int32_t js[STAGE_PER];
-    stage_ids(v, tile, S, js);
-    double f[6][STAGE_PER];
+    constexpr int SP = stage_per<NT>();
+    int32_t js[SP];
+    stage_ids<NT>(v, tile, S, js);
+    double f[6][SP];
 #pragma unroll
-    for (int u = 0; u < STAGE_PER; ++u) {
+    for (int u = 0; u < SP; ++u) {
         const int32_t j = js[u] < 0 ? 0 : js[u];
         f[0][u] = v.x[j];
         f[1][u] = v.y[j];
@@ -467,9 +501,9 @@ __device__ __forceinline__ void stage_pass1(const View& v, int64_t tile, int S, 
         f[5][u] = v.w[j];
     }
 #pragma unroll
-    for (int u = 0; u < STAGE_PER; ++u) {
+    for (int u = 0; u < SP; ++u) {
         if (js[u] < 0) continue;
-        const int q = (int)threadIdx.x + u * BLOCK;
+        const int q = (int)threadIdx.x + u * NT;
         sx[q] = f[0][u];
         sy[q] = f[1][u];
         sz[q] = f[2][u];
@@ -481,16 +515,18 @@ __device__ __forceinline__ void stage_pass1(const View& v, int64_t tile, int S, 
 
 // Loads the positions, P and eta of the tile's S list sources into LDS,
 // with the pressure a mirror of each source carries (pass2_values).
+template <int NT = BLOCK>
 __device__ __forceinline__ void stage_pass2(const View& v, const double* P,
                                             const double* eta, int64_t tile, int S,
                                             double* sx, double* sy, double* sz,
                                             double* sP, double* sE, double* sM)
 {
-    int32_t js[STAGE_PER];
-    stage_ids(v, tile, S, js);
-    double f[5][STAGE_PER];
+    constexpr int SP = stage_per<NT>();
+    int32_t js[SP];
+    stage_ids<NT>(v, tile, S, js);
+    double f[5][SP];
 #pragma unroll
-    for (int u = 0; u < STAGE_PER; ++u) {
+    for (int u = 0; u < SP; ++u) {
         const int32_t j = js[u] < 0 ? 0 : js[u];
         f[0][u] = v.x[j];
         f[1][u] = v.y[j];
@@ -499,9 +535,9 @@ __device__ __forceinline__ void stage_pass2(const View& v, const double* P,
         f[4][u] = eta[j];
     }
 #pragma unroll
-    for (int u = 0; u < STAGE_PER; ++u) {
+    for (int u = 0; u < SP; ++u) {
         if (js[u] < 0) continue;
-        const int q = (int)threadIdx.x + u * BLOCK;
+        const int q = (int)threadIdx.x + u * NT;
         const int32_t j = js[u];
         sx[q] = f[0][u];
         sy[q] = f[1][u];

@@ -196,6 +196,7 @@ struct MaskWalk {
     uint64_t b0, b1, b2, b3;
     __device__ __forceinline__ explicit MaskWalk(const Rec& r)
         : b0(r.mask[0]), b1(r.mask[1]), b2(r.mask[2]), b3(r.mask[3]) {}
+    __device__ __forceinline__ bool any() const { return (b0 | b1 | b2 | b3) != 0; }
     // next set bit; the caller pops at most popcount times
     __device__ __forceinline__ int pop()
     {
@@ -325,6 +326,53 @@ __device__ __forceinline__ void visit_staged(const View& v, const Seen& s, int64
         for (int u = 0; u < B; ++u) row(w[u]);
     }
     for (; t < r.m; ++t) row(v.vs[(int64_t)mw.pop() * n + i]);
+}
+
+// visit_staged with the rows of particle i spread over LPP adjacent lanes:
+// lane `sub` takes the kept rows sub, sub + LPP, sub + 2 LPP, ... (B of
+// them loaded together), in the order of visit_staged.
+template <int B, int LPP, class F>
+__device__ __forceinline__ void visit_staged_sub(const View& v, const Seen& s, int64_t i,
+                                                 const Rec& r, int sub, const double* sx,
+                                                 const double* sy, const double* sz, F&& f)
+{
+    const int64_t n = v.n;
+    auto row = [&](uint32_t word) {
+        Pt p;
+        const int q = (int)(word & (SLOT_MIRROR - 1u));
+        p.mirror = (word & SLOT_MIRROR) != 0u;
+        p.valid = true;
+        p.src = q;
+        p.id = -1;
+        p.x = sx[q];
+        p.y = sy[q];
+        p.z = p.mirror ? dsub(s.wall2, sz[q]) : sz[q];
+        if (v.periodic) {
+            p.x = image_coord(p.x, s.xi, s.Lx, s.hLx);
+            p.y = image_coord(p.y, s.yi, s.Ly, s.hLy);
+        }
+        f(p, dsub(p.x, s.xi), dsub(p.y, s.yi), dsub(p.z, s.zi));
+    };
+    MaskWalk mw(r);
+    // this lane's rows; the walk skips the other lanes' rows
+    const int mine = sub < r.m ? (r.m - sub + LPP - 1) / LPP : 0;
+    for (int q = 0; q < sub && mw.any(); ++q) mw.pop();
+    auto next = [&]() {
+        const int k = mw.pop();
+#pragma unroll
+        for (int q = 1; q < LPP; ++q)
+            if (mw.any()) mw.pop();
+        return k;
+    };
+    int t = 0;
+    for (; t + B <= mine; t += B) {
+        uint32_t w[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) w[u] = v.vs[(int64_t)next() * n + i];
+#pragma unroll
+        for (int u = 0; u < B; ++u) row(w[u]);
+    }
+    for (; t < mine; ++t) row(v.vs[(int64_t)next() * n + i]);
 }
 
 // visit_stencil with the rows of particle i spread over LPP adjacent
