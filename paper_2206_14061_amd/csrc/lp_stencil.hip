@@ -328,10 +328,12 @@ struct Mask4 {
         else
             w3 |= b;
     }
-    // bits of `bits` at entries k0, k0 + 1, ... (k0 a multiple of 8)
+    // bits of `bits` at entries k0, k0 + 1, ... (W bits, k0 a multiple
+    // of W, W dividing 64)
+    template <int W = 8>
     __device__ __forceinline__ void set_bits(int k0, uint32_t bits)
     {
-        const uint64_t b = (uint64_t)(bits & 0xFFu) << (k0 & 63);
+        const uint64_t b = (uint64_t)(bits & ((1u << W) - 1u)) << (k0 & 63);
         if (k0 < 64)
             w0 |= b;
         else if (k0 < 128)
@@ -541,22 +543,29 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
 
     // ---- pass 2: keep every lower bucket; the cut bucket whole, or its
     // members collected for exact ranking
+    // Sixteen entries at a time: their keep and member bits are formed
+    // with selects (no divergent branch per entry); the few members are
+    // then listed from their bits.
     Mask4 mk;
     int nl = 0;
+    const uint32_t ub = (uint32_t)bstar;
     for (int k0 = 0; k0 < cnt; k0 += 16) {
         uint32_t cw[4];
 #pragma unroll
         for (int w = 0; w < 4; ++w)
             cw[w] = k0 + 4 * w < cnt ? code[(int64_t)((k0 >> 2) + w) * n + i] : 0xFFFFFFFFu;
+        uint32_t keep = 0, memb = 0;
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int kc = (int)((cw[u >> 2] >> (8 * (u & 3))) & 0xFFu);
-            if (kc < bstar || (kc == bstar && !partial)) {
-                mk.set(k0 + u);
-            } else if (kc == bstar) {
-                lkey[nl][t] = (uint32_t)(k0 + u);
-                ++nl;
-            }
+            const uint32_t kc = (cw[u >> 2] >> (8 * (u & 3))) & 0xFFu;
+            keep |= (kc < ub || (kc == ub && !partial)) ? 1u << u : 0u;
+            memb |= (kc == ub && partial) ? 1u << u : 0u;
+        }
+        mk.set_bits<16>(k0, keep);
+        while (memb) {
+            lkey[nl][t] = (uint32_t)(k0 + __builtin_ctz(memb));
+            ++nl;
+            memb &= memb - 1;
         }
     }
     // keys of the members: r^2 rounded to float with its low 8 bits
