@@ -63,6 +63,8 @@ struct AdjBufs {
     double* dparams;     // n_sys x 3
     ErrWord* err;
     double* recv;        // 6 x n: contributions received from other particles
+    double* M;           // 31 x n: Gram moments of each particle's stencil rows
+                         // (written by the reverse pass 2, read by pass 1)
 };
 
 // LDS accumulators of a tile's staged sources: six per source slot
@@ -270,6 +272,12 @@ __device__ __forceinline__ void adj2_particle(const View& v, const AdjSeed& S,
         }
     }
     const bool lead = sub == 0;
+    // the moments are those of the u, v, w fit too (same rows, unit
+    // weights): the reverse pass 1 reads them instead of summing its rows
+    if (lead) {
+#pragma unroll
+        for (int q = 0; q < 31; ++q) B.M[(int64_t)q * n + i] = M[q];
+    }
     double U[45];
     gram_from_moments(M, U);
     const double ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
@@ -587,16 +595,10 @@ __global__ __launch_bounds__(BLOCK * LPP, 1) void k_adj_pass1(View v, AdjBufs B,
         // ---- reverse of the fit of u, v, w (coefficients per unit h)
         const double ih = g.inv_h, ih2 = g.inv_h * g.inv_h;
         const double hh = g.h, hh2 = g.h * g.h;
+        // the moments of the rows, as the reverse pass 2 summed them
         double M[31];
 #pragma unroll
-        for (int q = 0; q < 31; ++q) M[q] = 0.0;
-        rows([&](const double* a, double w, const Pt*, double, double, double) {
-            moments_add(M, a, w);
-        });
-        if (LPP > 1) {
-#pragma unroll
-            for (int q = 0; q < 31; ++q) M[q] = lane_sum<LPP>(M[q]);
-        }
+        for (int q = 0; q < 31; ++q) M[q] = B.M[(int64_t)q * n + i];
         double U[45];
         gram_from_moments(M, U);
         const double ratio = lin ? cholesky<3>(U) : cholesky<9>(U);
@@ -746,6 +748,7 @@ lp_status step_adjoint(lp_ctx* c, const double* const st[7], const AdjSeed& seed
     // before each reverse pass and added to the accumulators after it
     hipStream_t s = c->stream;
     B.recv = w.adj_recv;
+    B.M = w.adj_M;
     const int mo = c->map_ok ? 1 : 0;
     hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, seed, B);
     hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(NRECV * n)), dim3(BLOCK), 0, s,

@@ -88,7 +88,7 @@ void free_work(Work& w)
     f(w.P); f(w.eta); f(w.hand); f(w.uf);
     for (int a = 0; a < 7; ++a) f(w.adj[a]);
     f(w.adj_P); f(w.adj_E); f(w.adj_stash); f(w.coefu); f(w.adj_perm);
-    f(w.adj_recv);
+    f(w.adj_recv); f(w.adj_M);
     f(w.gate); f(w.ids_tmp);
     for (int a = 0; a < 7; ++a) f(w.sst2[a]);
     for (int a = 0; a < 7; ++a) f(w.adj2[a]);

@@ -220,6 +220,7 @@ struct Work {
     double* coefu = nullptr;              // 27 x n forward velocity coefficients
     int32_t* adj_perm = nullptr;
     double* adj_recv = nullptr;           // 6 x n: cotangents received from neighbours
+    double* adj_M = nullptr;              // 31 x n: Gram moments of the stencils
     // captured step sequences
     int32_t* gate = nullptr;              // [0] rebuild, [1] keep
     // second-order steps: predictor state and its right-hand side
@@ -277,6 +278,7 @@ constexpr void work_layout(Work& w, int64_t n_max, int64_t cells_max, int mm,
     A(w.adj_P, n_max); A(w.adj_E, n_max); A(w.adj_stash, (int64_t)11 * n_max);
     A(w.coefu, (int64_t)27 * n_max); A(w.adj_perm, n_max);
     A(w.adj_recv, 6 * n_max);
+    A(w.adj_M, (int64_t)31 * n_max);
     A(w.gate, 4); A(w.ids_tmp, n_max);
     for (int a = 0; a < 7; ++a) A(w.sst2[a], n_max);
     for (int a = 0; a < 7; ++a) A(w.adj2[a], n_max);
