@@ -56,3 +56,29 @@ def test_algorithmic_bytes_per_particle():
     # 24 + 4 + 4 L + 24 + L + 12 + 32 with L = 77.5 list entries
     assert abs(bench.SELECT_BYTES_PER_PARTICLE - 483.5) < 1e-9
     assert bench.PASS2_BYTES_PER_PARTICLE == 629
+
+
+def test_adjoint_flop_record_follows_the_sources(tmp_path, monkeypatch):
+    """The committed float64 flop record of the adjoint step parses and is
+    used exactly while the adjoint's sources are unchanged."""
+    import json
+    import re
+    text = open(os.path.join(ROOT, bench.ADJOINT_PROFILE)).read()
+    m = re.search(r"^flop-record: (\{.*\})\s*$", text, re.M)
+    assert m
+    rec = json.loads(m.group(1))
+    assert rec["flop_per_particle"] > 1e4 and rec["particles"] == 131072
+    got = bench.flop_record(bench.ADJOINT_PROFILE, bench.ADJOINT_SOURCES)
+    if rec["source_sha256"] == bench.sources_digest(bench.ADJOINT_SOURCES):
+        assert got == rec["flop_per_particle"]
+    else:
+        assert got is None
+    f = tmp_path / "a.md"
+    f.write_text("flop-record: " + json.dumps({"flop_per_particle": 5.0,
+                                                "source_sha256": "0" * 64}) + "\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.flop_record("a.md", []) is None
+    f.write_text("flop-record: " + json.dumps({"flop_per_particle": 5.0,
+                                                "source_sha256": bench.sources_digest([])})
+                 + "\n")
+    assert bench.flop_record("a.md", []) == 5.0
