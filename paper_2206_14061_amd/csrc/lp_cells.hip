@@ -576,9 +576,9 @@ void radix_sort(lp_ctx* c, int64_t cnt, int bits, unsigned long long*& kr,
     vr = vin;
 }
 
-// Rebuild decision of a captured step: gate[0] = rebuild, gate[1] = keep
-// the list (copy the state); rebuild when some particle has moved skin R /
-// 2 since the last build (or always when `force`).
+// Rebuild decision of a captured step: gate[0] = rebuild (re-sort and
+// rebuild the list), when some particle has moved 0.49 skin R since the
+// last build (or always when `force`).
 __global__ void k_decide(Summary* sum, int32_t* gate, Counters* cnt, int force,
                          unsigned long long* bbox, int n_sys)
 {
@@ -586,7 +586,6 @@ __global__ void k_decide(Summary* sum, int32_t* gate, Counters* cnt, int force,
     const double r = ord_dec(sum->disp);
     const bool rebuild = force || !(sqrt(r) < 0.49);
     gate[0] = rebuild ? 1 : 0;
-    gate[1] = rebuild ? 0 : 1;
     // the next step's displacement check starts from zero
     sum->disp = ord_enc(0.0);
     if (!rebuild) return;

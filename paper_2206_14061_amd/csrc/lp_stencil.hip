@@ -1002,16 +1002,16 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
     }
 }
 
-__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
-
 // 32-byte position records (x, y, z, 0) of the state the stencils are
 // built on; every neighbour gather of the selection and the fits reads
 // them (one cache line per neighbour instead of three).
 __global__ __launch_bounds__(BLOCK) void k_pack_pos(int64_t n, const double* x,
                                                     const double* y, const double* z,
-                                                    double* p4)
+                                                    double* p4, unsigned int* hard_n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the selection's list of particles for the sorted path starts empty
+    if (i == 0) *hard_n = 0u;
     if (i >= n) return;
     double2* r = reinterpret_cast<double2*>(p4 + 4 * i);
     r[0] = make_double2(x[i], y[i]);
@@ -1068,10 +1068,9 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7])
     }
     View v = make_view(c, st);
     hipStream_t s = c->stream;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, w.hard_n);
     if (n > 0) {
         hipLaunchKernelGGL(k_pack_pos, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, st[0],
-                           st[1], st[2], w.p4);
+                           st[1], st[2], w.p4, w.hard_n);
         // mirrors of the current state (ids n + k in ascending source order)
         const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
         hipLaunchKernelGGL(k_mirror_count, dim3((unsigned)nb), dim3(BLOCK), 0, s, n,
