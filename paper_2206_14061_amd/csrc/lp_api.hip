@@ -195,7 +195,7 @@ lp_status step_device(lp_ctx* c, double* const in[7], int32_t* ids, double dt, i
     if (r == LP_OK) r = tile_map_build(c, c->w.gate);
     const double* sorted[7];
     for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
-    if (r == LP_OK) r = stencils_build(c, sorted);
+    if (r == LP_OK) r = stencils_build(c, sorted, true);
     if (r == LP_OK) r = step_rhs(c, sorted);
     if (r == LP_OK) r = step_update(c, sorted, dt, in);
     return r;
@@ -512,7 +512,8 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
     const double* sorted[7];
     double* const* sst = c->w.sst;
     for (int a = 0; a < 7; ++a) sorted[a] = sst[a];
-    r = stencils_build(c, sorted);
+    // the displacement check's copy or the re-sort packed the positions
+    r = stencils_build(c, sorted, true);
     if (r == LP_OK) r = step_rhs(c, sorted);
     if (r == LP_OK) r = step_update(c, sorted, dt, in);
     // stencils of the API calls refer to lp_build_cells' state
@@ -576,7 +577,7 @@ lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
     }
     const double* sorted[7];
     for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
-    r = stencils_build(c, sorted);
+    r = stencils_build(c, sorted, true);
     if (r == LP_OK) r = step_rhs(c, sorted);
     if (r == LP_OK) r = step_pass2(c, sorted, dt, nullptr, c->w.acc, c->w.dVdt);
     if (r == LP_OK) r = step_heun(c, dt, in);

@@ -507,12 +507,14 @@ __global__ void k_disp_init(Summary* sum) { sum->disp = ord_enc(0.0); }
 
 // k_disp fused with the copy of the seven state arrays into the working
 // state (one pass over the state).
+// The positions also go to their 32-byte records (p4), which the
+// selection and the list build read.
 __global__ __launch_bounds__(BLOCK) void k_copy_disp(int64_t n, int n_sys,
                                                      const int64_t* off,
                                                      const GridInfo* grid, State7 st,
                                                      Dest7 dst, const double* rx,
                                                      const double* ry, const double* rz,
-                                                     Summary* sum)
+                                                     double* p4, Summary* sum)
 {
     __shared__ double part[BLOCK / 64];
     double r = 0.0;
@@ -525,6 +527,9 @@ __global__ __launch_bounds__(BLOCK) void k_copy_disp(int64_t n, int n_sys,
         for (int a = 0; a < 7; ++a) f[a] = st.a[a][i];
 #pragma unroll
         for (int a = 0; a < 7; ++a) dst.a[a][i] = f[a];
+        double2* rec = reinterpret_cast<double2*>(p4 + 4 * i);
+        rec[0] = make_double2(f[0], f[1]);
+        rec[1] = make_double2(f[2], 0.0);
         const GridInfo& g = grid[sys_of(off, n_sys, i)];
         const double dx = image_coord(f[0], rx[i], g.Lx, g.hLx) - rx[i];
         const double dy = image_coord(f[1], ry[i], g.Ly, g.hLy) - ry[i];
@@ -771,7 +776,7 @@ lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool
         }
         hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), 512u)), dim3(BLOCK), 0,
                            c->stream, n, c->n_sys, w.off, w.grid, s7, d7, w.xref[0],
-                           w.xref[1], w.xref[2], w.summary);
+                           w.xref[1], w.xref[2], w.p4, w.summary);
     }
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(1), 0, c->stream, w.summary, w.gate,
                        w.cnt, force, w.bbox, c->n_sys);
@@ -809,7 +814,7 @@ lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
         hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), 512u)), dim3(BLOCK), 0,
                            c->stream, n,
                            c->n_sys, w.off, w.grid, s7, d7, w.xref[0], w.xref[1],
-                           w.xref[2], w.summary);
+                           w.xref[2], w.p4, w.summary);
     } else if (n > 0) {
         hipLaunchKernelGGL(k_disp, dim3(std::min(blocks_for(n), 1024u)), dim3(BLOCK), 0,
                            c->stream, n,

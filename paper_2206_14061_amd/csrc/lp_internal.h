@@ -475,7 +475,9 @@ lp_status state_write_back(lp_ctx* c, double* const out[7]);
 lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
                             bool copy = false);
 // Mirror ids of the current state, stencil records.
-lp_status stencils_build(lp_ctx* c, const double* const st[7]);
+// packed: the positions' 32-byte records (p4) already hold st's positions
+// (written by the step's state copy or re-sort)
+lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed = false);
 lp_status stencils_export(lp_ctx* c, const double* const st[7],
                           int64_t* cand_off, int32_t* cand_idx, int64_t cap,
                           int64_t* needed, int32_t* sten_cnt,

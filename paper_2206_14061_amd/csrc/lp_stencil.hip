@@ -219,9 +219,11 @@ __device__ __forceinline__ uint32_t wall_flags(int64_t n, int n_sys, const int64
 
 __global__ void k_mirror_count(int64_t n, int n_sys, const int64_t* off,
                                const GridInfo* grid, const double* z,
-                               int32_t* bsum)
+                               int32_t* bsum, unsigned int* hard_n)
 {
     __shared__ uint32_t wsum[BLOCK / 64];
+    // the selection's list of particles for the sorted path starts empty
+    if (blockIdx.x == 0 && threadIdx.x == 0) *hard_n = 0u;
     const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
     const uint32_t c = __popc(wall_flags(n, n_sys, off, grid, z, b));
     uint32_t tot;
@@ -1007,11 +1009,9 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
 // them (one cache line per neighbour instead of three).
 __global__ __launch_bounds__(BLOCK) void k_pack_pos(int64_t n, const double* x,
                                                     const double* y, const double* z,
-                                                    double* p4, unsigned int* hard_n)
+                                                    double* p4)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // the selection's list of particles for the sorted path starts empty
-    if (i == 0) *hard_n = 0u;
     if (i >= n) return;
     double2* r = reinterpret_cast<double2*>(p4 + 4 * i);
     r[0] = make_double2(x[i], y[i]);
@@ -1057,7 +1057,7 @@ lp_status tile_map_build(lp_ctx* c, const int32_t* gate)
     return LP_OK;
 }
 
-lp_status stencils_build(lp_ctx* c, const double* const st[7])
+lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed)
 {
     Work& w = c->w;
     const int64_t n = c->n;
@@ -1069,12 +1069,14 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7])
     View v = make_view(c, st);
     hipStream_t s = c->stream;
     if (n > 0) {
-        hipLaunchKernelGGL(k_pack_pos, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, st[0],
-                           st[1], st[2], w.p4, w.hard_n);
+        // (the state copy or the re-sort of a step has packed them already)
+        if (!packed)
+            hipLaunchKernelGGL(k_pack_pos, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, st[0],
+                               st[1], st[2], w.p4);
         // mirrors of the current state (ids n + k in ascending source order)
         const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
         hipLaunchKernelGGL(k_mirror_count, dim3((unsigned)nb), dim3(BLOCK), 0, s, n,
-                           c->n_sys, w.off, w.grid, st[2], w.bsum);
+                           c->n_sys, w.off, w.grid, st[2], w.bsum, w.hard_n);
         hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1024), 0, s,
                            (uint32_t*)w.bsum, nb, &w.summary->n_mirror);
         hipLaunchKernelGGL(k_mirror_write, dim3((unsigned)nb), dim3(BLOCK), 0, s, n,
