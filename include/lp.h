@@ -58,7 +58,8 @@ enum { LP_W_UNIT = 0, LP_W_GAUSS = 1 };
  * 4 and the staged tile kernel in the first fit, 4, 2 and 1 in the
  * second; results agree to rounding) */
 enum { LP_DEBUG_SORTED_STENCIL = 1, LP_DEBUG_QR_FIT = 2, LP_DEBUG_LANES2 = 4,
-       LP_DEBUG_LANES4 = 8, LP_DEBUG_GLOBAL_GATHER = 16, LP_DEBUG_CLASSES = 32 };
+       LP_DEBUG_LANES4 = 8, LP_DEBUG_GLOBAL_GATHER = 16, LP_DEBUG_CLASSES = 32,
+       LP_DEBUG_MIRROR_SCAN = 64 };
 
 /* Physical constants of one system (Sec. 2.2, 2.2.1 and Sec. 4).
  * rho_s: grain material density (the paper's phi_s); d: grain diameter;
@@ -96,7 +97,9 @@ typedef struct {
  * fallback_tol: stencils with min|r_jj|/max|r_jj| below it (or fewer than 9
  * rows) use a linear fit (1e-12).  debug_flags: LP_DEBUG_* bits (sorted
  * stencil path for every particle, Householder refit for every stencil,
- * 2 or 4 lanes per particle in the fits).
+ * 2 or 4 lanes per particle in the fits, mirror numbering through a
+ * separate scan of the per-tile counts as above 2048 tiles of 4,096
+ * particles).
  * skin: neighbour-list margin in units of R (default 0.1): the list holds
  * every pair within R (1 + skin) and is rebuilt (with a Morton re-sort)
  * once a particle has moved skin R / 2 since the last build; 0 rebuilds

@@ -321,6 +321,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     w.m_max = mm;
     w.hist_cap = 256 * nb;
     c->cells_ok = c->stencils_ok = c->list_ok = c->map_ok = false;
+    c->redo_clear = c->disp_clear = false;
     if (c->n_sys > 0) {
         // re-upload the systems into the new buffers
         std::vector<int64_t> off = c->h_off;
@@ -706,6 +707,8 @@ lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,
         e = hipStreamEndCapture(c->cap_stream, &g);
         c->stream = saved;
         c->prof = prof;
+        // what the captured kernels leave is not tracked on the host
+        c->redo_clear = c->disp_clear = false;
         if (r != LP_OK) {
             if (g) hipGraphDestroy(g);
             return r;
@@ -720,6 +723,7 @@ lp_status lp_step_graph(lp_ctx* c, lp_state* s, int32_t* ids, double dt,
         c->gkey = key;
     }
     hipError_t e = hipGraphLaunch(c->gexec, c->stream);
+    c->redo_clear = c->disp_clear = false;
     if (e != hipSuccess) return hip_fail(c, e, "graph launch");
     // the replay may have rebuilt the list on the device: records of
     // earlier steps no longer describe the current list

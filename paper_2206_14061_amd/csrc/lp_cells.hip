@@ -503,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void k_disp(int64_t n, int n_sys, const int6
     }
 }
 
-__global__ void k_disp_init(Summary* sum) { sum->disp = ord_enc(0.0); }
+__global__ void k_disp_init(Summary* sum) { sum->disp = DISP_ZERO; }
 
 // k_disp fused with the copy of the seven state arrays into the working
 // state (one pass over the state).
@@ -592,7 +592,7 @@ __global__ void k_decide(Summary* sum, int32_t* gate, Counters* cnt, int force,
     const bool rebuild = force || !(sqrt(r) < 0.49);
     gate[0] = rebuild ? 1 : 0;
     // the next step's displacement check starts from zero
-    sum->disp = ord_enc(0.0);
+    sum->disp = DISP_ZERO;
     if (!rebuild) return;
     atomicAdd(&cnt->rebuilds, 1ull);
     // empty bounding boxes for the rebuild's k_bbox (as k_bbox_init)
@@ -765,6 +765,7 @@ lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool
     const int64_t n = c->n;
     // k_decide leaves the maximum at zero for the next captured step
     if (first) hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
+    c->disp_clear = false;
     if (n > 0) {
         // the state copied into the working state (in the current order)
         // with the displacement check; a rebuild then overwrites it
@@ -803,7 +804,10 @@ lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
     const int64_t n = c->n;
     *ratio = -1.0;
     if (!c->list_ok) return LP_OK;
-    hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
+    // (a stencil build since the last check left the maximum at zero)
+    if (!c->disp_clear)
+        hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
+    c->disp_clear = false;
     if (n > 0 && copy) {
         State7 s7;
         Dest7 d7;

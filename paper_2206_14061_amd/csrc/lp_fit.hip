@@ -1009,6 +1009,15 @@ __global__ __launch_bounds__(QR_TPB) void k_pass2_qr(View v, const double* P,
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
+// Clears the fits' refit counter unless the stencil build enqueued last
+// has (k_mirror_count clears it with the step's other counters).
+void redo_reset(lp_ctx* c)
+{
+    if (!c->redo_clear)
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, c->w.redo_n);
+    c->redo_clear = false;
+}
+
 __global__ void k_zero_classes(uint32_t* cnt)
 {
     if (threadIdx.x < NCLASS) cnt[threadIdx.x] = 0u;
@@ -1243,7 +1252,7 @@ lp_status fit_generic(lp_ctx* c, const double* const st[7], const double* f,
     }
     uint8_t* fl = flags ? flags : w.flags;
     const int fq = (c->cfg.debug_flags & LP_DEBUG_QR_FIT) ? 1 : 0;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+    redo_reset(c);
     if (n > 0 && c->cfg.fit_order == 3) {
         launch_fit3_generic(c, v, F, coef, fl);
     } else if (n > 0) {
@@ -1294,7 +1303,7 @@ lp_status rhs_from_coef(lp_ctx* c, const double* const st[7],
     View v = make_view(c, st);
     StepOut so{w.P, w.eta, w.hand, w.flags, diag, nullptr};
     const int fq = (c->cfg.debug_flags & LP_DEBUG_QR_FIT) ? 1 : 0;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+    redo_reset(c);
     if (n > 0) {
         hipLaunchKernelGGL(k_closure_coef, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, v, coef_u, so, w.redo, w.redo_n, fq);
@@ -1324,7 +1333,7 @@ lp_status step_rhs(lp_ctx* c, const double* const st[7])
     View v = make_view(c, st);
     StepOut so{w.P, w.eta, w.hand, w.flags, nullptr, nullptr};
     const int fq = (c->cfg.debug_flags & LP_DEBUG_QR_FIT) ? 1 : 0;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+    redo_reset(c);
     if (n > 0) {
         prof_mark(c, 3, false);
         if (c->cfg.fit_order == 3)
@@ -1358,7 +1367,7 @@ lp_status step_pass1_coef(lp_ctx* c, const double* const st[7])
     const int64_t n = c->n;
     View v = make_view(c, st);
     StepOut so{w.P, w.eta, w.hand, w.flags, nullptr, w.coefu};
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+    redo_reset(c);
     if (n > 0) {
         // the pass-2 fit of these stencils may run by size class
         if (classes_on(c)) classify(c, v);
@@ -1436,7 +1445,7 @@ lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice)
     auto timed = [&](auto&& launch) -> float {
         float t = 1e30f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+            redo_reset(c);
             e = hipEventRecord(e0, c->stream);
             launch();
             if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
@@ -1458,7 +1467,7 @@ lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice)
     }
     // pass 2 needs the pass-1 outputs
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+        redo_reset(c);
         launch_pass1(c, pick1, v, so, 0);
     }
     for (int q = 0; q < 3 && e == hipSuccess; ++q) {
@@ -1489,7 +1498,7 @@ lp_status autotune_fits(lp_ctx* c, const double* const st[7], int32_t* choice)
             }
         }
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, w.redo_n);
+            redo_reset(c);
             launch_pass1(c, pick1, v, so, 0);
         }
         for (int k = 0; k < NCLASS && e == hipSuccess; ++k) {

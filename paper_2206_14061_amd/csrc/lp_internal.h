@@ -75,6 +75,8 @@ constexpr int CLASS_ROWS0 = 16, CLASS_ROWS1 = 32;
 constexpr int BLOCK = 256;        // threads per block of per-particle kernels
 constexpr int SORT_ITEMS = 16;    // keys per thread in a radix tile
 constexpr int SORT_TILE = BLOCK * SORT_ITEMS;
+// mirror numbering without a separate scan up to this many tiles
+constexpr int MIRROR_SUM_BLOCKS = 2048;
 
 // flag bits per particle
 constexpr uint8_t FLAG_LINEAR = 1;
@@ -102,6 +104,10 @@ struct GridInfo {
 };
 
 // Small block read back by the host after the grid is built.
+// Ordered encoding (see the displacement check) of +0.0: the starting
+// value of the displacement maximum.
+constexpr unsigned long long DISP_ZERO = 0x8000000000000000ull;
+
 struct Summary {
     int64_t total_cells;
     int64_t n_mirror;
@@ -314,6 +320,10 @@ struct lp_ctx {
     int64_t cls_count[lp::NCLASS] = {0, 0, 0};
     double tune_ms[8] = {0};
     int64_t rebuilds = 0;       // list rebuilds since the last lp_stats
+    // the work enqueued last left the fits' refit counter (redo_clear) or
+    // the displacement maximum (disp_clear) at zero, so the next user
+    // need not clear it (set by a stencil build, taken by the next user)
+    bool redo_clear = false, disp_clear = false;
     // phase timing (lp_profile)
     bool prof = false;
     hipEvent_t ev[16] = {nullptr};

@@ -159,6 +159,7 @@ extern "C" lp_status lp_step_noalloc(void* stream, const lp_config* cfg, int32_t
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "lp_step_noalloc clear");
     c->list_ok = c->map_ok = c->cells_ok = c->stencils_ok = false;
+    c->redo_clear = c->disp_clear = false;
     c->built_x = nullptr;
     r = lp_step(c, s, dt, perm, nullptr);
     // device-side errors of this call (synchronises)

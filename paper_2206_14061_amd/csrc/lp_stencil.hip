@@ -217,13 +217,20 @@ __device__ __forceinline__ uint32_t wall_flags(int64_t n, int n_sys, const int64
     return bits;
 }
 
+// Also clears the step's counters: the selection's list of particles for
+// the sorted path, the fits' refit list and the displacement maximum of
+// the next list check (read by the host before this kernel is enqueued).
 __global__ void k_mirror_count(int64_t n, int n_sys, const int64_t* off,
                                const GridInfo* grid, const double* z,
-                               int32_t* bsum, unsigned int* hard_n)
+                               int32_t* bsum, unsigned int* hard_n,
+                               unsigned int* redo_n, Summary* sum)
 {
     __shared__ uint32_t wsum[BLOCK / 64];
-    // the selection's list of particles for the sorted path starts empty
-    if (blockIdx.x == 0 && threadIdx.x == 0) *hard_n = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *hard_n = 0u;
+        *redo_n = 0u;
+        sum->disp = DISP_ZERO;
+    }
     const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
     const uint32_t c = __popc(wall_flags(n, n_sys, off, grid, z, b));
     uint32_t tot;
@@ -259,16 +266,35 @@ __global__ void k_scan_total(uint32_t* a, int64_t cnt, int64_t* total)
     if (t == 1023) *total = (int64_t)part[1023];
 }
 
+// bsum holds the blocks' exclusive offsets (scanned) or their counts; with
+// counts (few blocks) each block sums those of the blocks before it and the
+// last block writes the total.
 __global__ void k_mirror_write(int64_t n, int n_sys, const int64_t* off,
                                const GridInfo* grid, const int32_t* bsum,
-                               const double* z, int32_t* mirror_of,
-                               int32_t* msrc)
+                               int scanned, int64_t* total, const double* z,
+                               int32_t* mirror_of, int32_t* msrc)
 {
     __shared__ uint32_t wsum[BLOCK / 64];
+    __shared__ uint32_t bpre[BLOCK / 64];
     const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
     const uint32_t bits = wall_flags(n, n_sys, off, grid, z, b);
+    uint32_t base;
+    if (scanned) {
+        base = (uint32_t)bsum[blockIdx.x];
+    } else {
+        uint32_t p = 0;
+        for (int q = threadIdx.x; q < (int)blockIdx.x; q += BLOCK) p += (uint32_t)bsum[q];
+        for (int d = 32; d > 0; d >>= 1) p += __shfl_xor(p, d);
+        if ((threadIdx.x & 63) == 0) bpre[threadIdx.x >> 6] = p;
+        __syncthreads();
+        base = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) base += bpre[w];
+    }
     uint32_t tot;
-    uint32_t k = block_excl_scan(__popc(bits), wsum, tot) + (uint32_t)bsum[blockIdx.x];
+    uint32_t k = block_excl_scan(__popc(bits), wsum, tot) + base;
+    if (!scanned && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        *total = (int64_t)(base + tot);
 #pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const int64_t i = b + r;
@@ -1076,12 +1102,18 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed)
         // mirrors of the current state (ids n + k in ascending source order)
         const int64_t nb = (n + SORT_TILE - 1) / SORT_TILE;
         hipLaunchKernelGGL(k_mirror_count, dim3((unsigned)nb), dim3(BLOCK), 0, s, n,
-                           c->n_sys, w.off, w.grid, st[2], w.bsum, w.hard_n);
-        hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1024), 0, s,
-                           (uint32_t*)w.bsum, nb, &w.summary->n_mirror);
+                           c->n_sys, w.off, w.grid, st[2], w.bsum, w.hard_n, w.redo_n,
+                           w.summary);
+        // up to MIRROR_SUM_BLOCKS blocks each add the counts before them
+        // (at most that many words per block, from L2) instead of a scan
+        const int scanned =
+            (nb > MIRROR_SUM_BLOCKS || (c->cfg.debug_flags & LP_DEBUG_MIRROR_SCAN)) ? 1 : 0;
+        if (scanned)
+            hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1024), 0, s,
+                               (uint32_t*)w.bsum, nb, &w.summary->n_mirror);
         hipLaunchKernelGGL(k_mirror_write, dim3((unsigned)nb), dim3(BLOCK), 0, s, n,
-                           c->n_sys, w.off, w.grid, w.bsum, st[2], w.mirror_of,
-                           w.msrc);
+                           c->n_sys, w.off, w.grid, w.bsum, scanned, &w.summary->n_mirror,
+                           st[2], w.mirror_of, w.msrc);
         const int force = (c->cfg.debug_flags & LP_DEBUG_SORTED_STENCIL) ? 1 : 0;
         // the select phase times the selection kernel alone
         prof_mark(c, 1, false);
@@ -1100,6 +1132,8 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "stencil launch");
     c->stencils_ok = true;
+    // k_mirror_count cleared the refit list and the displacement maximum
+    if (n > 0) c->redo_clear = c->disp_clear = true;
     return LP_OK;
 }
 

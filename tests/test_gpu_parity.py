@@ -122,6 +122,33 @@ def test_sorted_stencil_path_bit_exact(lp, case):
     _check_neighbours(lp, wl, debug_flags=lp.LP_DEBUG_SORTED_STENCIL)
 
 
+@pytest.mark.parametrize("case", ["sheared_20x20x12", "ensemble_3"])
+def test_mirror_numbering_through_the_block_scan(lp, case):
+    """Mirror ids from the separate scan of the per-tile wall counts (the
+    path above 2048 tiles) are those of the in-kernel prefix sums: both
+    bit-exact against the oracle on workloads of several tiles."""
+    wl = CASES[case]()
+    _log("case %s n=%d (mirror scan)" % (case, wl.n))
+    _check_neighbours(lp, wl, debug_flags=lp.LP_DEBUG_MIRROR_SCAN)
+
+
+def test_mirror_numbering_paths_agree_on_the_full_column(lp):
+    """128 tiles of the 524,288-particle column: mirror count, candidate
+    lists and stencils equal with either way of numbering the mirrors."""
+    wl = lpgen.column_bench()
+    got = []
+    for flags in (0, lp.LP_DEBUG_MIRROR_SCAN):
+        ctx, st, _ = _gpu_sorted(lp, wl, debug_flags=flags)
+        g = ctx.lp_neighbors(st)
+        ctx.sync_status()
+        got.append({k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in g.items()})
+        del ctx, st
+    _log("mirrors %d" % got[0]["n_mirror"])
+    assert got[0]["n_mirror"] > 0
+    for k in got[0]:
+        assert np.array_equal(np.asarray(got[0][k]), np.asarray(got[1][k])), k
+
+
 def _fields(st):
     x, y, z = st.x, st.y, st.z
     return np.stack([np.sin(3.0 * x + 1.0) * np.cos(2.0 * y) + z * z,
