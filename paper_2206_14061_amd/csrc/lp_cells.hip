@@ -505,6 +505,10 @@ __global__ __launch_bounds__(BLOCK) void k_disp(int64_t n, int n_sys, const int6
 
 __global__ void k_disp_init(Summary* sum) { sum->disp = DISP_ZERO; }
 
+// blocks of the state copy with the displacement check (one maximum per
+// block goes to the summary; 256 to 1,024 time alike, 2,048 slower)
+constexpr unsigned COPY_BLOCKS = 512u;
+
 // k_disp fused with the copy of the seven state arrays into the working
 // state (one pass over the state).
 // The positions also go to their 32-byte records (p4), which the
@@ -775,7 +779,7 @@ lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool
             s7.a[a] = st[a];
             d7.a[a] = w.sst[a];
         }
-        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), 512u)), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), COPY_BLOCKS)), dim3(BLOCK), 0,
                            c->stream, n, c->n_sys, w.off, w.grid, s7, d7, w.xref[0],
                            w.xref[1], w.xref[2], w.p4, w.summary);
     }
@@ -815,7 +819,7 @@ lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
             s7.a[a] = st[a];
             d7.a[a] = w.sst[a];
         }
-        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), 512u)), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), COPY_BLOCKS)), dim3(BLOCK), 0,
                            c->stream, n,
                            c->n_sys, w.off, w.grid, s7, d7, w.xref[0], w.xref[1],
                            w.xref[2], w.p4, w.summary);

@@ -193,27 +193,38 @@ __device__ __forceinline__ Rec load_rec(const View& v, int64_t i)
 // Set bits of a keep mask in ascending order (list indices).
 struct MaskWalk {
     static_assert(MASK_WORDS == 4, "keep mask walk assumes four words");
-    uint64_t b0, b1, b2, b3;
+    // the word being walked (entries base, base + 1, ...) and the words
+    // after it
+    uint64_t cur, b1, b2, b3;
+    int base = 0;
     __device__ __forceinline__ explicit MaskWalk(const Rec& r)
-        : b0(r.mask[0]), b1(r.mask[1]), b2(r.mask[2]), b3(r.mask[3]) {}
-    __device__ __forceinline__ bool any() const { return (b0 | b1 | b2 | b3) != 0; }
-    // next set bit; the caller pops at most popcount times
+        : cur(r.mask[0]), b1(r.mask[1]), b2(r.mask[2]), b3(r.mask[3]) {}
+    __device__ __forceinline__ bool any() const { return (cur | b1 | b2 | b3) != 0; }
+    // next set bit; the caller pops at most popcount times.  A lane moves
+    // to the next word only when its current one is used up (a few times
+    // per stencil), so the common pop is one count of trailing zeros.
     __device__ __forceinline__ int pop()
     {
-        int k;
-        if (b0) {
-            k = __builtin_ctzll(b0);
-            b0 &= b0 - 1;
-        } else if (b1) {
-            k = 64 + __builtin_ctzll(b1);
-            b1 &= b1 - 1;
-        } else if (b2) {
-            k = 128 + __builtin_ctzll(b2);
-            b2 &= b2 - 1;
-        } else {
-            k = 192 + __builtin_ctzll(b3);
-            b3 &= b3 - 1;
+        if (cur == 0) {
+            cur = b1;
+            b1 = b2;
+            b2 = b3;
+            b3 = 0;
+            base += 64;
+            if (cur == 0) {
+                cur = b1;
+                b1 = b2;
+                b2 = 0;
+                base += 64;
+                if (cur == 0) {
+                    cur = b1;
+                    b1 = 0;
+                    base += 64;
+                }
+            }
         }
+        const int k = base + __builtin_ctzll(cur);
+        cur &= cur - 1;
         return k;
     }
 };
