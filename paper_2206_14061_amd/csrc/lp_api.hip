@@ -275,6 +275,7 @@ void lp_destroy(lp_ctx* c)
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (int q = 0; q < 16; ++q)
         if (c->ev[q]) hipEventDestroy(c->ev[q]);
+    if (c->chk_ev) hipEventDestroy(c->chk_ev);
     free_work(c->w);
     delete c;
 }
@@ -470,6 +471,30 @@ lp_status lp_rheology_rhs(lp_ctx* c, const lp_state* s, const double* coef_u,
     return rhs_from_coef(c, st, coef_u, dVdt, acc, diag, grad, flags);
 }
 
+// The displacement check of a step on the current list, with the state
+// copied into the working state: its result comes back to the host while
+// the stream already runs the mirrors and the histogram selection on the
+// current list (when its tile map is current), which a rebuild then
+// repeats.  rebuild: some particle moved `limit` skins or more; ahead: the
+// selection was enqueued (the step then adds only its tail).
+static lp_status check_ahead(lp_ctx* c, double* const in[7], const double* const sorted[7],
+                             double limit, bool* rebuild, bool* ahead)
+{
+    lp_status r = list_check_start(c, in, true);
+    if (r != LP_OK) return r;
+    *ahead = c->chk_pending && c->map_ok;
+    if (*ahead) {
+        prof_mark(c, 0, true);
+        r = stencils_build(c, sorted, true, STENCIL_HEAD);
+        if (r != LP_OK) return r;
+    }
+    double ratio = -1.0;
+    r = list_check_wait(c, &ratio);
+    if (r != LP_OK) return r;
+    *rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < limit);
+    return LP_OK;
+}
+
 lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
                   lp_step_record* rec)
 {
@@ -486,15 +511,16 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
     double* in[7];
     state_arrays(s, in);
     prof_mark(c, 0, false);
+    const double* sorted[7];
+    double* const* sst = c->w.sst;
+    for (int a = 0; a < 7; ++a) sorted[a] = sst[a];
     // the neighbour list stays valid until some particle has moved half
     // the skin since the last build
     bool rebuild = !c->list_ok || !(c->cfg.skin > 0.0) || (rec && rec->force_sort);
+    bool ahead = false;
     if (!rebuild) {
-        // the check also copies the state, which a rebuild then overwrites
-        double ratio = -1.0;
-        r = list_displacement(c, in, &ratio, true);
+        r = check_ahead(c, in, sorted, 0.49, &rebuild, &ahead);
         if (r != LP_OK) return r;
-        rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.49);
     }
     if (rebuild) {
         r = cells_build(c, in, rec ? rec->perm : perm);
@@ -503,18 +529,15 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
         r = state_copy(c, in, perm, nullptr, false);
     }
     if (r == LP_OK && !c->map_ok) r = tile_map_build(c);
-    prof_mark(c, 0, true);
+    if (!ahead || rebuild) prof_mark(c, 0, true);
     if (r != LP_OK) return r;
     if (rebuild) ++c->rebuilds;
     if (rec) {
         rec->resorted = rebuild ? 1 : 0;
         rec->list_gen = c->list_gen;
     }
-    const double* sorted[7];
-    double* const* sst = c->w.sst;
-    for (int a = 0; a < 7; ++a) sorted[a] = sst[a];
     // the displacement check's copy or the re-sort packed the positions
-    r = stencils_build(c, sorted, true);
+    r = stencils_build(c, sorted, true, ahead && !rebuild ? STENCIL_TAIL : STENCIL_ALL);
     if (r == LP_OK) r = step_rhs(c, sorted);
     if (r == LP_OK) r = step_update(c, sorted, dt, in);
     // stencils of the API calls refer to lp_build_cells' state
@@ -553,15 +576,15 @@ lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
     }
     double* in[7];
     state_arrays(s, in);
+    const double* sorted[7];
+    for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
     // rebuild earlier than lp_step: the predictor stage moves particles a
     // further dt |u| on the same list and must stay within half the skin
     bool rebuild = !c->list_ok || (rec && rec->force_sort);
+    bool ahead = false;
     if (!rebuild) {
-        // the check also copies the state, which a rebuild then overwrites
-        double ratio = -1.0;
-        r = list_displacement(c, in, &ratio, true);
+        r = check_ahead(c, in, sorted, 0.4, &rebuild, &ahead);
         if (r != LP_OK) return r;
-        rebuild = !(ratio >= 0.0) || !(std::sqrt(ratio) < 0.4);
     }
     if (rebuild) {
         r = cells_build(c, in, rec ? rec->perm : perm);
@@ -576,9 +599,7 @@ lp_status lp_step2(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
         rec->resorted = rebuild ? 1 : 0;
         rec->list_gen = c->list_gen;
     }
-    const double* sorted[7];
-    for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
-    r = stencils_build(c, sorted, true);
+    r = stencils_build(c, sorted, true, ahead && !rebuild ? STENCIL_TAIL : STENCIL_ALL);
     if (r == LP_OK) r = step_rhs(c, sorted);
     if (r == LP_OK) r = step_pass2(c, sorted, dt, nullptr, c->w.acc, c->w.dVdt);
     if (r == LP_OK) r = step_heun(c, dt, in);

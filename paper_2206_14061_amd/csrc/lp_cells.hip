@@ -801,12 +801,11 @@ lp_status state_write_back(lp_ctx* c, double* const out[7])
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "state write-back");
 }
 
-lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
-                            bool copy)
+lp_status list_check_start(lp_ctx* c, const double* const st[7], bool copy)
 {
     Work& w = c->w;
     const int64_t n = c->n;
-    *ratio = -1.0;
+    c->chk_pending = false;
     if (!c->list_ok) return LP_OK;
     // (a stencil build since the last check left the maximum at zero)
     if (!c->disp_clear)
@@ -829,16 +828,41 @@ lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
                            c->n_sys, w.off, w.grid, st[0], st[1], st[2], w.xref[0],
                            w.xref[1], w.xref[2], w.summary);
     }
-    hipError_t e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary),
-                                  hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    hipError_t e = hipSuccess;
+    if (!c->chk_ev) e = hipEventCreateWithFlags(&c->chk_ev, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w.h_summary, w.summary, sizeof(Summary), hipMemcpyDeviceToHost,
+                           c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->chk_ev, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "displacement check");
-    const unsigned long long enc = w.h_summary->disp;
+    c->chk_pending = true;
+    return LP_OK;
+}
+
+lp_status list_check_wait(lp_ctx* c, double* ratio)
+{
+    *ratio = -1.0;
+    if (!c->chk_pending) return LP_OK;
+    c->chk_pending = false;
+    hipError_t e = hipEventSynchronize(c->chk_ev);
+    if (e != hipSuccess) return hip_fail(c, e, "displacement check");
+    const unsigned long long enc = c->w.h_summary->disp;
     const unsigned long long b = (enc >> 63) ? (enc & 0x7FFFFFFFFFFFFFFFull) : ~enc;
     double r;
     std::memcpy(&r, &b, sizeof(r));
     *ratio = r;
     return LP_OK;
+}
+
+lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
+                            bool copy)
+{
+    lp_status r = list_check_start(c, st, copy);
+    if (r != LP_OK) {
+        *ratio = -1.0;
+        return r;
+    }
+    return list_check_wait(c, ratio);
 }
 
 }  // namespace lp

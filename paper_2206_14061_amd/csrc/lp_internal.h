@@ -324,6 +324,10 @@ struct lp_ctx {
     // the displacement maximum (disp_clear) at zero, so the next user
     // need not clear it (set by a stencil build, taken by the next user)
     bool redo_clear = false, disp_clear = false;
+    // the displacement check's maximum, copied to the host behind this
+    // event (list_check_start), not yet read (list_check_wait)
+    hipEvent_t chk_ev = nullptr;
+    bool chk_pending = false;
     // phase timing (lp_profile)
     bool prof = false;
     hipEvent_t ev[16] = {nullptr};
@@ -484,10 +488,20 @@ lp_status state_write_back(lp_ctx* c, double* const out[7]);
 // state_copy does) when a list exists.
 lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
                             bool copy = false);
+// list_displacement in two halves: the check enqueued with its result
+// copied to the host, and the wait for that copy (the stream may run later
+// work meanwhile).  ratio < 0 when no list exists.
+lp_status list_check_start(lp_ctx* c, const double* const st[7], bool copy);
+lp_status list_check_wait(lp_ctx* c, double* ratio);
 // Mirror ids of the current state, stencil records.
 // packed: the positions' 32-byte records (p4) already hold st's positions
-// (written by the step's state copy or re-sort)
-lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed = false);
+// (written by the step's state copy or re-sort).  part: STENCIL_ALL, or
+// STENCIL_HEAD (mirrors and the histogram selection, which a step enqueues
+// before it knows whether the list must be rebuilt) and then STENCIL_TAIL
+// (the exact path for the particles the selection handed over).
+enum { STENCIL_ALL = 0, STENCIL_HEAD = 1, STENCIL_TAIL = 2 };
+lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed = false,
+                         int part = STENCIL_ALL);
 lp_status stencils_export(lp_ctx* c, const double* const st[7],
                           int64_t* cand_off, int32_t* cand_idx, int64_t cap,
                           int64_t* needed, int32_t* sten_cnt,

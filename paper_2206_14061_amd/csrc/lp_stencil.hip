@@ -1083,7 +1083,7 @@ lp_status tile_map_build(lp_ctx* c, const int32_t* gate)
     return LP_OK;
 }
 
-lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed)
+lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed, int part)
 {
     Work& w = c->w;
     const int64_t n = c->n;
@@ -1094,7 +1094,7 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed)
     }
     View v = make_view(c, st);
     hipStream_t s = c->stream;
-    if (n > 0) {
+    if (n > 0 && part != STENCIL_TAIL) {
         // (the state copy or the re-sort of a step has packed them already)
         if (!packed)
             hipLaunchKernelGGL(k_pack_pos, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, st[0],
@@ -1124,6 +1124,8 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed)
             hipLaunchKernelGGL(k_select<false>, dim3(blocks_for(n)), dim3(BLOCK), 0, s, v,
                                w.hard, w.hard_n, force);
         prof_mark(c, 1, true);
+    }
+    if (n > 0 && part != STENCIL_HEAD) {
         prof_mark(c, 2, false);
         hipLaunchKernelGGL(k_select_sorted, dim3(HARD_BLOCKS), dim3(BLOCK), 0, s, v,
                            w.hard, w.hard_n, w.err, w.cnt);
@@ -1131,9 +1133,9 @@ lp_status stencils_build(lp_ctx* c, const double* const st[7], bool packed)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "stencil launch");
-    c->stencils_ok = true;
+    if (part != STENCIL_HEAD) c->stencils_ok = true;
     // k_mirror_count cleared the refit list and the displacement maximum
-    if (n > 0) c->redo_clear = c->disp_clear = true;
+    if (n > 0 && part != STENCIL_TAIL) c->redo_clear = c->disp_clear = true;
     return LP_OK;
 }
 
