@@ -483,10 +483,13 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
     // time (their list words, then their positions, all in flight
     // together); the buckets are stored four to a word (word k / 4 of all
     // lanes at once: coalesced).  Per octant only the lowest bucket is
-    // tracked (a byte each in mb_lo / mb_hi): it holds the octant's first.
+    // tracked: it holds the octant's first.  Those minima are LDS words
+    // of the thread's member column (unused until the keep pass), lowered
+    // with no-return atomic minima.
     int nc = 0, covered = 0;
     Mask4 cm;                          // candidate entries
-    uint32_t mb_lo = 0xFFFFFFFFu, mb_hi = 0xFFFFFFFFu;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) lkey[o][t] = 0xFFu;
     for (int k0 = 0; k0 < cnt; k0 += SEL_BATCH) {
         Pt pb[SEL_BATCH];
         select_gather<PERIODIC>(v, s, g, i, k0, cnt, pb);
@@ -512,13 +515,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
             covered |= (c && far) ? 1 << oct : 0;
             const int bi = bucket_of(d2, scale);
             const uint32_t b = (uint32_t)(bi < 0 ? 0 : bi);
-            const bool hiw = oct >= 4;
-            const uint32_t sh = 8u * (uint32_t)(oct & 3);
-            const uint32_t word = hiw ? mb_hi : mb_lo;
-            const uint32_t nw = (c && b < ((word >> sh) & 0xFFu))
-                                    ? (word & ~(0xFFu << sh)) | (b << sh) : word;
-            mb_hi = hiw ? nw : mb_hi;
-            mb_lo = hiw ? mb_lo : nw;
+            atomicMin(&lkey[oct][t], c ? b : 0xFFu);
             atomicAdd(&hist[b >> 2][t], (c ? 1u : 0u) << (8u * (b & 3u)));
             const uint32_t cs = 8u * (uint32_t)(u & 3);
             cw[u >> 2] = c ? (cw[u >> 2] & ~(0xFFu << cs)) | (b << cs) : cw[u >> 2];
@@ -539,9 +536,10 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
         write_rec(v, i, nc, gm, MODE_ALL, cm);
         return;
     }
-    auto minb = [&](int o) -> uint32_t {
-        return ((o < 4 ? mb_lo : mb_hi) >> (8 * (o & 3))) & 0xFFu;
-    };
+    uint32_t mbv[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) mbv[o] = lkey[o][t];
+    auto minb = [&](int o) -> uint32_t { return mbv[o]; };
     int n_oct = 0;
 #pragma unroll
     for (int o = 0; o < 8; ++o)
