@@ -509,6 +509,81 @@ __global__ void k_disp_init(Summary* sum) { sum->disp = DISP_ZERO; }
 // block goes to the summary; 256 to 1,024 time alike, 2,048 slower)
 constexpr unsigned COPY_BLOCKS = 512u;
 
+// (displacement since the last build / skin)^2 of one particle; infinite
+// for non-finite positions, which force a rebuild
+__device__ __forceinline__ double disp_ratio(const GridInfo& g, double x, double y, double z,
+                                             double rx, double ry, double rz)
+{
+    const double dx = image_coord(x, rx, g.Lx, g.hLx) - rx;
+    const double dy = image_coord(y, ry, g.Ly, g.hLy) - ry;
+    const double dz = z - rz;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    double q = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
+    if (!(q == q)) q = INFINITY;
+    return q;
+}
+
+__device__ __forceinline__ void disp_block_max(double r, double* part, Summary* sum)
+{
+    for (int d = 32; d > 0; d >>= 1) r = fmax(r, __shfl_xor(r, d));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLOCK / 64; ++w) r = fmax(r, part[w]);
+        atomicMax(&sum->disp, ord_enc(r));
+    }
+}
+
+// k_copy_disp on pairs of particles: 16-byte loads and stores of every
+// array (all 16-byte aligned), half the memory instructions; an odd last
+// particle is taken by one thread.
+__global__ __launch_bounds__(BLOCK) void k_copy_disp2(int64_t n, int n_sys,
+                                                      const int64_t* off,
+                                                      const GridInfo* grid, State7 st,
+                                                      Dest7 dst, const double* rx,
+                                                      const double* ry, const double* rz,
+                                                      double* p4, Summary* sum)
+{
+    __shared__ double part[BLOCK / 64];
+    double r = 0.0;
+    const int64_t np = n >> 1;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = 2 * j;
+        double2 f[7];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) f[a] = reinterpret_cast<const double2*>(st.a[a])[j];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) reinterpret_cast<double2*>(dst.a[a])[j] = f[a];
+        double2* rec = reinterpret_cast<double2*>(p4 + 4 * i);
+        rec[0] = make_double2(f[0].x, f[1].x);
+        rec[1] = make_double2(f[2].x, 0.0);
+        rec[2] = make_double2(f[0].y, f[1].y);
+        rec[3] = make_double2(f[2].y, 0.0);
+        const double2 qx = reinterpret_cast<const double2*>(rx)[j];
+        const double2 qy = reinterpret_cast<const double2*>(ry)[j];
+        const double2 qz = reinterpret_cast<const double2*>(rz)[j];
+        r = fmax(r, disp_ratio(grid[sys_of(off, n_sys, i)], f[0].x, f[1].x, f[2].x, qx.x,
+                               qy.x, qz.x));
+        r = fmax(r, disp_ratio(grid[sys_of(off, n_sys, i + 1)], f[0].y, f[1].y, f[2].y,
+                               qx.y, qy.y, qz.y));
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t i = n - 1;
+        double f[7];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) f[a] = st.a[a][i];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) dst.a[a][i] = f[a];
+        double2* rec = reinterpret_cast<double2*>(p4 + 4 * i);
+        rec[0] = make_double2(f[0], f[1]);
+        rec[1] = make_double2(f[2], 0.0);
+        r = fmax(r, disp_ratio(grid[sys_of(off, n_sys, i)], f[0], f[1], f[2], rx[i], ry[i],
+                               rz[i]));
+    }
+    disp_block_max(r, part, sum);
+}
+
 // k_disp fused with the copy of the seven state arrays into the working
 // state (one pass over the state).
 // The positions also go to their 32-byte records (p4), which the
@@ -534,22 +609,10 @@ __global__ __launch_bounds__(BLOCK) void k_copy_disp(int64_t n, int n_sys,
         double2* rec = reinterpret_cast<double2*>(p4 + 4 * i);
         rec[0] = make_double2(f[0], f[1]);
         rec[1] = make_double2(f[2], 0.0);
-        const GridInfo& g = grid[sys_of(off, n_sys, i)];
-        const double dx = image_coord(f[0], rx[i], g.Lx, g.hLx) - rx[i];
-        const double dy = image_coord(f[1], ry[i], g.Ly, g.hLy) - ry[i];
-        const double dz = f[2] - rz[i];
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        double q = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
-        if (!(q == q)) q = INFINITY;   // non-finite positions force a rebuild
-        r = fmax(r, q);
+        r = fmax(r, disp_ratio(grid[sys_of(off, n_sys, i)], f[0], f[1], f[2], rx[i], ry[i],
+                               rz[i]));
     }
-    for (int d = 32; d > 0; d >>= 1) r = fmax(r, __shfl_xor(r, d));
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = r;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < BLOCK / 64; ++w) r = fmax(r, part[w]);
-        atomicMax(&sum->disp, ord_enc(r));
-    }
+    disp_block_max(r, part, sum);
 }
 
 inline unsigned int blocks_for(int64_t n, int per = BLOCK)
@@ -763,6 +826,32 @@ lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "state gather");
 }
 
+// The state copy with the displacement check (k_copy_disp, or its
+// paired form when every array is 16-byte aligned).
+static void launch_copy_disp(lp_ctx* c, const double* const st[7])
+{
+    Work& w = c->w;
+    const int64_t n = c->n;
+    State7 s7;
+    Dest7 d7;
+    bool al = (reinterpret_cast<uintptr_t>(w.p4) & 15u) == 0;
+    for (int a = 0; a < 7; ++a) {
+        s7.a[a] = st[a];
+        d7.a[a] = w.sst[a];
+        al = al && (reinterpret_cast<uintptr_t>(st[a]) & 15u) == 0 &&
+             (reinterpret_cast<uintptr_t>(w.sst[a]) & 15u) == 0;
+    }
+    for (int a = 0; a < 3; ++a) al = al && (reinterpret_cast<uintptr_t>(w.xref[a]) & 15u) == 0;
+    if (al)
+        hipLaunchKernelGGL(k_copy_disp2, dim3(std::min(blocks_for((n + 1) / 2), COPY_BLOCKS)),
+                           dim3(BLOCK), 0, c->stream, n, c->n_sys, w.off, w.grid, s7, d7,
+                           w.xref[0], w.xref[1], w.xref[2], w.p4, w.summary);
+    else
+        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), COPY_BLOCKS)), dim3(BLOCK),
+                           0, c->stream, n, c->n_sys, w.off, w.grid, s7, d7, w.xref[0],
+                           w.xref[1], w.xref[2], w.p4, w.summary);
+}
+
 lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool first)
 {
     Work& w = c->w;
@@ -770,19 +859,9 @@ lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool
     // k_decide leaves the maximum at zero for the next captured step
     if (first) hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
     c->disp_clear = false;
-    if (n > 0) {
-        // the state copied into the working state (in the current order)
-        // with the displacement check; a rebuild then overwrites it
-        State7 s7;
-        Dest7 d7;
-        for (int a = 0; a < 7; ++a) {
-            s7.a[a] = st[a];
-            d7.a[a] = w.sst[a];
-        }
-        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), COPY_BLOCKS)), dim3(BLOCK), 0,
-                           c->stream, n, c->n_sys, w.off, w.grid, s7, d7, w.xref[0],
-                           w.xref[1], w.xref[2], w.p4, w.summary);
-    }
+    // the state copied into the working state (in the current order) with
+    // the displacement check; a rebuild then overwrites it
+    if (n > 0) launch_copy_disp(c, st);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(1), 0, c->stream, w.summary, w.gate,
                        w.cnt, force, w.bbox, c->n_sys);
     hipError_t e = hipGetLastError();
@@ -812,16 +891,7 @@ lp_status list_check_start(lp_ctx* c, const double* const st[7], bool copy)
         hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
     c->disp_clear = false;
     if (n > 0 && copy) {
-        State7 s7;
-        Dest7 d7;
-        for (int a = 0; a < 7; ++a) {
-            s7.a[a] = st[a];
-            d7.a[a] = w.sst[a];
-        }
-        hipLaunchKernelGGL(k_copy_disp, dim3(std::min(blocks_for(n), COPY_BLOCKS)), dim3(BLOCK), 0,
-                           c->stream, n,
-                           c->n_sys, w.off, w.grid, s7, d7, w.xref[0], w.xref[1],
-                           w.xref[2], w.p4, w.summary);
+        launch_copy_disp(c, st);
     } else if (n > 0) {
         hipLaunchKernelGGL(k_disp, dim3(std::min(blocks_for(n), 1024u)), dim3(BLOCK), 0,
                            c->stream, n,

@@ -149,6 +149,34 @@ def test_mirror_numbering_paths_agree_on_the_full_column(lp):
         assert np.array_equal(np.asarray(got[0][k]), np.asarray(got[1][k])), k
 
 
+def test_steps_on_unaligned_state_arrays(lp):
+    """State arrays that start 8 bytes past a 16-byte boundary take the
+    one-particle form of the state copy; the trajectory equals the one on
+    aligned arrays bit for bit (odd particle count: the paired form's last
+    particle too)."""
+    import torch
+    wl = CASES["column16_flow_ragged"]()
+    assert wl.n % 2 == 1
+    got = []
+    for shift in (0, 1):
+        arrs = []
+        for a in wl.state.arrays():
+            buf = torch.empty(wl.n + 1, dtype=torch.float64, device="cuda")
+            t = buf[shift:shift + wl.n]
+            t.copy_(torch.as_tensor(a))
+            arrs.append(t)
+        assert all((t.data_ptr() % 16 == 8) == (shift == 1) for t in arrs)
+        ctx = lp.make_context(wl)
+        st = lp.DeviceState(arrs)
+        for _ in range(3):
+            ctx.lp_step(st, wl.dt)
+        ctx.sync_status()
+        _log("shift %d stats %s" % (shift, ctx.stats()))
+        got.append(st.to_host())
+    for a, b in zip(got[0].arrays(), got[1].arrays()):
+        assert np.array_equal(a, b)
+
+
 def _fields(st):
     x, y, z = st.x, st.y, st.z
     return np.stack([np.sin(3.0 * x + 1.0) * np.cos(2.0 * y) + z * z,
