@@ -182,40 +182,55 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum,
     return pre + inc - v;
 }
 
-__device__ __forceinline__ bool wall_flag(const int64_t* off, int n_sys,
-                                          const GridInfo* grid, const double* z,
-                                          int64_t i)
+// Wall flags of the SORT_ITEMS chunks of 64 particles from wb on (chunk q:
+// particles wb + 64 q + lane, false past n) as wave masks, bit l for
+// particle wb + 64 q + l; all heights are loaded before any test.  s_tile:
+// the system of the whole tile, or -1 when the tile spans several.
+__device__ __forceinline__ void wall_masks(int64_t n, int n_sys, const int64_t* off,
+                                           const GridInfo* grid, const double* z, int64_t wb,
+                                           int s_tile, uint64_t (&m)[SORT_ITEMS])
 {
-    const GridInfo& g = grid[sys_of(off, n_sys, i)];
-    return dsub(z[i], g.wall) < g.R;
+    const int lane = threadIdx.x & 63;
+    double zz[SORT_ITEMS];
+#pragma unroll
+    for (int q = 0; q < SORT_ITEMS; ++q) {
+        const int64_t i = wb + 64 * q + lane;
+        zz[q] = i < n ? z[i] : INFINITY;
+    }
+    if (s_tile >= 0) {
+        const double wall = grid[s_tile].wall, R = grid[s_tile].R;
+#pragma unroll
+        for (int q = 0; q < SORT_ITEMS; ++q) m[q] = __ballot(dsub(zz[q], wall) < R);
+    } else {
+#pragma unroll
+        for (int q = 0; q < SORT_ITEMS; ++q) {
+            const int64_t i = wb + 64 * q + lane;
+            bool f = false;
+            if (i < n) {
+                const GridInfo& g = grid[sys_of(off, n_sys, i)];
+                f = dsub(zz[q], g.wall) < g.R;
+            }
+            m[q] = __ballot(f);
+        }
+    }
 }
 
-// Wall flags of the SORT_ITEMS particles b, b + 1, ... of one thread (0
-// past n), loaded together; the system is looked up once when all of them
-// share one.
-__device__ __forceinline__ uint32_t wall_flags(int64_t n, int n_sys, const int64_t* off,
-                                               const GridInfo* grid, const double* z,
-                                               int64_t b)
+// The system holding every particle of tile `tile`, or -1.
+__device__ __forceinline__ int tile_system(int64_t n, int n_sys, const int64_t* off,
+                                           int64_t tile)
 {
-    static_assert(SORT_ITEMS <= 32, "one flag bit per item");
-    const int64_t last = b + SORT_ITEMS - 1 < n ? b + SORT_ITEMS - 1 : n - 1;
-    uint32_t bits = 0;
-    if (b >= n) return 0;
-    const int s0 = sys_of(off, n_sys, b);
-    if (s0 == sys_of(off, n_sys, last)) {
-        const double wall = grid[s0].wall, R = grid[s0].R;
-        double zz[SORT_ITEMS];
-#pragma unroll
-        for (int r = 0; r < SORT_ITEMS; ++r) zz[r] = b + r < n ? z[b + r] : INFINITY;
-#pragma unroll
-        for (int r = 0; r < SORT_ITEMS; ++r)
-            bits |= (dsub(zz[r], wall) < R ? 1u : 0u) << r;
-    } else {
-        for (int r = 0; r < SORT_ITEMS; ++r)
-            if (b + r < n && wall_flag(off, n_sys, grid, z, b + r)) bits |= 1u << r;
-    }
-    return bits;
+    const int64_t t0 = tile * SORT_TILE;
+    const int64_t t1 = t0 + SORT_TILE - 1 < n ? t0 + SORT_TILE - 1 : n - 1;
+    const int s0 = sys_of(off, n_sys, t0);
+    return s0 == sys_of(off, n_sys, t1) ? s0 : -1;
 }
+
+// Mirrors are counted and numbered a tile of SORT_TILE particles per block:
+// wave w takes the SORT_ITEMS chunks of 64 consecutive particles from
+// t0 + 64 SORT_ITEMS w on, one particle per lane (coalesced loads of z),
+// with the wall flags of a chunk as one ballot mask.
+constexpr int MIRROR_WAVES = BLOCK / 64;
+static_assert(SORT_TILE == MIRROR_WAVES * 64 * SORT_ITEMS, "a tile per block");
 
 // Also clears the step's counters: the selection's list of particles for
 // the sorted path, the fits' refit list and the displacement maximum of
@@ -225,17 +240,28 @@ __global__ void k_mirror_count(int64_t n, int n_sys, const int64_t* off,
                                int32_t* bsum, unsigned int* hard_n,
                                unsigned int* redo_n, Summary* sum)
 {
-    __shared__ uint32_t wsum[BLOCK / 64];
+    __shared__ uint32_t wsum[MIRROR_WAVES];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *hard_n = 0u;
         *redo_n = 0u;
         sum->disp = DISP_ZERO;
     }
-    const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
-    const uint32_t c = __popc(wall_flags(n, n_sys, off, grid, z, b));
-    uint32_t tot;
-    block_excl_scan(c, wsum, tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = (int32_t)tot;
+    const int w = threadIdx.x >> 6;
+    const int s_tile = tile_system(n, n_sys, off, blockIdx.x);
+    const int64_t wb = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * 64 * SORT_ITEMS;
+    uint64_t m[SORT_ITEMS];
+    wall_masks(n, n_sys, off, grid, z, wb, s_tile, m);
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < SORT_ITEMS; ++q) c += (uint32_t)__popcll(m[q]);
+    if ((threadIdx.x & 63) == 0) wsum[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int q = 0; q < MIRROR_WAVES; ++q) tot += wsum[q];
+        bsum[blockIdx.x] = (int32_t)tot;
+    }
 }
 
 // Exclusive scan in place of a uint32 array (single block of 1024); the
@@ -268,16 +294,15 @@ __global__ void k_scan_total(uint32_t* a, int64_t cnt, int64_t* total)
 
 // bsum holds the blocks' exclusive offsets (scanned) or their counts; with
 // counts (few blocks) each block sums those of the blocks before it and the
-// last block writes the total.
+// last block writes the total.  Mirror ids follow the source order.
 __global__ void k_mirror_write(int64_t n, int n_sys, const int64_t* off,
                                const GridInfo* grid, const int32_t* bsum,
                                int scanned, int64_t* total, const double* z,
                                int32_t* mirror_of, int32_t* msrc)
 {
-    __shared__ uint32_t wsum[BLOCK / 64];
-    __shared__ uint32_t bpre[BLOCK / 64];
-    const int64_t b = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * SORT_ITEMS;
-    const uint32_t bits = wall_flags(n, n_sys, off, grid, z, b);
+    __shared__ uint32_t wsum[MIRROR_WAVES];
+    __shared__ uint32_t bpre[MIRROR_WAVES];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t base;
     if (scanned) {
         base = (uint32_t)bsum[blockIdx.x];
@@ -285,27 +310,40 @@ __global__ void k_mirror_write(int64_t n, int n_sys, const int64_t* off,
         uint32_t p = 0;
         for (int q = threadIdx.x; q < (int)blockIdx.x; q += BLOCK) p += (uint32_t)bsum[q];
         for (int d = 32; d > 0; d >>= 1) p += __shfl_xor(p, d);
-        if ((threadIdx.x & 63) == 0) bpre[threadIdx.x >> 6] = p;
+        if (lane == 0) bpre[w] = p;
         __syncthreads();
         base = 0;
 #pragma unroll
-        for (int w = 0; w < BLOCK / 64; ++w) base += bpre[w];
+        for (int q = 0; q < MIRROR_WAVES; ++q) base += bpre[q];
     }
-    uint32_t tot;
-    uint32_t k = block_excl_scan(__popc(bits), wsum, tot) + base;
+    const int s_tile = tile_system(n, n_sys, off, blockIdx.x);
+    const int64_t wb = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * 64 * SORT_ITEMS;
+    uint64_t m[SORT_ITEMS];
+    wall_masks(n, n_sys, off, grid, z, wb, s_tile, m);
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < SORT_ITEMS; ++q) c += (uint32_t)__popcll(m[q]);
+    if (lane == 0) wsum[w] = c;
+    __syncthreads();
+    uint32_t k = base, tot = 0;
+#pragma unroll
+    for (int q = 0; q < MIRROR_WAVES; ++q) {
+        k += q < w ? wsum[q] : 0u;
+        tot += wsum[q];
+    }
     if (!scanned && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
         *total = (int64_t)(base + tot);
+    const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        const int64_t i = b + r;
-        if (i >= n) break;
-        if ((bits >> r) & 1u) {
-            mirror_of[i] = (int32_t)k;
-            msrc[k] = (int32_t)i;
-            ++k;
-        } else {
-            mirror_of[i] = -1;
+    for (int q = 0; q < SORT_ITEMS; ++q) {
+        const int64_t i = wb + 64 * q + lane;
+        if (i < n) {
+            const bool f = (m[q] >> lane) & 1ull;
+            const uint32_t kk = k + (uint32_t)__popcll(m[q] & below);
+            mirror_of[i] = f ? (int32_t)kk : -1;
+            if (f) msrc[kk] = (int32_t)i;
         }
+        k += (uint32_t)__popcll(m[q]);
     }
 }
 
