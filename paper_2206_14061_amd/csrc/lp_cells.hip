@@ -550,9 +550,14 @@ __global__ __launch_bounds__(BLOCK) void k_copy_disp2(int64_t n, int n_sys,
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np;
          j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = 2 * j;
+        // every load before the first store (the compiler cannot move
+        // loads above stores to arrays that might alias them)
         double2 f[7];
 #pragma unroll
         for (int a = 0; a < 7; ++a) f[a] = reinterpret_cast<const double2*>(st.a[a])[j];
+        const double2 qx = reinterpret_cast<const double2*>(rx)[j];
+        const double2 qy = reinterpret_cast<const double2*>(ry)[j];
+        const double2 qz = reinterpret_cast<const double2*>(rz)[j];
 #pragma unroll
         for (int a = 0; a < 7; ++a) reinterpret_cast<double2*>(dst.a[a])[j] = f[a];
         double2* rec = reinterpret_cast<double2*>(p4 + 4 * i);
@@ -560,9 +565,6 @@ __global__ __launch_bounds__(BLOCK) void k_copy_disp2(int64_t n, int n_sys,
         rec[1] = make_double2(f[2].x, 0.0);
         rec[2] = make_double2(f[0].y, f[1].y);
         rec[3] = make_double2(f[2].y, 0.0);
-        const double2 qx = reinterpret_cast<const double2*>(rx)[j];
-        const double2 qy = reinterpret_cast<const double2*>(ry)[j];
-        const double2 qz = reinterpret_cast<const double2*>(rz)[j];
         r = fmax(r, disp_ratio(grid[sys_of(off, n_sys, i)], f[0].x, f[1].x, f[2].x, qx.x,
                                qy.x, qz.x));
         r = fmax(r, disp_ratio(grid[sys_of(off, n_sys, i + 1)], f[0].y, f[1].y, f[2].y,
