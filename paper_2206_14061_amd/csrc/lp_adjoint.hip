@@ -134,32 +134,31 @@ __device__ __forceinline__ void row_xi_bar(const double (&A)[9], double ex, doub
     gz = A[2] + A[5] * ez + A[7] * ex + A[8] * ey;
 }
 
-// zeroes n values (any length)
-__global__ void k_zero_f64(int64_t n, double* a)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0.0;
-}
-
 // adds the contributions received in a pass to the accumulators: pass 2
-// (P, eta, V, x, y, z) or pass 1 (u, v, w, x, y, z)
+// (P, eta, V, x, y, z) or pass 1 (u, v, w, x, y, z).  After pass 2 the
+// receive buffers are cleared for pass 1.
 __global__ __launch_bounds__(BLOCK) void k_fold(int64_t n, AdjBufs B, int pass)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double* r = B.recv;
+    double* r = B.recv;
+    double v[NRECV];
+#pragma unroll
+    for (int f = 0; f < NRECV; ++f) v[f] = r[f * n + j];
     if (pass == 2) {
-        B.aP[j] += r[j];
-        B.aE[j] += r[n + j];
-        B.a[6][j] += r[2 * n + j];
+        B.aP[j] += v[0];
+        B.aE[j] += v[1];
+        B.a[6][j] += v[2];
+#pragma unroll
+        for (int f = 0; f < NRECV; ++f) r[f * n + j] = 0.0;
     } else {
-        B.a[3][j] += r[j];
-        B.a[4][j] += r[n + j];
-        B.a[5][j] += r[2 * n + j];
+        B.a[3][j] += v[0];
+        B.a[4][j] += v[1];
+        B.a[5][j] += v[2];
     }
-    B.a[0][j] += r[3 * n + j];
-    B.a[1][j] += r[4 * n + j];
-    B.a[2][j] += r[5 * n + j];
+    B.a[0][j] += v[3];
+    B.a[1][j] += v[4];
+    B.a[2][j] += v[5];
 }
 
 // N = nA A + nB B at particle i, component a (B optional)
@@ -187,6 +186,9 @@ __global__ void k_adj_init(int64_t n, AdjSeed S, AdjBufs B)
     B.a[6][i] = id[6];
     B.aP[i] = 0.0;
     B.aE[i] = 0.0;
+    // the receive buffers start empty for the reverse pass 2
+#pragma unroll
+    for (int f = 0; f < NRECV; ++f) B.recv[f * n + i] = 0.0;
 }
 
 // ---- reverse of the update, the RHS and the fit of P and eta -------------
@@ -750,14 +752,12 @@ lp_status step_adjoint(lp_ctx* c, const double* const st[7], const AdjSeed& seed
     B.recv = w.adj_recv;
     B.M = w.adj_M;
     const int mo = c->map_ok ? 1 : 0;
+    // (k_adj_init clears the receive buffers, the first fold clears them
+    // again for pass 1)
     hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, seed, B);
-    hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(NRECV * n)), dim3(BLOCK), 0, s,
-                       NRECV * n, w.adj_recv);
     hipLaunchKernelGGL(k_adj_pass2<ADJ_LPP>, dim3(blocks_for(n)), dim3(BLOCK * ADJ_LPP), 0, s,
                        v, seed, B, mo);
     hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B, 2);
-    hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(NRECV * n)), dim3(BLOCK), 0, s,
-                       NRECV * n, w.adj_recv);
     hipLaunchKernelGGL(k_adj_pass1<ADJ_LPP>, dim3(blocks_for(n)), dim3(BLOCK * ADJ_LPP), 0, s,
                        v, B, mo);
     hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B, 1);

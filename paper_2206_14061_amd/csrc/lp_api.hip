@@ -177,7 +177,7 @@ lp_status adjoint_order(lp_ctx* c, double* const in[7], const lp_step_record* re
         return state_gather(c, cin, rec->perm);
     }
     *order = nullptr;
-    return state_copy(c, in, nullptr, nullptr, true);
+    return state_gather(c, cin, nullptr);
 }
 
 // One step with no host synchronisation: device-side rebuild decision,
@@ -777,7 +777,8 @@ lp_status lp_step_adjoint(lp_ctx* c, const lp_state* s, double dt,
     r = adjoint_order(c, in, rec, &order);
     const double* sorted[7];
     for (int a = 0; a < 7; ++a) sorted[a] = c->w.sst[a];
-    if (r == LP_OK) r = stencils_build(c, sorted);
+    // (the working copy came with its positions' records)
+    if (r == LP_OK) r = stencils_build(c, sorted, true);
     if (r == LP_OK) r = step_pass1_coef(c, sorted);
     double* lam_in[7];
     double* out[7];
@@ -836,7 +837,7 @@ lp_status lp_step2_adjoint(lp_ctx* c, const lp_state* s, double dt,
     // stencils
     const int32_t* order = nullptr;
     r = adjoint_order(c, in, rec, &order);
-    if (r == LP_OK) r = stencils_build(c, sorted);
+    if (r == LP_OK) r = stencils_build(c, sorted, true);
     if (r == LP_OK) r = step_pass1_coef(c, sorted);
     if (r == LP_OK) r = step_pass2(c, sorted, 0.0, nullptr, w.acc, w.dVdt, true);
     if (r == LP_OK) r = heun_predictor(c, dt);

@@ -382,9 +382,10 @@ struct Dest7 {
     double* a[7];
 };
 
-// The state in sorted order (perm[new] = old); for a rebuild (rx not
-// null) the positions again as the reference of the next displacement
-// check, and the caller's particle ids (ids, optional) into ids_tmp.
+// The state in sorted order (perm[new] = old; perm null: the same order);
+// for a rebuild (rx not null) the positions again as the reference of the
+// next displacement check; the positions' 32-byte records (p4, optional);
+// and the caller's particle ids (ids, optional) into ids_tmp.
 __global__ void k_gather7(int64_t n, const int32_t* perm, State7 in, Dest7 out,
                           double* rx, double* ry, double* rz, double* p4,
                           const int32_t* ids, int32_t* ids_tmp, const int32_t* gate)
@@ -392,7 +393,7 @@ __global__ void k_gather7(int64_t n, const int32_t* perm, State7 in, Dest7 out,
     LP_GATE(gate);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t j = perm[i];
+    const int64_t j = perm ? perm[i] : i;
     double v[7];
 #pragma unroll
     for (int a = 0; a < 7; ++a) v[a] = in.a[a][j];
@@ -402,7 +403,9 @@ __global__ void k_gather7(int64_t n, const int32_t* perm, State7 in, Dest7 out,
         rx[i] = v[0];
         ry[i] = v[1];
         rz[i] = v[2];
-        // the positions' records, which the list build reads
+    }
+    if (p4) {
+        // the positions' records, which the list build and the selection read
         double2* r = reinterpret_cast<double2*>(p4 + 4 * i);
         r[0] = make_double2(v[0], v[1]);
         r[1] = make_double2(v[2], 0.0);
@@ -821,7 +824,7 @@ lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm
             d7.a[a] = w.sst[a];
         }
         hipLaunchKernelGGL(k_gather7, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n,
-                           perm, s7, d7, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           perm, s7, d7, nullptr, nullptr, nullptr, w.p4, nullptr,
                            nullptr, nullptr);
     }
     hipError_t e = hipGetLastError();

@@ -476,7 +476,8 @@ lp_status cells_build_device(lp_ctx* c, double* const st[7], int32_t* ids,
                              const int32_t* gate, int bits);
 // ids[i] = ids[perm[i]]
 lp_status permute_ids(lp_ctx* c, const int32_t* perm, int32_t* ids);
-// working copy of st in the order perm (sst[new] = st[perm[new]])
+// working copy of st in the order perm (sst[new] = st[perm[new]]; perm
+// null: the same order) with its positions' 32-byte records
 lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm);
 // Device-side rebuild decision into w.gate (no synchronisation).
 lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool first);
