@@ -134,10 +134,9 @@ __device__ __forceinline__ void row_xi_bar(const double (&A)[9], double ex, doub
     gz = A[2] + A[5] * ez + A[7] * ex + A[8] * ey;
 }
 
-// adds the contributions received in a pass to the accumulators: pass 2
-// (P, eta, V, x, y, z) or pass 1 (u, v, w, x, y, z).  After pass 2 the
-// receive buffers are cleared for pass 1.
-__global__ __launch_bounds__(BLOCK) void k_fold(int64_t n, AdjBufs B, int pass)
+// adds the contributions received in pass 2 (P, eta, V, x, y, z) to the
+// accumulators and clears the receive buffers for pass 1
+__global__ __launch_bounds__(BLOCK) void k_fold2(int64_t n, AdjBufs B)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -145,20 +144,14 @@ __global__ __launch_bounds__(BLOCK) void k_fold(int64_t n, AdjBufs B, int pass)
     double v[NRECV];
 #pragma unroll
     for (int f = 0; f < NRECV; ++f) v[f] = r[f * n + j];
-    if (pass == 2) {
-        B.aP[j] += v[0];
-        B.aE[j] += v[1];
-        B.a[6][j] += v[2];
-#pragma unroll
-        for (int f = 0; f < NRECV; ++f) r[f * n + j] = 0.0;
-    } else {
-        B.a[3][j] += v[0];
-        B.a[4][j] += v[1];
-        B.a[5][j] += v[2];
-    }
+    B.aP[j] += v[0];
+    B.aE[j] += v[1];
+    B.a[6][j] += v[2];
     B.a[0][j] += v[3];
     B.a[1][j] += v[4];
     B.a[2][j] += v[5];
+#pragma unroll
+    for (int f = 0; f < NRECV; ++f) r[f * n + j] = 0.0;
 }
 
 // N = nA A + nB B at particle i, component a (B optional)
@@ -713,14 +706,26 @@ __global__ __launch_bounds__(BLOCK * LPP, 1) void k_adj_pass1(View v, AdjBufs B,
     }
 }
 
-// adj_in[perm[j]] = acc[j] (perm null: adj_in[j] = acc[j])
-__global__ void k_adj_unpermute(int64_t n, const int32_t* perm, AdjBufs B, Ptr7 out)
+// The fold of pass 1 (u, v, w, x, y, z received) written straight to the
+// caller's order: adj_in[perm[j]] = acc[j] + received[j] (perm null:
+// adj_in[j]).
+__global__ void k_fold_unpermute(int64_t n, const int32_t* perm, AdjBufs B, Ptr7 out)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int64_t o = perm ? perm[j] : j;
+    const double* r = B.recv;
+    double v[7];
 #pragma unroll
-    for (int a = 0; a < 7; ++a) const_cast<double*>(out.p[a])[o] = B.a[a][j];
+    for (int a = 0; a < 7; ++a) v[a] = B.a[a][j];
+    v[3] += r[j];
+    v[4] += r[n + j];
+    v[5] += r[2 * n + j];
+    v[0] += r[3 * n + j];
+    v[1] += r[4 * n + j];
+    v[2] += r[5 * n + j];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) const_cast<double*>(out.p[a])[o] = v[a];
 }
 
 }  // namespace
@@ -752,16 +757,15 @@ lp_status step_adjoint(lp_ctx* c, const double* const st[7], const AdjSeed& seed
     B.recv = w.adj_recv;
     B.M = w.adj_M;
     const int mo = c->map_ok ? 1 : 0;
-    // (k_adj_init clears the receive buffers, the first fold clears them
-    // again for pass 1)
+    // (k_adj_init clears the receive buffers, the fold of pass 2 clears
+    // them again for pass 1, whose fold writes the result)
     hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, seed, B);
     hipLaunchKernelGGL(k_adj_pass2<ADJ_LPP>, dim3(blocks_for(n)), dim3(BLOCK * ADJ_LPP), 0, s,
                        v, seed, B, mo);
-    hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B, 2);
+    hipLaunchKernelGGL(k_fold2, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B);
     hipLaunchKernelGGL(k_adj_pass1<ADJ_LPP>, dim3(blocks_for(n)), dim3(BLOCK * ADJ_LPP), 0, s,
                        v, B, mo);
-    hipLaunchKernelGGL(k_fold, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, B, 1);
-    hipLaunchKernelGGL(k_adj_unpermute, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, perm, B,
+    hipLaunchKernelGGL(k_fold_unpermute, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, perm, B,
                        dout);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
