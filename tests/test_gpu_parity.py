@@ -177,6 +177,39 @@ def test_steps_on_unaligned_state_arrays(lp):
         assert np.array_equal(a, b)
 
 
+def test_other_entry_points_between_steps_leave_the_step_unchanged(lp):
+    """Stencils, fits of other fields and a rheology RHS between two steps
+    (with many refits: cond_max = 3) leave the second step as it is without
+    them, bit for bit and with the same refit count: the counters a step
+    relies on (refit list, sorted-path list, displacement maximum) start
+    from zero whatever ran before."""
+    import torch
+    wl = CASES["column16_flow_ragged"]()
+    got = []
+    for extra in (False, True):
+        ctx = lp.make_context(wl, cond_max=3.0)
+        st = lp.DeviceState.from_host(wl.state)
+        ctx.lp_step(st, wl.dt)
+        ctx.lp_build_cells(st, want_perm=False)
+        if extra:
+            ctx.lp_neighbors(st)
+            F = torch.stack([st.t[3], st.t[4], st.t[5]])
+            coef, _ = ctx.lp_fit_derivs(st, F, [1, 1, -1], [0, 0, 0])
+            ctx.lp_rheology_rhs(st, coef)
+        ctx.sync_status()
+        before = ctx.stats()
+        for _ in range(2):
+            ctx.lp_step(st, wl.dt)
+        ctx.sync_status()
+        after = ctx.stats()
+        _log("extra %s stats before %s after %s" % (extra, before, after))
+        got.append((st.to_host(), after["qr_refits"], after["rebuilds"]))
+    assert got[0][1] > 0
+    assert got[0][1:] == got[1][1:]
+    for a, b in zip(got[0][0].arrays(), got[1][0].arrays()):
+        assert np.array_equal(a, b)
+
+
 def _fields(st):
     x, y, z = st.x, st.y, st.z
     return np.stack([np.sin(3.0 * x + 1.0) * np.cos(2.0 * y) + z * z,
