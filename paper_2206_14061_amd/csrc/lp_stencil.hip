@@ -66,7 +66,9 @@ __device__ __forceinline__ void cell_clamp(const GridInfo& g, double x, double y
 constexpr int LIST_BATCH = 8;
 
 // The candidates' positions come from their 32-byte records (x, y, z, 0),
-// which the rebuild's gather writes: two loads per candidate.
+// which the rebuild's gather writes: two loads per candidate.  Nearest
+// images are taken only where some system is periodic (PERIODIC).
+template <bool PERIODIC>
 __global__ __launch_bounds__(BLOCK) void k_list_build(
     int64_t n, int n_sys, const int64_t* __restrict__ off,
     const GridInfo* __restrict__ grid, const double* __restrict__ x,
@@ -135,8 +137,10 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
                     for (int u = 0; u < LIST_BATCH; ++u) {
                         const int32_t j = jb[u];
                         if (t0 + u >= tot || (!mirror && j == (int32_t)i)) continue;
-                        const double dx = image_coord(qxs[u], qx, g.Lx, g.hLx) - qx;
-                        const double dy = image_coord(qys[u], qy, g.Ly, g.hLy) - qy;
+                        const double dx =
+                            (PERIODIC ? image_coord(qxs[u], qx, g.Lx, g.hLx) : qxs[u]) - qx;
+                        const double dy =
+                            (PERIODIC ? image_coord(qys[u], qy, g.Ly, g.hLy) : qys[u]) - qy;
                         const double dz = qzs[u] - qz;
                         if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
                         if (mirror && !(qzs[u] - g.wall < g.Rv)) continue;
@@ -1087,8 +1091,12 @@ lp_status list_build(lp_ctx* c, const int32_t* gate)
     Work& w = c->w;
     const int64_t n = c->n;
     if (!gate) c->list_ok = false;
-    if (n > 0)
-        hipLaunchKernelGGL(k_list_build, dim3(blocks_for(n)), dim3(BLOCK), 0,
+    if (n > 0 && c->periodic)
+        hipLaunchKernelGGL(k_list_build<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                           c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
+                           w.sst[2], w.p4, w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
+    else if (n > 0)
+        hipLaunchKernelGGL(k_list_build<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
                            c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
                            w.sst[2], w.p4, w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
     hipError_t e = hipGetLastError();
