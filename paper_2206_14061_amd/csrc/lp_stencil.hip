@@ -85,6 +85,12 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
     const double Rv2 = g.Rv2 * (1.0 + 1e-12);
     const double xi = x[i], yi = y[i], zi = z[i];
     int cnt = 0;
+    // entry cnt goes to out[cnt % VCHUNK]; out moves to the next chunk of
+    // the particle (n VCHUNK entries on) whenever one fills
+    int32_t* out = vl + (int64_t)i * VCHUNK;
+    const int64_t cstride = n * VCHUNK;
+    // the records as a byte base with 32-bit offsets (j < 2^27)
+    const char* p4b = reinterpret_cast<const char*>(p4);
     // neighbouring cell d in {-1, 0, 1} of cell c along an axis of nc
     // cells: clipped on an open axis; wrapped on a periodic one, where
     // fewer than three cells are each visited once
@@ -127,7 +133,8 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
                         const int32_t j = t < len[0] ? b[0] + t
                                           : (t < l01 ? b[1] + (t - len[0]) : b[2] + (t - l01));
                         jb[u] = j;
-                        const double* r = p4 + 4 * (int64_t)j;
+                        const double* r =
+                            reinterpret_cast<const double*>(p4b + ((uint32_t)j << 5));
                         const double2 xy = *reinterpret_cast<const double2*>(r);
                         qxs[u] = xy.x;
                         qys[u] = xy.y;
@@ -144,8 +151,10 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
                         const double dz = qzs[u] - qz;
                         if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
                         if (mirror && !(qzs[u] - g.wall < g.Rv)) continue;
-                        if (cnt < VCAP)
-                            vl[vl_at(n, i, cnt)] = mirror ? (j | MBIT) : j;
+                        if (cnt < VCAP) {
+                            out[cnt & (VCHUNK - 1)] = mirror ? (j | MBIT) : j;
+                            if ((cnt & (VCHUNK - 1)) == VCHUNK - 1) out += cstride;
+                        }
                         ++cnt;
                     }
                 }
