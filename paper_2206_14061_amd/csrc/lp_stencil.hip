@@ -149,7 +149,10 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
                         const double dy =
                             (PERIODIC ? image_coord(qys[u], qy, g.Ly, g.hLy) : qys[u]) - qy;
                         const double dz = qzs[u] - qz;
-                        if (dx * dx + dy * dy + dz * dz >= Rv2) continue;
+                        // the list only has to hold every pair within the
+                        // list radius: fused products are fine here, their
+                        // rounding far inside Rv2's 1e-12 margin
+                        if (fma(dz, dz, fma(dy, dy, dx * dx)) >= Rv2) continue;
                         if (mirror && !(qzs[u] - g.wall < g.Rv)) continue;
                         if (cnt < VCAP) {
                             out[cnt & (VCHUNK - 1)] = mirror ? (j | MBIT) : j;
