@@ -35,7 +35,7 @@ __global__ void k_bbox_init(unsigned long long* bbox, int n_sys, const int32_t* 
     if (t < 6 * n_sys) bbox[t] = (t % 6) < 3 ? ~0ull : 0ull;
 }
 
-constexpr int BBOX_CHUNK = 32;
+constexpr int BBOX_CHUNK = 8;
 
 __device__ void bbox_flush(unsigned long long* bbox, int s, const double* lo,
                            const double* hi)
@@ -57,6 +57,56 @@ __global__ void k_bbox(int64_t n, int n_sys, const int64_t* off,
     // increasing indices, so the systems it meets come in order)
     const int64_t b = (int64_t)blockIdx.x * BLOCK * BBOX_CHUNK + threadIdx.x;
     const int lane = threadIdx.x & 63;
+    // a block inside one system (the common case): every load of a thread
+    // issued before its minima, then one flush per block
+    {
+        const int64_t b0 = (int64_t)blockIdx.x * BLOCK * BBOX_CHUNK;
+        const int64_t b1 = (b0 + BLOCK * BBOX_CHUNK < n ? b0 + BLOCK * BBOX_CHUNK : n) - 1;
+        const int s0 = sys_of(off, n_sys, b0);
+        if (s0 == sys_of(off, n_sys, b1)) {
+            __shared__ double part[6][BLOCK / 64];
+            double q[3][BBOX_CHUNK];
+#pragma unroll
+            for (int k = 0; k < BBOX_CHUNK; ++k) {
+                // past n: the first particle of the block again
+                const int64_t i = b + (int64_t)k * BLOCK < n ? b + (int64_t)k * BLOCK : b0;
+                q[0][k] = x[i];
+                q[1][k] = y[i];
+                q[2][k] = z[i];
+            }
+            double m[6];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                m[a] = m[3 + a] = q[a][0];
+#pragma unroll
+                for (int k = 1; k < BBOX_CHUNK; ++k) {
+                    m[a] = fmin(m[a], q[a][k]);
+                    m[3 + a] = fmax(m[3 + a], q[a][k]);
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    m[a] = fmin(m[a], __shfl_xor(m[a], o));
+                    m[3 + a] = fmax(m[3 + a], __shfl_xor(m[3 + a], o));
+                }
+            if (lane == 0)
+#pragma unroll
+                for (int a = 0; a < 6; ++a) part[a][threadIdx.x >> 6] = m[a];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int w = 1; w < BLOCK / 64; ++w)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        m[a] = fmin(m[a], part[a][w]);
+                        m[3 + a] = fmax(m[3 + a], part[3 + a][w]);
+                    }
+                bbox_flush(bbox, s0, m, m + 3);
+            }
+            return;
+        }
+    }
     int cur = -1;
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     if (b < n) {
