@@ -480,7 +480,7 @@ lp_status lp_rheology_rhs(lp_ctx* c, const lp_state* s, const double* coef_u,
 static lp_status check_ahead(lp_ctx* c, double* const in[7], const double* const sorted[7],
                              double limit, bool* rebuild, bool* ahead)
 {
-    lp_status r = list_check_start(c, in, true);
+    lp_status r = list_check_start(c, in);
     if (r != LP_OK) return r;
     *ahead = c->chk_pending && c->map_ok;
     if (*ahead) {

@@ -525,37 +525,6 @@ __global__ void k_iota(int64_t n, int32_t* p, const int32_t* gate)
     if (i < n) p[i] = (int32_t)i;
 }
 
-// Largest (displacement / (skin R))^2 since the list build.
-// Largest squared displacement since the list build, in units of
-// (skin R)^2; grid-stride, one atomic per block.
-__global__ __launch_bounds__(BLOCK) void k_disp(int64_t n, int n_sys, const int64_t* off,
-                                                const GridInfo* grid, const double* x,
-                                                const double* y, const double* z,
-                                                const double* rx, const double* ry,
-                                                const double* rz, Summary* sum)
-{
-    __shared__ double part[BLOCK / 64];
-    double r = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const GridInfo& g = grid[sys_of(off, n_sys, i)];
-        const double dx = image_coord(x[i], rx[i], g.Lx, g.hLx) - rx[i];
-        const double dy = image_coord(y[i], ry[i], g.Ly, g.hLy) - ry[i];
-        const double dz = z[i] - rz[i];
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        double q = g.inv_skin2 > 0.0 ? d2 * g.inv_skin2 : (d2 > 0.0 ? INFINITY : 0.0);
-        if (!(q == q)) q = INFINITY;   // non-finite positions force a rebuild
-        r = fmax(r, q);
-    }
-    for (int d = 32; d > 0; d >>= 1) r = fmax(r, __shfl_xor(r, d));
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = r;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < BLOCK / 64; ++w) r = fmax(r, part[w]);
-        atomicMax(&sum->disp, ord_enc(r));
-    }
-}
-
 __global__ void k_disp_init(Summary* sum) { sum->disp = DISP_ZERO; }
 
 // blocks of the state copy with the displacement check (one maximum per
@@ -935,7 +904,7 @@ lp_status state_write_back(lp_ctx* c, double* const out[7])
     return e == hipSuccess ? LP_OK : hip_fail(c, e, "state write-back");
 }
 
-lp_status list_check_start(lp_ctx* c, const double* const st[7], bool copy)
+lp_status list_check_start(lp_ctx* c, const double* const st[7])
 {
     Work& w = c->w;
     const int64_t n = c->n;
@@ -945,14 +914,7 @@ lp_status list_check_start(lp_ctx* c, const double* const st[7], bool copy)
     if (!c->disp_clear)
         hipLaunchKernelGGL(k_disp_init, dim3(1), dim3(1), 0, c->stream, w.summary);
     c->disp_clear = false;
-    if (n > 0 && copy) {
-        launch_copy_disp(c, st);
-    } else if (n > 0) {
-        hipLaunchKernelGGL(k_disp, dim3(std::min(blocks_for(n), 1024u)), dim3(BLOCK), 0,
-                           c->stream, n,
-                           c->n_sys, w.off, w.grid, st[0], st[1], st[2], w.xref[0],
-                           w.xref[1], w.xref[2], w.summary);
-    }
+    if (n > 0) launch_copy_disp(c, st);
     hipError_t e = hipSuccess;
     if (!c->chk_ev) e = hipEventCreateWithFlags(&c->chk_ev, hipEventDisableTiming);
     if (e == hipSuccess)
@@ -977,17 +939,6 @@ lp_status list_check_wait(lp_ctx* c, double* ratio)
     std::memcpy(&r, &b, sizeof(r));
     *ratio = r;
     return LP_OK;
-}
-
-lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
-                            bool copy)
-{
-    lp_status r = list_check_start(c, st, copy);
-    if (r != LP_OK) {
-        *ratio = -1.0;
-        return r;
-    }
-    return list_check_wait(c, ratio);
 }
 
 }  // namespace lp

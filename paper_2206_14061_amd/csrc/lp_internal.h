@@ -483,16 +483,12 @@ lp_status state_gather(lp_ctx* c, const double* const st[7], const int32_t* perm
 lp_status rebuild_decision(lp_ctx* c, const double* const st[7], int force, bool first);
 // Copies the working copy back into the caller's arrays.
 lp_status state_write_back(lp_ctx* c, double* const out[7]);
-// Largest displacement since the list build in units of the skin
-// (synchronises); returns a negative value when no list exists.  With
-// copy, the same pass also copies st into the working copy (as
-// state_copy does) when a list exists.
-lp_status list_displacement(lp_ctx* c, const double* const st[7], double* ratio,
-                            bool copy = false);
-// list_displacement in two halves: the check enqueued with its result
-// copied to the host, and the wait for that copy (the stream may run later
-// work meanwhile).  ratio < 0 when no list exists.
-lp_status list_check_start(lp_ctx* c, const double* const st[7], bool copy);
+// Largest displacement since the list build in units of the skin: the
+// check enqueued with the state copied into the working copy (the 32-byte
+// position records too), its result copied to the host behind an event,
+// and the wait for that copy (the stream may run later work meanwhile).
+// ratio < 0 when no list exists.
+lp_status list_check_start(lp_ctx* c, const double* const st[7]);
 lp_status list_check_wait(lp_ctx* c, double* ratio);
 // Mirror ids of the current state, stencil records.
 // packed: the positions' 32-byte records (p4) already hold st's positions
