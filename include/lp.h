@@ -56,10 +56,12 @@ enum { LP_W_UNIT = 0, LP_W_GAUSS = 1 };
  * neighbours staged in LDS, or dispatch the fits by stencil size class
  * (classes of at most 16, at most 32 and more rows; lanes per particle 1,
  * 4 and the staged tile kernel in the first fit, 4, 2 and 1 in the
- * second; results agree to rounding) */
+ * second; results agree to rounding), number mirrors through a separate
+ * scan of the tile counts, or build the neighbour list with a thread per
+ * particle instead of a wavefront per cell (the lists are identical) */
 enum { LP_DEBUG_SORTED_STENCIL = 1, LP_DEBUG_QR_FIT = 2, LP_DEBUG_LANES2 = 4,
        LP_DEBUG_LANES4 = 8, LP_DEBUG_GLOBAL_GATHER = 16, LP_DEBUG_CLASSES = 32,
-       LP_DEBUG_MIRROR_SCAN = 64 };
+       LP_DEBUG_MIRROR_SCAN = 64, LP_DEBUG_PARTICLE_LIST = 128 };
 
 /* Physical constants of one system (Sec. 2.2, 2.2.1 and Sec. 4).
  * rho_s: grain material density (the paper's phi_s); d: grain diameter;

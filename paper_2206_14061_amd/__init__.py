@@ -14,7 +14,7 @@ from typing import Dict, List, Optional, Sequence
 
 from . import _lib
 from ._lib import (LP_DEBUG_CLASSES, LP_DEBUG_GLOBAL_GATHER, LP_DEBUG_LANES2,
-                   LP_DEBUG_LANES4, LP_DEBUG_MIRROR_SCAN,
+                   LP_DEBUG_LANES4, LP_DEBUG_MIRROR_SCAN, LP_DEBUG_PARTICLE_LIST,
                    LP_DEBUG_QR_FIT, LP_DEBUG_SORTED_STENCIL, LP_FP32_REFINED,
                    LP_FP64, LP_W_GAUSS, LP_W_UNIT, LPConfig, LPError,
                    LPParams, LPState, LPStepRecord)

@@ -20,6 +20,7 @@ LP_DEBUG_SORTED_STENCIL, LP_DEBUG_QR_FIT = 1, 2
 LP_DEBUG_LANES2, LP_DEBUG_LANES4, LP_DEBUG_GLOBAL_GATHER = 4, 8, 16
 LP_DEBUG_CLASSES = 32
 LP_DEBUG_MIRROR_SCAN = 64
+LP_DEBUG_PARTICLE_LIST = 128
 
 STATUS_NAMES = {0: "LP_OK", 1: "LP_E_ARG", 2: "LP_E_CAPACITY",
                 3: "LP_E_NUMERIC", 4: "LP_E_HIP", 5: "LP_E_STATE"}

@@ -60,6 +60,24 @@ __device__ __forceinline__ void cell_clamp(const GridInfo& g, double x, double y
     cz = iz < 0 ? 0 : (iz >= g.nz ? g.nz - 1 : iz);
 }
 
+// Orders the LDS accesses of one wavefront's lanes (no block barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Neighbouring cell d in {-1, 0, 1} of cell c along an axis of nc cells:
+// clipped on an open axis; wrapped on a periodic one, where fewer than
+// three cells are each visited once.  -1: no cell.
+__device__ __forceinline__ int nb_cell(int c, int d, int nc, bool periodic)
+{
+    if (!periodic) return (c + d < 0 || c + d >= nc) ? -1 : c + d;
+    if (nc < 3 && (d == -1 || (nc == 1 && d == 1))) return -1;
+    return (c + d + nc) % nc;
+}
+
 // ---- neighbour-list build ---------------------------------------------
 
 // Candidates of the list build whose positions are loaded together.
@@ -91,14 +109,6 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
     const int64_t cstride = n * VCHUNK;
     // the records as a byte base with 32-bit offsets (j < 2^27)
     const char* p4b = reinterpret_cast<const char*>(p4);
-    // neighbouring cell d in {-1, 0, 1} of cell c along an axis of nc
-    // cells: clipped on an open axis; wrapped on a periodic one, where
-    // fewer than three cells are each visited once
-    auto nb_cell = [](int c, int d, int nc, bool periodic) {
-        if (!periodic) return (c + d < 0 || c + d >= nc) ? -1 : c + d;
-        if (nc < 3 && (d == -1 || (nc == 1 && d == 1))) return -1;
-        return (c + d + nc) % nc;
-    };
     const bool px = g.Lx > 0.0, py = g.Ly > 0.0;
     auto scan = [&](double qx, double qy, double qz, bool mirror) {
         int cx, cy, cz;
@@ -173,6 +183,193 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
         cnt = VCAP;
     }
     vcnt[i] = cnt;
+}
+
+// ---- neighbour-list build, a wavefront per cell ------------------------
+//
+// Every particle of a cell scans the same 27 cells, so one wavefront takes
+// a cell: each row's candidates are loaded once, one per lane (consecutive
+// 32-byte records), and tested against the cell's particles in turn; for
+// each particle the accepted lanes append their ids in lane order (a
+// ballot prefix count), which is the order the per-particle scan above
+// gives (rows in the same order, a row's three cells as one sequence, the
+// same test on the same values).  The lists are therefore identical.  A
+// particle's potential mirror sources (the cells of its reflection, which
+// differ between the particles of a cell) follow its real entries, one
+// particle at a time.  The cell's particles are taken 64 at a time; their
+// positions sit in LDS (read with one address by the whole wavefront) and
+// their running counts in lane q of `cntv`.
+constexpr int LC_WAVES = BLOCK / 64;   // cells per block and pass
+constexpr int LC_MAX_BLOCKS = 16384;   // grid-stride launches
+
+__device__ __forceinline__ int sys_of_cell(const GridInfo* grid, int n_sys, int64_t c)
+{
+    int lo = 0, hi = n_sys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (grid[mid].cell_base <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// entry pos of particle i, as vl_at places it; cst = n VCHUNK (< 2^30)
+__device__ __forceinline__ void vl_put(int32_t* vl, int32_t i, uint32_t cst, uint32_t pos,
+                                       int32_t e)
+{
+    vl[(uint64_t)(pos / VCHUNK) * cst + (uint64_t)(uint32_t)i * VCHUNK + pos % VCHUNK] = e;
+}
+
+template <bool PERIODIC>
+__global__ __launch_bounds__(BLOCK) void k_list_cells(
+    int64_t n, int n_sys, const GridInfo* __restrict__ grid,
+    const double* __restrict__ p4, const int32_t* __restrict__ cs,
+    const int32_t* __restrict__ ce, int64_t n_cells, const int64_t* __restrict__ n_cells_dev,
+    int32_t* __restrict__ vl, int32_t* __restrict__ vcnt, ErrWord* err,
+    const int32_t* gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ double4 ppos[LC_WAVES][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t tc = n_cells_dev ? *n_cells_dev : n_cells;
+    const int64_t groups = (tc + LC_WAVES - 1) / LC_WAVES;
+    const char* p4b = reinterpret_cast<const char*>(p4);
+    const uint32_t cst = (uint32_t)(n * VCHUNK);
+    for (int64_t grp = xcd_block(blockIdx.x, gridDim.x); grp < groups; grp += gridDim.x) {
+        const int64_t cell = grp * LC_WAVES + wv;
+        if (cell >= tc) break;
+        const int32_t cb = cs[cell], cend = ce[cell];
+        if (cend <= cb) continue;
+        const GridInfo& g = grid[sys_of_cell(grid, n_sys, cell)];
+        const int loc = (int)(cell - g.cell_base);
+        const int cx = loc % g.nx, cy = (loc / g.nx) % g.ny, cz = loc / (g.nx * g.ny);
+        const double Rv2 = g.Rv2 * (1.0 + 1e-12);
+        const bool px = g.Lx > 0.0, py = g.Ly > 0.0;
+        // the candidates of row (zz, yy) around cell x coordinate ccx,
+        // 64 at a time: lane t's candidate and its position (lanes past
+        // the row hold the cell's first particle and are not candidates)
+        auto row_ranges = [&](int zz, int yy, int ccx, int32_t (&b)[3], int32_t (&len)[3]) {
+            const int64_t row = g.cell_base + (int64_t)g.nx * (yy + (int64_t)g.ny * zz);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int xx = nb_cell(ccx, q - 1, g.nx, px);
+                const int64_t c = row + (xx < 0 ? 0 : xx);
+                const int32_t a = cs[c], e = ce[c];
+                b[q] = a;
+                len[q] = xx < 0 ? 0 : e - a;
+            }
+        };
+        auto load_cand = [&](const int32_t (&b)[3], const int32_t (&len)[3], int t,
+                             int tot, int32_t& j, double& qx, double& qy, double& qz) {
+            const int l01 = len[0] + len[1];
+            j = t < len[0] ? b[0] + t : (t < l01 ? b[1] + (t - len[0]) : b[2] + (t - l01));
+            j = t < tot ? j : cb;
+            const double* r = reinterpret_cast<const double*>(p4b + ((uint32_t)j << 5));
+            const double2 xy = *reinterpret_cast<const double2*>(r);
+            qx = xy.x;
+            qy = xy.y;
+            qz = r[2];
+        };
+        for (int32_t q0 = cb; q0 < cend; q0 += 64) {
+            const int nq = cend - q0 < 64 ? cend - q0 : 64;
+            const int32_t mi = q0 + lane;          // this lane's particle
+            if (lane < nq) {
+                const double2* r = reinterpret_cast<const double2*>(p4b + ((uint32_t)mi << 5));
+                const double2 a = r[0], c2 = r[1];
+                ppos[wv][lane] = make_double4(a.x, a.y, c2.x, 0.0);
+            }
+            wave_sync();
+            int cntv = 0;
+            // real candidates
+            for (int zz = cz - 1; zz <= cz + 1; ++zz) {
+                if (zz < 0 || zz >= g.nz) continue;
+                for (int dy0 = -1; dy0 <= 1; ++dy0) {
+                    const int yy = nb_cell(cy, dy0, g.ny, py);
+                    if (yy < 0) continue;
+                    int32_t b[3], len[3];
+                    row_ranges(zz, yy, cx, b, len);
+                    const int tot = len[0] + len[1] + len[2];
+                    for (int t0 = 0; t0 < tot; t0 += 64) {
+                        int32_t j;
+                        double qx, qy, qz;
+                        load_cand(b, len, t0 + lane, tot, j, qx, qy, qz);
+                        const bool in = t0 + lane < tot;
+                        for (int q = 0; q < nq; ++q) {
+                            const double4 pq = ppos[wv][q];
+                            const int32_t iq = q0 + q;
+                            const double dx =
+                                (PERIODIC ? image_coord(qx, pq.x, g.Lx, g.hLx) : qx) - pq.x;
+                            const double dy =
+                                (PERIODIC ? image_coord(qy, pq.y, g.Ly, g.hLy) : qy) - pq.y;
+                            const double dz = qz - pq.z;
+                            const bool acc = in && j != iq &&
+                                             !(fma(dz, dz, fma(dy, dy, dx * dx)) >= Rv2);
+                            const uint64_t m = __ballot(acc);
+                            if (m) {
+                                const int c0 = __builtin_amdgcn_readlane(cntv, q);
+                                const uint32_t pos = (uint32_t)c0 + __builtin_amdgcn_mbcnt_hi(
+                                                         (uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                if (acc && pos < (uint32_t)VCAP)
+                                    vl_put(vl, iq, cst, pos, j);
+                                cntv = lane == q ? c0 + __popcll(m) : cntv;
+                            }
+                        }
+                    }
+                }
+            }
+            // potential mirrors of each particle near the wall: reals near
+            // the wall that lie near its reflection
+            for (int q = 0; q < nq; ++q) {
+                const double4 pq = ppos[wv][q];
+                if (!(pq.z - g.wall < g.Rv)) continue;
+                const int32_t iq = q0 + q;
+                const double zm = dsub(dmul(2.0, g.wall), pq.z);
+                int mx, my, mz;
+                cell_clamp(g, pq.x, pq.y, zm, mx, my, mz);
+                int c = __builtin_amdgcn_readlane(cntv, q);
+                for (int zz = mz - 1; zz <= mz + 1; ++zz) {
+                    if (zz < 0 || zz >= g.nz) continue;
+                    for (int dy0 = -1; dy0 <= 1; ++dy0) {
+                        const int yy = nb_cell(my, dy0, g.ny, py);
+                        if (yy < 0) continue;
+                        int32_t b[3], len[3];
+                        row_ranges(zz, yy, mx, b, len);
+                        const int tot = len[0] + len[1] + len[2];
+                        for (int t0 = 0; t0 < tot; t0 += 64) {
+                            int32_t j;
+                            double qx, qy, qz;
+                            load_cand(b, len, t0 + lane, tot, j, qx, qy, qz);
+                            const double dx =
+                                (PERIODIC ? image_coord(qx, pq.x, g.Lx, g.hLx) : qx) - pq.x;
+                            const double dy =
+                                (PERIODIC ? image_coord(qy, pq.y, g.Ly, g.hLy) : qy) - pq.y;
+                            const double dz = qz - zm;
+                            const bool acc = t0 + lane < tot &&
+                                             !(fma(dz, dz, fma(dy, dy, dx * dx)) >= Rv2) &&
+                                             qz - g.wall < g.Rv;
+                            const uint64_t m = __ballot(acc);
+                            const uint32_t pos = (uint32_t)c + __builtin_amdgcn_mbcnt_hi(
+                                                         (uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                            if (acc && pos < (uint32_t)VCAP) vl_put(vl, iq, cst, pos, j | MBIT);
+                            c += __popcll(m);
+                        }
+                    }
+                }
+                cntv = lane == q ? c : cntv;
+            }
+            if (lane < nq) {
+                if (cntv > VCAP) {
+                    raise_error(err, ERR_CAPACITY, mi);
+                    cntv = VCAP;
+                }
+                vcnt[mi] = cntv;
+            }
+            // the next chunk's positions overwrite these
+            wave_sync();
+        }
+    }
 }
 
 // ---- mirrors of the current state --------------------------------------
@@ -740,13 +937,6 @@ __global__ __launch_bounds__(BLOCK) void k_select(View v, int32_t* hard,
 // into LDS, each is ranked by key (r^2, id) against all others, and the
 // stencil rule is applied directly (octant-firsts in octant order, then
 // the others in key order, m_max in all).
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
 __global__ __launch_bounds__(BLOCK) void k_select_sorted(
     View v, const int32_t* hard, const unsigned int* hard_n, ErrWord* err,
     Counters* cnt)
@@ -1103,14 +1293,34 @@ lp_status list_build(lp_ctx* c, const int32_t* gate)
     Work& w = c->w;
     const int64_t n = c->n;
     if (!gate) c->list_ok = false;
-    if (n > 0 && c->periodic)
-        hipLaunchKernelGGL(k_list_build<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                           c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
-                           w.sst[2], w.p4, w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
-    else if (n > 0)
-        hipLaunchKernelGGL(k_list_build<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
-                           c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
-                           w.sst[2], w.p4, w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
+    if (n > 0 && (c->cfg.debug_flags & LP_DEBUG_PARTICLE_LIST)) {
+        // the per-particle scan (same lists; kept to check the cell scan)
+        if (c->periodic)
+            hipLaunchKernelGGL(k_list_build<true>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
+                               w.sst[2], w.p4, w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
+        else
+            hipLaunchKernelGGL(k_list_build<false>, dim3(blocks_for(n)), dim3(BLOCK), 0,
+                               c->stream, n, c->n_sys, w.off, w.grid, w.sst[0], w.sst[1],
+                               w.sst[2], w.p4, w.cs, w.ce, w.vl, w.vcnt, w.err, gate);
+    } else if (n > 0) {
+        // a wavefront per cell: the eager build knows the cell count; a
+        // gated build reads it on the device and strides over the tables
+        // with a grid sized by the particle count
+        const int64_t tc = gate ? w.cells_max : c->total_cells;
+        const int64_t* tdev = gate ? &w.summary->total_cells : nullptr;
+        const int64_t groups = (tc + LC_WAVES - 1) / LC_WAVES;
+        const int64_t cap = gate ? 2 * (int64_t)blocks_for(n) : (int64_t)LC_MAX_BLOCKS;
+        const unsigned nb = (unsigned)std::max<int64_t>(1, std::min(groups, cap));
+        if (c->periodic)
+            hipLaunchKernelGGL(k_list_cells<true>, dim3(nb), dim3(BLOCK), 0, c->stream, n,
+                               c->n_sys, w.grid, w.p4, w.cs, w.ce, tc, tdev, w.vl, w.vcnt,
+                               w.err, gate);
+        else
+            hipLaunchKernelGGL(k_list_cells<false>, dim3(nb), dim3(BLOCK), 0, c->stream, n,
+                               c->n_sys, w.grid, w.p4, w.cs, w.ce, tc, tdev, w.vl, w.vcnt,
+                               w.err, gate);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "list build launch");
     c->list_ok = true;
