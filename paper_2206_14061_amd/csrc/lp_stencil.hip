@@ -188,17 +188,19 @@ __global__ __launch_bounds__(BLOCK) void k_list_build(
 // ---- neighbour-list build, a wavefront per cell ------------------------
 //
 // Every particle of a cell scans the same 27 cells, so one wavefront takes
-// a cell: each row's candidates are loaded once, one per lane (consecutive
-// 32-byte records), and tested against the cell's particles in turn; for
-// each particle the accepted lanes append their ids in lane order (a
-// ballot prefix count), which is the order the per-particle scan above
-// gives (rows in the same order, a row's three cells as one sequence, the
-// same test on the same values).  The lists are therefore identical.  A
+// a cell: the 27 cells' candidates, in the order the per-particle scan
+// above visits them (rows by z, then y; a row's three cells by x; a cell's
+// particles by index), form one sequence that is loaded 64 at a time, one
+// candidate per lane, and tested against the cell's particles in turn.
+// For each particle the accepted lanes append their ids in lane order (a
+// ballot prefix count), so the lists are identical to the per-particle
+// scan's (same entries, same order, same test on the same values).  A
 // particle's potential mirror sources (the cells of its reflection, which
 // differ between the particles of a cell) follow its real entries, one
-// particle at a time.  The cell's particles are taken 64 at a time; their
-// positions sit in LDS (read with one address by the whole wavefront) and
-// their running counts in lane q of `cntv`.
+// particle at a time, through the same sequence around the reflection.
+// The cell's particles are taken 64 at a time; their positions sit in LDS
+// (read with one address by the whole wavefront) and their running counts
+// in lane q of `cntv`.
 constexpr int LC_WAVES = BLOCK / 64;   // cells per block and pass
 constexpr int LC_MAX_BLOCKS = 16384;   // grid-stride launches
 
@@ -219,6 +221,58 @@ __device__ __forceinline__ void vl_put(int32_t* vl, int32_t i, uint32_t cst, uin
     vl[(uint64_t)(pos / VCHUNK) * cst + (uint64_t)(uint32_t)i * VCHUNK + pos % VCHUNK] = e;
 }
 
+// The 27 cells around (ccx, ccy, ccz) in scan order, cell l = 9 (z + 1) +
+// 3 (y + 1) + (x + 1) for offsets x, y, z in {-1, 0, 1}: lane l < 27
+// finds its cell's particle range (empty where the cell does not exist),
+// and the wavefront stores the ranges' first particles and the exclusive
+// prefix sums of their lengths (lanes 27..31: the total).  Returns the
+// total.
+__device__ __forceinline__ int cell_seq(const GridInfo& g, const int32_t* __restrict__ cs,
+                                        const int32_t* __restrict__ ce, int ccx, int ccy,
+                                        int ccz, int32_t* sb, int32_t* so)
+{
+    const int lane = threadIdx.x & 63;
+    const bool px = g.Lx > 0.0, py = g.Ly > 0.0;
+    int32_t b = 0, len = 0;
+    if (lane < 27) {
+        const int zz = ccz + lane / 9 - 1;
+        const int yy = nb_cell(ccy, (lane / 3) % 3 - 1, g.ny, py);
+        const int xx = nb_cell(ccx, lane % 3 - 1, g.nx, px);
+        if (zz >= 0 && zz < g.nz && yy >= 0 && xx >= 0) {
+            const int64_t c = g.cell_base + xx + (int64_t)g.nx * (yy + (int64_t)g.ny * zz);
+            b = cs[c];
+            len = ce[c] - b;
+        }
+    }
+    int inc = len;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int o = __shfl_up(inc, d);
+        if (lane >= d) inc += o;
+    }
+    if (lane < 32) {
+        sb[lane] = b;
+        so[lane] = inc - len;
+    }
+    wave_sync();
+    return __builtin_amdgcn_readlane(inc, 31);
+}
+
+// Candidate t (< tot) of the sequence cell_seq stored: the last cell
+// whose offset is at most t holds it (an empty cell shares its offset
+// with the next one).  Lanes past the sequence take `dflt`.
+__device__ __forceinline__ int32_t seq_at(const int32_t* sb, const int32_t* so, int t,
+                                          int tot, int32_t dflt)
+{
+    int lo = 0, hi = 26;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (so[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return t < tot ? sb[lo] + (t - so[lo]) : dflt;
+}
+
 template <bool PERIODIC>
 __global__ __launch_bounds__(BLOCK) void k_list_cells(
     int64_t n, int n_sys, const GridInfo* __restrict__ grid,
@@ -229,12 +283,22 @@ __global__ __launch_bounds__(BLOCK) void k_list_cells(
 {
     if (gate && *gate == 0) return;
     __shared__ double4 ppos[LC_WAVES][64];
+    __shared__ int32_t seqb[LC_WAVES][32], seqo[LC_WAVES][32];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int32_t* sb = seqb[wv];
+    int32_t* so = seqo[wv];
     const int64_t tc = n_cells_dev ? *n_cells_dev : n_cells;
     const int64_t groups = (tc + LC_WAVES - 1) / LC_WAVES;
     const char* p4b = reinterpret_cast<const char*>(p4);
     const uint32_t cst = (uint32_t)(n * VCHUNK);
+    auto load_pos = [&](int32_t j, double& qx, double& qy, double& qz) {
+        const double* r = reinterpret_cast<const double*>(p4b + ((uint32_t)j << 5));
+        const double2 xy = *reinterpret_cast<const double2*>(r);
+        qx = xy.x;
+        qy = xy.y;
+        qz = r[2];
+    };
     for (int64_t grp = xcd_block(blockIdx.x, gridDim.x); grp < groups; grp += gridDim.x) {
         const int64_t cell = grp * LC_WAVES + wv;
         if (cell >= tc) break;
@@ -244,32 +308,7 @@ __global__ __launch_bounds__(BLOCK) void k_list_cells(
         const int loc = (int)(cell - g.cell_base);
         const int cx = loc % g.nx, cy = (loc / g.nx) % g.ny, cz = loc / (g.nx * g.ny);
         const double Rv2 = g.Rv2 * (1.0 + 1e-12);
-        const bool px = g.Lx > 0.0, py = g.Ly > 0.0;
-        // the candidates of row (zz, yy) around cell x coordinate ccx,
-        // 64 at a time: lane t's candidate and its position (lanes past
-        // the row hold the cell's first particle and are not candidates)
-        auto row_ranges = [&](int zz, int yy, int ccx, int32_t (&b)[3], int32_t (&len)[3]) {
-            const int64_t row = g.cell_base + (int64_t)g.nx * (yy + (int64_t)g.ny * zz);
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int xx = nb_cell(ccx, q - 1, g.nx, px);
-                const int64_t c = row + (xx < 0 ? 0 : xx);
-                const int32_t a = cs[c], e = ce[c];
-                b[q] = a;
-                len[q] = xx < 0 ? 0 : e - a;
-            }
-        };
-        auto load_cand = [&](const int32_t (&b)[3], const int32_t (&len)[3], int t,
-                             int tot, int32_t& j, double& qx, double& qy, double& qz) {
-            const int l01 = len[0] + len[1];
-            j = t < len[0] ? b[0] + t : (t < l01 ? b[1] + (t - len[0]) : b[2] + (t - l01));
-            j = t < tot ? j : cb;
-            const double* r = reinterpret_cast<const double*>(p4b + ((uint32_t)j << 5));
-            const double2 xy = *reinterpret_cast<const double2*>(r);
-            qx = xy.x;
-            qy = xy.y;
-            qz = r[2];
-        };
+        const int tot = cell_seq(g, cs, ce, cx, cy, cz, sb, so);
         for (int32_t q0 = cb; q0 < cend; q0 += 64) {
             const int nq = cend - q0 < 64 ? cend - q0 : 64;
             const int32_t mi = q0 + lane;          // this lane's particle
@@ -281,45 +320,35 @@ __global__ __launch_bounds__(BLOCK) void k_list_cells(
             wave_sync();
             int cntv = 0;
             // real candidates
-            for (int zz = cz - 1; zz <= cz + 1; ++zz) {
-                if (zz < 0 || zz >= g.nz) continue;
-                for (int dy0 = -1; dy0 <= 1; ++dy0) {
-                    const int yy = nb_cell(cy, dy0, g.ny, py);
-                    if (yy < 0) continue;
-                    int32_t b[3], len[3];
-                    row_ranges(zz, yy, cx, b, len);
-                    const int tot = len[0] + len[1] + len[2];
-                    for (int t0 = 0; t0 < tot; t0 += 64) {
-                        int32_t j;
-                        double qx, qy, qz;
-                        load_cand(b, len, t0 + lane, tot, j, qx, qy, qz);
-                        const bool in = t0 + lane < tot;
-                        for (int q = 0; q < nq; ++q) {
-                            const double4 pq = ppos[wv][q];
-                            const int32_t iq = q0 + q;
-                            const double dx =
-                                (PERIODIC ? image_coord(qx, pq.x, g.Lx, g.hLx) : qx) - pq.x;
-                            const double dy =
-                                (PERIODIC ? image_coord(qy, pq.y, g.Ly, g.hLy) : qy) - pq.y;
-                            const double dz = qz - pq.z;
-                            const bool acc = in && j != iq &&
-                                             !(fma(dz, dz, fma(dy, dy, dx * dx)) >= Rv2);
-                            const uint64_t m = __ballot(acc);
-                            if (m) {
-                                const int c0 = __builtin_amdgcn_readlane(cntv, q);
-                                const uint32_t pos = (uint32_t)c0 + __builtin_amdgcn_mbcnt_hi(
-                                                         (uint32_t)(m >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                                if (acc && pos < (uint32_t)VCAP)
-                                    vl_put(vl, iq, cst, pos, j);
-                                cntv = lane == q ? c0 + __popcll(m) : cntv;
-                            }
-                        }
+            for (int t0 = 0; t0 < tot; t0 += 64) {
+                const bool in = t0 + lane < tot;
+                const int32_t j = seq_at(sb, so, t0 + lane, tot, cb);
+                double qx, qy, qz;
+                load_pos(j, qx, qy, qz);
+                for (int q = 0; q < nq; ++q) {
+                    const double4 pq = ppos[wv][q];
+                    const int32_t iq = q0 + q;
+                    const double dx =
+                        (PERIODIC ? image_coord(qx, pq.x, g.Lx, g.hLx) : qx) - pq.x;
+                    const double dy =
+                        (PERIODIC ? image_coord(qy, pq.y, g.Ly, g.hLy) : qy) - pq.y;
+                    const double dz = qz - pq.z;
+                    const bool acc =
+                        in && j != iq && !(fma(dz, dz, fma(dy, dy, dx * dx)) >= Rv2);
+                    const uint64_t m = __ballot(acc);
+                    if (m) {
+                        const int c0 = __builtin_amdgcn_readlane(cntv, q);
+                        const uint32_t pos = (uint32_t)c0 + __builtin_amdgcn_mbcnt_hi(
+                                                 (uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if (acc && pos < (uint32_t)VCAP) vl_put(vl, iq, cst, pos, j);
+                        cntv = lane == q ? c0 + __popcll(m) : cntv;
                     }
                 }
             }
             // potential mirrors of each particle near the wall: reals near
             // the wall that lie near its reflection
+            bool reseq = false;
             for (int q = 0; q < nq; ++q) {
                 const double4 pq = ppos[wv][q];
                 if (!(pq.z - g.wall < g.Rv)) continue;
@@ -327,35 +356,28 @@ __global__ __launch_bounds__(BLOCK) void k_list_cells(
                 const double zm = dsub(dmul(2.0, g.wall), pq.z);
                 int mx, my, mz;
                 cell_clamp(g, pq.x, pq.y, zm, mx, my, mz);
+                wave_sync();
+                const int mtot = cell_seq(g, cs, ce, mx, my, mz, sb, so);
+                reseq = true;
                 int c = __builtin_amdgcn_readlane(cntv, q);
-                for (int zz = mz - 1; zz <= mz + 1; ++zz) {
-                    if (zz < 0 || zz >= g.nz) continue;
-                    for (int dy0 = -1; dy0 <= 1; ++dy0) {
-                        const int yy = nb_cell(my, dy0, g.ny, py);
-                        if (yy < 0) continue;
-                        int32_t b[3], len[3];
-                        row_ranges(zz, yy, mx, b, len);
-                        const int tot = len[0] + len[1] + len[2];
-                        for (int t0 = 0; t0 < tot; t0 += 64) {
-                            int32_t j;
-                            double qx, qy, qz;
-                            load_cand(b, len, t0 + lane, tot, j, qx, qy, qz);
-                            const double dx =
-                                (PERIODIC ? image_coord(qx, pq.x, g.Lx, g.hLx) : qx) - pq.x;
-                            const double dy =
-                                (PERIODIC ? image_coord(qy, pq.y, g.Ly, g.hLy) : qy) - pq.y;
-                            const double dz = qz - zm;
-                            const bool acc = t0 + lane < tot &&
-                                             !(fma(dz, dz, fma(dy, dy, dx * dx)) >= Rv2) &&
-                                             qz - g.wall < g.Rv;
-                            const uint64_t m = __ballot(acc);
-                            const uint32_t pos = (uint32_t)c + __builtin_amdgcn_mbcnt_hi(
-                                                         (uint32_t)(m >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                            if (acc && pos < (uint32_t)VCAP) vl_put(vl, iq, cst, pos, j | MBIT);
-                            c += __popcll(m);
-                        }
-                    }
+                for (int t0 = 0; t0 < mtot; t0 += 64) {
+                    const int32_t j = seq_at(sb, so, t0 + lane, mtot, cb);
+                    double qx, qy, qz;
+                    load_pos(j, qx, qy, qz);
+                    const double dx =
+                        (PERIODIC ? image_coord(qx, pq.x, g.Lx, g.hLx) : qx) - pq.x;
+                    const double dy =
+                        (PERIODIC ? image_coord(qy, pq.y, g.Ly, g.hLy) : qy) - pq.y;
+                    const double dz = qz - zm;
+                    const bool acc = t0 + lane < mtot &&
+                                     !(fma(dz, dz, fma(dy, dy, dx * dx)) >= Rv2) &&
+                                     qz - g.wall < g.Rv;
+                    const uint64_t m = __ballot(acc);
+                    const uint32_t pos = (uint32_t)c + __builtin_amdgcn_mbcnt_hi(
+                                             (uint32_t)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (acc && pos < (uint32_t)VCAP) vl_put(vl, iq, cst, pos, j | MBIT);
+                    c += __popcll(m);
                 }
                 cntv = lane == q ? c : cntv;
             }
@@ -366,9 +388,12 @@ __global__ __launch_bounds__(BLOCK) void k_list_cells(
                 }
                 vcnt[mi] = cntv;
             }
-            // the next chunk's positions overwrite these
+            // the next chunk's positions (and the cell's own sequence, if
+            // a mirror scan replaced it) overwrite the LDS words
             wave_sync();
+            if (reseq && q0 + 64 < cend) cell_seq(g, cs, ce, cx, cy, cz, sb, so);
         }
+        wave_sync();
     }
 }
 
