@@ -1223,11 +1223,9 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
         int32_t jb[MAP_BATCH];
         vl_load(vl, n, i, k0, jb);
 #pragma unroll
-        for (int u = 0; u < MAP_BATCH; ++u) jb[u] = k0 + u < cnt ? jb[u] & ~MBIT : -1;
-#pragma unroll
         for (int u = 0; u < MAP_BATCH; ++u) {
-            const int32_t j = jb[u];
-            if (j < 0) continue;
+            if (k0 + u >= cnt) continue;
+            const int32_t j = jb[u] & ~MBIT;
             uint32_t h = src_hash(j);
             int probe = 0;
             for (; probe < HASH_SIZE; ++probe) {
@@ -1236,6 +1234,10 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
                 h = (h + 1) & (HASH_SIZE - 1);
             }
             if (probe == HASH_SIZE) full = 1;
+            // the entry's hash slot (and mirror bit) until its source's
+            // place in the sorted set is known
+            vs[(int64_t)(k0 + u) * n + i] =
+                (uint16_t)(h | ((jb[u] & MBIT) ? SLOT_MIRROR : 0u));
         }
     }
     __syncthreads();
@@ -1283,16 +1285,18 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
     }
     if (t == 0) tile_cnt[tile] = S;
     __syncthreads();
+    // hash slots -> slots in the sorted set (the thread rereads its own
+    // words)
     for (int k0 = 0; k0 < cnt; k0 += MAP_BATCH) {
-        int32_t eb[MAP_BATCH];
-        vl_load(vl, n, i, k0, eb);
+        uint32_t hb[MAP_BATCH];
+#pragma unroll
+        for (int u = 0; u < MAP_BATCH; ++u)
+            hb[u] = k0 + u < cnt ? vs[(int64_t)(k0 + u) * n + i] : 0u;
 #pragma unroll
         for (int u = 0; u < MAP_BATCH; ++u) {
             if (k0 + u >= cnt) continue;
-            const int32_t e = eb[u];
-            const int h = hash_find(hkey, e & ~MBIT);
-            const uint32_t q = h >= 0 ? hslot[h] : 0u;
-            vs[(int64_t)(k0 + u) * n + i] = (uint16_t)(q | ((e & MBIT) ? SLOT_MIRROR : 0u));
+            const uint32_t q = hslot[hb[u] & (HASH_SIZE - 1)];
+            vs[(int64_t)(k0 + u) * n + i] = (uint16_t)(q | (hb[u] & SLOT_MIRROR));
         }
     }
 }
