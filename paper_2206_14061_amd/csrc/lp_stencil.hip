@@ -1176,7 +1176,8 @@ __global__ void k_export_stencils(View v, int32_t* cnt_out, int32_t* idx_out,
 
 constexpr int HASH_SIZE = 4096;        // LDS hash slots per tile (power of 2)
 constexpr int SORT_N = 2048;           // keys sorted per tile (>= STAGE_CAP)
-static_assert(STAGE_CAP <= SORT_N && SORT_N <= HASH_SIZE, "tile map sizes");
+static_assert(STAGE_CAP <= SORT_N && SORT_N <= HASH_SIZE && SORT_N % BLOCK == 0 &&
+                  HASH_SIZE % BLOCK == 0, "tile map sizes");
 static_assert(STAGE_CAP <= (int)SLOT_MIRROR, "slots fit below the mirror bit");
 
 __device__ __forceinline__ uint32_t src_hash(int32_t j)
@@ -1202,8 +1203,8 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
 {
     static_assert(HASH_SIZE == 1 << 12, "src_hash keeps 12 bits");
     if (gate && *gate == 0) return;
+    // hkey: the set's keys, then (once sorted) each key's slot in the set
     __shared__ int32_t hkey[HASH_SIZE];
-    __shared__ uint16_t hslot[HASH_SIZE];
     __shared__ int32_t keys[SORT_N];
     __shared__ uint32_t wsum[BLOCK / 64];
     __shared__ int full;
@@ -1278,11 +1279,22 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
             __syncthreads();
         }
     }
-    for (int q = t; q < S; q += BLOCK) {
-        tile_src[tile * STAGE_CAP + q] = keys[q];
-        const int h = hash_find(hkey, keys[q]);
-        if (h >= 0) hslot[h] = (uint16_t)q;
+    // every key's hash slot is found before any slot is overwritten
+    constexpr int QPT = SORT_N / BLOCK;
+    int hq[QPT];
+#pragma unroll
+    for (int r = 0; r < QPT; ++r) {
+        const int q = t + r * BLOCK;
+        hq[r] = -1;
+        if (q < S) {
+            tile_src[tile * STAGE_CAP + q] = keys[q];
+            hq[r] = hash_find(hkey, keys[q]);
+        }
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < QPT; ++r)
+        if (hq[r] >= 0) hkey[hq[r]] = t + r * BLOCK;
     if (t == 0) tile_cnt[tile] = S;
     __syncthreads();
     // hash slots -> slots in the sorted set (the thread rereads its own
@@ -1295,7 +1307,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_map(
 #pragma unroll
         for (int u = 0; u < MAP_BATCH; ++u) {
             if (k0 + u >= cnt) continue;
-            const uint32_t q = hslot[hb[u] & (HASH_SIZE - 1)];
+            const uint32_t q = (uint32_t)hkey[hb[u] & (HASH_SIZE - 1)];
             vs[(int64_t)(k0 + u) * n + i] = (uint16_t)(q | (hb[u] & SLOT_MIRROR));
         }
     }
