@@ -126,3 +126,18 @@ def test_list_overflow_with_either_scan(lp, flags):
     with pytest.raises(lp.LPError) as e:
         ctx.sync_status()
     assert e.value.status == 2
+
+
+def test_cell_scan_with_an_empty_system(lp):
+    """Systems may be empty (equal offsets): an empty system keeps one empty
+    cell in the tables, which the cell scan skips; the other systems' lists
+    and steps equal the per-particle scan's bit for bit."""
+    base = CASES["ensemble_3"]()
+    off = [int(v) for v in base.offsets]
+    offsets = np.array([off[0], off[1], off[1], off[2], off[3]], dtype=np.int64)
+    params = [base.params[0], base.params[1], base.params[1], base.params[2]]
+    wl = lpgen.Workload("ensemble_3_empty", base.state, offsets, params, base.dt, 1)
+    _log("systems %d offsets %s" % (wl.n_sys, list(offsets)))
+    a = _run(lp, wl, 0, 3, skin=0.0)
+    b = _run(lp, wl, lp.LP_DEBUG_PARTICLE_LIST, 3, skin=0.0)
+    _same_runs(a, b)
