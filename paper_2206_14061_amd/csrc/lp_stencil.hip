@@ -7,7 +7,10 @@
 // Until some particle has moved more than skin R / 2, the list contains
 // every pair that can be closer than R, so every pass below applies the
 // exact candidate test r2 = (dx*dx + dy*dy) + dz*dz < R*R to the list and
-// obtains exactly the candidates a full search would.
+// obtains exactly the candidates a full search would.  The list is built
+// with a wavefront per cell (k_list_cells: the cell's particles share the
+// 27 cells they scan); k_list_build, a thread per particle, gives the same
+// lists and serves as the check of the former.
 //
 // Stencil selection (nearest candidate of each octant, then the nearest
 // others by key (r^2, id), m_max in all), one thread per particle, without
