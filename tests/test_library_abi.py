@@ -62,3 +62,18 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_enum_constants_match_header():
+    """Every LP_* enum constant of include/lp.h has the same value in the
+    binding (debug flags, precision, weights)."""
+    from paper_2206_14061_amd import _lib
+    text = open(os.path.join(ROOT, "include", "lp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    found = 0
+    for body in re.findall(r"enum\s*\{([^}]*)\}", text):
+        for name, val in re.findall(r"(LP_[A-Z0-9_]+)\s*=\s*(\d+)", body):
+            assert getattr(_lib, name) == int(val), name
+            found += 1
+    assert found >= 12
+    assert _lib.LP_DEBUG_PARTICLE_LIST == 128
