@@ -141,3 +141,57 @@ def test_cell_scan_with_an_empty_system(lp):
     a = _run(lp, wl, 0, 3, skin=0.0)
     b = _run(lp, wl, lp.LP_DEBUG_PARTICLE_LIST, 3, skin=0.0)
     _same_runs(a, b)
+
+
+def _clumps(k=70, nclump=8, seed=21):
+    """Dense clumps of k particles (more than a wavefront's 64 in one cell)
+    within 0.3 list radii of their centres, centres three list radii apart
+    on the wall plane (so their particles have mirror sources): every clump
+    stays below the list capacity."""
+    h = 1.0 / 16.0
+    p = lpgen.default_params(h)
+    rv = p.R * 1.1
+    rng = np.random.default_rng(seed)
+    pts = []
+    for c in range(nclump):
+        cx, cy = 3.0 * rv * (c % 4), 3.0 * rv * (c // 4)
+        d = rng.normal(size=(k, 3))
+        d *= (0.3 * rv * rng.random(k) ** (1.0 / 3.0) / np.linalg.norm(d, axis=1))[:, None]
+        pts.append(d + np.array([cx, cy, 0.5 * rv]))
+    xyz = np.concatenate(pts)
+    n = xyz.shape[0]
+    z0 = np.zeros(n)
+    st = lpgen.State(xyz[:, 0].copy(), xyz[:, 1].copy(), xyz[:, 2].copy(),
+                     z0.copy(), z0.copy(), z0.copy(), np.full(n, 1.0 / 0.55))
+    return lpgen.Workload("clumps", st, np.array([0, n]), [p], 1e-5, 1)
+
+
+def test_cell_scan_on_cells_of_more_than_64_particles(lp):
+    """Cells holding 70 particles take two chunks of the wavefront, and
+    their mirror scans replace and restore the cell's candidate sequence
+    between chunks: the same neighbours as the per-particle scan, and both
+    equal to the oracle's candidate sets."""
+    import oracle
+    wl = _clumps()
+    got = []
+    for flags in (0, lp.LP_DEBUG_PARTICLE_LIST):
+        ctx = lp.make_context(wl, debug_flags=flags)
+        st = lp.DeviceState.from_host(wl.state)
+        ctx.lp_build_cells(st)
+        got.append(_host(ctx.lp_neighbors(st)))
+        ctx.sync_status()
+        del ctx, st
+    _log("clumps n=%d mirrors %d" % (wl.n, got[0]["n_mirror"]))
+    assert got[0]["n_mirror"] > 0
+    for k in got[0]:
+        assert np.array_equal(np.asarray(got[0][k]), np.asarray(got[1][k])), k
+    perm, _ = oracle.sort_perm(wl.state, wl.offsets, wl.params)
+    ost = wl.state.take(perm)
+    ost = lpgen.State(*[np.ascontiguousarray(a) for a in ost.arrays()])
+    nb = oracle.Oracle(ost, wl.offsets, wl.params, brute=True).neighbours()
+    g = got[0]
+    assert g["n_mirror"] == nb.n_mirror
+    assert np.array_equal(g["cand_off"], nb.cand_off)
+    assert np.array_equal(g["cand_idx"], nb.cand_idx)
+    assert np.array_equal(g["ghost_mask"], nb.ghost_mask)
+    assert np.array_equal(g["sten_cnt"], nb.sten_cnt)
