@@ -320,7 +320,7 @@ lp_status lp_reserve(lp_ctx* c, int64_t n_max, int64_t cells_max)
     w.n_max = n_max;
     w.cells_max = cells_max;
     w.m_max = mm;
-    w.hist_cap = 256 * nb;
+    w.hist_cap = RADIX_MAX_DIGITS * nb;
     c->cells_ok = c->stencils_ok = c->list_ok = c->map_ok = false;
     c->redo_clear = c->disp_clear = false;
     if (c->n_sys > 0) {

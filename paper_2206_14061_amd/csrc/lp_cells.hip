@@ -294,22 +294,30 @@ __global__ void k_keys(int64_t n, int n_sys, const int64_t* off,
     if (outx || outy) raise_error(err, ERR_BOX, i);
 }
 
-// ---- stable LSD radix sort, 8-bit digits ------------------------------
+// ---- stable LSD radix sort, digits of up to RADIX_MAX_BITS bits ---------
+
+static_assert(RADIX_MAX_DIGITS == 2 * BLOCK, "each thread owns two digits");
 
 __global__ void k_radix_hist(const unsigned long long* keys, int64_t n,
-                             int shift, uint32_t* hist, int64_t nblk, const int32_t* gate)
+                             int shift, int dbits, uint32_t* hist, int64_t nblk,
+                             const int32_t* gate)
 {
     LP_GATE(gate);
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[RADIX_MAX_DIGITS];
+    const int t = threadIdx.x;
+    const unsigned long long mask = (1ull << dbits) - 1ull;
+    h[t] = 0;
+    h[t + BLOCK] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
     for (int r = 0; r < SORT_ITEMS; ++r) {
-        const int64_t i = base + (int64_t)r * BLOCK + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        const int64_t i = base + (int64_t)r * BLOCK + t;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    const int nd = 1 << dbits;
+    if (t < nd) hist[(int64_t)t * nblk + blockIdx.x] = h[t];
+    if (t + BLOCK < nd) hist[(int64_t)(t + BLOCK) * nblk + blockIdx.x] = h[t + BLOCK];
 }
 
 // Exclusive scan in place of a uint32 array (single block of 1024).
@@ -379,18 +387,24 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_u32(uint32_t* a, int64_t 
 
 __global__ void k_radix_scatter(const unsigned long long* kin,
                                 const int32_t* vin, unsigned long long* kout,
-                                int32_t* vout, int64_t n, int shift,
+                                int32_t* vout, int64_t n, int shift, int dbits,
                                 const uint32_t* hist, int64_t nblk, const int32_t* gate)
 {
     LP_GATE(gate);
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[BLOCK / 64][256];
+    __shared__ uint32_t base[RADIX_MAX_DIGITS];
+    __shared__ uint32_t run[RADIX_MAX_DIGITS];
+    __shared__ uint32_t wcnt[BLOCK / 64][RADIX_MAX_DIGITS];
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    base[t] = hist[(int64_t)t * nblk + blockIdx.x];
-    run[t] = 0;
-    for (int w = 0; w < BLOCK / 64; ++w) wcnt[w][t] = 0;
+    const int nd = 1 << dbits;
+    const uint32_t mask = (uint32_t)nd - 1u;
+    // thread t owns digits t and t + BLOCK
+    for (int q = 0; q < 2; ++q) {
+        const int d = t + q * BLOCK;
+        base[d] = d < nd ? hist[(int64_t)d * nblk + blockIdx.x] : 0u;
+        run[d] = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) wcnt[w][d] = 0;
+    }
     __syncthreads();
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int64_t tb = (int64_t)blockIdx.x * SORT_TILE;
@@ -398,9 +412,10 @@ __global__ void k_radix_scatter(const unsigned long long* kin,
         const int64_t i = tb + (int64_t)r * BLOCK + t;
         const bool valid = i < n;
         const unsigned long long key = valid ? kin[i] : 0ull;
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t d = (uint32_t)(key >> shift) & mask;
+        // lanes holding the same digit: match the digit bit by bit
         unsigned long long peers = __ballot(valid);
-        for (int bit = 0; bit < 8; ++bit) {
+        for (int bit = 0; bit < dbits; ++bit) {
             const bool on = (d >> bit) & 1u;
             const unsigned long long bal = __ballot(on);
             peers &= on ? bal : ~bal;
@@ -415,12 +430,15 @@ __global__ void k_radix_scatter(const unsigned long long* kin,
             vout[pos] = vin[i];
         }
         __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < BLOCK / 64; ++w) {
-            add += wcnt[w][t];
-            wcnt[w][t] = 0;
+        for (int q = 0; q < 2; ++q) {
+            const int dd = t + q * BLOCK;
+            uint32_t add = 0;
+            for (int w = 0; w < BLOCK / 64; ++w) {
+                add += wcnt[w][dd];
+                wcnt[w][dd] = 0;
+            }
+            run[dd] += add;
         }
-        run[t] += add;
         __syncthreads();
     }
 }
@@ -655,15 +673,18 @@ void radix_sort(lp_ctx* c, int64_t cnt, int bits, unsigned long long*& kr,
     int32_t* vin = w.vals0;
     int32_t* vout = w.vals1;
     const int64_t nblk = (cnt + SORT_TILE - 1) / SORT_TILE;
-    const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
+    // the fewest passes of at most RADIX_MAX_BITS bits, digits of equal
+    // width (18 bits: two passes of 9)
+    const int passes = bits <= 0 ? 0 : (bits + RADIX_MAX_BITS - 1) / RADIX_MAX_BITS;
+    const int dbits = passes > 0 ? (bits + passes - 1) / passes : 0;
     for (int p = 0; p < passes && cnt > 0; ++p) {
-        const int shift = 8 * p;
+        const int shift = dbits * p;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(BLOCK), 0,
-                           c->stream, kin, cnt, shift, w.hist, nblk, gate);
+                           c->stream, kin, cnt, shift, dbits, w.hist, nblk, gate);
         hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(SCAN_THREADS), 0, c->stream,
-                           w.hist, 256 * nblk, gate);
+                           w.hist, (int64_t)(1 << dbits) * nblk, gate);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(BLOCK),
-                           0, c->stream, kin, vin, kout, vout, cnt, shift,
+                           0, c->stream, kin, vin, kout, vout, cnt, shift, dbits,
                            w.hist, nblk, gate);
         std::swap(kin, kout);
         std::swap(vin, vout);

@@ -74,6 +74,8 @@ constexpr int NCLASS = 3;
 constexpr int CLASS_ROWS0 = 16, CLASS_ROWS1 = 32;
 constexpr int BLOCK = 256;        // threads per block of per-particle kernels
 constexpr int SORT_ITEMS = 16;    // keys per thread in a radix tile
+constexpr int RADIX_MAX_BITS = 9; // digit width of the radix sort, at most
+constexpr int RADIX_MAX_DIGITS = 1 << RADIX_MAX_BITS;
 constexpr int SORT_TILE = BLOCK * SORT_ITEMS;
 // mirror numbering without a separate scan up to this many tiles
 constexpr int MIRROR_SUM_BLOCKS = 2048;
@@ -260,7 +262,7 @@ constexpr void work_layout(Work& w, int64_t n_max, int64_t cells_max, int mm,
     A(w.off, sys_cap + 1); A(w.prm, sys_cap); A(w.grid, sys_cap);
     A(w.bbox, 6 * sys_cap); A(w.summary, 1); A(w.err, 1); A(w.cnt, 1);
     A(w.keys0, n_max); A(w.keys1, n_max); A(w.vals0, n_max); A(w.vals1, n_max);
-    A(w.hist, 256 * nb);
+    A(w.hist, RADIX_MAX_DIGITS * nb);
     for (int a = 0; a < 7; ++a) A(w.sst[a], n_max);
     A(w.p4, 4 * n_max);
     for (int a = 0; a < 3; ++a) A(w.xref[a], n_max);

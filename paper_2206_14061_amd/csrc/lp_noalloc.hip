@@ -97,7 +97,7 @@ void init_slot(DevSlot& d)
     w.n_max = NOALLOC_N;
     w.cells_max = NOALLOC_CELLS;
     w.m_max = MMAX_LIMIT;
-    w.hist_cap = 256 * ((NOALLOC_N + SORT_TILE - 1) / SORT_TILE);
+    w.hist_cap = RADIX_MAX_DIGITS * ((NOALLOC_N + SORT_TILE - 1) / SORT_TILE);
     if (hipGetDevice(&c->device) != hipSuccess) {
         d.init_err = hipErrorInvalidDevice;
         delete c;
