@@ -272,6 +272,12 @@ void lp_destroy(lp_ctx* c)
     if (!c) return;
     hipStreamSynchronize(c->stream);
     drop_graph(c);
+    if (c->map_stream) {
+        hipStreamSynchronize(c->map_stream);
+        hipStreamDestroy(c->map_stream);
+    }
+    if (c->map_fork) hipEventDestroy(c->map_fork);
+    if (c->map_join) hipEventDestroy(c->map_join);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (int q = 0; q < 16; ++q)
         if (c->ev[q]) hipEventDestroy(c->ev[q]);
@@ -495,6 +501,34 @@ static lp_status check_ahead(lp_ctx* c, double* const in[7], const double* const
     return LP_OK;
 }
 
+// The tile map of a list just built, on the side stream after the list
+// (fork); tile_map_join makes the step's stream wait for it.
+static lp_status tile_map_fork(lp_ctx* c)
+{
+    hipError_t e = hipSuccess;
+    if (!c->map_stream) e = hipStreamCreateWithFlags(&c->map_stream, hipStreamNonBlocking);
+    if (e == hipSuccess && !c->map_fork)
+        e = hipEventCreateWithFlags(&c->map_fork, hipEventDisableTiming);
+    if (e == hipSuccess && !c->map_join)
+        e = hipEventCreateWithFlags(&c->map_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(c->map_fork, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->map_stream, c->map_fork, 0);
+    if (e != hipSuccess) return hip_fail(c, e, "tile map fork");
+    hipStream_t own = c->stream;
+    c->stream = c->map_stream;
+    lp_status r = tile_map_build(c);
+    c->stream = own;
+    if (r != LP_OK) return r;
+    e = hipEventRecord(c->map_join, c->map_stream);
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "tile map join");
+}
+
+static lp_status tile_map_join(lp_ctx* c)
+{
+    const hipError_t e = hipStreamWaitEvent(c->stream, c->map_join, 0);
+    return e == hipSuccess ? LP_OK : hip_fail(c, e, "tile map join");
+}
+
 lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
                   lp_step_record* rec)
 {
@@ -528,7 +562,11 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
     } else {
         r = state_copy(c, in, perm, nullptr, false);
     }
-    if (r == LP_OK && !c->map_ok) r = tile_map_build(c);
+    bool forked = false;
+    if (r == LP_OK && !c->map_ok) {
+        r = tile_map_fork(c);
+        forked = r == LP_OK;
+    }
     if (!ahead || rebuild) prof_mark(c, 0, true);
     if (r != LP_OK) return r;
     if (rebuild) ++c->rebuilds;
@@ -538,6 +576,7 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
     }
     // the displacement check's copy or the re-sort packed the positions
     r = stencils_build(c, sorted, true, ahead && !rebuild ? STENCIL_TAIL : STENCIL_ALL);
+    if (r == LP_OK && forked) r = tile_map_join(c);
     if (r == LP_OK) r = step_rhs(c, sorted);
     if (r == LP_OK) r = step_update(c, sorted, dt, in);
     // stencils of the API calls refer to lp_build_cells' state

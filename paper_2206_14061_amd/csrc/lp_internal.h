@@ -339,6 +339,11 @@ struct lp_ctx {
     const double* built_x = nullptr;
     bool cells_ok = false;
     bool stencils_ok = false;
+    // side stream of an eager step that rebuilt its list: the tile map is
+    // built there while the step's own stream runs the mirrors and the
+    // selection, which do not read it; the fits wait for map_join
+    hipStream_t map_stream = nullptr;
+    hipEvent_t map_fork = nullptr, map_join = nullptr;
     // captured step sequence (lp_step_graph) and what it was captured for
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
