@@ -18,7 +18,11 @@
  *    (at most 2^28 - 1 real + mirror particles).
  *  - Work is enqueued asynchronously on the stream given to lp_create.
  *    Only calls that return host values (lp_build_cells, lp_neighbors'
- *    counts, lp_sync_status) synchronise that stream.
+ *    counts, lp_sync_status) synchronise that stream.  An lp_step that
+ *    builds a new neighbour list runs one kernel on a second stream of the
+ *    library's (default priority), forked from and joined back into that
+ *    stream within the call, so work ordered after the call on that stream
+ *    sees all of it.
  *  - Every call returns an lp_status; nothing throws across the ABI.
  *    lp_last_error() gives a text description of the last failure.
  *    Failures detected on the device (capacity overflow, non-finite
