@@ -563,9 +563,11 @@ lp_status lp_step(lp_ctx* c, lp_state* s, double dt, int32_t* perm,
         r = state_copy(c, in, perm, nullptr, false);
     }
     bool forked = false;
-    if (r == LP_OK && !c->map_ok) {
+    if (r == LP_OK && !c->map_ok && c->map_side) {
         r = tile_map_fork(c);
         forked = r == LP_OK;
+    } else if (r == LP_OK && !c->map_ok) {
+        r = tile_map_build(c);
     }
     if (!ahead || rebuild) prof_mark(c, 0, true);
     if (r != LP_OK) return r;

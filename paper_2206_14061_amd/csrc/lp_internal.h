@@ -344,6 +344,8 @@ struct lp_ctx {
     // selection, which do not read it; the fits wait for map_join
     hipStream_t map_stream = nullptr;
     hipEvent_t map_fork = nullptr, map_join = nullptr;
+    bool map_side = true;       // false: the allocation-free step's context
+                                // (which creates no stream) builds it in line
     // captured step sequence (lp_step_graph) and what it was captured for
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;

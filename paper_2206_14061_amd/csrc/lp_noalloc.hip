@@ -98,6 +98,8 @@ void init_slot(DevSlot& d)
     w.cells_max = NOALLOC_CELLS;
     w.m_max = MMAX_LIMIT;
     w.hist_cap = RADIX_MAX_DIGITS * ((NOALLOC_N + SORT_TILE - 1) / SORT_TILE);
+    // no side stream for the tile map: this context creates no stream
+    c->map_side = false;
     if (hipGetDevice(&c->device) != hipSuccess) {
         d.init_err = hipErrorInvalidDevice;
         delete c;
